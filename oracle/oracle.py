@@ -1,0 +1,254 @@
+"""ctypes binding of the CPU FP64 oracle (hh_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by __graft_entry__.smoke() and by
+the cpu_baseline leg of bench.py, never by the product package.  It shares no
+code with the HIP path; both receive the same seeded inputs from
+paper_0912_0180_amd.workloads, which holds no arithmetic of the method.
+
+Vectors are numpy complex128 arrays, x fastest (index i + nx*(j + ny*k)).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hh_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+GCC_FLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c99"]
+
+OK, ERR_ARG, ERR_NOCONV, ERR_BREAKDOWN, ERR_NONFINITE = 0, -1, -4, -5, -6
+
+
+def build(verbose=False):
+    """Compile the oracle with gcc (no FMA contraction, OpenMP)."""
+    cmd = ["gcc"] + GCC_FLAGS + ["-o", LIB, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    return LIB
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("s", ctypes.c_int), ("tol", ctypes.c_double),
+                ("max_matvec", ctypes.c_int), ("max_restarts", ctypes.c_int), ("x0_given", ctypes.c_int),
+                ("P", ctypes.c_void_p), ("history", ctypes.c_void_p), ("history_len", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("matvecs", ctypes.c_int), ("iterations", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("rel_res_recurrence", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        P, D, I = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
+        L.og_create.restype = P
+        L.og_create.argtypes = [I, P, P, P, P, P, D, D, I, I, I, I, I, D, P]
+        L.og_free.argtypes = [P]
+        L.og_levels.argtypes = [P]
+        L.og_level_dims.argtypes = [P, I, P]
+        L.og_coarse_size.restype = ctypes.c_long
+        L.og_coarse_size.argtypes = [P]
+        L.og_coeffs.argtypes = [P, I, I, I, P]
+        L.og_phi.argtypes = [P, I, P]
+        L.og_coarse_inverse.argtypes = [P, P]
+        L.og_apply.argtypes = [P, I, I, P, P]
+        L.og_vcycle.argtypes = [P, P, P]
+        L.og_restrict.argtypes = [P, I, P, P]
+        L.og_prolong.argtypes = [P, I, P, P]
+        L.og_jacobi.argtypes = [P, I, P, P]
+        L.og_coarse_solve.argtypes = [P, P, P]
+        L.og_dotc.argtypes = [P, P, ctypes.c_long, P]
+        L.og_nrm2.restype = D
+        L.og_nrm2.argtypes = [P, ctypes.c_long]
+        L.og_solve.argtypes = [P, P, P, P, P]
+        L.og_num_threads.restype = I
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c128(x):
+    return np.ascontiguousarray(x, dtype=np.complex128)
+
+
+def _three(v, fill):
+    v = list(v)
+    return v + [fill] * (3 - len(v))
+
+
+class Grid:
+    """One discretised problem: geometry, coefficients of H (ECS) and M (CSG)
+    on every level, coarse phi, the explicit coarsest inverse.
+
+    desc keys (same meaning as the library's grid descriptor): dim, n, lo, hi,
+    a, b, theta_ecs, theta_csg, csg_mode (0 uniform, 1 interior), centering
+    (0 cell, 1 vertex), levels (0 auto), nu1, nu2, omega; phi is the real array
+    k(x)^2 on the finest grid (shape prod(n)), or phi_const."""
+
+    def __init__(self, desc, phi=None):
+        L = lib()
+        d = dict(desc)
+        dim = int(d["dim"])
+        n = [int(v) for v in d["n"]][:dim]
+        N = int(np.prod(n))
+        if phi is None:
+            phi = d.get("phi")
+        if phi is None:
+            phi = np.full(N, float(d.get("phi_const", 0.0)))
+        phi = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).reshape(-1))
+        assert phi.size == N, (phi.size, N)
+        self._keep = [np.array(_three(n, 1), dtype=np.int32),
+                      np.array(_three(d["lo"], 0.0)), np.array(_three(d["hi"], 1.0)),
+                      np.array(_three(d["a"], 0.0)), np.array(_three(d["b"], 1.0)), phi]
+        ni, lo, hi, a, b, _ = self._keep
+        self.h = L.og_create(dim, _ptr(ni), _ptr(lo), _ptr(hi), _ptr(a), _ptr(b),
+                             float(d.get("theta_ecs", np.pi / 6)), float(d.get("theta_csg", np.pi / 8)),
+                             int(d.get("csg_mode", 0)), int(d.get("centering", 0)), int(d.get("levels", 0)),
+                             int(d.get("nu1", 1)), int(d.get("nu2", 1)), float(d.get("omega", 0.8)), _ptr(phi))
+        if not self.h:
+            raise ValueError("oracle rejected the grid description")
+        self.dim = dim
+        self.n = n
+        self.N = N
+        self.nlev = L.og_levels(self.h)
+        self.Nc = int(L.og_coarse_size(self.h))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().og_free(self.h)
+            self.h = None
+
+    def level_dims(self, lev):
+        out = np.zeros(3, dtype=np.int32)
+        lib().og_level_dims(self.h, lev, _ptr(out))
+        return [int(v) for v in out]
+
+    def level_size(self, lev):
+        return int(np.prod(self.level_dims(lev)))
+
+    def coeffs(self, lev, axis, which):
+        """which in {'aH','cH','dH','aM','cM','dM'}"""
+        w = ["aH", "cH", "dH", "aM", "cM", "dM"].index(which)
+        n = self.level_dims(lev)[axis]
+        out = np.zeros(n, dtype=np.complex128)
+        rc = lib().og_coeffs(self.h, lev, axis, w, _ptr(out))
+        assert rc == n
+        return out
+
+    def phi(self, lev):
+        out = np.zeros(self.level_size(lev))
+        lib().og_phi(self.h, lev, _ptr(out))
+        return out
+
+    def coarse_inverse(self):
+        out = np.zeros((self.Nc, self.Nc), dtype=np.complex128)
+        lib().og_coarse_inverse(self.h, _ptr(out))
+        return out
+
+    def apply(self, x, op="H", lev=0):
+        x = _c128(x).reshape(-1)
+        y = np.empty_like(x)
+        lib().og_apply(self.h, 0 if op == "H" else 1, lev, _ptr(x), _ptr(y))
+        return y
+
+    def matrix(self, op="H", lev=0):
+        """Dense matrix of the operator (column q = A e_q); tiny grids only."""
+        N = self.level_size(lev)
+        A = np.zeros((N, N), dtype=np.complex128)
+        e = np.zeros(N, dtype=np.complex128)
+        for q in range(N):
+            e[q] = 1.0
+            A[:, q] = self.apply(e, op, lev)
+            e[q] = 0.0
+        return A
+
+    def vcycle(self, f):
+        f = _c128(f).reshape(-1)
+        u = np.empty_like(f)
+        lib().og_vcycle(self.h, _ptr(f), _ptr(u))
+        return u
+
+    def restrict(self, r, lev=0):
+        r = _c128(r).reshape(-1)
+        out = np.empty(self.level_size(lev + 1), dtype=np.complex128)
+        lib().og_restrict(self.h, lev, _ptr(r), _ptr(out))
+        return out
+
+    def prolong(self, e, lev=0):
+        e = _c128(e).reshape(-1)
+        out = np.empty(self.level_size(lev), dtype=np.complex128)
+        lib().og_prolong(self.h, lev, _ptr(e), _ptr(out))
+        return out
+
+    def jacobi(self, f, u, lev=0):
+        f = _c128(f).reshape(-1)
+        u = _c128(u).reshape(-1).copy()
+        lib().og_jacobi(self.h, lev, _ptr(f), _ptr(u))
+        return u
+
+    def coarse_solve(self, f):
+        f = _c128(f).reshape(-1)
+        e = np.empty_like(f)
+        lib().og_coarse_solve(self.h, _ptr(f), _ptr(e))
+        return e
+
+    def solve(self, b, method="bicgstab", tol=1e-8, max_matvec=10000, max_restarts=3, x0=None,
+              s=4, P=None, history=False):
+        b = _c128(b).reshape(-1)
+        x = np.zeros_like(b) if x0 is None else _c128(x0).reshape(-1).copy()
+        o = _Opts()
+        o.method = 0 if method == "bicgstab" else 1
+        o.s = int(s)
+        o.tol = float(tol)
+        o.max_matvec = int(max_matvec)
+        o.max_restarts = int(max_restarts)
+        o.x0_given = 0 if x0 is None else 1
+        Pk = None
+        if o.method == 1:
+            Pk = np.asfortranarray(_c128(P).reshape(self.N, s, order="F")) if P is not None else None
+            if Pk is None:
+                raise ValueError("IDR(s) needs the shadow space P")
+            o.P = Pk.ctypes.data
+        hist = np.full(max_matvec, np.nan) if history else None
+        if hist is not None:
+            o.history = hist.ctypes.data
+            o.history_len = max_matvec
+        info = _Info()
+        lib().og_solve(self.h, ctypes.byref(o), _ptr(b), _ptr(x), ctypes.byref(info))
+        res = {"status": info.status, "matvecs": info.matvecs, "iterations": info.iterations,
+               "restarts": info.restarts, "rel_res_recurrence": info.rel_res_recurrence,
+               "rel_res_true": info.rel_res_true}
+        if hist is not None:
+            res["history"] = hist[: info.matvecs]
+        return x, res
+
+
+def dotc(x, y):
+    x, y = _c128(x).reshape(-1), _c128(y).reshape(-1)
+    out = np.zeros(2)
+    lib().og_dotc(_ptr(x), _ptr(y), x.size, _ptr(out))
+    return complex(out[0], out[1])
+
+
+def nrm2(x):
+    x = _c128(x).reshape(-1)
+    return float(lib().og_nrm2(_ptr(x), x.size))
+
+
+def num_threads():
+    return int(lib().og_num_threads())
