@@ -1,0 +1,212 @@
+/*
+ * hh.h -- C ABI of the MI355X (gfx950) Helmholtz solver with a complex
+ * stretched grid (CSG) multigrid preconditioner.
+ *
+ * The operation follows Reps, Vanroose & bin Zubair, "On the indefinite
+ * Helmholtz equation: complex stretched absorbing boundary layers, iterative
+ * analysis, and preconditioning":
+ *   - the problem  -(Lap + phi(x)) u = chi  (Sec. 4, eq. (Helgen)), phi = k(x)^2,
+ *     on a tensor grid whose interior [a,b] per axis is extended by exterior
+ *     complex scaled (ECS) layers out to [lo,hi] (Sec. 2, eq. (ecstrans), the
+ *     linear map z = r + (x - r) e^{i theta} on the layer), homogeneous
+ *     Dirichlet at the contour ends (eq. (lapctuecs));
+ *   - Shortley-Weller differences on the complex widths (Sec. 3, eq.
+ *     (shortwell)), cell-centred unknowns (Sec. 6);
+ *   - the CSG preconditioner M: the same operator on a grid whose widths are
+ *     all multiplied by beta = e^{i theta_csg} (uniform mode, Sec. 5.3 and eq.
+ *     (CSL-CSG)) or only the interior widths (interior mode, eq.
+ *     (lapctucsg));
+ *   - one multigrid V(1,1) cycle per preconditioner application (Sec. 6.2)
+ *     with weighted Jacobi, full weighting, bilinear/trilinear prolongation,
+ *     rediscretised coarse operators and an exact coarsest solve;
+ *   - right-preconditioned Bi-CGSTAB or IDR(s) (Sec. 6.2), stopped on the
+ *     relative residual ||b - H x|| / ||b|| < tol.
+ *
+ * Conventions for every call:
+ *   - Every call returns an hh_status; nothing aborts or throws across the ABI.
+ *     On a non-OK status hh_last_error() gives a thread-local message.
+ *   - Complex vectors are interleaved (re, im) pairs: HH_C128 = 2 x double
+ *     (16 bytes), HH_C64 = 2 x float (8 bytes); index i + nx*(j + ny*k), x
+ *     fastest (the layout of a contiguous torch/numpy complex array indexed
+ *     [k][j][i]).  Device vectors must be 16-byte aligned (8 for C64).
+ *   - Device pointers are owned by the caller and never retained past the call;
+ *     the library owns only hh_grid objects, the solve work space it attaches
+ *     to a grid, and the server arena.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue their
+ *     work on it; hh_apply_operator and hh_vcycle return without waiting,
+ *     hh_solve and hh_solve_batch synchronise the stream before returning.
+ *   - The library never falls back to the CPU: without a usable gfx950 device
+ *     every compute call returns HH_ERR_HIP.
+ */
+#ifndef HH_H
+#define HH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HH_OK = 0,
+    HH_PENDING = 1,          /* hh_poll: request not finished yet                */
+    HH_ERR_ARG = -1,         /* invalid argument or description                  */
+    HH_ERR_OOM = -2,         /* device allocation failed / footprint over budget */
+    HH_ERR_HIP = -3,         /* HIP runtime error, or no usable device           */
+    HH_ERR_NOCONV = -4,      /* matvec limit reached (x holds the last iterate)  */
+    HH_ERR_BREAKDOWN = -5,   /* Krylov breakdown persisted through the restarts  */
+    HH_ERR_NONFINITE = -6,   /* NaN/Inf in the data or the iteration             */
+    HH_ERR_BUSY = -7,        /* server queue full                                */
+    HH_ERR_TICKET = -8       /* unknown ticket                                   */
+} hh_status;
+
+typedef enum { HH_C128 = 0, HH_C64 = 1 } hh_prec;
+typedef enum { HH_OP_H = 0, HH_OP_M = 1 } hh_op;
+typedef enum { HH_CSG_UNIFORM = 0, HH_CSG_INTERIOR = 1 } hh_csg_mode;
+typedef enum { HH_METHOD_BICGSTAB = 0, HH_METHOD_IDR = 1 } hh_method;
+
+/* Grid description (host memory, read during hh_setup_grid only). */
+typedef struct {
+    int32_t dim;            /* 2 or 3                                                    */
+    int32_t n[3];           /* cells per axis on the finest grid, layers included        */
+    double lo[3], hi[3];    /* real coordinates of the outer Dirichlet ends              */
+    double a[3], b[3];      /* interior [a,b] per axis (ECS turning points), lo<=a<b<=hi;
+                               a == lo (b == hi) means no layer on that side             */
+    double theta_ecs;       /* ECS angle theta_gamma of H, in (0, pi/2)                  */
+    double theta_csg;       /* CSG angle theta_beta of M, in (0, pi/2)                   */
+    int32_t csg_mode;       /* hh_csg_mode                                               */
+    int32_t levels;         /* multigrid levels; 0 = halve while every side is even and
+                               the largest side exceeds 16 (2D) / 8 (3D)                 */
+    int32_t nu1, nu2;       /* smoothing steps; this build supports (1,1)                */
+    double omega;           /* Jacobi weight, e.g. 0.8                                   */
+    const double *phi;      /* host, prod(n) reals: k(x)^2 at the cell centres; NULL ->
+                               phi_const everywhere                                      */
+    double phi_const;
+    int32_t host_only;      /* 1: build the host-side setup only (no device memory);
+                               only hh_grid_query / hh_grid_export / hh_free_grid may
+                               then be called                                            */
+} hh_grid_desc;
+
+typedef struct hh_grid hh_grid;   /* opaque */
+
+/* Builds node maps, Shortley-Weller coefficients of H and M on every level,
+ * the coarse phi hierarchy (mean of children) and the explicit inverse of
+ * the coarsest M (dense LU with partial pivoting), and uploads them.
+ * Errors: HH_ERR_ARG (dim not 2/3; side not divisible by 2^(levels-1);
+ * coarsest grid above 1024 unknowns; theta outside (0, pi/2); a, b outside
+ * [lo, hi]; nu1/nu2 other than 1; singular coarse matrix), HH_ERR_OOM,
+ * HH_ERR_HIP.  *out is set only on HH_OK. */
+hh_status hh_setup_grid(const hh_grid_desc *d, hh_grid **out);
+hh_status hh_free_grid(hh_grid *g);
+
+typedef struct {
+    int32_t dim, levels;
+    int32_t n[16][3];        /* per level                                  */
+    int64_t unknowns;        /* finest N                                   */
+    int32_t coarse_unknowns;
+    uint64_t device_bytes;   /* device memory the grid holds right now     */
+} hh_grid_info;
+hh_status hh_grid_query(const hh_grid *g, hh_grid_info *info);
+
+/* Copies a host-side setup array of the grid (for inspection and tests):
+ * what = 0 aH, 1 cH, 2 dH (ECS coefficients, level 0 only), 3 aM, 4 cM, 5 dM
+ * (CSG coefficients), complex double per unknown of `axis` on `level`;
+ * 6 phi of `level` (N_level doubles); 7 the coarsest inverse (Nc*Nc complex
+ * double, row major).  `bytes` must equal the array size. */
+hh_status hh_grid_export(const hh_grid *g, int32_t what, int32_t level, int32_t axis, void *host_dst,
+                         size_t bytes);
+
+/* y = A x on the finest grid; A = H (ECS operator, prec must be HH_C128) or
+ * M (CSG preconditioner; HH_C128 uses FP64 coefficients, HH_C64 the FP32
+ * copies).  x, y: device, N elements of `prec`, must not overlap. */
+hh_status hh_apply_operator(const hh_grid *g, hh_op op, hh_prec prec, const void *x, void *y, void *stream);
+
+/* u = V(f): one V(1,1) cycle on M from a zero initial guess.
+ * prec = HH_C128: f and u are complex double, all levels in FP64.
+ * prec = HH_C64 : f is complex double, u is complex float, every level
+ *                 computes in FP32 (the mixed-precision preconditioner). */
+hh_status hh_vcycle(const hh_grid *g, hh_prec prec, const void *f, void *u, void *stream);
+
+typedef struct {
+    int32_t method;          /* hh_method                                              */
+    int32_t s;               /* IDR shadow dimension (1..8)                            */
+    double tol;              /* stop when ||b - H x|| / ||b|| < tol                     */
+    int32_t max_matvec;      /* one matvec = one V-cycle + one H apply                  */
+    int32_t max_restarts;    /* restarts from the true residual after a false stop or
+                                a breakdown (e.g. 3)                                    */
+    int32_t vcycle_prec;     /* HH_C128 plain FP64, HH_C64 mixed (FP32 V-cycle)         */
+    int32_t x0_given;        /* 0: start from x = 0; 1: x holds the initial guess       */
+    const void *idr_P;       /* device, N x s complex double, column-major, orthonormal
+                                columns; required for IDR                               */
+    double *history;         /* optional host buffer: ||r||/||b|| after every matvec    */
+    int32_t history_len;
+} hh_solve_opts;
+
+typedef struct {
+    int32_t status;          /* hh_status of this problem                              */
+    int32_t matvecs, iterations, restarts;
+    double rel_res_recurrence;  /* last recurrence residual / ||b||                    */
+    double rel_res_true;        /* ||b - H x|| / ||b|| in FP64 at exit                 */
+    double seconds;             /* wall time inside the call                           */
+} hh_solve_info;
+
+/* Solves H x = b.  b, x: device complex double, N elements.  Fills *info.
+ * HH_ERR_NOCONV / HH_ERR_BREAKDOWN still leave the last iterate in x and a
+ * complete info.  A zero b gives x = 0 with 0 matvecs.  The grid keeps its
+ * solve work space allocated until hh_free_grid. */
+hh_status hh_solve(hh_grid *g, const hh_solve_opts *o, const void *b, void *x, hh_solve_info *info, void *stream);
+
+/* Solves `count` independent problems together: every pass of the method is
+ * one launch over the tiles of all problems still running.  All problems must
+ * use the same method and vcycle_prec; grids must be distinct.  o, b, x and
+ * info are arrays of `count`.  The return value is HH_OK when every problem
+ * converged, otherwise the first non-OK per-problem status. */
+hh_status hh_solve_batch(hh_grid *const *g, int32_t count, const hh_solve_opts *o, const void *const *b,
+                         void *const *x, hh_solve_info *info, void *stream);
+
+/* ---- serving ---------------------------------------------------------- */
+typedef struct {
+    uint64_t hbm_budget_bytes;   /* 0: 80% of the free device memory at creation   */
+    int32_t max_slots;           /* problems on the device at once                 */
+    int32_t device;
+} hh_server_opts;
+
+typedef struct {
+    hh_grid_desc grid;           /* phi (if non-NULL) is copied at submit            */
+    hh_solve_opts opts;          /* history is ignored; IDR needs idr_P_host         */
+    const void *b_host;          /* N complex double, copied at submit               */
+    void *x_host;                /* N complex double; written before hh_poll returns
+                                    HH_OK for this ticket; must stay valid until then */
+    const void *idr_P_host;      /* IDR only: N x s complex double, column-major     */
+} hh_request;
+
+typedef struct {
+    hh_solve_info info;
+    double t_submit, t_admit, t_done;   /* seconds on the server's monotonic clock */
+} hh_result;
+
+typedef struct hh_server hh_server;
+hh_status hh_server_create(const hh_server_opts *o, hh_server **out);
+/* Copies the request and queues it.  HH_ERR_OOM if its device footprint
+ * exceeds the whole budget, HH_ERR_ARG for an invalid description. */
+hh_status hh_submit(hh_server *sv, const hh_request *r, uint64_t *ticket);
+/* HH_PENDING until the solve finished; then HH_OK (result filled, x_host
+ * written, ticket released) -- the solve's own status is in result.info. */
+hh_status hh_poll(hh_server *sv, uint64_t ticket, hh_result *out);
+hh_status hh_server_destroy(hh_server *sv);
+
+typedef struct {
+    uint64_t submitted, admitted, completed, rejected;
+    uint64_t bytes_in_use, bytes_budget, peak_bytes;
+    int32_t active_slots, queued;
+} hh_server_stats;
+hh_status hh_server_query(hh_server *sv, hh_server_stats *st);
+
+const char *hh_last_error(void);
+const char *hh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HH_H */

@@ -1,0 +1,150 @@
+// hh_common.h -- internal types shared by the host setup, the kernels and the
+// C-ABI drivers of the gfx950 Helmholtz solver.
+//
+// Data layout in HBM (one problem):
+//   * per level and axis: three complex coefficient arrays of the rediscretised
+//     preconditioner M (lower a, upper c, centre d = a + c), FP64 and (for the
+//     mixed-precision V-cycle) FP32 copies; level 0 also holds the ECS
+//     operator H's arrays (FP64 only).  O(n) per axis, cache resident.
+//   * phi_l = k^2 per level (N_l reals), FP64 and FP32.
+//   * the explicit inverse of the coarsest M (Nc x Nc, row major), c128/c64.
+//   * per level l >= 1: f_l (restricted residual) and e_l (level solution),
+//     in the precision of the V-cycle.
+//   * solve work space: x, b-copy-free, r, rhat, p, v, t (c128), phat/shat
+//     (c128, or c64 in mixed mode), chunk partial sums, a state block.
+// Complex values are interleaved (re, im), x fastest.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define HH_MAXLEV 16
+#define HH_WG 256                 // threads per workgroup (4 wave64)
+#define HH_PER_SLOT 8             // elements per thread slot in a reduction chunk
+#define HH_CHUNK (HH_WG * HH_PER_SLOT)
+#define HH_NPART 16               // reals per chunk partial record
+#define HH_MAX_COARSE 1024
+#define HH_MAX_S 8
+
+// ---------------------------------------------------------------------------
+// complex helpers (fixed operation order: no FMA contraction, the build uses
+// -ffp-contract=off)
+// ---------------------------------------------------------------------------
+template <typename T> struct V2t;
+template <> struct V2t<double> { using type = double2; };
+template <> struct V2t<float> { using type = float2; };
+template <typename T> using V2 = typename V2t<T>::type;
+
+template <typename T> __host__ __device__ inline V2<T> cmk(T re, T im) { V2<T> z; z.x = re; z.y = im; return z; }
+template <typename T> __host__ __device__ inline V2<T> cadd(V2<T> a, V2<T> b) { return cmk<T>(a.x + b.x, a.y + b.y); }
+template <typename T> __host__ __device__ inline V2<T> csub(V2<T> a, V2<T> b) { return cmk<T>(a.x - b.x, a.y - b.y); }
+template <typename T> __host__ __device__ inline V2<T> cmul(V2<T> a, V2<T> b)
+{
+    return cmk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T> __host__ __device__ inline V2<T> cdiv(V2<T> a, V2<T> b)
+{
+    T d = b.x * b.x + b.y * b.y;
+    return cmk<T>((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+template <typename T> __host__ __device__ inline V2<T> crs(T s, V2<T> a) { return cmk<T>(s * a.x, s * a.y); }
+
+// conversions between the two complex precisions
+template <typename T, typename S> __device__ inline V2<T> ccvt(S v) { return cmk<T>((T)v.x, (T)v.y); }
+
+// ---------------------------------------------------------------------------
+// 32-bit division by a runtime constant (round-up magic number method)
+// ---------------------------------------------------------------------------
+struct FastDiv {
+    uint32_t d, m, l;
+};
+inline FastDiv make_fastdiv(uint32_t d)
+{
+    FastDiv f;
+    f.d = d;
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    f.l = l;
+    f.m = d <= 1 ? 0u : (uint32_t)((((1ull << 32) * ((1ull << l) - d)) / d) + 1);
+    return f;
+}
+__host__ __device__ inline uint32_t fdiv(uint32_t n, FastDiv f)
+{
+    if (f.d == 1) return n;
+#ifdef __HIP_DEVICE_COMPILE__
+    uint32_t t = __umulhi(n, f.m);
+#else
+    uint32_t t = (uint32_t)(((uint64_t)n * f.m) >> 32);
+#endif
+    return (t + ((n - t) >> 1)) >> (f.l - 1);
+}
+
+// ---------------------------------------------------------------------------
+// per-level data of one problem, in one precision
+// ---------------------------------------------------------------------------
+template <typename T> struct LevelDev {
+    int n[3];
+    int64_t N;
+    FastDiv fx, fxy;                 // linear index -> (i, j, k)
+    const V2<T> *a[3], *c[3], *d[3]; // M coefficients per axis
+    const T *phi;
+    V2<T> *f;                        // restricted right-hand side (levels >= 1)
+    V2<T> *e;                        // level solution / correction (levels >= 1)
+};
+
+// vectors a problem can name in a kernel argument
+enum VecSel {
+    VS_X = 0, VS_B, VS_R, VS_RH, VS_P, VS_V, VS_T, VS_PH, VS_SH, VS_IN, VS_OUT, VS_W, VS_Q, VS_TMP,
+    VS_NVEC
+};
+
+// solve phases (first int of every state block)
+enum Phase { PH_RUN = 0, PH_HALF = 1, PH_STOP = 2, PH_IDLE = 3 };
+// stop reasons
+enum Reason { RS_NONE = 0, RS_CONV = 1, RS_MAXMV = 2, RS_BREAK = 3, RS_NONFIN = 4 };
+
+struct SolveState {
+    int phase, reason, mv, it;
+    int max_mv, hist_len, pad0, pad1;
+    double tol, bnorm, rel, true_rel;
+    double2 rho, alpha, omega, beta;
+    // IDR(s)
+    int s, kstep, oldest, startup;   // kstep in 0..s within a cycle; startup steps left
+    double2 om_idr;
+    double2 G[HH_MAX_S * HH_MAX_S];  // row major s x s
+    double2 m[HH_MAX_S];
+    double2 c[HH_MAX_S];
+};
+
+struct ProbDev {
+    int dim, nlev, Nc, nchunk;
+    int n[3];
+    int64_t N;
+    FastDiv fx, fxy;
+    const double2 *aH[3], *cH[3], *dH[3];
+    const double *phi;
+    const LevelDev<double> *L64;     // device array [nlev]
+    const LevelDev<float> *L32;      // device array [nlev] (null if no FP32 set)
+    const double2 *Minv64;
+    const float2 *Minv32;
+    double omega;
+    void *vec[VS_NVEC];
+    double2 *dR, *dX;                // IDR: s columns of N each
+    const double2 *P;                // IDR shadow space, N x s column-major
+    double *part;                    // [nchunk * HH_NPART]
+    SolveState *st;
+    double *hist;                    // device history (optional)
+};
+
+struct Tile {
+    int prob, idx;
+};
+
+// Tile shapes of the fused V-cycle kernels (coarse tile of the down-leg; the
+// up-leg's fine tile is twice it).
+template <int DIM, typename T> struct VTile;
+template <> struct VTile<2, double> { static constexpr int X = 16, Y = 16, Z = 1; };
+template <> struct VTile<2, float> { static constexpr int X = 16, Y = 16, Z = 1; };
+template <> struct VTile<3, double> { static constexpr int X = 4, Y = 4, Z = 4; };
+template <> struct VTile<3, float> { static constexpr int X = 8, Y = 4, Z = 4; };
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }

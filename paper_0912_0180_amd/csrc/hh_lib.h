@@ -1,0 +1,80 @@
+// hh_lib.h -- host-side objects of the library: grids, launch plans, solve
+// work spaces, and the launchers the drivers use.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "hh_common.h"
+#include "hh_setup.h"
+#include "../../include/hh.h"
+
+struct DevList {
+    Tile *t = nullptr;
+    int n = 0;
+};
+
+// Tile lists of every pass for a fixed set of problems (one dimension, one
+// V-cycle precision), plus the device array of their descriptors.
+struct Plan {
+    int count = 0, dim = 2, Lmax = 0;
+    bool fp32 = false;
+    DevList chunks, coarse, down[HH_MAXLEV], up[HH_MAXLEV];
+    int *fin = nullptr;
+    int nfin = 0;
+    ProbDev *probs = nullptr;
+    void *mem = nullptr;
+};
+
+// Solve work space of one grid.
+struct Workspace {
+    int method = -1, fp32 = -1, s = 0, hist_cap = 0;
+    void *mem = nullptr;
+    size_t bytes = 0;
+    double2 *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *t = nullptr;
+    void *ph = nullptr, *sh = nullptr;
+    double2 *w = nullptr, *q = nullptr, *dR = nullptr, *dX = nullptr;
+    void *wlow = nullptr;       // IDR: V-cycle output in the V-cycle precision
+    double *part = nullptr;
+    SolveState *st = nullptr;
+    double *hist = nullptr;
+};
+
+struct hh_grid {
+    HostSetup hs;
+    hh_grid_desc desc{};
+    bool host_only = false;
+    int device = 0;
+    void *dmem = nullptr;
+    size_t dbytes = 0;
+    const double2 *aH[3] = {}, *cH[3] = {}, *dH[3] = {};
+    LevelDev<double> L64h[HH_MAXLEV] = {};
+    LevelDev<float> L32h[HH_MAXLEV] = {};
+    LevelDev<double> *L64 = nullptr;
+    LevelDev<float> *L32 = nullptr;
+    double2 *Minv64 = nullptr;
+    float2 *Minv32 = nullptr;
+    ProbDev pd_static{};
+    ProbDev *pd_static_dev = nullptr;
+    Tile *chunks_dev = nullptr;
+    int nchunks = 0;
+    Plan vplan64, vplan32;   // single-problem V-cycle plans (static descriptor)
+    Plan plan;               // single-problem solve plan
+    int plan_fp32 = -1;
+    Workspace ws;
+    size_t plan_bytes() const { return 0; }
+};
+
+hh_status hh_fail(hh_status st, const char *fmt, ...);
+void grid_fill_prob(const hh_grid *g, ProbDev &pd);
+hh_status grid_vplan(hh_grid *g, bool fp32);
+void workspace_release(Workspace &w);
+void plan_release(Plan &p);
+hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32);
+
+void launch_vcycle(const Plan &pl, const ProbDev *P, int fsel, int osel, const void *fptr, void *optr, hipStream_t s);
+void launch_bicg_iteration(const Plan &pl, hipStream_t s);
+void launch_resid(const Plan &pl, const DevList &tiles, int mode, hipStream_t s);
+void launch_norm(const Plan &pl, const DevList &tiles, int sel, hipStream_t s);
+void launch_zero(const Plan &pl, const DevList &tiles, int sel, hipStream_t s);
+void launch_fin(const Plan &pl, const int *probs, int n, int kind, hipStream_t s);

@@ -1,0 +1,481 @@
+// hh_lib.hip -- grids, launch plans, solver drivers and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hh_common.h"
+#include "hh_kernels.hpp"
+#include "hh_lib.h"
+#include "hh_setup.h"
+
+using namespace hh;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+hh_status hh_fail(hh_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return hh_fail(HH_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------------------
+// device arena: one hipMalloc carved into aligned pieces
+// ---------------------------------------------------------------------------
+struct Carver {
+    char *base = nullptr;
+    size_t used = 0;
+    template <typename X> X *take(size_t count)
+    {
+        X *p = (X *)(base ? base + used : nullptr);
+        used += align256(sizeof(X) * count);
+        return p;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// grid
+// ---------------------------------------------------------------------------
+hh_status grid_upload(hh_grid *g)
+{
+    const HostSetup &hs = g->hs;
+    HIPCHK(hipGetDevice(&g->device));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, g->device));
+    // two passes: size, then carve
+    for (int pass = 0; pass < 2; ++pass) {
+        Carver c;
+        if (pass == 1) {
+            hipError_t e = hipMalloc((void **)&c.base, g->dbytes);
+            if (e != hipSuccess) return hh_fail(HH_ERR_OOM, "hipMalloc(%zu) for the grid: %s", g->dbytes, hipGetErrorString(e));
+            g->dmem = c.base;
+        }
+        for (int a = 0; a < hs.dim; ++a) {
+            g->aH[a] = c.take<double2>(hs.aH[a].size());
+            g->cH[a] = c.take<double2>(hs.cH[a].size());
+            g->dH[a] = c.take<double2>(hs.dH[a].size());
+        }
+        for (int l = 0; l < hs.nlev; ++l) {
+            const HostLevel &L = hs.lev[l];
+            LevelDev<double> &D = g->L64h[l];
+            LevelDev<float> &F = g->L32h[l];
+            for (int a = 0; a < 3; ++a) { D.n[a] = L.n[a]; F.n[a] = L.n[a]; }
+            D.N = F.N = L.N;
+            D.fx = F.fx = make_fastdiv((uint32_t)L.n[0]);
+            D.fxy = F.fxy = make_fastdiv((uint32_t)(L.n[0] * L.n[1]));
+            for (int a = 0; a < 3; ++a) {
+                if (a < hs.dim) {
+                    D.a[a] = c.take<double2>(L.n[a]); D.c[a] = c.take<double2>(L.n[a]); D.d[a] = c.take<double2>(L.n[a]);
+                    F.a[a] = c.take<float2>(L.n[a]); F.c[a] = c.take<float2>(L.n[a]); F.d[a] = c.take<float2>(L.n[a]);
+                } else {
+                    D.a[a] = D.c[a] = D.d[a] = nullptr;
+                    F.a[a] = F.c[a] = F.d[a] = nullptr;
+                }
+            }
+            D.phi = c.take<double>(L.N);
+            F.phi = c.take<float>(L.N);
+            if (l >= 1) {
+                D.f = c.take<double2>(L.N); D.e = c.take<double2>(L.N);
+                F.f = c.take<float2>(L.N); F.e = c.take<float2>(L.N);
+            } else {
+                D.f = D.e = nullptr;
+                F.f = F.e = nullptr;
+            }
+        }
+        g->Minv64 = c.take<double2>((size_t)hs.Nc * hs.Nc);
+        g->Minv32 = c.take<float2>((size_t)hs.Nc * hs.Nc);
+        g->L64 = c.take<LevelDev<double>>(HH_MAXLEV);
+        g->L32 = c.take<LevelDev<float>>(HH_MAXLEV);
+        g->pd_static_dev = c.take<ProbDev>(1);
+        g->chunks_dev = c.take<Tile>(ceil_div(hs.lev[0].N, HH_CHUNK));
+        if (pass == 0) g->dbytes = c.used;
+    }
+    // host staging of every array, then one copy each
+    std::vector<float2> tmp;
+    auto put64 = [&](const void *dst, const void *src, size_t bytes) {
+        return hipMemcpy((void *)dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    auto put32c = [&](const float2 *dst, const std::vector<double2> &src) {
+        tmp.resize(src.size());
+        for (size_t i = 0; i < src.size(); ++i) { tmp[i].x = (float)src[i].x; tmp[i].y = (float)src[i].y; }
+        return hipMemcpy((void *)dst, tmp.data(), sizeof(float2) * tmp.size(), hipMemcpyHostToDevice);
+    };
+    for (int a = 0; a < hs.dim; ++a) {
+        HIPCHK(put64(g->aH[a], hs.aH[a].data(), sizeof(double2) * hs.aH[a].size()));
+        HIPCHK(put64(g->cH[a], hs.cH[a].data(), sizeof(double2) * hs.cH[a].size()));
+        HIPCHK(put64(g->dH[a], hs.dH[a].data(), sizeof(double2) * hs.dH[a].size()));
+    }
+    for (int l = 0; l < hs.nlev; ++l) {
+        const HostLevel &L = hs.lev[l];
+        for (int a = 0; a < hs.dim; ++a) {
+            HIPCHK(put64(g->L64h[l].a[a], L.aM[a].data(), sizeof(double2) * L.n[a]));
+            HIPCHK(put64(g->L64h[l].c[a], L.cM[a].data(), sizeof(double2) * L.n[a]));
+            HIPCHK(put64(g->L64h[l].d[a], L.dM[a].data(), sizeof(double2) * L.n[a]));
+            HIPCHK(put32c(g->L32h[l].a[a], L.aM[a]));
+            HIPCHK(put32c(g->L32h[l].c[a], L.cM[a]));
+            HIPCHK(put32c(g->L32h[l].d[a], L.dM[a]));
+        }
+        HIPCHK(put64(g->L64h[l].phi, L.phi.data(), sizeof(double) * L.N));
+        std::vector<float> p32(L.N);
+        for (int64_t i = 0; i < L.N; ++i) p32[i] = (float)L.phi[i];
+        HIPCHK(put64(g->L32h[l].phi, p32.data(), sizeof(float) * L.N));
+    }
+    HIPCHK(put64(g->Minv64, hs.Minv.data(), sizeof(double2) * hs.Minv.size()));
+    HIPCHK(put32c(g->Minv32, hs.Minv));
+    HIPCHK(put64(g->L64, g->L64h, sizeof(LevelDev<double>) * HH_MAXLEV));
+    HIPCHK(put64(g->L32, g->L32h, sizeof(LevelDev<float>) * HH_MAXLEV));
+    // static descriptor (no solve state) for hh_apply_operator / hh_vcycle
+    ProbDev &pd = g->pd_static;
+    grid_fill_prob(g, pd);
+    HIPCHK(put64(g->pd_static_dev, &pd, sizeof(ProbDev)));
+    std::vector<Tile> ch(ceil_div(hs.lev[0].N, HH_CHUNK));
+    for (size_t i = 0; i < ch.size(); ++i) ch[i] = Tile{0, (int)i};
+    HIPCHK(put64(g->chunks_dev, ch.data(), sizeof(Tile) * ch.size()));
+    g->nchunks = (int)ch.size();
+    return HH_OK;
+}
+
+void grid_fill_prob(const hh_grid *g, ProbDev &pd)
+{
+    const HostSetup &hs = g->hs;
+    memset(&pd, 0, sizeof pd);
+    pd.dim = hs.dim;
+    pd.nlev = hs.nlev;
+    pd.Nc = hs.Nc;
+    for (int a = 0; a < 3; ++a) pd.n[a] = hs.lev[0].n[a];
+    pd.N = hs.lev[0].N;
+    pd.nchunk = ceil_div(pd.N, HH_CHUNK);
+    pd.fx = make_fastdiv((uint32_t)pd.n[0]);
+    pd.fxy = make_fastdiv((uint32_t)(pd.n[0] * pd.n[1]));
+    for (int a = 0; a < 3; ++a) {
+        pd.aH[a] = a < hs.dim ? g->aH[a] : nullptr;
+        pd.cH[a] = a < hs.dim ? g->cH[a] : nullptr;
+        pd.dH[a] = a < hs.dim ? g->dH[a] : nullptr;
+    }
+    pd.phi = g->L64h[0].phi;
+    pd.L64 = g->L64;
+    pd.L32 = g->L32;
+    pd.Minv64 = g->Minv64;
+    pd.Minv32 = g->Minv32;
+    pd.omega = hs.omega;
+}
+
+static void grid_release(hh_grid *g)
+{
+    if (!g) return;
+    if (g->dmem) (void)hipFree(g->dmem);
+    workspace_release(g->ws);
+    plan_release(g->plan);
+    delete g;
+}
+
+// ---------------------------------------------------------------------------
+// launch plans: tile lists of every pass for a set of problems
+// ---------------------------------------------------------------------------
+static void vtile_counts(int dim, bool fp32, const HostLevel &Lf, const HostLevel &Lc, int &ndown, int &nup)
+{
+    int CX, CY, CZ;
+    if (dim == 2) { CX = 16; CY = 16; CZ = 1; }
+    else if (!fp32) { CX = VTile<3, double>::X; CY = VTile<3, double>::Y; CZ = VTile<3, double>::Z; }
+    else { CX = VTile<3, float>::X; CY = VTile<3, float>::Y; CZ = VTile<3, float>::Z; }
+    ndown = ceil_div(Lc.n[0], CX) * ceil_div(Lc.n[1], CY) * (dim == 3 ? ceil_div(Lc.n[2], CZ) : 1);
+    nup = ceil_div(Lf.n[0], 2 * CX) * ceil_div(Lf.n[1], 2 * CY) * (dim == 3 ? ceil_div(Lf.n[2], 2 * CZ) : 1);
+}
+
+void plan_release(Plan &p)
+{
+    if (p.mem) (void)hipFree(p.mem);
+    p = Plan();
+}
+
+hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
+{
+    plan_release(pl);
+    pl.count = (int)G.size();
+    pl.dim = G.empty() ? 2 : G[0]->hs.dim;
+    pl.fp32 = fp32;
+    pl.Lmax = 0;
+    for (auto *g : G) pl.Lmax = std::max(pl.Lmax, g->hs.nlev);
+    std::vector<Tile> chunks, coarse, down[HH_MAXLEV], up[HH_MAXLEV];
+    std::vector<int> fin;
+    for (int q = 0; q < pl.count; ++q) {
+        const HostSetup &hs = G[q]->hs;
+        int nch = ceil_div(hs.lev[0].N, HH_CHUNK);
+        for (int i = 0; i < nch; ++i) chunks.push_back(Tile{q, i});
+        for (int i = 0; i < ceil_div(hs.Nc, 4); ++i) coarse.push_back(Tile{q, i});
+        for (int l = 0; l + 1 < hs.nlev; ++l) {
+            int nd, nu;
+            vtile_counts(hs.dim, fp32, hs.lev[l], hs.lev[l + 1], nd, nu);
+            for (int i = 0; i < nd; ++i) down[l].push_back(Tile{q, i});
+            for (int i = 0; i < nu; ++i) up[l].push_back(Tile{q, i});
+        }
+        fin.push_back(q);
+    }
+    size_t bytes = align256(sizeof(Tile) * chunks.size()) + align256(sizeof(Tile) * coarse.size()) +
+                   align256(sizeof(int) * fin.size()) + align256(sizeof(ProbDev) * pl.count);
+    for (int l = 0; l < HH_MAXLEV; ++l) bytes += align256(sizeof(Tile) * down[l].size()) + align256(sizeof(Tile) * up[l].size());
+    hipError_t e = hipMalloc(&pl.mem, bytes);
+    if (e != hipSuccess) return hh_fail(HH_ERR_OOM, "hipMalloc(%zu) for a launch plan: %s", bytes, hipGetErrorString(e));
+    Carver c;
+    c.base = (char *)pl.mem;
+    auto up_list = [&](std::vector<Tile> &v, DevList &d) -> hipError_t {
+        d.n = (int)v.size();
+        d.t = c.take<Tile>(v.size());
+        return v.empty() ? hipSuccess : hipMemcpy(d.t, v.data(), sizeof(Tile) * v.size(), hipMemcpyHostToDevice);
+    };
+    HIPCHK(up_list(chunks, pl.chunks));
+    HIPCHK(up_list(coarse, pl.coarse));
+    for (int l = 0; l < HH_MAXLEV; ++l) {
+        HIPCHK(up_list(down[l], pl.down[l]));
+        HIPCHK(up_list(up[l], pl.up[l]));
+    }
+    pl.fin = c.take<int>(fin.size());
+    pl.nfin = (int)fin.size();
+    HIPCHK(hipMemcpy(pl.fin, fin.data(), sizeof(int) * fin.size(), hipMemcpyHostToDevice));
+    pl.probs = c.take<ProbDev>(pl.count);
+    return HH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+#define LAUNCH(kernel, n, stream, ...)                                                  \
+    do {                                                                                \
+        if ((n) > 0) hipLaunchKernelGGL(kernel, dim3(n), dim3(HH_WG), 0, stream, __VA_ARGS__); \
+    } while (0)
+
+template <int DIM, typename T>
+static void vcycle_t(const Plan &pl, const ProbDev *P, int fsel, int osel, const void *fptr, void *optr, hipStream_t s)
+{
+    using C = V2<T>;
+    using TO = V2<T>;  // level-0 output in the V-cycle precision
+    for (int l = 0; l + 1 < pl.Lmax; ++l) {
+        if (l == 0) LAUNCH((k_vdown<DIM, T, double2>), pl.down[l].n, s, P, pl.down[l].t, l, fsel, fptr);
+        else LAUNCH((k_vdown<DIM, T, C>), pl.down[l].n, s, P, pl.down[l].t, l, fsel, fptr);
+    }
+    LAUNCH((k_coarse<T>), pl.coarse.n, s, P, pl.coarse.t);
+    for (int l = pl.Lmax - 2; l >= 0; --l) {
+        if (l == 0) LAUNCH((k_vup<DIM, T, double2, TO>), pl.up[l].n, s, P, pl.up[l].t, l, fsel, osel, fptr, optr);
+        else LAUNCH((k_vup<DIM, T, C, C>), pl.up[l].n, s, P, pl.up[l].t, l, fsel, osel, fptr, optr);
+    }
+}
+
+void launch_vcycle(const Plan &pl, const ProbDev *P, int fsel, int osel, const void *fptr, void *optr, hipStream_t s)
+{
+    if (pl.dim == 2) {
+        if (pl.fp32) vcycle_t<2, float>(pl, P, fsel, osel, fptr, optr, s);
+        else vcycle_t<2, double>(pl, P, fsel, osel, fptr, optr, s);
+    } else {
+        if (pl.fp32) vcycle_t<3, float>(pl, P, fsel, osel, fptr, optr, s);
+        else vcycle_t<3, double>(pl, P, fsel, osel, fptr, optr, s);
+    }
+}
+
+template <int DIM, typename SP>
+static void bicg_iter_t(const Plan &pl, hipStream_t s)
+{
+    const ProbDev *P = pl.probs;
+    LAUNCH(k_bicg_p, pl.chunks.n, s, P, pl.chunks.t);
+    launch_vcycle(pl, P, VS_P, VS_PH, nullptr, nullptr, s);
+    LAUNCH((k_bicg_v<DIM, SP>), pl.chunks.n, s, P, pl.chunks.t);
+    LAUNCH(k_fin, pl.nfin, s, P, pl.fin, (int)FIN_ALPHA);
+    LAUNCH(k_bicg_s, pl.chunks.n, s, P, pl.chunks.t);
+    LAUNCH(k_fin, pl.nfin, s, P, pl.fin, (int)FIN_S);
+    launch_vcycle(pl, P, VS_R, VS_SH, nullptr, nullptr, s);
+    LAUNCH((k_bicg_t<DIM, SP>), pl.chunks.n, s, P, pl.chunks.t);
+    LAUNCH(k_fin, pl.nfin, s, P, pl.fin, (int)FIN_OMEGA);
+    LAUNCH((k_bicg_xr<SP>), pl.chunks.n, s, P, pl.chunks.t);
+    LAUNCH(k_fin, pl.nfin, s, P, pl.fin, (int)FIN_RHO);
+}
+
+void launch_bicg_iteration(const Plan &pl, hipStream_t s)
+{
+    if (pl.dim == 2) {
+        if (pl.fp32) bicg_iter_t<2, float2>(pl, s);
+        else bicg_iter_t<2, double2>(pl, s);
+    } else {
+        if (pl.fp32) bicg_iter_t<3, float2>(pl, s);
+        else bicg_iter_t<3, double2>(pl, s);
+    }
+}
+
+void launch_resid(const Plan &pl, const DevList &tiles, int mode, hipStream_t s)
+{
+    if (pl.dim == 2) LAUNCH(k_resid<2>, tiles.n, s, pl.probs, tiles.t, mode);
+    else LAUNCH(k_resid<3>, tiles.n, s, pl.probs, tiles.t, mode);
+}
+
+void launch_norm(const Plan &pl, const DevList &tiles, int sel, hipStream_t s)
+{
+    LAUNCH(k_norm, tiles.n, s, pl.probs, tiles.t, sel);
+}
+
+void launch_zero(const Plan &pl, const DevList &tiles, int sel, hipStream_t s)
+{
+    LAUNCH(k_zero, tiles.n, s, pl.probs, tiles.t, sel);
+}
+
+void launch_fin(const Plan &pl, const int *probs, int n, int kind, hipStream_t s)
+{
+    LAUNCH(k_fin, n, s, pl.probs, probs, kind);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI: grids, apply, V-cycle
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *hh_last_error(void) { return g_err.c_str(); }
+const char *hh_version(void) { return "hh 0.1 gfx950"; }
+
+hh_status hh_setup_grid(const hh_grid_desc *d, hh_grid **out)
+{
+    if (!out) return hh_fail(HH_ERR_ARG, "out is null");
+    *out = nullptr;
+    hh_grid *g = new hh_grid();
+    std::string err;
+    hh_status st = host_setup(d, g->hs, err);
+    if (st != HH_OK) {
+        delete g;
+        return hh_fail(st, "%s", err.c_str());
+    }
+    g->desc = *d;
+    g->desc.phi = nullptr;
+    g->host_only = d->host_only != 0;
+    if (!g->host_only) {
+        st = grid_upload(g);
+        if (st != HH_OK) {
+            grid_release(g);
+            return st;
+        }
+    }
+    *out = g;
+    return HH_OK;
+}
+
+hh_status hh_free_grid(hh_grid *g)
+{
+    if (!g) return HH_OK;
+    grid_release(g);
+    return HH_OK;
+}
+
+hh_status hh_grid_query(const hh_grid *g, hh_grid_info *info)
+{
+    if (!g || !info) return hh_fail(HH_ERR_ARG, "null argument");
+    memset(info, 0, sizeof *info);
+    info->dim = g->hs.dim;
+    info->levels = g->hs.nlev;
+    for (int l = 0; l < g->hs.nlev; ++l)
+        for (int a = 0; a < 3; ++a) info->n[l][a] = g->hs.lev[l].n[a];
+    info->unknowns = g->hs.lev[0].N;
+    info->coarse_unknowns = g->hs.Nc;
+    info->device_bytes = g->dbytes + g->ws.bytes + g->plan_bytes();
+    return HH_OK;
+}
+
+hh_status hh_grid_export(const hh_grid *g, int32_t what, int32_t level, int32_t axis, void *host_dst, size_t bytes)
+{
+    if (!g || !host_dst) return hh_fail(HH_ERR_ARG, "null argument");
+    const HostSetup &hs = g->hs;
+    if (level < 0 || level >= hs.nlev) return hh_fail(HH_ERR_ARG, "level %d out of range", level);
+    const void *src = nullptr;
+    size_t need = 0;
+    if (what >= 0 && what <= 5) {
+        if (axis < 0 || axis >= hs.dim) return hh_fail(HH_ERR_ARG, "axis %d out of range", axis);
+        if (what <= 2 && level != 0) return hh_fail(HH_ERR_ARG, "H coefficients exist on level 0 only");
+        const std::vector<double2> *v = what == 0 ? &hs.aH[axis] : what == 1 ? &hs.cH[axis] : what == 2 ? &hs.dH[axis]
+                                      : what == 3 ? &hs.lev[level].aM[axis] : what == 4 ? &hs.lev[level].cM[axis]
+                                                  : &hs.lev[level].dM[axis];
+        src = v->data();
+        need = sizeof(double2) * v->size();
+    } else if (what == 6) {
+        src = hs.lev[level].phi.data();
+        need = sizeof(double) * hs.lev[level].phi.size();
+    } else if (what == 7) {
+        src = hs.Minv.data();
+        need = sizeof(double2) * hs.Minv.size();
+    } else {
+        return hh_fail(HH_ERR_ARG, "unknown export %d", what);
+    }
+    if (bytes != need) return hh_fail(HH_ERR_ARG, "export needs %zu bytes, got %zu", need, bytes);
+    memcpy(host_dst, src, need);
+    return HH_OK;
+}
+
+hh_status hh_apply_operator(const hh_grid *g, hh_op op, hh_prec prec, const void *x, void *y, void *stream)
+{
+    if (!g || !x || !y) return hh_fail(HH_ERR_ARG, "null argument");
+    if (g->host_only) return hh_fail(HH_ERR_ARG, "grid was built host-only");
+    if (x == y) return hh_fail(HH_ERR_ARG, "x and y must not overlap");
+    hipStream_t s = (hipStream_t)stream;
+    const ProbDev *P = g->pd_static_dev;
+    const int n = g->nchunks;
+    if (op == HH_OP_H) {
+        if (prec != HH_C128) return hh_fail(HH_ERR_ARG, "H is applied in complex double only");
+        if (g->hs.dim == 2) LAUNCH(k_applyH<2>, n, s, P, g->chunks_dev, x, y);
+        else LAUNCH(k_applyH<3>, n, s, P, g->chunks_dev, x, y);
+    } else if (op == HH_OP_M) {
+        if (prec == HH_C128) {
+            if (g->hs.dim == 2) LAUNCH((k_applyM<2, double>), n, s, P, g->chunks_dev, x, y);
+            else LAUNCH((k_applyM<3, double>), n, s, P, g->chunks_dev, x, y);
+        } else if (prec == HH_C64) {
+            if (g->hs.dim == 2) LAUNCH((k_applyM<2, float>), n, s, P, g->chunks_dev, x, y);
+            else LAUNCH((k_applyM<3, float>), n, s, P, g->chunks_dev, x, y);
+        } else {
+            return hh_fail(HH_ERR_ARG, "unknown precision %d", (int)prec);
+        }
+    } else {
+        return hh_fail(HH_ERR_ARG, "unknown operator %d", (int)op);
+    }
+    HIPCHK(hipGetLastError());
+    return HH_OK;
+}
+
+hh_status hh_vcycle(const hh_grid *g, hh_prec prec, const void *f, void *u, void *stream)
+{
+    if (!g || !f || !u) return hh_fail(HH_ERR_ARG, "null argument");
+    if (g->host_only) return hh_fail(HH_ERR_ARG, "grid was built host-only");
+    if (f == u) return hh_fail(HH_ERR_ARG, "f and u must not overlap");
+    if (prec != HH_C128 && prec != HH_C64) return hh_fail(HH_ERR_ARG, "unknown precision %d", (int)prec);
+    hh_grid *gm = const_cast<hh_grid *>(g);
+    hh_status st = grid_vplan(gm, prec == HH_C64);
+    if (st != HH_OK) return st;
+    const Plan &pl = prec == HH_C64 ? gm->vplan32 : gm->vplan64;
+    launch_vcycle(pl, g->pd_static_dev, VS_IN, VS_OUT, f, u, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
+    return HH_OK;
+}
+
+} // extern "C"
+
+hh_status grid_vplan(hh_grid *g, bool fp32)
+{
+    Plan &pl = fp32 ? g->vplan32 : g->vplan64;
+    if (pl.mem) return HH_OK;
+    std::vector<const hh_grid *> G{g};
+    return plan_build(pl, G, fp32);
+}

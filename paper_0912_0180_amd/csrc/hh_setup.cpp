@@ -1,0 +1,282 @@
+// hh_setup.cpp -- host-side setup of one grid.
+//
+// Per axis and level the unknowns are cell centres; the two Dirichlet ends
+// are the outer edges lo and hi (half a cell from the first/last centre).
+// Node maps (paper Sec. 2, eq. (ecstrans) with Simon's linear exterior
+// scaling; Sec. 5.3 for the CSG map of the preconditioner):
+//   H (ECS):  z = a + (x - a) e^{i th_g} for x < a,  x on [a, b],
+//             z = b + (x - b) e^{i th_g} for x > b
+//   M (CSG, uniform):  z_M = beta z_H with beta = e^{i th_b}
+//   M (CSG, interior): interior widths times beta, layer widths unchanged.
+// Shortley-Weller coefficients (Sec. 3, eq. (shortwell)) at node j with
+// hl = z_j - z_{j-1}, hr = z_{j+1} - z_j, s = hl + hr:
+//   a_j = 2 / (hl s),  c_j = 2 / (hr s),  d_j = a_j + c_j
+// so that -u'' ~ -a_j u_{j-1} + d_j u_j - c_j u_{j+1}.
+// Coarse levels rediscretise on the halved grid; coarse phi is the mean of
+// the 2^d children.  The coarsest M is assembled densely (column q = M e_q),
+// factorised by LU with partial pivoting and inverted explicitly (the
+// paper's multigrid used a direct "backslash" solve on its hierarchy).
+//
+// All arithmetic follows the fixed operation order of the device kernels
+// (complex multiply/divide formulas of hh_common.h, no FMA contraction).
+#include "hh_setup.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace {
+
+double2 ecs_map(double x, double a, double b, double c, double s)
+{
+    if (x < a) {
+        double t = x - a;
+        return cmk<double>(a + t * c, t * s);
+    }
+    if (x > b) {
+        double t = x - b;
+        return cmk<double>(b + t * c, t * s);
+    }
+    return cmk<double>(x, 0.0);
+}
+
+double2 csg_map(double x, double a, double b, double cg, double sg, double cb, double sb, int mode)
+{
+    if (mode == HH_CSG_UNIFORM) return cmul<double>(cmk<double>(cb, sb), ecs_map(x, a, b, cg, sg));
+    if (x < a) {
+        double t = x - a;
+        return cmk<double>(a * cb + t * cg, a * sb + t * sg);
+    }
+    if (x > b) {
+        double t = x - b;
+        return cmk<double>(b * cb + t * cg, b * sb + t * sg);
+    }
+    return cmk<double>(x * cb, x * sb);
+}
+
+void sw(int n, const std::vector<double2> &z, std::vector<double2> &A, std::vector<double2> &C,
+        std::vector<double2> &D)
+{
+    A.resize(n);
+    C.resize(n);
+    D.resize(n);
+    const double2 two = cmk<double>(2.0, 0.0);
+    for (int j = 1; j <= n; ++j) {
+        double2 hl = csub<double>(z[j], z[j - 1]);
+        double2 hr = csub<double>(z[j + 1], z[j]);
+        double2 s = cadd<double>(hl, hr);
+        double2 aj = cdiv<double>(two, cmul<double>(hl, s));
+        double2 cj = cdiv<double>(two, cmul<double>(hr, s));
+        A[j - 1] = aj;
+        C[j - 1] = cj;
+        D[j - 1] = cadd<double>(aj, cj);
+    }
+}
+
+double abs1(double2 z) { return std::fabs(z.x) + std::fabs(z.y); }
+
+// LU with partial pivoting (first maximum of |re|+|im|), k-i-j order.
+bool lu(std::vector<double2> &A, int n, std::vector<int> &perm)
+{
+    perm.resize(n);
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = abs1(A[(size_t)k * n + k]);
+        for (int i = k + 1; i < n; ++i) {
+            double v = abs1(A[(size_t)i * n + k]);
+            if (v > best) {
+                best = v;
+                p = i;
+            }
+        }
+        if (best == 0.0) return false;
+        if (p != k) {
+            for (int j = 0; j < n; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
+            std::swap(perm[k], perm[p]);
+        }
+        const double2 piv = A[(size_t)k * n + k];
+        for (int i = k + 1; i < n; ++i) {
+            double2 l = cdiv<double>(A[(size_t)i * n + k], piv);
+            A[(size_t)i * n + k] = l;
+            double2 *ri = &A[(size_t)i * n];
+            const double2 *rk = &A[(size_t)k * n];
+            for (int j = k + 1; j < n; ++j) ri[j] = csub<double>(ri[j], cmul<double>(l, rk[j]));
+        }
+    }
+    return true;
+}
+
+void lu_solve_unit(const std::vector<double2> &LU, int n, const std::vector<int> &perm, int col, double2 *x)
+{
+    for (int i = 0; i < n; ++i) {
+        double2 s = cmk<double>(perm[i] == col ? 1.0 : 0.0, 0.0);
+        for (int j = 0; j < i; ++j) s = csub<double>(s, cmul<double>(LU[(size_t)i * n + j], x[j]));
+        x[i] = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double2 s = x[i];
+        for (int j = i + 1; j < n; ++j) s = csub<double>(s, cmul<double>(LU[(size_t)i * n + j], x[j]));
+        x[i] = cdiv<double>(s, LU[(size_t)i * n + i]);
+    }
+}
+
+} // namespace
+
+int auto_levels(int dim, const int *n)
+{
+    const int thr = dim == 3 ? 8 : 16;
+    int m[3] = {n[0], n[1], dim == 3 ? n[2] : 1};
+    int nl = 1;
+    for (;;) {
+        bool even = true;
+        int mx = 0;
+        for (int d = 0; d < dim; ++d) {
+            if (m[d] % 2) even = false;
+            if (m[d] > mx) mx = m[d];
+        }
+        if (!even || mx <= thr || nl >= HH_MAXLEV) break;
+        for (int d = 0; d < dim; ++d) m[d] /= 2;
+        ++nl;
+    }
+    return nl;
+}
+
+void host_apply_M(const HostSetup &hs, int lev, const double2 *x, double2 *y)
+{
+    const HostLevel &L = hs.lev[lev];
+    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const double2 zero = cmk<double>(0.0, 0.0);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int64_t p = i + sy * j + sz * k;
+                double2 d = L.dM[0][i];
+                d = cadd<double>(d, L.dM[1][j]);
+                if (hs.dim == 3) d = cadd<double>(d, L.dM[2][k]);
+                double2 D = cmk<double>(d.x - L.phi[p], d.y);
+                double2 t = cmul<double>(D, x[p]);
+                t = csub<double>(t, cmul<double>(L.aM[0][i], i > 0 ? x[p - 1] : zero));
+                t = csub<double>(t, cmul<double>(L.cM[0][i], i < nx - 1 ? x[p + 1] : zero));
+                t = csub<double>(t, cmul<double>(L.aM[1][j], j > 0 ? x[p - sy] : zero));
+                t = csub<double>(t, cmul<double>(L.cM[1][j], j < ny - 1 ? x[p + sy] : zero));
+                if (hs.dim == 3) {
+                    t = csub<double>(t, cmul<double>(L.aM[2][k], k > 0 ? x[p - sz] : zero));
+                    t = csub<double>(t, cmul<double>(L.cM[2][k], k < nz - 1 ? x[p + sz] : zero));
+                }
+                y[p] = t;
+            }
+}
+
+hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err)
+{
+    char buf[256];
+    if (!d) { err = "null grid description"; return HH_ERR_ARG; }
+    if (d->dim != 2 && d->dim != 3) { err = "dim must be 2 or 3"; return HH_ERR_ARG; }
+    const int dim = d->dim;
+    const double half_pi = 1.5707963267948966;
+    if (!(d->theta_ecs > 0.0 && d->theta_ecs < half_pi)) { err = "theta_ecs must lie in (0, pi/2)"; return HH_ERR_ARG; }
+    if (!(d->theta_csg > 0.0 && d->theta_csg < half_pi)) { err = "theta_csg must lie in (0, pi/2)"; return HH_ERR_ARG; }
+    if (d->csg_mode != HH_CSG_UNIFORM && d->csg_mode != HH_CSG_INTERIOR) { err = "csg_mode must be 0 or 1"; return HH_ERR_ARG; }
+    if (d->nu1 != 1 || d->nu2 != 1) { err = "only the V(1,1) cycle is supported (nu1 = nu2 = 1)"; return HH_ERR_ARG; }
+    if (!(d->omega > 0.0 && d->omega < 2.0)) { err = "omega must lie in (0, 2)"; return HH_ERR_ARG; }
+    int64_t N = 1;
+    for (int a = 0; a < dim; ++a) {
+        if (d->n[a] < 2) { err = "every side needs at least 2 cells"; return HH_ERR_ARG; }
+        if (!(d->lo[a] <= d->a[a] && d->a[a] < d->b[a] && d->b[a] <= d->hi[a] && d->lo[a] < d->hi[a])) {
+            snprintf(buf, sizeof buf, "axis %d: need lo <= a < b <= hi", a);
+            err = buf;
+            return HH_ERR_ARG;
+        }
+        N *= d->n[a];
+    }
+    if (N >= ((int64_t)1 << 31)) { err = "more than 2^31 - 1 unknowns"; return HH_ERR_ARG; }
+    int nl = d->levels > 0 ? d->levels : auto_levels(dim, d->n);
+    if (nl > HH_MAXLEV) { err = "too many levels"; return HH_ERR_ARG; }
+    if (nl < 2) { err = "the multigrid preconditioner needs at least 2 levels (set levels, or use a larger grid)"; return HH_ERR_ARG; }
+    for (int a = 0; a < dim; ++a)
+        if (d->n[a] % (1 << (nl - 1))) {
+            snprintf(buf, sizeof buf, "side %d (%d cells) is not divisible by 2^(levels-1) = %d", a, d->n[a], 1 << (nl - 1));
+            err = buf;
+            return HH_ERR_ARG;
+        }
+    int64_t Nc = 1;
+    for (int a = 0; a < dim; ++a) Nc *= d->n[a] >> (nl - 1);
+    if (Nc > HH_MAX_COARSE) {
+        snprintf(buf, sizeof buf, "coarsest grid has %lld unknowns (limit %d); use more levels",
+                 (long long)Nc, HH_MAX_COARSE);
+        err = buf;
+        return HH_ERR_ARG;
+    }
+    hs.dim = dim;
+    hs.nlev = nl;
+    hs.omega = d->omega;
+    const double cg = std::cos(d->theta_ecs), sg = std::sin(d->theta_ecs);
+    const double cb = std::cos(d->theta_csg), sb = std::sin(d->theta_csg);
+    for (int l = 0; l < nl; ++l) {
+        HostLevel &L = hs.lev[l];
+        L.N = 1;
+        for (int a = 0; a < 3; ++a) {
+            L.n[a] = a < dim ? d->n[a] >> l : 1;
+            L.N *= L.n[a];
+        }
+        for (int a = 0; a < dim; ++a) {
+            const int n = L.n[a];
+            const double lo = d->lo[a], hi = d->hi[a], h = (hi - lo) / (double)n;
+            std::vector<double> x(n + 2);
+            x[0] = lo;
+            for (int j = 1; j <= n; ++j) x[j] = lo + ((double)j - 0.5) * h;
+            x[n + 1] = hi;
+            std::vector<double2> zH(n + 2), zM(n + 2);
+            for (int j = 0; j <= n + 1; ++j) {
+                zH[j] = ecs_map(x[j], d->a[a], d->b[a], cg, sg);
+                zM[j] = csg_map(x[j], d->a[a], d->b[a], cg, sg, cb, sb, d->csg_mode);
+            }
+            sw(n, zM, L.aM[a], L.cM[a], L.dM[a]);
+            if (l == 0) sw(n, zH, hs.aH[a], hs.cH[a], hs.dH[a]);
+        }
+        L.phi.resize(L.N);
+        if (l == 0) {
+            for (int64_t p = 0; p < L.N; ++p) {
+                double v = d->phi ? d->phi[p] : d->phi_const;
+                if (!std::isfinite(v)) { err = "phi has a non-finite value"; return HH_ERR_ARG; }
+                L.phi[p] = v;
+            }
+        } else {
+            const HostLevel &F = hs.lev[l - 1];
+            const double scale = dim == 2 ? 0.25 : 0.125;
+            const int cz = dim == 3 ? 2 : 1;
+            for (int k = 0; k < L.n[2]; ++k)
+                for (int j = 0; j < L.n[1]; ++j)
+                    for (int i = 0; i < L.n[0]; ++i) {
+                        double s = 0.0;
+                        for (int dz = 0; dz < cz; ++dz)
+                            for (int dy = 0; dy < 2; ++dy)
+                                for (int dx = 0; dx < 2; ++dx) {
+                                    int64_t fi = (2 * i + dx) + (int64_t)F.n[0] * ((2 * j + dy) + (int64_t)F.n[1] * (cz == 2 ? 2 * k + dz : k));
+                                    s = s + F.phi[fi];
+                                }
+                        L.phi[i + (int64_t)L.n[0] * (j + (int64_t)L.n[1] * k)] = s * scale;
+                    }
+        }
+    }
+    // coarsest inverse
+    const int n = (int)Nc;
+    hs.Nc = n;
+    std::vector<double2> A((size_t)n * n), e(n), col(n);
+    for (int q = 0; q < n; ++q) {
+        for (int p = 0; p < n; ++p) e[p] = cmk<double>(p == q ? 1.0 : 0.0, 0.0);
+        host_apply_M(hs, nl - 1, e.data(), col.data());
+        for (int p = 0; p < n; ++p) A[(size_t)p * n + q] = col[p];
+    }
+    std::vector<int> perm;
+    if (!lu(A, n, perm)) { err = "the coarsest preconditioner matrix is singular"; return HH_ERR_ARG; }
+    hs.Minv.assign((size_t)n * n, cmk<double>(0.0, 0.0));
+    std::vector<double2> x(n);
+    for (int c = 0; c < n; ++c) {
+        lu_solve_unit(A, n, perm, c, x.data());
+        for (int p = 0; p < n; ++p) hs.Minv[(size_t)p * n + c] = x[p];
+    }
+    return HH_OK;
+}

@@ -1,0 +1,34 @@
+// hh_setup.h -- host-side setup of one grid: node maps, Shortley-Weller
+// coefficients, coarse phi, explicit inverse of the coarsest preconditioner.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "hh_common.h"
+#include "../../include/hh.h"
+
+struct HostLevel {
+    int n[3] = {1, 1, 1};
+    int64_t N = 1;
+    std::vector<double2> aM[3], cM[3], dM[3];
+    std::vector<double> phi;
+};
+
+struct HostSetup {
+    int dim = 2, nlev = 1;
+    double omega = 0.8;
+    std::vector<double2> aH[3], cH[3], dH[3];   // finest level, ECS operator
+    HostLevel lev[HH_MAXLEV];
+    int Nc = 0;
+    std::vector<double2> Minv;                  // Nc x Nc row major
+};
+
+// Validates the description and fills hs.  Returns HH_OK or HH_ERR_ARG with
+// a message in err.
+hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err);
+
+// Number of levels the automatic rule picks for sides n[0..dim).
+int auto_levels(int dim, const int *n);
+
+// Host evaluation of y = M x on one level (used to build the coarse matrix).
+void host_apply_M(const HostSetup &hs, int lev, const double2 *x, double2 *y);

@@ -1,0 +1,127 @@
+"""CPU tests of the C-ABI library: it loads, exports every symbol include/hh.h
+declares, validates descriptions, and its host-side setup (node maps,
+Shortley-Weller coefficients, coarse phi, coarsest inverse) equals the
+oracle's value for value.  No GPU compute call is made here."""
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_0912_0180_amd import hh
+from paper_0912_0180_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "hh.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hh_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = hh.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(names) == sorted(hh.EXPORTS)
+    assert b"gfx950" in L.hh_version()
+
+
+def host_grid(desc, phi=None):
+    return hh.Grid(desc, phi, host_only=True)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c1_interior", "c3_small", "c2_small"])
+def test_host_setup_equals_oracle_bitwise(oracle_mod, cfg):
+    if cfg == "c1":
+        c = W.c1()
+    elif cfg == "c1_interior":
+        c = W.c1(mode=1)
+    elif cfg == "c2_small":
+        c = W.c2(n=128, levels=4)
+    else:
+        c = W.c3(n=32, layer=4, method="bicgstab")
+    g = host_grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    assert g.levels == o.nlev and g.Nc == o.Nc
+    for lev in range(g.levels):
+        assert g.level_dims[lev][: g.dim] == o.level_dims(lev)[: g.dim]
+        for ax in range(g.dim):
+            names = ["aM", "cM", "dM"] + (["aH", "cH", "dH"] if lev == 0 else [])
+            for w in names:
+                a, b = g.export(w, lev, ax), o.coeffs(lev, ax, w)
+                assert np.array_equal(a.view(np.float64), b.view(np.float64)), (lev, ax, w)
+        assert np.array_equal(g.export("phi", lev), o.phi(lev))
+    assert np.array_equal(g.export("Minv").view(np.float64), o.coarse_inverse().view(np.float64))
+
+
+def bad(desc, **kw):
+    d = dict(desc)
+    d.update(kw)
+    return d
+
+
+def test_invalid_descriptions_are_rejected():
+    c = W.c1()
+    d = c["desc"]
+    cases = [bad(d, dim=4), bad(d, theta_ecs=0.0), bad(d, theta_csg=2.0), bad(d, levels=9),
+             bad(d, n=[130, 128]), bad(d, nu1=2), bad(d, a=[-0.5, 0.0]), bad(d, levels=1), bad(d, omega=0.0),
+             bad(d, csg_mode=5), bad(d, n=[16, 16], levels=0)]
+    for dd in cases:
+        with pytest.raises(hh.HHError) as e:
+            host_grid(dd, c["phi"])
+        assert e.value.status == -1
+    phi = c["phi"].copy()
+    phi[7] = np.nan
+    with pytest.raises(hh.HHError):
+        host_grid(d, phi)
+
+
+def test_host_only_grid_refuses_compute():
+    c = W.c1()
+    g = host_grid(c["desc"], c["phi"])
+    L = hh.lib()
+    assert L.hh_apply_operator(g.h, 0, 0, 1, 2, None) == -1
+    assert "host-only" in hh.last_error()
+    assert L.hh_vcycle(g.h, 0, 1, 2, None) == -1
+
+
+def test_auto_levels_rule():
+    for n, want in [(128, 4), (1024, 7), (384, 6), (768, 7), (2048, 8)]:
+        d = W.base_desc(2, (n, n), (0, 0), (1, 1), (0, 0), (1, 1), levels=0)
+        g = host_grid(d, np.ones(n * n))
+        assert g.levels == want, (n, g.levels)
+        assert g.level_dims[-1][0] <= 16
+
+
+def test_fastdiv_host_emulation(tmp_path):
+    """The 32-bit division by a runtime constant used for index decomposition
+    agrees with integer division (host build of the same inline function)."""
+    src = tmp_path / "fd.cpp"
+    src.write_text(r'''
+#include "hh_common.h"
+#include <cstdio>
+#include <random>
+int main() {
+  std::mt19937 r(1);
+  unsigned ds[] = {1,2,3,5,7,12,16,17,96,100,128,129,255,256,384,1000,1023,1024,2048,4095,65536,1048576,16777216};
+  for (unsigned d : ds) {
+    FastDiv f = make_fastdiv(d);
+    for (int t = 0; t < 200000; ++t) {
+      unsigned n = (t < 1000) ? t : (r() & 0x7fffffff);
+      if (fdiv(n, f) != n / d) { printf("FAIL %u %u\n", n, d); return 1; }
+    }
+    unsigned n = 0x7fffffff; if (fdiv(n, f) != n / d) { printf("FAIL max %u\n", d); return 1; }
+  }
+  printf("ok\n"); return 0; }
+''')
+    exe = tmp_path / "fd"
+    inc = os.path.join(ROOT, "paper_0912_0180_amd", "csrc")
+    subprocess.check_call(["hipcc", "-O1", "-std=c++17", "-I", inc, str(src), "-o", str(exe)],
+                          stderr=subprocess.DEVNULL)
+    assert subprocess.check_output([str(exe)]).strip() == b"ok"

@@ -1,0 +1,216 @@
+"""GPU parity of the HIP path against the CPU FP64 oracle, through the C ABI.
+
+FP64 paths follow the same fixed operation order as the oracle, so operator
+applies, V-cycles and whole Bi-CGSTAB solves are compared value for value
+(iteration counts equal).  Mixed precision (complex-FP32 V-cycle) is judged by
+the FP64 true residual and the solution error against the oracle.
+Tolerance of the method (fixed by the target): relative solution error
+<= 1e-6 at an FP64 relative residual of 1e-8, iteration counts within +-1.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_0912_0180_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def hh_mod(torch_dev):
+    from paper_0912_0180_amd import hh
+    hh.lib()
+    return hh
+
+
+def dev(torch, a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.to("cuda") if dtype is None else t.to("cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def same(a, b):
+    """value-for-value equality of complex arrays (+0 == -0)"""
+    return np.array_equal(np.asarray(a), np.asarray(b))
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# problem shapes: full configs' geometry at sizes the oracle finishes in
+# seconds, spanning several tiles and ragged tails
+def ragged_2d():
+    d = W.base_desc(2, (96, 80), (-0.2, -0.3), (1.3, 1.1), (0.0, 0.0), (1.0, 0.9), levels=3)
+    rng = np.random.default_rng(21)
+    phi = (30.0 ** 2) * (1 + 0.3 * rng.uniform(size=96 * 80))
+    return {"desc": d, "phi": phi}
+
+
+def ragged_3d():
+    d = W.base_desc(3, (24, 16, 40), (-0.2, -0.25, -0.1), (1.2, 1.3, 1.15), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), levels=3)
+    rng = np.random.default_rng(22)
+    phi = (12.0 ** 2) * (1 + 0.3 * rng.uniform(size=24 * 16 * 40))
+    return {"desc": d, "phi": phi}
+
+
+CASES = {
+    "c1": lambda: W.c1(),
+    "c1_interior": lambda: W.c1(mode=1),
+    "c2_256": lambda: W.c2(n=256, levels=6),
+    "ragged_2d": ragged_2d,
+    "ragged_3d": ragged_3d,
+    "c3_32": lambda: W.c3(n=32, layer=4, method="bicgstab"),
+}
+
+
+def rand_c(rng, n):
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_operator_apply_matches_oracle(torch_dev, hh_mod, oracle_mod, name):
+    torch = torch_dev
+    c = CASES[name]()
+    print("case", name, flush=True)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    x = rand_c(np.random.default_rng(1), g.N)
+    xd = dev(torch, x)
+    yH = host(g.apply(xd, "H"))
+    yM = host(g.apply(xd, "M"))
+    yM32 = host(g.apply(xd.to(torch.complex64), "M", prec="c64"))
+    torch.cuda.synchronize()
+    assert same(yH, o.apply(x, "H"))
+    assert same(yM, o.apply(x, "M"))
+    assert rel(yM32, o.apply(x.astype(np.complex64).astype(np.complex128), "M")) < 1e-5
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_vcycle_matches_oracle(torch_dev, hh_mod, oracle_mod, name):
+    torch = torch_dev
+    c = CASES[name]()
+    print("case", name, flush=True)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    f = rand_c(np.random.default_rng(2), g.N)
+    fd = dev(torch, f)
+    u64 = host(g.vcycle(fd, "c128"))
+    u32 = host(g.vcycle(fd, "c64"))
+    torch.cuda.synchronize()
+    ref = o.vcycle(f)
+    assert same(u64, ref)
+    assert rel(u32.astype(np.complex128), ref) < 1e-4
+
+
+@pytest.mark.parametrize("name", ["c1", "c1_interior", "ragged_2d", "ragged_3d", "c3_32"])
+def test_bicgstab_fp64_matches_oracle(torch_dev, hh_mod, oracle_mod, name):
+    torch = torch_dev
+    c = CASES[name]()
+    print("case", name, flush=True)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    b = c.get("b")
+    if b is None:
+        b = rand_c(np.random.default_rng(3), g.N)
+    xo, io = o.solve(b, tol=1e-8, history=True)
+    xg, ig = g.solve(dev(torch, b), tol=1e-8, vcycle_prec="c128", history=True)
+    xg = host(xg)
+    assert io["status"] == 0 and ig["status"] == 0
+    assert abs(ig["matvecs"] - io["matvecs"]) <= 1
+    assert ig["rel_res_true"] < 1e-8
+    assert rel(xg, xo) <= 1e-6
+    # the arithmetic contract makes the whole iteration reproduce the oracle
+    assert ig["matvecs"] == io["matvecs"] and ig["iterations"] == io["iterations"]
+    assert same(xg, xo)
+    assert np.array_equal(ig["history"], io["history"])
+
+
+@pytest.mark.parametrize("name", ["c1", "c2_256", "ragged_3d", "c3_32"])
+def test_bicgstab_mixed_precision(torch_dev, hh_mod, oracle_mod, name):
+    torch = torch_dev
+    c = CASES[name]()
+    print("case", name, flush=True)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    b = c.get("b")
+    if b is None:
+        b = rand_c(np.random.default_rng(4), g.N)
+    xo, io = o.solve(b, tol=1e-8)
+    xg, ig = g.solve(dev(torch, b), tol=1e-8, vcycle_prec="c64")
+    xg = host(xg)
+    assert ig["status"] == 0 and ig["rel_res_true"] < 1e-8
+    assert rel(xg, xo) <= 1e-6
+    print(name, "matvecs fp64", io["matvecs"], "mixed", ig["matvecs"], "err", rel(xg, xo))
+
+
+def test_batch_equals_single(torch_dev, hh_mod):
+    """Problems solved together give exactly the results they give alone."""
+    torch = torch_dev
+    cs = [W.c1(), W.c2(n=256, levels=6), ragged_2d(), W.c1(mode=1)]
+    rng = np.random.default_rng(5)
+    grids, bs = [], []
+    for c in cs:
+        g = hh_mod.Grid(c["desc"], c["phi"])
+        grids.append(g)
+        b = c.get("b")
+        bs.append(dev(torch, b if b is not None else rand_c(rng, g.N)))
+    single = [g.solve(b, tol=1e-8) for g, b in zip(grids, bs)]
+    for prec in ("c128", "c64"):
+        xs, infos = hh_mod.solve_batch(grids, bs, tol=1e-8, vcycle_prec=prec)
+        for q in range(len(cs)):
+            xq, iq = grids[q].solve(bs[q], tol=1e-8, vcycle_prec=prec)
+            assert infos[q]["status"] == 0
+            assert infos[q]["matvecs"] == iq["matvecs"]
+            assert same(host(xs[q]), host(xq))
+    for q in range(len(cs)):
+        assert single[q][1]["status"] == 0
+
+
+def test_solve_is_deterministic(torch_dev, hh_mod):
+    torch = torch_dev
+    c = W.c2(n=256, levels=6)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    b = dev(torch, c["b"])
+    ref, ir = g.solve(b, tol=1e-8, vcycle_prec="c64")
+    ref = host(ref)
+    for _ in range(3):
+        x, i = g.solve(b, tol=1e-8, vcycle_prec="c64")
+        assert i["matvecs"] == ir["matvecs"] and same(host(x), ref)
+
+
+def test_edge_cases(torch_dev, hh_mod, oracle_mod):
+    torch = torch_dev
+    c = W.c1()
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    z = torch.zeros(g.N, dtype=torch.complex128, device="cuda")
+    x, info = g.solve(z)
+    assert info["status"] == 0 and info["matvecs"] == 0 and torch.count_nonzero(x).item() == 0
+    b = dev(torch, c["b"])
+    x, info = g.solve(b, max_matvec=1, max_restarts=0)
+    xo, io = oracle_mod.Grid(c["desc"], c["phi"]).solve(c["b"], max_matvec=1, max_restarts=0)
+    assert info["status"] == -4 == io["status"] and info["matvecs"] == 1
+    assert same(host(x), xo)
+    bad = c["b"].copy()
+    bad[5] = np.nan
+    x, info = g.solve(dev(torch, bad))
+    assert info["status"] == -6
+    # warm start (resume from a saved iterate) follows the oracle exactly
+    x0, i0 = g.solve(b, tol=1e-8, max_matvec=40, max_restarts=0)
+    assert i0["status"] == -4
+    x1, i1 = g.solve(b, x=x0.clone(), x0_given=True, tol=1e-8)
+    xo1, io1 = oracle_mod.Grid(c["desc"], c["phi"]).solve(c["b"], x0=host(x0), tol=1e-8)
+    assert i1["status"] == 0 == io1["status"] and i1["matvecs"] == io1["matvecs"]
+    assert same(host(x1), xo1)
