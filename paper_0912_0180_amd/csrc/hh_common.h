@@ -48,6 +48,47 @@ template <typename T> __host__ __device__ inline V2<T> cdiv(V2<T> a, V2<T> b)
 }
 template <typename T> __host__ __device__ inline V2<T> crs(T s, V2<T> a) { return cmk<T>(s * a.x, s * a.y); }
 
+// Explicit global-address-space accesses: pointers taken from descriptors in
+// memory are generic to the compiler, which would otherwise emit flat
+// loads/stores; these emit global_load / global_store.
+#define HH_GLOBAL __attribute__((address_space(1)))
+typedef double hh_dvec2 __attribute__((ext_vector_type(2)));
+typedef float hh_fvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double ldg(const double *p, int64_t i) { return ((const HH_GLOBAL double *)p)[i]; }
+__device__ __forceinline__ float ldg(const float *p, int64_t i) { return ((const HH_GLOBAL float *)p)[i]; }
+__device__ __forceinline__ double2 ldg(const double2 *p, int64_t i)
+{
+    hh_dvec2 v = ((const HH_GLOBAL hh_dvec2 *)p)[i];
+    double2 r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+__device__ __forceinline__ float2 ldg(const float2 *p, int64_t i)
+{
+    hh_fvec2 v = ((const HH_GLOBAL hh_fvec2 *)p)[i];
+    float2 r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+typedef unsigned hh_uvec4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ hh_uvec4 ldg16(const void *p, int64_t i) { return ((const HH_GLOBAL hh_uvec4 *)p)[i]; }
+__device__ __forceinline__ void stg(double2 *p, int64_t i, double2 v)
+{
+    hh_dvec2 w;
+    w.x = v.x;
+    w.y = v.y;
+    ((HH_GLOBAL hh_dvec2 *)p)[i] = w;
+}
+__device__ __forceinline__ void stg(float2 *p, int64_t i, float2 v)
+{
+    hh_fvec2 w;
+    w.x = v.x;
+    w.y = v.y;
+    ((HH_GLOBAL hh_fvec2 *)p)[i] = w;
+}
+
 // conversions between the two complex precisions
 template <typename T, typename S> __device__ inline V2<T> ccvt(S v) { return cmk<T>((T)v.x, (T)v.y); }
 
@@ -104,7 +145,9 @@ enum Reason { RS_NONE = 0, RS_CONV = 1, RS_MAXMV = 2, RS_BREAK = 3, RS_NONFIN = 
 
 struct SolveState {
     int phase, reason, mv, it;
-    int max_mv, hist_len, pad0, pad1;
+    int max_mv, hist_len;
+    unsigned count;                  // blocks of the current reduction done (last one finalises)
+    int pad0;
     double tol, bnorm, rel, true_rel;
     double2 rho, alpha, omega, beta;
     // IDR(s)
@@ -115,8 +158,17 @@ struct SolveState {
     double2 c[HH_MAX_S];
 };
 
+// Per-problem control block of a launch plan: the phase and the Krylov
+// scalars every pass needs, read by one scalar load from a kernel argument.
+struct Ctrl {
+    int phase, pad0, pad1, pad2;
+    double2 alpha, beta, omega;
+    double2 om_idr;
+};
+
 struct ProbDev {
     int dim, nlev, Nc, nchunk;
+    int tail64, tail32;              // first level of the one-workgroup tail kernel, per precision
     int n[3];
     int64_t N;
     FastDiv fx, fxy;
@@ -126,18 +178,37 @@ struct ProbDev {
     const LevelDev<float> *L32;      // device array [nlev] (null if no FP32 set)
     const double2 *Minv64;
     const float2 *Minv32;
+    const void *timg64, *timg32;     // LDS image of the tail levels (phi, coefficients), per precision
+    int timg_bytes64, timg_bytes32;
     double omega;
     void *vec[VS_NVEC];
     double2 *dR, *dX;                // IDR: s columns of N each
     const double2 *P;                // IDR shadow space, N x s column-major
     double *part;                    // [nchunk * HH_NPART]
     SolveState *st;
+    Ctrl *ctrl;                      // this problem's slot in the plan's control array
     double *hist;                    // device history (optional)
 };
 
 struct Tile {
     int prob, idx;
 };
+
+// Launch context passed by value to every kernel.
+struct Ctx {
+    const ProbDev *P;                // problem descriptors
+    const Tile *tiles;               // tile list; null: one problem, tile = blockIdx.x
+    const Ctrl *ctrl;                // control blocks; null: every problem runs
+    const void *L;                   // one problem: its LevelDev array in the V-cycle precision
+    double omega;                    // one problem: Jacobi weight
+};
+
+// Levels with at most TailCap<T>::N unknowns (and every coarser level) run
+// inside one workgroup with all data in LDS.
+template <typename T> struct TailCap;
+template <> struct TailCap<double> { static constexpr int N = 1024; static constexpr int BYTES = 96 * 1024; };
+template <> struct TailCap<float> { static constexpr int N = 1024; static constexpr int BYTES = 64 * 1024; };
+#define HH_TAIL_WG 512
 
 // Tile shapes of the fused V-cycle kernels (coarse tile of the down-leg; the
 // up-leg's fine tile is twice it).

@@ -1,9 +1,9 @@
 // hh_kernels.hpp -- gfx950 kernels of the CSG-preconditioned Helmholtz solver.
 //
 // Every kernel takes the device array of problem descriptors and a tile list
-// (problem id, tile index); one workgroup of 256 threads (4 x wave64) handles
-// one tile, so a single launch covers any number of independent problems.
-// Kernels whose problem is not in the running phase return at once.
+// (problem id, tile index); one workgroup handles one tile, so one launch
+// covers any number of independent problems.  Kernels whose problem is not in
+// the running phase return at once.
 //
 // Arithmetic follows a fixed operation order (no FMA contraction; the build
 // passes -ffp-contract=off), so FP64 results are reproducible run to run and
@@ -16,6 +16,12 @@
 //   2048 elements, thread slot t summing elements t + 256 j (j = 0..7) in
 //   order, slots combined by a pairwise tree (wave butterfly, then
 //   (w0 + w1) + (w2 + w3)), chunk partials by a pairwise tree.
+//
+// Memory-level parallelism: each thread first issues all of its global loads
+// into registers, then computes, then stores, so several HBM requests per
+// thread are in flight.  Descriptor fields are copied to registers once per
+// workgroup.
+#pragma once
 #include "hh_common.h"
 
 namespace hh {
@@ -24,8 +30,8 @@ namespace hh {
 // reductions
 // ---------------------------------------------------------------------------
 
-// Pairwise tree over the 256 thread slots of the workgroup; thread 0 writes
-// the NV sums to out[0..NV).
+// Pairwise tree over the 256 thread slots of a 256-thread workgroup; thread 0
+// writes the NV sums to out[0..NV).
 template <int NV>
 __device__ inline void block_reduce(double (&v)[NV], double *out)
 {
@@ -44,9 +50,13 @@ __device__ inline void block_reduce(double (&v)[NV], double *out)
         for (int q = 0; q < NV; ++q) out[q] = (red[q] + red[NV + q]) + (red[2 * NV + q] + red[3 * NV + q]);
 }
 
-// Pairwise sum of v[0..n) with zero padding to a power of two >= 256, by one
-// workgroup; returns the sum in thread 0.  Each thread sums its contiguous
-// segment with the iterative (binary counter) form of the pairwise tree.
+
+// Pairwise sum of v[0..n) (stride `stride`; LDS if LOCAL, else global) with
+// zero padding to a power of two >= 256, by one 256-thread workgroup; every
+// thread gets the sum.  Each thread sums its contiguous segment with the
+// iterative (binary counter) form of the pairwise tree, then the slots are
+// combined by block_reduce.
+template <bool LOCAL>
 __device__ inline double pairwise_wg(const double *v, int stride, int n)
 {
     int np = 256;
@@ -57,7 +67,7 @@ __device__ inline double pairwise_wg(const double *v, int stride, int n)
     int top = 0;
     for (int i = 0; i < seg; ++i) {
         int e = beg + i;
-        double x = e < n ? v[(int64_t)e * stride] : 0.0;
+        double x = e < n ? (LOCAL ? v[e * stride] : ldg(v, (int64_t)e * stride)) : 0.0;
         for (int c = i; c & 1; c >>= 1) x = stack[--top] + x;
         stack[top++] = x;
     }
@@ -71,113 +81,369 @@ __device__ inline double pairwise_wg(const double *v, int stride, int n)
 }
 
 // ---------------------------------------------------------------------------
-// helpers
+// descriptor views (copied to registers once per workgroup)
 // ---------------------------------------------------------------------------
-template <typename T> __device__ inline const LevelDev<T> *levels(const ProbDev &pd);
-template <> __device__ inline const LevelDev<double> *levels<double>(const ProbDev &pd) { return pd.L64; }
-template <> __device__ inline const LevelDev<float> *levels<float>(const ProbDev &pd) { return pd.L32; }
+struct HView {
+    int nx, ny, nz;
+    int64_t N;
+    FastDiv fx, fxy;
+    const double2 *a0, *c0, *d0, *a1, *c1, *d1, *a2, *c2, *d2;
+    const double *phi;
+};
 
-__device__ inline bool running(const ProbDev &pd) { return pd.st == nullptr || pd.st->phase == PH_RUN; }
-
-template <typename S> __device__ inline double2 ld64(const S *p, int64_t i) { return ccvt<double>(p[i]); }
-
-// y = H x at fine point (i, j, k), FP64 ECS coefficients; x of storage type S.
-template <int DIM, typename S>
-__device__ inline double2 applyH_at(const ProbDev &pd, const S *x, int i, int j, int k, int64_t p)
+__device__ inline HView hview(const ProbDev *pd)
 {
-    const int nx = pd.n[0], ny = pd.n[1], nz = pd.n[2];
-    const int64_t sy = nx, sz = (int64_t)nx * ny;
-    const double2 zero = cmk<double>(0.0, 0.0);
-    double2 d = pd.dH[0][i];
-    d = cadd<double>(d, pd.dH[1][j]);
-    if (DIM == 3) d = cadd<double>(d, pd.dH[2][k]);
-    double2 D = cmk<double>(d.x - pd.phi[p], d.y);
-    double2 t = cmul<double>(D, ld64(x, p));
-    double2 uw = i > 0 ? ld64(x, p - 1) : zero, ue = i < nx - 1 ? ld64(x, p + 1) : zero;
-    t = csub<double>(t, cmul<double>(pd.aH[0][i], uw));
-    t = csub<double>(t, cmul<double>(pd.cH[0][i], ue));
-    double2 us = j > 0 ? ld64(x, p - sy) : zero, un = j < ny - 1 ? ld64(x, p + sy) : zero;
-    t = csub<double>(t, cmul<double>(pd.aH[1][j], us));
-    t = csub<double>(t, cmul<double>(pd.cH[1][j], un));
-    if (DIM == 3) {
-        double2 ud = k > 0 ? ld64(x, p - sz) : zero, uu = k < nz - 1 ? ld64(x, p + sz) : zero;
-        t = csub<double>(t, cmul<double>(pd.aH[2][k], ud));
-        t = csub<double>(t, cmul<double>(pd.cH[2][k], uu));
-    }
-    return t;
+    HView h;
+    h.nx = pd->n[0];
+    h.ny = pd->n[1];
+    h.nz = pd->n[2];
+    h.N = pd->N;
+    h.fx = pd->fx;
+    h.fxy = pd->fxy;
+    h.a0 = pd->aH[0]; h.c0 = pd->cH[0]; h.d0 = pd->dH[0];
+    h.a1 = pd->aH[1]; h.c1 = pd->cH[1]; h.d1 = pd->dH[1];
+    h.a2 = pd->aH[2]; h.c2 = pd->cH[2]; h.d2 = pd->dH[2];
+    h.phi = pd->phi;
+    return h;
 }
 
-// y = M x on level `lev` in precision T at point (i,j,k); x of type V2<T>.
-template <int DIM, typename T>
-__device__ inline V2<T> applyM_at(const LevelDev<T> &L, const V2<T> *x, int i, int j, int k, int64_t p)
+template <typename T> struct MView {
+    int nx, ny, nz;
+    int64_t N;
+    FastDiv fx, fxy;
+    const V2<T> *a0, *c0, *d0, *a1, *c1, *d1, *a2, *c2, *d2;
+    const T *phi;
+};
+
+template <typename T> __device__ inline MView<T> mview(const LevelDev<T> *L)
+{
+    MView<T> h;
+    h.nx = L->n[0];
+    h.ny = L->n[1];
+    h.nz = L->n[2];
+    h.N = L->N;
+    h.fx = L->fx;
+    h.fxy = L->fxy;
+    h.a0 = L->a[0]; h.c0 = L->c[0]; h.d0 = L->d[0];
+    h.a1 = L->a[1]; h.c1 = L->c[1]; h.d1 = L->d[1];
+    h.a2 = L->a[2]; h.c2 = L->c[2]; h.d2 = L->d[2];
+    h.phi = L->phi;
+    return h;
+}
+
+template <typename T> __device__ inline const LevelDev<T> *levels(const ProbDev *pd);
+template <> __device__ inline const LevelDev<double> *levels<double>(const ProbDev *pd) { return pd->L64; }
+template <> __device__ inline const LevelDev<float> *levels<float>(const ProbDev *pd) { return pd->L32; }
+template <typename T> __device__ inline int tail_level(const ProbDev *pd);
+template <> __device__ inline int tail_level<double>(const ProbDev *pd) { return pd->tail64; }
+template <> __device__ inline int tail_level<float>(const ProbDev *pd) { return pd->tail32; }
+
+__device__ inline Tile ldg_tile(const Tile *t, int i)
+{
+    const HH_GLOBAL int *p = (const HH_GLOBAL int *)(t + i);
+    Tile r;
+    r.prob = p[0];
+    r.idx = p[1];
+    return r;
+}
+__device__ inline Tile tile_of(const Ctx &c)
+{
+    if (c.tiles) return ldg_tile(c.tiles, blockIdx.x);
+    Tile t;
+    t.prob = 0;
+    t.idx = (int)blockIdx.x;
+    return t;
+}
+__device__ inline int phase_of(const Ctx &c, int prob)
+{
+    return c.ctrl ? ((const HH_GLOBAL int *)(c.ctrl + prob))[0] : (int)PH_RUN;
+}
+__device__ inline Ctrl ctrl_of(const Ctx &c, int prob)
+{
+    const Ctrl *q = c.ctrl + prob;
+    Ctrl r;
+    r.phase = ((const HH_GLOBAL int *)q)[0];
+    r.pad0 = r.pad1 = r.pad2 = 0;
+    r.alpha = ldg(&q->alpha, 0);
+    r.beta = ldg(&q->beta, 0);
+    r.omega = ldg(&q->omega, 0);
+    r.om_idr = ldg(&q->om_idr, 0);
+    return r;
+}
+template <typename T> __device__ inline const LevelDev<T> *levels_of(const Ctx &c, const ProbDev *pd)
+{
+    return c.L ? (const LevelDev<T> *)c.L : levels<T>(pd);
+}
+
+template <typename S> __device__ inline double2 ld64(const S *p, int64_t i) { return ccvt<double>(ldg(p, i)); }
+
+__device__ inline void split(int64_t p, int nx, int ny, FastDiv fx, FastDiv fxy, int &i, int &j, int &k)
+{
+    uint32_t q = fdiv((uint32_t)p, fx);
+    i = (int)((uint32_t)p - q * (uint32_t)nx);
+    k = (int)fdiv((uint32_t)p, fxy);
+    j = (int)(q - (uint32_t)k * (uint32_t)ny);
+}
+
+// Stencil of a view V (HView or MView<T>) at point (i,j,k), x of storage S
+// converted to precision T.
+template <int DIM, typename T, typename VW, typename S>
+__device__ inline V2<T> stencil(const VW &h, const S *__restrict__ x, int i, int j, int k, int64_t p)
 {
     using C = V2<T>;
-    const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
-    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int64_t sy = h.nx, sz = (int64_t)h.nx * h.ny;
     const C zero = cmk<T>(0, 0);
-    C d = L.d[0][i];
-    d = cadd<T>(d, L.d[1][j]);
-    if (DIM == 3) d = cadd<T>(d, L.d[2][k]);
-    C D = cmk<T>(d.x - L.phi[p], d.y);
-    C t = cmul<T>(D, x[p]);
-    t = csub<T>(t, cmul<T>(L.a[0][i], i > 0 ? x[p - 1] : zero));
-    t = csub<T>(t, cmul<T>(L.c[0][i], i < nx - 1 ? x[p + 1] : zero));
-    t = csub<T>(t, cmul<T>(L.a[1][j], j > 0 ? x[p - sy] : zero));
-    t = csub<T>(t, cmul<T>(L.c[1][j], j < ny - 1 ? x[p + sy] : zero));
+    C xc = ccvt<T>(ldg(x, p));
+    C xw = i > 0 ? ccvt<T>(ldg(x, p - 1)) : zero, xe = i < h.nx - 1 ? ccvt<T>(ldg(x, p + 1)) : zero;
+    C xs = j > 0 ? ccvt<T>(ldg(x, p - sy)) : zero, xn = j < h.ny - 1 ? ccvt<T>(ldg(x, p + sy)) : zero;
+    C xd = zero, xu = zero;
     if (DIM == 3) {
-        t = csub<T>(t, cmul<T>(L.a[2][k], k > 0 ? x[p - sz] : zero));
-        t = csub<T>(t, cmul<T>(L.c[2][k], k < nz - 1 ? x[p + sz] : zero));
+        xd = k > 0 ? ccvt<T>(ldg(x, p - sz)) : zero;
+        xu = k < h.nz - 1 ? ccvt<T>(ldg(x, p + sz)) : zero;
+    }
+    C d = ldg(h.d0, i);
+    d = cadd<T>(d, ldg(h.d1, j));
+    if (DIM == 3) d = cadd<T>(d, ldg(h.d2, k));
+    C D = cmk<T>(d.x - ldg(h.phi, p), d.y);
+    C t = cmul<T>(D, xc);
+    t = csub<T>(t, cmul<T>(ldg(h.a0, i), xw));
+    t = csub<T>(t, cmul<T>(ldg(h.c0, i), xe));
+    t = csub<T>(t, cmul<T>(ldg(h.a1, j), xs));
+    t = csub<T>(t, cmul<T>(ldg(h.c1, j), xn));
+    if (DIM == 3) {
+        t = csub<T>(t, cmul<T>(ldg(h.a2, k), xd));
+        t = csub<T>(t, cmul<T>(ldg(h.c2, k), xu));
     }
     return t;
 }
 
-__device__ inline void coords(const ProbDev &pd, int64_t p, int &i, int &j, int &k)
+// ---------------------------------------------------------------------------
+// finalisation: the last workgroup of a reducing pass (per problem) sums the
+// chunk partials in the fixed pairwise order and advances the scalar state
+// ---------------------------------------------------------------------------
+#define HH_FIN_STAGE 6144
+enum FinKind { FIN_BNORM = 0, FIN_INIT, FIN_ALPHA, FIN_S, FIN_OMEGA, FIN_RHO, FIN_TRUE, FIN_NONE,
+               FIN_IDR_OMEGA, FIN_IDR_STEP, FIN_IDR_INIT, FIN_IDR_M };
+
+__device__ inline bool cfin(double2 v) { return isfinite(v.x) && isfinite(v.y); }
+
+__device__ inline void stop(SolveState *st, int reason)
 {
-    uint32_t q = fdiv((uint32_t)p, pd.fx);
-    i = (int)((uint32_t)p - q * (uint32_t)pd.n[0]);
-    k = (int)fdiv((uint32_t)p, pd.fxy);
-    j = (int)(q - (uint32_t)k * (uint32_t)pd.n[1]);
+    st->phase = PH_STOP;
+    st->reason = reason;
+}
+
+__device__ inline void record(const ProbDev *pd, SolveState *st, double rel)
+{
+    st->rel = rel;
+    if (pd->hist && st->mv - 1 < st->hist_len && st->mv >= 1) pd->hist[st->mv - 1] = rel;
+}
+
+// copy of the phase and scalars into the plan's control block
+__device__ inline void mirror(const ProbDev *pd, const SolveState *st)
+{
+    if (!pd->ctrl) return;
+    Ctrl c;
+    c.phase = st->phase;
+    c.pad0 = c.pad1 = c.pad2 = 0;
+    c.alpha = st->alpha;
+    c.beta = st->beta;
+    c.omega = st->omega;
+    c.om_idr = st->om_idr;
+    *pd->ctrl = c;
+}
+
+// defined with the IDR kernels
+__device__ void idr_finalize(const ProbDev *pd, SolveState *st, int kind, const double *s, int phase);
+__device__ int idr_nvals(const ProbDev *pd, int kind);
+
+__device__ void finalize(const ProbDev *pd, int kind)
+{
+    SolveState *st = pd->st;
+    const int phase = st->phase;
+    const int nv = kind >= FIN_IDR_OMEGA ? idr_nvals(pd, kind)
+                 : (kind == FIN_S || kind == FIN_BNORM || kind == FIN_TRUE) ? 1 : (kind == FIN_ALPHA ? 2 : 3);
+    const int first = (kind == FIN_BNORM || kind == FIN_TRUE) ? 2 : 0;
+    double s[2 * HH_MAX_S + 4];
+    const int n = pd->nchunk;
+    if (n * nv <= HH_FIN_STAGE) {
+        // stage the partials in LDS with all loads in flight, then reduce
+        __shared__ double stage[HH_FIN_STAGE];
+        const int tot = n * nv;
+        for (int b = 0; b < tot; b += 8 * HH_WG) {
+            double tmp[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = b + threadIdx.x + q * HH_WG;
+                if (e < tot) {
+                    const int c = e / nv, k = e - c * nv;
+                    tmp[q] = ldg(pd->part, (int64_t)c * HH_NPART + first + k);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = b + threadIdx.x + q * HH_WG;
+                if (e < tot) stage[e] = tmp[q];
+            }
+        }
+        __syncthreads();
+        for (int q = 0; q < nv; ++q) s[q] = pairwise_wg<true>(stage + q, nv, n);
+    } else {
+        for (int q = 0; q < nv; ++q) s[q] = pairwise_wg<false>(pd->part + first + q, HH_NPART, n);
+    }
+    if (threadIdx.x != 0) return;
+    if (kind >= FIN_IDR_OMEGA) {
+        idr_finalize(pd, st, kind, s, phase);
+        mirror(pd, st);
+        return;
+    }
+    switch (kind) {
+    case FIN_BNORM:
+        st->bnorm = sqrt(s[0]);
+        break;
+    case FIN_TRUE:
+        st->true_rel = sqrt(s[0]) / st->bnorm;
+        break;
+    case FIN_INIT: {
+        // start (or restart) of Bi-CGSTAB: rho = alpha = omega = 1, then the
+        // first beta from rho1 = (rhat, r)
+        const double2 one = cmk<double>(1.0, 0.0);
+        st->rho = one;
+        st->alpha = one;
+        st->omega = one;
+        st->phase = PH_RUN;
+        st->reason = RS_NONE;
+        double2 rho1 = cmk<double>(s[0], s[1]);
+        if (!cfin(rho1)) { stop(st, RS_NONFIN); break; }
+        if (rho1.x == 0.0 && rho1.y == 0.0) { stop(st, RS_BREAK); break; }
+        st->beta = cmul<double>(cdiv<double>(rho1, st->rho), cdiv<double>(st->alpha, st->omega));
+        st->rho = rho1;
+        break;
+    }
+    case FIN_ALPHA: {
+        if (phase != PH_RUN) break;
+        st->mv += 1;
+        double2 rv = cmk<double>(s[0], s[1]);
+        if (!cfin(rv)) { stop(st, RS_NONFIN); break; }
+        if (rv.x == 0.0 && rv.y == 0.0) { stop(st, RS_BREAK); break; }
+        st->alpha = cdiv<double>(st->rho, rv);
+        break;
+    }
+    case FIN_S: {
+        if (phase != PH_RUN) break;
+        double rel = sqrt(s[0]) / st->bnorm;
+        record(pd, st, rel);
+        if (!isfinite(rel)) { stop(st, RS_NONFIN); break; }
+        if (rel < st->tol) { st->phase = PH_HALF; st->reason = RS_CONV; break; }
+        if (st->mv >= st->max_mv) { st->phase = PH_HALF; st->reason = RS_MAXMV; break; }
+        break;
+    }
+    case FIN_OMEGA: {
+        if (phase != PH_RUN) break;
+        st->mv += 1;
+        double2 ts = cmk<double>(s[0], s[1]);
+        double tt = s[2];
+        if (!cfin(ts) || !isfinite(tt)) { stop(st, RS_NONFIN); break; }
+        if (tt == 0.0) { stop(st, RS_BREAK); break; }
+        st->omega = cmk<double>(ts.x / tt, ts.y / tt);
+        break;
+    }
+    case FIN_RHO: {
+        if (phase != PH_RUN && phase != PH_HALF) break;
+        st->it += 1;
+        if (phase == PH_HALF) { st->phase = PH_STOP; break; }
+        double rel = sqrt(s[2]) / st->bnorm;
+        record(pd, st, rel);
+        if (!isfinite(rel)) { stop(st, RS_NONFIN); break; }
+        if (rel < st->tol) { stop(st, RS_CONV); break; }
+        if (st->omega.x == 0.0 && st->omega.y == 0.0) { stop(st, RS_BREAK); break; }
+        if (st->mv >= st->max_mv) { stop(st, RS_MAXMV); break; }
+        double2 rho1 = cmk<double>(s[0], s[1]);
+        if (!cfin(rho1)) { stop(st, RS_NONFIN); break; }
+        if (rho1.x == 0.0 && rho1.y == 0.0) { stop(st, RS_BREAK); break; }
+        st->beta = cmul<double>(cdiv<double>(rho1, st->rho), cdiv<double>(st->alpha, st->omega));
+        st->rho = rho1;
+        break;
+    }
+    default:
+        break;
+    }
+    mirror(pd, st);
+}
+
+// Writes this chunk's partial sums; the pass's finalisation runs in k_fin.
+template <int NV>
+__device__ inline void chunk_finish(const ProbDev *pd, int chunk, double (&acc)[NV], int)
+{
+    block_reduce<NV>(acc, pd->part + (int64_t)chunk * HH_NPART);
+}
+
+// One workgroup per problem: sums the chunk partials of the pass just run and
+// advances the scalar state (kind = FinKind).
+__global__ __launch_bounds__(HH_WG) void k_fin(Ctx cx, const int *__restrict__ probs, int kind)
+{
+    const ProbDev *pd = cx.P + (probs ? probs[blockIdx.x] : 0);
+    const int phase = pd->st->phase;
+    if (kind == FIN_RHO) {
+        if (phase != PH_RUN && phase != PH_HALF) return;
+    } else if (kind == FIN_ALPHA || kind == FIN_S || kind == FIN_OMEGA) {
+        if (phase != PH_RUN) return;
+    } else if (kind >= FIN_IDR_OMEGA && kind != FIN_IDR_INIT) {
+        if (phase != PH_RUN) return;
+    }
+    finalize(pd, kind);
 }
 
 // ---------------------------------------------------------------------------
 // operator apply (standalone): y = H x or y = M x on the finest level
 // ---------------------------------------------------------------------------
 template <int DIM>
-__global__ __launch_bounds__(HH_WG) void k_applyH(const ProbDev *P, const Tile *tiles, const void *xp, void *yp)
+__global__ __launch_bounds__(HH_WG) void k_applyH(Ctx cx, const void *xp, void *yp)
 {
-    const Tile tl = tiles[blockIdx.x];
-    const ProbDev &pd = P[tl.prob];
-    const double2 *x = (const double2 *)xp;
-    double2 *y = (double2 *)yp;
+    const Tile tl = tile_of(cx);
+    const HView h = hview(cx.P + tl.prob);
+    const double2 *__restrict__ x = (const double2 *)xp;
+    double2 *__restrict__ y = (double2 *)yp;
     const int64_t base = (int64_t)tl.idx * HH_CHUNK;
+    double2 out[HH_PER_SLOT];
 #pragma unroll
     for (int s = 0; s < HH_PER_SLOT; ++s) {
-        int64_t p = base + threadIdx.x + (int64_t)HH_WG * s;
-        if (p < pd.N) {
+        const int64_t p = base + threadIdx.x + (int64_t)HH_WG * s;
+        if (p < h.N) {
             int i, j, k;
-            coords(pd, p, i, j, k);
-            y[p] = applyH_at<DIM>(pd, x, i, j, k, p);
+            split(p, h.nx, h.ny, h.fx, h.fxy, i, j, k);
+            out[s] = stencil<DIM, double>(h, x, i, j, k, p);
         }
+    }
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s) {
+        const int64_t p = base + threadIdx.x + (int64_t)HH_WG * s;
+        if (p < h.N) stg(y, p, out[s]);
     }
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(HH_WG) void k_applyM(const ProbDev *P, const Tile *tiles, const void *xp, void *yp)
+__global__ __launch_bounds__(HH_WG) void k_applyM(Ctx cx, const void *xp, void *yp)
 {
-    const Tile tl = tiles[blockIdx.x];
-    const ProbDev &pd = P[tl.prob];
-    const LevelDev<T> &L = levels<T>(pd)[0];
-    const V2<T> *x = (const V2<T> *)xp;
-    V2<T> *y = (V2<T> *)yp;
+    const Tile tl = tile_of(cx);
+    const MView<T> h = mview<T>(levels_of<T>(cx, cx.P + tl.prob));
+    const V2<T> *__restrict__ x = (const V2<T> *)xp;
+    V2<T> *__restrict__ y = (V2<T> *)yp;
     const int64_t base = (int64_t)tl.idx * HH_CHUNK;
+    V2<T> out[HH_PER_SLOT];
 #pragma unroll
     for (int s = 0; s < HH_PER_SLOT; ++s) {
-        int64_t p = base + threadIdx.x + (int64_t)HH_WG * s;
-        if (p < pd.N) {
+        const int64_t p = base + threadIdx.x + (int64_t)HH_WG * s;
+        if (p < h.N) {
             int i, j, k;
-            coords(pd, p, i, j, k);
-            y[p] = applyM_at<DIM, T>(L, x, i, j, k, p);
+            split(p, h.nx, h.ny, h.fx, h.fxy, i, j, k);
+            out[s] = stencil<DIM, T>(h, x, i, j, k, p);
         }
+    }
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s) {
+        const int64_t p = base + threadIdx.x + (int64_t)HH_WG * s;
+        if (p < h.N) stg(y, p, out[s]);
     }
 }
 
@@ -188,27 +454,40 @@ __global__ __launch_bounds__(HH_WG) void k_applyM(const ProbDev *P, const Tile *
 // Tile = a box of coarse points; LDS holds f, phi and u1 on the fine box
 // with a halo of 2 (restriction footprint + stencil).
 // ---------------------------------------------------------------------------
+template <int DIM, typename T>
+struct Box {
+    static constexpr int CX = VTile<DIM, T>::X, CY = VTile<DIM, T>::Y, CZ = VTile<DIM, T>::Z;
+};
+
 template <int DIM, typename T, typename TF>
-__global__ __launch_bounds__(HH_WG) void k_vdown(const ProbDev *P, const Tile *tiles, int lev, int fsel, const void *fptr)
+__global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, const void *fptr)
 {
     using C = V2<T>;
     constexpr int CX = VTile<DIM, T>::X, CY = VTile<DIM, T>::Y, CZ = VTile<DIM, T>::Z;
     constexpr int RX = 2 * CX + 4, RY = 2 * CY + 4, RZ = DIM == 3 ? 2 * CZ + 4 : 1;
     constexpr int RN = RX * RY * RZ;
+    constexpr int RM = RX > RY ? (RX > RZ ? RX : RZ) : (RY > RZ ? RY : RZ);
+    constexpr int NL = (RN + HH_WG - 1) / HH_WG;
     __shared__ C U[RN];
     __shared__ C F[RN];
     __shared__ T PH[RN];
-    __shared__ C A[3][RX > RY ? (RX > RZ ? RX : RZ) : (RY > RZ ? RY : RZ)];
-    __shared__ C Cc[3][RX > RY ? (RX > RZ ? RX : RZ) : (RY > RZ ? RY : RZ)];
-    __shared__ C Dd[3][RX > RY ? (RX > RZ ? RX : RZ) : (RY > RZ ? RY : RZ)];
+    __shared__ C A[3][RM];
+    __shared__ C Cc[3][RM];
+    __shared__ C Dd[3][RM];
 
-    const Tile tl = tiles[blockIdx.x];
-    const ProbDev &pd = P[tl.prob];
-    if (!running(pd)) return;
-    const LevelDev<T> &Lf = levels<T>(pd)[lev];
-    const LevelDev<T> &Lc = levels<T>(pd)[lev + 1];
-    const int nfx = Lf.n[0], nfy = Lf.n[1], nfz = Lf.n[2];
-    const int ncx = Lc.n[0], ncy = Lc.n[1], ncz = Lc.n[2];
+    const Tile tl = tile_of(cx);
+    if (phase_of(cx, tl.prob) != PH_RUN) return;
+    const ProbDev *pd = cx.P + tl.prob;
+    const LevelDev<T> *Lv = levels_of<T>(cx, pd);
+    const int nfx = Lv[lev].n[0], nfy = Lv[lev].n[1], nfz = Lv[lev].n[2];
+    const int ncx = Lv[lev + 1].n[0], ncy = Lv[lev + 1].n[1], ncz = Lv[lev + 1].n[2];
+    const V2<T> *ax0 = Lv[lev].a[0], *cx0 = Lv[lev].c[0], *dx0 = Lv[lev].d[0];
+    const V2<T> *ax1 = Lv[lev].a[1], *cx1 = Lv[lev].c[1], *dx1 = Lv[lev].d[1];
+    const V2<T> *ax2 = Lv[lev].a[2], *cx2 = Lv[lev].c[2], *dx2 = Lv[lev].d[2];
+    const T *__restrict__ phi = Lv[lev].phi;
+    C *__restrict__ fout = Lv[lev + 1].f;
+    const TF *__restrict__ f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lv[lev].f;
+    const T omega = (T)(cx.L ? cx.omega : pd->omega);
     const int tx = (ncx + CX - 1) / CX, ty = (ncy + CY - 1) / CY;
     int t = tl.idx;
     const int bx = t % tx;
@@ -216,38 +495,55 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(const ProbDev *P, const Tile *t
     const int by = t % ty, bz = t / ty;
     const int c0x = bx * CX, c0y = by * CY, c0z = DIM == 3 ? bz * CZ : 0;
     const int ox = 2 * c0x - 2, oy = 2 * c0y - 2, oz = DIM == 3 ? 2 * c0z - 2 : 0;
-    const TF *f = lev == 0 ? (const TF *)(fptr ? fptr : pd.vec[fsel]) : (const TF *)Lf.f;
-    const T omega = (T)pd.omega;
     const C zero = cmk<T>(0, 0);
     const int64_t sy = nfx, sz = (int64_t)nfx * nfy;
 
-    // per-axis coefficients of the box
+    // issue all global loads of the box first
+    TF fr[NL];
+    T pr[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int l = threadIdx.x + q * HH_WG;
+        const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
+        const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+        const bool in = l < RN && gx >= 0 && gx < nfx && gy >= 0 && gy < nfy && (DIM == 2 || (gz >= 0 && gz < nfz));
+        if (in) {
+            const int64_t p = gx + sy * gy + sz * gz;
+            fr[q] = ldg(f, p);
+            pr[q] = ldg(phi, p);
+        }
+    }
     for (int l = threadIdx.x; l < RX + RY + RZ; l += HH_WG) {
-        int ax = l < RX ? 0 : (l < RX + RY ? 1 : 2);
-        int q = ax == 0 ? l : (ax == 1 ? l - RX : l - RX - RY);
-        int g = (ax == 0 ? ox : (ax == 1 ? oy : oz)) + q;
-        int nn = ax == 0 ? nfx : (ax == 1 ? nfy : nfz);
-        bool in = (ax < DIM) && g >= 0 && g < nn;
-        A[ax][q] = in ? Lf.a[ax][g] : zero;
-        Cc[ax][q] = in ? Lf.c[ax][g] : zero;
-        Dd[ax][q] = in ? Lf.d[ax][g] : zero;
+        const int ax = l < RX ? 0 : (l < RX + RY ? 1 : 2);
+        const int q = ax == 0 ? l : (ax == 1 ? l - RX : l - RX - RY);
+        const int g = (ax == 0 ? ox : (ax == 1 ? oy : oz)) + q;
+        const int nn = ax == 0 ? nfx : (ax == 1 ? nfy : nfz);
+        const bool in = (ax < DIM) && g >= 0 && g < nn;
+        const V2<T> *pa = ax == 0 ? ax0 : (ax == 1 ? ax1 : ax2);
+        const V2<T> *pc = ax == 0 ? cx0 : (ax == 1 ? cx1 : cx2);
+        const V2<T> *pdd = ax == 0 ? dx0 : (ax == 1 ? dx1 : dx2);
+        A[ax][q] = in ? ldg(pa, g) : zero;
+        Cc[ax][q] = in ? ldg(pc, g) : zero;
+        Dd[ax][q] = in ? ldg(pdd, g) : zero;
     }
     __syncthreads();
-    // step 1: f, phi and u1 = g f on the whole box
-    for (int l = threadIdx.x; l < RN; l += HH_WG) {
+    // step 1: u1 = g f on the whole box
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int l = threadIdx.x + q * HH_WG;
+        if (l >= RN) break;
         const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
         const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
         C fv = zero, u1 = zero;
         T ph = 0;
         if (gx >= 0 && gx < nfx && gy >= 0 && gy < nfy && (DIM == 2 || (gz >= 0 && gz < nfz))) {
-            const int64_t p = gx + sy * gy + sz * gz;
-            fv = ccvt<T>(f[p]);
-            ph = Lf.phi[p];
+            fv = ccvt<T>(fr[q]);
+            ph = pr[q];
             C d = cadd<T>(Dd[0][lx], Dd[1][ly]);
             if (DIM == 3) d = cadd<T>(d, Dd[2][lz]);
             C D = cmk<T>(d.x - ph, d.y);
-            T q = omega / (D.x * D.x + D.y * D.y);
-            C gw = cmk<T>(D.x * q, -(D.y * q));
+            T qq = omega / (D.x * D.x + D.y * D.y);
+            C gw = cmk<T>(D.x * qq, -(D.y * qq));
             u1 = cmul<T>(gw, fv);
         }
         U[l] = u1;
@@ -293,6 +589,7 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(const ProbDev *P, const Tile *t
         for (int c = 0; c < (DIM == 3 ? 4 : 1); ++c) {
             const T wz = (c == 0 || c == 3) ? w0 : w1;
             C acc_y = zero;
+#pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const T wy = (b == 0 || b == 3) ? w0 : w1;
                 const C *row = &F[bxl + RX * ((byl + b) + RY * (bzl + c))];
@@ -305,7 +602,7 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(const ProbDev *P, const Tile *t
             if (DIM == 3) acc_z = c == 0 ? crs<T>(wz, acc_y) : cadd<T>(acc_z, crs<T>(wz, acc_y));
             else acc_z = acc_y;
         }
-        Lc.f[I + (int64_t)ncx * (J + (int64_t)ncy * K)] = acc_z;
+        stg(fout, I + (int64_t)ncx * (J + (int64_t)ncy * K), acc_z);
     }
 }
 
@@ -315,7 +612,7 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(const ProbDev *P, const Tile *t
 // Output: e_lev (lev >= 1) or the output vector (lev == 0, storage TO).
 // ---------------------------------------------------------------------------
 template <int DIM, typename T, typename TF, typename TO>
-__global__ __launch_bounds__(HH_WG) void k_vup(const ProbDev *P, const Tile *tiles, int lev, int fsel, int osel, const void *fptr, void *optr)
+__global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int osel, const void *fptr, void *optr)
 {
     using C = V2<T>;
     constexpr int CX = VTile<DIM, T>::X, CY = VTile<DIM, T>::Y, CZ = VTile<DIM, T>::Z;
@@ -325,6 +622,8 @@ __global__ __launch_bounds__(HH_WG) void k_vup(const ProbDev *P, const Tile *til
     constexpr int EX = CX + 4, EY = CY + 4, EZ = DIM == 3 ? CZ + 4 : 1;
     constexpr int EN = EX * EY * EZ;
     constexpr int RM = RX > RY ? (RX > RZ ? RX : RZ) : (RY > RZ ? RY : RZ);
+    constexpr int NL = (RN + HH_WG - 1) / HH_WG;
+    constexpr int NE = (EN + HH_WG - 1) / HH_WG;
     __shared__ C U[RN];
     __shared__ C F[RN];
     __shared__ T PH[RN];
@@ -333,13 +632,21 @@ __global__ __launch_bounds__(HH_WG) void k_vup(const ProbDev *P, const Tile *til
     __shared__ C Cc[3][RM];
     __shared__ C Dd[3][RM];
 
-    const Tile tl = tiles[blockIdx.x];
-    const ProbDev &pd = P[tl.prob];
-    if (!running(pd)) return;
-    const LevelDev<T> &Lf = levels<T>(pd)[lev];
-    const LevelDev<T> &Lc = levels<T>(pd)[lev + 1];
-    const int nfx = Lf.n[0], nfy = Lf.n[1], nfz = Lf.n[2];
-    const int ncx = Lc.n[0], ncy = Lc.n[1], ncz = Lc.n[2];
+    const Tile tl = tile_of(cx);
+    if (phase_of(cx, tl.prob) != PH_RUN) return;
+    const ProbDev *pd = cx.P + tl.prob;
+    const LevelDev<T> *Lv = levels_of<T>(cx, pd);
+    const int nfx = Lv[lev].n[0], nfy = Lv[lev].n[1], nfz = Lv[lev].n[2];
+    const int ncx = Lv[lev + 1].n[0], ncy = Lv[lev + 1].n[1], ncz = Lv[lev + 1].n[2];
+    const V2<T> *ax0 = Lv[lev].a[0], *cx0 = Lv[lev].c[0], *dx0 = Lv[lev].d[0];
+    const V2<T> *ax1 = Lv[lev].a[1], *cx1 = Lv[lev].c[1], *dx1 = Lv[lev].d[1];
+    const V2<T> *ax2 = Lv[lev].a[2], *cx2 = Lv[lev].c[2], *dx2 = Lv[lev].d[2];
+    const T *__restrict__ phi = Lv[lev].phi;
+    const C *__restrict__ ec = Lv[lev + 1].e;
+    C *__restrict__ eout = Lv[lev].e;
+    const TF *__restrict__ f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lv[lev].f;
+    TO *__restrict__ outv = lev == 0 ? (TO *)(optr ? optr : pd->vec[osel]) : nullptr;
+    const T omega = (T)(cx.L ? cx.omega : pd->omega);
     const int tx = (nfx + FX - 1) / FX, ty = (nfy + FY - 1) / FY;
     int t = tl.idx;
     const int bx = t % tx;
@@ -348,48 +655,72 @@ __global__ __launch_bounds__(HH_WG) void k_vup(const ProbDev *P, const Tile *til
     const int f0x = bx * FX, f0y = by * FY, f0z = DIM == 3 ? bz * FZ : 0;
     const int ox = f0x - 1, oy = f0y - 1, oz = DIM == 3 ? f0z - 1 : 0;
     const int ex0 = (f0x >> 1) - 2, ey0 = (f0y >> 1) - 2, ez0 = DIM == 3 ? (f0z >> 1) - 2 : 0;
-    const TF *f = lev == 0 ? (const TF *)(fptr ? fptr : pd.vec[fsel]) : (const TF *)Lf.f;
-    const T omega = (T)pd.omega;
     const C zero = cmk<T>(0, 0);
     const int64_t sy = nfx, sz = (int64_t)nfx * nfy;
 
-    for (int l = threadIdx.x; l < EN; l += HH_WG) {
+    // all global loads first: f and phi on the box, e on the coarse box
+    TF fr[NL];
+    T pr[NL];
+    C er[NE];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int l = threadIdx.x + q * HH_WG;
+        const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
+        const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+        const bool in = l < RN && gx >= 0 && gx < nfx && gy >= 0 && gy < nfy && (DIM == 2 || (gz >= 0 && gz < nfz));
+        if (in) {
+            const int64_t p = gx + sy * gy + sz * gz;
+            fr[q] = ldg(f, p);
+            pr[q] = ldg(phi, p);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int l = threadIdx.x + q * HH_WG;
         const int lx = l % EX, ly = (l / EX) % EY, lz = l / (EX * EY);
         const int gx = ex0 + lx, gy = ey0 + ly, gz = ez0 + lz;
-        C v = zero;
-        if (gx >= 0 && gx < ncx && gy >= 0 && gy < ncy && (DIM == 2 || (gz >= 0 && gz < ncz)))
-            v = Lc.e[gx + (int64_t)ncx * (gy + (int64_t)ncy * gz)];
-        E[l] = v;
+        er[q] = zero;
+        if (l < EN && gx >= 0 && gx < ncx && gy >= 0 && gy < ncy && (DIM == 2 || (gz >= 0 && gz < ncz)))
+            er[q] = ldg(ec, gx + (int64_t)ncx * (gy + (int64_t)ncy * gz));
     }
     for (int l = threadIdx.x; l < RX + RY + RZ; l += HH_WG) {
-        int ax = l < RX ? 0 : (l < RX + RY ? 1 : 2);
-        int q = ax == 0 ? l : (ax == 1 ? l - RX : l - RX - RY);
-        int g = (ax == 0 ? ox : (ax == 1 ? oy : oz)) + q;
-        int nn = ax == 0 ? nfx : (ax == 1 ? nfy : nfz);
-        bool in = (ax < DIM) && g >= 0 && g < nn;
-        A[ax][q] = in ? Lf.a[ax][g] : zero;
-        Cc[ax][q] = in ? Lf.c[ax][g] : zero;
-        Dd[ax][q] = in ? Lf.d[ax][g] : zero;
+        const int ax = l < RX ? 0 : (l < RX + RY ? 1 : 2);
+        const int q = ax == 0 ? l : (ax == 1 ? l - RX : l - RX - RY);
+        const int g = (ax == 0 ? ox : (ax == 1 ? oy : oz)) + q;
+        const int nn = ax == 0 ? nfx : (ax == 1 ? nfy : nfz);
+        const bool in = (ax < DIM) && g >= 0 && g < nn;
+        const V2<T> *pa = ax == 0 ? ax0 : (ax == 1 ? ax1 : ax2);
+        const V2<T> *pc = ax == 0 ? cx0 : (ax == 1 ? cx1 : cx2);
+        const V2<T> *pdd = ax == 0 ? dx0 : (ax == 1 ? dx1 : dx2);
+        A[ax][q] = in ? ldg(pa, g) : zero;
+        Cc[ax][q] = in ? ldg(pc, g) : zero;
+        Dd[ax][q] = in ? ldg(pdd, g) : zero;
+    }
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int l = threadIdx.x + q * HH_WG;
+        if (l < EN) E[l] = er[q];
     }
     __syncthreads();
     const T p3 = (T)0.75, p1 = (T)0.25;
     // step 1: u2 = g f + P e on the tile plus a halo of one
-    for (int l = threadIdx.x; l < RN; l += HH_WG) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int l = threadIdx.x + q * HH_WG;
+        if (l >= RN) break;
         const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
         const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
         C fv = zero, u2 = zero;
         T ph = 0;
         if (gx >= 0 && gx < nfx && gy >= 0 && gy < nfy && (DIM == 2 || (gz >= 0 && gz < nfz))) {
-            const int64_t p = gx + sy * gy + sz * gz;
-            fv = ccvt<T>(f[p]);
-            ph = Lf.phi[p];
+            fv = ccvt<T>(fr[q]);
+            ph = pr[q];
             C d = cadd<T>(Dd[0][lx], Dd[1][ly]);
             if (DIM == 3) d = cadd<T>(d, Dd[2][lz]);
             C D = cmk<T>(d.x - ph, d.y);
-            T q = omega / (D.x * D.x + D.y * D.y);
-            C gw = cmk<T>(D.x * q, -(D.y * q));
+            T qq = omega / (D.x * D.x + D.y * D.y);
+            C gw = cmk<T>(D.x * qq, -(D.y * qq));
             C u1 = cmul<T>(gw, fv);
-            // prolongation: per axis near = g>>1, far = near -/+ 1
             const int Ix = (gx >> 1) - ex0, Iox = ((gx & 1) ? (gx >> 1) + 1 : (gx >> 1) - 1) - ex0;
             const int Iy = (gy >> 1) - ey0, Ioy = ((gy & 1) ? (gy >> 1) + 1 : (gy >> 1) - 1) - ey0;
             C pe;
@@ -417,7 +748,6 @@ __global__ __launch_bounds__(HH_WG) void k_vup(const ProbDev *P, const Tile *til
     }
     __syncthreads();
     // step 2: post-smoothing on the tile
-    TO *outv = lev == 0 ? (TO *)(optr ? optr : pd.vec[osel]) : nullptr;
     for (int r = threadIdx.x; r < FX * FY * FZ; r += HH_WG) {
         const int lx = 1 + r % FX, ly = 1 + (r / FX) % FY, lz = (DIM == 3 ? 1 : 0) + r / (FX * FY);
         const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
@@ -426,8 +756,8 @@ __global__ __launch_bounds__(HH_WG) void k_vup(const ProbDev *P, const Tile *til
         C d = cadd<T>(Dd[0][lx], Dd[1][ly]);
         if (DIM == 3) d = cadd<T>(d, Dd[2][lz]);
         C D = cmk<T>(d.x - PH[l], d.y);
-        T q = omega / (D.x * D.x + D.y * D.y);
-        C gw = cmk<T>(D.x * q, -(D.y * q));
+        T qq = omega / (D.x * D.x + D.y * D.y);
+        C gw = cmk<T>(D.x * qq, -(D.y * qq));
         C mu = cmul<T>(D, U[l]);
         mu = csub<T>(mu, cmul<T>(A[0][lx], U[l - 1]));
         mu = csub<T>(mu, cmul<T>(Cc[0][lx], U[l + 1]));
@@ -443,338 +773,607 @@ __global__ __launch_bounds__(HH_WG) void k_vup(const ProbDev *P, const Tile *til
             TO o;
             o.x = u.x;
             o.y = u.y;
-            outv[p] = o;
+            stg(outv, p, o);
         } else {
-            Lf.e[p] = u;
+            stg(eout, p, u);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// coarsest solve e = Minv f: one wave per row, pairwise over the row
+// tail of the V-cycle: every level from `tail` down to the coarsest inside
+// one workgroup, all fields in LDS.  Reads f_tail, writes e_tail.  Same
+// arithmetic as the tiled kernels; the coarsest solve applies the explicit
+// inverse with a pairwise sum per row.
 // ---------------------------------------------------------------------------
+// Coarsest solve by one wave: rows row0, row0 + rstep, ... (up to 16 / seg
+// rows at once, loads issued together) of Minv applied to f (LDS); each row
+// is summed pairwise over its zero-padded length (lane segments of Np/64
+// terms, then a butterfly).  Lane 0 writes e[row].
 template <typename T>
-__global__ __launch_bounds__(HH_WG) void k_coarse(const ProbDev *P, const Tile *tiles)
+__device__ inline void coarse_rows(const V2<T> *__restrict__ Minv, const V2<T> *f, V2<T> *e, int n, int row0, int rstep)
 {
-    using C = V2<T>;
-    const Tile tl = tiles[blockIdx.x];
-    const ProbDev &pd = P[tl.prob];
-    if (!running(pd)) return;
-    const LevelDev<T> &L = levels<T>(pd)[pd.nlev - 1];
-    const C *Minv = (const C *)(sizeof(T) == 8 ? (const void *)pd.Minv64 : (const void *)pd.Minv32);
-    const int n = pd.Nc;
-    const int row = tl.idx * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (row >= n) return;
     int np = 64;
     while (np < n) np <<= 1;
-    const int seg = np >> 6;   // 1..16
-    T re[16], im[16];
+    const int seg = np >> 6;       // 1..16
+    const int rpb = 16 / seg;      // rows per batch
+    for (int rb = row0; rb < n; rb += rpb * rstep) {
+        T re[16], im[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        re[i] = 0;
-        im[i] = 0;
-        const int col = lane * seg + i;
-        if (i < seg && col < n) {
-            C pr = cmul<T>(Minv[(int64_t)row * n + col], L.f[col]);
-            re[i] = pr.x;
-            im[i] = pr.y;
-        }
-    }
-#pragma unroll
-    for (int w = 1; w < 16; w <<= 1) {
-        if (w < seg) {
-#pragma unroll
-            for (int i = 0; i + w < 16; i += 2 * w) {
-                re[i] = re[i] + re[i + w];
-                im[i] = im[i] + im[i + w];
+        for (int q = 0; q < 16; ++q) {
+            re[q] = 0;
+            im[q] = 0;
+            const int r = q / seg, i = q - r * seg;
+            const int row = rb + r * rstep, col = lane * seg + i;
+            if (r < rpb && row < n && col < n) {
+                V2<T> pr = cmul<T>(ldg(Minv, (int64_t)row * n + col), f[col]);
+                re[q] = pr.x;
+                im[q] = pr.y;
             }
         }
-    }
-    T sr = re[0], si = im[0];
+        // in-lane pairwise over each row's segment (segments are aligned
+        // power-of-two blocks of the 16 slots)
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        sr = sr + __shfl_xor(sr, off, 64);
-        si = si + __shfl_xor(si, off, 64);
+        for (int w = 1; w < 16; w <<= 1) {
+            if (w < seg) {
+#pragma unroll
+                for (int i = 0; i + w < 16; i += 2 * w) {
+                    re[i] = re[i] + re[i + w];
+                    im[i] = im[i] + im[i + w];
+                }
+            }
+        }
+        for (int r = 0; r < rpb; ++r) {
+            T sr = 0, si = 0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (q == r * seg) {
+                    sr = re[q];
+                    si = im[q];
+                }
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                sr = sr + __shfl_xor(sr, off, 64);
+                si = si + __shfl_xor(si, off, 64);
+            }
+            const int row = rb + r * rstep;
+            if (lane == 0 && row < n) e[row] = cmk<T>(sr, si);
+        }
     }
-    if (lane == 0) L.e[row] = cmk<T>(sr, si);
+}
+
+template <typename T> __device__ inline V2<T> jweight(V2<T> D, T omega)
+{
+    T q = omega / (D.x * D.x + D.y * D.y);
+    return cmk<T>(D.x * q, -(D.y * q));
+}
+
+// LDS layout of one tail level: byte offsets of f, e, phi and the per-axis
+// coefficient arrays (16-byte rounded, carved level after level from the
+// tail's first level; the shared scratch U follows the last level).
+struct TailOff {
+    int n[3], N;
+    int F, E, PH, A[3], Cc[3], Dd[3];
+};
+
+template <int DIM, typename T>
+__device__ inline TailOff tail_off(const LevelDev<T> *Lv, int t0, int l, int &end)
+{
+    const int cb = sizeof(V2<T>), rb = sizeof(T);
+    auto r16 = [](int b) { return (b + 15) & ~15; };
+    int off = 0;
+    TailOff o;
+    for (int q = t0; q <= l; ++q) {
+        const int N = (int)Lv[q].N;
+        o.N = N;
+        for (int a = 0; a < 3; ++a) o.n[a] = Lv[q].n[a];
+        o.F = off; off += r16(cb * N);
+        o.E = off; off += r16(cb * N);
+        o.PH = off; off += r16(rb * N);
+        for (int a = 0; a < 3; ++a) {
+            const int na = a < DIM ? o.n[a] : 1;
+            o.A[a] = off; off += r16(cb * na);
+            o.Cc[a] = off; off += r16(cb * na);
+            o.Dd[a] = off; off += r16(cb * na);
+        }
+    }
+    end = off;
+    return o;
+}
+
+// pointers of one tail level into the LDS block
+template <typename T> struct TailPtr {
+    int nx, ny, nz, N;
+    FastDiv fx, fxy;
+    V2<T> *F, *E, *A0, *A1, *A2, *C0, *C1, *C2, *D0, *D1, *D2;
+    T *PH;
+};
+
+template <int DIM, typename T>
+__device__ inline TailPtr<T> tail_ptr(char *lds, const LevelDev<T> *Lv, int t0, int l)
+{
+    int end;
+    const TailOff o = tail_off<DIM, T>(Lv, t0, l, end);
+    TailPtr<T> q;
+    q.nx = o.n[0];
+    q.ny = o.n[1];
+    q.nz = o.n[2];
+    q.N = o.N;
+    q.fx = Lv[l].fx;
+    q.fxy = Lv[l].fxy;
+    q.F = (V2<T> *)(lds + o.F);
+    q.E = (V2<T> *)(lds + o.E);
+    q.PH = (T *)(lds + o.PH);
+    q.A0 = (V2<T> *)(lds + o.A[0]); q.A1 = (V2<T> *)(lds + o.A[1]); q.A2 = (V2<T> *)(lds + o.A[2]);
+    q.C0 = (V2<T> *)(lds + o.Cc[0]); q.C1 = (V2<T> *)(lds + o.Cc[1]); q.C2 = (V2<T> *)(lds + o.Cc[2]);
+    q.D0 = (V2<T> *)(lds + o.Dd[0]); q.D1 = (V2<T> *)(lds + o.Dd[1]); q.D2 = (V2<T> *)(lds + o.Dd[2]);
+    return q;
+}
+
+template <int DIM, typename T>
+__device__ inline V2<T> tail_diag(const TailPtr<T> &Q, int i, int j, int k, int p)
+{
+    V2<T> d = cadd<T>(Q.D0[i], Q.D1[j]);
+    if (DIM == 3) d = cadd<T>(d, Q.D2[k]);
+    return cmk<T>(d.x - Q.PH[p], d.y);
+}
+
+template <int DIM, typename T>
+__device__ inline V2<T> tail_Mu(const TailPtr<T> &Q, const V2<T> *U, V2<T> D, int i, int j, int k, int p)
+{
+    using C = V2<T>;
+    const C zero = cmk<T>(0, 0);
+    const int sy = Q.nx, sz = Q.nx * Q.ny;
+    C mu = cmul<T>(D, U[p]);
+    mu = csub<T>(mu, cmul<T>(Q.A0[i], i > 0 ? U[p - 1] : zero));
+    mu = csub<T>(mu, cmul<T>(Q.C0[i], i < Q.nx - 1 ? U[p + 1] : zero));
+    mu = csub<T>(mu, cmul<T>(Q.A1[j], j > 0 ? U[p - sy] : zero));
+    mu = csub<T>(mu, cmul<T>(Q.C1[j], j < Q.ny - 1 ? U[p + sy] : zero));
+    if (DIM == 3) {
+        mu = csub<T>(mu, cmul<T>(Q.A2[k], k > 0 ? U[p - sz] : zero));
+        mu = csub<T>(mu, cmul<T>(Q.C2[k], k < Q.nz - 1 ? U[p + sz] : zero));
+    }
+    return mu;
+}
+
+template <typename T>
+__device__ inline void tail_ijk(const TailPtr<T> &Q, int p, int &i, int &j, int &k)
+{
+    split(p, Q.nx, Q.ny, Q.fx, Q.fxy, i, j, k);
 }
 
 // ---------------------------------------------------------------------------
-// Bi-CGSTAB passes (right preconditioned; s is kept in r)
+// tail of the V-cycle: every level from `tail` down to the coarsest inside
+// one workgroup, all fields in LDS.  Reads f_tail, writes e_tail.  Same
+// arithmetic as the tiled kernels; the coarsest solve applies the explicit
+// inverse with a pairwise sum per row.
 // ---------------------------------------------------------------------------
-#define CHUNK_LOOP(...)                                                               \
-    const int64_t base = (int64_t)tl.idx * HH_CHUNK;                                  \
-    _Pragma("unroll") for (int s_ = 0; s_ < HH_PER_SLOT; ++s_)                        \
-    {                                                                                 \
-        const int64_t p = base + threadIdx.x + (int64_t)HH_WG * s_;                   \
-        if (p < pd.N) { __VA_ARGS__ }                                                 \
+template <int DIM, typename T>
+__global__ __launch_bounds__(HH_TAIL_WG) void k_vtail(Ctx cx, const int *__restrict__ probs)
+{
+    using C = V2<T>;
+    __shared__ __attribute__((aligned(16))) char lds[TailCap<T>::BYTES];
+    const int prob = probs ? probs[blockIdx.x] : 0;
+    if (phase_of(cx, prob) != PH_RUN) return;
+    const ProbDev *pd = cx.P + prob;
+    const LevelDev<T> *Lv = levels_of<T>(cx, pd);
+    const int t0 = tail_level<T>(pd), L = pd->nlev;
+    const T omega = (T)pd->omega;
+    const C zero = cmk<T>(0, 0);
+    const int tid = threadIdx.x, nth = HH_TAIL_WG;
+    int uoff;
+    tail_off<DIM, T>(Lv, t0, L - 1, uoff);
+    C *U = (C *)(lds + uoff);
+    // the tail image (phi and coefficients of every tail level, zeros
+    // elsewhere) in one coalesced sweep, then f at the top level
+    {
+        const void *img = sizeof(T) == 8 ? pd->timg64 : pd->timg32;
+        const int n16 = (sizeof(T) == 8 ? pd->timg_bytes64 : pd->timg_bytes32) / 16;
+        hh_uvec4 *l16 = (hh_uvec4 *)lds;
+        for (int b = 0; b < n16; b += 8 * nth) {
+            hh_uvec4 tmp[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int i = b + tid + q * nth;
+                if (i < n16) tmp[q] = ldg16(img, i);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int i = b + tid + q * nth;
+                if (i < n16) l16[i] = tmp[q];
+            }
+        }
+        __syncthreads();
+        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, Lv, t0, t0);
+        const C *__restrict__ fg = Lv[t0].f;
+        for (int b = 0; b < Q.N; b += 4 * nth) {
+            C tmp[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (b + tid + q * nth < Q.N) tmp[q] = ldg(fg, b + tid + q * nth);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (b + tid + q * nth < Q.N) Q.F[b + tid + q * nth] = tmp[q];
+        }
     }
+    __syncthreads();
+    const T w0 = (T)0.125, w1 = (T)0.375, p3 = (T)0.75, p1 = (T)0.25;
+    // down-legs
+    for (int l = t0; l < L - 1; ++l) {
+        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, Lv, t0, l);
+        const TailPtr<T> R = tail_ptr<DIM, T>(lds, Lv, t0, l + 1);
+        for (int p = tid; p < Q.N; p += nth) {
+            int i, j, k;
+            tail_ijk(Q, p, i, j, k);
+            U[p] = cmul<T>(jweight<T>(tail_diag<DIM, T>(Q, i, j, k, p), omega), Q.F[p]);
+        }
+        __syncthreads();
+        for (int p = tid; p < Q.N; p += nth) {
+            int i, j, k;
+            tail_ijk(Q, p, i, j, k);
+            C D = tail_diag<DIM, T>(Q, i, j, k, p);
+            Q.E[p] = csub<T>(Q.F[p], tail_Mu<DIM, T>(Q, U, D, i, j, k, p));   // residual kept in E
+        }
+        __syncthreads();
+        for (int p = tid; p < R.N; p += nth) {
+            int I, J, K;
+            tail_ijk(R, p, I, J, K);
+            C acc_z = zero;
+            for (int c = 0; c < (DIM == 3 ? 4 : 1); ++c) {
+                const T wz = (c == 0 || c == 3) ? w0 : w1;
+                const int kk = DIM == 3 ? 2 * K - 1 + c : 0;
+                const bool kin = DIM == 2 || (kk >= 0 && kk < Q.nz);
+                C acc_y = zero;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const T wy = (b == 0 || b == 3) ? w0 : w1;
+                    const int jj = 2 * J - 1 + b;
+                    const bool jin = kin && jj >= 0 && jj < Q.ny;
+                    C v[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const int ii = 2 * I - 1 + a;
+                        v[a] = (jin && ii >= 0 && ii < Q.nx) ? Q.E[ii + Q.nx * (jj + Q.ny * kk)] : zero;
+                    }
+                    C sx = crs<T>(w0, v[0]);
+                    sx = cadd<T>(sx, crs<T>(w1, v[1]));
+                    sx = cadd<T>(sx, crs<T>(w1, v[2]));
+                    sx = cadd<T>(sx, crs<T>(w0, v[3]));
+                    acc_y = b == 0 ? crs<T>(wy, sx) : cadd<T>(acc_y, crs<T>(wy, sx));
+                }
+                if (DIM == 3) acc_z = c == 0 ? crs<T>(wz, acc_y) : cadd<T>(acc_z, crs<T>(wz, acc_y));
+                else acc_z = acc_y;
+            }
+            R.F[p] = acc_z;
+        }
+        __syncthreads();
+    }
+    // coarsest solve
+    {
+        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, Lv, t0, L - 1);
+        const C *__restrict__ Minv = (const C *)(sizeof(T) == 8 ? (const void *)pd->Minv64 : (const void *)pd->Minv32);
+        coarse_rows<T>(Minv, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
+        __syncthreads();
+    }
+    // up-legs
+    for (int l = L - 2; l >= t0; --l) {
+        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, Lv, t0, l);
+        const TailPtr<T> R = tail_ptr<DIM, T>(lds, Lv, t0, l + 1);
+        for (int p = tid; p < Q.N; p += nth) {
+            int i, j, k;
+            tail_ijk(Q, p, i, j, k);
+            C u1 = cmul<T>(jweight<T>(tail_diag<DIM, T>(Q, i, j, k, p), omega), Q.F[p]);
+            const int Ix = i >> 1, Iox = (i & 1) ? Ix + 1 : Ix - 1;
+            const int Iy = j >> 1, Ioy = (j & 1) ? Iy + 1 : Iy - 1;
+            auto ev = [&](int a, int b, int c) -> C {
+                return (a >= 0 && a < R.nx && b >= 0 && b < R.ny && c >= 0 && c < R.nz) ? R.E[a + R.nx * (b + R.ny * c)] : zero;
+            };
+            C pe;
+            if (DIM == 2) {
+                C a0 = cadd<T>(crs<T>(p3, ev(Ix, Iy, 0)), crs<T>(p1, ev(Iox, Iy, 0)));
+                C a1 = cadd<T>(crs<T>(p3, ev(Ix, Ioy, 0)), crs<T>(p1, ev(Iox, Ioy, 0)));
+                pe = cadd<T>(crs<T>(p3, a0), crs<T>(p1, a1));
+            } else {
+                const int Iz = k >> 1, Ioz = (k & 1) ? Iz + 1 : Iz - 1;
+                C pz[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int zz = c == 0 ? Iz : Ioz;
+                    C a0 = cadd<T>(crs<T>(p3, ev(Ix, Iy, zz)), crs<T>(p1, ev(Iox, Iy, zz)));
+                    C a1 = cadd<T>(crs<T>(p3, ev(Ix, Ioy, zz)), crs<T>(p1, ev(Iox, Ioy, zz)));
+                    pz[c] = cadd<T>(crs<T>(p3, a0), crs<T>(p1, a1));
+                }
+                pe = cadd<T>(crs<T>(p3, pz[0]), crs<T>(p1, pz[1]));
+            }
+            U[p] = cadd<T>(u1, pe);
+        }
+        __syncthreads();
+        for (int p = tid; p < Q.N; p += nth) {
+            int i, j, k;
+            tail_ijk(Q, p, i, j, k);
+            C D = tail_diag<DIM, T>(Q, i, j, k, p);
+            C mu = tail_Mu<DIM, T>(Q, U, D, i, j, k, p);
+            Q.E[p] = cadd<T>(U[p], cmul<T>(jweight<T>(D, omega), csub<T>(Q.F[p], mu)));
+        }
+        __syncthreads();
+    }
+    // write e at the top tail level
+    {
+        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, Lv, t0, t0);
+        C *__restrict__ eg = Lv[t0].e;
+        for (int p = tid; p < Q.N; p += nth) stg(eg, p, Q.E[p]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bi-CGSTAB passes (right preconditioned; s is kept in r).  Each pass
+// reduces its dot products per chunk and finalises in its last workgroup.
+// ---------------------------------------------------------------------------
+#define CHUNK_P(s_) (base + threadIdx.x + (int64_t)HH_WG * (s_))
 
 // p = r + beta (p - omega v)
-__global__ __launch_bounds__(HH_WG) void k_bicg_p(const ProbDev *P, const Tile *tiles)
+__global__ __launch_bounds__(HH_WG) void k_bicg_p(Ctx cx)
 {
-    const Tile tl = tiles[blockIdx.x];
-    const ProbDev &pd = P[tl.prob];
-    if (!running(pd)) return;
-    const double2 beta = pd.st->beta, omega = pd.st->omega;
-    double2 *pv = (double2 *)pd.vec[VS_P];
-    const double2 *r = (const double2 *)pd.vec[VS_R], *v = (const double2 *)pd.vec[VS_V];
-    CHUNK_LOOP(pv[p] = cadd<double>(r[p], cmul<double>(beta, csub<double>(pv[p], cmul<double>(omega, v[p]))));)
+    const Tile tl = tile_of(cx);
+    const Ctrl ct = ctrl_of(cx, tl.prob);
+    if (ct.phase != PH_RUN) return;
+    const ProbDev *pd = cx.P + tl.prob;
+    const double2 beta = ct.beta, omega = ct.omega;
+    double2 *__restrict__ pv = (double2 *)pd->vec[VS_P];
+    const double2 *__restrict__ r = (const double2 *)pd->vec[VS_R];
+    const double2 *__restrict__ v = (const double2 *)pd->vec[VS_V];
+    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_CHUNK;
+    double2 pr[HH_PER_SLOT], rr[HH_PER_SLOT], vr[HH_PER_SLOT];
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s)
+        if (CHUNK_P(s) < N) {
+            pr[s] = ldg(pv, CHUNK_P(s));
+            rr[s] = ldg(r, CHUNK_P(s));
+            vr[s] = ldg(v, CHUNK_P(s));
+        }
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s)
+        if (CHUNK_P(s) < N)
+            stg(pv, CHUNK_P(s), cadd<double>(rr[s], cmul<double>(beta, csub<double>(pr[s], cmul<double>(omega, vr[s])))));
 }
 
-// v = H phat ; partial (rhat, v)
+// v = H phat ; partial (rhat, v) ; finalise alpha
 template <int DIM, typename SP>
-__global__ __launch_bounds__(HH_WG) void k_bicg_v(const ProbDev *P, const Tile *tiles)
+__global__ __launch_bounds__(HH_WG) void k_bicg_v(Ctx cx)
 {
-    const Tile tl = tiles[blockIdx.x];
-    const ProbDev &pd = P[tl.prob];
-    if (!running(pd)) return;
-    const SP *ph = (const SP *)pd.vec[VS_PH];
-    double2 *v = (double2 *)pd.vec[VS_V];
-    const double2 *rh = (const double2 *)pd.vec[VS_RH];
-    double acc[2] = {0.0, 0.0};
-    CHUNK_LOOP({
-        int i, j, k;
-        coords(pd, p, i, j, k);
-        double2 y = applyH_at<DIM>(pd, ph, i, j, k, p);
-        v[p] = y;
-        double2 a = rh[p];
-        acc[0] = acc[0] + (a.x * y.x + a.y * y.y);
-        acc[1] = acc[1] + (a.x * y.y - a.y * y.x);
-    })
-    block_reduce<2>(acc, pd.part + (int64_t)tl.idx * HH_NPART);
-}
-
-// s = r - alpha v (in r) ; partial ||s||^2
-__global__ __launch_bounds__(HH_WG) void k_bicg_s(const ProbDev *P, const Tile *tiles)
-{
-    const Tile tl = tiles[blockIdx.x];
-    const ProbDev &pd = P[tl.prob];
-    if (!running(pd)) return;
-    const double2 alpha = pd.st->alpha;
-    double2 *r = (double2 *)pd.vec[VS_R];
-    const double2 *v = (const double2 *)pd.vec[VS_V];
-    double acc[1] = {0.0};
-    CHUNK_LOOP({
-        double2 s = csub<double>(r[p], cmul<double>(alpha, v[p]));
-        r[p] = s;
-        acc[0] = acc[0] + (s.x * s.x + s.y * s.y);
-    })
-    block_reduce<1>(acc, pd.part + (int64_t)tl.idx * HH_NPART);
-}
-
-// t = H shat ; partials (t, s), (t, t)
-template <int DIM, typename SP>
-__global__ __launch_bounds__(HH_WG) void k_bicg_t(const ProbDev *P, const Tile *tiles)
-{
-    const Tile tl = tiles[blockIdx.x];
-    const ProbDev &pd = P[tl.prob];
-    if (!running(pd)) return;
-    const SP *sh = (const SP *)pd.vec[VS_SH];
-    double2 *t = (double2 *)pd.vec[VS_T];
-    const double2 *s = (const double2 *)pd.vec[VS_R];
-    double acc[3] = {0.0, 0.0, 0.0};
-    CHUNK_LOOP({
-        int i, j, k;
-        coords(pd, p, i, j, k);
-        double2 y = applyH_at<DIM>(pd, sh, i, j, k, p);
-        t[p] = y;
-        double2 b = s[p];
-        acc[0] = acc[0] + (y.x * b.x + y.y * b.y);
-        acc[1] = acc[1] + (y.x * b.y - y.y * b.x);
-        acc[2] = acc[2] + (y.x * y.x + y.y * y.y);
-    })
-    block_reduce<3>(acc, pd.part + (int64_t)tl.idx * HH_NPART);
-}
-
-// x = x + alpha phat + omega shat ; r = s - omega t ; partials (rhat, r), ||r||^2
-// (half-step exit: x = x + alpha phat only)
-template <typename SP>
-__global__ __launch_bounds__(HH_WG) void k_bicg_xr(const ProbDev *P, const Tile *tiles)
-{
-    const Tile tl = tiles[blockIdx.x];
-    const ProbDev &pd = P[tl.prob];
-    const int phase = pd.st->phase;
-    if (phase != PH_RUN && phase != PH_HALF) return;
-    const double2 alpha = pd.st->alpha, omega = pd.st->omega;
-    double2 *x = (double2 *)pd.vec[VS_X];
-    const SP *ph = (const SP *)pd.vec[VS_PH];
-    if (phase == PH_HALF) {
-        CHUNK_LOOP(x[p] = cadd<double>(x[p], cmul<double>(alpha, ld64(ph, p)));)
-        return;
+    const Tile tl = tile_of(cx);
+    if (phase_of(cx, tl.prob) != PH_RUN) return;
+    const ProbDev *pd = cx.P + tl.prob;
+    const HView h = hview(pd);
+    const SP *__restrict__ ph = (const SP *)pd->vec[VS_PH];
+    double2 *__restrict__ v = (double2 *)pd->vec[VS_V];
+    const double2 *__restrict__ rh = (const double2 *)pd->vec[VS_RH];
+    const int64_t base = (int64_t)tl.idx * HH_CHUNK;
+    double2 y[HH_PER_SLOT], a[HH_PER_SLOT];
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s) {
+        const int64_t p = CHUNK_P(s);
+        if (p < h.N) {
+            int i, j, k;
+            split(p, h.nx, h.ny, h.fx, h.fxy, i, j, k);
+            y[s] = stencil<DIM, double>(h, ph, i, j, k, p);
+            a[s] = ldg(rh, p);
+        }
     }
-    const SP *sh = (const SP *)pd.vec[VS_SH];
-    double2 *r = (double2 *)pd.vec[VS_R];
-    const double2 *t = (const double2 *)pd.vec[VS_T], *rh = (const double2 *)pd.vec[VS_RH];
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s) {
+        const int64_t p = CHUNK_P(s);
+        if (p < h.N) {
+            stg(v, p, y[s]);
+            acc[0] = acc[0] + (a[s].x * y[s].x + a[s].y * y[s].y);
+            acc[1] = acc[1] + (a[s].x * y[s].y - a[s].y * y[s].x);
+        }
+    }
+    chunk_finish<2>(pd, tl.idx, acc, FIN_ALPHA);
+}
+
+// s = r - alpha v (in r) ; partial ||s||^2 ; finalise the half-step check
+__global__ __launch_bounds__(HH_WG) void k_bicg_s(Ctx cx)
+{
+    const Tile tl = tile_of(cx);
+    const Ctrl ct = ctrl_of(cx, tl.prob);
+    if (ct.phase != PH_RUN) return;
+    const ProbDev *pd = cx.P + tl.prob;
+    const double2 alpha = ct.alpha;
+    double2 *__restrict__ r = (double2 *)pd->vec[VS_R];
+    const double2 *__restrict__ v = (const double2 *)pd->vec[VS_V];
+    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_CHUNK;
+    double2 rr[HH_PER_SLOT], vr[HH_PER_SLOT];
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s)
+        if (CHUNK_P(s) < N) {
+            rr[s] = ldg(r, CHUNK_P(s));
+            vr[s] = ldg(v, CHUNK_P(s));
+        }
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s)
+        if (CHUNK_P(s) < N) {
+            double2 sv = csub<double>(rr[s], cmul<double>(alpha, vr[s]));
+            stg(r, CHUNK_P(s), sv);
+            acc[0] = acc[0] + (sv.x * sv.x + sv.y * sv.y);
+        }
+    chunk_finish<1>(pd, tl.idx, acc, FIN_S);
+}
+
+// t = H shat ; partials (t, s), (t, t) ; finalise omega
+template <int DIM, typename SP>
+__global__ __launch_bounds__(HH_WG) void k_bicg_t(Ctx cx)
+{
+    const Tile tl = tile_of(cx);
+    if (phase_of(cx, tl.prob) != PH_RUN) return;
+    const ProbDev *pd = cx.P + tl.prob;
+    const HView h = hview(pd);
+    const SP *__restrict__ sh = (const SP *)pd->vec[VS_SH];
+    double2 *__restrict__ t = (double2 *)pd->vec[VS_T];
+    const double2 *__restrict__ sv = (const double2 *)pd->vec[VS_R];
+    const int64_t base = (int64_t)tl.idx * HH_CHUNK;
+    double2 y[HH_PER_SLOT], b[HH_PER_SLOT];
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s) {
+        const int64_t p = CHUNK_P(s);
+        if (p < h.N) {
+            int i, j, k;
+            split(p, h.nx, h.ny, h.fx, h.fxy, i, j, k);
+            y[s] = stencil<DIM, double>(h, sh, i, j, k, p);
+            b[s] = ldg(sv, p);
+        }
+    }
     double acc[3] = {0.0, 0.0, 0.0};
-    CHUNK_LOOP({
-        x[p] = cadd<double>(cadd<double>(x[p], cmul<double>(alpha, ld64(ph, p))), cmul<double>(omega, ld64(sh, p)));
-        double2 rn = csub<double>(r[p], cmul<double>(omega, t[p]));
-        r[p] = rn;
-        double2 a = rh[p];
-        acc[0] = acc[0] + (a.x * rn.x + a.y * rn.y);
-        acc[1] = acc[1] + (a.x * rn.y - a.y * rn.x);
-        acc[2] = acc[2] + (rn.x * rn.x + rn.y * rn.y);
-    })
-    block_reduce<3>(acc, pd.part + (int64_t)tl.idx * HH_NPART);
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s) {
+        const int64_t p = CHUNK_P(s);
+        if (p < h.N) {
+            stg(t, p, y[s]);
+            acc[0] = acc[0] + (y[s].x * b[s].x + y[s].y * b[s].y);
+            acc[1] = acc[1] + (y[s].x * b[s].y - y[s].y * b[s].x);
+            acc[2] = acc[2] + (y[s].x * y[s].x + y[s].y * y[s].y);
+        }
+    }
+    chunk_finish<3>(pd, tl.idx, acc, FIN_OMEGA);
+}
+
+// x = x + alpha phat + omega shat ; r = s - omega t ; partials (rhat, r),
+// ||r||^2 ; finalise rho/beta (half-step exit: x = x + alpha phat only)
+template <typename SP>
+__global__ __launch_bounds__(HH_WG) void k_bicg_xr(Ctx cx)
+{
+    const Tile tl = tile_of(cx);
+    const Ctrl ct = ctrl_of(cx, tl.prob);
+    const int phase = ct.phase;
+    if (phase != PH_RUN && phase != PH_HALF) return;
+    const ProbDev *pd = cx.P + tl.prob;
+    const double2 alpha = ct.alpha, omega = ct.omega;
+    double2 *__restrict__ x = (double2 *)pd->vec[VS_X];
+    const SP *__restrict__ ph = (const SP *)pd->vec[VS_PH];
+    const SP *__restrict__ sh = (const SP *)pd->vec[VS_SH];
+    double2 *__restrict__ r = (double2 *)pd->vec[VS_R];
+    const double2 *__restrict__ t = (const double2 *)pd->vec[VS_T];
+    const double2 *__restrict__ rh = (const double2 *)pd->vec[VS_RH];
+    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_CHUNK;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (phase == PH_HALF) {
+        double2 xr[HH_PER_SLOT], pr[HH_PER_SLOT];
+#pragma unroll
+        for (int s = 0; s < HH_PER_SLOT; ++s)
+            if (CHUNK_P(s) < N) {
+                xr[s] = ldg(x, CHUNK_P(s));
+                pr[s] = ccvt<double>(ldg(ph, CHUNK_P(s)));
+            }
+#pragma unroll
+        for (int s = 0; s < HH_PER_SLOT; ++s)
+            if (CHUNK_P(s) < N) stg(x, CHUNK_P(s), cadd<double>(xr[s], cmul<double>(alpha, pr[s])));
+    } else {
+        double2 xr[HH_PER_SLOT], pr[HH_PER_SLOT], sr[HH_PER_SLOT], rr[HH_PER_SLOT], tr[HH_PER_SLOT], hr[HH_PER_SLOT];
+#pragma unroll
+        for (int s = 0; s < HH_PER_SLOT; ++s)
+            if (CHUNK_P(s) < N) {
+                const int64_t p = CHUNK_P(s);
+                xr[s] = ldg(x, p);
+                pr[s] = ccvt<double>(ldg(ph, p));
+                sr[s] = ccvt<double>(ldg(sh, p));
+                rr[s] = ldg(r, p);
+                tr[s] = ldg(t, p);
+                hr[s] = ldg(rh, p);
+            }
+#pragma unroll
+        for (int s = 0; s < HH_PER_SLOT; ++s)
+            if (CHUNK_P(s) < N) {
+                const int64_t p = CHUNK_P(s);
+                stg(x, p, cadd<double>(cadd<double>(xr[s], cmul<double>(alpha, pr[s])), cmul<double>(omega, sr[s])));
+                double2 rn = csub<double>(rr[s], cmul<double>(omega, tr[s]));
+                stg(r, p, rn);
+                acc[0] = acc[0] + (hr[s].x * rn.x + hr[s].y * rn.y);
+                acc[1] = acc[1] + (hr[s].x * rn.y - hr[s].y * rn.x);
+                acc[2] = acc[2] + (rn.x * rn.x + rn.y * rn.y);
+            }
+    }
+    chunk_finish<3>(pd, tl.idx, acc, FIN_RHO);
 }
 
 // out = b - H x.  mode 0 (Bi-CGSTAB start): out = r, also rhat = r, p = v = 0,
-// partials (rhat, r) and ||r||^2.  mode 1 (true residual): out = tmp,
-// partial ||.||^2 in slot 2.  mode 2 (IDR start): out = r, partial ||r||^2.
+// partials (rhat, r) and ||r||^2, finalise INIT.  mode 1 (true residual):
+// out = tmp, partial ||.||^2 in slot 2, finalise TRUE.  mode 2 (IDR start):
+// out = r, partial ||r||^2, finalise IDR_INIT.
 template <int DIM>
-__global__ __launch_bounds__(HH_WG) void k_resid(const ProbDev *P, const Tile *tiles, int mode)
+__global__ __launch_bounds__(HH_WG) void k_resid(Ctx cx, int mode)
 {
-    const Tile tl = tiles[blockIdx.x];
-    const ProbDev &pd = P[tl.prob];
-    const double2 *x = (const double2 *)pd.vec[VS_X], *b = (const double2 *)pd.vec[VS_B];
-    double2 *out = (double2 *)pd.vec[mode == 1 ? VS_TMP : VS_R];
-    double2 *rh = (double2 *)pd.vec[VS_RH], *pv = (double2 *)pd.vec[VS_P], *v = (double2 *)pd.vec[VS_V];
-    double acc[3] = {0.0, 0.0, 0.0};
-    CHUNK_LOOP({
-        int i, j, k;
-        coords(pd, p, i, j, k);
-        double2 hx = applyH_at<DIM>(pd, x, i, j, k, p);
-        double2 r = csub<double>(b[p], hx);
-        out[p] = r;
-        if (mode == 0) {
-            rh[p] = r;
-            pv[p] = cmk<double>(0.0, 0.0);
-            v[p] = cmk<double>(0.0, 0.0);
-            acc[0] = acc[0] + (r.x * r.x + r.y * r.y);
-            acc[1] = acc[1] + (r.x * r.y - r.y * r.x);
+    const Tile tl = tile_of(cx);
+    const ProbDev *pd = cx.P + tl.prob;
+    const HView h = hview(pd);
+    const double2 *__restrict__ x = (const double2 *)pd->vec[VS_X];
+    const double2 *__restrict__ b = (const double2 *)pd->vec[VS_B];
+    double2 *__restrict__ out = (double2 *)pd->vec[mode == 1 ? VS_TMP : VS_R];
+    double2 *__restrict__ rh = (double2 *)pd->vec[VS_RH];
+    double2 *__restrict__ pv = (double2 *)pd->vec[VS_P];
+    double2 *__restrict__ v = (double2 *)pd->vec[VS_V];
+    const int64_t base = (int64_t)tl.idx * HH_CHUNK;
+    double2 rr[HH_PER_SLOT];
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s) {
+        const int64_t p = CHUNK_P(s);
+        if (p < h.N) {
+            int i, j, k;
+            split(p, h.nx, h.ny, h.fx, h.fxy, i, j, k);
+            double2 hx = stencil<DIM, double>(h, x, i, j, k, p);
+            rr[s] = csub<double>(ldg(b, p), hx);
         }
-        acc[2] = acc[2] + (r.x * r.x + r.y * r.y);
-    })
-    block_reduce<3>(acc, pd.part + (int64_t)tl.idx * HH_NPART);
+    }
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s) {
+        const int64_t p = CHUNK_P(s);
+        if (p < h.N) {
+            const double2 rv = rr[s];
+            stg(out, p, rv);
+            if (mode == 0) {
+                stg(rh, p, rv);
+                stg(pv, p, cmk<double>(0.0, 0.0));
+                stg(v, p, cmk<double>(0.0, 0.0));
+                acc[0] = acc[0] + (rv.x * rv.x + rv.y * rv.y);
+                acc[1] = acc[1] + (rv.x * rv.y - rv.y * rv.x);
+            }
+            acc[2] = acc[2] + (rv.x * rv.x + rv.y * rv.y);
+        }
+    }
+    chunk_finish<3>(pd, tl.idx, acc, mode == 0 ? FIN_INIT : (mode == 1 ? FIN_TRUE : FIN_IDR_INIT));
 }
 
-// partial ||vec||^2 (slot 2) ; used for ||b||
-__global__ __launch_bounds__(HH_WG) void k_norm(const ProbDev *P, const Tile *tiles, int sel)
+// partial ||vec||^2 (slot 2) ; finalise ||b||
+__global__ __launch_bounds__(HH_WG) void k_norm(Ctx cx, int sel)
 {
-    const Tile tl = tiles[blockIdx.x];
-    const ProbDev &pd = P[tl.prob];
-    const double2 *x = (const double2 *)pd.vec[sel];
+    const Tile tl = tile_of(cx);
+    const ProbDev *pd = cx.P + tl.prob;
+    const double2 *__restrict__ x = (const double2 *)pd->vec[sel];
+    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_CHUNK;
+    double2 xr[HH_PER_SLOT];
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s)
+        if (CHUNK_P(s) < N) xr[s] = ldg(x, CHUNK_P(s));
     double acc[3] = {0.0, 0.0, 0.0};
-    CHUNK_LOOP({
-        double2 a = x[p];
-        acc[2] = acc[2] + (a.x * a.x + a.y * a.y);
-    })
-    block_reduce<3>(acc, pd.part + (int64_t)tl.idx * HH_NPART);
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s)
+        if (CHUNK_P(s) < N) acc[2] = acc[2] + (xr[s].x * xr[s].x + xr[s].y * xr[s].y);
+    chunk_finish<3>(pd, tl.idx, acc, FIN_BNORM);
 }
 
 // set a complex double vector to zero
-__global__ __launch_bounds__(HH_WG) void k_zero(const ProbDev *P, const Tile *tiles, int sel)
+__global__ __launch_bounds__(HH_WG) void k_zero(Ctx cx, int sel)
 {
-    const Tile tl = tiles[blockIdx.x];
-    const ProbDev &pd = P[tl.prob];
-    double2 *x = (double2 *)pd.vec[sel];
-    CHUNK_LOOP(x[p] = cmk<double>(0.0, 0.0);)
-}
-
-// ---------------------------------------------------------------------------
-// finalisation: one workgroup per problem reduces the chunk partials and
-// advances the scalar state.
-// ---------------------------------------------------------------------------
-enum FinKind { FIN_BNORM = 0, FIN_INIT, FIN_ALPHA, FIN_S, FIN_OMEGA, FIN_RHO, FIN_TRUE };
-
-__device__ inline bool fin_ok(double v) { return isfinite(v); }
-__device__ inline bool cfin(double2 v) { return isfinite(v.x) && isfinite(v.y); }
-
-__device__ inline void stop(SolveState *st, int reason)
-{
-    st->phase = PH_STOP;
-    st->reason = reason;
-}
-
-__device__ inline void record(const ProbDev &pd, SolveState *st, double rel)
-{
-    st->rel = rel;
-    if (pd.hist && st->mv - 1 < st->hist_len && st->mv >= 1) pd.hist[st->mv - 1] = rel;
-}
-
-__global__ __launch_bounds__(HH_WG) void k_fin(const ProbDev *P, const int *probs, int kind)
-{
-    const ProbDev &pd = P[probs[blockIdx.x]];
-    SolveState *st = pd.st;
-    const int phase = st->phase;
-    if (kind == FIN_RHO) {
-        if (phase != PH_RUN && phase != PH_HALF) return;
-    } else if (kind != FIN_BNORM && kind != FIN_INIT && kind != FIN_TRUE) {
-        if (phase != PH_RUN) return;
-    }
-    __syncthreads();
-    double s[3] = {0.0, 0.0, 0.0};
-    const int nv = (kind == FIN_S || kind == FIN_BNORM || kind == FIN_TRUE) ? 1 : (kind == FIN_ALPHA ? 2 : 3);
-    const int first = (kind == FIN_S) ? 0 : ((kind == FIN_BNORM || kind == FIN_TRUE) ? 2 : 0);
-    for (int q = 0; q < nv; ++q) s[q] = pairwise_wg(pd.part + first + q, HH_NPART, pd.nchunk);
-    if (threadIdx.x != 0) return;
-    switch (kind) {
-    case FIN_BNORM:
-        st->bnorm = sqrt(s[0]);
-        break;
-    case FIN_TRUE:
-        st->true_rel = sqrt(s[0]) / st->bnorm;
-        break;
-    case FIN_INIT: {
-        // start (or restart) of Bi-CGSTAB: rho = alpha = omega = 1, then the
-        // first beta from rho1 = (rhat, r)
-        const double2 one = cmk<double>(1.0, 0.0);
-        st->rho = one;
-        st->alpha = one;
-        st->omega = one;
-        st->phase = PH_RUN;
-        st->reason = RS_NONE;
-        double2 rho1 = cmk<double>(s[0], s[1]);
-        if (!cfin(rho1)) { stop(st, RS_NONFIN); break; }
-        if (rho1.x == 0.0 && rho1.y == 0.0) { stop(st, RS_BREAK); break; }
-        st->beta = cmul<double>(cdiv<double>(rho1, st->rho), cdiv<double>(st->alpha, st->omega));
-        st->rho = rho1;
-        break;
-    }
-    case FIN_ALPHA: {
-        st->mv += 1;
-        double2 rv = cmk<double>(s[0], s[1]);
-        if (!cfin(rv)) { stop(st, RS_NONFIN); break; }
-        if (rv.x == 0.0 && rv.y == 0.0) { stop(st, RS_BREAK); break; }
-        st->alpha = cdiv<double>(st->rho, rv);
-        break;
-    }
-    case FIN_S: {
-        double rel = sqrt(s[0]) / st->bnorm;
-        record(pd, st, rel);
-        if (!fin_ok(rel)) { stop(st, RS_NONFIN); break; }
-        if (rel < st->tol) { st->phase = PH_HALF; st->reason = RS_CONV; break; }
-        if (st->mv >= st->max_mv) { st->phase = PH_HALF; st->reason = RS_MAXMV; break; }
-        break;
-    }
-    case FIN_OMEGA: {
-        st->mv += 1;
-        double2 ts = cmk<double>(s[0], s[1]);
-        double tt = s[2];
-        if (!cfin(ts) || !fin_ok(tt)) { stop(st, RS_NONFIN); break; }
-        if (tt == 0.0) { stop(st, RS_BREAK); break; }
-        st->omega = cmk<double>(ts.x / tt, ts.y / tt);
-        break;
-    }
-    case FIN_RHO: {
-        st->it += 1;
-        if (phase == PH_HALF) { st->phase = PH_STOP; break; }
-        double rel = sqrt(s[2]) / st->bnorm;
-        record(pd, st, rel);
-        if (!fin_ok(rel)) { stop(st, RS_NONFIN); break; }
-        if (rel < st->tol) { stop(st, RS_CONV); break; }
-        if (st->omega.x == 0.0 && st->omega.y == 0.0) { stop(st, RS_BREAK); break; }
-        if (st->mv >= st->max_mv) { stop(st, RS_MAXMV); break; }
-        double2 rho1 = cmk<double>(s[0], s[1]);
-        if (!cfin(rho1)) { stop(st, RS_NONFIN); break; }
-        if (rho1.x == 0.0 && rho1.y == 0.0) { stop(st, RS_BREAK); break; }
-        st->beta = cmul<double>(cdiv<double>(rho1, st->rho), cdiv<double>(st->alpha, st->omega));
-        st->rho = rho1;
-        break;
-    }
-    }
+    const Tile tl = tile_of(cx);
+    const ProbDev *pd = cx.P + tl.prob;
+    double2 *__restrict__ x = (double2 *)pd->vec[sel];
+    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_CHUNK;
+#pragma unroll
+    for (int s = 0; s < HH_PER_SLOT; ++s)
+        if (CHUNK_P(s) < N) stg(x, CHUNK_P(s), cmk<double>(0.0, 0.0));
 }
 
 } // namespace hh

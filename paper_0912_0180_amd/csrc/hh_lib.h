@@ -19,11 +19,16 @@ struct DevList {
 struct Plan {
     int count = 0, dim = 2, Lmax = 0;
     bool fp32 = false;
-    DevList chunks, coarse, down[HH_MAXLEV], up[HH_MAXLEV];
+    DevList chunks, down[HH_MAXLEV], up[HH_MAXLEV];   // down/up: levels above the tail
     int *fin = nullptr;
     int nfin = 0;
     ProbDev *probs = nullptr;
+    Ctrl *ctrl = nullptr;            // per-problem control blocks (device)
+    const void *L1 = nullptr;        // one-problem plans: LevelDev array of the V-cycle precision
+    double omega1 = 0.8;
+    std::vector<ProbDev> host;       // host copies of the descriptors of the current solve
     void *mem = nullptr;
+    size_t bytes = 0;
 };
 
 // Solve work space of one grid.
@@ -54,6 +59,8 @@ struct hh_grid {
     LevelDev<float> *L32 = nullptr;
     double2 *Minv64 = nullptr;
     float2 *Minv32 = nullptr;
+    void *timg64 = nullptr, *timg32 = nullptr;
+    size_t timg_bytes64 = 0, timg_bytes32 = 0;
     ProbDev pd_static{};
     ProbDev *pd_static_dev = nullptr;
     Tile *chunks_dev = nullptr;
@@ -62,7 +69,7 @@ struct hh_grid {
     Plan plan;               // single-problem solve plan
     int plan_fp32 = -1;
     Workspace ws;
-    size_t plan_bytes() const { return 0; }
+    size_t plan_bytes() const { return plan.bytes + vplan64.bytes + vplan32.bytes; }
 };
 
 hh_status hh_fail(hh_status st, const char *fmt, ...);
@@ -72,9 +79,11 @@ void workspace_release(Workspace &w);
 void plan_release(Plan &p);
 hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32);
 
-void launch_vcycle(const Plan &pl, const ProbDev *P, int fsel, int osel, const void *fptr, void *optr, hipStream_t s);
+void launch_vcycle(const Plan &pl, int fsel, int osel, const void *fptr, void *optr, hipStream_t s);
 void launch_bicg_iteration(const Plan &pl, hipStream_t s);
 void launch_resid(const Plan &pl, const DevList &tiles, int mode, hipStream_t s);
 void launch_norm(const Plan &pl, const DevList &tiles, int sel, hipStream_t s);
 void launch_zero(const Plan &pl, const DevList &tiles, int sel, hipStream_t s);
+int tail_level(const HostSetup &hs, bool fp32);
+std::vector<char> tail_image(const HostSetup &hs, bool fp32);
 void launch_fin(const Plan &pl, const int *probs, int n, int kind, hipStream_t s);

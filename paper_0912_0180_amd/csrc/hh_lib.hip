@@ -13,6 +13,7 @@
 
 #include "hh_common.h"
 #include "hh_kernels.hpp"
+#include "hh_idr_kernels.hpp"
 #include "hh_lib.h"
 #include "hh_setup.h"
 
@@ -107,6 +108,12 @@ hh_status grid_upload(hh_grid *g)
         }
         g->Minv64 = c.take<double2>((size_t)hs.Nc * hs.Nc);
         g->Minv32 = c.take<float2>((size_t)hs.Nc * hs.Nc);
+        if (pass == 0) {
+            g->timg_bytes64 = tail_image(hs, false).size();
+            g->timg_bytes32 = tail_image(hs, true).size();
+        }
+        g->timg64 = c.take<char>(g->timg_bytes64);
+        g->timg32 = c.take<char>(g->timg_bytes32);
         g->L64 = c.take<LevelDev<double>>(HH_MAXLEV);
         g->L32 = c.take<LevelDev<float>>(HH_MAXLEV);
         g->pd_static_dev = c.take<ProbDev>(1);
@@ -144,6 +151,11 @@ hh_status grid_upload(hh_grid *g)
         HIPCHK(put64(g->L32h[l].phi, p32.data(), sizeof(float) * L.N));
     }
     HIPCHK(put64(g->Minv64, hs.Minv.data(), sizeof(double2) * hs.Minv.size()));
+    {
+        std::vector<char> i64 = tail_image(hs, false), i32 = tail_image(hs, true);
+        HIPCHK(put64(g->timg64, i64.data(), i64.size()));
+        HIPCHK(put64(g->timg32, i32.data(), i32.size()));
+    }
     HIPCHK(put32c(g->Minv32, hs.Minv));
     HIPCHK(put64(g->L64, g->L64h, sizeof(LevelDev<double>) * HH_MAXLEV));
     HIPCHK(put64(g->L32, g->L32h, sizeof(LevelDev<float>) * HH_MAXLEV));
@@ -181,6 +193,12 @@ void grid_fill_prob(const hh_grid *g, ProbDev &pd)
     pd.Minv64 = g->Minv64;
     pd.Minv32 = g->Minv32;
     pd.omega = hs.omega;
+    pd.tail64 = tail_level(hs, false);
+    pd.tail32 = tail_level(hs, true);
+    pd.timg64 = g->timg64;
+    pd.timg32 = g->timg32;
+    pd.timg_bytes64 = (int)g->timg_bytes64;
+    pd.timg_bytes32 = (int)g->timg_bytes32;
 }
 
 static void grid_release(hh_grid *g)
@@ -211,6 +229,86 @@ void plan_release(Plan &p)
     p = Plan();
 }
 
+// LDS bytes the tail kernel carves for levels t..nlev-1 (same order and
+// 16-byte rounding as k_vtail).
+static size_t tail_bytes(const HostSetup &hs, int t, bool fp32)
+{
+    const size_t cb = fp32 ? sizeof(float2) : sizeof(double2), rb = fp32 ? sizeof(float) : sizeof(double);
+    auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    size_t off = 0;
+    int64_t nmax = 0;
+    for (int l = t; l < hs.nlev; ++l) {
+        const HostLevel &L = hs.lev[l];
+        nmax = std::max(nmax, L.N);
+        off += r16(cb * L.N) + r16(cb * L.N) + r16(rb * L.N);
+        for (int a = 0; a < 3; ++a) {
+            const int na = a < hs.dim ? L.n[a] : 1;
+            off += 3 * r16(cb * na);
+        }
+    }
+    off += r16(cb * nmax);
+    return off;
+}
+
+// First level of the one-workgroup tail: the finest level >= 1 whose level
+// and every coarser one fit the tail's LDS budget.
+int tail_level(const HostSetup &hs, bool fp32)
+{
+    const int cap = fp32 ? TailCap<float>::N : TailCap<double>::N;
+    const size_t bytes = fp32 ? TailCap<float>::BYTES : TailCap<double>::BYTES;
+    for (int t = 1; t < hs.nlev; ++t)
+        if (hs.lev[t].N <= cap && tail_bytes(hs, t, fp32) <= bytes) return t;
+    return hs.nlev - 1;
+}
+
+// Byte image of the tail's LDS block (same layout as tail_bytes / k_vtail):
+// per level f and e (zero), phi, and the coefficient arrays a, c, d per axis;
+// then the scratch U (zero).  Values in the V-cycle precision.
+std::vector<char> tail_image(const HostSetup &hs, bool fp32)
+{
+    const int t = tail_level(hs, fp32);
+    std::vector<char> img(tail_bytes(hs, t, fp32), 0);
+    const size_t cb = fp32 ? sizeof(float2) : sizeof(double2), rb = fp32 ? sizeof(float) : sizeof(double);
+    auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    size_t off = 0;
+    auto put_c = [&](const std::vector<double2> &v, size_t n) {
+        for (size_t i = 0; i < n; ++i) {
+            if (fp32) {
+                float2 z;
+                z.x = (float)v[i].x;
+                z.y = (float)v[i].y;
+                memcpy(&img[off + i * cb], &z, cb);
+            } else {
+                memcpy(&img[off + i * cb], &v[i], cb);
+            }
+        }
+        off += r16(cb * n);
+    };
+    for (int l = t; l < hs.nlev; ++l) {
+        const HostLevel &L = hs.lev[l];
+        off += r16(cb * L.N) + r16(cb * L.N);
+        for (int64_t i = 0; i < L.N; ++i) {
+            if (fp32) {
+                float v = (float)L.phi[i];
+                memcpy(&img[off + i * rb], &v, rb);
+            } else {
+                memcpy(&img[off + i * rb], &L.phi[i], rb);
+            }
+        }
+        off += r16(rb * L.N);
+        for (int a = 0; a < 3; ++a) {
+            if (a < hs.dim) {
+                put_c(L.aM[a], L.n[a]);
+                put_c(L.cM[a], L.n[a]);
+                put_c(L.dM[a], L.n[a]);
+            } else {
+                off += 3 * r16(cb);
+            }
+        }
+    }
+    return img;
+}
+
 hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
 {
     plan_release(pl);
@@ -218,15 +316,15 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
     pl.dim = G.empty() ? 2 : G[0]->hs.dim;
     pl.fp32 = fp32;
     pl.Lmax = 0;
-    for (auto *g : G) pl.Lmax = std::max(pl.Lmax, g->hs.nlev);
-    std::vector<Tile> chunks, coarse, down[HH_MAXLEV], up[HH_MAXLEV];
+    std::vector<Tile> chunks, down[HH_MAXLEV], up[HH_MAXLEV];
     std::vector<int> fin;
     for (int q = 0; q < pl.count; ++q) {
         const HostSetup &hs = G[q]->hs;
+        const int t = tail_level(hs, fp32);
+        pl.Lmax = std::max(pl.Lmax, t);
         int nch = ceil_div(hs.lev[0].N, HH_CHUNK);
         for (int i = 0; i < nch; ++i) chunks.push_back(Tile{q, i});
-        for (int i = 0; i < ceil_div(hs.Nc, 4); ++i) coarse.push_back(Tile{q, i});
-        for (int l = 0; l + 1 < hs.nlev; ++l) {
+        for (int l = 0; l < t; ++l) {
             int nd, nu;
             vtile_counts(hs.dim, fp32, hs.lev[l], hs.lev[l + 1], nd, nu);
             for (int i = 0; i < nd; ++i) down[l].push_back(Tile{q, i});
@@ -234,11 +332,12 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         }
         fin.push_back(q);
     }
-    size_t bytes = align256(sizeof(Tile) * chunks.size()) + align256(sizeof(Tile) * coarse.size()) +
-                   align256(sizeof(int) * fin.size()) + align256(sizeof(ProbDev) * pl.count);
+    size_t bytes = align256(sizeof(Tile) * chunks.size()) + align256(sizeof(int) * fin.size()) +
+                   align256(sizeof(ProbDev) * pl.count) + align256(sizeof(Ctrl) * pl.count);
     for (int l = 0; l < HH_MAXLEV; ++l) bytes += align256(sizeof(Tile) * down[l].size()) + align256(sizeof(Tile) * up[l].size());
     hipError_t e = hipMalloc(&pl.mem, bytes);
     if (e != hipSuccess) return hh_fail(HH_ERR_OOM, "hipMalloc(%zu) for a launch plan: %s", bytes, hipGetErrorString(e));
+    pl.bytes = bytes;
     Carver c;
     c.base = (char *)pl.mem;
     auto up_list = [&](std::vector<Tile> &v, DevList &d) -> hipError_t {
@@ -247,7 +346,6 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         return v.empty() ? hipSuccess : hipMemcpy(d.t, v.data(), sizeof(Tile) * v.size(), hipMemcpyHostToDevice);
     };
     HIPCHK(up_list(chunks, pl.chunks));
-    HIPCHK(up_list(coarse, pl.coarse));
     for (int l = 0; l < HH_MAXLEV; ++l) {
         HIPCHK(up_list(down[l], pl.down[l]));
         HIPCHK(up_list(up[l], pl.up[l]));
@@ -256,6 +354,11 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
     pl.nfin = (int)fin.size();
     HIPCHK(hipMemcpy(pl.fin, fin.data(), sizeof(int) * fin.size(), hipMemcpyHostToDevice));
     pl.probs = c.take<ProbDev>(pl.count);
+    pl.ctrl = c.take<Ctrl>(pl.count);
+    if (pl.count == 1) {
+        pl.L1 = fp32 ? (const void *)G[0]->L32 : (const void *)G[0]->L64;
+        pl.omega1 = G[0]->hs.omega;
+    }
     return HH_OK;
 }
 
@@ -267,48 +370,78 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         if ((n) > 0) hipLaunchKernelGGL(kernel, dim3(n), dim3(HH_WG), 0, stream, __VA_ARGS__); \
     } while (0)
 
+// launch context of a pass over `tiles` (a one-problem plan needs no tile
+// list: the workgroup index is the tile index)
+static Ctx ctx_of(const Plan &pl, const DevList &tiles)
+{
+    Ctx c;
+    c.P = pl.probs;
+    c.tiles = pl.count == 1 ? nullptr : tiles.t;
+    c.ctrl = pl.ctrl;
+    c.L = pl.count == 1 ? pl.L1 : nullptr;
+    c.omega = pl.omega1;
+    return c;
+}
+
 template <int DIM, typename T>
-static void vcycle_t(const Plan &pl, const ProbDev *P, int fsel, int osel, const void *fptr, void *optr, hipStream_t s)
+static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void *optr, hipStream_t s)
 {
     using C = V2<T>;
     using TO = V2<T>;  // level-0 output in the V-cycle precision
-    for (int l = 0; l + 1 < pl.Lmax; ++l) {
-        if (l == 0) LAUNCH((k_vdown<DIM, T, double2>), pl.down[l].n, s, P, pl.down[l].t, l, fsel, fptr);
-        else LAUNCH((k_vdown<DIM, T, C>), pl.down[l].n, s, P, pl.down[l].t, l, fsel, fptr);
+    if (pl.count == 1 && !fptr) {
+        fptr = pl.host.at(0).vec[fsel];
+        optr = pl.host.at(0).vec[osel];
     }
-    LAUNCH((k_coarse<T>), pl.coarse.n, s, P, pl.coarse.t);
-    for (int l = pl.Lmax - 2; l >= 0; --l) {
-        if (l == 0) LAUNCH((k_vup<DIM, T, double2, TO>), pl.up[l].n, s, P, pl.up[l].t, l, fsel, osel, fptr, optr);
-        else LAUNCH((k_vup<DIM, T, C, C>), pl.up[l].n, s, P, pl.up[l].t, l, fsel, osel, fptr, optr);
+    for (int l = 0; l < pl.Lmax; ++l) {
+        const Ctx c = ctx_of(pl, pl.down[l]);
+        if (l == 0) LAUNCH((k_vdown<DIM, T, double2>), pl.down[l].n, s, c, l, fsel, fptr);
+        else LAUNCH((k_vdown<DIM, T, C>), pl.down[l].n, s, c, l, fsel, fptr);
+    }
+    {
+        Ctx c = ctx_of(pl, pl.chunks);
+        if (pl.nfin > 0) hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(HH_TAIL_WG), 0, s, c,
+                                            pl.count == 1 ? nullptr : pl.fin);
+    }
+    for (int l = pl.Lmax - 1; l >= 0; --l) {
+        const Ctx c = ctx_of(pl, pl.up[l]);
+        if (l == 0) LAUNCH((k_vup<DIM, T, double2, TO>), pl.up[l].n, s, c, l, fsel, osel, fptr, optr);
+        else LAUNCH((k_vup<DIM, T, C, C>), pl.up[l].n, s, c, l, fsel, osel, fptr, optr);
     }
 }
 
-void launch_vcycle(const Plan &pl, const ProbDev *P, int fsel, int osel, const void *fptr, void *optr, hipStream_t s)
+void launch_vcycle(const Plan &pl, int fsel, int osel, const void *fptr, void *optr, hipStream_t s)
 {
     if (pl.dim == 2) {
-        if (pl.fp32) vcycle_t<2, float>(pl, P, fsel, osel, fptr, optr, s);
-        else vcycle_t<2, double>(pl, P, fsel, osel, fptr, optr, s);
+        if (pl.fp32) vcycle_t<2, float>(pl, fsel, osel, fptr, optr, s);
+        else vcycle_t<2, double>(pl, fsel, osel, fptr, optr, s);
     } else {
-        if (pl.fp32) vcycle_t<3, float>(pl, P, fsel, osel, fptr, optr, s);
-        else vcycle_t<3, double>(pl, P, fsel, osel, fptr, optr, s);
+        if (pl.fp32) vcycle_t<3, float>(pl, fsel, osel, fptr, optr, s);
+        else vcycle_t<3, double>(pl, fsel, osel, fptr, optr, s);
     }
+}
+
+void launch_fin(const Plan &pl, const int *probs, int n, int kind, hipStream_t s)
+{
+    const Ctx c = ctx_of(pl, pl.chunks);
+    LAUNCH(k_fin, n, s, c, pl.count == 1 ? nullptr : probs, kind);
 }
 
 template <int DIM, typename SP>
 static void bicg_iter_t(const Plan &pl, hipStream_t s)
 {
-    const ProbDev *P = pl.probs;
-    LAUNCH(k_bicg_p, pl.chunks.n, s, P, pl.chunks.t);
-    launch_vcycle(pl, P, VS_P, VS_PH, nullptr, nullptr, s);
-    LAUNCH((k_bicg_v<DIM, SP>), pl.chunks.n, s, P, pl.chunks.t);
-    LAUNCH(k_fin, pl.nfin, s, P, pl.fin, (int)FIN_ALPHA);
-    LAUNCH(k_bicg_s, pl.chunks.n, s, P, pl.chunks.t);
-    LAUNCH(k_fin, pl.nfin, s, P, pl.fin, (int)FIN_S);
-    launch_vcycle(pl, P, VS_R, VS_SH, nullptr, nullptr, s);
-    LAUNCH((k_bicg_t<DIM, SP>), pl.chunks.n, s, P, pl.chunks.t);
-    LAUNCH(k_fin, pl.nfin, s, P, pl.fin, (int)FIN_OMEGA);
-    LAUNCH((k_bicg_xr<SP>), pl.chunks.n, s, P, pl.chunks.t);
-    LAUNCH(k_fin, pl.nfin, s, P, pl.fin, (int)FIN_RHO);
+    const Ctx c = ctx_of(pl, pl.chunks);
+    const int n = pl.chunks.n;
+    LAUNCH(k_bicg_p, n, s, c);
+    launch_vcycle(pl, VS_P, VS_PH, nullptr, nullptr, s);
+    LAUNCH((k_bicg_v<DIM, SP>), n, s, c);
+    launch_fin(pl, pl.fin, pl.nfin, FIN_ALPHA, s);
+    LAUNCH(k_bicg_s, n, s, c);
+    launch_fin(pl, pl.fin, pl.nfin, FIN_S, s);
+    launch_vcycle(pl, VS_R, VS_SH, nullptr, nullptr, s);
+    LAUNCH((k_bicg_t<DIM, SP>), n, s, c);
+    launch_fin(pl, pl.fin, pl.nfin, FIN_OMEGA, s);
+    LAUNCH((k_bicg_xr<SP>), n, s, c);
+    launch_fin(pl, pl.fin, pl.nfin, FIN_RHO, s);
 }
 
 void launch_bicg_iteration(const Plan &pl, hipStream_t s)
@@ -324,23 +457,19 @@ void launch_bicg_iteration(const Plan &pl, hipStream_t s)
 
 void launch_resid(const Plan &pl, const DevList &tiles, int mode, hipStream_t s)
 {
-    if (pl.dim == 2) LAUNCH(k_resid<2>, tiles.n, s, pl.probs, tiles.t, mode);
-    else LAUNCH(k_resid<3>, tiles.n, s, pl.probs, tiles.t, mode);
+    const Ctx c = ctx_of(pl, tiles);
+    if (pl.dim == 2) LAUNCH(k_resid<2>, tiles.n, s, c, mode);
+    else LAUNCH(k_resid<3>, tiles.n, s, c, mode);
 }
 
 void launch_norm(const Plan &pl, const DevList &tiles, int sel, hipStream_t s)
 {
-    LAUNCH(k_norm, tiles.n, s, pl.probs, tiles.t, sel);
+    LAUNCH(k_norm, tiles.n, s, ctx_of(pl, tiles), sel);
 }
 
 void launch_zero(const Plan &pl, const DevList &tiles, int sel, hipStream_t s)
 {
-    LAUNCH(k_zero, tiles.n, s, pl.probs, tiles.t, sel);
-}
-
-void launch_fin(const Plan &pl, const int *probs, int n, int kind, hipStream_t s)
-{
-    LAUNCH(k_fin, n, s, pl.probs, probs, kind);
+    LAUNCH(k_zero, tiles.n, s, ctx_of(pl, tiles), sel);
 }
 
 // ---------------------------------------------------------------------------
@@ -432,19 +561,24 @@ hh_status hh_apply_operator(const hh_grid *g, hh_op op, hh_prec prec, const void
     if (g->host_only) return hh_fail(HH_ERR_ARG, "grid was built host-only");
     if (x == y) return hh_fail(HH_ERR_ARG, "x and y must not overlap");
     hipStream_t s = (hipStream_t)stream;
-    const ProbDev *P = g->pd_static_dev;
     const int n = g->nchunks;
+    Ctx c;
+    c.P = g->pd_static_dev;
+    c.tiles = nullptr;
+    c.ctrl = nullptr;
+    c.L = prec == HH_C64 ? (const void *)g->L32 : (const void *)g->L64;
+    c.omega = g->hs.omega;
     if (op == HH_OP_H) {
         if (prec != HH_C128) return hh_fail(HH_ERR_ARG, "H is applied in complex double only");
-        if (g->hs.dim == 2) LAUNCH(k_applyH<2>, n, s, P, g->chunks_dev, x, y);
-        else LAUNCH(k_applyH<3>, n, s, P, g->chunks_dev, x, y);
+        if (g->hs.dim == 2) LAUNCH(k_applyH<2>, n, s, c, x, y);
+        else LAUNCH(k_applyH<3>, n, s, c, x, y);
     } else if (op == HH_OP_M) {
         if (prec == HH_C128) {
-            if (g->hs.dim == 2) LAUNCH((k_applyM<2, double>), n, s, P, g->chunks_dev, x, y);
-            else LAUNCH((k_applyM<3, double>), n, s, P, g->chunks_dev, x, y);
+            if (g->hs.dim == 2) LAUNCH((k_applyM<2, double>), n, s, c, x, y);
+            else LAUNCH((k_applyM<3, double>), n, s, c, x, y);
         } else if (prec == HH_C64) {
-            if (g->hs.dim == 2) LAUNCH((k_applyM<2, float>), n, s, P, g->chunks_dev, x, y);
-            else LAUNCH((k_applyM<3, float>), n, s, P, g->chunks_dev, x, y);
+            if (g->hs.dim == 2) LAUNCH((k_applyM<2, float>), n, s, c, x, y);
+            else LAUNCH((k_applyM<3, float>), n, s, c, x, y);
         } else {
             return hh_fail(HH_ERR_ARG, "unknown precision %d", (int)prec);
         }
@@ -465,7 +599,7 @@ hh_status hh_vcycle(const hh_grid *g, hh_prec prec, const void *f, void *u, void
     hh_status st = grid_vplan(gm, prec == HH_C64);
     if (st != HH_OK) return st;
     const Plan &pl = prec == HH_C64 ? gm->vplan32 : gm->vplan64;
-    launch_vcycle(pl, g->pd_static_dev, VS_IN, VS_OUT, f, u, (hipStream_t)stream);
+    launch_vcycle(pl, VS_IN, VS_OUT, f, u, (hipStream_t)stream);
     HIPCHK(hipGetLastError());
     return HH_OK;
 }
@@ -477,5 +611,11 @@ hh_status grid_vplan(hh_grid *g, bool fp32)
     Plan &pl = fp32 ? g->vplan32 : g->vplan64;
     if (pl.mem) return HH_OK;
     std::vector<const hh_grid *> G{g};
-    return plan_build(pl, G, fp32);
+    hh_status st = plan_build(pl, G, fp32);
+    if (st != HH_OK) return st;
+    // standalone cycles: the static descriptor, no control block (always run)
+    pl.probs = g->pd_static_dev;
+    pl.ctrl = nullptr;
+    pl.host.assign(1, g->pd_static);
+    return HH_OK;
 }

@@ -156,8 +156,16 @@ static hh_status solve_bicg(std::vector<Ctl> &C, Plan &pl, const void *const *b,
 {
     const int nb = (int)C.size();
     std::vector<ProbDev> hp(nb);
-    for (int q = 0; q < nb; ++q) fill_solve_prob(C[q].g, C[q].o, b[q], x[q], hp[q]);
+    std::vector<Ctrl> hc(nb);
+    for (int q = 0; q < nb; ++q) {
+        fill_solve_prob(C[q].g, C[q].o, b[q], x[q], hp[q]);
+        hp[q].ctrl = pl.ctrl + q;
+        memset(&hc[q], 0, sizeof(Ctrl));
+        hc[q].phase = PH_IDLE;
+    }
+    pl.host = hp;
     HIPCHK(hipMemcpyAsync(pl.probs, hp.data(), sizeof(ProbDev) * nb, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(pl.ctrl, hc.data(), sizeof(Ctrl) * nb, hipMemcpyHostToDevice, s));
     int total_chunks = 0;
     for (int q = 0; q < nb; ++q) {
         C[q].chunk0 = total_chunks;
