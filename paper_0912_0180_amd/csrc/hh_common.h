@@ -21,7 +21,7 @@
 #define HH_WG 256                 // threads per workgroup (4 wave64)
 #define HH_PER_SLOT 8             // elements per thread slot in a reduction chunk
 #define HH_CHUNK (HH_WG * HH_PER_SLOT)
-#define HH_NPART 16               // reals per chunk partial record
+#define HH_NPART 40               // reals per chunk partial record (IDR(8) start-up needs 4s+1)
 #define HH_MAX_COARSE 1024
 #define HH_MAX_S 8
 
@@ -161,9 +161,13 @@ struct SolveState {
 // Per-problem control block of a launch plan: the phase and the Krylov
 // scalars every pass needs, read by one scalar load from a kernel argument.
 struct Ctrl {
-    int phase, pad0, pad1, pad2;
-    double2 alpha, beta, omega;
-    double2 om_idr;
+    int phase;
+    int mode;                        // IDR: 0 start-up step, 1 cycle step k = 0, 2 cycle step k >= 1
+    int old;                         // IDR: column of dR/dX this step writes
+    int pad;
+    double2 alpha, beta, omega;      // Bi-CGSTAB
+    double2 om_idr;                  // IDR omega
+    double2 c[8];                    // IDR: solution of G c = m for this step
 };
 
 struct ProbDev {
@@ -183,6 +187,7 @@ struct ProbDev {
     double omega;
     void *vec[VS_NVEC];
     double2 *dR, *dX;                // IDR: s columns of N each
+    int nidr;                        // IDR: s
     const double2 *P;                // IDR shadow space, N x s column-major
     double *part;                    // [nchunk * HH_NPART]
     SolveState *st;

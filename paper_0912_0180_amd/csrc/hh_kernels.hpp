@@ -162,12 +162,17 @@ __device__ inline Ctrl ctrl_of(const Ctx &c, int prob)
 {
     const Ctrl *q = c.ctrl + prob;
     Ctrl r;
-    r.phase = ((const HH_GLOBAL int *)q)[0];
-    r.pad0 = r.pad1 = r.pad2 = 0;
+    const HH_GLOBAL int *qi = (const HH_GLOBAL int *)q;
+    r.phase = qi[0];
+    r.mode = qi[1];
+    r.old = qi[2];
+    r.pad = 0;
     r.alpha = ldg(&q->alpha, 0);
     r.beta = ldg(&q->beta, 0);
     r.omega = ldg(&q->omega, 0);
     r.om_idr = ldg(&q->om_idr, 0);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r.c[i] = ldg(&q->c[i], 0);
     return r;
 }
 template <typename T> __device__ inline const LevelDev<T> *levels_of(const Ctx &c, const ProbDev *pd)
@@ -221,7 +226,7 @@ __device__ inline V2<T> stencil(const VW &h, const S *__restrict__ x, int i, int
 // finalisation: the last workgroup of a reducing pass (per problem) sums the
 // chunk partials in the fixed pairwise order and advances the scalar state
 // ---------------------------------------------------------------------------
-#define HH_FIN_STAGE 6144
+#define HH_FIN_STAGE 16384
 enum FinKind { FIN_BNORM = 0, FIN_INIT, FIN_ALPHA, FIN_S, FIN_OMEGA, FIN_RHO, FIN_TRUE, FIN_NONE,
                FIN_IDR_OMEGA, FIN_IDR_STEP, FIN_IDR_INIT, FIN_IDR_M };
 
@@ -245,11 +250,14 @@ __device__ inline void mirror(const ProbDev *pd, const SolveState *st)
     if (!pd->ctrl) return;
     Ctrl c;
     c.phase = st->phase;
-    c.pad0 = c.pad1 = c.pad2 = 0;
+    c.mode = st->startup >= 0 ? 0 : (st->kstep == 0 ? 1 : 2);
+    c.old = st->startup >= 0 ? st->startup : st->oldest;
+    c.pad = 0;
     c.alpha = st->alpha;
     c.beta = st->beta;
     c.omega = st->omega;
     c.om_idr = st->om_idr;
+    for (int i = 0; i < 8; ++i) c.c[i] = i < HH_MAX_S ? st->c[i] : cmk<double>(0.0, 0.0);
     *pd->ctrl = c;
 }
 
@@ -264,7 +272,7 @@ __device__ void finalize(const ProbDev *pd, int kind)
     const int nv = kind >= FIN_IDR_OMEGA ? idr_nvals(pd, kind)
                  : (kind == FIN_S || kind == FIN_BNORM || kind == FIN_TRUE) ? 1 : (kind == FIN_ALPHA ? 2 : 3);
     const int first = (kind == FIN_BNORM || kind == FIN_TRUE) ? 2 : 0;
-    double s[2 * HH_MAX_S + 4];
+    double s[4 * HH_MAX_S + 4];
     const int n = pd->nchunk;
     if (n * nv <= HH_FIN_STAGE) {
         // stage the partials in LDS with all loads in flight, then reduce

@@ -81,6 +81,7 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
 
 void launch_vcycle(const Plan &pl, int fsel, int osel, const void *fptr, void *optr, hipStream_t s);
 void launch_bicg_iteration(const Plan &pl, hipStream_t s);
+void launch_idr_step(const Plan &pl, hipStream_t s);
 void launch_resid(const Plan &pl, const DevList &tiles, int mode, hipStream_t s);
 void launch_norm(const Plan &pl, const DevList &tiles, int sel, hipStream_t s);
 void launch_zero(const Plan &pl, const DevList &tiles, int sel, hipStream_t s);

@@ -455,6 +455,30 @@ void launch_bicg_iteration(const Plan &pl, hipStream_t s)
     }
 }
 
+template <int DIM, typename SW>
+static void idr_step_t(const Plan &pl, hipStream_t s)
+{
+    const Ctx c = ctx_of(pl, pl.chunks);
+    const int n = pl.chunks.n;
+    LAUNCH(k_idr_v, n, s, c);
+    launch_vcycle(pl, VS_V, VS_W, nullptr, nullptr, s);
+    LAUNCH((k_idr_t<DIM, SW>), n, s, c);
+    launch_fin(pl, pl.fin, pl.nfin, FIN_IDR_OMEGA, s);
+    LAUNCH((k_idr_up<DIM, SW>), n, s, c);
+    launch_fin(pl, pl.fin, pl.nfin, FIN_IDR_STEP, s);
+}
+
+void launch_idr_step(const Plan &pl, hipStream_t s)
+{
+    if (pl.dim == 2) {
+        if (pl.fp32) idr_step_t<2, float2>(pl, s);
+        else idr_step_t<2, double2>(pl, s);
+    } else {
+        if (pl.fp32) idr_step_t<3, float2>(pl, s);
+        else idr_step_t<3, double2>(pl, s);
+    }
+}
+
 void launch_resid(const Plan &pl, const DevList &tiles, int mode, hipStream_t s)
 {
     const Ctx c = ctx_of(pl, tiles);

@@ -96,6 +96,7 @@ static void fill_solve_prob(hh_grid *g, const hh_solve_opts *o, const void *b, v
     pd.part = w.part;
     pd.st = w.st;
     pd.hist = o->history && o->history_len > 0 ? w.hist : nullptr;
+    pd.nidr = o->method == HH_METHOD_IDR ? o->s : 0;
 }
 
 namespace {
@@ -152,8 +153,18 @@ hh_status read_states(const std::vector<Ctl> &C, std::vector<SolveState> &S, hip
 
 } // namespace
 
-static hh_status solve_bicg(std::vector<Ctl> &C, Plan &pl, const void *const *b, void *const *x, hipStream_t s)
+// Bi-CGSTAB and IDR(s) share the driver: start (r = b - H x and the method's
+// initial scalars), iterations of the method's passes, true-residual checks
+// and restarts.
+static hh_status solve_krylov(std::vector<Ctl> &C, Plan &pl, const void *const *b, void *const *x, hipStream_t s,
+                              int method)
 {
+    const int init_mode = method == HH_METHOD_BICGSTAB ? 0 : 2;
+    const int init_fin = method == HH_METHOD_BICGSTAB ? 1 /*FIN_INIT*/ : 10 /*FIN_IDR_INIT*/;
+    auto iterate = [&]() {
+        if (method == HH_METHOD_BICGSTAB) launch_bicg_iteration(pl, s);
+        else launch_idr_step(pl, s);
+    };
     const int nb = (int)C.size();
     std::vector<ProbDev> hp(nb);
     std::vector<Ctrl> hc(nb);
@@ -177,6 +188,8 @@ static hh_status solve_bicg(std::vector<Ctl> &C, Plan &pl, const void *const *b,
         st.tol = C[q].o->tol;
         st.max_mv = C[q].o->max_matvec;
         st.hist_len = C[q].o->history ? C[q].o->history_len : 0;
+        st.s = method == HH_METHOD_IDR ? C[q].o->s : 0;
+        st.startup = -1;
         HIPCHK(hipMemcpyAsync(C[q].g->ws.st, &st, sizeof st, hipMemcpyHostToDevice, s));
     }
     Subset sub;
@@ -211,13 +224,13 @@ static hh_status solve_bicg(std::vector<Ctl> &C, Plan &pl, const void *const *b,
     if (!start.empty()) {
         rc = sub.set(C, start, s);
         if (rc != HH_OK) return rc;
-        launch_resid(pl, sub.list(), 0, s);
-        launch_fin(pl, sub.p, (int)start.size(), 1 /*FIN_INIT*/, s);
+        launch_resid(pl, sub.list(), init_mode, s);
+        launch_fin(pl, sub.p, (int)start.size(), init_fin, s);
     }
     HIPCHK(hipGetLastError());
     int active = (int)start.size();
     while (active > 0) {
-        launch_bicg_iteration(pl, s);
+        iterate();
         HIPCHK(hipGetLastError());
         rc = read_states(C, S, s);
         if (rc != HH_OK) return rc;
@@ -262,8 +275,8 @@ static hh_status solve_bicg(std::vector<Ctl> &C, Plan &pl, const void *const *b,
         if (!restart.empty()) {
             rc = sub.set(C, restart, s);
             if (rc != HH_OK) return rc;
-            launch_resid(pl, sub.list(), 0, s);
-            launch_fin(pl, sub.p, (int)restart.size(), 1 /*FIN_INIT*/, s);
+            launch_resid(pl, sub.list(), init_mode, s);
+            launch_fin(pl, sub.p, (int)restart.size(), init_fin, s);
             HIPCHK(hipGetLastError());
         }
     }
@@ -310,7 +323,6 @@ static hh_status check_opts(const hh_grid *g, const hh_solve_opts *o)
     return HH_OK;
 }
 
-hh_status solve_idr(std::vector<Ctl> &C, Plan &pl, const void *const *b, void *const *x, hipStream_t s);
 
 extern "C" hh_status hh_solve_batch(hh_grid *const *g, int32_t count, const hh_solve_opts *o, const void *const *b,
                                     void *const *x, hh_solve_info *info, void *stream)
@@ -354,7 +366,7 @@ extern "C" hh_status hh_solve_batch(hh_grid *const *g, int32_t count, const hh_s
         hh_status rc = plan_build(local, G, fp32);
         if (rc != HH_OK) return rc;
     }
-    hh_status rc = o[0].method == HH_METHOD_BICGSTAB ? solve_bicg(C, *pl, b, x, s) : solve_idr(C, *pl, b, x, s);
+    hh_status rc = solve_krylov(C, *pl, b, x, s, o[0].method);
     if (pl == &local) plan_release(local);
     if (rc != HH_OK) return rc;
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -375,7 +387,3 @@ extern "C" hh_status hh_solve(hh_grid *g, const hh_solve_opts *o, const void *b,
     return hh_solve_batch(gg, 1, o, bb, xx, info, stream);
 }
 
-hh_status solve_idr(std::vector<Ctl> &, Plan &, const void *const *, void *const *, hipStream_t)
-{
-    return hh_fail(HH_ERR_ARG, "IDR(s) is not built yet");
-}

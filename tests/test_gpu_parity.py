@@ -214,3 +214,81 @@ def test_edge_cases(torch_dev, hh_mod, oracle_mod):
     xo1, io1 = oracle_mod.Grid(c["desc"], c["phi"]).solve(c["b"], x0=host(x0), tol=1e-8)
     assert i1["status"] == 0 == io1["status"] and i1["matvecs"] == io1["matvecs"]
     assert same(host(x1), xo1)
+
+
+@pytest.mark.parametrize("name,s", [("c1", 4), ("ragged_2d", 4), ("ragged_3d", 4), ("c3_32", 4), ("c1_interior", 1),
+                                    ("c1", 2), ("c1", 8)])
+def test_idr_fp64_matches_oracle(torch_dev, hh_mod, oracle_mod, name, s):
+    torch = torch_dev
+    c = CASES[name]()
+    print("case", name, "s", s, flush=True)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    b = c.get("b")
+    if b is None:
+        b = rand_c(np.random.default_rng(13), g.N)
+    P = W.shadow_space(g.N, s, 1000 + s)
+    xo, io = o.solve(b, method="idr", s=s, P=P, tol=1e-8, history=True)
+    Pd = hh_mod.shadow_to_device(P)
+    xg, ig = g.solve(dev(torch, b), method="idr", s=s, P=Pd, tol=1e-8, vcycle_prec="c128", history=True)
+    xg = host(xg)
+    assert io["status"] == 0 and ig["status"] == 0
+    assert ig["rel_res_true"] < 1e-8 and rel(xg, xo) <= 1e-6
+    assert ig["matvecs"] == io["matvecs"] and ig["iterations"] == io["iterations"]
+    assert same(xg, xo)
+    assert np.array_equal(ig["history"], io["history"])
+
+
+@pytest.mark.parametrize("name", ["c1", "ragged_3d", "c3_32"])
+def test_idr_mixed_precision(torch_dev, hh_mod, oracle_mod, name):
+    torch = torch_dev
+    c = CASES[name]()
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    b = c.get("b")
+    if b is None:
+        b = rand_c(np.random.default_rng(14), g.N)
+    P = W.shadow_space(g.N, 4, 1004)
+    xo, io = o.solve(b, method="idr", s=4, P=P, tol=1e-8)
+    xg, ig = g.solve(dev(torch, b), method="idr", s=4, P=hh_mod.shadow_to_device(P), tol=1e-8, vcycle_prec="c64")
+    assert ig["status"] == 0 and ig["rel_res_true"] < 1e-8
+    assert rel(host(xg), xo) <= 1e-6
+    print(name, "IDR(4) matvecs fp64", io["matvecs"], "mixed", ig["matvecs"])
+
+
+def test_idr_batch_equals_single(torch_dev, hh_mod):
+    torch = torch_dev
+    cs = [W.c1(), ragged_2d(), W.c2(n=256, levels=6)]
+    rng = np.random.default_rng(15)
+    grids, bs, Ps = [], [], []
+    for c in cs:
+        g = hh_mod.Grid(c["desc"], c["phi"])
+        grids.append(g)
+        b = c.get("b")
+        bs.append(dev(torch, b if b is not None else rand_c(rng, g.N)))
+    # one shared options set: all problems use s = 4 with their own P
+    xs_single = []
+    for g, b in zip(grids, bs):
+        P = hh_mod.shadow_to_device(W.shadow_space(g.N, 4, 77))
+        Ps.append(P)
+        x, i = g.solve(b, method="idr", s=4, P=P, tol=1e-8, vcycle_prec="c64")
+        assert i["status"] == 0
+        xs_single.append((host(x), i["matvecs"]))
+    L = hh_mod.lib()
+    import ctypes
+    n = len(grids)
+    opts = (hh_mod.SolveOpts * n)()
+    for q in range(n):
+        o, _ = hh_mod.make_opts(method="idr", s=4, P=Ps[q], tol=1e-8, vcycle_prec="c64")
+        opts[q] = o
+    infos = (hh_mod.SolveInfo * n)()
+    xs = [torch.zeros_like(b) for b in bs]
+    G = (ctypes.c_void_p * n)(*[g.h.value for g in grids])
+    B = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
+    X = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+    st = L.hh_solve_batch(G, n, opts, B, X, infos, None)
+    torch.cuda.synchronize()
+    assert st == 0
+    for q in range(n):
+        assert infos[q].matvecs == xs_single[q][1]
+        assert same(host(xs[q]), xs_single[q][0])
