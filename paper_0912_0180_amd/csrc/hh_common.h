@@ -164,7 +164,7 @@ struct Ctrl {
     int phase;
     int mode;                        // IDR: 0 start-up step, 1 cycle step k = 0, 2 cycle step k >= 1
     int old;                         // IDR: column of dR/dX this step writes
-    int pad;
+    int reason;                      // stop reason (host reads it with the phase)
     double2 alpha, beta, omega;      // Bi-CGSTAB
     double2 om_idr;                  // IDR omega
     double2 c[8];                    // IDR: solution of G c = m for this step
@@ -211,9 +211,8 @@ struct Ctx {
 // Levels with at most TailCap<T>::N unknowns (and every coarser level) run
 // inside one workgroup with all data in LDS.
 template <typename T> struct TailCap;
-template <> struct TailCap<double> { static constexpr int N = 1024; static constexpr int BYTES = 96 * 1024; };
-template <> struct TailCap<float> { static constexpr int N = 1024; static constexpr int BYTES = 64 * 1024; };
-#define HH_TAIL_WG 512
+template <> struct TailCap<double> { static constexpr int N = 1024; static constexpr int BYTES = 96 * 1024; static constexpr int WG = 256; };
+template <> struct TailCap<float> { static constexpr int N = 1024; static constexpr int BYTES = 64 * 1024; static constexpr int WG = 512; };
 
 // Tile shapes of the fused V-cycle kernels (coarse tile of the down-leg; the
 // up-leg's fine tile is twice it).

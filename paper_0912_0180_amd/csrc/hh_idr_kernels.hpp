@@ -35,8 +35,8 @@ __device__ int idr_nvals(const ProbDev *pd, int kind)
 // setup's dense LU.  Returns false for an exactly singular pivot.
 __device__ bool small_solve(const double2 *Gin, int s, const double2 *m, double2 *c)
 {
-    double2 A[HH_MAX_S * HH_MAX_S];
-    int perm[HH_MAX_S];
+    __shared__ double2 A[HH_MAX_S * HH_MAX_S];   // thread 0 only (keeps the solve out of scratch memory)
+    __shared__ int perm[HH_MAX_S];
     for (int i = 0; i < s * s; ++i) A[i] = Gin[i];
     for (int i = 0; i < s; ++i) perm[i] = i;
     for (int k = 0; k < s; ++k) {

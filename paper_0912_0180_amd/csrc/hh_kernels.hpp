@@ -166,7 +166,7 @@ __device__ inline Ctrl ctrl_of(const Ctx &c, int prob)
     r.phase = qi[0];
     r.mode = qi[1];
     r.old = qi[2];
-    r.pad = 0;
+    r.reason = qi[3];
     r.alpha = ldg(&q->alpha, 0);
     r.beta = ldg(&q->beta, 0);
     r.omega = ldg(&q->omega, 0);
@@ -244,6 +244,65 @@ __device__ inline void record(const ProbDev *pd, SolveState *st, double rel)
     if (pd->hist && st->mv - 1 < st->hist_len && st->mv >= 1) pd->hist[st->mv - 1] = rel;
 }
 
+// Sums value q (q < nv) of the chunk partial records part[c * HH_NPART + q]
+// over the n chunks, each by the pairwise tree over the zero-padded
+// power-of-two length; results in out[q].  The partials are staged in LDS in
+// blocks of HH_FIN_STAGE entries (an aligned power-of-two block of a pairwise
+// tree is itself a subtree, so block sums combine exactly).
+__device__ void reduce_partials(const double *part, int n, int nv, double *out)
+{
+    __shared__ double stage[HH_FIN_STAGE];
+    __shared__ double bsum[4 * HH_MAX_S + 4][64];
+    int np = 1;
+    while (np < n) np <<= 1;
+    // values per staging pass: all nv at once when they fit
+    const int blk = np < HH_FIN_STAGE ? np : HH_FIN_STAGE;
+    const int qstep = (HH_FIN_STAGE / blk) < nv ? (HH_FIN_STAGE / blk) : nv;
+    const int nblk = np / blk;
+    for (int q0 = 0; q0 < nv; q0 += qstep) {
+        const int nq = nv - q0 < qstep ? nv - q0 : qstep;
+        for (int b = 0; b < nblk; ++b) {
+            const int tot = nq * blk;
+            for (int e0 = 0; e0 < tot; e0 += 8 * HH_WG) {
+                double tmp[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + threadIdx.x + u * HH_WG;
+                    tmp[u] = 0.0;
+                    if (e < tot) {
+                        const int qq = e / blk, c = b * blk + (e - qq * blk);
+                        if (c < n) tmp[u] = ldg(part, (int64_t)c * HH_NPART + q0 + qq);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + threadIdx.x + u * HH_WG;
+                    if (e < tot) stage[e] = tmp[u];
+                }
+            }
+            __syncthreads();
+            for (int w = 1; w < blk; w <<= 1) {
+                const int pairs = blk / (2 * w);
+                for (int e = threadIdx.x; e < nq * pairs; e += HH_WG) {
+                    const int qq = e / pairs, i = (e - qq * pairs) * 2 * w;
+                    stage[qq * blk + i] = stage[qq * blk + i] + stage[qq * blk + i + w];
+                }
+                __syncthreads();
+            }
+            if (threadIdx.x < nq) bsum[q0 + threadIdx.x][b] = stage[threadIdx.x * blk];
+            __syncthreads();
+        }
+    }
+    // combine block sums (nblk is a power of two, at most 64 here)
+    if (threadIdx.x < nv) {
+        const int q = threadIdx.x;
+        for (int w = 1; w < nblk; w <<= 1)
+            for (int i = 0; i + w < nblk; i += 2 * w) bsum[q][i] = bsum[q][i] + bsum[q][i + w];
+        out[q] = bsum[q][0];
+    }
+    __syncthreads();
+}
+
 // copy of the phase and scalars into the plan's control block
 __device__ inline void mirror(const ProbDev *pd, const SolveState *st)
 {
@@ -252,7 +311,7 @@ __device__ inline void mirror(const ProbDev *pd, const SolveState *st)
     c.phase = st->phase;
     c.mode = st->startup >= 0 ? 0 : (st->kstep == 0 ? 1 : 2);
     c.old = st->startup >= 0 ? st->startup : st->oldest;
-    c.pad = 0;
+    c.reason = st->reason;
     c.alpha = st->alpha;
     c.beta = st->beta;
     c.omega = st->omega;
@@ -265,40 +324,51 @@ __device__ inline void mirror(const ProbDev *pd, const SolveState *st)
 __device__ void idr_finalize(const ProbDev *pd, SolveState *st, int kind, const double *s, int phase);
 __device__ int idr_nvals(const ProbDev *pd, int kind);
 
+// Scalar state of a Bi-CGSTAB solve, copied to registers before the
+// reduction (its loads overlap the partial sums) and written back once.
+struct BiLoc {
+    int phase, reason, mv, it, max_mv, hist_len;
+    double tol, bnorm, rel, true_rel;
+    double2 rho, alpha, omega, beta;
+};
+
+__device__ inline void bi_stop(BiLoc &b, int reason)
+{
+    b.phase = PH_STOP;
+    b.reason = reason;
+}
+
+__device__ inline void bi_record(const ProbDev *pd, BiLoc &b, double rel)
+{
+    b.rel = rel;
+    if (pd->hist && b.mv - 1 < b.hist_len && b.mv >= 1) pd->hist[b.mv - 1] = rel;
+}
+
 __device__ void finalize(const ProbDev *pd, int kind)
 {
     SolveState *st = pd->st;
-    const int phase = st->phase;
+    BiLoc b;
+    b.phase = st->phase;
+    b.reason = st->reason;
+    b.mv = st->mv;
+    b.it = st->it;
+    b.max_mv = st->max_mv;
+    b.hist_len = st->hist_len;
+    b.tol = st->tol;
+    b.bnorm = st->bnorm;
+    b.rel = st->rel;
+    b.true_rel = st->true_rel;
+    b.rho = st->rho;
+    b.alpha = st->alpha;
+    b.omega = st->omega;
+    b.beta = st->beta;
+    const int phase = b.phase;
     const int nv = kind >= FIN_IDR_OMEGA ? idr_nvals(pd, kind)
                  : (kind == FIN_S || kind == FIN_BNORM || kind == FIN_TRUE) ? 1 : (kind == FIN_ALPHA ? 2 : 3);
     const int first = (kind == FIN_BNORM || kind == FIN_TRUE) ? 2 : 0;
-    double s[4 * HH_MAX_S + 4];
-    const int n = pd->nchunk;
-    if (n * nv <= HH_FIN_STAGE) {
-        // stage the partials in LDS with all loads in flight, then reduce
-        __shared__ double stage[HH_FIN_STAGE];
-        const int tot = n * nv;
-        for (int b = 0; b < tot; b += 8 * HH_WG) {
-            double tmp[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int e = b + threadIdx.x + q * HH_WG;
-                if (e < tot) {
-                    const int c = e / nv, k = e - c * nv;
-                    tmp[q] = ldg(pd->part, (int64_t)c * HH_NPART + first + k);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int e = b + threadIdx.x + q * HH_WG;
-                if (e < tot) stage[e] = tmp[q];
-            }
-        }
-        __syncthreads();
-        for (int q = 0; q < nv; ++q) s[q] = pairwise_wg<true>(stage + q, nv, n);
-    } else {
-        for (int q = 0; q < nv; ++q) s[q] = pairwise_wg<false>(pd->part + first + q, HH_NPART, n);
-    }
+    __shared__ double res[4 * HH_MAX_S + 4];
+    reduce_partials(pd->part + first, pd->nchunk, nv, res);
+    const double *s = res;
     if (threadIdx.x != 0) return;
     if (kind >= FIN_IDR_OMEGA) {
         idr_finalize(pd, st, kind, s, phase);
@@ -307,76 +377,99 @@ __device__ void finalize(const ProbDev *pd, int kind)
     }
     switch (kind) {
     case FIN_BNORM:
-        st->bnorm = sqrt(s[0]);
+        b.bnorm = sqrt(s[0]);
         break;
     case FIN_TRUE:
-        st->true_rel = sqrt(s[0]) / st->bnorm;
+        b.true_rel = sqrt(s[0]) / b.bnorm;
         break;
     case FIN_INIT: {
         // start (or restart) of Bi-CGSTAB: rho = alpha = omega = 1, then the
         // first beta from rho1 = (rhat, r)
         const double2 one = cmk<double>(1.0, 0.0);
-        st->rho = one;
-        st->alpha = one;
-        st->omega = one;
-        st->phase = PH_RUN;
-        st->reason = RS_NONE;
+        b.rho = one;
+        b.alpha = one;
+        b.omega = one;
+        b.phase = PH_RUN;
+        b.reason = RS_NONE;
         double2 rho1 = cmk<double>(s[0], s[1]);
-        if (!cfin(rho1)) { stop(st, RS_NONFIN); break; }
-        if (rho1.x == 0.0 && rho1.y == 0.0) { stop(st, RS_BREAK); break; }
-        st->beta = cmul<double>(cdiv<double>(rho1, st->rho), cdiv<double>(st->alpha, st->omega));
-        st->rho = rho1;
+        if (!cfin(rho1)) { bi_stop(b, RS_NONFIN); break; }
+        if (rho1.x == 0.0 && rho1.y == 0.0) { bi_stop(b, RS_BREAK); break; }
+        b.beta = cmul<double>(cdiv<double>(rho1, b.rho), cdiv<double>(b.alpha, b.omega));
+        b.rho = rho1;
         break;
     }
     case FIN_ALPHA: {
         if (phase != PH_RUN) break;
-        st->mv += 1;
+        b.mv += 1;
         double2 rv = cmk<double>(s[0], s[1]);
-        if (!cfin(rv)) { stop(st, RS_NONFIN); break; }
-        if (rv.x == 0.0 && rv.y == 0.0) { stop(st, RS_BREAK); break; }
-        st->alpha = cdiv<double>(st->rho, rv);
+        if (!cfin(rv)) { bi_stop(b, RS_NONFIN); break; }
+        if (rv.x == 0.0 && rv.y == 0.0) { bi_stop(b, RS_BREAK); break; }
+        b.alpha = cdiv<double>(b.rho, rv);
         break;
     }
     case FIN_S: {
         if (phase != PH_RUN) break;
-        double rel = sqrt(s[0]) / st->bnorm;
-        record(pd, st, rel);
-        if (!isfinite(rel)) { stop(st, RS_NONFIN); break; }
-        if (rel < st->tol) { st->phase = PH_HALF; st->reason = RS_CONV; break; }
-        if (st->mv >= st->max_mv) { st->phase = PH_HALF; st->reason = RS_MAXMV; break; }
+        double rel = sqrt(s[0]) / b.bnorm;
+        bi_record(pd, b, rel);
+        if (!isfinite(rel)) { bi_stop(b, RS_NONFIN); break; }
+        if (rel < b.tol) { b.phase = PH_HALF; b.reason = RS_CONV; break; }
+        if (b.mv >= b.max_mv) { b.phase = PH_HALF; b.reason = RS_MAXMV; break; }
         break;
     }
     case FIN_OMEGA: {
         if (phase != PH_RUN) break;
-        st->mv += 1;
+        b.mv += 1;
         double2 ts = cmk<double>(s[0], s[1]);
         double tt = s[2];
-        if (!cfin(ts) || !isfinite(tt)) { stop(st, RS_NONFIN); break; }
-        if (tt == 0.0) { stop(st, RS_BREAK); break; }
-        st->omega = cmk<double>(ts.x / tt, ts.y / tt);
+        if (!cfin(ts) || !isfinite(tt)) { bi_stop(b, RS_NONFIN); break; }
+        if (tt == 0.0) { bi_stop(b, RS_BREAK); break; }
+        b.omega = cmk<double>(ts.x / tt, ts.y / tt);
         break;
     }
     case FIN_RHO: {
         if (phase != PH_RUN && phase != PH_HALF) break;
-        st->it += 1;
-        if (phase == PH_HALF) { st->phase = PH_STOP; break; }
-        double rel = sqrt(s[2]) / st->bnorm;
-        record(pd, st, rel);
-        if (!isfinite(rel)) { stop(st, RS_NONFIN); break; }
-        if (rel < st->tol) { stop(st, RS_CONV); break; }
-        if (st->omega.x == 0.0 && st->omega.y == 0.0) { stop(st, RS_BREAK); break; }
-        if (st->mv >= st->max_mv) { stop(st, RS_MAXMV); break; }
+        b.it += 1;
+        if (phase == PH_HALF) { b.phase = PH_STOP; break; }
+        double rel = sqrt(s[2]) / b.bnorm;
+        bi_record(pd, b, rel);
+        if (!isfinite(rel)) { bi_stop(b, RS_NONFIN); break; }
+        if (rel < b.tol) { bi_stop(b, RS_CONV); break; }
+        if (b.omega.x == 0.0 && b.omega.y == 0.0) { bi_stop(b, RS_BREAK); break; }
+        if (b.mv >= b.max_mv) { bi_stop(b, RS_MAXMV); break; }
         double2 rho1 = cmk<double>(s[0], s[1]);
-        if (!cfin(rho1)) { stop(st, RS_NONFIN); break; }
-        if (rho1.x == 0.0 && rho1.y == 0.0) { stop(st, RS_BREAK); break; }
-        st->beta = cmul<double>(cdiv<double>(rho1, st->rho), cdiv<double>(st->alpha, st->omega));
-        st->rho = rho1;
+        if (!cfin(rho1)) { bi_stop(b, RS_NONFIN); break; }
+        if (rho1.x == 0.0 && rho1.y == 0.0) { bi_stop(b, RS_BREAK); break; }
+        b.beta = cmul<double>(cdiv<double>(rho1, b.rho), cdiv<double>(b.alpha, b.omega));
+        b.rho = rho1;
         break;
     }
     default:
         break;
     }
-    mirror(pd, st);
+    st->phase = b.phase;
+    st->reason = b.reason;
+    st->mv = b.mv;
+    st->it = b.it;
+    st->bnorm = b.bnorm;
+    st->rel = b.rel;
+    st->true_rel = b.true_rel;
+    st->rho = b.rho;
+    st->alpha = b.alpha;
+    st->omega = b.omega;
+    st->beta = b.beta;
+    if (pd->ctrl && kind != FIN_BNORM && kind != FIN_TRUE) {
+        Ctrl c;
+        c.phase = b.phase;
+        c.mode = 0;
+        c.old = 0;
+        c.reason = b.reason;
+        c.alpha = b.alpha;
+        c.beta = b.beta;
+        c.omega = b.omega;
+        c.om_idr = cmk<double>(1.0, 0.0);
+        for (int i = 0; i < 8; ++i) c.c[i] = cmk<double>(0.0, 0.0);
+        *pd->ctrl = c;
+    }
 }
 
 // Writes this chunk's partial sums; the pass's finalisation runs in k_fin.
@@ -863,10 +956,11 @@ template <typename T> __device__ inline V2<T> jweight(V2<T> D, T omega)
 struct TailOff {
     int n[3], N;
     int F, E, PH, A[3], Cc[3], Dd[3];
+    int end;
 };
 
 template <int DIM, typename T>
-__device__ inline TailOff tail_off(const LevelDev<T> *Lv, int t0, int l, int &end)
+__device__ inline TailOff tail_off(const LevelDev<T> *Lv, int t0, int l)
 {
     const int cb = sizeof(V2<T>), rb = sizeof(T);
     auto r16 = [](int b) { return (b + 15) & ~15; };
@@ -886,7 +980,7 @@ __device__ inline TailOff tail_off(const LevelDev<T> *Lv, int t0, int l, int &en
             o.Dd[a] = off; off += r16(cb * na);
         }
     }
-    end = off;
+    o.end = off;
     return o;
 }
 
@@ -898,18 +992,36 @@ template <typename T> struct TailPtr {
     T *PH;
 };
 
+// Level table of the tail, computed once per workgroup into LDS: byte
+// offsets of every array of level l and its index decomposition.
+struct TailTab {
+    TailOff o[HH_MAXLEV];
+    FastDiv fx[HH_MAXLEV], fxy[HH_MAXLEV];
+    int uoff;
+};
+
 template <int DIM, typename T>
-__device__ inline TailPtr<T> tail_ptr(char *lds, const LevelDev<T> *Lv, int t0, int l)
+__device__ inline void tail_tab_fill(TailTab &tab, const LevelDev<T> *Lv, int t0, int L)
 {
-    int end;
-    const TailOff o = tail_off<DIM, T>(Lv, t0, l, end);
+    for (int l = t0; l < L; ++l) {
+        tab.o[l] = tail_off<DIM, T>(Lv, t0, l);
+        tab.fx[l] = Lv[l].fx;
+        tab.fxy[l] = Lv[l].fxy;
+    }
+    tab.uoff = tab.o[L - 1].end;
+}
+
+template <int DIM, typename T>
+__device__ inline TailPtr<T> tail_ptr(char *lds, const TailTab &tab, int l)
+{
+    const TailOff &o = tab.o[l];
     TailPtr<T> q;
     q.nx = o.n[0];
     q.ny = o.n[1];
     q.nz = o.n[2];
     q.N = o.N;
-    q.fx = Lv[l].fx;
-    q.fxy = Lv[l].fxy;
+    q.fx = tab.fx[l];
+    q.fxy = tab.fxy[l];
     q.F = (V2<T> *)(lds + o.F);
     q.E = (V2<T> *)(lds + o.E);
     q.PH = (T *)(lds + o.PH);
@@ -958,7 +1070,7 @@ __device__ inline void tail_ijk(const TailPtr<T> &Q, int p, int &i, int &j, int 
 // inverse with a pairwise sum per row.
 // ---------------------------------------------------------------------------
 template <int DIM, typename T>
-__global__ __launch_bounds__(HH_TAIL_WG) void k_vtail(Ctx cx, const int *__restrict__ probs)
+__global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__restrict__ probs)
 {
     using C = V2<T>;
     __shared__ __attribute__((aligned(16))) char lds[TailCap<T>::BYTES];
@@ -969,10 +1081,14 @@ __global__ __launch_bounds__(HH_TAIL_WG) void k_vtail(Ctx cx, const int *__restr
     const int t0 = tail_level<T>(pd), L = pd->nlev;
     const T omega = (T)pd->omega;
     const C zero = cmk<T>(0, 0);
-    const int tid = threadIdx.x, nth = HH_TAIL_WG;
-    int uoff;
-    tail_off<DIM, T>(Lv, t0, L - 1, uoff);
-    C *U = (C *)(lds + uoff);
+    const int tid = threadIdx.x, nth = TailCap<T>::WG;
+    __shared__ TailTab tab;
+    if (tid == 0) tail_tab_fill<DIM, T>(tab, Lv, t0, L);
+    __syncthreads();
+    C *U = (C *)(lds + tab.uoff);
+    const C *fg_top = Lv[t0].f;
+    C *eg_top = Lv[t0].e;
+    const C *__restrict__ Minv = (const C *)(sizeof(T) == 8 ? (const void *)pd->Minv64 : (const void *)pd->Minv32);
     // the tail image (phi and coefficients of every tail level, zeros
     // elsewhere) in one coalesced sweep, then f at the top level
     {
@@ -993,8 +1109,8 @@ __global__ __launch_bounds__(HH_TAIL_WG) void k_vtail(Ctx cx, const int *__restr
             }
         }
         __syncthreads();
-        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, Lv, t0, t0);
-        const C *__restrict__ fg = Lv[t0].f;
+        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, t0);
+        const C *__restrict__ fg = fg_top;
         for (int b = 0; b < Q.N; b += 4 * nth) {
             C tmp[4];
 #pragma unroll
@@ -1009,8 +1125,8 @@ __global__ __launch_bounds__(HH_TAIL_WG) void k_vtail(Ctx cx, const int *__restr
     const T w0 = (T)0.125, w1 = (T)0.375, p3 = (T)0.75, p1 = (T)0.25;
     // down-legs
     for (int l = t0; l < L - 1; ++l) {
-        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, Lv, t0, l);
-        const TailPtr<T> R = tail_ptr<DIM, T>(lds, Lv, t0, l + 1);
+        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, l);
+        const TailPtr<T> R = tail_ptr<DIM, T>(lds, tab, l + 1);
         for (int p = tid; p < Q.N; p += nth) {
             int i, j, k;
             tail_ijk(Q, p, i, j, k);
@@ -1059,23 +1175,23 @@ __global__ __launch_bounds__(HH_TAIL_WG) void k_vtail(Ctx cx, const int *__restr
     }
     // coarsest solve
     {
-        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, Lv, t0, L - 1);
-        const C *__restrict__ Minv = (const C *)(sizeof(T) == 8 ? (const void *)pd->Minv64 : (const void *)pd->Minv32);
+        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, L - 1);
         coarse_rows<T>(Minv, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
         __syncthreads();
     }
     // up-legs
     for (int l = L - 2; l >= t0; --l) {
-        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, Lv, t0, l);
-        const TailPtr<T> R = tail_ptr<DIM, T>(lds, Lv, t0, l + 1);
+        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, l);
+        const TailPtr<T> R = tail_ptr<DIM, T>(lds, tab, l + 1);
         for (int p = tid; p < Q.N; p += nth) {
             int i, j, k;
             tail_ijk(Q, p, i, j, k);
             C u1 = cmul<T>(jweight<T>(tail_diag<DIM, T>(Q, i, j, k, p), omega), Q.F[p]);
             const int Ix = i >> 1, Iox = (i & 1) ? Ix + 1 : Ix - 1;
             const int Iy = j >> 1, Ioy = (j & 1) ? Iy + 1 : Iy - 1;
-            auto ev = [&](int a, int b, int c) -> C {
-                return (a >= 0 && a < R.nx && b >= 0 && b < R.ny && c >= 0 && c < R.nz) ? R.E[a + R.nx * (b + R.ny * c)] : zero;
+            auto ev = [R](int a, int b, int c) -> C {
+                return (a >= 0 && a < R.nx && b >= 0 && b < R.ny && c >= 0 && c < R.nz) ? R.E[a + R.nx * (b + R.ny * c)]
+                                                                                      : cmk<T>(0, 0);
             };
             C pe;
             if (DIM == 2) {
@@ -1108,9 +1224,8 @@ __global__ __launch_bounds__(HH_TAIL_WG) void k_vtail(Ctx cx, const int *__restr
     }
     // write e at the top tail level
     {
-        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, Lv, t0, t0);
-        C *__restrict__ eg = Lv[t0].e;
-        for (int p = tid; p < Q.N; p += nth) stg(eg, p, Q.E[p]);
+        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, t0);
+        for (int p = tid; p < Q.N; p += nth) stg(eg_top, p, Q.E[p]);
     }
 }
 

@@ -29,6 +29,13 @@ struct Plan {
     std::vector<ProbDev> host;       // host copies of the descriptors of the current solve
     void *mem = nullptr;
     size_t bytes = 0;
+    // solve execution: an internal stream, K iterations captured as one
+    // graph, a pinned copy of the control blocks
+    hipStream_t stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int gmethod = -1, gK = 0;
+    const void *gkey = nullptr;
+    Ctrl *hctrl = nullptr;
 };
 
 // Solve work space of one grid.

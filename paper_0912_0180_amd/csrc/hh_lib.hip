@@ -225,6 +225,9 @@ static void vtile_counts(int dim, bool fp32, const HostLevel &Lf, const HostLeve
 
 void plan_release(Plan &p)
 {
+    if (p.gexec) (void)hipGraphExecDestroy(p.gexec);
+    if (p.stream) (void)hipStreamDestroy(p.stream);
+    if (p.hctrl) (void)hipHostFree(p.hctrl);
     if (p.mem) (void)hipFree(p.mem);
     p = Plan();
 }
@@ -399,7 +402,7 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
     }
     {
         Ctx c = ctx_of(pl, pl.chunks);
-        if (pl.nfin > 0) hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(HH_TAIL_WG), 0, s, c,
+        if (pl.nfin > 0) hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c,
                                             pl.count == 1 ? nullptr : pl.fin);
     }
     for (int l = pl.Lmax - 1; l >= 0; --l) {

@@ -9,6 +9,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -161,9 +162,43 @@ static hh_status solve_krylov(std::vector<Ctl> &C, Plan &pl, const void *const *
 {
     const int init_mode = method == HH_METHOD_BICGSTAB ? 0 : 2;
     const int init_fin = method == HH_METHOD_BICGSTAB ? 1 /*FIN_INIT*/ : 10 /*FIN_IDR_INIT*/;
-    auto iterate = [&]() {
+    auto iterate1 = [&]() {
         if (method == HH_METHOD_BICGSTAB) launch_bicg_iteration(pl, s);
         else launch_idr_step(pl, s);
+    };
+    // K iterations per check of the control blocks, replayed from a graph
+    const char *ek = getenv("HH_ITERS_PER_CHECK");
+    const int K = ek ? std::max(1, atoi(ek)) : 4;
+    const bool use_graph = !getenv("HH_NO_GRAPH");
+    const void *key = C[0].g->ws.mem;
+    auto iterate = [&]() -> hh_status {
+        if (!use_graph) {
+            for (int k = 0; k < K; ++k) iterate1();
+            return HH_OK;
+        }
+        if (!pl.gexec || pl.gmethod != method || pl.gK != K || pl.gkey != key) {
+            if (pl.gexec) {
+                HIPCHK(hipGraphExecDestroy(pl.gexec));
+                pl.gexec = nullptr;
+            }
+            hipGraph_t graph;
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < K; ++k) iterate1();
+            HIPCHK(hipStreamEndCapture(s, &graph));
+            hipError_t e = hipGraphInstantiate(&pl.gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return hh_fail(HH_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            pl.gmethod = method;
+            pl.gK = K;
+            pl.gkey = key;
+        }
+        HIPCHK(hipGraphLaunch(pl.gexec, s));
+        return HH_OK;
+    };
+    auto read_ctrl = [&]() -> hh_status {
+        HIPCHK(hipMemcpyAsync(pl.hctrl, pl.ctrl, sizeof(Ctrl) * C.size(), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return HH_OK;
     };
     const int nb = (int)C.size();
     std::vector<ProbDev> hp(nb);
@@ -230,13 +265,15 @@ static hh_status solve_krylov(std::vector<Ctl> &C, Plan &pl, const void *const *
     HIPCHK(hipGetLastError());
     int active = (int)start.size();
     while (active > 0) {
-        iterate();
+        rc = iterate();
+        if (rc != HH_OK) return rc;
         HIPCHK(hipGetLastError());
-        rc = read_states(C, S, s);
+        rc = read_ctrl();
         if (rc != HH_OK) return rc;
         std::vector<int> verify;
         for (int q = 0; q < nb; ++q) {
-            if (C[q].done || S[q].phase != PH_STOP) continue;
+            if (C[q].done || pl.hctrl[q].phase != PH_STOP) continue;
+            S[q].reason = pl.hctrl[q].reason;
             if (S[q].reason == RS_NONFIN) {
                 C[q].done = true;
                 C[q].status = HH_ERR_NONFINITE;
@@ -366,7 +403,19 @@ extern "C" hh_status hh_solve_batch(hh_grid *const *g, int32_t count, const hh_s
         hh_status rc = plan_build(local, G, fp32);
         if (rc != HH_OK) return rc;
     }
-    hh_status rc = solve_krylov(C, *pl, b, x, s, o[0].method);
+    // the solve runs on the plan's own stream (graphs cannot be captured on
+    // the null stream), ordered after the caller's stream by an event
+    if (!pl->stream) HIPCHK(hipStreamCreateWithFlags(&pl->stream, hipStreamNonBlocking));
+    if (!pl->hctrl) HIPCHK(hipHostMalloc((void **)&pl->hctrl, sizeof(Ctrl) * pl->count, 0));
+    {
+        hipEvent_t ev;
+        HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(ev, s));
+        HIPCHK(hipStreamWaitEvent(pl->stream, ev, 0));
+        HIPCHK(hipEventDestroy(ev));
+    }
+    hh_status rc = solve_krylov(C, *pl, b, x, pl->stream, o[0].method);
+    HIPCHK(hipStreamSynchronize(pl->stream));
     if (pl == &local) plan_release(local);
     if (rc != HH_OK) return rc;
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

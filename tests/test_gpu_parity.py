@@ -292,3 +292,33 @@ def test_idr_batch_equals_single(torch_dev, hh_mod):
     for q in range(n):
         assert infos[q].matvecs == xs_single[q][1]
         assert same(host(xs[q]), xs_single[q][0])
+
+
+def test_graph_replay_equals_eager(torch_dev, hh_mod, monkeypatch):
+    """Iterations replayed from a captured graph (K per check) give exactly the
+    eager-launch results, over several solves in a row, for both methods."""
+    torch = torch_dev
+    c = W.c2(n=256, levels=6)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    b = dev(torch, c["b"])
+    P = hh_mod.shadow_to_device(W.shadow_space(g.N, 4, 5))
+    runs = {}
+    for mode in ("eager", "graph4", "graph1", "graph7"):
+        monkeypatch.delenv("HH_NO_GRAPH", raising=False)
+        if mode == "eager":
+            monkeypatch.setenv("HH_NO_GRAPH", "1")
+            monkeypatch.setenv("HH_ITERS_PER_CHECK", "1")
+        else:
+            monkeypatch.setenv("HH_ITERS_PER_CHECK", mode[5:])
+        out = []
+        for rep in range(2):
+            x1, i1 = g.solve(b, tol=1e-8, vcycle_prec="c64")
+            x2, i2 = g.solve(b, tol=1e-8, vcycle_prec="c128", method="idr", s=4, P=P)
+            torch.cuda.synchronize()
+            out.append((host(x1), i1["matvecs"], host(x2), i2["matvecs"]))
+        runs[mode] = out
+    ref = runs["eager"][0]
+    for mode, out in runs.items():
+        for r in out:
+            assert r[1] == ref[1] and r[3] == ref[3], mode
+            assert same(r[0], ref[0]) and same(r[2], ref[2]), mode
