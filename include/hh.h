@@ -186,7 +186,14 @@ typedef struct {
     double t_submit, t_admit, t_done;   /* seconds on the server's monotonic clock */
 } hh_result;
 
+/* Device bytes one request of this description and these options may hold
+ * while it is admitted: its hierarchy, solve work space, b, x, the IDR
+ * shadow space and its share of the launch lists.  An upper bound; the server
+ * admits by it.  HH_ERR_ARG for an invalid description.  Needs no device. */
+hh_status hh_request_footprint(const hh_grid_desc *d, const hh_solve_opts *o, uint64_t *bytes);
+
 typedef struct hh_server hh_server;
+/* Starts the server's worker and preparation threads on `device`. */
 hh_status hh_server_create(const hh_server_opts *o, hh_server **out);
 /* Copies the request and queues it.  HH_ERR_OOM if its device footprint
  * exceeds the whole budget, HH_ERR_ARG for an invalid description. */
@@ -198,7 +205,8 @@ hh_status hh_server_destroy(hh_server *sv);
 
 typedef struct {
     uint64_t submitted, admitted, completed, rejected;
-    uint64_t bytes_in_use, bytes_budget, peak_bytes;
+    uint64_t bytes_in_use, bytes_budget, peak_bytes;   /* admission footprints */
+    uint64_t actual_in_use, peak_actual;                /* bytes the admitted solves hold */
     int32_t active_slots, queued;
 } hh_server_stats;
 hh_status hh_server_query(hh_server *sv, hh_server_stats *st);

@@ -140,6 +140,9 @@ enum VecSel {
 
 // solve phases (first int of every state block)
 enum Phase { PH_RUN = 0, PH_HALF = 1, PH_STOP = 2, PH_IDLE = 3 };
+// what a finaliser pass does with the chunk partials of one problem
+enum FinKind { FIN_BNORM = 0, FIN_INIT, FIN_ALPHA, FIN_S, FIN_OMEGA, FIN_RHO, FIN_TRUE, FIN_NONE,
+               FIN_IDR_OMEGA, FIN_IDR_STEP, FIN_IDR_INIT, FIN_IDR_M };
 // stop reasons
 enum Reason { RS_NONE = 0, RS_CONV = 1, RS_MAXMV = 2, RS_BREAK = 3, RS_NONFIN = 4 };
 

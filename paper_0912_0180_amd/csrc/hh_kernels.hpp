@@ -227,8 +227,6 @@ __device__ inline V2<T> stencil(const VW &h, const S *__restrict__ x, int i, int
 // chunk partials in the fixed pairwise order and advances the scalar state
 // ---------------------------------------------------------------------------
 #define HH_FIN_STAGE 16384
-enum FinKind { FIN_BNORM = 0, FIN_INIT, FIN_ALPHA, FIN_S, FIN_OMEGA, FIN_RHO, FIN_TRUE, FIN_NONE,
-               FIN_IDR_OMEGA, FIN_IDR_STEP, FIN_IDR_INIT, FIN_IDR_M };
 
 __device__ inline bool cfin(double2 v) { return isfinite(v.x) && isfinite(v.y); }
 

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <string>
 #include <vector>
 
 #include "hh_common.h"
@@ -36,6 +37,7 @@ struct Plan {
     int gmethod = -1, gK = 0;
     const void *gkey = nullptr;
     Ctrl *hctrl = nullptr;
+    int hcap = 0;                    // capacity of hctrl (problems)
 };
 
 // Solve work space of one grid.
@@ -80,6 +82,9 @@ struct hh_grid {
 };
 
 hh_status hh_fail(hh_status st, const char *fmt, ...);
+hh_status grid_create(HostSetup &&hs, const hh_grid_desc *d, hh_grid **out);
+hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_t &bytes, std::string &err);
+size_t solve_workspace_bytes(int64_t N, int method, bool fp32, int s, int hist_len);
 void grid_fill_prob(const hh_grid *g, ProbDev &pd);
 hh_status grid_vplan(hh_grid *g, bool fp32);
 void workspace_release(Workspace &w);

@@ -314,7 +314,23 @@ std::vector<char> tail_image(const HostSetup &hs, bool fp32)
 
 hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
 {
+    // a rebuilt plan keeps its stream and pinned control copy (grown below)
+    hipStream_t keep_stream = pl.stream;
+    Ctrl *keep_hctrl = pl.hctrl;
+    int keep_hcap = pl.hcap;
+    pl.stream = nullptr;
+    pl.hctrl = nullptr;
     plan_release(pl);
+    pl.stream = keep_stream;
+    pl.hctrl = keep_hctrl;
+    pl.hcap = keep_hcap;
+    if ((int)G.size() > pl.hcap) {
+        if (pl.hctrl) (void)hipHostFree(pl.hctrl);
+        pl.hctrl = nullptr;
+        pl.hcap = 0;
+        HIPCHK(hipHostMalloc((void **)&pl.hctrl, sizeof(Ctrl) * G.size(), 0));
+        pl.hcap = (int)G.size();
+    }
     pl.count = (int)G.size();
     pl.dim = G.empty() ? 2 : G[0]->hs.dim;
     pl.fp32 = fp32;
@@ -499,6 +515,78 @@ void launch_zero(const Plan &pl, const DevList &tiles, int sel, hipStream_t s)
     LAUNCH(k_zero, tiles.n, s, ctx_of(pl, tiles), sel);
 }
 
+// A grid from a finished host setup: copies the description (not phi) and
+// uploads the hierarchy unless the description asks for a host-only grid.
+hh_status grid_create(HostSetup &&hs, const hh_grid_desc *d, hh_grid **out)
+{
+    *out = nullptr;
+    hh_grid *g = new hh_grid();
+    g->hs = std::move(hs);
+    g->desc = *d;
+    g->desc.phi = nullptr;
+    g->host_only = d->host_only != 0;
+    if (!g->host_only) {
+        hh_status st = grid_upload(g);
+        if (st != HH_OK) {
+            grid_release(g);
+            return st;
+        }
+    }
+    *out = g;
+    return HH_OK;
+}
+
+// Upper bound of the device bytes one problem needs inside a batch: the grid
+// (the arrays grid_upload carves, with the tail images bounded by the LDS
+// capacity), the solve work space, b and x, the IDR shadow space, and its
+// entries in a plan's tile lists and subset lists.
+hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_t &bytes, std::string &err)
+{
+    int nl = 0, nc = 0;
+    hh_status st = desc_check(d, nl, nc, err);
+    if (st != HH_OK) return st;
+    if (!o) {
+        err = "null options";
+        return HH_ERR_ARG;
+    }
+    const int dim = d->dim;
+    HostLevel L[HH_MAXLEV];
+    for (int l = 0; l < nl; ++l) {
+        L[l].N = 1;
+        for (int a = 0; a < 3; ++a) {
+            L[l].n[a] = a < dim ? d->n[a] >> l : 1;
+            L[l].N *= L[l].n[a];
+        }
+    }
+    const int64_t N = L[0].N;
+    const bool fp32 = o->vcycle_prec == HH_C64;
+    const int s = o->method == HH_METHOD_IDR ? o->s : 0;
+    size_t g = 0;
+    for (int a = 0; a < dim; ++a) g += 3 * align256(sizeof(double2) * L[0].n[a]);
+    for (int l = 0; l < nl; ++l) {
+        for (int a = 0; a < dim; ++a) g += 3 * align256(sizeof(double2) * L[l].n[a]) + 3 * align256(sizeof(float2) * L[l].n[a]);
+        g += align256(sizeof(double) * L[l].N) + align256(sizeof(float) * L[l].N);
+        if (l >= 1) g += 2 * align256(sizeof(double2) * L[l].N) + 2 * align256(sizeof(float2) * L[l].N);
+    }
+    g += align256(sizeof(double2) * (size_t)nc * nc) + align256(sizeof(float2) * (size_t)nc * nc);
+    g += align256(TailCap<double>::BYTES) + align256(TailCap<float>::BYTES);
+    g += 2 * align256(sizeof(LevelDev<double>) * HH_MAXLEV) + align256(sizeof(ProbDev));
+    const int nch = ceil_div(N, HH_CHUNK);
+    g += align256(sizeof(Tile) * nch);
+    size_t ws = solve_workspace_bytes(N, o->method, fp32, s, 0);
+    size_t io = 2 * align256(sizeof(double2) * N) + (s > 0 ? align256(sizeof(double2) * (size_t)N * s) : 0);
+    size_t tiles = nch;
+    for (int l = 0; l + 1 < nl; ++l) {
+        int nd, nu;
+        vtile_counts(dim, fp32, L[l], L[l + 1], nd, nu);
+        tiles += nd + nu;
+    }
+    size_t plan = sizeof(Tile) * (tiles + nch) + sizeof(ProbDev) + sizeof(Ctrl) + 2 * sizeof(int) +
+                  256 * (2 * HH_MAXLEV + 8);
+    bytes = g + ws + io + plan;
+    return HH_OK;
+}
+
 // ---------------------------------------------------------------------------
 // C ABI: grids, apply, V-cycle
 // ---------------------------------------------------------------------------
@@ -511,25 +599,11 @@ hh_status hh_setup_grid(const hh_grid_desc *d, hh_grid **out)
 {
     if (!out) return hh_fail(HH_ERR_ARG, "out is null");
     *out = nullptr;
-    hh_grid *g = new hh_grid();
+    HostSetup hs;
     std::string err;
-    hh_status st = host_setup(d, g->hs, err);
-    if (st != HH_OK) {
-        delete g;
-        return hh_fail(st, "%s", err.c_str());
-    }
-    g->desc = *d;
-    g->desc.phi = nullptr;
-    g->host_only = d->host_only != 0;
-    if (!g->host_only) {
-        st = grid_upload(g);
-        if (st != HH_OK) {
-            grid_release(g);
-            return st;
-        }
-    }
-    *out = g;
-    return HH_OK;
+    hh_status st = host_setup(d, hs, err);
+    if (st != HH_OK) return hh_fail(st, "%s", err.c_str());
+    return grid_create(std::move(hs), d, out);
 }
 
 hh_status hh_free_grid(hh_grid *g)

@@ -169,7 +169,7 @@ void host_apply_M(const HostSetup &hs, int lev, const double2 *x, double2 *y)
             }
 }
 
-hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err)
+hh_status desc_check(const hh_grid_desc *d, int &levels, int &coarse, std::string &err)
 {
     char buf[256];
     if (!d) { err = "null grid description"; return HH_ERR_ARG; }
@@ -192,7 +192,7 @@ hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err)
         N *= d->n[a];
     }
     if (N >= ((int64_t)1 << 31)) { err = "more than 2^31 - 1 unknowns"; return HH_ERR_ARG; }
-    int nl = d->levels > 0 ? d->levels : auto_levels(dim, d->n);
+    const int nl = d->levels > 0 ? d->levels : auto_levels(dim, d->n);
     if (nl > HH_MAXLEV) { err = "too many levels"; return HH_ERR_ARG; }
     if (nl < 2) { err = "the multigrid preconditioner needs at least 2 levels (set levels, or use a larger grid)"; return HH_ERR_ARG; }
     for (int a = 0; a < dim; ++a)
@@ -209,6 +209,18 @@ hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err)
         err = buf;
         return HH_ERR_ARG;
     }
+    levels = nl;
+    coarse = (int)Nc;
+    return HH_OK;
+}
+
+hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err)
+{
+    int nl = 0, ncoarse = 0;
+    hh_status st = desc_check(d, nl, ncoarse, err);
+    if (st != HH_OK) return st;
+    const int dim = d->dim;
+    const int64_t Nc = ncoarse;
     hs.dim = dim;
     hs.nlev = nl;
     hs.omega = d->omega;

@@ -23,6 +23,10 @@ struct HostSetup {
     std::vector<double2> Minv;                  // Nc x Nc row major
 };
 
+// Validates a description without building anything: levels (the automatic
+// rule applied) and coarsest unknowns.  phi is not read.
+hh_status desc_check(const hh_grid_desc *d, int &levels, int &coarse, std::string &err);
+
 // Validates the description and fills hs.  Returns HH_OK or HH_ERR_ARG with
 // a message in err.
 hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err);

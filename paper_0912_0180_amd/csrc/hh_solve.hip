@@ -13,7 +13,7 @@
 #include <cstring>
 #include <vector>
 
-#include "hh_lib.h"
+#include "hh_batch.h"
 
 #define HIPCHK(call)                                                                          \
     do {                                                                                      \
@@ -23,13 +23,27 @@
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+static size_t solve_vectors_bytes(int64_t N, int method, bool fp32, int s)
+{
+    const size_t c16 = al256(sizeof(double2) * N), clow = al256((fp32 ? sizeof(float2) : sizeof(double2)) * N);
+    if (method == HH_METHOD_BICGSTAB) return 5 * c16 + 2 * clow;
+    return 4 * c16 + clow + 2 * (size_t)s * c16;
+}
+
+size_t solve_workspace_bytes(int64_t N, int method, bool fp32, int s, int hist_len)
+{
+    const int nch = ceil_div(N, HH_CHUNK);
+    return al256(sizeof(double) * HH_NPART * nch) + al256(sizeof(SolveState)) +
+           al256(sizeof(double) * std::max(hist_len, 1)) + solve_vectors_bytes(N, method, fp32, s);
+}
+
 void workspace_release(Workspace &w)
 {
     if (w.mem) (void)hipFree(w.mem);
     w = Workspace();
 }
 
-static hh_status workspace_ensure(hh_grid *g, int method, bool fp32, int s, int hist_len)
+hh_status workspace_ensure(hh_grid *g, int method, bool fp32, int s, int hist_len)
 {
     Workspace &w = g->ws;
     if (w.mem && w.method == method && w.fp32 == (int)fp32 && w.s >= s && w.hist_cap >= hist_len) return HH_OK;
@@ -37,9 +51,7 @@ static hh_status workspace_ensure(hh_grid *g, int method, bool fp32, int s, int 
     const int64_t N = g->hs.lev[0].N;
     const size_t c16 = al256(sizeof(double2) * N), clow = al256((fp32 ? sizeof(float2) : sizeof(double2)) * N);
     const int nch = ceil_div(N, HH_CHUNK);
-    size_t bytes = al256(sizeof(double) * HH_NPART * nch) + al256(sizeof(SolveState)) + al256(sizeof(double) * std::max(hist_len, 1));
-    if (method == HH_METHOD_BICGSTAB) bytes += 5 * c16 + 2 * clow;
-    else bytes += 4 * c16 + clow + 2 * (size_t)s * c16;
+    const size_t bytes = solve_workspace_bytes(N, method, fp32, s, hist_len);
     hipError_t e = hipMalloc(&w.mem, bytes);
     if (e != hipSuccess) {
         w.mem = nullptr;
@@ -100,255 +112,333 @@ static void fill_solve_prob(hh_grid *g, const hh_solve_opts *o, const void *b, v
     pd.nidr = o->method == HH_METHOD_IDR ? o->s : 0;
 }
 
-namespace {
-
-struct Ctl {
-    hh_grid *g;
-    const hh_solve_opts *o;
-    hh_solve_info *info;
-    int status = HH_OK;
-    bool done = false;
-    int restarts = 0;
-    int chunk0 = 0, nchunk = 0;   // range of the problem in the plan's chunk list
-};
-
-// device scratch for tile lists of subsets of the batch
-struct Subset {
-    Tile *t = nullptr;
-    int *p = nullptr;
-    void *mem = nullptr;
-    std::vector<Tile> ht;
-    std::vector<int> hp;
-    ~Subset() { if (mem) (void)hipFree(mem); }
-    hh_status alloc(int nchunks, int nprob)
-    {
-        size_t b = al256(sizeof(Tile) * nchunks) + al256(sizeof(int) * nprob);
-        if (hipMalloc(&mem, b) != hipSuccess) return hh_fail(HH_ERR_OOM, "hipMalloc for subset lists");
-        t = (Tile *)mem;
-        p = (int *)((char *)mem + al256(sizeof(Tile) * nchunks));
-        return HH_OK;
-    }
-    hh_status set(const std::vector<Ctl> &C, const std::vector<int> &which, hipStream_t s)
-    {
-        ht.clear();
-        hp.clear();
-        for (int q : which) {
-            for (int i = 0; i < C[q].nchunk; ++i) ht.push_back(Tile{q, i});
-            hp.push_back(q);
-        }
-        if (!ht.empty()) HIPCHK(hipMemcpyAsync(t, ht.data(), sizeof(Tile) * ht.size(), hipMemcpyHostToDevice, s));
-        if (!hp.empty()) HIPCHK(hipMemcpyAsync(p, hp.data(), sizeof(int) * hp.size(), hipMemcpyHostToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
-        return HH_OK;
-    }
-    DevList list() const { DevList d; d.t = t; d.n = (int)ht.size(); return d; }
-};
-
-hh_status read_states(const std::vector<Ctl> &C, std::vector<SolveState> &S, hipStream_t s)
+// ---------------------------------------------------------------------------
+// KBatch
+// ---------------------------------------------------------------------------
+KBatch::KBatch(int method, bool fp32, Plan *external) : method_(method), fp32_(fp32), pl_(external ? external : &own_)
 {
-    for (size_t q = 0; q < C.size(); ++q)
-        HIPCHK(hipMemcpyAsync(&S[q], C[q].g->ws.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+    const char *ek = getenv("HH_ITERS_PER_CHECK");
+    K_ = ek ? std::max(1, atoi(ek)) : 4;
+    graph_ = !getenv("HH_NO_GRAPH");
+}
+
+KBatch::~KBatch()
+{
+    if (sub_mem_) (void)hipFree(sub_mem_);
+    plan_release(own_);
+}
+
+int KBatch::running() const
+{
+    int n = 0;
+    for (const KProb *p : P_) n += !p->done;
+    return n;
+}
+
+hh_status KBatch::set(const std::vector<KProb *> &probs)
+{
+    // current control blocks of problems carried over
+    std::vector<Ctrl> old(P_.size());
+    if (!P_.empty() && pl_->ctrl && pl_->stream) {
+        HIPCHK(hipMemcpyAsync(old.data(), pl_->ctrl, sizeof(Ctrl) * P_.size(), hipMemcpyDeviceToHost, pl_->stream));
+        HIPCHK(hipStreamSynchronize(pl_->stream));
+    }
+    // carried-over problems are recognised by serial (a freed problem's
+    // address may have been reused by a new one)
+    std::vector<Ctrl> hc(probs.size());
+    for (size_t q = 0; q < probs.size(); ++q) {
+        memset(&hc[q], 0, sizeof(Ctrl));
+        hc[q].phase = PH_IDLE;
+        if (probs[q]->serial == 0) continue;
+        for (size_t r = 0; r < ids_.size(); ++r)
+            if (ids_[r] == probs[q]->serial) hc[q] = old[r];
+    }
+    if (pl_ == &own_) {
+        std::vector<const hh_grid *> G;
+        for (KProb *p : probs) G.push_back(p->g);
+        hh_status rc = plan_build(own_, G, fp32_);
+        if (rc != HH_OK) return rc;
+    } else if (pl_->count != (int)probs.size()) {
+        return hh_fail(HH_ERR_ARG, "external plan does not match the problem set");
+    }
+    P_ = probs;
+    ids_.resize(P_.size());
+    for (size_t q = 0; q < P_.size(); ++q) {
+        if (P_[q]->serial == 0) P_[q]->serial = next_serial_++;
+        ids_[q] = P_[q]->serial;
+    }
+    if (!pl_->stream) HIPCHK(hipStreamCreateWithFlags(&pl_->stream, hipStreamNonBlocking));
+    if (!pl_->hctrl || pl_->hcap < (int)probs.size()) {
+        if (pl_->hctrl) (void)hipHostFree(pl_->hctrl);
+        pl_->hctrl = nullptr;
+        pl_->hcap = 0;
+        HIPCHK(hipHostMalloc((void **)&pl_->hctrl, sizeof(Ctrl) * std::max<size_t>(probs.size(), 1), 0));
+        pl_->hcap = (int)std::max<size_t>(probs.size(), 1);
+    }
+    const int nb = (int)P_.size();
+    std::vector<ProbDev> hp(nb);
+    int total_chunks = 0;
+    for (int q = 0; q < nb; ++q) {
+        fill_solve_prob(P_[q]->g, &P_[q]->o, P_[q]->b, P_[q]->x, hp[q]);
+        hp[q].ctrl = pl_->ctrl + q;
+        total_chunks += hp[q].nchunk;
+    }
+    pl_->host = hp;
+    hipStream_t s = pl_->stream;
+    if (nb > 0) {
+        HIPCHK(hipMemcpyAsync(pl_->probs, hp.data(), sizeof(ProbDev) * nb, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(pl_->ctrl, hc.data(), sizeof(Ctrl) * nb, hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    const size_t need = al256(sizeof(Tile) * std::max(total_chunks, 1)) + al256(sizeof(int) * std::max(nb, 1));
+    if (need > sub_bytes_) {
+        if (sub_mem_) (void)hipFree(sub_mem_);
+        sub_mem_ = nullptr;
+        sub_bytes_ = 0;
+        hipError_t e = hipMalloc(&sub_mem_, need);
+        if (e != hipSuccess) {
+            sub_mem_ = nullptr;
+            return hh_fail(HH_ERR_OOM, "hipMalloc(%zu) for subset lists: %s", need, hipGetErrorString(e));
+        }
+        sub_bytes_ = need;
+    }
+    sub_t_ = (Tile *)sub_mem_;
+    sub_p_ = (int *)((char *)sub_mem_ + al256(sizeof(Tile) * std::max(total_chunks, 1)));
+    return HH_OK;
+}
+
+hh_status KBatch::sub_set(const std::vector<int> &which)
+{
+    ht_.clear();
+    hp_.clear();
+    for (int q : which) {
+        const int nch = pl_->host[q].nchunk;
+        for (int i = 0; i < nch; ++i) ht_.push_back(Tile{q, i});
+        hp_.push_back(q);
+    }
+    hipStream_t s = pl_->stream;
+    if (!ht_.empty()) HIPCHK(hipMemcpyAsync(sub_t_, ht_.data(), sizeof(Tile) * ht_.size(), hipMemcpyHostToDevice, s));
+    if (!hp_.empty()) HIPCHK(hipMemcpyAsync(sub_p_, hp_.data(), sizeof(int) * hp_.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     return HH_OK;
 }
 
-} // namespace
-
-// Bi-CGSTAB and IDR(s) share the driver: start (r = b - H x and the method's
-// initial scalars), iterations of the method's passes, true-residual checks
-// and restarts.
-static hh_status solve_krylov(std::vector<Ctl> &C, Plan &pl, const void *const *b, void *const *x, hipStream_t s,
-                              int method)
+hh_status KBatch::read_states(const std::vector<int> &which)
 {
-    const int init_mode = method == HH_METHOD_BICGSTAB ? 0 : 2;
-    const int init_fin = method == HH_METHOD_BICGSTAB ? 1 /*FIN_INIT*/ : 10 /*FIN_IDR_INIT*/;
-    auto iterate1 = [&]() {
-        if (method == HH_METHOD_BICGSTAB) launch_bicg_iteration(pl, s);
-        else launch_idr_step(pl, s);
-    };
-    // K iterations per check of the control blocks, replayed from a graph
-    const char *ek = getenv("HH_ITERS_PER_CHECK");
-    const int K = ek ? std::max(1, atoi(ek)) : 4;
-    const bool use_graph = !getenv("HH_NO_GRAPH");
-    const void *key = C[0].g->ws.mem;
-    auto iterate = [&]() -> hh_status {
-        if (!use_graph) {
-            for (int k = 0; k < K; ++k) iterate1();
-            return HH_OK;
-        }
-        if (!pl.gexec || pl.gmethod != method || pl.gK != K || pl.gkey != key) {
-            if (pl.gexec) {
-                HIPCHK(hipGraphExecDestroy(pl.gexec));
-                pl.gexec = nullptr;
-            }
-            hipGraph_t graph;
-            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < K; ++k) iterate1();
-            HIPCHK(hipStreamEndCapture(s, &graph));
-            hipError_t e = hipGraphInstantiate(&pl.gexec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (e != hipSuccess) return hh_fail(HH_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-            pl.gmethod = method;
-            pl.gK = K;
-            pl.gkey = key;
-        }
-        HIPCHK(hipGraphLaunch(pl.gexec, s));
-        return HH_OK;
-    };
-    auto read_ctrl = [&]() -> hh_status {
-        HIPCHK(hipMemcpyAsync(pl.hctrl, pl.ctrl, sizeof(Ctrl) * C.size(), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        return HH_OK;
-    };
-    const int nb = (int)C.size();
-    std::vector<ProbDev> hp(nb);
-    std::vector<Ctrl> hc(nb);
-    for (int q = 0; q < nb; ++q) {
-        fill_solve_prob(C[q].g, C[q].o, b[q], x[q], hp[q]);
-        hp[q].ctrl = pl.ctrl + q;
-        memset(&hc[q], 0, sizeof(Ctrl));
-        hc[q].phase = PH_IDLE;
-    }
-    pl.host = hp;
-    HIPCHK(hipMemcpyAsync(pl.probs, hp.data(), sizeof(ProbDev) * nb, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(pl.ctrl, hc.data(), sizeof(Ctrl) * nb, hipMemcpyHostToDevice, s));
-    int total_chunks = 0;
-    for (int q = 0; q < nb; ++q) {
-        C[q].chunk0 = total_chunks;
-        C[q].nchunk = ceil_div(C[q].g->hs.lev[0].N, HH_CHUNK);
-        total_chunks += C[q].nchunk;
+    hipStream_t s = pl_->stream;
+    for (int q : which)
+        HIPCHK(hipMemcpyAsync(&P_[q]->S, P_[q]->g->ws.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HH_OK;
+}
+
+hh_status KBatch::start(const std::vector<KProb *> &probs)
+{
+    const int init_mode = method_ == HH_METHOD_BICGSTAB ? 0 : 2;
+    const int init_fin = method_ == HH_METHOD_BICGSTAB ? FIN_INIT : FIN_IDR_INIT;
+    hipStream_t s = pl_->stream;
+    std::vector<int> idx;
+    for (KProb *p : probs) {
+        int q = -1;
+        for (size_t r = 0; r < P_.size(); ++r)
+            if (P_[r] == p) q = (int)r;
+        if (q < 0) return hh_fail(HH_ERR_ARG, "start: problem not in the set");
+        idx.push_back(q);
         SolveState st;
         memset(&st, 0, sizeof st);
         st.phase = PH_IDLE;
-        st.tol = C[q].o->tol;
-        st.max_mv = C[q].o->max_matvec;
-        st.hist_len = C[q].o->history ? C[q].o->history_len : 0;
-        st.s = method == HH_METHOD_IDR ? C[q].o->s : 0;
+        st.tol = p->o.tol;
+        st.max_mv = p->o.max_matvec;
+        st.hist_len = p->o.history ? p->o.history_len : 0;
+        st.s = method_ == HH_METHOD_IDR ? p->o.s : 0;
         st.startup = -1;
-        HIPCHK(hipMemcpyAsync(C[q].g->ws.st, &st, sizeof st, hipMemcpyHostToDevice, s));
+        p->S = st;
+        p->done = p->closed = false;
+        p->status = HH_OK;
+        p->restarts = 0;
+        HIPCHK(hipMemcpyAsync(p->g->ws.st, &p->S, sizeof st, hipMemcpyHostToDevice, s));
     }
-    Subset sub;
-    hh_status rc = sub.alloc(total_chunks, nb);
+    if (idx.empty()) return HH_OK;
+    hh_status rc = sub_set(idx);
     if (rc != HH_OK) return rc;
-    std::vector<SolveState> S(nb);
-    // ||b||
-    launch_norm(pl, pl.chunks, VS_B, s);
-    launch_fin(pl, pl.fin, pl.nfin, 0 /*FIN_BNORM*/, s);
+    DevList dl{sub_t_, (int)ht_.size()};
+    launch_norm(*pl_, dl, VS_B, s);
+    launch_fin(*pl_, sub_p_, (int)idx.size(), FIN_BNORM, s);
     HIPCHK(hipGetLastError());
-    rc = read_states(C, S, s);
+    rc = read_states(idx);
     if (rc != HH_OK) return rc;
-    std::vector<int> zero_x, start;
-    for (int q = 0; q < nb; ++q) {
-        if (!C[q].o->x0_given) zero_x.push_back(q);
-        if (!std::isfinite(S[q].bnorm)) {
-            C[q].done = true;
-            C[q].status = HH_ERR_NONFINITE;
-        } else if (S[q].bnorm == 0.0) {
-            C[q].done = true;
-            C[q].status = HH_OK;
-            if (C[q].o->x0_given) zero_x.push_back(q);
+    std::vector<int> zero_x, go;
+    for (int q : idx) {
+        KProb *p = P_[q];
+        if (!p->o.x0_given) zero_x.push_back(q);
+        if (!std::isfinite(p->S.bnorm)) {
+            p->done = true;
+            p->status = HH_ERR_NONFINITE;
+        } else if (p->S.bnorm == 0.0) {
+            p->done = true;
+            p->status = HH_OK;
+            if (p->o.x0_given) zero_x.push_back(q);
         } else {
-            start.push_back(q);
+            go.push_back(q);
         }
     }
     if (!zero_x.empty()) {
-        rc = sub.set(C, zero_x, s);
+        rc = sub_set(zero_x);
         if (rc != HH_OK) return rc;
-        launch_zero(pl, sub.list(), VS_X, s);
+        launch_zero(*pl_, DevList{sub_t_, (int)ht_.size()}, VS_X, s);
     }
-    if (!start.empty()) {
-        rc = sub.set(C, start, s);
+    if (!go.empty()) {
+        rc = sub_set(go);
         if (rc != HH_OK) return rc;
-        launch_resid(pl, sub.list(), init_mode, s);
-        launch_fin(pl, sub.p, (int)start.size(), init_fin, s);
+        launch_resid(*pl_, DevList{sub_t_, (int)ht_.size()}, init_mode, s);
+        launch_fin(*pl_, sub_p_, (int)go.size(), init_fin, s);
     }
     HIPCHK(hipGetLastError());
-    int active = (int)start.size();
-    while (active > 0) {
-        rc = iterate();
-        if (rc != HH_OK) return rc;
+    return HH_OK;
+}
+
+hh_status KBatch::launch()
+{
+    if (running() == 0) return HH_OK;
+    hipStream_t s = pl_->stream;
+    auto iterate1 = [&]() {
+        if (method_ == HH_METHOD_BICGSTAB) launch_bicg_iteration(*pl_, s);
+        else launch_idr_step(*pl_, s);
+    };
+    if (!graph_) {
+        for (int k = 0; k < K_; ++k) iterate1();
         HIPCHK(hipGetLastError());
-        rc = read_ctrl();
-        if (rc != HH_OK) return rc;
-        std::vector<int> verify;
-        for (int q = 0; q < nb; ++q) {
-            if (C[q].done || pl.hctrl[q].phase != PH_STOP) continue;
-            S[q].reason = pl.hctrl[q].reason;
-            if (S[q].reason == RS_NONFIN) {
-                C[q].done = true;
-                C[q].status = HH_ERR_NONFINITE;
-                --active;
-            } else if (S[q].reason == RS_MAXMV) {
-                C[q].done = true;
-                C[q].status = HH_ERR_NOCONV;
-                --active;
-            } else {
-                verify.push_back(q);
-            }
-        }
-        if (verify.empty()) continue;
-        rc = sub.set(C, verify, s);
-        if (rc != HH_OK) return rc;
-        launch_resid(pl, sub.list(), 1, s);
-        launch_fin(pl, sub.p, (int)verify.size(), 6 /*FIN_TRUE*/, s);
-        HIPCHK(hipGetLastError());
-        rc = read_states(C, S, s);
-        if (rc != HH_OK) return rc;
-        std::vector<int> restart;
-        for (int q : verify) {
-            if (S[q].reason == RS_CONV && S[q].true_rel < C[q].o->tol) {
-                C[q].done = true;
-                C[q].status = HH_OK;
-                --active;
-            } else if (C[q].restarts >= C[q].o->max_restarts) {
-                C[q].done = true;
-                C[q].status = S[q].reason == RS_BREAK ? HH_ERR_BREAKDOWN : HH_ERR_NOCONV;
-                --active;
-            } else {
-                C[q].restarts++;
-                restart.push_back(q);
-            }
-        }
-        if (!restart.empty()) {
-            rc = sub.set(C, restart, s);
-            if (rc != HH_OK) return rc;
-            launch_resid(pl, sub.list(), init_mode, s);
-            launch_fin(pl, sub.p, (int)restart.size(), init_fin, s);
-            HIPCHK(hipGetLastError());
-        }
+        return HH_OK;
     }
-    // final true residual of every finished problem with finite data
+    // the graph bakes in the plan's lists and, for one-problem plans, the
+    // work-space vectors the V-cycle reads and writes
+    const void *key = P_.empty() ? nullptr : P_[0]->g->ws.mem;
+    if (!pl_->gexec || pl_->gmethod != method_ || pl_->gK != K_ || pl_->gkey != key) {
+        if (pl_->gexec) {
+            HIPCHK(hipGraphExecDestroy(pl_->gexec));
+            pl_->gexec = nullptr;
+        }
+        hipGraph_t graph;
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < K_; ++k) iterate1();
+        HIPCHK(hipStreamEndCapture(s, &graph));
+        hipError_t e = hipGraphInstantiate(&pl_->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            pl_->gexec = nullptr;
+            return hh_fail(HH_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+        pl_->gmethod = method_;
+        pl_->gK = K_;
+        pl_->gkey = key;
+    }
+    HIPCHK(hipGraphLaunch(pl_->gexec, s));
+    return HH_OK;
+}
+
+hh_status KBatch::close(const std::vector<int> &which, std::vector<KProb *> &closed)
+{
+    if (which.empty()) return HH_OK;
+    hipStream_t s = pl_->stream;
     std::vector<int> fin;
-    for (int q = 0; q < nb; ++q)
-        if (C[q].status != HH_ERR_NONFINITE && S[q].bnorm > 0.0) fin.push_back(q);
+    for (int q : which)
+        if (P_[q]->status != HH_ERR_NONFINITE && P_[q]->S.bnorm > 0.0) fin.push_back(q);
     if (!fin.empty()) {
-        rc = sub.set(C, fin, s);
+        hh_status rc = sub_set(fin);
         if (rc != HH_OK) return rc;
-        launch_resid(pl, sub.list(), 1, s);
-        launch_fin(pl, sub.p, (int)fin.size(), 6 /*FIN_TRUE*/, s);
+        launch_resid(*pl_, DevList{sub_t_, (int)ht_.size()}, 1, s);
+        launch_fin(*pl_, sub_p_, (int)fin.size(), FIN_TRUE, s);
         HIPCHK(hipGetLastError());
     }
-    rc = read_states(C, S, s);
+    hh_status rc = read_states(which);
     if (rc != HH_OK) return rc;
-    for (int q = 0; q < nb; ++q) {
-        hh_solve_info &in = *C[q].info;
-        in.status = C[q].status;
-        in.matvecs = S[q].mv;
-        in.iterations = S[q].it;
-        in.restarts = C[q].restarts;
-        in.rel_res_recurrence = S[q].bnorm > 0.0 ? S[q].rel : 0.0;
-        in.rel_res_true = S[q].bnorm > 0.0 ? S[q].true_rel : 0.0;
-        if (C[q].status == HH_ERR_NONFINITE) in.rel_res_true = NAN;
-        const hh_solve_opts *o = C[q].o;
-        if (o->history && o->history_len > 0) {
-            int n = std::min(S[q].mv, o->history_len);
-            if (n > 0) HIPCHK(hipMemcpy(o->history, C[q].g->ws.hist, sizeof(double) * n, hipMemcpyDeviceToHost));
+    for (int q : which) {
+        KProb *p = P_[q];
+        const SolveState &S = p->S;
+        hh_solve_info &in = p->info;
+        memset(&in, 0, sizeof in);
+        in.status = p->status;
+        in.matvecs = S.mv;
+        in.iterations = S.it;
+        in.restarts = p->restarts;
+        in.rel_res_recurrence = S.bnorm > 0.0 ? S.rel : 0.0;
+        in.rel_res_true = S.bnorm > 0.0 ? S.true_rel : 0.0;
+        if (p->status == HH_ERR_NONFINITE) in.rel_res_true = NAN;
+        if (p->o.history && p->o.history_len > 0) {
+            int n = std::min(S.mv, p->o.history_len);
+            if (n > 0) {
+                HIPCHK(hipMemcpyAsync(p->o.history, p->g->ws.hist, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+            }
         }
+        p->closed = true;
+        closed.push_back(p);
     }
     return HH_OK;
 }
 
-static hh_status check_opts(const hh_grid *g, const hh_solve_opts *o)
+hh_status KBatch::collect(std::vector<KProb *> &closed)
+{
+    const int init_mode = method_ == HH_METHOD_BICGSTAB ? 0 : 2;
+    const int init_fin = method_ == HH_METHOD_BICGSTAB ? FIN_INIT : FIN_IDR_INIT;
+    hipStream_t s = pl_->stream;
+    const int nb = (int)P_.size();
+    if (running() > 0) {
+        HIPCHK(hipMemcpyAsync(pl_->hctrl, pl_->ctrl, sizeof(Ctrl) * nb, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<int> verify;
+        for (int q = 0; q < nb; ++q) {
+            KProb *p = P_[q];
+            if (p->done || pl_->hctrl[q].phase != PH_STOP) continue;
+            const int reason = pl_->hctrl[q].reason;
+            if (reason == RS_NONFIN) {
+                p->done = true;
+                p->status = HH_ERR_NONFINITE;
+            } else if (reason == RS_MAXMV) {
+                p->done = true;
+                p->status = HH_ERR_NOCONV;
+            } else {
+                verify.push_back(q);
+            }
+        }
+        if (!verify.empty()) {
+            hh_status rc = sub_set(verify);
+            if (rc != HH_OK) return rc;
+            launch_resid(*pl_, DevList{sub_t_, (int)ht_.size()}, 1, s);
+            launch_fin(*pl_, sub_p_, (int)verify.size(), FIN_TRUE, s);
+            HIPCHK(hipGetLastError());
+            rc = read_states(verify);
+            if (rc != HH_OK) return rc;
+            std::vector<int> restart;
+            for (int q : verify) {
+                KProb *p = P_[q];
+                if (p->S.reason == RS_CONV && p->S.true_rel < p->o.tol) {
+                    p->done = true;
+                    p->status = HH_OK;
+                } else if (p->restarts >= p->o.max_restarts) {
+                    p->done = true;
+                    p->status = p->S.reason == RS_BREAK ? HH_ERR_BREAKDOWN : HH_ERR_NOCONV;
+                } else {
+                    p->restarts++;
+                    restart.push_back(q);
+                }
+            }
+            if (!restart.empty()) {
+                rc = sub_set(restart);
+                if (rc != HH_OK) return rc;
+                launch_resid(*pl_, DevList{sub_t_, (int)ht_.size()}, init_mode, s);
+                launch_fin(*pl_, sub_p_, (int)restart.size(), init_fin, s);
+                HIPCHK(hipGetLastError());
+            }
+        }
+    }
+    std::vector<int> to_close;
+    for (int q = 0; q < nb; ++q)
+        if (P_[q]->done && !P_[q]->closed) to_close.push_back(q);
+    return close(to_close, closed);
+}
+
+hh_status check_solve_opts(const hh_grid *g, const hh_solve_opts *o)
 {
     if (!o) return hh_fail(HH_ERR_ARG, "null options");
     if (o->method != HH_METHOD_BICGSTAB && o->method != HH_METHOD_IDR) return hh_fail(HH_ERR_ARG, "unknown method %d", o->method);
@@ -367,19 +457,22 @@ extern "C" hh_status hh_solve_batch(hh_grid *const *g, int32_t count, const hh_s
     auto t0 = std::chrono::steady_clock::now();
     if (!g || !o || !b || !x || !info || count < 1) return hh_fail(HH_ERR_ARG, "null argument or empty batch");
     hipStream_t s = (hipStream_t)stream;
-    std::vector<Ctl> C(count);
+    std::vector<KProb> K(count);
+    std::vector<KProb *> ptrs(count);
     for (int q = 0; q < count; ++q) {
         if (!g[q] || !b[q] || !x[q]) return hh_fail(HH_ERR_ARG, "problem %d: null grid or vector", q);
-        hh_status rc = check_opts(g[q], &o[q]);
+        hh_status rc = check_solve_opts(g[q], &o[q]);
         if (rc != HH_OK) return rc;
         if (o[q].method != o[0].method || o[q].vcycle_prec != o[0].vcycle_prec)
             return hh_fail(HH_ERR_ARG, "all problems of a batch need the same method and V-cycle precision");
         if (g[q]->hs.dim != g[0]->hs.dim) return hh_fail(HH_ERR_ARG, "all problems of a batch need the same dimension");
         for (int r = 0; r < q; ++r)
             if (g[r] == g[q]) return hh_fail(HH_ERR_ARG, "grid used twice in one batch");
-        C[q].g = g[q];
-        C[q].o = &o[q];
-        C[q].info = &info[q];
+        K[q].g = g[q];
+        K[q].o = o[q];
+        K[q].b = b[q];
+        K[q].x = x[q];
+        ptrs[q] = &K[q];
         memset(&info[q], 0, sizeof(hh_solve_info));
     }
     const bool fp32 = o[0].vcycle_prec == HH_C64;
@@ -388,8 +481,8 @@ extern "C" hh_status hh_solve_batch(hh_grid *const *g, int32_t count, const hh_s
                                         o[q].history ? o[q].history_len : 0);
         if (rc != HH_OK) return rc;
     }
-    Plan local;
-    Plan *pl = &local;
+    // a single problem keeps its plan (and captured graph) in the grid
+    Plan *ext = nullptr;
     if (count == 1) {
         if (g[0]->plan_fp32 != (int)fp32 || !g[0]->plan.mem) {
             std::vector<const hh_grid *> G{g[0]};
@@ -397,30 +490,32 @@ extern "C" hh_status hh_solve_batch(hh_grid *const *g, int32_t count, const hh_s
             if (rc != HH_OK) return rc;
             g[0]->plan_fp32 = fp32;
         }
-        pl = &g[0]->plan;
-    } else {
-        std::vector<const hh_grid *> G(g, g + count);
-        hh_status rc = plan_build(local, G, fp32);
-        if (rc != HH_OK) return rc;
+        ext = &g[0]->plan;
     }
+    KBatch kb(o[0].method, fp32, ext);
+    hh_status rc = kb.set(ptrs);
+    if (rc != HH_OK) return rc;
     // the solve runs on the plan's own stream (graphs cannot be captured on
     // the null stream), ordered after the caller's stream by an event
-    if (!pl->stream) HIPCHK(hipStreamCreateWithFlags(&pl->stream, hipStreamNonBlocking));
-    if (!pl->hctrl) HIPCHK(hipHostMalloc((void **)&pl->hctrl, sizeof(Ctrl) * pl->count, 0));
     {
         hipEvent_t ev;
         HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         HIPCHK(hipEventRecord(ev, s));
-        HIPCHK(hipStreamWaitEvent(pl->stream, ev, 0));
+        HIPCHK(hipStreamWaitEvent(kb.stream(), ev, 0));
         HIPCHK(hipEventDestroy(ev));
     }
-    hh_status rc = solve_krylov(C, *pl, b, x, pl->stream, o[0].method);
-    HIPCHK(hipStreamSynchronize(pl->stream));
-    if (pl == &local) plan_release(local);
+    rc = kb.start(ptrs);
+    std::vector<KProb *> closed;
+    while (rc == HH_OK && (int)closed.size() < count) {
+        rc = kb.launch();
+        if (rc == HH_OK) rc = kb.collect(closed);
+    }
+    HIPCHK(hipStreamSynchronize(kb.stream()));
     if (rc != HH_OK) return rc;
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     hh_status first = HH_OK;
     for (int q = 0; q < count; ++q) {
+        info[q] = K[q].info;
         info[q].seconds = secs;
         if (first == HH_OK && info[q].status != HH_OK) first = (hh_status)info[q].status;
     }

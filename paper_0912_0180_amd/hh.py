@@ -24,7 +24,7 @@ BICGSTAB, IDR = 0, 1
 # every symbol include/hh.h declares
 EXPORTS = ["hh_setup_grid", "hh_free_grid", "hh_grid_query", "hh_grid_export", "hh_apply_operator", "hh_vcycle",
            "hh_solve", "hh_solve_batch", "hh_server_create", "hh_submit", "hh_poll", "hh_server_destroy",
-           "hh_server_query", "hh_last_error", "hh_version"]
+           "hh_server_query", "hh_request_footprint", "hh_last_error", "hh_version"]
 
 
 class HHError(RuntimeError):
@@ -80,7 +80,11 @@ class Result(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("rejected", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64), ("bytes_budget", ctypes.c_uint64),
-                ("peak_bytes", ctypes.c_uint64), ("active_slots", ctypes.c_int32), ("queued", ctypes.c_int32)]
+                ("peak_bytes", ctypes.c_uint64), ("actual_in_use", ctypes.c_uint64), ("peak_actual", ctypes.c_uint64),
+                ("active_slots", ctypes.c_int32), ("queued", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -108,11 +112,12 @@ def lib():
         L.hh_poll.argtypes = [V, ctypes.c_uint64, P(Result)]
         L.hh_server_destroy.argtypes = [V]
         L.hh_server_query.argtypes = [V, P(ServerStats)]
+        L.hh_request_footprint.argtypes = [P(GridDesc), P(SolveOpts), P(ctypes.c_uint64)]
         L.hh_last_error.restype = ctypes.c_char_p
         L.hh_version.restype = ctypes.c_char_p
         for name in ["hh_setup_grid", "hh_free_grid", "hh_grid_query", "hh_grid_export", "hh_apply_operator",
                      "hh_vcycle", "hh_solve", "hh_solve_batch", "hh_server_create", "hh_submit", "hh_poll",
-                     "hh_server_destroy", "hh_server_query"]:
+                     "hh_server_destroy", "hh_server_query", "hh_request_footprint"]:
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -315,3 +320,95 @@ def shadow_to_device(P, device="cuda"):
     torch = _torch()
     Pf = np.asfortranarray(P)
     return torch.from_numpy(Pf.reshape(-1, order="F").copy()).to(device)
+
+
+def request_footprint(desc, **kw):
+    """Device bytes the server reserves for one request (hh_request_footprint)."""
+    d, _ = make_desc(desc)
+    o = SolveOpts()
+    o.method = BICGSTAB if kw.get("method", "bicgstab") == "bicgstab" else IDR
+    o.s = int(kw.get("s", 4))
+    o.tol = float(kw.get("tol", 1e-8))
+    o.max_matvec = int(kw.get("max_matvec", 20000))
+    o.max_restarts = int(kw.get("max_restarts", 3))
+    o.vcycle_prec = C128 if kw.get("vcycle_prec", "c128") == "c128" else C64
+    out = ctypes.c_uint64()
+    check(lib().hh_request_footprint(ctypes.byref(d), ctypes.byref(o), ctypes.byref(out)))
+    return int(out.value)
+
+
+class Server:
+    """Continuous-batching request server (hh_server_*).  Requests carry host
+    arrays; results come back as host arrays."""
+
+    def __init__(self, budget=0, max_slots=64, device=0):
+        o = ServerOpts()
+        o.hbm_budget_bytes = int(budget)
+        o.max_slots = int(max_slots)
+        o.device = int(device)
+        self.h = ctypes.c_void_p()
+        check(lib().hh_server_create(ctypes.byref(o), ctypes.byref(self.h)))
+        self._keep = {}
+
+    def submit(self, desc, b, phi=None, P=None, method="bicgstab", tol=1e-8, max_matvec=20000, max_restarts=3,
+               vcycle_prec="c64", s=4):
+        """Queues one solve; b (and P, N x s, for IDR) are complex128 host arrays
+        in the grid's layout.  Returns the ticket."""
+        r = Request()
+        grid, phi_keep = make_desc(desc, phi=phi)
+        r.grid = grid
+        keep = {"phi": phi_keep}
+        o = SolveOpts()
+        o.method = BICGSTAB if method == "bicgstab" else IDR
+        o.s = int(s)
+        o.tol = float(tol)
+        o.max_matvec = int(max_matvec)
+        o.max_restarts = int(max_restarts)
+        o.vcycle_prec = C128 if vcycle_prec == "c128" else C64
+        r.opts = o
+        bb = np.ascontiguousarray(np.asarray(b, dtype=np.complex128).reshape(-1))
+        x = np.zeros_like(bb)
+        r.b_host = bb.ctypes.data
+        r.x_host = x.ctypes.data
+        if o.method == IDR:
+            if P is None:
+                raise ValueError("IDR(s) needs the shadow space P")
+            Pf = np.asfortranarray(np.asarray(P, dtype=np.complex128))
+            Pflat = Pf.reshape(-1, order="F").copy()
+            keep["P"] = Pflat
+            r.idr_P_host = Pflat.ctypes.data
+        keep["b"] = bb
+        t = ctypes.c_uint64()
+        # the library copies b, P and phi before hh_submit returns
+        check(lib().hh_submit(self.h, ctypes.byref(r), ctypes.byref(t)))
+        del keep
+        self._keep[t.value] = x
+        return int(t.value)
+
+    def poll(self, ticket):
+        """None while pending, else (x, result dict)."""
+        res = Result()
+        st = check(lib().hh_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(res)), allow=(OK, PENDING))
+        if st == PENDING:
+            return None
+        x = self._keep.pop(ticket)
+        out = res.info.as_dict()
+        out.update(t_submit=res.t_submit, t_admit=res.t_admit, t_done=res.t_done)
+        return x, out
+
+    def stats(self):
+        st = ServerStats()
+        check(lib().hh_server_query(self.h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self.h:
+            lib().hh_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
