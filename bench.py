@@ -1,17 +1,20 @@
-"""Benchmark: CSG-multigrid-preconditioned Bi-CGSTAB on the ECS Helmholtz
-problem, on one MI355X.
+"""Benchmark: CSG-multigrid-preconditioned Krylov solves of the ECS Helmholtz
+problem on one MI355X.
 
-Workload (one step = one whole solve, x0 = 0 -> ||b - Hx|| / ||b|| < 1e-8):
+Headline workload (one step = one whole solve, x0 = 0 -> ||b - Hx||/||b|| < 1e-8):
 2D 1024 x 1024 cells over [-0.25, 1.25]^2 (interior [0,1]^2, ECS layers of
 width 0.25 at angle pi/6), k0 at 10 points per wavelength,
 k(x) = k0 (1 + 0.3 * sum of 8 seeded Gaussian bumps of width 0.05), unit point
 source at the centre, CSG angle pi/8, 8 levels, one V(1,1) cycle per
-preconditioner application.  The headline value is solves/s of the
-mixed-precision solve (complex-FP32 V-cycle, FP64 Krylov); the FP64 solve,
-the V-cycle and operator bandwidths, the roofline of the dominant kernel and
-the CPU oracle on a bounded sample are reported beside it.
+preconditioner application, Bi-CGSTAB.  `value` is solves/s of the
+mixed-precision solve (complex-FP32 V-cycle, FP64 Krylov).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Reported beside it: the FP64 solve, V-cycle and operator bandwidths, the
+roofline of the operator-apply kernel, the 3D 128^3 solves (IDR(4) and
+Bi-CGSTAB), the 64-problem batched solve, a bounded sample of the serving
+stream, and the CPU oracle on a bounded sample of the headline solve.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--no-cpu-baseline]
 
 Prints one JSON line.
 """
@@ -19,6 +22,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -31,16 +35,17 @@ HBM_PEAK_GBPS = 8000.0
 
 def vcycle_bytes(g, fp32):
     """Algorithmic bytes of one fused V(1,1) cycle: every field read or
-    written once per fused pass at its storage precision."""
+    written once per fused pass at its storage precision (level-0 input is the
+    FP64 Krylov vector, read by the down-leg and again by the up-leg)."""
     dims = g.level_dims
     d = g.dim
-    cb = 8 if fp32 else 16          # complex bytes inside the cycle
-    pb = 4 if fp32 else 8           # phi bytes
+    cb = 8 if fp32 else 16
+    pb = 4 if fp32 else 8
     total = 0
     for l in range(g.levels - 1):
         N = int(np.prod(dims[l][:d]))
         Nc = N // (2 ** d)
-        fin = 16 if l == 0 else cb  # level-0 input is the FP64 Krylov vector
+        fin = 16 if l == 0 else cb
         down = N * (fin + pb) + Nc * cb
         up = N * (fin + pb) + Nc * cb + N * cb
         total += down + up
@@ -48,7 +53,14 @@ def vcycle_bytes(g, fp32):
     return total
 
 
+def apply_bytes(g):
+    """y = H x in FP64 with variable k: x and y (16 B each) and phi (8 B)."""
+    return 40 * g.N
+
+
 def time_calls(torch, fn, reps):
+    """Average duration of fn() over `reps` back-to-back calls, bracketed by
+    HIP events on torch's current stream (the stream the kernels go to)."""
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     fn()
     torch.cuda.synchronize()
@@ -60,27 +72,14 @@ def time_calls(torch, fn, reps):
     return s.elapsed_time(e) / 1e3 / reps
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--levels", type=int, default=8)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-matvecs", type=int, default=24)
-    ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (multi-GPU sharding is a design note, "
-              "not part of the measured path); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
+def pct(v, q):
+    return float(np.percentile(np.asarray(v, dtype=float), q)) if len(v) else None
 
-    import torch
-    from paper_0912_0180_amd import hh
-    from paper_0912_0180_amd import workloads as W
 
-    torch.cuda.set_device(0)
+# --------------------------------------------------------------------------
+# 2D 1024^2 (headline)
+# --------------------------------------------------------------------------
+def bench_c2(args, torch, hh, W, out):
     cfg = W.c2(n=args.n, levels=args.levels)
     t0 = time.perf_counter()
     g = hh.Grid(cfg["desc"], cfg["phi"])
@@ -91,9 +90,8 @@ def main():
     def solve(prec):
         return g.solve(b, x=x, tol=1e-8, vcycle_prec=prec, max_matvec=20000)
 
-    # warmup (also allocates the work space)
     for _ in range(args.warmup):
-        _, info = solve("c64")
+        solve("c64")
     torch.cuda.synchronize()
     t = time.perf_counter()
     infos = []
@@ -102,11 +100,10 @@ def main():
         infos.append(info)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
-    ms_step = elapsed / args.steps * 1e3
-    info_m = infos[-1]
     assert all(i["status"] == 0 and i["rel_res_true"] < 1e-8 for i in infos), infos
-
-    out = {
+    info_m = infos[-1]
+    ms_step = elapsed / args.steps * 1e3
+    out.update({
         "metric": "time-to-1e-8 residual & V-cycle HBM GB/s (FP64 vs mixed); solves/s + p99 lat",
         "value": args.steps / elapsed,
         "unit": "solves/s",
@@ -125,46 +122,250 @@ def main():
         "time_to_tol_ms_mixed": ms_step,
         "matvecs_mixed": info_m["matvecs"],
         "rel_res_true_mixed": info_m["rel_res_true"],
+        "fp64_fallback_mixed": info_m["fp64_fallback"],
         "setup_s": setup_s,
-    }
+    })
+    if args.quick:
+        return cfg, g
+    solve("c128")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    x64, i64 = solve("c128")
+    torch.cuda.synchronize()
+    out["time_to_tol_ms_fp64"] = (time.perf_counter() - t) * 1e3
+    out["matvecs_fp64"] = i64["matvecs"]
+    out["rel_res_true_fp64"] = i64["rel_res_true"]
+    x64 = x64.clone()
+    xm, _ = solve("c64")
+    out["rel_err_mixed_vs_fp64"] = float(torch.linalg.vector_norm(xm - x64) / torch.linalg.vector_norm(x64))
+    out["mixed_speedup_vs_fp64"] = out["time_to_tol_ms_fp64"] / ms_step
+    f = torch.randn(g.N, dtype=torch.complex128, device="cuda")
+    u64 = torch.empty_like(f)
+    u32 = torch.empty(g.N, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(f)
+    tv64 = time_calls(torch, lambda: g.vcycle(f, "c128", out=u64), 100)
+    tv32 = time_calls(torch, lambda: g.vcycle(f, "c64", out=u32), 100)
+    th = time_calls(torch, lambda: g.apply(f, "H", out=y), 200)
+    out["vcycle_us_fp64"] = tv64 * 1e6
+    out["vcycle_us_mixed"] = tv32 * 1e6
+    out["vcycle_GBps_fp64"] = vcycle_bytes(g, False) / tv64 / 1e9
+    out["vcycle_GBps_mixed"] = vcycle_bytes(g, True) / tv32 / 1e9
+    ah = apply_bytes(g) / th / 1e9
+    out["applyH_us"] = th * 1e6
+    out["roofline"] = {"bound": "hbm", "kernel": "hh::k_applyH<2> (y = H x, c128, variable k)",
+                       "achieved": ah, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ah / HBM_PEAK_GBPS,
+                       "traffic": None, "bytes_per_unknown": 40, "unknowns_per_launch": g.N,
+                       "launch_us": th * 1e6}
+    return cfg, g
+
+
+# --------------------------------------------------------------------------
+# 3D 128^3
+# --------------------------------------------------------------------------
+def bench_c3(args, torch, hh, W):
+    res = {"workload": "3D ECS Helmholtz %d^3, %d-cell layers, 8 ppw, 8-bump k(x), point + 4 sources, "
+                       "c64 V-cycle, c128 Krylov" % (args.n3, args.n3 // 8)}
+    cfg = W.c3(n=args.n3, layer=args.n3 // 8, method="idr", s=4)
+    t0 = time.perf_counter()
+    g = hh.Grid(cfg["desc"], cfg["phi"])
+    res["setup_s"] = time.perf_counter() - t0
+    res["unknowns"] = g.N
+    res["levels"] = g.levels
+    b = torch.from_numpy(cfg["b"]).to("cuda")
+    P = hh.shadow_to_device(cfg["P"])
+    x = torch.zeros_like(b)
+    runs = [("idr4_mixed", dict(method="idr", s=4, P=P, vcycle_prec="c64")),
+            ("bicgstab_mixed", dict(method="bicgstab", vcycle_prec="c64")),
+            ("bicgstab_fp64", dict(method="bicgstab", vcycle_prec="c128"))]
+    for name, kw in runs:
+        g.solve(b, x=x, tol=1e-8, max_matvec=20000, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, info = g.solve(b, x=x, tol=1e-8, max_matvec=20000, **kw)
+        torch.cuda.synchronize()
+        res[name] = {"time_to_tol_ms": (time.perf_counter() - t) * 1e3, "matvecs": info["matvecs"],
+                     "rel_res_true": info["rel_res_true"], "status": info["status"]}
+    f = torch.randn(g.N, dtype=torch.complex128, device="cuda")
+    u32 = torch.empty(g.N, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(f)
+    tv = time_calls(torch, lambda: g.vcycle(f, "c64", out=u32), 50)
+    th = time_calls(torch, lambda: g.apply(f, "H", out=y), 100)
+    res["vcycle_us_mixed"] = tv * 1e6
+    res["vcycle_GBps_mixed"] = vcycle_bytes(g, True) / tv / 1e9
+    res["applyH_GBps"] = apply_bytes(g) / th / 1e9
+    g.close()
+    return res
+
+
+# --------------------------------------------------------------------------
+# 64 independent 2D problems in one batch
+# --------------------------------------------------------------------------
+def bench_c4(args, torch, hh, W):
+    probs = W.c4(count=args.batch)
+    t0 = time.perf_counter()
+    grids = [hh.Grid(p["desc"], p["phi"]) for p in probs]
+    setup_s = time.perf_counter() - t0
+    bs = [torch.from_numpy(p["b"]).to("cuda") for p in probs]
+    xs = [torch.zeros_like(b) for b in bs]
+    hh.solve_batch(grids, bs, xs=xs, vcycle_prec="c64")       # warm (work spaces)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, infos = hh.solve_batch(grids, bs, xs=xs, vcycle_prec="c64")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    assert all(i["status"] == 0 and i["rel_res_true"] < 1e-8 for i in infos), [i["status"] for i in infos]
+    # the same problems one after another
+    t = time.perf_counter()
+    for g, b, x in zip(grids, bs, xs):
+        g.solve(b, x=x, vcycle_prec="c64")
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t
+    mv = [i["matvecs"] for i in infos]
+    res = {"workload": "%d independent 2D problems, sides from {256..1024}, 5-12 ppw, bump k(x), 1-4 Gaussian "
+                       "sources, auto levels, c64 V-cycle, c128 Bi-CGSTAB, one launch per pass" % len(probs),
+           "unknowns_total": int(sum(g.N for g in grids)), "setup_s": setup_s,
+           "batched_s": wall, "solves_per_s": len(probs) / wall,
+           "sequential_s": seq, "sequential_solves_per_s": len(probs) / seq, "batch_speedup": seq / wall,
+           "matvecs_p50": pct(mv, 50), "matvecs_max": int(max(mv)),
+           "fp64_fallbacks": int(sum(i["fp64_fallback"] for i in infos))}
+    for g in grids:
+        g.close()
+    return res
+
+
+# --------------------------------------------------------------------------
+# serving: a bounded sample of the Poisson stream
+# --------------------------------------------------------------------------
+def bench_c5(args, torch, hh, W):
+    g = W.rng(5)
+    nreq = args.serve_requests
+    reqs = [W.serving_request(g) for _ in range(nreq)]
+    arrivals = W.poisson_arrivals(args.serve_rate, nreq, 55)
+    sv = hh.Server(budget=0, max_slots=args.serve_slots)
+    tickets = [None] * nreq
+    submit_err = []
+
+    def producer():
+        t0 = time.perf_counter()
+        try:
+            for q, r in enumerate(reqs):
+                wait = arrivals[q] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+                tickets[q] = sv.submit(r["desc"], r["b"], phi=r["phi"], method="bicgstab", vcycle_prec="c64")
+        except Exception as e:       # reported below
+            submit_err.append(repr(e))
+
+    th = threading.Thread(target=producer)
+    t_start = time.perf_counter()
+    th.start()
+    done = {}
+    while len(done) < nreq and not submit_err:
+        for q in range(nreq):
+            if q in done or tickets[q] is None:
+                continue
+            r = sv.poll(tickets[q])
+            if r is not None:
+                done[q] = r
+        time.sleep(0.001)
+    th.join()
+    wall = time.perf_counter() - t_start
+    stats = sv.stats()
+    sv.close()
+    if submit_err:
+        raise RuntimeError("serving submit failed: %s" % submit_err[0])
+    lat = [done[q][1]["t_done"] - done[q][1]["t_submit"] for q in range(nreq)]
+    qwait = [done[q][1]["t_admit"] - done[q][1]["t_submit"] for q in range(nreq)]
+    ok = sum(done[q][1]["status"] == 0 for q in range(nreq))
+    res = {"workload": "Poisson stream at %.0f req/s, first %d requests: 75%% 2D 256-2048^2, 25%% 3D 64-160^3, "
+                       "8-12 ppw, bump k(x), 1-4 Gaussian sources, mixed precision Bi-CGSTAB to 1e-8"
+                       % (args.serve_rate, nreq),
+           "requests": nreq, "ok": ok, "wall_s": wall, "solves_per_s": nreq / wall,
+           "offered_req_per_s": args.serve_rate,
+           "latency_p50_s": pct(lat, 50), "latency_p99_s": pct(lat, 99),
+           "queue_wait_p50_s": pct(qwait, 50),
+           "unknowns_total": int(sum(int(np.prod(r["desc"]["n"][:r["desc"]["dim"]])) for r in reqs)),
+           "max_rel_res_true": float(max(done[q][1]["rel_res_true"] for q in range(nreq))),
+           "fp64_fallbacks": int(sum(done[q][1]["fp64_fallback"] for q in range(nreq))),
+           "peak_admitted_bytes": int(stats["peak_bytes"]), "budget_bytes": int(stats["bytes_budget"]),
+           "peak_actual_bytes": int(stats["peak_actual"])}
+    # error of each served result against the plain FP64 solve of the same
+    # request (the FP64 path matches the oracle value for value), for the
+    # requests up to 512^2 unknowns
+    errs = []
+    for q, r in enumerate(reqs):
+        N = int(np.prod(r["desc"]["n"][:r["desc"]["dim"]]))
+        if N > 512 * 512:
+            continue
+        grid = hh.Grid(r["desc"], r["phi"])
+        bb = torch.from_numpy(np.ascontiguousarray(r["b"].reshape(-1))).to("cuda")
+        x64, _ = grid.solve(bb, vcycle_prec="c128")
+        x64 = x64.cpu().numpy()
+        errs.append(float(np.linalg.norm(done[q][0] - x64) / np.linalg.norm(x64)))
+        grid.close()
+    res["rel_err_vs_fp64_checked"] = len(errs)
+    res["rel_err_vs_fp64_max"] = max(errs) if errs else None
+    return res
+
+
+def cpu_baseline(args, cfg, out):
+    from oracle import oracle as O
+    o = O.Grid(cfg["desc"], cfg["phi"])
+    m = args.cpu_sample_matvecs
+    t = time.perf_counter()
+    _, io = o.solve(cfg["b"], tol=1e-8, max_matvec=m, max_restarts=0)
+    ts = time.perf_counter() - t
+    full_mv = out.get("matvecs_fp64", out["matvecs_mixed"])
+    est = ts / io["matvecs"] * full_mv
+    out["cpu_baseline"] = {"value": 1.0 / est, "unit": "solves/s", "cores": O.num_threads(), "kind": "oracle",
+                           "sample": "FP64 oracle Bi-CGSTAB on the headline problem, first %d matvecs in %.1f s, "
+                                     "scaled to the %d matvecs of the full FP64 solve" % (io["matvecs"], ts, full_mv)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--levels", type=int, default=8)
+    ap.add_argument("--n3", type=int, default=128)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--skip", default="", help="comma list of c3,c4,c5 to skip")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-matvecs", type=int, default=300)
+    ap.add_argument("--quick", action="store_true", help="headline solve only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (multi-GPU sharding is a design note, "
+              "not part of the measured path); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0912_0180_amd import hh
+    from paper_0912_0180_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    out = {}
+    skip = set(s for s in args.skip.split(",") if s)
+    cfg, g = bench_c2(args, torch, hh, W, out)
+    g.close()
     if not args.quick:
-        _, i64 = solve("c128")
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        _, i64 = solve("c128")
-        torch.cuda.synchronize()
-        out["time_to_tol_ms_fp64"] = (time.perf_counter() - t) * 1e3
-        out["matvecs_fp64"] = i64["matvecs"]
-        out["rel_res_true_fp64"] = i64["rel_res_true"]
-        # V-cycle and operator bandwidth (algorithmic bytes / time)
-        f = torch.randn(g.N, dtype=torch.complex128, device="cuda")
-        u64 = torch.empty_like(f)
-        u32 = torch.empty(g.N, dtype=torch.complex64, device="cuda")
-        y = torch.empty_like(f)
-        tv64 = time_calls(torch, lambda: g.vcycle(f, "c128", out=u64), 100)
-        tv32 = time_calls(torch, lambda: g.vcycle(f, "c64", out=u32), 100)
-        th = time_calls(torch, lambda: g.apply(f, "H", out=y), 200)
-        out["vcycle_us_fp64"] = tv64 * 1e6
-        out["vcycle_us_mixed"] = tv32 * 1e6
-        out["vcycle_GBps_fp64"] = vcycle_bytes(g, False) / tv64 / 1e9
-        out["vcycle_GBps_mixed"] = vcycle_bytes(g, True) / tv32 / 1e9
-        ah = 40.0 * g.N / th / 1e9
-        out["applyH_GBps"] = ah
-        out["roofline"] = {"bound": "hbm", "kernel": "k_applyH (y = H x, c128)", "achieved": ah,
-                           "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ah / HBM_PEAK_GBPS,
-                           "traffic": None, "bytes_per_unknown": 40}
+        if "c3" not in skip:
+            print("bench: c3", file=sys.stderr, flush=True)
+            out["c3"] = bench_c3(args, torch, hh, W)
+        if "c4" not in skip:
+            print("bench: c4", file=sys.stderr, flush=True)
+            out["c4"] = bench_c4(args, torch, hh, W)
+        if "c5" not in skip:
+            print("bench: c5", file=sys.stderr, flush=True)
+            out["serving"] = bench_c5(args, torch, hh, W)
     if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        o = O.Grid(cfg["desc"], cfg["phi"])
-        m = args.cpu_sample_matvecs
-        t = time.perf_counter()
-        _, io = o.solve(cfg["b"], tol=1e-8, max_matvec=m, max_restarts=0)
-        ts = time.perf_counter() - t
-        full_mv = out.get("matvecs_fp64", info_m["matvecs"])
-        est = ts / io["matvecs"] * full_mv
-        out["cpu_baseline"] = {"value": 1.0 / est, "unit": "solves/s", "cores": O.num_threads(), "kind": "oracle",
-                               "sample": "FP64 oracle Bi-CGSTAB on the same problem, first %d matvecs in %.1f s, "
-                                         "scaled to the %d matvecs of the full solve" % (io["matvecs"], ts, full_mv)}
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        cpu_baseline(args, cfg, out)
     print(json.dumps(out), flush=True)
 
 

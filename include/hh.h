@@ -149,6 +149,10 @@ typedef struct {
     double rel_res_recurrence;  /* last recurrence residual / ||b||                    */
     double rel_res_true;        /* ||b - H x|| / ||b|| in FP64 at exit                 */
     double seconds;             /* wall time inside the call                           */
+    int32_t fp64_fallback;      /* 1: a mixed-precision solve drifted (its residual
+                                   stalled or rose far above its best) and was
+                                   finished from its current iterate with the FP64
+                                   V-cycle; matvecs and iterations count both parts */
 } hh_solve_info;
 
 /* Solves H x = b.  b, x: device complex double, N elements.  Fills *info.

@@ -18,6 +18,8 @@ struct KProb {
     int restarts = 0;
     bool done = false;      // iteration over (status final); info valid once `closed`
     bool closed = false;
+    bool drift = false;     // stopped by the mixed-precision guard
+    int mv0 = 0, it0 = 0;   // counts carried over from an earlier phase of the solve
     SolveState S{};         // last state read back
     void *tag = nullptr;    // owner's handle
     uint64_t serial = 0;    // set when the problem first joins a batch

@@ -140,18 +140,30 @@ enum VecSel {
 
 // solve phases (first int of every state block)
 enum Phase { PH_RUN = 0, PH_HALF = 1, PH_STOP = 2, PH_IDLE = 3 };
+// Mixed-precision guard.  With a complex-FP32 V-cycle the preconditioner is
+// only accurate to FP32 rounding amplified by the cycle's norm, and on badly
+// resolved problems (few points per wavelength) the FP64 outer iteration can
+// stall or diverge once its residual nears that level.  A residual far above
+// the best one since the last (re)start, or no new best for a long stretch,
+// stops the solve so the host continues it from the current iterate with
+// the FP64 V-cycle.
+#define HH_DRIFT_GROW 100.0
+#define HH_DRIFT_STALL 400
+
 // what a finaliser pass does with the chunk partials of one problem
 enum FinKind { FIN_BNORM = 0, FIN_INIT, FIN_ALPHA, FIN_S, FIN_OMEGA, FIN_RHO, FIN_TRUE, FIN_NONE,
                FIN_IDR_OMEGA, FIN_IDR_STEP, FIN_IDR_INIT, FIN_IDR_M };
 // stop reasons
-enum Reason { RS_NONE = 0, RS_CONV = 1, RS_MAXMV = 2, RS_BREAK = 3, RS_NONFIN = 4 };
+enum Reason { RS_NONE = 0, RS_CONV = 1, RS_MAXMV = 2, RS_BREAK = 3, RS_NONFIN = 4, RS_DRIFT = 5 };
 
 struct SolveState {
     int phase, reason, mv, it;
     int max_mv, hist_len;
     unsigned count;                  // blocks of the current reduction done (last one finalises)
-    int pad0;
+    int guard;                       // 1: FP32 V-cycle, drift check on
     double tol, bnorm, rel, true_rel;
+    double best_rel;                 // smallest rel since the last (re)start
+    int best_mv, pad1;
     double2 rho, alpha, omega, beta;
     // IDR(s)
     int s, kstep, oldest, startup;   // kstep in 0..s within a cycle; startup steps left

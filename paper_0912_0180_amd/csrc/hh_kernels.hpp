@@ -146,12 +146,24 @@ __device__ inline Tile ldg_tile(const Tile *t, int i)
     r.idx = p[1];
     return r;
 }
+// Workgroups are dealt to the eight XCDs round robin (workgroup w runs on
+// XCD w mod 8) and every XCD has its own L2.  Renumbering them so that XCD x
+// takes one contiguous run of tiles keeps the rows a stencil tile shares with
+// its neighbours inside a single L2 instead of fetching them once per XCD.
+__device__ inline int xcd_tile_index()
+{
+    const int b = (int)blockIdx.x, nb = (int)gridDim.x;
+    const int x = b & 7, loc = b >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return x < r ? x * (q + 1) + loc : r * (q + 1) + (x - r) * q + loc;
+}
 __device__ inline Tile tile_of(const Ctx &c)
 {
-    if (c.tiles) return ldg_tile(c.tiles, blockIdx.x);
+    const int i = xcd_tile_index();
+    if (c.tiles) return ldg_tile(c.tiles, i);
     Tile t;
     t.prob = 0;
-    t.idx = (int)blockIdx.x;
+    t.idx = i;
     return t;
 }
 __device__ inline int phase_of(const Ctx &c, int prob)
@@ -325,10 +337,21 @@ __device__ int idr_nvals(const ProbDev *pd, int kind);
 // Scalar state of a Bi-CGSTAB solve, copied to registers before the
 // reduction (its loads overlap the partial sums) and written back once.
 struct BiLoc {
-    int phase, reason, mv, it, max_mv, hist_len;
-    double tol, bnorm, rel, true_rel;
+    int phase, reason, mv, it, max_mv, hist_len, guard, best_mv;
+    double tol, bnorm, rel, true_rel, best_rel;
     double2 rho, alpha, omega, beta;
 };
+
+// drift check of the mixed-precision guard; updates the best residual
+__device__ inline bool drift(double rel, int mv, double &best_rel, int &best_mv)
+{
+    if (rel < best_rel) {
+        best_rel = rel;
+        best_mv = mv;
+        return false;
+    }
+    return rel > HH_DRIFT_GROW * best_rel || mv - best_mv > HH_DRIFT_STALL;
+}
 
 __device__ inline void bi_stop(BiLoc &b, int reason)
 {
@@ -360,6 +383,9 @@ __device__ void finalize(const ProbDev *pd, int kind)
     b.alpha = st->alpha;
     b.omega = st->omega;
     b.beta = st->beta;
+    b.guard = st->guard;
+    b.best_rel = st->best_rel;
+    b.best_mv = st->best_mv;
     const int phase = b.phase;
     const int nv = kind >= FIN_IDR_OMEGA ? idr_nvals(pd, kind)
                  : (kind == FIN_S || kind == FIN_BNORM || kind == FIN_TRUE) ? 1 : (kind == FIN_ALPHA ? 2 : 3);
@@ -389,6 +415,8 @@ __device__ void finalize(const ProbDev *pd, int kind)
         b.omega = one;
         b.phase = PH_RUN;
         b.reason = RS_NONE;
+        b.best_rel = INFINITY;
+        b.best_mv = b.mv;
         double2 rho1 = cmk<double>(s[0], s[1]);
         if (!cfin(rho1)) { bi_stop(b, RS_NONFIN); break; }
         if (rho1.x == 0.0 && rho1.y == 0.0) { bi_stop(b, RS_BREAK); break; }
@@ -412,6 +440,7 @@ __device__ void finalize(const ProbDev *pd, int kind)
         if (!isfinite(rel)) { bi_stop(b, RS_NONFIN); break; }
         if (rel < b.tol) { b.phase = PH_HALF; b.reason = RS_CONV; break; }
         if (b.mv >= b.max_mv) { b.phase = PH_HALF; b.reason = RS_MAXMV; break; }
+        if (b.guard && drift(rel, b.mv, b.best_rel, b.best_mv)) { bi_stop(b, RS_DRIFT); break; }
         break;
     }
     case FIN_OMEGA: {
@@ -434,6 +463,7 @@ __device__ void finalize(const ProbDev *pd, int kind)
         if (rel < b.tol) { bi_stop(b, RS_CONV); break; }
         if (b.omega.x == 0.0 && b.omega.y == 0.0) { bi_stop(b, RS_BREAK); break; }
         if (b.mv >= b.max_mv) { bi_stop(b, RS_MAXMV); break; }
+        if (b.guard && drift(rel, b.mv, b.best_rel, b.best_mv)) { bi_stop(b, RS_DRIFT); break; }
         double2 rho1 = cmk<double>(s[0], s[1]);
         if (!cfin(rho1)) { bi_stop(b, RS_NONFIN); break; }
         if (rho1.x == 0.0 && rho1.y == 0.0) { bi_stop(b, RS_BREAK); break; }
@@ -455,6 +485,8 @@ __device__ void finalize(const ProbDev *pd, int kind)
     st->alpha = b.alpha;
     st->omega = b.omega;
     st->beta = b.beta;
+    st->best_rel = b.best_rel;
+    st->best_mv = b.best_mv;
     if (pd->ctrl && kind != FIN_BNORM && kind != FIN_TRUE) {
         Ctrl c;
         c.phase = b.phase;

@@ -35,7 +35,7 @@ struct Plan {
     hipStream_t stream = nullptr;
     hipGraphExec_t gexec = nullptr;
     int gmethod = -1, gK = 0;
-    const void *gkey = nullptr;
+    void *gvec[VS_NVEC] = {};        // one-problem plans: the vectors the graph's V-cycles name
     Ctrl *hctrl = nullptr;
     int hcap = 0;                    // capacity of hctrl (problems)
 };

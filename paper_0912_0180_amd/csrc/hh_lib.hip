@@ -573,7 +573,9 @@ hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_
     g += 2 * align256(sizeof(LevelDev<double>) * HH_MAXLEV) + align256(sizeof(ProbDev));
     const int nch = ceil_div(N, HH_CHUNK);
     g += align256(sizeof(Tile) * nch);
-    size_t ws = solve_workspace_bytes(N, o->method, fp32, s, 0);
+    // a mixed-precision solve may continue with the FP64 V-cycle (larger work
+    // space), so the FP64 work space is reserved either way
+    size_t ws = solve_workspace_bytes(N, o->method, false, s, 0);
     size_t io = 2 * align256(sizeof(double2) * N) + (s > 0 ? align256(sizeof(double2) * (size_t)N * s) : 0);
     size_t tiles = nch;
     for (int l = 0; l + 1 < nl; ++l) {

@@ -47,6 +47,7 @@ struct Req {
     size_t io_bytes = 0;
     KProb kp;
     int group = -1;
+    bool escalated = false;      // continued with the FP64 V-cycle after a drift stop
     hh_result result{};
     // guarded by the server mutex
     bool finished = false;       // result valid (x_host written)
@@ -162,6 +163,7 @@ static void finish_req(hh_server *sv, Req *r, int status)
     r->result.t_admit = r->t_admit;
     r->result.t_done = r->t_done;
     r->result.info.seconds = r->t_done - r->t_admit;
+    r->result.info.fp64_fallback = r->escalated ? 1 : 0;
 }
 
 static void release_req_device(Req *r)
@@ -212,6 +214,44 @@ static hh_status admit_device(Req *r)
     r->kp.b = b;
     r->kp.x = x;
     r->kp.tag = r;
+    return HH_OK;
+}
+
+static int group_of(hh_server *sv, int dim, int method, bool fp32)
+{
+    for (size_t i = 0; i < sv->groups.size(); ++i)
+        if (sv->groups[i].dim == dim && sv->groups[i].method == method && sv->groups[i].fp32 == fp32) return (int)i;
+    Group gr;
+    gr.dim = dim;
+    gr.method = method;
+    gr.fp32 = fp32;
+    gr.kb.reset(new KBatch(method, fp32));
+    sv->groups.push_back(std::move(gr));
+    return (int)sv->groups.size() - 1;
+}
+
+// A drift-stopped mixed-precision problem continues from its iterate with
+// the FP64 V-cycle in the FP64 group (its footprint reserved the FP64 work
+// space at admission).
+static hh_status escalate(hh_server *sv, Req *r)
+{
+    const int s = r->opts.method == HH_METHOD_IDR ? r->opts.s : 0;
+    hh_status st = workspace_ensure(r->g, r->opts.method, false, s, 0);
+    if (st != HH_OK) return st;
+    KProb e = r->kp;
+    e.o.vcycle_prec = HH_C128;
+    e.o.x0_given = 1;
+    e.mv0 = r->kp.info.matvecs;
+    e.it0 = r->kp.info.iterations;
+    e.serial = 0;
+    e.done = e.closed = e.drift = false;
+    r->kp = e;
+    r->escalated = true;
+    const int gi = group_of(sv, r->desc.dim, r->opts.method, false);
+    r->group = gi;
+    sv->groups[gi].members.push_back(r);
+    sv->groups[gi].joining.push_back(r);
+    sv->groups[gi].dirty = true;
     return HH_OK;
 }
 
@@ -296,20 +336,7 @@ static void worker_loop(hh_server *sv)
                 publish(sv, r, true, true);
                 continue;
             }
-            const int dim = r->desc.dim, method = r->opts.method;
-            const bool fp32 = r->opts.vcycle_prec == HH_C64;
-            int gi = -1;
-            for (size_t i = 0; i < sv->groups.size(); ++i)
-                if (sv->groups[i].dim == dim && sv->groups[i].method == method && sv->groups[i].fp32 == fp32) gi = (int)i;
-            if (gi < 0) {
-                Group gr;
-                gr.dim = dim;
-                gr.method = method;
-                gr.fp32 = fp32;
-                gr.kb.reset(new KBatch(method, fp32));
-                sv->groups.push_back(std::move(gr));
-                gi = (int)sv->groups.size() - 1;
-            }
+            const int gi = group_of(sv, r->desc.dim, r->opts.method, r->opts.vcycle_prec == HH_C64);
             r->group = gi;
             sv->groups[gi].members.push_back(r);
             sv->groups[gi].joining.push_back(r);
@@ -351,6 +378,7 @@ static void worker_loop(hh_server *sv)
             sv->st.peak_actual = std::max(sv->st.peak_actual, act);
         }
         // ---- K iterations of every group, then one check of each ----------
+        std::vector<Req *> drifted;
         for (Group &gr : sv->groups)
             if (!gr.members.empty()) {
                 hh_status st = gr.kb->launch();
@@ -377,6 +405,11 @@ static void worker_loop(hh_server *sv)
             if (out.empty()) continue;
             (void)hipStreamSynchronize(gr.kb->stream());
             for (Req *r : out) {
+                if (r->kp.drift && gr.fp32 && !r->escalated) {
+                    gr.members.erase(std::find(gr.members.begin(), gr.members.end(), r));
+                    drifted.push_back(r);
+                    continue;
+                }
                 if (r->kp.info.status != HH_ERR_HIP)
                     (void)hipMemcpy(r->x_host, r->kp.x, sizeof(double2) * (size_t)r->g->hs.lev[0].N,
                                     hipMemcpyDeviceToHost);
@@ -387,6 +420,14 @@ static void worker_loop(hh_server *sv)
                 publish(sv, r, true, false);
             }
             gr.dirty = true;
+        }
+        for (Req *r : drifted) {
+            hh_status st = escalate(sv, r);
+            if (st != HH_OK) {
+                release_req_device(r);
+                finish_req(sv, r, st);
+                publish(sv, r, true, true);
+            }
         }
     }
     // shutdown: release everything still on the device

@@ -252,10 +252,12 @@ hh_status KBatch::start(const std::vector<KProb *> &probs)
         st.hist_len = p->o.history ? p->o.history_len : 0;
         st.s = method_ == HH_METHOD_IDR ? p->o.s : 0;
         st.startup = -1;
+        st.guard = fp32_ ? 1 : 0;
+        st.mv = p->mv0;
+        st.it = p->it0;
         p->S = st;
-        p->done = p->closed = false;
+        p->done = p->closed = p->drift = false;
         p->status = HH_OK;
-        p->restarts = 0;
         HIPCHK(hipMemcpyAsync(p->g->ws.st, &p->S, sizeof st, hipMemcpyHostToDevice, s));
     }
     if (idx.empty()) return HH_OK;
@@ -311,9 +313,11 @@ hh_status KBatch::launch()
         return HH_OK;
     }
     // the graph bakes in the plan's lists and, for one-problem plans, the
-    // work-space vectors the V-cycle reads and writes
-    const void *key = P_.empty() ? nullptr : P_[0]->g->ws.mem;
-    if (!pl_->gexec || pl_->gmethod != method_ || pl_->gK != K_ || pl_->gkey != key) {
+    // work-space vectors the V-cycle reads and writes (a work space
+    // reallocated at the same address may be carved differently)
+    void *vec[VS_NVEC] = {};
+    if (pl_->count == 1) memcpy(vec, pl_->host[0].vec, sizeof vec);
+    if (!pl_->gexec || pl_->gmethod != method_ || pl_->gK != K_ || memcmp(vec, pl_->gvec, sizeof vec) != 0) {
         if (pl_->gexec) {
             HIPCHK(hipGraphExecDestroy(pl_->gexec));
             pl_->gexec = nullptr;
@@ -330,7 +334,7 @@ hh_status KBatch::launch()
         }
         pl_->gmethod = method_;
         pl_->gK = K_;
-        pl_->gkey = key;
+        memcpy(pl_->gvec, vec, sizeof vec);
     }
     HIPCHK(hipGraphLaunch(pl_->gexec, s));
     return HH_OK;
@@ -365,9 +369,11 @@ hh_status KBatch::close(const std::vector<int> &which, std::vector<KProb *> &clo
         in.rel_res_true = S.bnorm > 0.0 ? S.true_rel : 0.0;
         if (p->status == HH_ERR_NONFINITE) in.rel_res_true = NAN;
         if (p->o.history && p->o.history_len > 0) {
-            int n = std::min(S.mv, p->o.history_len);
-            if (n > 0) {
-                HIPCHK(hipMemcpyAsync(p->o.history, p->g->ws.hist, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+            // entries of this phase only: [mv0, mv)
+            const int lo = p->mv0, hi = std::min(S.mv, p->o.history_len);
+            if (hi > lo) {
+                HIPCHK(hipMemcpyAsync(p->o.history + lo, p->g->ws.hist + lo, sizeof(double) * (hi - lo),
+                                      hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
             }
         }
@@ -396,6 +402,10 @@ hh_status KBatch::collect(std::vector<KProb *> &closed)
                 p->status = HH_ERR_NONFINITE;
             } else if (reason == RS_MAXMV) {
                 p->done = true;
+                p->status = HH_ERR_NOCONV;
+            } else if (reason == RS_DRIFT) {
+                p->done = true;
+                p->drift = true;
                 p->status = HH_ERR_NOCONV;
             } else {
                 verify.push_back(q);
@@ -451,6 +461,43 @@ hh_status check_solve_opts(const hh_grid *g, const hh_solve_opts *o)
 }
 
 
+// One phase of a batch solve: every problem from start to stop in one
+// KBatch.  A single problem uses (and keeps) the plan cached in its grid.
+static hh_status run_phase(hh_grid *const *g, const std::vector<KProb *> &ptrs, int method, bool fp32, hipStream_t s)
+{
+    const int count = (int)ptrs.size();
+    Plan *ext = nullptr;
+    if (count == 1) {
+        if (g[0]->plan_fp32 != (int)fp32 || !g[0]->plan.mem) {
+            std::vector<const hh_grid *> G{g[0]};
+            hh_status rc = plan_build(g[0]->plan, G, fp32);
+            if (rc != HH_OK) return rc;
+            g[0]->plan_fp32 = fp32;
+        }
+        ext = &g[0]->plan;
+    }
+    KBatch kb(method, fp32, ext);
+    hh_status rc = kb.set(ptrs);
+    if (rc != HH_OK) return rc;
+    // the solve runs on the plan's own stream (graphs cannot be captured on
+    // the null stream), ordered after the caller's stream by an event
+    {
+        hipEvent_t ev;
+        HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(ev, s));
+        HIPCHK(hipStreamWaitEvent(kb.stream(), ev, 0));
+        HIPCHK(hipEventDestroy(ev));
+    }
+    rc = kb.start(ptrs);
+    std::vector<KProb *> closed;
+    while (rc == HH_OK && (int)closed.size() < count) {
+        rc = kb.launch();
+        if (rc == HH_OK) rc = kb.collect(closed);
+    }
+    HIPCHK(hipStreamSynchronize(kb.stream()));
+    return rc;
+}
+
 extern "C" hh_status hh_solve_batch(hh_grid *const *g, int32_t count, const hh_solve_opts *o, const void *const *b,
                                     void *const *x, hh_solve_info *info, void *stream)
 {
@@ -481,37 +528,39 @@ extern "C" hh_status hh_solve_batch(hh_grid *const *g, int32_t count, const hh_s
                                         o[q].history ? o[q].history_len : 0);
         if (rc != HH_OK) return rc;
     }
-    // a single problem keeps its plan (and captured graph) in the grid
-    Plan *ext = nullptr;
-    if (count == 1) {
-        if (g[0]->plan_fp32 != (int)fp32 || !g[0]->plan.mem) {
-            std::vector<const hh_grid *> G{g[0]};
-            hh_status rc = plan_build(g[0]->plan, G, fp32);
+    hh_status rc = run_phase(g, ptrs, o[0].method, fp32, s);
+    if (rc != HH_OK) return rc;
+    // mixed-precision solves stopped by the drift guard continue from their
+    // current iterate with the FP64 V-cycle
+    std::vector<KProb> E;
+    std::vector<int> eq;
+    for (int q = 0; q < count; ++q)
+        if (K[q].drift && fp32) eq.push_back(q);
+    if (!eq.empty()) {
+        std::vector<hh_grid *> eg;
+        for (int q : eq) {
+            rc = workspace_ensure(g[q], o[q].method, false, o[q].method == HH_METHOD_IDR ? o[q].s : 0,
+                                  o[q].history ? o[q].history_len : 0);
             if (rc != HH_OK) return rc;
-            g[0]->plan_fp32 = fp32;
+            KProb e = K[q];
+            e.o.vcycle_prec = HH_C128;
+            e.o.x0_given = 1;
+            e.mv0 = K[q].info.matvecs;
+            e.it0 = K[q].info.iterations;
+            e.serial = 0;
+            e.done = e.closed = e.drift = false;
+            E.push_back(e);
+            eg.push_back(g[q]);
         }
-        ext = &g[0]->plan;
+        std::vector<KProb *> ep;
+        for (KProb &e : E) ep.push_back(&e);
+        rc = run_phase(eg.data(), ep, o[0].method, false, s);
+        if (rc != HH_OK) return rc;
+        for (size_t i = 0; i < eq.size(); ++i) {
+            K[eq[i]].info = E[i].info;
+            K[eq[i]].info.fp64_fallback = 1;
+        }
     }
-    KBatch kb(o[0].method, fp32, ext);
-    hh_status rc = kb.set(ptrs);
-    if (rc != HH_OK) return rc;
-    // the solve runs on the plan's own stream (graphs cannot be captured on
-    // the null stream), ordered after the caller's stream by an event
-    {
-        hipEvent_t ev;
-        HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        HIPCHK(hipEventRecord(ev, s));
-        HIPCHK(hipStreamWaitEvent(kb.stream(), ev, 0));
-        HIPCHK(hipEventDestroy(ev));
-    }
-    rc = kb.start(ptrs);
-    std::vector<KProb *> closed;
-    while (rc == HH_OK && (int)closed.size() < count) {
-        rc = kb.launch();
-        if (rc == HH_OK) rc = kb.collect(closed);
-    }
-    HIPCHK(hipStreamSynchronize(kb.stream()));
-    if (rc != HH_OK) return rc;
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     hh_status first = HH_OK;
     for (int q = 0; q < count; ++q) {

@@ -179,3 +179,27 @@ def test_destroy_with_requests_in_flight(hh_mod):
     for m in MIX[:4]:
         submit(hh, sv, small_request(**m))
     sv.close()          # running and queued requests are dropped; no leak, no hang
+
+
+def test_server_drift_fallback_matches_alone(hh_mod):
+    """A request whose mixed solve drifts continues in the FP64 group and
+    returns what hh_solve returns for it alone."""
+    hh = hh_mod
+    p = W.c4(64)[27]
+    req = {"desc": p["desc"], "phi": p["phi"], "b": p["b"], "method": "bicgstab", "vcycle_prec": "c64", "s": 4}
+    xa, ia = solve_alone(hh, req)
+    assert ia["fp64_fallback"] == 1
+    small = small_request(seed=31, dim=2, n=96)
+    xs, is_ = solve_alone(hh, small)
+    sv = hh.Server(max_slots=4)
+    try:
+        t1 = submit(hh, sv, req)
+        t2 = submit(hh, sv, small)
+        res = wait_all(sv, [t1, t2])
+    finally:
+        sv.close()
+    x1, i1 = res[t1]
+    assert i1["status"] == 0 and i1["fp64_fallback"] == 1 and i1["matvecs"] == ia["matvecs"]
+    assert np.array_equal(x1, xa)
+    x2, i2 = res[t2]
+    assert i2["fp64_fallback"] == 0 and np.array_equal(x2, xs)
