@@ -70,6 +70,8 @@ class KBatch {
     int *sub_p_ = nullptr;
     int K_;
     bool graph_;
+    double drift_grow_;
+    int drift_stall_;
 };
 
 hh_status workspace_ensure(hh_grid *g, int method, bool fp32, int s, int hist_len);

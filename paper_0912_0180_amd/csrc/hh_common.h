@@ -24,6 +24,10 @@
 #define HH_NPART 40               // reals per chunk partial record (IDR(8) start-up needs 4s+1)
 #define HH_MAX_COARSE 1024
 #define HH_MAX_S 8
+// Coarsest grids above this many unknowns are solved by k_coarse, rows spread
+// over many workgroups (one workgroup streaming a 512 x 512 inverse is
+// latency bound); smaller ones are solved inside the tail kernel.
+#define HH_SPLIT_NC 128
 
 // ---------------------------------------------------------------------------
 // complex helpers (fixed operation order: no FMA contraction, the build uses
@@ -147,8 +151,8 @@ enum Phase { PH_RUN = 0, PH_HALF = 1, PH_STOP = 2, PH_IDLE = 3 };
 // the best one since the last (re)start, or no new best for a long stretch,
 // stops the solve so the host continues it from the current iterate with
 // the FP64 V-cycle.
-#define HH_DRIFT_GROW 100.0
-#define HH_DRIFT_STALL 400
+#define HH_DRIFT_GROW 1000.0
+#define HH_DRIFT_STALL 300           // 0: no stall test
 
 // what a finaliser pass does with the chunk partials of one problem
 enum FinKind { FIN_BNORM = 0, FIN_INIT, FIN_ALPHA, FIN_S, FIN_OMEGA, FIN_RHO, FIN_TRUE, FIN_NONE,
@@ -163,7 +167,8 @@ struct SolveState {
     int guard;                       // 1: FP32 V-cycle, drift check on
     double tol, bnorm, rel, true_rel;
     double best_rel;                 // smallest rel since the last (re)start
-    int best_mv, pad1;
+    int best_mv, drift_stall;        // guard: stop after this many matvecs without a new best
+    double drift_grow;               // guard: stop when rel exceeds this multiple of the best
     double2 rho, alpha, omega, beta;
     // IDR(s)
     int s, kstep, oldest, startup;   // kstep in 0..s within a cycle; startup steps left
@@ -188,6 +193,7 @@ struct Ctrl {
 struct ProbDev {
     int dim, nlev, Nc, nchunk;
     int tail64, tail32;              // first level of the one-workgroup tail kernel, per precision
+    int csplit;                      // 1: the coarsest solve runs in k_coarse (many workgroups)
     int n[3];
     int64_t N;
     FastDiv fx, fxy;

@@ -114,7 +114,7 @@ __device__ void idr_finalize(const ProbDev *pd, SolveState *st, int kind, const 
     if (!isfinite(rel)) { stop(st, RS_NONFIN); return; }
     if (rel < st->tol) { stop(st, RS_CONV); return; }
     if (st->mv >= st->max_mv) { stop(st, RS_MAXMV); return; }
-    if (st->guard && drift(rel, st->mv, st->best_rel, st->best_mv)) { stop(st, RS_DRIFT); return; }
+    if (st->guard && drift(rel, st->mv, st->best_rel, st->best_mv, st->drift_grow, st->drift_stall)) { stop(st, RS_DRIFT); return; }
     const int col = mode == 0 ? st->startup : st->oldest;
     for (int i = 0; i < s; ++i) {
         double2 dm = cmk<double>(v[1 + 2 * i], v[2 + 2 * i]);

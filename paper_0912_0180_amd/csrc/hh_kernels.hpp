@@ -337,20 +337,20 @@ __device__ int idr_nvals(const ProbDev *pd, int kind);
 // Scalar state of a Bi-CGSTAB solve, copied to registers before the
 // reduction (its loads overlap the partial sums) and written back once.
 struct BiLoc {
-    int phase, reason, mv, it, max_mv, hist_len, guard, best_mv;
-    double tol, bnorm, rel, true_rel, best_rel;
+    int phase, reason, mv, it, max_mv, hist_len, guard, best_mv, drift_stall;
+    double tol, bnorm, rel, true_rel, best_rel, drift_grow;
     double2 rho, alpha, omega, beta;
 };
 
 // drift check of the mixed-precision guard; updates the best residual
-__device__ inline bool drift(double rel, int mv, double &best_rel, int &best_mv)
+__device__ inline bool drift(double rel, int mv, double &best_rel, int &best_mv, double grow, int stall)
 {
     if (rel < best_rel) {
         best_rel = rel;
         best_mv = mv;
         return false;
     }
-    return rel > HH_DRIFT_GROW * best_rel || mv - best_mv > HH_DRIFT_STALL;
+    return rel > grow * best_rel || (stall > 0 && mv - best_mv > stall);
 }
 
 __device__ inline void bi_stop(BiLoc &b, int reason)
@@ -386,6 +386,8 @@ __device__ void finalize(const ProbDev *pd, int kind)
     b.guard = st->guard;
     b.best_rel = st->best_rel;
     b.best_mv = st->best_mv;
+    b.drift_stall = st->drift_stall;
+    b.drift_grow = st->drift_grow;
     const int phase = b.phase;
     const int nv = kind >= FIN_IDR_OMEGA ? idr_nvals(pd, kind)
                  : (kind == FIN_S || kind == FIN_BNORM || kind == FIN_TRUE) ? 1 : (kind == FIN_ALPHA ? 2 : 3);
@@ -440,7 +442,7 @@ __device__ void finalize(const ProbDev *pd, int kind)
         if (!isfinite(rel)) { bi_stop(b, RS_NONFIN); break; }
         if (rel < b.tol) { b.phase = PH_HALF; b.reason = RS_CONV; break; }
         if (b.mv >= b.max_mv) { b.phase = PH_HALF; b.reason = RS_MAXMV; break; }
-        if (b.guard && drift(rel, b.mv, b.best_rel, b.best_mv)) { bi_stop(b, RS_DRIFT); break; }
+        if (b.guard && drift(rel, b.mv, b.best_rel, b.best_mv, b.drift_grow, b.drift_stall)) { bi_stop(b, RS_DRIFT); break; }
         break;
     }
     case FIN_OMEGA: {
@@ -463,7 +465,7 @@ __device__ void finalize(const ProbDev *pd, int kind)
         if (rel < b.tol) { bi_stop(b, RS_CONV); break; }
         if (b.omega.x == 0.0 && b.omega.y == 0.0) { bi_stop(b, RS_BREAK); break; }
         if (b.mv >= b.max_mv) { bi_stop(b, RS_MAXMV); break; }
-        if (b.guard && drift(rel, b.mv, b.best_rel, b.best_mv)) { bi_stop(b, RS_DRIFT); break; }
+        if (b.guard && drift(rel, b.mv, b.best_rel, b.best_mv, b.drift_grow, b.drift_stall)) { bi_stop(b, RS_DRIFT); break; }
         double2 rho1 = cmk<double>(s[0], s[1]);
         if (!cfin(rho1)) { bi_stop(b, RS_NONFIN); break; }
         if (rho1.x == 0.0 && rho1.y == 0.0) { bi_stop(b, RS_BREAK); break; }
@@ -1099,14 +1101,21 @@ __device__ inline void tail_ijk(const TailPtr<T> &Q, int p, int &i, int &j, int 
 // arithmetic as the tiled kernels; the coarsest solve applies the explicit
 // inverse with a pairwise sum per row.
 // ---------------------------------------------------------------------------
+// up = 0: the whole tail (down-legs, coarsest solve, up-legs), or, for a
+// problem whose coarsest solve runs in k_coarse, the down-legs only (the
+// restricted right-hand sides of the tail levels go to global memory).
+// up = 1: the up-legs of such a problem, from those right-hand sides and the
+// coarsest solution k_coarse left in global memory.
 template <int DIM, typename T>
-__global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__restrict__ probs)
+__global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__restrict__ probs, int up)
 {
     using C = V2<T>;
     __shared__ __attribute__((aligned(16))) char lds[TailCap<T>::BYTES];
     const int prob = probs ? probs[blockIdx.x] : 0;
     if (phase_of(cx, prob) != PH_RUN) return;
     const ProbDev *pd = cx.P + prob;
+    const int split = pd->csplit;
+    if (up && !split) return;
     const LevelDev<T> *Lv = levels_of<T>(cx, pd);
     const int t0 = tail_level<T>(pd), L = pd->nlev;
     const T omega = (T)pd->omega;
@@ -1139,22 +1148,32 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
             }
         }
         __syncthreads();
-        const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, t0);
-        const C *__restrict__ fg = fg_top;
-        for (int b = 0; b < Q.N; b += 4 * nth) {
-            C tmp[4];
+        // f of the top level (and, for the up-legs of a split tail, f of
+        // every tail level and e of the coarsest)
+        const int lf = up ? L - 1 : t0 + 1;
+        for (int l = t0; l < lf; ++l) {
+            const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, l);
+            const C *__restrict__ fg = l == t0 ? fg_top : Lv[l].f;
+            for (int b = 0; b < Q.N; b += 4 * nth) {
+                C tmp[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (b + tid + q * nth < Q.N) tmp[q] = ldg(fg, b + tid + q * nth);
+                for (int q = 0; q < 4; ++q)
+                    if (b + tid + q * nth < Q.N) tmp[q] = ldg(fg, b + tid + q * nth);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (b + tid + q * nth < Q.N) Q.F[b + tid + q * nth] = tmp[q];
+                for (int q = 0; q < 4; ++q)
+                    if (b + tid + q * nth < Q.N) Q.F[b + tid + q * nth] = tmp[q];
+            }
+        }
+        if (up) {
+            const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, L - 1);
+            const C *__restrict__ eg = Lv[L - 1].e;
+            for (int p = tid; p < Q.N; p += nth) Q.E[p] = ldg(eg, p);
         }
     }
     __syncthreads();
     const T w0 = (T)0.125, w1 = (T)0.375, p3 = (T)0.75, p1 = (T)0.25;
     // down-legs
-    for (int l = t0; l < L - 1; ++l) {
+    for (int l = t0; l < L - 1 && !up; ++l) {
         const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, l);
         const TailPtr<T> R = tail_ptr<DIM, T>(lds, tab, l + 1);
         for (int p = tid; p < Q.N; p += nth) {
@@ -1203,8 +1222,17 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
         }
         __syncthreads();
     }
+    if (!up && split) {
+        // hand the restricted right-hand sides to k_coarse and the up-legs
+        for (int l = t0 + 1; l < L; ++l) {
+            const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, l);
+            C *fg = Lv[l].f;
+            for (int p = tid; p < Q.N; p += nth) stg(fg, p, Q.F[p]);
+        }
+        return;
+    }
     // coarsest solve
-    {
+    if (!up) {
         const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, L - 1);
         coarse_rows<T>(Minv, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
         __syncthreads();
@@ -1257,6 +1285,38 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
         const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, t0);
         for (int p = tid; p < Q.N; p += nth) stg(eg_top, p, Q.E[p]);
     }
+}
+
+// Waves k_coarse gives one coarsest solve of n unknowns (rows per wave as in
+// coarse_rows).
+__host__ __device__ inline int coarse_waves(int n)
+{
+    int np = 64;
+    while (np < n) np <<= 1;
+    const int rpb = 16 / (np >> 6);
+    return (n + rpb - 1) / rpb;
+}
+
+// Coarsest solve e = Minv f with the rows spread over workgroups: wave w of
+// the problem takes rows w, w + W, ... (W waves in all), each row summed
+// exactly as in the tail kernel.  f is staged in LDS.
+template <typename T>
+__global__ __launch_bounds__(HH_WG) void k_coarse(Ctx cx)
+{
+    using C = V2<T>;
+    const Tile tl = tile_of(cx);
+    if (phase_of(cx, tl.prob) != PH_RUN) return;
+    const ProbDev *pd = cx.P + tl.prob;
+    const LevelDev<T> *Lv = levels_of<T>(cx, pd);
+    const int L = pd->nlev, n = pd->Nc;
+    __shared__ C fs[HH_MAX_COARSE];
+    const C *__restrict__ fg = Lv[L - 1].f;
+    for (int i = threadIdx.x; i < n; i += HH_WG) fs[i] = ldg(fg, i);
+    __syncthreads();
+    const C *__restrict__ Minv = (const C *)(sizeof(T) == 8 ? (const void *)pd->Minv64 : (const void *)pd->Minv32);
+    const int w = tl.idx * (HH_WG / 64) + (int)(threadIdx.x >> 6), W = coarse_waves(n);
+    if (w >= W) return;
+    coarse_rows<T>(Minv, fs, Lv[L - 1].e, n, w, W);
 }
 
 // ---------------------------------------------------------------------------

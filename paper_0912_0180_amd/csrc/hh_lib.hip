@@ -195,6 +195,7 @@ void grid_fill_prob(const hh_grid *g, ProbDev &pd)
     pd.omega = hs.omega;
     pd.tail64 = tail_level(hs, false);
     pd.tail32 = tail_level(hs, true);
+    pd.csplit = hs.Nc > HH_SPLIT_NC ? 1 : 0;
     pd.timg64 = g->timg64;
     pd.timg32 = g->timg32;
     pd.timg_bytes64 = (int)g->timg_bytes64;
@@ -335,12 +336,20 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
     pl.dim = G.empty() ? 2 : G[0]->hs.dim;
     pl.fp32 = fp32;
     pl.Lmax = 0;
-    std::vector<Tile> chunks, down[HH_MAXLEV], up[HH_MAXLEV];
+    std::vector<Tile> chunks, down[HH_MAXLEV], up[HH_MAXLEV], coarse;
     std::vector<int> fin;
+    pl.tail_down = pl.tail_up = false;
     for (int q = 0; q < pl.count; ++q) {
         const HostSetup &hs = G[q]->hs;
         const int t = tail_level(hs, fp32);
         pl.Lmax = std::max(pl.Lmax, t);
+        const bool split = hs.Nc > HH_SPLIT_NC;
+        if (split) {
+            const int nwg = ceil_div(coarse_waves(hs.Nc), HH_WG / 64);
+            for (int i = 0; i < nwg; ++i) coarse.push_back(Tile{q, i});
+        }
+        if (!split || t < hs.nlev - 1) pl.tail_down = true;
+        if (split && t < hs.nlev - 1) pl.tail_up = true;
         int nch = ceil_div(hs.lev[0].N, HH_CHUNK);
         for (int i = 0; i < nch; ++i) chunks.push_back(Tile{q, i});
         for (int l = 0; l < t; ++l) {
@@ -351,7 +360,8 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         }
         fin.push_back(q);
     }
-    size_t bytes = align256(sizeof(Tile) * chunks.size()) + align256(sizeof(int) * fin.size()) +
+    size_t bytes = align256(sizeof(Tile) * chunks.size()) + align256(sizeof(Tile) * coarse.size()) +
+                   align256(sizeof(int) * fin.size()) +
                    align256(sizeof(ProbDev) * pl.count) + align256(sizeof(Ctrl) * pl.count);
     for (int l = 0; l < HH_MAXLEV; ++l) bytes += align256(sizeof(Tile) * down[l].size()) + align256(sizeof(Tile) * up[l].size());
     hipError_t e = hipMalloc(&pl.mem, bytes);
@@ -365,6 +375,7 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         return v.empty() ? hipSuccess : hipMemcpy(d.t, v.data(), sizeof(Tile) * v.size(), hipMemcpyHostToDevice);
     };
     HIPCHK(up_list(chunks, pl.chunks));
+    HIPCHK(up_list(coarse, pl.coarse));
     for (int l = 0; l < HH_MAXLEV; ++l) {
         HIPCHK(up_list(down[l], pl.down[l]));
         HIPCHK(up_list(up[l], pl.up[l]));
@@ -417,9 +428,15 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
         else LAUNCH((k_vdown<DIM, T, C>), pl.down[l].n, s, c, l, fsel, fptr);
     }
     {
+        // coarse part: tail kernel (whole, or down-legs of split problems),
+        // multi-workgroup coarsest solves, up-legs of split problems
         Ctx c = ctx_of(pl, pl.chunks);
-        if (pl.nfin > 0) hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c,
-                                            pl.count == 1 ? nullptr : pl.fin);
+        const int *probs = pl.count == 1 ? nullptr : pl.fin;
+        if (pl.nfin > 0 && pl.tail_down)
+            hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c, probs, 0);
+        LAUNCH(k_coarse<T>, pl.coarse.n, s, ctx_of(pl, pl.coarse));
+        if (pl.nfin > 0 && pl.tail_up)
+            hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c, probs, 1);
     }
     for (int l = pl.Lmax - 1; l >= 0; --l) {
         const Ctx c = ctx_of(pl, pl.up[l]);
@@ -577,7 +594,7 @@ hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_
     // space), so the FP64 work space is reserved either way
     size_t ws = solve_workspace_bytes(N, o->method, false, s, 0);
     size_t io = 2 * align256(sizeof(double2) * N) + (s > 0 ? align256(sizeof(double2) * (size_t)N * s) : 0);
-    size_t tiles = nch;
+    size_t tiles = nch + (nc > HH_SPLIT_NC ? ceil_div(coarse_waves(nc), HH_WG / 64) : 0);
     for (int l = 0; l + 1 < nl; ++l) {
         int nd, nu;
         vtile_counts(dim, fp32, L[l], L[l + 1], nd, nu);

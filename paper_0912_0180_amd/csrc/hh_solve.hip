@@ -120,6 +120,9 @@ KBatch::KBatch(int method, bool fp32, Plan *external) : method_(method), fp32_(f
     const char *ek = getenv("HH_ITERS_PER_CHECK");
     K_ = ek ? std::max(1, atoi(ek)) : 4;
     graph_ = !getenv("HH_NO_GRAPH");
+    const char *eg = getenv("HH_DRIFT_GROW"), *es = getenv("HH_DRIFT_STALL");
+    drift_grow_ = eg ? atof(eg) : HH_DRIFT_GROW;
+    drift_stall_ = es ? atoi(es) : HH_DRIFT_STALL;
 }
 
 KBatch::~KBatch()
@@ -253,6 +256,8 @@ hh_status KBatch::start(const std::vector<KProb *> &probs)
         st.s = method_ == HH_METHOD_IDR ? p->o.s : 0;
         st.startup = -1;
         st.guard = fp32_ ? 1 : 0;
+        st.drift_grow = drift_grow_;
+        st.drift_stall = drift_stall_;
         st.mv = p->mv0;
         st.it = p->it0;
         p->S = st;
