@@ -919,61 +919,93 @@ __global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int os
 // arithmetic as the tiled kernels; the coarsest solve applies the explicit
 // inverse with a pairwise sum per row.
 // ---------------------------------------------------------------------------
-// Coarsest solve by one wave: rows row0, row0 + rstep, ... (up to 16 / seg
-// rows at once, loads issued together) of Minv applied to f (LDS); each row
-// is summed pairwise over its zero-padded length (lane segments of Np/64
-// terms, then a butterfly).  Lane 0 writes e[row].
-template <typename T>
-__device__ inline void coarse_rows(const V2<T> *__restrict__ Minv, const V2<T> *f, V2<T> *e, int n, int row0, int rstep)
+// Slots per lane and batch of the coarse solve (rows per batch = slots / seg);
+// fewer for FP64 to stay within the register file.
+template <typename T> __host__ __device__ constexpr int coarse_slots(int seg)
 {
+    return sizeof(T) == 8 ? (seg > 8 ? seg : 8) : 16;
+}
+
+template <typename T, int SEG>
+__device__ inline void coarse_rows_seg(const V2<T> *__restrict__ Minv, const V2<T> *f, V2<T> *e, int n, int row0, int rstep)
+{
+    constexpr int NS = coarse_slots<T>(SEG);
+    constexpr int RPB = NS / SEG;  // rows per batch
     const int lane = threadIdx.x & 63;
-    int np = 64;
-    while (np < n) np <<= 1;
-    const int seg = np >> 6;       // 1..16
-    const int rpb = 16 / seg;      // rows per batch
-    for (int rb = row0; rb < n; rb += rpb * rstep) {
-        T re[16], im[16];
+    for (int rb = row0; rb < n; rb += RPB * rstep) {
+        T re[NS], im[NS];
+        // inverse entries in groups of 8 loads in flight together (unused
+        // slots read entry 0)
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            re[q] = 0;
-            im[q] = 0;
-            const int r = q / seg, i = q - r * seg;
-            const int row = rb + r * rstep, col = lane * seg + i;
-            if (r < rpb && row < n && col < n) {
-                V2<T> pr = cmul<T>(ldg(Minv, (int64_t)row * n + col), f[col]);
-                re[q] = pr.x;
-                im[q] = pr.y;
+        for (int h = 0; h < NS; h += 8) {
+            V2<T> mv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int row = rb + ((h + q) / SEG) * rstep, col = lane * SEG + (h + q) % SEG;
+                mv[q] = ldg(Minv, (row < n && col < n) ? (int64_t)row * n + col : 0);
             }
-        }
-        // in-lane pairwise over each row's segment (segments are aligned
-        // power-of-two blocks of the 16 slots)
 #pragma unroll
-        for (int w = 1; w < 16; w <<= 1) {
-            if (w < seg) {
-#pragma unroll
-                for (int i = 0; i + w < 16; i += 2 * w) {
-                    re[i] = re[i] + re[i + w];
-                    im[i] = im[i] + im[i + w];
+            for (int q = 0; q < 8; ++q) {
+                const int row = rb + ((h + q) / SEG) * rstep, col = lane * SEG + (h + q) % SEG;
+                re[h + q] = 0;
+                im[h + q] = 0;
+                if (row < n && col < n) {
+                    V2<T> pr = cmul<T>(mv[q], f[col]);
+                    re[h + q] = pr.x;
+                    im[h + q] = pr.y;
                 }
             }
         }
-        for (int r = 0; r < rpb; ++r) {
-            T sr = 0, si = 0;
+        // in-lane pairwise over each row's segment (aligned power-of-two
+        // blocks of the slots); row r's partial ends in slot r * SEG
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
-                if (q == r * seg) {
-                    sr = re[q];
-                    si = im[q];
-                }
+        for (int w = 1; w < SEG; w <<= 1) {
+#pragma unroll
+            for (int i = 0; i + w < NS; i += 2 * w) {
+                re[i] = re[i] + re[i + w];
+                im[i] = im[i] + im[i + w];
+            }
+        }
+        // butterfly across the wave, up to 4 rows of the batch together
+        constexpr int RG = RPB < 4 ? RPB : 4;
+#pragma unroll
+        for (int r0 = 0; r0 < RPB; r0 += RG) {
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
-                sr = sr + __shfl_xor(sr, off, 64);
-                si = si + __shfl_xor(si, off, 64);
+#pragma unroll
+                for (int r = r0; r < r0 + RG; ++r) {
+                    re[r * SEG] = re[r * SEG] + __shfl_xor(re[r * SEG], off, 64);
+                    im[r * SEG] = im[r * SEG] + __shfl_xor(im[r * SEG], off, 64);
+                }
             }
-            const int row = rb + r * rstep;
-            if (lane == 0 && row < n) e[row] = cmk<T>(sr, si);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < RPB; ++r) {
+                const int row = rb + r * rstep;
+                if (row < n) e[row] = cmk<T>(re[r * SEG], im[r * SEG]);
+            }
         }
     }
+}
+
+// Coarsest solve by one wave: rows row0, row0 + rstep, ... (16 / seg rows
+// per batch, loads issued together) of Minv applied to f; each row is summed
+// pairwise over its zero-padded length np = max(64, 2^ceil(log2 n)) (lane
+// segments of seg = np/64 terms, then a butterfly).  Lane 0 writes e[row].
+// Inside the tail kernel n <= HH_SPLIT_NC, so seg is 1 or 2.
+__host__ __device__ inline int coarse_seg(int n)
+{
+    int np = 64;
+    while (np < n) np <<= 1;
+    return np >> 6;
+}
+template <typename T>
+__device__ inline void coarse_rows_tail(const V2<T> *__restrict__ Minv, const V2<T> *f, V2<T> *e, int n, int row0, int rstep)
+{
+    static_assert(HH_SPLIT_NC <= 128, "tail coarse solve handles seg 1 and 2");
+    if (coarse_seg(n) == 1) coarse_rows_seg<T, 1>(Minv, f, e, n, row0, rstep);
+    else coarse_rows_seg<T, 2>(Minv, f, e, n, row0, rstep);
 }
 
 template <typename T> __device__ inline V2<T> jweight(V2<T> D, T omega)
@@ -1032,15 +1064,16 @@ struct TailTab {
     int uoff;
 };
 
+// one thread per level (callers synchronise before use)
 template <int DIM, typename T>
 __device__ inline void tail_tab_fill(TailTab &tab, const LevelDev<T> *Lv, int t0, int L)
 {
-    for (int l = t0; l < L; ++l) {
+    for (int l = t0 + (int)threadIdx.x; l < L; l += (int)blockDim.x) {
         tab.o[l] = tail_off<DIM, T>(Lv, t0, l);
         tab.fx[l] = Lv[l].fx;
         tab.fxy[l] = Lv[l].fxy;
+        if (l == L - 1) tab.uoff = tab.o[l].end;
     }
-    tab.uoff = tab.o[L - 1].end;
 }
 
 template <int DIM, typename T>
@@ -1122,14 +1155,12 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
     const C zero = cmk<T>(0, 0);
     const int tid = threadIdx.x, nth = TailCap<T>::WG;
     __shared__ TailTab tab;
-    if (tid == 0) tail_tab_fill<DIM, T>(tab, Lv, t0, L);
-    __syncthreads();
-    C *U = (C *)(lds + tab.uoff);
     const C *fg_top = Lv[t0].f;
     C *eg_top = Lv[t0].e;
     const C *__restrict__ Minv = (const C *)(sizeof(T) == 8 ? (const void *)pd->Minv64 : (const void *)pd->Minv32);
     // the tail image (phi and coefficients of every tail level, zeros
-    // elsewhere) in one coalesced sweep, then f at the top level
+    // elsewhere) in one coalesced sweep, its first batch in flight while the
+    // level table is built; then f at the top level
     {
         const void *img = sizeof(T) == 8 ? pd->timg64 : pd->timg32;
         const int n16 = (sizeof(T) == 8 ? pd->timg_bytes64 : pd->timg_bytes32) / 16;
@@ -1141,12 +1172,14 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
                 const int i = b + tid + q * nth;
                 if (i < n16) tmp[q] = ldg16(img, i);
             }
+            if (b == 0) tail_tab_fill<DIM, T>(tab, Lv, t0, L);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int i = b + tid + q * nth;
                 if (i < n16) l16[i] = tmp[q];
             }
         }
+        if (n16 <= 0) tail_tab_fill<DIM, T>(tab, Lv, t0, L);
         __syncthreads();
         // f of the top level (and, for the up-legs of a split tail, f of
         // every tail level and e of the coarsest)
@@ -1171,6 +1204,7 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
         }
     }
     __syncthreads();
+    C *U = (C *)(lds + tab.uoff);
     const T w0 = (T)0.125, w1 = (T)0.375, p3 = (T)0.75, p1 = (T)0.25;
     // down-legs
     for (int l = t0; l < L - 1 && !up; ++l) {
@@ -1234,7 +1268,7 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
     // coarsest solve
     if (!up) {
         const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, L - 1);
-        coarse_rows<T>(Minv, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
+        coarse_rows_tail<T>(Minv, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
         __syncthreads();
     }
     // up-legs
@@ -1288,19 +1322,19 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
 }
 
 // Waves k_coarse gives one coarsest solve of n unknowns (rows per wave as in
-// coarse_rows).
-__host__ __device__ inline int coarse_waves(int n)
+// coarse_rows_seg).
+template <typename T> __host__ __device__ inline int coarse_waves(int n)
 {
-    int np = 64;
-    while (np < n) np <<= 1;
-    const int rpb = 16 / (np >> 6);
+    const int seg = coarse_seg(n);
+    const int rpb = coarse_slots<T>(seg) / seg;
     return (n + rpb - 1) / rpb;
 }
 
 // Coarsest solve e = Minv f with the rows spread over workgroups: wave w of
 // the problem takes rows w, w + W, ... (W waves in all), each row summed
-// exactly as in the tail kernel.  f is staged in LDS.
-template <typename T>
+// exactly as in the tail kernel.  f is staged in LDS.  SEG = coarse_seg(Nc)
+// of every problem in the launch.
+template <typename T, int SEG>
 __global__ __launch_bounds__(HH_WG) void k_coarse(Ctx cx)
 {
     using C = V2<T>;
@@ -1314,9 +1348,9 @@ __global__ __launch_bounds__(HH_WG) void k_coarse(Ctx cx)
     for (int i = threadIdx.x; i < n; i += HH_WG) fs[i] = ldg(fg, i);
     __syncthreads();
     const C *__restrict__ Minv = (const C *)(sizeof(T) == 8 ? (const void *)pd->Minv64 : (const void *)pd->Minv32);
-    const int w = tl.idx * (HH_WG / 64) + (int)(threadIdx.x >> 6), W = coarse_waves(n);
+    const int w = tl.idx * (HH_WG / 64) + (int)(threadIdx.x >> 6), W = coarse_waves<T>(n);
     if (w >= W) return;
-    coarse_rows<T>(Minv, fs, Lv[L - 1].e, n, w, W);
+    coarse_rows_seg<T, SEG>(Minv, fs, Lv[L - 1].e, n, w, W);
 }
 
 // ---------------------------------------------------------------------------

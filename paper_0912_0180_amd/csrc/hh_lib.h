@@ -21,7 +21,7 @@ struct Plan {
     int count = 0, dim = 2, Lmax = 0;
     bool fp32 = false;
     DevList chunks, down[HH_MAXLEV], up[HH_MAXLEV];   // down/up: levels above the tail
-    DevList coarse;                  // k_coarse workgroups of problems with a split tail
+    DevList coarse[5];               // k_coarse workgroups of problems with a split tail, by log2(seg)
     bool tail_down = false;          // some problem needs the (full or down-only) tail kernel
     bool tail_up = false;            // some problem needs the up-only tail kernel
     int *fin = nullptr;

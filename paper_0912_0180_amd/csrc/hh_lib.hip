@@ -336,7 +336,7 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
     pl.dim = G.empty() ? 2 : G[0]->hs.dim;
     pl.fp32 = fp32;
     pl.Lmax = 0;
-    std::vector<Tile> chunks, down[HH_MAXLEV], up[HH_MAXLEV], coarse;
+    std::vector<Tile> chunks, down[HH_MAXLEV], up[HH_MAXLEV], coarse[5];
     std::vector<int> fin;
     pl.tail_down = pl.tail_up = false;
     for (int q = 0; q < pl.count; ++q) {
@@ -345,8 +345,10 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         pl.Lmax = std::max(pl.Lmax, t);
         const bool split = hs.Nc > HH_SPLIT_NC;
         if (split) {
-            const int nwg = ceil_div(coarse_waves(hs.Nc), HH_WG / 64);
-            for (int i = 0; i < nwg; ++i) coarse.push_back(Tile{q, i});
+            const int nwg = ceil_div(fp32 ? coarse_waves<float>(hs.Nc) : coarse_waves<double>(hs.Nc), HH_WG / 64);
+            int lg = 0;
+            while ((1 << lg) < coarse_seg(hs.Nc)) ++lg;
+            for (int i = 0; i < nwg; ++i) coarse[lg].push_back(Tile{q, i});
         }
         if (!split || t < hs.nlev - 1) pl.tail_down = true;
         if (split && t < hs.nlev - 1) pl.tail_up = true;
@@ -360,10 +362,11 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         }
         fin.push_back(q);
     }
-    size_t bytes = align256(sizeof(Tile) * chunks.size()) + align256(sizeof(Tile) * coarse.size()) +
+    size_t bytes = align256(sizeof(Tile) * chunks.size()) +
                    align256(sizeof(int) * fin.size()) +
                    align256(sizeof(ProbDev) * pl.count) + align256(sizeof(Ctrl) * pl.count);
     for (int l = 0; l < HH_MAXLEV; ++l) bytes += align256(sizeof(Tile) * down[l].size()) + align256(sizeof(Tile) * up[l].size());
+    for (int g = 0; g < 5; ++g) bytes += align256(sizeof(Tile) * coarse[g].size());
     hipError_t e = hipMalloc(&pl.mem, bytes);
     if (e != hipSuccess) return hh_fail(HH_ERR_OOM, "hipMalloc(%zu) for a launch plan: %s", bytes, hipGetErrorString(e));
     pl.bytes = bytes;
@@ -375,7 +378,7 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         return v.empty() ? hipSuccess : hipMemcpy(d.t, v.data(), sizeof(Tile) * v.size(), hipMemcpyHostToDevice);
     };
     HIPCHK(up_list(chunks, pl.chunks));
-    HIPCHK(up_list(coarse, pl.coarse));
+    for (int g = 0; g < 5; ++g) HIPCHK(up_list(coarse[g], pl.coarse[g]));
     for (int l = 0; l < HH_MAXLEV; ++l) {
         HIPCHK(up_list(down[l], pl.down[l]));
         HIPCHK(up_list(up[l], pl.up[l]));
@@ -434,7 +437,11 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
         const int *probs = pl.count == 1 ? nullptr : pl.fin;
         if (pl.nfin > 0 && pl.tail_down)
             hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c, probs, 0);
-        LAUNCH(k_coarse<T>, pl.coarse.n, s, ctx_of(pl, pl.coarse));
+        LAUNCH((k_coarse<T, 1>), pl.coarse[0].n, s, ctx_of(pl, pl.coarse[0]));
+        LAUNCH((k_coarse<T, 2>), pl.coarse[1].n, s, ctx_of(pl, pl.coarse[1]));
+        LAUNCH((k_coarse<T, 4>), pl.coarse[2].n, s, ctx_of(pl, pl.coarse[2]));
+        LAUNCH((k_coarse<T, 8>), pl.coarse[3].n, s, ctx_of(pl, pl.coarse[3]));
+        LAUNCH((k_coarse<T, 16>), pl.coarse[4].n, s, ctx_of(pl, pl.coarse[4]));
         if (pl.nfin > 0 && pl.tail_up)
             hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c, probs, 1);
     }
@@ -594,7 +601,7 @@ hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_
     // space), so the FP64 work space is reserved either way
     size_t ws = solve_workspace_bytes(N, o->method, false, s, 0);
     size_t io = 2 * align256(sizeof(double2) * N) + (s > 0 ? align256(sizeof(double2) * (size_t)N * s) : 0);
-    size_t tiles = nch + (nc > HH_SPLIT_NC ? ceil_div(coarse_waves(nc), HH_WG / 64) : 0);
+    size_t tiles = nch + (nc > HH_SPLIT_NC ? ceil_div(coarse_waves<double>(nc), HH_WG / 64) : 0);
     for (int l = 0; l + 1 < nl; ++l) {
         int nd, nu;
         vtile_counts(dim, fp32, L[l], L[l + 1], nd, nu);
