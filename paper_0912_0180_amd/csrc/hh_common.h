@@ -235,12 +235,21 @@ template <typename T> struct TailCap;
 template <> struct TailCap<double> { static constexpr int N = 1024; static constexpr int BYTES = 96 * 1024; static constexpr int WG = 256; };
 template <> struct TailCap<float> { static constexpr int N = 1024; static constexpr int BYTES = 64 * 1024; static constexpr int WG = 512; };
 
-// Tile shapes of the fused V-cycle kernels (coarse tile of the down-leg; the
-// up-leg's fine tile is twice it).
-template <int DIM, typename T> struct VTile;
-template <> struct VTile<2, double> { static constexpr int X = 16, Y = 16, Z = 1; };
-template <> struct VTile<2, float> { static constexpr int X = 16, Y = 16, Z = 1; };
-template <> struct VTile<3, double> { static constexpr int X = 4, Y = 4, Z = 4; };
-template <> struct VTile<3, float> { static constexpr int X = 8, Y = 4, Z = 4; };
+// Tile shapes of the fused V-cycle level kernels (coarse points per axis of
+// the down-leg's tile; the up-leg's fine tile is twice it).  The kernels are
+// built for every shape of the set and the autotuner picks one per
+// (dimension, precision, leg, level class); results do not depend on it.
+#define HH_NTILE 5
+template <int DIM> struct TileSet;
+template <> struct TileSet<2> {
+    static constexpr int X[HH_NTILE] = {16, 32, 16, 8, 32};
+    static constexpr int Y[HH_NTILE] = {16, 8, 8, 8, 16};
+    static constexpr int Z[HH_NTILE] = {1, 1, 1, 1, 1};
+};
+template <> struct TileSet<3> {
+    static constexpr int X[HH_NTILE] = {4, 8, 8, 4, 8};
+    static constexpr int Y[HH_NTILE] = {4, 4, 8, 4, 4};
+    static constexpr int Z[HH_NTILE] = {4, 4, 2, 2, 2};
+};
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }

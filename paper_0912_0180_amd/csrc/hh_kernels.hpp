@@ -587,16 +587,11 @@ __global__ __launch_bounds__(HH_WG) void k_applyM(Ctx cx, const void *xp, void *
 // Tile = a box of coarse points; LDS holds f, phi and u1 on the fine box
 // with a halo of 2 (restriction footprint + stencil).
 // ---------------------------------------------------------------------------
-template <int DIM, typename T>
-struct Box {
-    static constexpr int CX = VTile<DIM, T>::X, CY = VTile<DIM, T>::Y, CZ = VTile<DIM, T>::Z;
-};
-
-template <int DIM, typename T, typename TF>
+template <int DIM, typename T, typename TF, int VT>
 __global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, const void *fptr)
 {
     using C = V2<T>;
-    constexpr int CX = VTile<DIM, T>::X, CY = VTile<DIM, T>::Y, CZ = VTile<DIM, T>::Z;
+    constexpr int CX = TileSet<DIM>::X[VT], CY = TileSet<DIM>::Y[VT], CZ = DIM == 3 ? TileSet<DIM>::Z[VT] : 1;
     constexpr int RX = 2 * CX + 4, RY = 2 * CY + 4, RZ = DIM == 3 ? 2 * CZ + 4 : 1;
     constexpr int RN = RX * RY * RZ;
     constexpr int RM = RX > RY ? (RX > RZ ? RX : RZ) : (RY > RZ ? RY : RZ);
@@ -744,11 +739,11 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, cons
 //   u2 = g f + P e_{lev+1},  u = u2 + g (f - M u2).
 // Output: e_lev (lev >= 1) or the output vector (lev == 0, storage TO).
 // ---------------------------------------------------------------------------
-template <int DIM, typename T, typename TF, typename TO>
+template <int DIM, typename T, typename TF, typename TO, int VT>
 __global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int osel, const void *fptr, void *optr)
 {
     using C = V2<T>;
-    constexpr int CX = VTile<DIM, T>::X, CY = VTile<DIM, T>::Y, CZ = VTile<DIM, T>::Z;
+    constexpr int CX = TileSet<DIM>::X[VT], CY = TileSet<DIM>::Y[VT], CZ = DIM == 3 ? TileSet<DIM>::Z[VT] : 1;
     constexpr int FX = 2 * CX, FY = 2 * CY, FZ = DIM == 3 ? 2 * CZ : 1;
     constexpr int RX = FX + 2, RY = FY + 2, RZ = DIM == 3 ? FZ + 2 : 1;
     constexpr int RN = RX * RY * RZ;

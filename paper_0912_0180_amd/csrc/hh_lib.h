@@ -24,6 +24,7 @@ struct Plan {
     DevList coarse[5];               // k_coarse workgroups of problems with a split tail, by log2(seg)
     bool tail_down = false;          // some problem needs the (full or down-only) tail kernel
     bool tail_up = false;            // some problem needs the up-only tail kernel
+    int vdv[HH_MAXLEV] = {}, vuv[HH_MAXLEV] = {};   // tile shape of each level's down- and up-leg
     int *fin = nullptr;
     int nfin = 0;
     ProbDev *probs = nullptr;

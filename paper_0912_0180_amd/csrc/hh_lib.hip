@@ -7,6 +7,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <array>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -214,15 +216,30 @@ static void grid_release(hh_grid *g)
 // ---------------------------------------------------------------------------
 // launch plans: tile lists of every pass for a set of problems
 // ---------------------------------------------------------------------------
-static void vtile_counts(int dim, bool fp32, const HostLevel &Lf, const HostLevel &Lc, int &ndown, int &nup)
+static void tile_shape(int dim, int v, int &x, int &y, int &z)
+{
+    if (dim == 2) {
+        x = TileSet<2>::X[v];
+        y = TileSet<2>::Y[v];
+        z = 1;
+    } else {
+        x = TileSet<3>::X[v];
+        y = TileSet<3>::Y[v];
+        z = TileSet<3>::Z[v];
+    }
+}
+
+// workgroups of the down-leg (coarse tiles) and the up-leg (fine tiles of
+// twice the size) of one level for tile shape v
+static void vtile_counts(int dim, int v, const HostLevel &Lf, const HostLevel &Lc, int &ndown, int &nup)
 {
     int CX, CY, CZ;
-    if (dim == 2) { CX = 16; CY = 16; CZ = 1; }
-    else if (!fp32) { CX = VTile<3, double>::X; CY = VTile<3, double>::Y; CZ = VTile<3, double>::Z; }
-    else { CX = VTile<3, float>::X; CY = VTile<3, float>::Y; CZ = VTile<3, float>::Z; }
+    tile_shape(dim, v, CX, CY, CZ);
     ndown = ceil_div(Lc.n[0], CX) * ceil_div(Lc.n[1], CY) * (dim == 3 ? ceil_div(Lc.n[2], CZ) : 1);
     nup = ceil_div(Lf.n[0], 2 * CX) * ceil_div(Lf.n[1], 2 * CY) * (dim == 3 ? ceil_div(Lf.n[2], 2 * CZ) : 1);
 }
+
+static int tune_leg(const hh_grid *g, bool fp32, int leg, int l);
 
 void plan_release(Plan &p)
 {
@@ -339,6 +356,16 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
     std::vector<Tile> chunks, down[HH_MAXLEV], up[HH_MAXLEV], coarse[5];
     std::vector<int> fin;
     pl.tail_down = pl.tail_up = false;
+    // tile shape per level and leg, tuned on the largest problem having the level
+    for (int l = 0; l < HH_MAXLEV; ++l) {
+        pl.vdv[l] = pl.vuv[l] = 0;
+        const hh_grid *rep = nullptr;
+        for (const hh_grid *g : G)
+            if (l < tail_level(g->hs, fp32) && (!rep || g->hs.lev[l].N > rep->hs.lev[l].N)) rep = g;
+        if (!rep || rep->host_only) continue;
+        pl.vdv[l] = tune_leg(rep, fp32, 0, l);
+        pl.vuv[l] = tune_leg(rep, fp32, 1, l);
+    }
     for (int q = 0; q < pl.count; ++q) {
         const HostSetup &hs = G[q]->hs;
         const int t = tail_level(hs, fp32);
@@ -356,8 +383,9 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         for (int i = 0; i < nch; ++i) chunks.push_back(Tile{q, i});
         for (int l = 0; l < t; ++l) {
             int nd, nu;
-            vtile_counts(hs.dim, fp32, hs.lev[l], hs.lev[l + 1], nd, nu);
+            vtile_counts(hs.dim, pl.vdv[l], hs.lev[l], hs.lev[l + 1], nd, nu);
             for (int i = 0; i < nd; ++i) down[l].push_back(Tile{q, i});
+            vtile_counts(hs.dim, pl.vuv[l], hs.lev[l], hs.lev[l + 1], nd, nu);
             for (int i = 0; i < nu; ++i) up[l].push_back(Tile{q, i});
         }
         fin.push_back(q);
@@ -416,6 +444,135 @@ static Ctx ctx_of(const Plan &pl, const DevList &tiles)
     return c;
 }
 
+template <int DIM, typename T, typename TF>
+static void launch_down_v(int v, int n, hipStream_t s, const Ctx &c, int lev, int fsel, const void *fptr)
+{
+    switch (v) {
+    case 0: LAUNCH((k_vdown<DIM, T, TF, 0>), n, s, c, lev, fsel, fptr); break;
+    case 1: LAUNCH((k_vdown<DIM, T, TF, 1>), n, s, c, lev, fsel, fptr); break;
+    case 2: LAUNCH((k_vdown<DIM, T, TF, 2>), n, s, c, lev, fsel, fptr); break;
+    case 3: LAUNCH((k_vdown<DIM, T, TF, 3>), n, s, c, lev, fsel, fptr); break;
+    default: LAUNCH((k_vdown<DIM, T, TF, 4>), n, s, c, lev, fsel, fptr); break;
+    }
+}
+
+template <int DIM, typename T, typename TF, typename TO>
+static void launch_up_v(int v, int n, hipStream_t s, const Ctx &c, int lev, int fsel, int osel, const void *fptr,
+                        void *optr)
+{
+    switch (v) {
+    case 0: LAUNCH((k_vup<DIM, T, TF, TO, 0>), n, s, c, lev, fsel, osel, fptr, optr); break;
+    case 1: LAUNCH((k_vup<DIM, T, TF, TO, 1>), n, s, c, lev, fsel, osel, fptr, optr); break;
+    case 2: LAUNCH((k_vup<DIM, T, TF, TO, 2>), n, s, c, lev, fsel, osel, fptr, optr); break;
+    case 3: LAUNCH((k_vup<DIM, T, TF, TO, 3>), n, s, c, lev, fsel, osel, fptr, optr); break;
+    default: LAUNCH((k_vup<DIM, T, TF, TO, 4>), n, s, c, lev, fsel, osel, fptr, optr); break;
+    }
+}
+
+// one launch of level lev's down- (leg 0) or up-leg (leg 1) with tile shape v
+template <int DIM, typename T>
+static void launch_leg(int leg, int v, int n, hipStream_t s, const Ctx &c, int lev, int fsel, int osel,
+                       const void *fptr, void *optr)
+{
+    using C = V2<T>;
+    if (leg == 0) {
+        if (lev == 0) launch_down_v<DIM, T, double2>(v, n, s, c, lev, fsel, fptr);
+        else launch_down_v<DIM, T, C>(v, n, s, c, lev, fsel, fptr);
+    } else {
+        if (lev == 0) launch_up_v<DIM, T, double2, C>(v, n, s, c, lev, fsel, osel, fptr, optr);
+        else launch_up_v<DIM, T, C, C>(v, n, s, c, lev, fsel, osel, fptr, optr);
+    }
+}
+
+static void launch_leg_any(int dim, bool fp32, int leg, int v, int n, hipStream_t s, const Ctx &c, int lev, int fsel,
+                           int osel, const void *fptr, void *optr)
+{
+    if (dim == 2) {
+        if (fp32) launch_leg<2, float>(leg, v, n, s, c, lev, fsel, osel, fptr, optr);
+        else launch_leg<2, double>(leg, v, n, s, c, lev, fsel, osel, fptr, optr);
+    } else {
+        if (fp32) launch_leg<3, float>(leg, v, n, s, c, lev, fsel, osel, fptr, optr);
+        else launch_leg<3, double>(leg, v, n, s, c, lev, fsel, osel, fptr, optr);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tile autotuner: the fastest shape per (dimension, precision, leg, finest
+// level or not, log2 of the level's unknowns), timed on the grid at hand the
+// first time such a level is planned, then cached for the process.
+// HH_TILE=v forces shape v everywhere; HH_TUNE=0 keeps shape 0.
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<std::array<int, 5>, int> g_tune;
+
+static int tune_leg(const hh_grid *g, bool fp32, int leg, int l)
+{
+    if (const char *e = getenv("HH_TILE")) return std::min(std::max(atoi(e), 0), HH_NTILE - 1);
+    if (const char *e = getenv("HH_TUNE"))
+        if (atoi(e) == 0) return 0;
+    const HostSetup &hs = g->hs;
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= hs.lev[l].N) ++lg;
+    const std::array<int, 5> key{hs.dim, (int)fp32, leg, l == 0 ? 0 : 1, lg};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) return it->second;
+    }
+    // time every shape on this grid's level (inputs of level 0 from a
+    // scratch buffer; the level arrays it writes are rewritten by every use)
+    int best = 0;
+    const int64_t N0 = hs.lev[0].N;
+    void *in = nullptr, *out = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    if (ok && l == 0)
+        ok = hipMalloc(&in, sizeof(double2) * N0) == hipSuccess && hipMalloc(&out, sizeof(double2) * N0) == hipSuccess &&
+             hipMemsetAsync(in, 0, sizeof(double2) * N0, st) == hipSuccess;
+    if (ok) {
+        Ctx c;
+        c.P = g->pd_static_dev;
+        c.tiles = nullptr;
+        c.ctrl = nullptr;
+        c.L = fp32 ? (const void *)g->L32 : (const void *)g->L64;
+        c.omega = hs.omega;
+        float bt = 0.f, tv[HH_NTILE] = {};
+        for (int v = 0; v < HH_NTILE && ok; ++v) {
+            int nd, nu;
+            vtile_counts(hs.dim, v, hs.lev[l], hs.lev[l + 1], nd, nu);
+            const int n = leg == 0 ? nd : nu;
+            launch_leg_any(hs.dim, fp32, leg, v, n, st, c, l, VS_IN, VS_OUT, in, out);
+            ok = hipEventRecord(e0, st) == hipSuccess;
+            for (int r = 0; r < 3; ++r) launch_leg_any(hs.dim, fp32, leg, v, n, st, c, l, VS_IN, VS_OUT, in, out);
+            ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                 hipGetLastError() == hipSuccess;
+            float ms = 0.f;
+            if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            tv[v] = ms / 3.f;
+            if (ok && (v == 0 || ms < bt)) {
+                bt = ms;
+                best = v;
+            }
+        }
+        if (ok && getenv("HH_TUNE_LOG"))
+            fprintf(stderr, "hh tile tune: dim %d %s leg %s level %s 2^%d unknowns: %.1f %.1f %.1f %.1f %.1f us -> shape %d\n",
+                    hs.dim, fp32 ? "c64" : "c128", leg == 0 ? "down" : "up", l == 0 ? "finest" : "coarse", lg,
+                    tv[0] * 1e3f, tv[1] * 1e3f, tv[2] * 1e3f, tv[3] * 1e3f, tv[4] * 1e3f, best);
+    }
+    if (st) (void)hipStreamSynchronize(st);
+    if (in) (void)hipFree(in);
+    if (out) (void)hipFree(out);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    if (!ok) return 0;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+    return best;
+}
+
 template <int DIM, typename T>
 static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void *optr, hipStream_t s)
 {
@@ -425,11 +582,8 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
         fptr = pl.host.at(0).vec[fsel];
         optr = pl.host.at(0).vec[osel];
     }
-    for (int l = 0; l < pl.Lmax; ++l) {
-        const Ctx c = ctx_of(pl, pl.down[l]);
-        if (l == 0) LAUNCH((k_vdown<DIM, T, double2>), pl.down[l].n, s, c, l, fsel, fptr);
-        else LAUNCH((k_vdown<DIM, T, C>), pl.down[l].n, s, c, l, fsel, fptr);
-    }
+    for (int l = 0; l < pl.Lmax; ++l)
+        launch_leg<DIM, T>(0, pl.vdv[l], pl.down[l].n, s, ctx_of(pl, pl.down[l]), l, fsel, osel, fptr, optr);
     {
         // coarse part: tail kernel (whole, or down-legs of split problems),
         // multi-workgroup coarsest solves, up-legs of split problems
@@ -445,11 +599,8 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
         if (pl.nfin > 0 && pl.tail_up)
             hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c, probs, 1);
     }
-    for (int l = pl.Lmax - 1; l >= 0; --l) {
-        const Ctx c = ctx_of(pl, pl.up[l]);
-        if (l == 0) LAUNCH((k_vup<DIM, T, double2, TO>), pl.up[l].n, s, c, l, fsel, osel, fptr, optr);
-        else LAUNCH((k_vup<DIM, T, C, C>), pl.up[l].n, s, c, l, fsel, osel, fptr, optr);
-    }
+    for (int l = pl.Lmax - 1; l >= 0; --l)
+        launch_leg<DIM, T>(1, pl.vuv[l], pl.up[l].n, s, ctx_of(pl, pl.up[l]), l, fsel, osel, fptr, optr);
 }
 
 void launch_vcycle(const Plan &pl, int fsel, int osel, const void *fptr, void *optr, hipStream_t s)
@@ -603,9 +754,14 @@ hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_
     size_t io = 2 * align256(sizeof(double2) * N) + (s > 0 ? align256(sizeof(double2) * (size_t)N * s) : 0);
     size_t tiles = nch + (nc > HH_SPLIT_NC ? ceil_div(coarse_waves<double>(nc), HH_WG / 64) : 0);
     for (int l = 0; l + 1 < nl; ++l) {
-        int nd, nu;
-        vtile_counts(dim, fp32, L[l], L[l + 1], nd, nu);
-        tiles += nd + nu;
+        int md = 0, mu = 0;
+        for (int v = 0; v < HH_NTILE; ++v) {
+            int nd, nu;
+            vtile_counts(dim, v, L[l], L[l + 1], nd, nu);
+            md = std::max(md, nd);
+            mu = std::max(mu, nu);
+        }
+        tiles += md + mu;
     }
     size_t plan = sizeof(Tile) * (tiles + nch) + sizeof(ProbDev) + sizeof(Ctrl) + 2 * sizeof(int) +
                   256 * (2 * HH_MAXLEV + 8);

@@ -353,3 +353,26 @@ def test_graph_replay_equals_eager(torch_dev, hh_mod, monkeypatch):
         for r in out:
             assert r[1] == ref[1] and r[3] == ref[3], mode
             assert same(r[0], ref[0]) and same(r[2], ref[2]), mode
+
+
+@pytest.mark.parametrize("name", ["c2_256", "ragged_2d", "ragged_3d", "c3_32"])
+def test_every_tile_shape_gives_the_same_cycle(torch_dev, hh_mod, oracle_mod, monkeypatch, name):
+    """The autotuner may pick any tile shape: every shape must give the FP64
+    V-cycle of the oracle value for value, and one FP32 result for all."""
+    torch = torch_dev
+    c = CASES[name]()
+    print("case", name, flush=True)
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    f = rand_c(np.random.default_rng(8), o.N)
+    ref = o.vcycle(f)
+    fd = dev(torch, f)
+    u32 = None
+    for v in range(5):
+        monkeypatch.setenv("HH_TILE", str(v))
+        g = hh_mod.Grid(c["desc"], c["phi"])
+        assert same(host(g.vcycle(fd, "c128")), ref), (name, v)
+        u = host(g.vcycle(fd, "c64"))
+        if u32 is None:
+            u32 = u
+        assert same(u, u32), (name, v)
+        g.close()
