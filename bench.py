@@ -31,6 +31,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+# HBM traffic of the roofline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs (see the file); valid only while the kernel sources are unchanged
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_applyH_2d_1024_pmc.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0912_0180_amd", "csrc", f) for f in ("hh_kernels.hpp", "hh_common.h")]
+
+
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the roofline kernel from the committed counter
+    summary, or None if it is missing or the kernel changed since."""
+    try:
+        text = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "kernel_sources_sha256")):
+            k, v = line.strip().strip("`").split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def vcycle_bytes(g, fp32):
@@ -154,8 +187,8 @@ def bench_c2(args, torch, hh, W, out):
     out["applyH_us"] = th * 1e6
     out["roofline"] = {"bound": "hbm", "kernel": "hh::k_applyH<2> (y = H x, c128, variable k)",
                        "achieved": ah, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ah / HBM_PEAK_GBPS,
-                       "traffic": None, "bytes_per_unknown": 40, "unknowns_per_launch": g.N,
-                       "launch_us": th * 1e6}
+                       "traffic": measured_traffic(), "bytes_per_unknown": 40, "unknowns_per_launch": g.N,
+                       "algorithmic_bytes_per_launch": apply_bytes(g), "launch_us": th * 1e6}
     return cfg, g
 
 
@@ -322,6 +355,27 @@ def cpu_baseline(args, cfg, out):
                                      "scaled to the %d matvecs of the full FP64 solve" % (io["matvecs"], ts, full_mv)}
 
 
+def pmc_probe(torch, hh, W):
+    """Launches for counter runs: 10 operator applies at the headline size
+    and 10 elementwise copies of 512 MiB (the calibration kernel)."""
+    cfg = W.c2()
+    g = hh.Grid(cfg["desc"], cfg["phi"])
+    f = torch.randn(g.N, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(f)
+    for _ in range(10):
+        g.apply(f, "H", out=y)
+    # calibration: an elementwise kernel reading and writing 512 MiB, over two
+    # buffer pairs in turn so every source was last touched 1 GiB of traffic
+    # earlier (beyond L2 and the Infinity Cache)
+    n = (512 << 20) // 4
+    xs = [torch.ones(n, dtype=torch.int32, device="cuda") for _ in range(2)]
+    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    for i in range(10):
+        torch.mul(xs[i % 2], 1, out=ys[i % 2])
+    torch.cuda.synchronize()
+    print("pmc probe: 10 x k_applyH<2> on %d unknowns, 10 x elementwise copy of %d bytes" % (g.N, 4 * n), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -338,6 +392,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-matvecs", type=int, default=300)
     ap.add_argument("--quick", action="store_true", help="headline solve only")
+    ap.add_argument("--pmc-probe", action="store_true", help="only the launches the counter runs read")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (multi-GPU sharding is a design note, "
@@ -349,6 +404,9 @@ def main():
     from paper_0912_0180_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.pmc_probe:
+        pmc_probe(torch, hh, W)
+        return
     out = {}
     skip = set(s for s in args.skip.split(",") if s)
     cfg, g = bench_c2(args, torch, hh, W, out)
