@@ -52,11 +52,11 @@
  *                          - a_z*u_d - c_z*u_u,  Dg = (d_x + d_y + d_z) - phi
  *   Jacobi weight      g = omega*conj(Dg)/|Dg|^2 : q = omega/(Dr*Dr + Di*Di),
  *                      g = (Dr*q, -(Di*q))
- *   reductions         chunks of 2048 elements; slot t (0..255) of a chunk
- *                      sums elements t + 256 j (j = 0..7) left to right from
- *                      0.0; the 256 slots are summed by a pairwise (recursive
- *                      halving) tree; chunk partials are summed by a pairwise
- *                      tree after zero padding to a power of two.
+ *   reductions         chunks of 256 elements; slot t (0..255) of a chunk
+ *                      holds 0.0 + its element (0.0 past the end); the 256
+ *                      slots are summed by a pairwise (recursive halving)
+ *                      tree; chunk partials are summed by a pairwise tree
+ *                      after zero padding to a power of two.
  *   dense solves       LU with partial pivoting (first maximum of |re|+|im|),
  *                      k-i-j elimination, unit-lower forward substitution and
  *                      upper back substitution with ascending inner loops.
@@ -268,7 +268,7 @@ static void apply_level(const og_grid *g, int op, int lev, const cx *x, cx *y)
 /* ------------------------------------------------------------------------ */
 
 #define OG_SLOTS 256
-#define OG_PER_SLOT 8
+#define OG_PER_SLOT 1
 #define OG_CHUNK (OG_SLOTS * OG_PER_SLOT)
 
 /* Pairwise (recursive halving) sum of v[0..n), n a power of two. */

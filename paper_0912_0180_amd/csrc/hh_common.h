@@ -19,7 +19,7 @@
 
 #define HH_MAXLEV 16
 #define HH_WG 256                 // threads per workgroup (4 wave64)
-#define HH_PER_SLOT 8             // elements per thread slot in a reduction chunk
+#define HH_PER_SLOT 1             // elements per thread slot in a reduction chunk (chunk = 256)
 #define HH_CHUNK (HH_WG * HH_PER_SLOT)
 #define HH_NPART 40               // reals per chunk partial record (IDR(8) start-up needs 4s+1)
 #define HH_MAX_COARSE 1024
@@ -210,7 +210,7 @@ struct ProbDev {
     double2 *dR, *dX;                // IDR: s columns of N each
     int nidr;                        // IDR: s
     const double2 *P;                // IDR shadow space, N x s column-major
-    double *part;                    // [nchunk * HH_NPART]
+    double *part;                    // chunk partials, value-major: part[v * nchunk + c], v < HH_NPART
     SolveState *st;
     Ctrl *ctrl;                      // this problem's slot in the plan's control array
     double *hist;                    // device history (optional)

@@ -31,9 +31,9 @@ namespace hh {
 // ---------------------------------------------------------------------------
 
 // Pairwise tree over the 256 thread slots of a 256-thread workgroup; thread 0
-// writes the NV sums to out[0..NV).
+// writes the NV sums to out[q * stride], q < NV.
 template <int NV>
-__device__ inline void block_reduce(double (&v)[NV], double *out)
+__device__ inline void block_reduce(double (&v)[NV], double *out, int64_t stride = 1)
 {
     __shared__ double red[4 * NV];
 #pragma unroll
@@ -47,7 +47,7 @@ __device__ inline void block_reduce(double (&v)[NV], double *out)
     __syncthreads();
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int q = 0; q < NV; ++q) out[q] = (red[q] + red[NV + q]) + (red[2 * NV + q] + red[3 * NV + q]);
+        for (int q = 0; q < NV; ++q) out[q * stride] = (red[q] + red[NV + q]) + (red[2 * NV + q] + red[3 * NV + q]);
 }
 
 
@@ -254,17 +254,84 @@ __device__ inline void record(const ProbDev *pd, SolveState *st, double rel)
     if (pd->hist && st->mv - 1 < st->hist_len && st->mv >= 1) pd->hist[st->mv - 1] = rel;
 }
 
-// Sums value q (q < nv) of the chunk partial records part[c * HH_NPART + q]
-// over the n chunks, each by the pairwise tree over the zero-padded
-// power-of-two length; results in out[q].  The partials are staged in LDS in
-// blocks of HH_FIN_STAGE entries (an aligned power-of-two block of a pairwise
-// tree is itself a subtree, so block sums combine exactly).
-__device__ void reduce_partials(const double *part, int n, int nv, double *out)
+// Sums value first + q (q < nv) of the chunk partials, stored value-major
+// (part[v * n + c] for chunk c of n), each by the pairwise tree over the
+// zero-padded power-of-two length; results in out[q].  The partials are
+// staged in LDS in blocks of HH_FIN_STAGE entries (an aligned power-of-two
+// block of a pairwise tree is itself a subtree, so block sums combine
+// exactly).
+// np = PER * 256 partials of each of G values.  Loads are coalesced
+// (thread t takes partials t + 256 i), then transposed through LDS (one
+// padding word per 16 against bank conflicts) so that thread t sums the
+// aligned block [t PER, (t+1) PER) pairwise in registers; the 256 block sums
+// are combined by the wave butterfly and the four-wave sum (block_reduce),
+// which is the same tree.  Zero past n.  lds holds PER * 256 * 17 / 16
+// doubles.
+template <int PER, int G>
+__device__ inline void reduce_values_blocked(const double *part, int n, int64_t off, int ng, double *out, double *lds)
+{
+    const int t = (int)threadIdx.x;
+    double r[G][PER];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = t + HH_WG * i;
+            r[g][i] = (g < ng && e < n) ? ldg(part, off + (int64_t)g * n + e) : 0.0;
+        }
+    double sums[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = t + HH_WG * i;
+            lds[e + (e >> 4)] = r[g][i];
+        }
+        __syncthreads();
+        double v[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = t * PER + i;
+            v[i] = lds[e + (e >> 4)];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 1; w < PER; w <<= 1)
+#pragma unroll
+            for (int i = 0; i + w < PER; i += 2 * w) v[i] = v[i] + v[i + w];
+        sums[g] = v[0];
+    }
+    __shared__ double tmp[G];
+    block_reduce<G>(sums, tmp);
+    __syncthreads();
+    if (t < ng) out[t] = tmp[t];
+}
+
+__device__ void reduce_partials(const double *part, int n, int first, int nv, double *out)
 {
     __shared__ double stage[HH_FIN_STAGE];
     __shared__ double bsum[4 * HH_MAX_S + 4][64];
     int np = 1;
     while (np < n) np <<= 1;
+    if (np >= HH_WG && np <= 32 * HH_WG) {
+        // groups of up to 4 values in flight (1 for the longest blocks); the
+        // transpose uses the staging buffer
+        const int per = np / HH_WG, G = per <= 16 ? 4 : 1;
+        for (int q = 0; q < nv; q += G) {
+            const int64_t off = (int64_t)(first + q) * n;
+            const int ng = nv - q < G ? nv - q : G;
+            switch (per) {
+            case 1: reduce_values_blocked<1, 4>(part, n, off, ng, out + q, stage); break;
+            case 2: reduce_values_blocked<2, 4>(part, n, off, ng, out + q, stage); break;
+            case 4: reduce_values_blocked<4, 4>(part, n, off, ng, out + q, stage); break;
+            case 8: reduce_values_blocked<8, 4>(part, n, off, ng, out + q, stage); break;
+            case 16: reduce_values_blocked<16, 4>(part, n, off, ng, out + q, stage); break;
+            default: reduce_values_blocked<32, 1>(part, n, off, ng, out + q, stage); break;
+            }
+            __syncthreads();   // block_reduce's LDS is reused by the next group
+        }
+        return;
+    }
     // values per staging pass: all nv at once when they fit
     const int blk = np < HH_FIN_STAGE ? np : HH_FIN_STAGE;
     const int qstep = (HH_FIN_STAGE / blk) < nv ? (HH_FIN_STAGE / blk) : nv;
@@ -273,19 +340,19 @@ __device__ void reduce_partials(const double *part, int n, int nv, double *out)
         const int nq = nv - q0 < qstep ? nv - q0 : qstep;
         for (int b = 0; b < nblk; ++b) {
             const int tot = nq * blk;
-            for (int e0 = 0; e0 < tot; e0 += 8 * HH_WG) {
-                double tmp[8];
+            for (int e0 = 0; e0 < tot; e0 += 16 * HH_WG) {
+                double tmp[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < 16; ++u) {
                     const int e = e0 + threadIdx.x + u * HH_WG;
                     tmp[u] = 0.0;
                     if (e < tot) {
                         const int qq = e / blk, c = b * blk + (e - qq * blk);
-                        if (c < n) tmp[u] = ldg(part, (int64_t)c * HH_NPART + q0 + qq);
+                        if (c < n) tmp[u] = ldg(part, (int64_t)(first + q0 + qq) * n + c);
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < 16; ++u) {
                     const int e = e0 + threadIdx.x + u * HH_WG;
                     if (e < tot) stage[e] = tmp[u];
                 }
@@ -393,7 +460,7 @@ __device__ void finalize(const ProbDev *pd, int kind)
                  : (kind == FIN_S || kind == FIN_BNORM || kind == FIN_TRUE) ? 1 : (kind == FIN_ALPHA ? 2 : 3);
     const int first = (kind == FIN_BNORM || kind == FIN_TRUE) ? 2 : 0;
     __shared__ double res[4 * HH_MAX_S + 4];
-    reduce_partials(pd->part + first, pd->nchunk, nv, res);
+    reduce_partials(pd->part, pd->nchunk, first, nv, res);
     const double *s = res;
     if (threadIdx.x != 0) return;
     if (kind >= FIN_IDR_OMEGA) {
@@ -508,15 +575,17 @@ __device__ void finalize(const ProbDev *pd, int kind)
 template <int NV>
 __device__ inline void chunk_finish(const ProbDev *pd, int chunk, double (&acc)[NV], int)
 {
-    block_reduce<NV>(acc, pd->part + (int64_t)chunk * HH_NPART);
+    block_reduce<NV>(acc, pd->part + chunk, pd->nchunk);
 }
 
 // One workgroup per problem: sums the chunk partials of the pass just run and
 // advances the scalar state (kind = FinKind).
 __global__ __launch_bounds__(HH_WG) void k_fin(Ctx cx, const int *__restrict__ probs, int kind)
 {
-    const ProbDev *pd = cx.P + (probs ? probs[blockIdx.x] : 0);
-    const int phase = pd->st->phase;
+    const int prob = probs ? probs[blockIdx.x] : 0;
+    const ProbDev *pd = cx.P + prob;
+    // the control block mirrors the phase of the state block; one load
+    const int phase = phase_of(cx, prob);
     if (kind == FIN_RHO) {
         if (phase != PH_RUN && phase != PH_HALF) return;
     } else if (kind == FIN_ALPHA || kind == FIN_S || kind == FIN_OMEGA) {

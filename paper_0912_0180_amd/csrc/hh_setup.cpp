@@ -191,7 +191,8 @@ hh_status desc_check(const hh_grid_desc *d, int &levels, int &coarse, std::strin
         }
         N *= d->n[a];
     }
-    if (N >= ((int64_t)1 << 31)) { err = "more than 2^31 - 1 unknowns"; return HH_ERR_ARG; }
+    // the finaliser stages at most 64 blocks of HH_FIN_STAGE chunk partials
+    if (N > ((int64_t)1 << 28)) { err = "more than 2^28 unknowns"; return HH_ERR_ARG; }
     const int nl = d->levels > 0 ? d->levels : auto_levels(dim, d->n);
     if (nl > HH_MAXLEV) { err = "too many levels"; return HH_ERR_ARG; }
     if (nl < 2) { err = "the multigrid preconditioner needs at least 2 levels (set levels, or use a larger grid)"; return HH_ERR_ARG; }

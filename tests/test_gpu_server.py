@@ -181,15 +181,16 @@ def test_destroy_with_requests_in_flight(hh_mod):
     sv.close()          # running and queued requests are dropped; no leak, no hang
 
 
-def test_server_drift_fallback_matches_alone(hh_mod):
-    """A request whose mixed solve drifts continues in the FP64 group and
-    returns what hh_solve returns for it alone."""
+def test_server_drift_fallback_matches_alone(hh_mod, monkeypatch):
+    """A request whose mixed solve drifts (forced by a 3-matvec stall limit)
+    continues in the FP64 group and returns what hh_solve returns for it
+    alone; a request in FP64 from the start is unaffected."""
     hh = hh_mod
-    p = W.c4(64)[27]
-    req = {"desc": p["desc"], "phi": p["phi"], "b": p["b"], "method": "bicgstab", "vcycle_prec": "c64", "s": 4}
+    monkeypatch.setenv("HH_DRIFT_STALL", "3")
+    req = small_request(seed=32, dim=2, n=128)
     xa, ia = solve_alone(hh, req)
     assert ia["fp64_fallback"] == 1
-    small = small_request(seed=31, dim=2, n=96)
+    small = small_request(seed=31, dim=2, n=96, prec="c128")
     xs, is_ = solve_alone(hh, small)
     sv = hh.Server(max_slots=4)
     try:

@@ -469,7 +469,7 @@ def test_zero_rhs_and_limits(oracle_mod):
 
 def test_blocked_reductions(oracle_mod):
     rng = np.random.default_rng(9)
-    for n in (1, 255, 2048, 2049, 70001):
+    for n in (1, 255, 256, 257, 2048, 2049, 70001):
         xi = rng.integers(-1000, 1000, size=n) + 1j * rng.integers(-1000, 1000, size=n)
         yi = rng.integers(-1000, 1000, size=n) + 1j * rng.integers(-1000, 1000, size=n)
         exact = np.sum(np.conj(xi) * yi)  # integers: exact in FP64
