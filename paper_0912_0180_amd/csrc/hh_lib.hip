@@ -543,14 +543,19 @@ static int tune_leg(const hh_grid *g, bool fp32, int leg, int l)
             int nd, nu;
             vtile_counts(hs.dim, v, hs.lev[l], hs.lev[l + 1], nd, nu);
             const int n = leg == 0 ? nd : nu;
-            launch_leg_any(hs.dim, fp32, leg, v, n, st, c, l, VS_IN, VS_OUT, in, out);
-            ok = hipEventRecord(e0, st) == hipSuccess;
-            for (int r = 0; r < 3; ++r) launch_leg_any(hs.dim, fp32, leg, v, n, st, c, l, VS_IN, VS_OUT, in, out);
-            ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-                 hipGetLastError() == hipSuccess;
-            float ms = 0.f;
-            if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-            tv[v] = ms / 3.f;
+            // two warm-up launches, then the median of five timed ones
+            for (int r = 0; r < 2; ++r) launch_leg_any(hs.dim, fp32, leg, v, n, st, c, l, VS_IN, VS_OUT, in, out);
+            float rep[5];
+            for (int r = 0; r < 5 && ok; ++r) {
+                ok = hipEventRecord(e0, st) == hipSuccess;
+                launch_leg_any(hs.dim, fp32, leg, v, n, st, c, l, VS_IN, VS_OUT, in, out);
+                ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                     hipGetLastError() == hipSuccess && hipEventElapsedTime(&rep[r], e0, e1) == hipSuccess;
+            }
+            if (!ok) break;
+            std::sort(rep, rep + 5);
+            const float ms = rep[2];
+            tv[v] = ms;
             if (ok && (v == 0 || ms < bt)) {
                 bt = ms;
                 best = v;
