@@ -136,6 +136,13 @@ template <typename T> struct LevelDev {
     V2<T> *e;                        // level solution / correction (levels >= 1)
 };
 
+// the two levels a V-cycle level kernel works on, passed by value for
+// one-problem launches (valid = 0: read them from the problem's descriptor)
+template <typename T> struct LvPair {
+    LevelDev<T> f, c;
+    int valid;
+};
+
 // vectors a problem can name in a kernel argument
 enum VecSel {
     VS_X = 0, VS_B, VS_R, VS_RH, VS_P, VS_V, VS_T, VS_PH, VS_SH, VS_IN, VS_OUT, VS_W, VS_Q, VS_TMP,

@@ -657,7 +657,7 @@ __global__ __launch_bounds__(HH_WG) void k_applyM(Ctx cx, const void *xp, void *
 // with a halo of 2 (restriction footprint + stencil).
 // ---------------------------------------------------------------------------
 template <int DIM, typename T, typename TF, int VT>
-__global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, const void *fptr)
+__global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, const void *fptr, LvPair<T> lp)
 {
     using C = V2<T>;
     constexpr int CX = TileSet<DIM>::X[VT], CY = TileSet<DIM>::Y[VT], CZ = DIM == 3 ? TileSet<DIM>::Z[VT] : 1;
@@ -673,17 +673,29 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, cons
     __shared__ C Dd[3][RM];
 
     const Tile tl = tile_of(cx);
-    if (phase_of(cx, tl.prob) != PH_RUN) return;
     const ProbDev *pd = cx.P + tl.prob;
-    const LevelDev<T> *Lv = levels_of<T>(cx, pd);
-    const int nfx = Lv[lev].n[0], nfy = Lv[lev].n[1], nfz = Lv[lev].n[2];
-    const int ncx = Lv[lev + 1].n[0], ncy = Lv[lev + 1].n[1], ncz = Lv[lev + 1].n[2];
-    const V2<T> *ax0 = Lv[lev].a[0], *cx0 = Lv[lev].c[0], *dx0 = Lv[lev].d[0];
-    const V2<T> *ax1 = Lv[lev].a[1], *cx1 = Lv[lev].c[1], *dx1 = Lv[lev].d[1];
-    const V2<T> *ax2 = Lv[lev].a[2], *cx2 = Lv[lev].c[2], *dx2 = Lv[lev].d[2];
-    const T *__restrict__ phi = Lv[lev].phi;
-    C *__restrict__ fout = Lv[lev + 1].f;
-    const TF *__restrict__ f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lv[lev].f;
+    // one problem: the level descriptors come by value and the phase load
+    // overlaps the data loads; a batch reads both from memory first
+    LevelDev<T> Lf, Lc;
+    int run = PH_RUN;
+    if (lp.valid) {
+        run = phase_of(cx, tl.prob);
+        Lf = lp.f;
+        Lc = lp.c;
+    } else {
+        if (phase_of(cx, tl.prob) != PH_RUN) return;
+        const LevelDev<T> *Lv = levels_of<T>(cx, pd);
+        Lf = Lv[lev];
+        Lc = Lv[lev + 1];
+    }
+    const int nfx = Lf.n[0], nfy = Lf.n[1], nfz = Lf.n[2];
+    const int ncx = Lc.n[0], ncy = Lc.n[1], ncz = Lc.n[2];
+    const V2<T> *ax0 = Lf.a[0], *cx0 = Lf.c[0], *dx0 = Lf.d[0];
+    const V2<T> *ax1 = Lf.a[1], *cx1 = Lf.c[1], *dx1 = Lf.d[1];
+    const V2<T> *ax2 = Lf.a[2], *cx2 = Lf.c[2], *dx2 = Lf.d[2];
+    const T *__restrict__ phi = Lf.phi;
+    C *__restrict__ fout = Lc.f;
+    const TF *__restrict__ f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lf.f;
     const T omega = (T)(cx.L ? cx.omega : pd->omega);
     const int tx = (ncx + CX - 1) / CX, ty = (ncy + CY - 1) / CY;
     int t = tl.idx;
@@ -723,6 +735,7 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, cons
         Cc[ax][q] = in ? ldg(pc, g) : zero;
         Dd[ax][q] = in ? ldg(pdd, g) : zero;
     }
+    if (run != PH_RUN) return;   // uniform over the workgroup
     __syncthreads();
     // step 1: u1 = g f on the whole box
 #pragma unroll
@@ -809,7 +822,8 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, cons
 // Output: e_lev (lev >= 1) or the output vector (lev == 0, storage TO).
 // ---------------------------------------------------------------------------
 template <int DIM, typename T, typename TF, typename TO, int VT>
-__global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int osel, const void *fptr, void *optr)
+__global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int osel, const void *fptr, void *optr,
+                                                LvPair<T> lp)
 {
     using C = V2<T>;
     constexpr int CX = TileSet<DIM>::X[VT], CY = TileSet<DIM>::Y[VT], CZ = DIM == 3 ? TileSet<DIM>::Z[VT] : 1;
@@ -830,18 +844,30 @@ __global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int os
     __shared__ C Dd[3][RM];
 
     const Tile tl = tile_of(cx);
-    if (phase_of(cx, tl.prob) != PH_RUN) return;
     const ProbDev *pd = cx.P + tl.prob;
-    const LevelDev<T> *Lv = levels_of<T>(cx, pd);
-    const int nfx = Lv[lev].n[0], nfy = Lv[lev].n[1], nfz = Lv[lev].n[2];
-    const int ncx = Lv[lev + 1].n[0], ncy = Lv[lev + 1].n[1], ncz = Lv[lev + 1].n[2];
-    const V2<T> *ax0 = Lv[lev].a[0], *cx0 = Lv[lev].c[0], *dx0 = Lv[lev].d[0];
-    const V2<T> *ax1 = Lv[lev].a[1], *cx1 = Lv[lev].c[1], *dx1 = Lv[lev].d[1];
-    const V2<T> *ax2 = Lv[lev].a[2], *cx2 = Lv[lev].c[2], *dx2 = Lv[lev].d[2];
-    const T *__restrict__ phi = Lv[lev].phi;
-    const C *__restrict__ ec = Lv[lev + 1].e;
-    C *__restrict__ eout = Lv[lev].e;
-    const TF *__restrict__ f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lv[lev].f;
+    // one problem: the level descriptors come by value and the phase load
+    // overlaps the data loads; a batch reads both from memory first
+    LevelDev<T> Lf, Lc;
+    int run = PH_RUN;
+    if (lp.valid) {
+        run = phase_of(cx, tl.prob);
+        Lf = lp.f;
+        Lc = lp.c;
+    } else {
+        if (phase_of(cx, tl.prob) != PH_RUN) return;
+        const LevelDev<T> *Lv = levels_of<T>(cx, pd);
+        Lf = Lv[lev];
+        Lc = Lv[lev + 1];
+    }
+    const int nfx = Lf.n[0], nfy = Lf.n[1], nfz = Lf.n[2];
+    const int ncx = Lc.n[0], ncy = Lc.n[1], ncz = Lc.n[2];
+    const V2<T> *ax0 = Lf.a[0], *cx0 = Lf.c[0], *dx0 = Lf.d[0];
+    const V2<T> *ax1 = Lf.a[1], *cx1 = Lf.c[1], *dx1 = Lf.d[1];
+    const V2<T> *ax2 = Lf.a[2], *cx2 = Lf.c[2], *dx2 = Lf.d[2];
+    const T *__restrict__ phi = Lf.phi;
+    const C *__restrict__ ec = Lc.e;
+    C *__restrict__ eout = Lf.e;
+    const TF *__restrict__ f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lf.f;
     TO *__restrict__ outv = lev == 0 ? (TO *)(optr ? optr : pd->vec[osel]) : nullptr;
     const T omega = (T)(cx.L ? cx.omega : pd->omega);
     const int tx = (nfx + FX - 1) / FX, ty = (nfy + FY - 1) / FY;
@@ -898,6 +924,7 @@ __global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int os
         const int l = threadIdx.x + q * HH_WG;
         if (l < EN) E[l] = er[q];
     }
+    if (run != PH_RUN) return;   // uniform over the workgroup
     __syncthreads();
     const T p3 = (T)0.75, p1 = (T)0.25;
     // step 1: u2 = g f + P e on the tile plus a halo of one

@@ -30,6 +30,8 @@ struct Plan {
     ProbDev *probs = nullptr;
     Ctrl *ctrl = nullptr;            // per-problem control blocks (device)
     const void *L1 = nullptr;        // one-problem plans: LevelDev array of the V-cycle precision
+    const LevelDev<double> *lv64h = nullptr;   // one-problem plans: host copies of its level descriptors
+    const LevelDev<float> *lv32h = nullptr;
     double omega1 = 0.8;
     std::vector<ProbDev> host;       // host copies of the descriptors of the current solve
     void *mem = nullptr;

@@ -419,6 +419,8 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
     if (pl.count == 1) {
         pl.L1 = fp32 ? (const void *)G[0]->L32 : (const void *)G[0]->L64;
         pl.omega1 = G[0]->hs.omega;
+        pl.lv64h = G[0]->L64h;
+        pl.lv32h = G[0]->L32h;
     }
     return HH_OK;
 }
@@ -445,54 +447,71 @@ static Ctx ctx_of(const Plan &pl, const DevList &tiles)
 }
 
 template <int DIM, typename T, typename TF>
-static void launch_down_v(int v, int n, hipStream_t s, const Ctx &c, int lev, int fsel, const void *fptr)
+static void launch_down_v(int v, int n, hipStream_t s, const Ctx &c, int lev, int fsel, const void *fptr,
+                          const LvPair<T> &lp)
 {
     switch (v) {
-    case 0: LAUNCH((k_vdown<DIM, T, TF, 0>), n, s, c, lev, fsel, fptr); break;
-    case 1: LAUNCH((k_vdown<DIM, T, TF, 1>), n, s, c, lev, fsel, fptr); break;
-    case 2: LAUNCH((k_vdown<DIM, T, TF, 2>), n, s, c, lev, fsel, fptr); break;
-    case 3: LAUNCH((k_vdown<DIM, T, TF, 3>), n, s, c, lev, fsel, fptr); break;
-    default: LAUNCH((k_vdown<DIM, T, TF, 4>), n, s, c, lev, fsel, fptr); break;
+    case 0: LAUNCH((k_vdown<DIM, T, TF, 0>), n, s, c, lev, fsel, fptr, lp); break;
+    case 1: LAUNCH((k_vdown<DIM, T, TF, 1>), n, s, c, lev, fsel, fptr, lp); break;
+    case 2: LAUNCH((k_vdown<DIM, T, TF, 2>), n, s, c, lev, fsel, fptr, lp); break;
+    case 3: LAUNCH((k_vdown<DIM, T, TF, 3>), n, s, c, lev, fsel, fptr, lp); break;
+    default: LAUNCH((k_vdown<DIM, T, TF, 4>), n, s, c, lev, fsel, fptr, lp); break;
     }
 }
 
 template <int DIM, typename T, typename TF, typename TO>
 static void launch_up_v(int v, int n, hipStream_t s, const Ctx &c, int lev, int fsel, int osel, const void *fptr,
-                        void *optr)
+                        void *optr, const LvPair<T> &lp)
 {
     switch (v) {
-    case 0: LAUNCH((k_vup<DIM, T, TF, TO, 0>), n, s, c, lev, fsel, osel, fptr, optr); break;
-    case 1: LAUNCH((k_vup<DIM, T, TF, TO, 1>), n, s, c, lev, fsel, osel, fptr, optr); break;
-    case 2: LAUNCH((k_vup<DIM, T, TF, TO, 2>), n, s, c, lev, fsel, osel, fptr, optr); break;
-    case 3: LAUNCH((k_vup<DIM, T, TF, TO, 3>), n, s, c, lev, fsel, osel, fptr, optr); break;
-    default: LAUNCH((k_vup<DIM, T, TF, TO, 4>), n, s, c, lev, fsel, osel, fptr, optr); break;
+    case 0: LAUNCH((k_vup<DIM, T, TF, TO, 0>), n, s, c, lev, fsel, osel, fptr, optr, lp); break;
+    case 1: LAUNCH((k_vup<DIM, T, TF, TO, 1>), n, s, c, lev, fsel, osel, fptr, optr, lp); break;
+    case 2: LAUNCH((k_vup<DIM, T, TF, TO, 2>), n, s, c, lev, fsel, osel, fptr, optr, lp); break;
+    case 3: LAUNCH((k_vup<DIM, T, TF, TO, 3>), n, s, c, lev, fsel, osel, fptr, optr, lp); break;
+    default: LAUNCH((k_vup<DIM, T, TF, TO, 4>), n, s, c, lev, fsel, osel, fptr, optr, lp); break;
     }
 }
+
+// host copies of one problem's level descriptors (null for a batch)
+struct LvHost {
+    const LevelDev<double> *d = nullptr;
+    const LevelDev<float> *f = nullptr;
+};
+template <typename T> static const LevelDev<T> *lv_of(const LvHost &h);
+template <> const LevelDev<double> *lv_of<double>(const LvHost &h) { return h.d; }
+template <> const LevelDev<float> *lv_of<float>(const LvHost &h) { return h.f; }
 
 // one launch of level lev's down- (leg 0) or up-leg (leg 1) with tile shape v
 template <int DIM, typename T>
 static void launch_leg(int leg, int v, int n, hipStream_t s, const Ctx &c, int lev, int fsel, int osel,
-                       const void *fptr, void *optr)
+                       const void *fptr, void *optr, const LvHost &lh)
 {
     using C = V2<T>;
+    LvPair<T> lp;
+    memset(&lp, 0, sizeof lp);
+    if (const LevelDev<T> *L = lv_of<T>(lh)) {
+        lp.f = L[lev];
+        lp.c = L[lev + 1];
+        lp.valid = 1;
+    }
     if (leg == 0) {
-        if (lev == 0) launch_down_v<DIM, T, double2>(v, n, s, c, lev, fsel, fptr);
-        else launch_down_v<DIM, T, C>(v, n, s, c, lev, fsel, fptr);
+        if (lev == 0) launch_down_v<DIM, T, double2>(v, n, s, c, lev, fsel, fptr, lp);
+        else launch_down_v<DIM, T, C>(v, n, s, c, lev, fsel, fptr, lp);
     } else {
-        if (lev == 0) launch_up_v<DIM, T, double2, C>(v, n, s, c, lev, fsel, osel, fptr, optr);
-        else launch_up_v<DIM, T, C, C>(v, n, s, c, lev, fsel, osel, fptr, optr);
+        if (lev == 0) launch_up_v<DIM, T, double2, C>(v, n, s, c, lev, fsel, osel, fptr, optr, lp);
+        else launch_up_v<DIM, T, C, C>(v, n, s, c, lev, fsel, osel, fptr, optr, lp);
     }
 }
 
 static void launch_leg_any(int dim, bool fp32, int leg, int v, int n, hipStream_t s, const Ctx &c, int lev, int fsel,
-                           int osel, const void *fptr, void *optr)
+                           int osel, const void *fptr, void *optr, const LvHost &lh)
 {
     if (dim == 2) {
-        if (fp32) launch_leg<2, float>(leg, v, n, s, c, lev, fsel, osel, fptr, optr);
-        else launch_leg<2, double>(leg, v, n, s, c, lev, fsel, osel, fptr, optr);
+        if (fp32) launch_leg<2, float>(leg, v, n, s, c, lev, fsel, osel, fptr, optr, lh);
+        else launch_leg<2, double>(leg, v, n, s, c, lev, fsel, osel, fptr, optr, lh);
     } else {
-        if (fp32) launch_leg<3, float>(leg, v, n, s, c, lev, fsel, osel, fptr, optr);
-        else launch_leg<3, double>(leg, v, n, s, c, lev, fsel, osel, fptr, optr);
+        if (fp32) launch_leg<3, float>(leg, v, n, s, c, lev, fsel, osel, fptr, optr, lh);
+        else launch_leg<3, double>(leg, v, n, s, c, lev, fsel, osel, fptr, optr, lh);
     }
 }
 
@@ -538,17 +557,20 @@ static int tune_leg(const hh_grid *g, bool fp32, int leg, int l)
         c.ctrl = nullptr;
         c.L = fp32 ? (const void *)g->L32 : (const void *)g->L64;
         c.omega = hs.omega;
+        LvHost lh;
+        lh.d = g->L64h;
+        lh.f = g->L32h;
         float bt = 0.f, tv[HH_NTILE] = {};
         for (int v = 0; v < HH_NTILE && ok; ++v) {
             int nd, nu;
             vtile_counts(hs.dim, v, hs.lev[l], hs.lev[l + 1], nd, nu);
             const int n = leg == 0 ? nd : nu;
             // two warm-up launches, then the median of five timed ones
-            for (int r = 0; r < 2; ++r) launch_leg_any(hs.dim, fp32, leg, v, n, st, c, l, VS_IN, VS_OUT, in, out);
+            for (int r = 0; r < 2; ++r) launch_leg_any(hs.dim, fp32, leg, v, n, st, c, l, VS_IN, VS_OUT, in, out, lh);
             float rep[5];
             for (int r = 0; r < 5 && ok; ++r) {
                 ok = hipEventRecord(e0, st) == hipSuccess;
-                launch_leg_any(hs.dim, fp32, leg, v, n, st, c, l, VS_IN, VS_OUT, in, out);
+                launch_leg_any(hs.dim, fp32, leg, v, n, st, c, l, VS_IN, VS_OUT, in, out, lh);
                 ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
                      hipGetLastError() == hipSuccess && hipEventElapsedTime(&rep[r], e0, e1) == hipSuccess;
             }
@@ -587,8 +609,13 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
         fptr = pl.host.at(0).vec[fsel];
         optr = pl.host.at(0).vec[osel];
     }
+    LvHost lh;
+    if (pl.count == 1) {
+        lh.d = pl.lv64h;
+        lh.f = pl.lv32h;
+    }
     for (int l = 0; l < pl.Lmax; ++l)
-        launch_leg<DIM, T>(0, pl.vdv[l], pl.down[l].n, s, ctx_of(pl, pl.down[l]), l, fsel, osel, fptr, optr);
+        launch_leg<DIM, T>(0, pl.vdv[l], pl.down[l].n, s, ctx_of(pl, pl.down[l]), l, fsel, osel, fptr, optr, lh);
     {
         // coarse part: tail kernel (whole, or down-legs of split problems),
         // multi-workgroup coarsest solves, up-legs of split problems
@@ -605,7 +632,7 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
             hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c, probs, 1);
     }
     for (int l = pl.Lmax - 1; l >= 0; --l)
-        launch_leg<DIM, T>(1, pl.vuv[l], pl.up[l].n, s, ctx_of(pl, pl.up[l]), l, fsel, osel, fptr, optr);
+        launch_leg<DIM, T>(1, pl.vuv[l], pl.up[l].n, s, ctx_of(pl, pl.up[l]), l, fsel, osel, fptr, optr, lh);
 }
 
 void launch_vcycle(const Plan &pl, int fsel, int osel, const void *fptr, void *optr, hipStream_t s)
