@@ -1017,7 +1017,7 @@ template <typename T> __host__ __device__ constexpr int coarse_slots(int seg)
     return sizeof(T) == 8 ? (seg > 8 ? seg : 8) : 16;
 }
 
-template <typename T, int SEG>
+template <typename T, int SEG, bool MLDS = false>
 __device__ inline void coarse_rows_seg(const V2<T> *__restrict__ Minv, const V2<T> *f, V2<T> *e, int n, int row0, int rstep)
 {
     constexpr int NS = coarse_slots<T>(SEG);
@@ -1033,7 +1033,8 @@ __device__ inline void coarse_rows_seg(const V2<T> *__restrict__ Minv, const V2<
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int row = rb + ((h + q) / SEG) * rstep, col = lane * SEG + (h + q) % SEG;
-                mv[q] = ldg(Minv, (row < n && col < n) ? (int64_t)row * n + col : 0);
+                const int64_t idx = (row < n && col < n) ? (int64_t)row * n + col : 0;
+                mv[q] = MLDS ? Minv[idx] : ldg(Minv, idx);
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -1061,6 +1062,7 @@ __device__ inline void coarse_rows_seg(const V2<T> *__restrict__ Minv, const V2<
         constexpr int RG = RPB < 4 ? RPB : 4;
 #pragma unroll
         for (int r0 = 0; r0 < RPB; r0 += RG) {
+            if (rb + r0 * rstep >= n) break;   // rest of the batch past the last row (uniform)
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
 #pragma unroll
@@ -1091,12 +1093,12 @@ __host__ __device__ inline int coarse_seg(int n)
     while (np < n) np <<= 1;
     return np >> 6;
 }
-template <typename T>
+template <typename T, bool MLDS>
 __device__ inline void coarse_rows_tail(const V2<T> *__restrict__ Minv, const V2<T> *f, V2<T> *e, int n, int row0, int rstep)
 {
     static_assert(HH_SPLIT_NC <= 128, "tail coarse solve handles seg 1 and 2");
-    if (coarse_seg(n) == 1) coarse_rows_seg<T, 1>(Minv, f, e, n, row0, rstep);
-    else coarse_rows_seg<T, 2>(Minv, f, e, n, row0, rstep);
+    if (coarse_seg(n) == 1) coarse_rows_seg<T, 1, MLDS>(Minv, f, e, n, row0, rstep);
+    else coarse_rows_seg<T, 2, MLDS>(Minv, f, e, n, row0, rstep);
 }
 
 template <typename T> __device__ inline V2<T> jweight(V2<T> D, T omega)
@@ -1246,6 +1248,10 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
     const C zero = cmk<T>(0, 0);
     const int tid = threadIdx.x, nth = TailCap<T>::WG;
     __shared__ TailTab tab;
+    __shared__ C minv_lds[TailMinv<T>::N];
+    // FP32 with a coarsest grid of at most 64 unknowns: the coarsest inverse
+    // (32 KiB) comes into LDS with the image, off the critical path
+    const bool mlds = sizeof(T) == 4 && !up && !split && pd->Nc <= TailMinv<T>::N / 64 && pd->Nc <= 64;
     const C *fg_top = Lv[t0].f;
     C *eg_top = Lv[t0].e;
     const C *__restrict__ Minv = (const C *)(sizeof(T) == 8 ? (const void *)pd->Minv64 : (const void *)pd->Minv32);
@@ -1256,6 +1262,21 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
         const void *img = sizeof(T) == 8 ? pd->timg64 : pd->timg32;
         const int n16 = (sizeof(T) == 8 ? pd->timg_bytes64 : pd->timg_bytes32) / 16;
         hh_uvec4 *l16 = (hh_uvec4 *)lds;
+        if (mlds) {
+            constexpr int MT = (TailMinv<T>::N + TailCap<T>::WG - 1) / TailCap<T>::WG;
+            const int nm = pd->Nc * pd->Nc;
+            C mt[MT];
+#pragma unroll
+            for (int q = 0; q < MT; ++q) {
+                const int i = tid + q * nth;
+                if (i < nm) mt[q] = ldg(Minv, i);
+            }
+#pragma unroll
+            for (int q = 0; q < MT; ++q) {
+                const int i = tid + q * nth;
+                if (i < nm) minv_lds[i] = mt[q];
+            }
+        }
         for (int b = 0; b < n16; b += 8 * nth) {
             hh_uvec4 tmp[8];
 #pragma unroll
@@ -1359,7 +1380,13 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
     // coarsest solve
     if (!up) {
         const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, L - 1);
-        coarse_rows_tail<T>(Minv, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
+        if constexpr (sizeof(T) == 4) {
+            // at most 64 unknowns (one segment) from LDS, else 65..128 (two)
+            if (mlds) coarse_rows_seg<T, 1, true>(minv_lds, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
+            else coarse_rows_seg<T, 2, false>(Minv, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
+        } else {
+            coarse_rows_tail<T, false>(Minv, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
+        }
         __syncthreads();
     }
     // up-legs

@@ -73,6 +73,8 @@ CASES = {
     "ragged_2d": ragged_2d,
     "ragged_3d": ragged_3d,
     "c3_32": lambda: W.c3(n=32, layer=4, method="bicgstab"),
+    # coarsest grid 10 x 10 = 100 unknowns: the tail's two-segment coarse solve
+    "c2_80": lambda: W.c2(n=80, levels=4),
 }
 
 
@@ -115,7 +117,7 @@ def test_vcycle_matches_oracle(torch_dev, hh_mod, oracle_mod, name):
     assert rel(u32.astype(np.complex128), ref) < 1e-4
 
 
-@pytest.mark.parametrize("name", ["c1", "c1_interior", "ragged_2d", "ragged_3d", "c3_32"])
+@pytest.mark.parametrize("name", ["c1", "c1_interior", "ragged_2d", "ragged_3d", "c3_32", "c2_80"])
 def test_bicgstab_fp64_matches_oracle(torch_dev, hh_mod, oracle_mod, name):
     torch = torch_dev
     c = CASES[name]()
@@ -138,7 +140,7 @@ def test_bicgstab_fp64_matches_oracle(torch_dev, hh_mod, oracle_mod, name):
     assert np.array_equal(ig["history"], io["history"])
 
 
-@pytest.mark.parametrize("name", ["c1", "c2_256", "ragged_3d", "c3_32"])
+@pytest.mark.parametrize("name", ["c1", "c2_256", "ragged_3d", "c3_32", "c2_80"])
 def test_bicgstab_mixed_precision(torch_dev, hh_mod, oracle_mod, name):
     torch = torch_dev
     c = CASES[name]()
