@@ -162,7 +162,7 @@ enum Phase { PH_RUN = 0, PH_HALF = 1, PH_STOP = 2, PH_IDLE = 3 };
 #define HH_DRIFT_STALL 300           // 0: no stall test
 
 // what a finaliser pass does with the chunk partials of one problem
-enum FinKind { FIN_BNORM = 0, FIN_INIT, FIN_ALPHA, FIN_S, FIN_OMEGA, FIN_RHO, FIN_TRUE, FIN_NONE,
+enum FinKind { FIN_BNORM = 0, FIN_INIT, FIN_ALPHA, FIN_OMEGA, FIN_RHO, FIN_TRUE, FIN_NONE,
                FIN_IDR_OMEGA, FIN_IDR_STEP, FIN_IDR_INIT, FIN_IDR_M };
 // stop reasons
 enum Reason { RS_NONE = 0, RS_CONV = 1, RS_MAXMV = 2, RS_BREAK = 3, RS_NONFIN = 4, RS_DRIFT = 5 };
@@ -212,6 +212,9 @@ struct ProbDev {
     const float2 *Minv32;
     const void *timg64, *timg32;     // LDS image of the tail levels (phi, coefficients), per precision
     int timg_bytes64, timg_bytes32;
+    // image segments, one per tail level: LDS offset << 16 | length, in 16-byte units
+    uint32_t tseg64[HH_MAXLEV], tseg32[HH_MAXLEV];
+    int tnseg64, tnseg32;
     double omega;
     void *vec[VS_NVEC];
     double2 *dR, *dX;                // IDR: s columns of N each

@@ -236,7 +236,7 @@ __global__ __launch_bounds__(HH_WG) void k_idr_t(Ctx cx)
             acc[2] = acc[2] + (y[e].x * y[e].x + y[e].y * y[e].y);
         }
     }
-    chunk_finish<3>(pd, tl.idx, acc, FIN_IDR_OMEGA);
+    chunk_finish<3>(pd, tl.idx, acc);
 }
 
 // P4: the dR/dX column of this step, r += dR, x += dX; partials ||r||^2,
@@ -313,12 +313,12 @@ __global__ __launch_bounds__(HH_WG) void k_idr_up(Ctx cx)
         }
     }
     if (mode == 0) {
-        chunk_finish<NV>(pd, tl.idx, acc, FIN_IDR_STEP);
+        chunk_finish<NV>(pd, tl.idx, acc);
     } else {
         double a2[1 + 2 * HH_MAX_S];
 #pragma unroll
         for (int k = 0; k < 1 + 2 * HH_MAX_S; ++k) a2[k] = acc[k];
-        chunk_finish<1 + 2 * HH_MAX_S>(pd, tl.idx, a2, FIN_IDR_STEP);
+        chunk_finish<1 + 2 * HH_MAX_S>(pd, tl.idx, a2);
     }
 }
 

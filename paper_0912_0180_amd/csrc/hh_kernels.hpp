@@ -457,7 +457,7 @@ __device__ void finalize(const ProbDev *pd, int kind)
     b.drift_grow = st->drift_grow;
     const int phase = b.phase;
     const int nv = kind >= FIN_IDR_OMEGA ? idr_nvals(pd, kind)
-                 : (kind == FIN_S || kind == FIN_BNORM || kind == FIN_TRUE) ? 1 : (kind == FIN_ALPHA ? 2 : 3);
+                 : (kind == FIN_BNORM || kind == FIN_TRUE) ? 1 : (kind == FIN_ALPHA ? 2 : (kind == FIN_OMEGA ? 4 : 3));
     const int first = (kind == FIN_BNORM || kind == FIN_TRUE) ? 2 : 0;
     __shared__ double res[4 * HH_MAX_S + 4];
     reduce_partials(pd->part, pd->nchunk, first, nv, res);
@@ -502,18 +502,16 @@ __device__ void finalize(const ProbDev *pd, int kind)
         b.alpha = cdiv<double>(b.rho, rv);
         break;
     }
-    case FIN_S: {
+    case FIN_OMEGA: {
         if (phase != PH_RUN) break;
-        double rel = sqrt(s[0]) / b.bnorm;
+        // half-step check on ||s|| first: when it ends the iteration, t
+        // (computed anyway, from the same s) is not used and not counted
+        double rel = sqrt(s[3]) / b.bnorm;
         bi_record(pd, b, rel);
         if (!isfinite(rel)) { bi_stop(b, RS_NONFIN); break; }
         if (rel < b.tol) { b.phase = PH_HALF; b.reason = RS_CONV; break; }
         if (b.mv >= b.max_mv) { b.phase = PH_HALF; b.reason = RS_MAXMV; break; }
         if (b.guard && drift(rel, b.mv, b.best_rel, b.best_mv, b.drift_grow, b.drift_stall)) { bi_stop(b, RS_DRIFT); break; }
-        break;
-    }
-    case FIN_OMEGA: {
-        if (phase != PH_RUN) break;
         b.mv += 1;
         double2 ts = cmk<double>(s[0], s[1]);
         double tt = s[2];
@@ -571,11 +569,12 @@ __device__ void finalize(const ProbDev *pd, int kind)
     }
 }
 
-// Writes this chunk's partial sums; the pass's finalisation runs in k_fin.
+// Writes this chunk's partial sums as values first .. first + NV - 1; the
+// pass's finalisation runs in k_fin.
 template <int NV>
-__device__ inline void chunk_finish(const ProbDev *pd, int chunk, double (&acc)[NV], int)
+__device__ inline void chunk_finish(const ProbDev *pd, int chunk, double (&acc)[NV], int first = 0)
 {
-    block_reduce<NV>(acc, pd->part + chunk, pd->nchunk);
+    block_reduce<NV>(acc, pd->part + (int64_t)first * pd->nchunk + chunk, pd->nchunk);
 }
 
 // One workgroup per problem: sums the chunk partials of the pass just run and
@@ -588,7 +587,7 @@ __global__ __launch_bounds__(HH_WG) void k_fin(Ctx cx, const int *__restrict__ p
     const int phase = phase_of(cx, prob);
     if (kind == FIN_RHO) {
         if (phase != PH_RUN && phase != PH_HALF) return;
-    } else if (kind == FIN_ALPHA || kind == FIN_S || kind == FIN_OMEGA) {
+    } else if (kind == FIN_ALPHA || kind == FIN_OMEGA) {
         if (phase != PH_RUN) return;
     } else if (kind >= FIN_IDR_OMEGA && kind != FIN_IDR_INIT) {
         if (phase != PH_RUN) return;
@@ -1017,16 +1016,26 @@ template <typename T> __host__ __device__ constexpr int coarse_slots(int seg)
     return sizeof(T) == 8 ? (seg > 8 ? seg : 8) : 16;
 }
 
+// (always inlined: LDS operands then keep their address space)
 template <typename T, int SEG, bool MLDS = false>
-__device__ inline void coarse_rows_seg(const V2<T> *__restrict__ Minv, const V2<T> *f, V2<T> *e, int n, int row0, int rstep)
+__device__ __forceinline__ void coarse_rows_seg(const V2<T> *__restrict__ Minv, const V2<T> *f, V2<T> *e, int n, int row0, int rstep)
 {
     constexpr int NS = coarse_slots<T>(SEG);
     constexpr int RPB = NS / SEG;  // rows per batch
     const int lane = threadIdx.x & 63;
+    // the entries of f this lane multiplies (reads clamped into f, masked
+    // by the column test below)
+    V2<T> fv[SEG];
+#pragma unroll
+    for (int c = 0; c < SEG; ++c) {
+        const int col = lane * SEG + c;
+        fv[c] = f[col < n ? col : n - 1];
+    }
     for (int rb = row0; rb < n; rb += RPB * rstep) {
         T re[NS], im[NS];
         // inverse entries in groups of 8 loads in flight together (unused
-        // slots read entry 0)
+        // slots read entry 0); the products of unused slots are replaced by
+        // zero
 #pragma unroll
         for (int h = 0; h < NS; h += 8) {
             V2<T> mv[8];
@@ -1039,13 +1048,10 @@ __device__ inline void coarse_rows_seg(const V2<T> *__restrict__ Minv, const V2<
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int row = rb + ((h + q) / SEG) * rstep, col = lane * SEG + (h + q) % SEG;
-                re[h + q] = 0;
-                im[h + q] = 0;
-                if (row < n && col < n) {
-                    V2<T> pr = cmul<T>(mv[q], f[col]);
-                    re[h + q] = pr.x;
-                    im[h + q] = pr.y;
-                }
+                const V2<T> pr = cmul<T>(mv[q], fv[(h + q) % SEG]);
+                const bool in = row < n && col < n;
+                re[h + q] = in ? pr.x : (T)0;
+                im[h + q] = in ? pr.y : (T)0;
             }
         }
         // in-lane pairwise over each row's segment (aligned power-of-two
@@ -1094,7 +1100,7 @@ __host__ __device__ inline int coarse_seg(int n)
     return np >> 6;
 }
 template <typename T, bool MLDS>
-__device__ inline void coarse_rows_tail(const V2<T> *__restrict__ Minv, const V2<T> *f, V2<T> *e, int n, int row0, int rstep)
+__device__ __forceinline__ void coarse_rows_tail(const V2<T> *__restrict__ Minv, const V2<T> *f, V2<T> *e, int n, int row0, int rstep)
 {
     static_assert(HH_SPLIT_NC <= 128, "tail coarse solve handles seg 1 and 2");
     if (coarse_seg(n) == 1) coarse_rows_seg<T, 1, MLDS>(Minv, f, e, n, row0, rstep);
@@ -1203,14 +1209,19 @@ __device__ inline V2<T> tail_Mu(const TailPtr<T> &Q, const V2<T> *U, V2<T> D, in
     using C = V2<T>;
     const C zero = cmk<T>(0, 0);
     const int sy = Q.nx, sz = Q.nx * Q.ny;
+    // neighbours outside the level are zero: every read stays inside the
+    // level (clamped to p) and is masked, so the reads issue together
+    const C uw = U[i > 0 ? p - 1 : p], ue = U[i < Q.nx - 1 ? p + 1 : p];
+    const C us = U[j > 0 ? p - sy : p], un = U[j < Q.ny - 1 ? p + sy : p];
     C mu = cmul<T>(D, U[p]);
-    mu = csub<T>(mu, cmul<T>(Q.A0[i], i > 0 ? U[p - 1] : zero));
-    mu = csub<T>(mu, cmul<T>(Q.C0[i], i < Q.nx - 1 ? U[p + 1] : zero));
-    mu = csub<T>(mu, cmul<T>(Q.A1[j], j > 0 ? U[p - sy] : zero));
-    mu = csub<T>(mu, cmul<T>(Q.C1[j], j < Q.ny - 1 ? U[p + sy] : zero));
+    mu = csub<T>(mu, cmul<T>(Q.A0[i], i > 0 ? uw : zero));
+    mu = csub<T>(mu, cmul<T>(Q.C0[i], i < Q.nx - 1 ? ue : zero));
+    mu = csub<T>(mu, cmul<T>(Q.A1[j], j > 0 ? us : zero));
+    mu = csub<T>(mu, cmul<T>(Q.C1[j], j < Q.ny - 1 ? un : zero));
     if (DIM == 3) {
-        mu = csub<T>(mu, cmul<T>(Q.A2[k], k > 0 ? U[p - sz] : zero));
-        mu = csub<T>(mu, cmul<T>(Q.C2[k], k < Q.nz - 1 ? U[p + sz] : zero));
+        const C ub = U[k > 0 ? p - sz : p], ut = U[k < Q.nz - 1 ? p + sz : p];
+        mu = csub<T>(mu, cmul<T>(Q.A2[k], k > 0 ? ub : zero));
+        mu = csub<T>(mu, cmul<T>(Q.C2[k], k < Q.nz - 1 ? ut : zero));
     }
     return mu;
 }
@@ -1255,12 +1266,14 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
     const C *fg_top = Lv[t0].f;
     C *eg_top = Lv[t0].e;
     const C *__restrict__ Minv = (const C *)(sizeof(T) == 8 ? (const void *)pd->Minv64 : (const void *)pd->Minv32);
-    // the tail image (phi and coefficients of every tail level, zeros
-    // elsewhere) in one coalesced sweep, its first batch in flight while the
-    // level table is built; then f at the top level
+    // the tail image (phi and coefficients of every tail level, see
+    // tail_image), the coarsest inverse when it goes to LDS, and f of the top
+    // level, all loads in flight together while the level table is built
     {
         const void *img = sizeof(T) == 8 ? pd->timg64 : pd->timg32;
         const int n16 = (sizeof(T) == 8 ? pd->timg_bytes64 : pd->timg_bytes32) / 16;
+        const uint32_t *seg = sizeof(T) == 8 ? pd->tseg64 : pd->tseg32;
+        const int nseg = sizeof(T) == 8 ? pd->tnseg64 : pd->tnseg32;
         hh_uvec4 *l16 = (hh_uvec4 *)lds;
         if (mlds) {
             constexpr int MT = (TailMinv<T>::N + TailCap<T>::WG - 1) / TailCap<T>::WG;
@@ -1277,6 +1290,15 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
                 if (i < nm) minv_lds[i] = mt[q];
             }
         }
+        // f of the top level leads the LDS block (offset 0)
+        constexpr int FT = (TailCap<T>::N + TailCap<T>::WG - 1) / TailCap<T>::WG;
+        const int ntop = up ? 0 : (int)Lv[t0].N;
+        C ft[FT];
+#pragma unroll
+        for (int q = 0; q < FT; ++q) {
+            const int i = tid + q * nth;
+            if (i < ntop) ft[q] = ldg(fg_top, i);
+        }
         for (int b = 0; b < n16; b += 8 * nth) {
             hh_uvec4 tmp[8];
 #pragma unroll
@@ -1288,15 +1310,28 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int i = b + tid + q * nth;
-                if (i < n16) l16[i] = tmp[q];
+                if (i < n16) {
+                    // segment of entry i (one per level, in order)
+                    int k = 0, s0 = 0;
+                    for (; k < nseg - 1; ++k) {
+                        const int len = (int)(seg[k] & 0xffffu);
+                        if (i < s0 + len) break;
+                        s0 += len;
+                    }
+                    l16[(int)(seg[k] >> 16) + (i - s0)] = tmp[q];
+                }
             }
         }
         if (n16 <= 0) tail_tab_fill<DIM, T>(tab, Lv, t0, L);
+#pragma unroll
+        for (int q = 0; q < FT; ++q) {
+            const int i = tid + q * nth;
+            if (i < ntop) ((C *)lds)[i] = ft[q];
+        }
         __syncthreads();
-        // f of the top level (and, for the up-legs of a split tail, f of
-        // every tail level and e of the coarsest)
-        const int lf = up ? L - 1 : t0 + 1;
-        for (int l = t0; l < lf; ++l) {
+        // for the up-legs of a split tail: f of every tail level and e of the
+        // coarsest
+        for (int l = t0; l < (up ? L - 1 : t0); ++l) {
             const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, l);
             const C *__restrict__ fg = l == t0 ? fg_top : Lv[l].f;
             for (int b = 0; b < Q.N; b += 4 * nth) {
@@ -1315,7 +1350,7 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
             for (int p = tid; p < Q.N; p += nth) Q.E[p] = ldg(eg, p);
         }
     }
-    __syncthreads();
+    if (up) __syncthreads();   // uniform
     C *U = (C *)(lds + tab.uoff);
     const T w0 = (T)0.125, w1 = (T)0.375, p3 = (T)0.75, p1 = (T)0.25;
     // down-legs
@@ -1344,16 +1379,21 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
                 const int kk = DIM == 3 ? 2 * K - 1 + c : 0;
                 const bool kin = DIM == 2 || (kk >= 0 && kk < Q.nz);
                 C acc_y = zero;
+                const int kc = kk < 0 ? 0 : (kk >= Q.nz ? Q.nz - 1 : kk);
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const T wy = (b == 0 || b == 3) ? w0 : w1;
                     const int jj = 2 * J - 1 + b;
                     const bool jin = kin && jj >= 0 && jj < Q.ny;
+                    const int jc = jj < 0 ? 0 : (jj >= Q.ny ? Q.ny - 1 : jj);
+                    // reads clamped into the level, points outside it masked to zero
                     C v[4];
 #pragma unroll
                     for (int a = 0; a < 4; ++a) {
                         const int ii = 2 * I - 1 + a;
-                        v[a] = (jin && ii >= 0 && ii < Q.nx) ? Q.E[ii + Q.nx * (jj + Q.ny * kk)] : zero;
+                        const int ic = ii < 0 ? 0 : (ii >= Q.nx ? Q.nx - 1 : ii);
+                        const C e = Q.E[ic + Q.nx * (jc + Q.ny * kc)];
+                        v[a] = (jin && ii >= 0 && ii < Q.nx) ? e : zero;
                     }
                     C sx = crs<T>(w0, v[0]);
                     sx = cadd<T>(sx, crs<T>(w1, v[1]));
@@ -1399,9 +1439,13 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
             C u1 = cmul<T>(jweight<T>(tail_diag<DIM, T>(Q, i, j, k, p), omega), Q.F[p]);
             const int Ix = i >> 1, Iox = (i & 1) ? Ix + 1 : Ix - 1;
             const int Iy = j >> 1, Ioy = (j & 1) ? Iy + 1 : Iy - 1;
+            // coarse values outside the level are zero (read clamped, then masked)
             auto ev = [R](int a, int b, int c) -> C {
-                return (a >= 0 && a < R.nx && b >= 0 && b < R.ny && c >= 0 && c < R.nz) ? R.E[a + R.nx * (b + R.ny * c)]
-                                                                                      : cmk<T>(0, 0);
+                const int ac = a < 0 ? 0 : (a >= R.nx ? R.nx - 1 : a);
+                const int bc = b < 0 ? 0 : (b >= R.ny ? R.ny - 1 : b);
+                const int cc = c < 0 ? 0 : (c >= R.nz ? R.nz - 1 : c);
+                const C e = R.E[ac + R.nx * (bc + R.ny * cc)];
+                return (a >= 0 && a < R.nx && b >= 0 && b < R.ny && c >= 0 && c < R.nz) ? e : cmk<T>(0, 0);
             };
             C pe;
             if (DIM == 2) {
@@ -1536,10 +1580,11 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_v(Ctx cx)
             acc[1] = acc[1] + (a[s].x * y[s].y - a[s].y * y[s].x);
         }
     }
-    chunk_finish<2>(pd, tl.idx, acc, FIN_ALPHA);
+    chunk_finish<2>(pd, tl.idx, acc);
 }
 
-// s = r - alpha v (in r) ; partial ||s||^2 ; finalise the half-step check
+// s = r - alpha v (in r) ; partial ||s||^2 (value 3, checked by the omega
+// finaliser before it uses t)
 __global__ __launch_bounds__(HH_WG) void k_bicg_s(Ctx cx)
 {
     const Tile tl = tile_of(cx);
@@ -1565,7 +1610,7 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_s(Ctx cx)
             stg(r, CHUNK_P(s), sv);
             acc[0] = acc[0] + (sv.x * sv.x + sv.y * sv.y);
         }
-    chunk_finish<1>(pd, tl.idx, acc, FIN_S);
+    chunk_finish<1>(pd, tl.idx, acc, 3);   // ||s||^2, finalised with omega
 }
 
 // t = H shat ; partials (t, s), (t, t) ; finalise omega
@@ -1602,7 +1647,7 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_t(Ctx cx)
             acc[2] = acc[2] + (y[s].x * y[s].x + y[s].y * y[s].y);
         }
     }
-    chunk_finish<3>(pd, tl.idx, acc, FIN_OMEGA);
+    chunk_finish<3>(pd, tl.idx, acc);
 }
 
 // x = x + alpha phat + omega shat ; r = s - omega t ; partials (rhat, r),
@@ -1660,7 +1705,7 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_xr(Ctx cx)
                 acc[2] = acc[2] + (rn.x * rn.x + rn.y * rn.y);
             }
     }
-    chunk_finish<3>(pd, tl.idx, acc, FIN_RHO);
+    chunk_finish<3>(pd, tl.idx, acc);
 }
 
 // out = b - H x.  mode 0 (Bi-CGSTAB start): out = r, also rhat = r, p = v = 0,
@@ -1708,7 +1753,7 @@ __global__ __launch_bounds__(HH_WG) void k_resid(Ctx cx, int mode)
             acc[2] = acc[2] + (rv.x * rv.x + rv.y * rv.y);
         }
     }
-    chunk_finish<3>(pd, tl.idx, acc, mode == 0 ? FIN_INIT : (mode == 1 ? FIN_TRUE : FIN_IDR_INIT));
+    chunk_finish<3>(pd, tl.idx, acc);
 }
 
 // partial ||vec||^2 (slot 2) ; finalise ||b||
@@ -1726,7 +1771,7 @@ __global__ __launch_bounds__(HH_WG) void k_norm(Ctx cx, int sel)
 #pragma unroll
     for (int s = 0; s < HH_PER_SLOT; ++s)
         if (CHUNK_P(s) < N) acc[2] = acc[2] + (xr[s].x * xr[s].x + xr[s].y * xr[s].y);
-    chunk_finish<3>(pd, tl.idx, acc, FIN_BNORM);
+    chunk_finish<3>(pd, tl.idx, acc);
 }
 
 // set a complex double vector to zero

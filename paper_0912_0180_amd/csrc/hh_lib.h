@@ -76,6 +76,7 @@ struct hh_grid {
     float2 *Minv32 = nullptr;
     void *timg64 = nullptr, *timg32 = nullptr;
     size_t timg_bytes64 = 0, timg_bytes32 = 0;
+    std::vector<uint32_t> tseg64, tseg32;   // segments of the tail images (see tail_image)
     ProbDev pd_static{};
     ProbDev *pd_static_dev = nullptr;
     Tile *chunks_dev = nullptr;
@@ -104,5 +105,5 @@ void launch_resid(const Plan &pl, const DevList &tiles, int mode, hipStream_t s)
 void launch_norm(const Plan &pl, const DevList &tiles, int sel, hipStream_t s);
 void launch_zero(const Plan &pl, const DevList &tiles, int sel, hipStream_t s);
 int tail_level(const HostSetup &hs, bool fp32);
-std::vector<char> tail_image(const HostSetup &hs, bool fp32);
+std::vector<char> tail_image(const HostSetup &hs, bool fp32, std::vector<uint32_t> *seg);
 void launch_fin(const Plan &pl, const int *probs, int n, int kind, hipStream_t s);

@@ -111,8 +111,8 @@ hh_status grid_upload(hh_grid *g)
         g->Minv64 = c.take<double2>((size_t)hs.Nc * hs.Nc);
         g->Minv32 = c.take<float2>((size_t)hs.Nc * hs.Nc);
         if (pass == 0) {
-            g->timg_bytes64 = tail_image(hs, false).size();
-            g->timg_bytes32 = tail_image(hs, true).size();
+            g->timg_bytes64 = tail_image(hs, false, nullptr).size();
+            g->timg_bytes32 = tail_image(hs, true, nullptr).size();
         }
         g->timg64 = c.take<char>(g->timg_bytes64);
         g->timg32 = c.take<char>(g->timg_bytes32);
@@ -154,7 +154,7 @@ hh_status grid_upload(hh_grid *g)
     }
     HIPCHK(put64(g->Minv64, hs.Minv.data(), sizeof(double2) * hs.Minv.size()));
     {
-        std::vector<char> i64 = tail_image(hs, false), i32 = tail_image(hs, true);
+        std::vector<char> i64 = tail_image(hs, false, &g->tseg64), i32 = tail_image(hs, true, &g->tseg32);
         HIPCHK(put64(g->timg64, i64.data(), i64.size()));
         HIPCHK(put64(g->timg32, i32.data(), i32.size()));
     }
@@ -202,6 +202,12 @@ void grid_fill_prob(const hh_grid *g, ProbDev &pd)
     pd.timg32 = g->timg32;
     pd.timg_bytes64 = (int)g->timg_bytes64;
     pd.timg_bytes32 = (int)g->timg_bytes32;
+    pd.tnseg64 = (int)g->tseg64.size();
+    pd.tnseg32 = (int)g->tseg32.size();
+    for (int i = 0; i < HH_MAXLEV; ++i) {
+        pd.tseg64[i] = i < pd.tnseg64 ? g->tseg64[i] : 0u;
+        pd.tseg32[i] = i < pd.tnseg32 ? g->tseg32[i] : 0u;
+    }
 }
 
 static void grid_release(hh_grid *g)
@@ -282,17 +288,24 @@ int tail_level(const HostSetup &hs, bool fp32)
     return hs.nlev - 1;
 }
 
-// Byte image of the tail's LDS block (same layout as tail_bytes / k_vtail):
-// per level f and e (zero), phi, and the coefficient arrays a, c, d per axis;
-// then the scratch U (zero).  Values in the V-cycle precision.
-std::vector<char> tail_image(const HostSetup &hs, bool fp32)
+// Compact image of the tail's LDS block (layout of tail_bytes / k_vtail):
+// for each tail level the bytes from its phi to the end of its coefficient
+// arrays (a, c, d per axis), levels one after another, values in the V-cycle
+// precision.  f, e and the scratch U are never read before the kernel writes
+// them, so they are not part of the image.  seg[i] = (LDS offset of level
+// t + i's phi in 16-byte units) << 16 | (its length in 16-byte units).
+std::vector<char> tail_image(const HostSetup &hs, bool fp32, std::vector<uint32_t> *seg)
 {
     const int t = tail_level(hs, fp32);
-    std::vector<char> img(tail_bytes(hs, t, fp32), 0);
     const size_t cb = fp32 ? sizeof(float2) : sizeof(double2), rb = fp32 ? sizeof(float) : sizeof(double);
     auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
-    size_t off = 0;
+    std::vector<char> img;
+    if (seg) seg->clear();
+    size_t lds = 0;   // LDS offset of the next array
+    size_t off = 0;   // image offset of the next array
+    auto grow = [&](size_t b) { img.resize(off + r16(b), 0); };
     auto put_c = [&](const std::vector<double2> &v, size_t n) {
+        grow(cb * n);
         for (size_t i = 0; i < n; ++i) {
             if (fp32) {
                 float2 z;
@@ -304,10 +317,13 @@ std::vector<char> tail_image(const HostSetup &hs, bool fp32)
             }
         }
         off += r16(cb * n);
+        lds += r16(cb * n);
     };
     for (int l = t; l < hs.nlev; ++l) {
         const HostLevel &L = hs.lev[l];
-        off += r16(cb * L.N) + r16(cb * L.N);
+        lds += r16(cb * L.N) + r16(cb * L.N);   // f and e
+        const size_t lds0 = lds, off0 = off;
+        grow(rb * L.N);
         for (int64_t i = 0; i < L.N; ++i) {
             if (fp32) {
                 float v = (float)L.phi[i];
@@ -317,15 +333,20 @@ std::vector<char> tail_image(const HostSetup &hs, bool fp32)
             }
         }
         off += r16(rb * L.N);
+        lds += r16(rb * L.N);
         for (int a = 0; a < 3; ++a) {
             if (a < hs.dim) {
                 put_c(L.aM[a], L.n[a]);
                 put_c(L.cM[a], L.n[a]);
                 put_c(L.dM[a], L.n[a]);
             } else {
-                off += 3 * r16(cb);
+                const std::vector<double2> zero(1, double2{0.0, 0.0});
+                put_c(zero, 1);
+                put_c(zero, 1);
+                put_c(zero, 1);
             }
         }
+        if (seg) seg->push_back((uint32_t)(lds0 / 16) << 16 | (uint32_t)((off - off0) / 16));
     }
     return img;
 }
@@ -662,7 +683,7 @@ static void bicg_iter_t(const Plan &pl, hipStream_t s)
     LAUNCH((k_bicg_v<DIM, SP>), n, s, c);
     launch_fin(pl, pl.fin, pl.nfin, FIN_ALPHA, s);
     LAUNCH(k_bicg_s, n, s, c);
-    launch_fin(pl, pl.fin, pl.nfin, FIN_S, s);
+    // the half-step check on ||s|| runs in the omega finaliser
     launch_vcycle(pl, VS_R, VS_SH, nullptr, nullptr, s);
     LAUNCH((k_bicg_t<DIM, SP>), n, s, c);
     launch_fin(pl, pl.fin, pl.nfin, FIN_OMEGA, s);
