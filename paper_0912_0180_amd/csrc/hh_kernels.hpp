@@ -30,6 +30,40 @@ namespace hh {
 // reductions
 // ---------------------------------------------------------------------------
 
+// Lane exchange by DPP within a row of 16 lanes (CTRL: a quad permute or a
+// mirror); every source lane is inside the row, so no lane reads out of range.
+template <int CTRL> __device__ inline float dpp_x(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ inline double dpp_x(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline float lane_value(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+__device__ inline double lane_value(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l), __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Pairwise tree over the 64 lanes of a wave (all lanes active); every lane
+// gets the sum.  Aligned blocks of 1, 2, 4 and 8 lanes are paired with the
+// neighbouring block by DPP (xor 1 and xor 2 by quad permutes, then the
+// half-row and row mirrors, which pair lane i with the mirror lane of the
+// other block; after each step all lanes of a block hold the block sum), then
+// the four row sums are combined as (r0 + r1) + (r2 + r3): the tree of the
+// xor butterfly, with no LDS traffic.
+template <typename T> __device__ inline T wave_sum(T v)
+{
+    v = v + dpp_x<0xB1>(v);    // quad_perm [1,0,3,2]
+    v = v + dpp_x<0x4E>(v);    // quad_perm [2,3,0,1]
+    v = v + dpp_x<0x141>(v);   // row_half_mirror
+    v = v + dpp_x<0x140>(v);   // row_mirror
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
 // Pairwise tree over the 256 thread slots of a 256-thread workgroup; thread 0
 // writes the NV sums to out[q * stride], q < NV.
 template <int NV>
@@ -37,9 +71,7 @@ __device__ inline void block_reduce(double (&v)[NV], double *out, int64_t stride
 {
     __shared__ double red[4 * NV];
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1)
-#pragma unroll
-        for (int q = 0; q < NV; ++q) v[q] = v[q] + __shfl_xor(v[q], off, 64);
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0)
 #pragma unroll
@@ -1064,18 +1096,15 @@ __device__ __forceinline__ void coarse_rows_seg(const V2<T> *__restrict__ Minv, 
                 im[i] = im[i] + im[i + w];
             }
         }
-        // butterfly across the wave, up to 4 rows of the batch together
+        // pairwise across the wave, up to 4 rows of the batch together
         constexpr int RG = RPB < 4 ? RPB : 4;
 #pragma unroll
         for (int r0 = 0; r0 < RPB; r0 += RG) {
             if (rb + r0 * rstep >= n) break;   // rest of the batch past the last row (uniform)
 #pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-#pragma unroll
-                for (int r = r0; r < r0 + RG; ++r) {
-                    re[r * SEG] = re[r * SEG] + __shfl_xor(re[r * SEG], off, 64);
-                    im[r * SEG] = im[r * SEG] + __shfl_xor(im[r * SEG], off, 64);
-                }
+            for (int r = r0; r < r0 + RG; ++r) {
+                re[r * SEG] = wave_sum(re[r * SEG]);
+                im[r * SEG] = wave_sum(im[r * SEG]);
             }
         }
         if (lane == 0) {
