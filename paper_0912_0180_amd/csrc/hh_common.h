@@ -45,6 +45,12 @@ template <typename T> __host__ __device__ inline V2<T> cmul(V2<T> a, V2<T> b)
 {
     return cmk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+// FP32 is the V-cycle precision of mixed solves, held to a tolerance against
+// FP64 rather than to its operation order: fused multiply-adds
+template <> __host__ __device__ inline V2<float> cmul<float>(V2<float> a, V2<float> b)
+{
+    return cmk<float>(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
+}
 template <typename T> __host__ __device__ inline V2<T> cdiv(V2<T> a, V2<T> b)
 {
     T d = b.x * b.x + b.y * b.y;
@@ -254,17 +260,19 @@ template <> struct TailMinv<float> { static constexpr int N = 64 * 64; };
 // the down-leg's tile; the up-leg's fine tile is twice it).  The kernels are
 // built for every shape of the set and the autotuner picks one per
 // (dimension, precision, leg, level class); results do not depend on it.
-#define HH_NTILE 5
+#define HH_NTILE 7
 template <int DIM> struct TileSet;
 template <> struct TileSet<2> {
-    static constexpr int X[HH_NTILE] = {16, 32, 16, 8, 32};
-    static constexpr int Y[HH_NTILE] = {16, 8, 8, 8, 16};
-    static constexpr int Z[HH_NTILE] = {1, 1, 1, 1, 1};
+    static constexpr int X[HH_NTILE] = {16, 32, 16, 8, 32, 32, 32};
+    static constexpr int Y[HH_NTILE] = {16, 8, 8, 8, 16, 8, 16};
+    static constexpr int Z[HH_NTILE] = {1, 1, 1, 1, 1, 1, 1};
+    static constexpr int T[HH_NTILE] = {256, 256, 256, 256, 256, 512, 512};   // threads per workgroup
 };
 template <> struct TileSet<3> {
-    static constexpr int X[HH_NTILE] = {4, 8, 8, 4, 8};
-    static constexpr int Y[HH_NTILE] = {4, 4, 8, 4, 4};
-    static constexpr int Z[HH_NTILE] = {4, 4, 2, 2, 2};
+    static constexpr int X[HH_NTILE] = {4, 8, 8, 4, 8, 8, 8};
+    static constexpr int Y[HH_NTILE] = {4, 4, 8, 4, 4, 4, 8};
+    static constexpr int Z[HH_NTILE] = {4, 4, 2, 2, 2, 4, 2};
+    static constexpr int T[HH_NTILE] = {256, 256, 256, 256, 256, 512, 512};
 };
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }

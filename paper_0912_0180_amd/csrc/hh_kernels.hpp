@@ -26,6 +26,15 @@
 
 namespace hh {
 
+// Scale of the Jacobi weight omega / D = (omega / |D|^2) conj(D): the IEEE
+// quotient in FP64; FP32 (held to a tolerance) takes the hardware
+// reciprocal (1 ulp) and a fused |D|^2.
+template <typename T> __device__ inline T jscale(T omega, V2<T> D) { return omega / (D.x * D.x + D.y * D.y); }
+template <> __device__ inline float jscale<float>(float omega, V2<float> D)
+{
+    return omega * __builtin_amdgcn_rcpf(fmaf(D.x, D.x, D.y * D.y));
+}
+
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
@@ -688,14 +697,15 @@ __global__ __launch_bounds__(HH_WG) void k_applyM(Ctx cx, const void *xp, void *
 // with a halo of 2 (restriction footprint + stencil).
 // ---------------------------------------------------------------------------
 template <int DIM, typename T, typename TF, int VT>
-__global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, const void *fptr, LvPair<T> lp)
+__global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vdown(Ctx cx, int lev, int fsel, const void *fptr, LvPair<T> lp)
 {
     using C = V2<T>;
     constexpr int CX = TileSet<DIM>::X[VT], CY = TileSet<DIM>::Y[VT], CZ = DIM == 3 ? TileSet<DIM>::Z[VT] : 1;
+    constexpr int NT = TileSet<DIM>::T[VT];   // threads
     constexpr int RX = 2 * CX + 4, RY = 2 * CY + 4, RZ = DIM == 3 ? 2 * CZ + 4 : 1;
     constexpr int RN = RX * RY * RZ;
     constexpr int RM = RX > RY ? (RX > RZ ? RX : RZ) : (RY > RZ ? RY : RZ);
-    constexpr int NL = (RN + HH_WG - 1) / HH_WG;
+    constexpr int NL = (RN + NT - 1) / NT;
     __shared__ C U[RN];
     __shared__ C F[RN];
     __shared__ T PH[RN];
@@ -743,7 +753,7 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, cons
     T pr[NL];
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
-        const int l = threadIdx.x + q * HH_WG;
+        const int l = threadIdx.x + q * NT;
         const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
         const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
         const bool in = l < RN && gx >= 0 && gx < nfx && gy >= 0 && gy < nfy && (DIM == 2 || (gz >= 0 && gz < nfz));
@@ -753,7 +763,7 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, cons
             pr[q] = ldg(phi, p);
         }
     }
-    for (int l = threadIdx.x; l < RX + RY + RZ; l += HH_WG) {
+    for (int l = threadIdx.x; l < RX + RY + RZ; l += NT) {
         const int ax = l < RX ? 0 : (l < RX + RY ? 1 : 2);
         const int q = ax == 0 ? l : (ax == 1 ? l - RX : l - RX - RY);
         const int g = (ax == 0 ? ox : (ax == 1 ? oy : oz)) + q;
@@ -771,7 +781,7 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, cons
     // step 1: u1 = g f on the whole box
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
-        const int l = threadIdx.x + q * HH_WG;
+        const int l = threadIdx.x + q * NT;
         if (l >= RN) break;
         const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
         const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
@@ -783,7 +793,7 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, cons
             C d = cadd<T>(Dd[0][lx], Dd[1][ly]);
             if (DIM == 3) d = cadd<T>(d, Dd[2][lz]);
             C D = cmk<T>(d.x - ph, d.y);
-            T qq = omega / (D.x * D.x + D.y * D.y);
+            T qq = jscale<T>(omega, D);
             C gw = cmk<T>(D.x * qq, -(D.y * qq));
             u1 = cmul<T>(gw, fv);
         }
@@ -795,7 +805,7 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, cons
     // step 2: r = f - M u1 on the box minus its outer ring, in place in F
     {
         constexpr int QX = RX - 2, QY = RY - 2, QZ = DIM == 3 ? RZ - 2 : 1;
-        for (int r = threadIdx.x; r < QX * QY * QZ; r += HH_WG) {
+        for (int r = threadIdx.x; r < QX * QY * QZ; r += NT) {
             const int lx = 1 + r % QX, ly = 1 + (r / QX) % QY, lz = (DIM == 3 ? 1 : 0) + r / (QX * QY);
             const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
             const int l = lx + RX * (ly + RY * lz);
@@ -821,7 +831,7 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, cons
     __syncthreads();
     // step 3: full weighting, x then y then z
     const T w0 = (T)0.125, w1 = (T)0.375;
-    for (int cl = threadIdx.x; cl < CX * CY * CZ; cl += HH_WG) {
+    for (int cl = threadIdx.x; cl < CX * CY * CZ; cl += NT) {
         const int ix = cl % CX, iy = (cl / CX) % CY, iz = cl / (CX * CY);
         const int I = c0x + ix, J = c0y + iy, K = c0z + iz;
         if (I >= ncx || J >= ncy || (DIM == 3 && K >= ncz)) continue;
@@ -853,19 +863,20 @@ __global__ __launch_bounds__(HH_WG) void k_vdown(Ctx cx, int lev, int fsel, cons
 // Output: e_lev (lev >= 1) or the output vector (lev == 0, storage TO).
 // ---------------------------------------------------------------------------
 template <int DIM, typename T, typename TF, typename TO, int VT>
-__global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int osel, const void *fptr, void *optr,
+__global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, int fsel, int osel, const void *fptr, void *optr,
                                                 LvPair<T> lp)
 {
     using C = V2<T>;
     constexpr int CX = TileSet<DIM>::X[VT], CY = TileSet<DIM>::Y[VT], CZ = DIM == 3 ? TileSet<DIM>::Z[VT] : 1;
+    constexpr int NT = TileSet<DIM>::T[VT];   // threads
     constexpr int FX = 2 * CX, FY = 2 * CY, FZ = DIM == 3 ? 2 * CZ : 1;
     constexpr int RX = FX + 2, RY = FY + 2, RZ = DIM == 3 ? FZ + 2 : 1;
     constexpr int RN = RX * RY * RZ;
     constexpr int EX = CX + 4, EY = CY + 4, EZ = DIM == 3 ? CZ + 4 : 1;
     constexpr int EN = EX * EY * EZ;
     constexpr int RM = RX > RY ? (RX > RZ ? RX : RZ) : (RY > RZ ? RY : RZ);
-    constexpr int NL = (RN + HH_WG - 1) / HH_WG;
-    constexpr int NE = (EN + HH_WG - 1) / HH_WG;
+    constexpr int NL = (RN + NT - 1) / NT;
+    constexpr int NE = (EN + NT - 1) / NT;
     __shared__ C U[RN];
     __shared__ C F[RN];
     __shared__ T PH[RN];
@@ -918,7 +929,7 @@ __global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int os
     C er[NE];
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
-        const int l = threadIdx.x + q * HH_WG;
+        const int l = threadIdx.x + q * NT;
         const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
         const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
         const bool in = l < RN && gx >= 0 && gx < nfx && gy >= 0 && gy < nfy && (DIM == 2 || (gz >= 0 && gz < nfz));
@@ -930,14 +941,14 @@ __global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int os
     }
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
-        const int l = threadIdx.x + q * HH_WG;
+        const int l = threadIdx.x + q * NT;
         const int lx = l % EX, ly = (l / EX) % EY, lz = l / (EX * EY);
         const int gx = ex0 + lx, gy = ey0 + ly, gz = ez0 + lz;
         er[q] = zero;
         if (l < EN && gx >= 0 && gx < ncx && gy >= 0 && gy < ncy && (DIM == 2 || (gz >= 0 && gz < ncz)))
             er[q] = ldg(ec, gx + (int64_t)ncx * (gy + (int64_t)ncy * gz));
     }
-    for (int l = threadIdx.x; l < RX + RY + RZ; l += HH_WG) {
+    for (int l = threadIdx.x; l < RX + RY + RZ; l += NT) {
         const int ax = l < RX ? 0 : (l < RX + RY ? 1 : 2);
         const int q = ax == 0 ? l : (ax == 1 ? l - RX : l - RX - RY);
         const int g = (ax == 0 ? ox : (ax == 1 ? oy : oz)) + q;
@@ -952,7 +963,7 @@ __global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int os
     }
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
-        const int l = threadIdx.x + q * HH_WG;
+        const int l = threadIdx.x + q * NT;
         if (l < EN) E[l] = er[q];
     }
     if (run != PH_RUN) return;   // uniform over the workgroup
@@ -961,7 +972,7 @@ __global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int os
     // step 1: u2 = g f + P e on the tile plus a halo of one
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
-        const int l = threadIdx.x + q * HH_WG;
+        const int l = threadIdx.x + q * NT;
         if (l >= RN) break;
         const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
         const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
@@ -973,7 +984,7 @@ __global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int os
             C d = cadd<T>(Dd[0][lx], Dd[1][ly]);
             if (DIM == 3) d = cadd<T>(d, Dd[2][lz]);
             C D = cmk<T>(d.x - ph, d.y);
-            T qq = omega / (D.x * D.x + D.y * D.y);
+            T qq = jscale<T>(omega, D);
             C gw = cmk<T>(D.x * qq, -(D.y * qq));
             C u1 = cmul<T>(gw, fv);
             const int Ix = (gx >> 1) - ex0, Iox = ((gx & 1) ? (gx >> 1) + 1 : (gx >> 1) - 1) - ex0;
@@ -1003,7 +1014,7 @@ __global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int os
     }
     __syncthreads();
     // step 2: post-smoothing on the tile
-    for (int r = threadIdx.x; r < FX * FY * FZ; r += HH_WG) {
+    for (int r = threadIdx.x; r < FX * FY * FZ; r += NT) {
         const int lx = 1 + r % FX, ly = 1 + (r / FX) % FY, lz = (DIM == 3 ? 1 : 0) + r / (FX * FY);
         const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
         if (gx >= nfx || gy >= nfy || (DIM == 3 && gz >= nfz)) continue;
@@ -1011,7 +1022,7 @@ __global__ __launch_bounds__(HH_WG) void k_vup(Ctx cx, int lev, int fsel, int os
         C d = cadd<T>(Dd[0][lx], Dd[1][ly]);
         if (DIM == 3) d = cadd<T>(d, Dd[2][lz]);
         C D = cmk<T>(d.x - PH[l], d.y);
-        T qq = omega / (D.x * D.x + D.y * D.y);
+        T qq = jscale<T>(omega, D);
         C gw = cmk<T>(D.x * qq, -(D.y * qq));
         C mu = cmul<T>(D, U[l]);
         mu = csub<T>(mu, cmul<T>(A[0][lx], U[l - 1]));
@@ -1138,7 +1149,7 @@ __device__ __forceinline__ void coarse_rows_tail(const V2<T> *__restrict__ Minv,
 
 template <typename T> __device__ inline V2<T> jweight(V2<T> D, T omega)
 {
-    T q = omega / (D.x * D.x + D.y * D.y);
+    T q = jscale<T>(omega, D);
     return cmk<T>(D.x * q, -(D.y * q));
 }
 

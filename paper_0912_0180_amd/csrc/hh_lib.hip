@@ -454,6 +454,12 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         if ((n) > 0) hipLaunchKernelGGL(kernel, dim3(n), dim3(HH_WG), 0, stream, __VA_ARGS__); \
     } while (0)
 
+// level kernels: workgroup size of tile shape v
+#define LAUNCH_V(kernel, v, n, stream, ...)                                                          \
+    do {                                                                                             \
+        if ((n) > 0) hipLaunchKernelGGL(kernel, dim3(n), dim3(TileSet<DIM>::T[v]), 0, stream, __VA_ARGS__); \
+    } while (0)
+
 // launch context of a pass over `tiles` (a one-problem plan needs no tile
 // list: the workgroup index is the tile index)
 static Ctx ctx_of(const Plan &pl, const DevList &tiles)
@@ -472,11 +478,13 @@ static void launch_down_v(int v, int n, hipStream_t s, const Ctx &c, int lev, in
                           const LvPair<T> &lp)
 {
     switch (v) {
-    case 0: LAUNCH((k_vdown<DIM, T, TF, 0>), n, s, c, lev, fsel, fptr, lp); break;
-    case 1: LAUNCH((k_vdown<DIM, T, TF, 1>), n, s, c, lev, fsel, fptr, lp); break;
-    case 2: LAUNCH((k_vdown<DIM, T, TF, 2>), n, s, c, lev, fsel, fptr, lp); break;
-    case 3: LAUNCH((k_vdown<DIM, T, TF, 3>), n, s, c, lev, fsel, fptr, lp); break;
-    default: LAUNCH((k_vdown<DIM, T, TF, 4>), n, s, c, lev, fsel, fptr, lp); break;
+    case 0: LAUNCH_V((k_vdown<DIM, T, TF, 0>), 0, n, s, c, lev, fsel, fptr, lp); break;
+    case 1: LAUNCH_V((k_vdown<DIM, T, TF, 1>), 1, n, s, c, lev, fsel, fptr, lp); break;
+    case 2: LAUNCH_V((k_vdown<DIM, T, TF, 2>), 2, n, s, c, lev, fsel, fptr, lp); break;
+    case 3: LAUNCH_V((k_vdown<DIM, T, TF, 3>), 3, n, s, c, lev, fsel, fptr, lp); break;
+    case 4: LAUNCH_V((k_vdown<DIM, T, TF, 4>), 4, n, s, c, lev, fsel, fptr, lp); break;
+    case 5: LAUNCH_V((k_vdown<DIM, T, TF, 5>), 5, n, s, c, lev, fsel, fptr, lp); break;
+    default: LAUNCH_V((k_vdown<DIM, T, TF, 6>), 6, n, s, c, lev, fsel, fptr, lp); break;
     }
 }
 
@@ -485,11 +493,13 @@ static void launch_up_v(int v, int n, hipStream_t s, const Ctx &c, int lev, int 
                         void *optr, const LvPair<T> &lp)
 {
     switch (v) {
-    case 0: LAUNCH((k_vup<DIM, T, TF, TO, 0>), n, s, c, lev, fsel, osel, fptr, optr, lp); break;
-    case 1: LAUNCH((k_vup<DIM, T, TF, TO, 1>), n, s, c, lev, fsel, osel, fptr, optr, lp); break;
-    case 2: LAUNCH((k_vup<DIM, T, TF, TO, 2>), n, s, c, lev, fsel, osel, fptr, optr, lp); break;
-    case 3: LAUNCH((k_vup<DIM, T, TF, TO, 3>), n, s, c, lev, fsel, osel, fptr, optr, lp); break;
-    default: LAUNCH((k_vup<DIM, T, TF, TO, 4>), n, s, c, lev, fsel, osel, fptr, optr, lp); break;
+    case 0: LAUNCH_V((k_vup<DIM, T, TF, TO, 0>), 0, n, s, c, lev, fsel, osel, fptr, optr, lp); break;
+    case 1: LAUNCH_V((k_vup<DIM, T, TF, TO, 1>), 1, n, s, c, lev, fsel, osel, fptr, optr, lp); break;
+    case 2: LAUNCH_V((k_vup<DIM, T, TF, TO, 2>), 2, n, s, c, lev, fsel, osel, fptr, optr, lp); break;
+    case 3: LAUNCH_V((k_vup<DIM, T, TF, TO, 3>), 3, n, s, c, lev, fsel, osel, fptr, optr, lp); break;
+    case 4: LAUNCH_V((k_vup<DIM, T, TF, TO, 4>), 4, n, s, c, lev, fsel, osel, fptr, optr, lp); break;
+    case 5: LAUNCH_V((k_vup<DIM, T, TF, TO, 5>), 5, n, s, c, lev, fsel, osel, fptr, optr, lp); break;
+    default: LAUNCH_V((k_vup<DIM, T, TF, TO, 6>), 6, n, s, c, lev, fsel, osel, fptr, optr, lp); break;
     }
 }
 
@@ -560,14 +570,20 @@ static int tune_leg(const hh_grid *g, bool fp32, int leg, int l)
         if (it != g_tune.end()) return it->second;
     }
     // time every shape on this grid's level (inputs of level 0 from a
-    // scratch buffer; the level arrays it writes are rewritten by every use)
+    // scratch buffer; the level arrays it writes are rewritten by every use).
+    // Shapes are timed round-robin (a warm-up round, then NR timed rounds of
+    // RL back-to-back launches each, no host wait in between) so that clock
+    // and cache drift affect every shape alike; the median round decides.
+    constexpr int NR = 5, RL = 3;
     int best = 0;
     const int64_t N0 = hs.lev[0].N;
     void *in = nullptr, *out = nullptr;
     hipStream_t st = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    bool ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
-              hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    hipEvent_t ev[HH_NTILE][NR][2] = {};
+    bool ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    for (int v = 0; v < HH_NTILE && ok; ++v)
+        for (int r = 0; r < NR && ok; ++r)
+            ok = hipEventCreate(&ev[v][r][0]) == hipSuccess && hipEventCreate(&ev[v][r][1]) == hipSuccess;
     if (ok && l == 0)
         ok = hipMalloc(&in, sizeof(double2) * N0) == hipSuccess && hipMalloc(&out, sizeof(double2) * N0) == hipSuccess &&
              hipMemsetAsync(in, 0, sizeof(double2) * N0, st) == hipSuccess;
@@ -581,39 +597,47 @@ static int tune_leg(const hh_grid *g, bool fp32, int leg, int l)
         LvHost lh;
         lh.d = g->L64h;
         lh.f = g->L32h;
-        float bt = 0.f, tv[HH_NTILE] = {};
-        for (int v = 0; v < HH_NTILE && ok; ++v) {
+        int nt[HH_NTILE];
+        for (int v = 0; v < HH_NTILE; ++v) {
             int nd, nu;
             vtile_counts(hs.dim, v, hs.lev[l], hs.lev[l + 1], nd, nu);
-            const int n = leg == 0 ? nd : nu;
-            // two warm-up launches, then the median of five timed ones
-            for (int r = 0; r < 2; ++r) launch_leg_any(hs.dim, fp32, leg, v, n, st, c, l, VS_IN, VS_OUT, in, out, lh);
-            float rep[5];
-            for (int r = 0; r < 5 && ok; ++r) {
-                ok = hipEventRecord(e0, st) == hipSuccess;
-                launch_leg_any(hs.dim, fp32, leg, v, n, st, c, l, VS_IN, VS_OUT, in, out, lh);
-                ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-                     hipGetLastError() == hipSuccess && hipEventElapsedTime(&rep[r], e0, e1) == hipSuccess;
+            nt[v] = leg == 0 ? nd : nu;
+        }
+        for (int v = 0; v < HH_NTILE; ++v)
+            for (int q = 0; q < RL; ++q) launch_leg_any(hs.dim, fp32, leg, v, nt[v], st, c, l, VS_IN, VS_OUT, in, out, lh);
+        for (int r = 0; r < NR && ok; ++r)
+            for (int v = 0; v < HH_NTILE && ok; ++v) {
+                ok = hipEventRecord(ev[v][r][0], st) == hipSuccess;
+                for (int q = 0; q < RL; ++q) launch_leg_any(hs.dim, fp32, leg, v, nt[v], st, c, l, VS_IN, VS_OUT, in, out, lh);
+                ok = ok && hipEventRecord(ev[v][r][1], st) == hipSuccess;
             }
+        ok = ok && hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess;
+        float bt = 0.f, tv[HH_NTILE] = {};
+        for (int v = 0; v < HH_NTILE && ok; ++v) {
+            float rep[NR];
+            for (int r = 0; r < NR && ok; ++r) ok = hipEventElapsedTime(&rep[r], ev[v][r][0], ev[v][r][1]) == hipSuccess;
             if (!ok) break;
-            std::sort(rep, rep + 5);
-            const float ms = rep[2];
-            tv[v] = ms;
-            if (ok && (v == 0 || ms < bt)) {
-                bt = ms;
+            std::sort(rep, rep + NR);
+            tv[v] = rep[NR / 2] / RL;
+            if (v == 0 || tv[v] < bt) {
+                bt = tv[v];
                 best = v;
             }
         }
-        if (ok && getenv("HH_TUNE_LOG"))
-            fprintf(stderr, "hh tile tune: dim %d %s leg %s level %s 2^%d unknowns: %.1f %.1f %.1f %.1f %.1f us -> shape %d\n",
-                    hs.dim, fp32 ? "c64" : "c128", leg == 0 ? "down" : "up", l == 0 ? "finest" : "coarse", lg,
-                    tv[0] * 1e3f, tv[1] * 1e3f, tv[2] * 1e3f, tv[3] * 1e3f, tv[4] * 1e3f, best);
+        if (ok && getenv("HH_TUNE_LOG")) {
+            fprintf(stderr, "hh tile tune: dim %d %s leg %s level %s 2^%d unknowns:", hs.dim, fp32 ? "c64" : "c128",
+                    leg == 0 ? "down" : "up", l == 0 ? "finest" : "coarse", lg);
+            for (int v = 0; v < HH_NTILE; ++v) fprintf(stderr, " %.1f", tv[v] * 1e3f);
+            fprintf(stderr, " us -> shape %d\n", best);
+        }
     }
     if (st) (void)hipStreamSynchronize(st);
     if (in) (void)hipFree(in);
     if (out) (void)hipFree(out);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
+    for (int v = 0; v < HH_NTILE; ++v)
+        for (int r = 0; r < NR; ++r)
+            for (int q = 0; q < 2; ++q)
+                if (ev[v][r][q]) (void)hipEventDestroy(ev[v][r][q]);
     if (st) (void)hipStreamDestroy(st);
     if (!ok) return 0;
     std::lock_guard<std::mutex> lk(g_tune_mu);
