@@ -260,19 +260,25 @@ template <> struct TailMinv<float> { static constexpr int N = 64 * 64; };
 // the down-leg's tile; the up-leg's fine tile is twice it).  The kernels are
 // built for every shape of the set and the autotuner picks one per
 // (dimension, precision, leg, level class); results do not depend on it.
-#define HH_NTILE 7
+// In 3D, shapes HH_NBOX and up are z-streaming kernels: a column of X x Y
+// coarse points over Z coarse planes, walked plane by plane.
+#define HH_NTILE 9
+#define HH_NBOX 7
 template <int DIM> struct TileSet;
 template <> struct TileSet<2> {
-    static constexpr int X[HH_NTILE] = {16, 32, 16, 8, 32, 32, 32};
-    static constexpr int Y[HH_NTILE] = {16, 8, 8, 8, 16, 8, 16};
-    static constexpr int Z[HH_NTILE] = {1, 1, 1, 1, 1, 1, 1};
-    static constexpr int T[HH_NTILE] = {256, 256, 256, 256, 256, 512, 512};   // threads per workgroup
+    static constexpr int N = HH_NBOX;   // shapes in use
+    static constexpr int X[HH_NTILE] = {16, 32, 16, 8, 32, 32, 32, 16, 16};
+    static constexpr int Y[HH_NTILE] = {16, 8, 8, 8, 16, 8, 16, 16, 16};
+    static constexpr int Z[HH_NTILE] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
+    static constexpr int T[HH_NTILE] = {256, 256, 256, 256, 256, 512, 512, 256, 256};   // threads per workgroup
 };
 template <> struct TileSet<3> {
-    static constexpr int X[HH_NTILE] = {4, 8, 8, 4, 8, 8, 8};
-    static constexpr int Y[HH_NTILE] = {4, 4, 8, 4, 4, 4, 8};
-    static constexpr int Z[HH_NTILE] = {4, 4, 2, 2, 2, 4, 2};
-    static constexpr int T[HH_NTILE] = {256, 256, 256, 256, 256, 512, 512};
+    static constexpr int N = HH_NTILE;
+    static constexpr int X[HH_NTILE] = {4, 8, 8, 4, 8, 8, 8, 16, 8};
+    static constexpr int Y[HH_NTILE] = {4, 4, 8, 4, 4, 4, 8, 8, 8};
+    static constexpr int Z[HH_NTILE] = {4, 4, 2, 2, 2, 4, 2, 4, 4};
+    static constexpr int T[HH_NTILE] = {256, 256, 256, 256, 256, 512, 512, 512, 256};
 };
+inline int tile_shapes(int dim) { return dim == 2 ? TileSet<2>::N : TileSet<3>::N; }
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }

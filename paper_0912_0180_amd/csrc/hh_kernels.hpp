@@ -1047,6 +1047,477 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, in
 }
 
 // ---------------------------------------------------------------------------
+// 3D down-leg, z-streaming form (same results as k_vdown, value for value).
+// A workgroup owns a CX x CY column of coarse points over ZC coarse planes
+// and walks its fine planes upwards: the fine xy box (halo 2) of each plane
+// is computed once, four u1 planes and two residual planes stay in LDS, and
+// each coarse plane's full weighting is accumulated in registers as its four
+// fine planes go by (z terms in the same order as k_vdown).  One barrier per
+// fine plane; the loads of f and phi run PD planes ahead in registers.
+// Step j of the walk:  phase 1: u1 on plane j, restriction of residual plane
+// j - 3;  barrier;  phase 2: residual on plane j - 1.
+// ---------------------------------------------------------------------------
+template <typename T, int VT> struct ZTile {
+    static constexpr int CX = TileSet<3>::X[VT], CY = TileSet<3>::Y[VT], ZC = TileSet<3>::Z[VT];
+    static constexpr int NT = TileSet<3>::T[VT];
+    static constexpr int PD = 2;        // planes of f and phi loaded ahead
+    static constexpr int RS = PD + 1;   // register ring of planes
+};
+
+template <typename T, typename TF, int VT>
+__global__ __launch_bounds__(TileSet<3>::T[VT]) void k_vdown_z(Ctx cx, int lev, int fsel, const void *fptr, LvPair<T> lp)
+{
+    using C = V2<T>;
+    constexpr int CX = ZTile<T, VT>::CX, CY = ZTile<T, VT>::CY, ZC = ZTile<T, VT>::ZC, NT = ZTile<T, VT>::NT;
+    constexpr int RX = 2 * CX + 4, RY = 2 * CY + 4, RP = RX * RY;   // fine xy box, halo 2
+    constexpr int NZ = 2 * ZC + 4;                                  // fine planes of u1
+    constexpr int NL = (RP + NT - 1) / NT;                          // box points per thread
+    constexpr int RM = RX > RY ? RX : RY;
+    static_assert(CX * CY <= NT, "one thread per coarse column");
+    __shared__ C U[4][RP];
+    __shared__ C R[2][RP];
+    __shared__ C A[2][RM], Cc[2][RM], Dd[2][RM];   // x and y coefficients of the box
+    __shared__ C Az[NZ], Cz[NZ], Dz[NZ];           // z coefficients of the chunk's fine planes
+
+    const Tile tl = tile_of(cx);
+    const ProbDev *pd = cx.P + tl.prob;
+    LevelDev<T> Lf, Lc;
+    int run = PH_RUN;
+    if (lp.valid) {
+        run = phase_of(cx, tl.prob);
+        Lf = lp.f;
+        Lc = lp.c;
+    } else {
+        if (phase_of(cx, tl.prob) != PH_RUN) return;
+        const LevelDev<T> *Lv = levels_of<T>(cx, pd);
+        Lf = Lv[lev];
+        Lc = Lv[lev + 1];
+    }
+    const int nfx = Lf.n[0], nfy = Lf.n[1], nfz = Lf.n[2];
+    const int ncx = Lc.n[0], ncy = Lc.n[1], ncz = Lc.n[2];
+    const T *__restrict__ phi = Lf.phi;
+    C *__restrict__ fout = Lc.f;
+    const TF *__restrict__ f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lf.f;
+    const T omega = (T)(cx.L ? cx.omega : pd->omega);
+    const int tx = (ncx + CX - 1) / CX, ty = (ncy + CY - 1) / CY;
+    int t = tl.idx;
+    const int bx = t % tx;
+    t /= tx;
+    const int by = t % ty, bz = t / ty;
+    const int c0x = bx * CX, c0y = by * CY, c0z = bz * ZC;
+    const int ox = 2 * c0x - 2, oy = 2 * c0y - 2, oz = 2 * c0z - 2;
+    const C zero = cmk<T>(0, 0);
+    const int64_t sy = nfx, sz = (int64_t)nfx * nfy;
+    const int tid = threadIdx.x;
+
+    // this thread's box points (the same in every plane)
+    int64_t pxy[NL];
+    bool inxy[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int l = tid + q * NT;
+        const int gx = ox + l % RX, gy = oy + l / RX;
+        inxy[q] = l < RP && gx >= 0 && gx < nfx && gy >= 0 && gy < nfy;
+        pxy[q] = inxy[q] ? gx + sy * gy : 0;
+    }
+    // register ring of f and phi: plane j in slot j % RS
+    constexpr int PD = ZTile<T, VT>::PD, RS = ZTile<T, VT>::RS;
+    TF fr[RS][NL];
+    T pr[RS][NL];
+    auto load = [&](int j, TF(&fd)[NL], T(&pdst)[NL]) {
+        const int gz = oz + j;
+        const bool zin = j < NZ && gz >= 0 && gz < nfz;
+#pragma unroll
+        for (int q = 0; q < NL; ++q)
+            if (zin && inxy[q]) {
+                fd[q] = ldg(f, pxy[q] + sz * gz);
+                pdst[q] = ldg(phi, pxy[q] + sz * gz);
+            }
+    };
+#pragma unroll
+    for (int u = 0; u < PD; ++u) load(u, fr[u], pr[u]);
+    // coefficients of the box and of the chunk's planes
+    {
+        const V2<T> *ax0 = Lf.a[0], *cx0 = Lf.c[0], *dx0 = Lf.d[0];
+        const V2<T> *ax1 = Lf.a[1], *cx1 = Lf.c[1], *dx1 = Lf.d[1];
+        const V2<T> *ax2 = Lf.a[2], *cx2 = Lf.c[2], *dx2 = Lf.d[2];
+        for (int l = tid; l < RX + RY + NZ; l += NT) {
+            const int ax = l < RX ? 0 : (l < RX + RY ? 1 : 2);
+            const int q = ax == 0 ? l : (ax == 1 ? l - RX : l - RX - RY);
+            const int g = (ax == 0 ? ox : (ax == 1 ? oy : oz)) + q;
+            const int nn = ax == 0 ? nfx : (ax == 1 ? nfy : nfz);
+            const bool in = g >= 0 && g < nn;
+            const V2<T> *pa = ax == 0 ? ax0 : (ax == 1 ? ax1 : ax2);
+            const V2<T> *pc = ax == 0 ? cx0 : (ax == 1 ? cx1 : cx2);
+            const V2<T> *pdd = ax == 0 ? dx0 : (ax == 1 ? dx1 : dx2);
+            const C va = in ? ldg(pa, g) : zero, vc = in ? ldg(pc, g) : zero, vd = in ? ldg(pdd, g) : zero;
+            if (ax < 2) {
+                A[ax][q] = va;
+                Cc[ax][q] = vc;
+                Dd[ax][q] = vd;
+            } else {
+                Az[q] = va;
+                Cz[q] = vc;
+                Dz[q] = vd;
+            }
+        }
+    }
+    if (run != PH_RUN) return;   // uniform over the workgroup
+    __syncthreads();
+
+    // this thread's box columns: x and y coefficients and d_x + d_y, the
+    // same in every plane
+    int lxq[NL], lyq[NL];
+    C dxy[NL], a0q[NL], c0q[NL], a1q[NL], c1q[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int l = tid + q * NT < RP ? tid + q * NT : 0;
+        lxq[q] = l % RX;
+        lyq[q] = l / RX;
+        dxy[q] = cadd<T>(Dd[0][lxq[q]], Dd[1][lyq[q]]);
+        a0q[q] = A[0][lxq[q]];
+        c0q[q] = Cc[0][lxq[q]];
+        a1q[q] = A[1][lyq[q]];
+        c1q[q] = Cc[1][lyq[q]];
+    }
+    const T w0 = (T)0.125, w1 = (T)0.375;
+    // restriction: thread tid < CX * CY owns coarse column (ix, iy)
+    const int ix = tid % CX, iy = tid / CX;
+    const bool cown = tid < CX * CY && c0x + ix < ncx && c0y + iy < ncy;
+    C accOld = zero, accNew = zero;
+
+    // step j uses plane j (slot fj) and plane j - 1 (slot fm), then loads
+    // plane j + PD into the slot plane j - 1 leaves
+    auto step = [&](int j, TF(&fj)[NL], T(&pj)[NL], TF(&fm)[NL], T(&pm)[NL]) {
+        // phase 1a: u1 on plane j
+        if (j < NZ) {
+            const int gz = oz + j;
+            const bool zin = gz >= 0 && gz < nfz;
+            C *Uj = U[j & 3];
+#pragma unroll
+            for (int q = 0; q < NL; ++q) {
+                const int l = tid + q * NT;
+                if (l < RP) {
+                    C u1 = zero;
+                    if (zin && inxy[q]) {
+                        const C fv = ccvt<T>(fj[q]);
+                        const C d = cadd<T>(dxy[q], Dz[j]);
+                        C D = cmk<T>(d.x - pj[q], d.y);
+                        T qq = jscale<T>(omega, D);
+                        C gw = cmk<T>(D.x * qq, -(D.y * qq));
+                        u1 = cmul<T>(gw, fv);
+                    }
+                    Uj[l] = u1;
+                }
+            }
+        }
+        // phase 1b: restriction of residual plane m = j - 3 (box planes 1 .. NZ - 2)
+        const int m = j - 3;
+        if (m >= 1 && m <= NZ - 2 && cown) {
+            const C *Rm = R[m & 1];
+            const int bxl = 2 * ix + 1, byl = 2 * iy + 1;
+            C acc_y = zero;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const T wy = (b == 0 || b == 3) ? w0 : w1;
+                const C *row = &Rm[bxl + RX * (byl + b)];
+                C sx = crs<T>(w0, row[0]);
+                sx = cadd<T>(sx, crs<T>(w1, row[1]));
+                sx = cadd<T>(sx, crs<T>(w1, row[2]));
+                sx = cadd<T>(sx, crs<T>(w0, row[3]));
+                acc_y = b == 0 ? crs<T>(wy, sx) : cadd<T>(acc_y, crs<T>(wy, sx));
+            }
+            // plane m is term c = 0 of coarse plane (m - 1) / 2 and term
+            // c = 2 of the one below (m odd), or terms c = 1 and c = 3 (m even)
+            if (m & 1) {
+                const int i = (m - 1) >> 1;
+                if (i >= 1) accOld = cadd<T>(accOld, crs<T>(w1, acc_y));
+                accNew = crs<T>(w0, acc_y);
+            } else {
+                const int i = (m - 2) >> 1;
+                accNew = cadd<T>(accNew, crs<T>(w1, acc_y));
+                if (i >= 1) {
+                    accOld = cadd<T>(accOld, crs<T>(w0, acc_y));
+                    const int K = c0z + i - 1;
+                    if (K < ncz) stg(fout, (c0x + ix) + (int64_t)ncx * ((c0y + iy) + (int64_t)ncy * K), accOld);
+                }
+                accOld = accNew;
+            }
+        }
+        __syncthreads();
+        // phase 2: residual r = f - M u1 on plane j - 1 (inner box points)
+        const int r = j - 1;
+        if (r >= 1 && r <= NZ - 2) {
+            const int gzr = oz + r;
+            const bool zin = gzr >= 0 && gzr < nfz;
+            const C *Ub = U[(r - 1) & 3], *Uc = U[r & 3], *Ut = U[(r + 1) & 3];
+            C *Rr = R[r & 1];
+#pragma unroll
+            for (int q = 0; q < NL; ++q) {
+                const int l = tid + q * NT;
+                const int lx = lxq[q], ly = lyq[q];
+                if (l < RP && lx >= 1 && lx <= RX - 2 && ly >= 1 && ly <= RY - 2) {
+                    C res = zero;
+                    if (zin && inxy[q]) {
+                        const C d = cadd<T>(dxy[q], Dz[r]);
+                        C D = cmk<T>(d.x - pm[q], d.y);
+                        C mu = cmul<T>(D, Uc[l]);
+                        mu = csub<T>(mu, cmul<T>(a0q[q], Uc[l - 1]));
+                        mu = csub<T>(mu, cmul<T>(c0q[q], Uc[l + 1]));
+                        mu = csub<T>(mu, cmul<T>(a1q[q], Uc[l - RX]));
+                        mu = csub<T>(mu, cmul<T>(c1q[q], Uc[l + RX]));
+                        mu = csub<T>(mu, cmul<T>(Az[r], Ub[l]));
+                        mu = csub<T>(mu, cmul<T>(Cz[r], Ut[l]));
+                        res = csub<T>(ccvt<T>(fm[q]), mu);
+                    }
+                    Rr[l] = res;
+                }
+            }
+        }
+        load(j + PD, fm, pm);
+    };
+    constexpr int NS = NZ + 2;   // steps 0 .. NZ + 1
+    for (int j0 = 0; j0 < NS; j0 += RS) {
+#pragma unroll
+        for (int u = 0; u < RS; ++u)
+            if (j0 + u < NS) step(j0 + u, fr[u], pr[u], fr[(u + RS - 1) % RS], pr[(u + RS - 1) % RS]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3D up-leg, z-streaming form (same results as k_vup, value for value).
+// A workgroup owns a 2CX x 2CY column of fine points over 2ZC fine planes;
+// e of the coarse box it needs is staged in LDS first.  Step j: u2 = g f + P e
+// on plane j of the box (halo 1);  barrier;  smoothing of plane j - 1 and its
+// store.  Four u2 planes stay in LDS; f and phi run PD planes ahead in
+// registers.
+// ---------------------------------------------------------------------------
+template <typename T, typename TF, typename TO, int VT>
+__global__ __launch_bounds__(TileSet<3>::T[VT]) void k_vup_z(Ctx cx, int lev, int fsel, int osel, const void *fptr,
+                                                             void *optr, LvPair<T> lp)
+{
+    using C = V2<T>;
+    constexpr int CX = ZTile<T, VT>::CX, CY = ZTile<T, VT>::CY, ZC = ZTile<T, VT>::ZC, NT = ZTile<T, VT>::NT;
+    constexpr int FX = 2 * CX, FY = 2 * CY, FZ = 2 * ZC;
+    constexpr int RX = FX + 2, RY = FY + 2, RP = RX * RY;   // fine xy box, halo 1
+    constexpr int NZ = FZ + 2;                             // fine planes of u2
+    constexpr int EX = CX + 4, EY = CY + 4, EZ = ZC + 4, EN = EX * EY * EZ;
+    constexpr int NL = (RP + NT - 1) / NT;
+    constexpr int NE = (EN + NT - 1) / NT;
+    constexpr int RM = RX > RY ? RX : RY;
+    __shared__ C U[4][RP];
+    __shared__ C E[EN];
+    __shared__ C A[2][RM], Cc[2][RM], Dd[2][RM];
+    __shared__ C Az[NZ], Cz[NZ], Dz[NZ];
+
+    const Tile tl = tile_of(cx);
+    const ProbDev *pd = cx.P + tl.prob;
+    LevelDev<T> Lf, Lc;
+    int run = PH_RUN;
+    if (lp.valid) {
+        run = phase_of(cx, tl.prob);
+        Lf = lp.f;
+        Lc = lp.c;
+    } else {
+        if (phase_of(cx, tl.prob) != PH_RUN) return;
+        const LevelDev<T> *Lv = levels_of<T>(cx, pd);
+        Lf = Lv[lev];
+        Lc = Lv[lev + 1];
+    }
+    const int nfx = Lf.n[0], nfy = Lf.n[1], nfz = Lf.n[2];
+    const int ncx = Lc.n[0], ncy = Lc.n[1], ncz = Lc.n[2];
+    const T *__restrict__ phi = Lf.phi;
+    const C *__restrict__ ec = Lc.e;
+    C *__restrict__ eout = Lf.e;
+    const TF *__restrict__ f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lf.f;
+    TO *__restrict__ outv = lev == 0 ? (TO *)(optr ? optr : pd->vec[osel]) : nullptr;
+    const T omega = (T)(cx.L ? cx.omega : pd->omega);
+    const int tx = (nfx + FX - 1) / FX, ty = (nfy + FY - 1) / FY;
+    int t = tl.idx;
+    const int bx = t % tx;
+    t /= tx;
+    const int by = t % ty, bz = t / ty;
+    const int f0x = bx * FX, f0y = by * FY, f0z = bz * FZ;
+    const int ox = f0x - 1, oy = f0y - 1, oz = f0z - 1;
+    const int ex0 = (f0x >> 1) - 2, ey0 = (f0y >> 1) - 2, ez0 = (f0z >> 1) - 2;
+    const C zero = cmk<T>(0, 0);
+    const int64_t sy = nfx, sz = (int64_t)nfx * nfy;
+    const int tid = threadIdx.x;
+
+    int64_t pxy[NL];
+    bool inxy[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int l = tid + q * NT;
+        const int gx = ox + l % RX, gy = oy + l / RX;
+        inxy[q] = l < RP && gx >= 0 && gx < nfx && gy >= 0 && gy < nfy;
+        pxy[q] = inxy[q] ? gx + sy * gy : 0;
+    }
+    constexpr int PD = ZTile<T, VT>::PD, RS = ZTile<T, VT>::RS;
+    TF fr[RS][NL];
+    T pr[RS][NL];
+    auto load = [&](int j, TF(&fd)[NL], T(&pdst)[NL]) {
+        const int gz = oz + j;
+        const bool zin = j < NZ && gz >= 0 && gz < nfz;
+#pragma unroll
+        for (int q = 0; q < NL; ++q)
+            if (zin && inxy[q]) {
+                fd[q] = ldg(f, pxy[q] + sz * gz);
+                pdst[q] = ldg(phi, pxy[q] + sz * gz);
+            }
+    };
+#pragma unroll
+    for (int u = 0; u < PD; ++u) load(u, fr[u], pr[u]);
+    // e on the coarse box
+    {
+        C er[NE];
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int l = tid + q * NT;
+            const int lx = l % EX, ly = (l / EX) % EY, lz = l / (EX * EY);
+            const int gx = ex0 + lx, gy = ey0 + ly, gz = ez0 + lz;
+            er[q] = zero;
+            if (l < EN && gx >= 0 && gx < ncx && gy >= 0 && gy < ncy && gz >= 0 && gz < ncz)
+                er[q] = ldg(ec, gx + (int64_t)ncx * (gy + (int64_t)ncy * gz));
+        }
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int l = tid + q * NT;
+            if (l < EN) E[l] = er[q];
+        }
+    }
+    {
+        const V2<T> *ax0 = Lf.a[0], *cx0 = Lf.c[0], *dx0 = Lf.d[0];
+        const V2<T> *ax1 = Lf.a[1], *cx1 = Lf.c[1], *dx1 = Lf.d[1];
+        const V2<T> *ax2 = Lf.a[2], *cx2 = Lf.c[2], *dx2 = Lf.d[2];
+        for (int l = tid; l < RX + RY + NZ; l += NT) {
+            const int ax = l < RX ? 0 : (l < RX + RY ? 1 : 2);
+            const int q = ax == 0 ? l : (ax == 1 ? l - RX : l - RX - RY);
+            const int g = (ax == 0 ? ox : (ax == 1 ? oy : oz)) + q;
+            const int nn = ax == 0 ? nfx : (ax == 1 ? nfy : nfz);
+            const bool in = g >= 0 && g < nn;
+            const V2<T> *pa = ax == 0 ? ax0 : (ax == 1 ? ax1 : ax2);
+            const V2<T> *pc = ax == 0 ? cx0 : (ax == 1 ? cx1 : cx2);
+            const V2<T> *pdd = ax == 0 ? dx0 : (ax == 1 ? dx1 : dx2);
+            const C va = in ? ldg(pa, g) : zero, vc = in ? ldg(pc, g) : zero, vd = in ? ldg(pdd, g) : zero;
+            if (ax < 2) {
+                A[ax][q] = va;
+                Cc[ax][q] = vc;
+                Dd[ax][q] = vd;
+            } else {
+                Az[q] = va;
+                Cz[q] = vc;
+                Dz[q] = vd;
+            }
+        }
+    }
+    if (run != PH_RUN) return;   // uniform over the workgroup
+    __syncthreads();
+    const T p3 = (T)0.75, p1 = (T)0.25;
+    // this thread's box columns: x and y coefficients, d_x + d_y and the
+    // prolongation columns, the same in every plane
+    int lxq[NL], lyq[NL], ixq[NL], ioxq[NL], iyq[NL], ioyq[NL];
+    C dxy[NL], a0q[NL], c0q[NL], a1q[NL], c1q[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int l = tid + q * NT < RP ? tid + q * NT : 0;
+        lxq[q] = l % RX;
+        lyq[q] = l / RX;
+        const int gx = ox + lxq[q], gy = oy + lyq[q];
+        ixq[q] = (gx >> 1) - ex0;
+        ioxq[q] = ((gx & 1) ? (gx >> 1) + 1 : (gx >> 1) - 1) - ex0;
+        iyq[q] = (gy >> 1) - ey0;
+        ioyq[q] = ((gy & 1) ? (gy >> 1) + 1 : (gy >> 1) - 1) - ey0;
+        dxy[q] = cadd<T>(Dd[0][lxq[q]], Dd[1][lyq[q]]);
+        a0q[q] = A[0][lxq[q]];
+        c0q[q] = Cc[0][lxq[q]];
+        a1q[q] = A[1][lyq[q]];
+        c1q[q] = Cc[1][lyq[q]];
+    }
+
+    auto step = [&](int j, TF(&fj)[NL], T(&pj)[NL], TF(&fm)[NL], T(&pm)[NL]) {
+        // phase 1: u2 = g f + P e on plane j
+        if (j < NZ) {
+            const int gz = oz + j;
+            const bool zin = gz >= 0 && gz < nfz;
+            const int Iz = (gz >> 1) - ez0, Ioz = ((gz & 1) ? (gz >> 1) + 1 : (gz >> 1) - 1) - ez0;
+            C *Uj = U[j & 3];
+#pragma unroll
+            for (int q = 0; q < NL; ++q) {
+                const int l = tid + q * NT;
+                if (l < RP) {
+                    C u2 = zero;
+                    if (zin && inxy[q]) {
+                        const C fv = ccvt<T>(fj[q]);
+                        const C d = cadd<T>(dxy[q], Dz[j]);
+                        C D = cmk<T>(d.x - pj[q], d.y);
+                        T qq = jscale<T>(omega, D);
+                        C gw = cmk<T>(D.x * qq, -(D.y * qq));
+                        C u1 = cmul<T>(gw, fv);
+                        const int Ix = ixq[q], Iox = ioxq[q], Iy = iyq[q], Ioy = ioyq[q];
+                        C pz[2];
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const int zz = c == 0 ? Iz : Ioz;
+                            C a0 = cadd<T>(crs<T>(p3, E[Ix + EX * (Iy + EY * zz)]), crs<T>(p1, E[Iox + EX * (Iy + EY * zz)]));
+                            C a1 = cadd<T>(crs<T>(p3, E[Ix + EX * (Ioy + EY * zz)]), crs<T>(p1, E[Iox + EX * (Ioy + EY * zz)]));
+                            pz[c] = cadd<T>(crs<T>(p3, a0), crs<T>(p1, a1));
+                        }
+                        const C pe = cadd<T>(crs<T>(p3, pz[0]), crs<T>(p1, pz[1]));
+                        u2 = cadd<T>(u1, pe);
+                    }
+                    Uj[l] = u2;
+                }
+            }
+        }
+        __syncthreads();
+        // phase 2: smoothing of plane j - 1 on the tile, and its store
+        const int r = j - 1;
+        if (r >= 1 && r <= NZ - 2) {
+            const int gz = oz + r;
+            const C *Ub = U[(r - 1) & 3], *Uc = U[r & 3], *Ut = U[(r + 1) & 3];
+            if (gz < nfz) {
+#pragma unroll
+                for (int q = 0; q < NL; ++q) {
+                    const int l = tid + q * NT;
+                    const int lx = lxq[q], ly = lyq[q];
+                    if (l < RP && lx >= 1 && lx <= FX && ly >= 1 && ly <= FY && ox + lx < nfx && oy + ly < nfy) {
+                        const C d = cadd<T>(dxy[q], Dz[r]);
+                        C D = cmk<T>(d.x - pm[q], d.y);
+                        T qq = jscale<T>(omega, D);
+                        C gw = cmk<T>(D.x * qq, -(D.y * qq));
+                        C mu = cmul<T>(D, Uc[l]);
+                        mu = csub<T>(mu, cmul<T>(a0q[q], Uc[l - 1]));
+                        mu = csub<T>(mu, cmul<T>(c0q[q], Uc[l + 1]));
+                        mu = csub<T>(mu, cmul<T>(a1q[q], Uc[l - RX]));
+                        mu = csub<T>(mu, cmul<T>(c1q[q], Uc[l + RX]));
+                        mu = csub<T>(mu, cmul<T>(Az[r], Ub[l]));
+                        mu = csub<T>(mu, cmul<T>(Cz[r], Ut[l]));
+                        C u = cadd<T>(Uc[l], cmul<T>(gw, csub<T>(ccvt<T>(fm[q]), mu)));
+                        const int64_t p = pxy[q] + sz * gz;
+                        if (lev == 0) {
+                            TO o;
+                            o.x = u.x;
+                            o.y = u.y;
+                            stg(outv, p, o);
+                        } else {
+                            stg(eout, p, u);
+                        }
+                    }
+                }
+            }
+        }
+        load(j + PD, fm, pm);
+    };
+    constexpr int NS = NZ;   // steps 0 .. NZ - 1
+    for (int j0 = 0; j0 < NS; j0 += RS) {
+#pragma unroll
+        for (int u = 0; u < RS; ++u)
+            if (j0 + u < NS) step(j0 + u, fr[u], pr[u], fr[(u + RS - 1) % RS], pr[(u + RS - 1) % RS]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // tail of the V-cycle: every level from `tail` down to the coarsest inside
 // one workgroup, all fields in LDS.  Reads f_tail, writes e_tail.  Same
 // arithmetic as the tiled kernels; the coarsest solve applies the explicit

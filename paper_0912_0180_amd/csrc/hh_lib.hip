@@ -484,7 +484,13 @@ static void launch_down_v(int v, int n, hipStream_t s, const Ctx &c, int lev, in
     case 3: LAUNCH_V((k_vdown<DIM, T, TF, 3>), 3, n, s, c, lev, fsel, fptr, lp); break;
     case 4: LAUNCH_V((k_vdown<DIM, T, TF, 4>), 4, n, s, c, lev, fsel, fptr, lp); break;
     case 5: LAUNCH_V((k_vdown<DIM, T, TF, 5>), 5, n, s, c, lev, fsel, fptr, lp); break;
-    default: LAUNCH_V((k_vdown<DIM, T, TF, 6>), 6, n, s, c, lev, fsel, fptr, lp); break;
+    case 6: LAUNCH_V((k_vdown<DIM, T, TF, 6>), 6, n, s, c, lev, fsel, fptr, lp); break;
+    default:
+        if constexpr (DIM == 3) {
+            if (v == 7) LAUNCH_V((k_vdown_z<T, TF, 7>), 7, n, s, c, lev, fsel, fptr, lp);
+            else LAUNCH_V((k_vdown_z<T, TF, 8>), 8, n, s, c, lev, fsel, fptr, lp);
+        }
+        break;
     }
 }
 
@@ -499,7 +505,13 @@ static void launch_up_v(int v, int n, hipStream_t s, const Ctx &c, int lev, int 
     case 3: LAUNCH_V((k_vup<DIM, T, TF, TO, 3>), 3, n, s, c, lev, fsel, osel, fptr, optr, lp); break;
     case 4: LAUNCH_V((k_vup<DIM, T, TF, TO, 4>), 4, n, s, c, lev, fsel, osel, fptr, optr, lp); break;
     case 5: LAUNCH_V((k_vup<DIM, T, TF, TO, 5>), 5, n, s, c, lev, fsel, osel, fptr, optr, lp); break;
-    default: LAUNCH_V((k_vup<DIM, T, TF, TO, 6>), 6, n, s, c, lev, fsel, osel, fptr, optr, lp); break;
+    case 6: LAUNCH_V((k_vup<DIM, T, TF, TO, 6>), 6, n, s, c, lev, fsel, osel, fptr, optr, lp); break;
+    default:
+        if constexpr (DIM == 3) {
+            if (v == 7) LAUNCH_V((k_vup_z<T, TF, TO, 7>), 7, n, s, c, lev, fsel, osel, fptr, optr, lp);
+            else LAUNCH_V((k_vup_z<T, TF, TO, 8>), 8, n, s, c, lev, fsel, osel, fptr, optr, lp);
+        }
+        break;
     }
 }
 
@@ -557,7 +569,7 @@ static std::map<std::array<int, 5>, int> g_tune;
 
 static int tune_leg(const hh_grid *g, bool fp32, int leg, int l)
 {
-    if (const char *e = getenv("HH_TILE")) return std::min(std::max(atoi(e), 0), HH_NTILE - 1);
+    if (const char *e = getenv("HH_TILE")) return std::min(std::max(atoi(e), 0), tile_shapes(g->hs.dim) - 1);
     if (const char *e = getenv("HH_TUNE"))
         if (atoi(e) == 0) return 0;
     const HostSetup &hs = g->hs;
@@ -597,23 +609,24 @@ static int tune_leg(const hh_grid *g, bool fp32, int leg, int l)
         LvHost lh;
         lh.d = g->L64h;
         lh.f = g->L32h;
+        const int ns = tile_shapes(hs.dim);
         int nt[HH_NTILE];
-        for (int v = 0; v < HH_NTILE; ++v) {
+        for (int v = 0; v < ns; ++v) {
             int nd, nu;
             vtile_counts(hs.dim, v, hs.lev[l], hs.lev[l + 1], nd, nu);
             nt[v] = leg == 0 ? nd : nu;
         }
-        for (int v = 0; v < HH_NTILE; ++v)
+        for (int v = 0; v < ns; ++v)
             for (int q = 0; q < RL; ++q) launch_leg_any(hs.dim, fp32, leg, v, nt[v], st, c, l, VS_IN, VS_OUT, in, out, lh);
         for (int r = 0; r < NR && ok; ++r)
-            for (int v = 0; v < HH_NTILE && ok; ++v) {
+            for (int v = 0; v < ns && ok; ++v) {
                 ok = hipEventRecord(ev[v][r][0], st) == hipSuccess;
                 for (int q = 0; q < RL; ++q) launch_leg_any(hs.dim, fp32, leg, v, nt[v], st, c, l, VS_IN, VS_OUT, in, out, lh);
                 ok = ok && hipEventRecord(ev[v][r][1], st) == hipSuccess;
             }
         ok = ok && hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess;
         float bt = 0.f, tv[HH_NTILE] = {};
-        for (int v = 0; v < HH_NTILE && ok; ++v) {
+        for (int v = 0; v < ns && ok; ++v) {
             float rep[NR];
             for (int r = 0; r < NR && ok; ++r) ok = hipEventElapsedTime(&rep[r], ev[v][r][0], ev[v][r][1]) == hipSuccess;
             if (!ok) break;
@@ -627,7 +640,7 @@ static int tune_leg(const hh_grid *g, bool fp32, int leg, int l)
         if (ok && getenv("HH_TUNE_LOG")) {
             fprintf(stderr, "hh tile tune: dim %d %s leg %s level %s 2^%d unknowns:", hs.dim, fp32 ? "c64" : "c128",
                     leg == 0 ? "down" : "up", l == 0 ? "finest" : "coarse", lg);
-            for (int v = 0; v < HH_NTILE; ++v) fprintf(stderr, " %.1f", tv[v] * 1e3f);
+            for (int v = 0; v < ns; ++v) fprintf(stderr, " %.1f", tv[v] * 1e3f);
             fprintf(stderr, " us -> shape %d\n", best);
         }
     }
