@@ -185,7 +185,7 @@ def bench_c2(args, torch, hh, W, out):
     out["vcycle_GBps_mixed"] = vcycle_bytes(g, True) / tv32 / 1e9
     ah = apply_bytes(g) / th / 1e9
     out["applyH_us"] = th * 1e6
-    out["roofline"] = {"bound": "hbm", "kernel": "hh::k_applyH<2> (y = H x, c128, variable k)",
+    out["roofline"] = {"bound": "hbm", "kernel": "hh::k_applyH_band (y = H x, 2D rows of 256k, c128, variable k)",
                        "achieved": ah, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ah / HBM_PEAK_GBPS,
                        "traffic": measured_traffic(), "bytes_per_unknown": 40, "unknowns_per_launch": g.N,
                        "algorithmic_bytes_per_launch": apply_bytes(g), "launch_us": th * 1e6}
@@ -373,7 +373,7 @@ def pmc_probe(torch, hh, W):
     for i in range(10):
         torch.mul(xs[i % 2], 1, out=ys[i % 2])
     torch.cuda.synchronize()
-    print("pmc probe: 10 x k_applyH<2> on %d unknowns, 10 x elementwise copy of %d bytes" % (g.N, 4 * n), flush=True)
+    print("pmc probe: 10 x k_applyH_band on %d unknowns, 10 x elementwise copy of %d bytes" % (g.N, 4 * n), flush=True)
 
 
 def main():

@@ -275,6 +275,65 @@ __device__ inline V2<T> stencil(const VW &h, const S *__restrict__ x, int i, int
     return t;
 }
 
+// 2D band layout of the operator apply for rows whose length is a multiple of
+// 256: a workgroup takes 256 columns of two rows and a thread evaluates its
+// column in both rows, loading the x coefficients and the shared centre and
+// neighbour values once; every value as in stencil<2, double>.  (The matvec
+// kernels of the Krylov iteration keep one chunk per workgroup: their
+// per-chunk dot products make the two-row workgroup slower there.)
+struct Band {
+    int i, j0, nr;
+    int64_t p0;
+};
+__device__ inline Band band_of(const HView &h, int idx)
+{
+    const int nbx = h.nx >> 8;
+    const int bx = idx % nbx, by = idx / nbx;
+    Band b;
+    b.i = (bx << 8) + (int)threadIdx.x;
+    b.j0 = 2 * by;
+    b.nr = h.ny - b.j0 < 2 ? h.ny - b.j0 : 2;
+    b.p0 = (int64_t)b.j0 * h.nx + b.i;
+    return b;
+}
+template <typename S>
+__device__ inline void stencil_band(const HView &h, const S *__restrict__ x, const Band &b, double2 (&y)[2])
+{
+    using C = double2;
+    const C zero = cmk<double>(0, 0);
+    const int i = b.i, j0 = b.j0;
+    const int64_t sy = h.nx, p0 = b.p0;
+    const C a0 = ldg(h.a0, i), c0 = ldg(h.c0, i), d0 = ldg(h.d0, i);
+    const C xs = j0 > 0 ? ld64(x, p0 - sy) : zero;
+    const C xc = ld64(x, p0);
+    const C x1 = j0 < h.ny - 1 ? ld64(x, p0 + sy) : zero;       // row j0 + 1
+    const C x2 = j0 + 1 < h.ny - 1 ? ld64(x, p0 + 2 * sy) : zero;
+    C w[2], e[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int64_t p = p0 + r * sy;
+        const bool in = r < b.nr;
+        w[r] = in && i > 0 ? ld64(x, p - 1) : zero;
+        e[r] = in && i < h.nx - 1 ? ld64(x, p + 1) : zero;
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        if (r >= b.nr) break;
+        const int j = j0 + r;
+        const int64_t p = p0 + r * sy;
+        const C xcr = r == 0 ? xc : x1, xsr = r == 0 ? xs : xc, xnr = r == 0 ? x1 : x2;
+        C d = d0;
+        d = cadd<double>(d, ldg(h.d1, j));
+        C D = cmk<double>(d.x - ldg(h.phi, p), d.y);
+        C t = cmul<double>(D, xcr);
+        t = csub<double>(t, cmul<double>(a0, w[r]));
+        t = csub<double>(t, cmul<double>(c0, e[r]));
+        t = csub<double>(t, cmul<double>(ldg(h.a1, j), xsr));
+        t = csub<double>(t, cmul<double>(ldg(h.c1, j), xnr));
+        y[r] = t;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // finalisation: the last workgroup of a reducing pass (per problem) sums the
 // chunk partials in the fixed pairwise order and advances the scalar state
@@ -662,6 +721,18 @@ __global__ __launch_bounds__(HH_WG) void k_applyH(Ctx cx, const void *xp, void *
         const int64_t p = base + threadIdx.x + (int64_t)HH_WG * s;
         if (p < h.N) stg(y, p, out[s]);
     }
+}
+
+// y = H x in the 2D band layout (one problem, no tile list)
+__global__ __launch_bounds__(HH_WG) void k_applyH_band(Ctx cx, const void *xp, void *yp)
+{
+    const HView h = hview(cx.P);
+    const Band b = band_of(h, xcd_tile_index());
+    double2 y[2];
+    stencil_band(h, (const double2 *)xp, b, y);
+    double2 *__restrict__ yo = (double2 *)yp;
+    stg(yo, b.p0, y[0]);
+    if (b.nr > 1) stg(yo, b.p0 + h.nx, y[1]);
 }
 
 template <int DIM, typename T>
