@@ -432,6 +432,27 @@ __device__ void reduce_partials(const double *part, int n, int first, int nv, do
         }
         return;
     }
+    if (np > 32 * HH_WG && np <= 64 * 32 * HH_WG) {
+        // longer: aligned blocks of 32 * 256 partials (subtrees) by the
+        // blocked path one value at a time, then the block sums pairwise
+        constexpr int B = 32 * HH_WG;
+        const int nblk = np / B;
+        for (int q = 0; q < nv; ++q) {
+            for (int b = 0; b < nblk; ++b) {
+                const int valid = n - b * B < B ? (n - b * B > 0 ? n - b * B : 0) : B;
+                reduce_values_blocked<32, 1>(part, valid, (int64_t)(first + q) * n + (int64_t)b * B, 1, &bsum[q][b], stage);
+                __syncthreads();
+            }
+        }
+        if (threadIdx.x < nv) {
+            const int q = threadIdx.x;
+            for (int w = 1; w < nblk; w <<= 1)
+                for (int i = 0; i + w < nblk; i += 2 * w) bsum[q][i] = bsum[q][i] + bsum[q][i + w];
+            out[q] = bsum[q][0];
+        }
+        __syncthreads();
+        return;
+    }
     // values per staging pass: all nv at once when they fit
     const int blk = np < HH_FIN_STAGE ? np : HH_FIN_STAGE;
     const int qstep = (HH_FIN_STAGE / blk) < nv ? (HH_FIN_STAGE / blk) : nv;

@@ -377,6 +377,23 @@ def test_graph_replay_equals_eager(torch_dev, hh_mod, monkeypatch):
             assert same(r[0], ref[0]) and same(r[2], ref[2]), mode
 
 
+def test_long_partial_arrays_match_oracle(torch_dev, hh_mod, oracle_mod):
+    """2048^2 has 16384 reduction chunks, more than one finaliser block: the
+    first FP64 matvecs give the oracle's residual history and iterate value
+    for value."""
+    torch = torch_dev
+    c = W.c2(n=2048, levels=9)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    b = rand_c(np.random.default_rng(17), g.N)
+    xo, io = o.solve(b, tol=1e-14, max_matvec=4, history=True)
+    xg, ig = g.solve(dev(torch, b), tol=1e-14, max_matvec=4, vcycle_prec="c128", history=True)
+    assert ig["matvecs"] == io["matvecs"] == 4
+    assert np.array_equal(ig["history"], io["history"])
+    assert same(host(xg), xo)
+    assert ig["rel_res_true"] == io["rel_res_true"]
+
+
 @pytest.mark.parametrize("name", ["c2_256", "ragged_2d", "ragged_3d", "c3_32"])
 def test_every_tile_shape_gives_the_same_cycle(torch_dev, hh_mod, oracle_mod, monkeypatch, name):
     """The autotuner may pick any tile shape: every shape must give the FP64
