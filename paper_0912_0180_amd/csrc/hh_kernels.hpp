@@ -6,16 +6,21 @@
 // the running phase return at once.
 //
 // Arithmetic follows a fixed operation order (no FMA contraction; the build
-// passes -ffp-contract=off), so FP64 results are reproducible run to run and
-// independent of how problems are batched:
+// passes -ffp-contract=off), so FP64 results are reproducible run to run,
+// independent of how problems are batched or tiled, and equal to the
+// oracle's value for value:
 //   complex multiply (ar*br - ai*bi, ar*bi + ai*br); Jacobi weight
 //   g = omega conj(D)/|D|^2 with D = (d_x + d_y + d_z) - phi; stencil
 //   y = D u - a_x u_w - c_x u_e - a_y u_s - c_y u_n - a_z u_d - c_z u_u;
 //   full weighting (1,3,3,1)/8 applied x, then y, then z; prolongation
 //   3/4 near + 1/4 far applied x, then y, then z; reductions over chunks of
-//   2048 elements, thread slot t summing elements t + 256 j (j = 0..7) in
-//   order, slots combined by a pairwise tree (wave butterfly, then
-//   (w0 + w1) + (w2 + w3)), chunk partials by a pairwise tree.
+//   256 elements (one per thread slot), each chunk a pairwise tree (wave
+//   pairs by DPP, then (w0 + w1) + (w2 + w3)), chunk partials by a pairwise
+//   tree over their zero-padded power-of-two count.
+// The FP32 V-cycle of mixed solves is held to a tolerance against FP64, not
+// to this order: its complex products use fused multiply-adds and its
+// Jacobi weight the hardware reciprocal.  Every FP32 kernel uses the same
+// formulas, so FP32 results are still independent of batching and tiling.
 //
 // Memory-level parallelism: each thread first issues all of its global loads
 // into registers, then computes, then stores, so several HBM requests per
@@ -335,8 +340,8 @@ __device__ inline void stencil_band(const HView &h, const S *__restrict__ x, con
 }
 
 // ---------------------------------------------------------------------------
-// finalisation: the last workgroup of a reducing pass (per problem) sums the
-// chunk partials in the fixed pairwise order and advances the scalar state
+// finalisation: one workgroup per problem (k_fin) sums the chunk partials of
+// a reducing pass in the fixed pairwise order and advances the scalar state
 // ---------------------------------------------------------------------------
 #define HH_FIN_STAGE 16384
 
