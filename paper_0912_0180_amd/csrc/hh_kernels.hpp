@@ -1869,8 +1869,11 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
     __shared__ TailTab tab;
     __shared__ C minv_lds[TailMinv<T>::N];
     // FP32 with a coarsest grid of at most 64 unknowns: the coarsest inverse
-    // (32 KiB) comes into LDS with the image, off the critical path
+    // (32 KiB) is loaded with the image and goes to LDS just before the solve
     const bool mlds = sizeof(T) == 4 && !up && !split && pd->Nc <= TailMinv<T>::N / 64 && pd->Nc <= 64;
+    constexpr int MT = (TailMinv<T>::N + TailCap<T>::WG - 1) / TailCap<T>::WG;
+    const int nm = pd->Nc * pd->Nc;
+    C mt[MT];   // coarsest inverse in flight (mlds)
     const C *fg_top = Lv[t0].f;
     C *eg_top = Lv[t0].e;
     const C *__restrict__ Minv = (const C *)(sizeof(T) == 8 ? (const void *)pd->Minv64 : (const void *)pd->Minv32);
@@ -1884,18 +1887,12 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
         const int nseg = sizeof(T) == 8 ? pd->tnseg64 : pd->tnseg32;
         hh_uvec4 *l16 = (hh_uvec4 *)lds;
         if (mlds) {
-            constexpr int MT = (TailMinv<T>::N + TailCap<T>::WG - 1) / TailCap<T>::WG;
-            const int nm = pd->Nc * pd->Nc;
-            C mt[MT];
+            // stays in registers until the coarse solve; its latency overlaps
+            // the image, f and the down-legs
 #pragma unroll
             for (int q = 0; q < MT; ++q) {
                 const int i = tid + q * nth;
                 if (i < nm) mt[q] = ldg(Minv, i);
-            }
-#pragma unroll
-            for (int q = 0; q < MT; ++q) {
-                const int i = tid + q * nth;
-                if (i < nm) minv_lds[i] = mt[q];
             }
         }
         // f of the top level leads the LDS block (offset 0)
@@ -2027,6 +2024,14 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
     }
     // coarsest solve
     if (!up) {
+        if (mlds) {
+#pragma unroll
+            for (int q = 0; q < MT; ++q) {
+                const int i = tid + q * nth;
+                if (i < nm) minv_lds[i] = mt[q];
+            }
+            __syncthreads();
+        }
         const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, L - 1);
         if constexpr (sizeof(T) == 4) {
             // at most 64 unknowns (one segment) from LDS, else 65..128 (two)
