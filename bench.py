@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 # HBM traffic of the roofline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs (see the file); valid only while the kernel sources are unchanged
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_applyH_2d_1024_pmc.md")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_applyH_band_2d_1024_pmc.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0912_0180_amd", "csrc", f) for f in ("hh_kernels.hpp", "hh_common.h")]
 
 
