@@ -250,11 +250,6 @@ struct Ctx {
 template <typename T> struct TailCap;
 template <> struct TailCap<double> { static constexpr int N = 1024; static constexpr int BYTES = 96 * 1024; static constexpr int WG = 256; };
 template <> struct TailCap<float> { static constexpr int N = 1024; static constexpr int BYTES = 64 * 1024; static constexpr int WG = 512; };
-// LDS copy of the coarsest inverse inside the tail kernel (FP32, at most 64
-// unknowns on the coarsest grid); none for FP64
-template <typename T> struct TailMinv;
-template <> struct TailMinv<double> { static constexpr int N = 1; };
-template <> struct TailMinv<float> { static constexpr int N = 64 * 64; };
 
 // Tile shapes of the fused V-cycle level kernels (coarse points per axis of
 // the down-leg's tile; the up-leg's fine tile is twice it).  The kernels are

@@ -1628,7 +1628,7 @@ template <typename T> __host__ __device__ constexpr int coarse_slots(int seg)
 }
 
 // (always inlined: LDS operands then keep their address space)
-template <typename T, int SEG, bool MLDS = false>
+template <typename T, int SEG>
 __device__ __forceinline__ void coarse_rows_seg(const V2<T> *__restrict__ Minv, const V2<T> *f, V2<T> *e, int n, int row0, int rstep)
 {
     constexpr int NS = coarse_slots<T>(SEG);
@@ -1654,7 +1654,7 @@ __device__ __forceinline__ void coarse_rows_seg(const V2<T> *__restrict__ Minv, 
             for (int q = 0; q < 8; ++q) {
                 const int row = rb + ((h + q) / SEG) * rstep, col = lane * SEG + (h + q) % SEG;
                 const int64_t idx = (row < n && col < n) ? (int64_t)row * n + col : 0;
-                mv[q] = MLDS ? Minv[idx] : ldg(Minv, idx);
+                mv[q] = ldg(Minv, idx);
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -1707,12 +1707,40 @@ __host__ __device__ inline int coarse_seg(int n)
     while (np < n) np <<= 1;
     return np >> 6;
 }
-template <typename T, bool MLDS>
+// Coarsest solve from registers, at most 64 unknowns: lane l of wave w holds
+// m[k] = Minv[(w + k W) n + l] (W waves); each row summed pairwise over the 64
+// lanes with zeros past n, as in coarse_rows_seg with one-term segments.
+template <typename T, int MR>
+__device__ __forceinline__ void coarse_rows_reg(const V2<T> (&m)[MR], const V2<T> *f, V2<T> *e, int n, int w, int W)
+{
+    const int lane = threadIdx.x & 63;
+    const V2<T> fv = f[lane < n ? lane : n - 1];
+    T re[MR], im[MR];
+#pragma unroll
+    for (int k = 0; k < MR; ++k) {
+        const V2<T> pr = cmul<T>(m[k], fv);
+        const bool in = w + W * k < n && lane < n;
+        re[k] = in ? pr.x : (T)0;
+        im[k] = in ? pr.y : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < MR; ++k)
+        if (w + W * k < n) {   // uniform over the wave
+            re[k] = wave_sum(re[k]);
+            im[k] = wave_sum(im[k]);
+        }
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < MR; ++k)
+            if (w + W * k < n) e[w + W * k] = cmk<T>(re[k], im[k]);
+}
+
+template <typename T>
 __device__ __forceinline__ void coarse_rows_tail(const V2<T> *__restrict__ Minv, const V2<T> *f, V2<T> *e, int n, int row0, int rstep)
 {
     static_assert(HH_SPLIT_NC <= 128, "tail coarse solve handles seg 1 and 2");
-    if (coarse_seg(n) == 1) coarse_rows_seg<T, 1, MLDS>(Minv, f, e, n, row0, rstep);
-    else coarse_rows_seg<T, 2, MLDS>(Minv, f, e, n, row0, rstep);
+    if (coarse_seg(n) == 1) coarse_rows_seg<T, 1>(Minv, f, e, n, row0, rstep);
+    else coarse_rows_seg<T, 2>(Minv, f, e, n, row0, rstep);
 }
 
 template <typename T> __device__ inline V2<T> jweight(V2<T> D, T omega)
@@ -1867,13 +1895,15 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
     const C zero = cmk<T>(0, 0);
     const int tid = threadIdx.x, nth = TailCap<T>::WG;
     __shared__ TailTab tab;
-    __shared__ C minv_lds[TailMinv<T>::N];
     // FP32 with a coarsest grid of at most 64 unknowns: the coarsest inverse
-    // (32 KiB) is loaded with the image and goes to LDS just before the solve
-    const bool mlds = sizeof(T) == 4 && !up && !split && pd->Nc <= TailMinv<T>::N / 64 && pd->Nc <= 64;
-    constexpr int MT = (TailMinv<T>::N + TailCap<T>::WG - 1) / TailCap<T>::WG;
-    const int nm = pd->Nc * pd->Nc;
-    C mt[MT];   // coarsest inverse in flight (mlds)
+    // is loaded with the image straight into the registers of the lanes that
+    // use it (lane l of wave w: row w + k W, column l, W waves) and stays there
+    // until the coarse solve, so its latency overlaps the image, f and the
+    // down-legs
+    constexpr int MR = sizeof(T) == 4 ? 64 / (TailCap<T>::WG / 64) : 1;   // rows per lane
+    const bool mreg = sizeof(T) == 4 && !up && !split && pd->Nc <= 64;
+    const int nc = pd->Nc;
+    C mt[MR];
     const C *fg_top = Lv[t0].f;
     C *eg_top = Lv[t0].e;
     const C *__restrict__ Minv = (const C *)(sizeof(T) == 8 ? (const void *)pd->Minv64 : (const void *)pd->Minv32);
@@ -1886,13 +1916,12 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
         const uint32_t *seg = sizeof(T) == 8 ? pd->tseg64 : pd->tseg32;
         const int nseg = sizeof(T) == 8 ? pd->tnseg64 : pd->tnseg32;
         hh_uvec4 *l16 = (hh_uvec4 *)lds;
-        if (mlds) {
-            // stays in registers until the coarse solve; its latency overlaps
-            // the image, f and the down-legs
+        if (mreg) {
+            const int w = tid >> 6, lane = tid & 63;
 #pragma unroll
-            for (int q = 0; q < MT; ++q) {
-                const int i = tid + q * nth;
-                if (i < nm) mt[q] = ldg(Minv, i);
+            for (int k = 0; k < MR; ++k) {
+                const int row = w + (nth >> 6) * k;
+                mt[k] = (row < nc && lane < nc) ? ldg(Minv, (int64_t)row * nc + lane) : zero;
             }
         }
         // f of the top level leads the LDS block (offset 0)
@@ -2024,21 +2053,14 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
     }
     // coarsest solve
     if (!up) {
-        if (mlds) {
-#pragma unroll
-            for (int q = 0; q < MT; ++q) {
-                const int i = tid + q * nth;
-                if (i < nm) minv_lds[i] = mt[q];
-            }
-            __syncthreads();
-        }
         const TailPtr<T> Q = tail_ptr<DIM, T>(lds, tab, L - 1);
         if constexpr (sizeof(T) == 4) {
-            // at most 64 unknowns (one segment) from LDS, else 65..128 (two)
-            if (mlds) coarse_rows_seg<T, 1, true>(minv_lds, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
-            else coarse_rows_seg<T, 2, false>(Minv, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
+            // at most 64 unknowns (one segment) from registers, else 65..128
+            // (two segments) from memory
+            if (mreg) coarse_rows_reg<T, MR>(mt, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
+            else coarse_rows_seg<T, 2>(Minv, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
         } else {
-            coarse_rows_tail<T, false>(Minv, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
+            coarse_rows_tail<T>(Minv, Q.F, Q.E, Q.N, tid >> 6, nth >> 6);
         }
         __syncthreads();
     }
