@@ -21,6 +21,14 @@
 #define HH_WG 256                 // threads per workgroup (4 wave64)
 #define HH_PER_SLOT 1             // elements per thread slot in a reduction chunk (chunk = 256)
 #define HH_CHUNK (HH_WG * HH_PER_SLOT)
+// Krylov vector passes: a workgroup of HH_GROUP chunks (one unknown per
+// thread, chunk s = waves 4s..4s+3) writes one partial per value, the
+// group's node of the pairwise tree over chunk partials.  One chunk per
+// workgroup measures fastest (four: same 2D solve time, 3D 1-3% slower; the
+// finaliser's cost is its load latency, not the partial count).
+#define HH_GROUP 1
+#define HH_VWG (HH_WG * HH_GROUP)
+#define HH_SPAN (HH_CHUNK * HH_GROUP)
 #define HH_NPART 40               // reals per chunk partial record (IDR(8) start-up needs 4s+1)
 #define HH_MAX_COARSE 1024
 #define HH_MAX_S 8
@@ -204,7 +212,7 @@ struct Ctrl {
 };
 
 struct ProbDev {
-    int dim, nlev, Nc, nchunk;
+    int dim, nlev, Nc, ngroup;       // ngroup: chunk groups (partials per value)
     int tail64, tail32;              // first level of the one-workgroup tail kernel, per precision
     int csplit;                      // 1: the coarsest solve runs in k_coarse (many workgroups)
     int n[3];
@@ -226,7 +234,7 @@ struct ProbDev {
     double2 *dR, *dX;                // IDR: s columns of N each
     int nidr;                        // IDR: s
     const double2 *P;                // IDR shadow space, N x s column-major
-    double *part;                    // chunk partials, value-major: part[v * nchunk + c], v < HH_NPART
+    double *part;                    // group partials, value-major: part[v * ngroup + g], v < HH_NPART
     SolveState *st;
     Ctrl *ctrl;                      // this problem's slot in the plan's control array
     double *hist;                    // device history (optional)

@@ -136,13 +136,13 @@ __device__ void idr_finalize(const ProbDev *pd, SolveState *st, int kind, const 
 }
 
 // P1: v = r (start-up) or q = -sum_j dR_j c_j, v = r + q
-__global__ __launch_bounds__(HH_WG) void k_idr_v(Ctx cx)
+__global__ __launch_bounds__(HH_VWG) void k_idr_v(Ctx cx)
 {
     const Tile tl = tile_of(cx);
     const Ctrl ct = ctrl_of(cx, tl.prob);
     if (ct.phase != PH_RUN) return;
     const ProbDev *pd = cx.P + tl.prob;
-    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_CHUNK;
+    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_SPAN;
     const double2 *__restrict__ r = (const double2 *)pd->vec[VS_R];
     double2 *__restrict__ v = (double2 *)pd->vec[VS_V];
     double2 *__restrict__ q = (double2 *)pd->vec[VS_Q];
@@ -181,14 +181,14 @@ __global__ __launch_bounds__(HH_WG) void k_idr_v(Ctx cx)
 // P3: t = H w with partials (t, v), (t, t)   (start-up, k = 0)
 //     dX_old = om w - sum_j dX_j c_j          (k >= 1)
 template <int DIM, typename SW>
-__global__ __launch_bounds__(HH_WG) void k_idr_t(Ctx cx)
+__global__ __launch_bounds__(HH_VWG) void k_idr_t(Ctx cx)
 {
     const Tile tl = tile_of(cx);
     const Ctrl ct = ctrl_of(cx, tl.prob);
     if (ct.phase != PH_RUN) return;
     const ProbDev *pd = cx.P + tl.prob;
     const SW *__restrict__ w = (const SW *)pd->vec[VS_W];
-    const int64_t base = (int64_t)tl.idx * HH_CHUNK;
+    const int64_t base = (int64_t)tl.idx * HH_SPAN;
     if (ct.mode == 2) {
         const int64_t N = pd->N;
         const int ns = pd->nidr;
@@ -236,13 +236,13 @@ __global__ __launch_bounds__(HH_WG) void k_idr_t(Ctx cx)
             acc[2] = acc[2] + (y[e].x * y[e].x + y[e].y * y[e].y);
         }
     }
-    chunk_finish<3>(pd, tl.idx, acc);
+    group_finish<3>(pd, tl.idx, acc);
 }
 
 // P4: the dR/dX column of this step, r += dR, x += dX; partials ||r||^2,
 // P^H dR (and P^H r during start-up)
 template <int DIM, typename SW>
-__global__ __launch_bounds__(HH_WG) void k_idr_up(Ctx cx)
+__global__ __launch_bounds__(HH_VWG) void k_idr_up(Ctx cx)
 {
     constexpr int NV = 1 + 4 * HH_MAX_S;
     const Tile tl = tile_of(cx);
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(HH_WG) void k_idr_up(Ctx cx)
     if (ct.phase != PH_RUN) return;
     const ProbDev *pd = cx.P + tl.prob;
     const HView h = hview(pd);
-    const int64_t N = h.N, base = (int64_t)tl.idx * HH_CHUNK;
+    const int64_t N = h.N, base = (int64_t)tl.idx * HH_SPAN;
     const int ns = pd->nidr, mode = ct.mode;
     const double2 om = ct.om_idr;
     const SW *__restrict__ w = (const SW *)pd->vec[VS_W];
@@ -313,12 +313,12 @@ __global__ __launch_bounds__(HH_WG) void k_idr_up(Ctx cx)
         }
     }
     if (mode == 0) {
-        chunk_finish<NV>(pd, tl.idx, acc);
+        group_finish<NV>(pd, tl.idx, acc);
     } else {
         double a2[1 + 2 * HH_MAX_S];
 #pragma unroll
         for (int k = 0; k < 1 + 2 * HH_MAX_S; ++k) a2[k] = acc[k];
-        chunk_finish<1 + 2 * HH_MAX_S>(pd, tl.idx, a2);
+        group_finish<1 + 2 * HH_MAX_S>(pd, tl.idx, a2);
     }
 }
 

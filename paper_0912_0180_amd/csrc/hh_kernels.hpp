@@ -586,7 +586,7 @@ __device__ void finalize(const ProbDev *pd, int kind)
                  : (kind == FIN_BNORM || kind == FIN_TRUE) ? 1 : (kind == FIN_ALPHA ? 2 : (kind == FIN_OMEGA ? 4 : 3));
     const int first = (kind == FIN_BNORM || kind == FIN_TRUE) ? 2 : 0;
     __shared__ double res[4 * HH_MAX_S + 4];
-    reduce_partials(pd->part, pd->nchunk, first, nv, res);
+    reduce_partials(pd->part, pd->ngroup, first, nv, res);
     const double *s = res;
     if (threadIdx.x != 0) return;
     if (kind >= FIN_IDR_OMEGA) {
@@ -695,12 +695,41 @@ __device__ void finalize(const ProbDev *pd, int kind)
     }
 }
 
-// Writes this chunk's partial sums as values first .. first + NV - 1; the
-// pass's finalisation runs in k_fin.
+// Writes the group partials of a Krylov workgroup (HH_GROUP chunks, chunk s
+// held by waves 4s..4s+3, one unknown per thread) as values first .. first +
+// NV - 1; the pass's finalisation runs in k_fin.  Each chunk is summed by its
+// pairwise tree (wave sums, then (w0 + w1) + (w2 + w3)); the chunk sums are
+// then combined pairwise over the first min(HH_GROUP, np) of them, np the
+// problem's chunk count rounded up to a power of two.  That is this group's
+// node of the pairwise tree over the zero-padded chunk partials, and k_fin
+// sums the group partials by the rest of the same tree.
 template <int NV>
-__device__ inline void chunk_finish(const ProbDev *pd, int chunk, double (&acc)[NV], int first = 0)
+__device__ inline void group_finish(const ProbDev *pd, int grp, double (&acc)[NV], int first = 0)
 {
-    block_reduce<NV>(acc, pd->part + (int64_t)first * pd->nchunk + chunk, pd->nchunk);
+    static_assert(HH_PER_SLOT == 1 && HH_CHUNK == 256, "a chunk is four waves of one unknown per thread");
+    __shared__ double red[HH_VWG / 64][NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = wave_sum(acc[q]);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[w][q] = acc[q];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int q = threadIdx.x;
+        const int64_t nch = (pd->N + HH_CHUNK - 1) / HH_CHUNK;
+        int width = 1;
+        while (width < HH_GROUP && width < nch) width <<= 1;
+        double c[HH_GROUP];
+#pragma unroll
+        for (int s = 0; s < HH_GROUP; ++s) c[s] = (red[4 * s][q] + red[4 * s + 1][q]) + (red[4 * s + 2][q] + red[4 * s + 3][q]);
+#pragma unroll
+        for (int h = 1; h < HH_GROUP; h <<= 1)
+            if (h < width)
+#pragma unroll
+                for (int i = 0; i + h < HH_GROUP; i += 2 * h) c[i] = c[i] + c[i + h];
+        pd->part[(int64_t)(first + q) * pd->ngroup + grp] = c[0];
+    }
 }
 
 // One workgroup per problem: sums the chunk partials of the pass just run and
@@ -1140,6 +1169,445 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, in
         } else {
             stg(eout, p, u);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Merged 2D legs of K consecutive coarse levels lev0 .. lev0 + K - 1 (ending
+// at the tail's first level lev0 + K), one launch per leg instead of K.  On
+// these small levels a launch costs its latency, not its work.
+//
+// Down: the smoothing from zero is pointwise, so a coarse point's restricted
+// residual depends only on the finer level within two points of its
+// footprint.  A workgroup owning a C x C tile of level lev0 + K computes every
+// level from lev0 on the region its tile depends on (width W_K = C,
+// W_k = 2 W_{k+1} + 4, origin O_k = 2 O_{k+1} - 2), all in LDS, with the
+// arithmetic of k_vdown point for point.  It writes f of each coarser level
+// on its own part of the region (the up-legs read them).
+//
+// Up: a workgroup owning a UT x UT tile of level lev0 computes, from level
+// lev0 + K - 1 up, u2 = g f + P e and the post-smoothing on the region its
+// tile depends on (each coarser region is the prolongation footprint of the
+// finer region plus its halo of one), with the arithmetic of k_vup point for
+// point; only e of level lev0 is written.
+// ---------------------------------------------------------------------------
+template <typename T, int K> struct LvChain {
+    LevelDev<T> L[K + 1];
+};
+// (no recursion: the sizes fold to constants once the level loops unroll)
+template <int K, int C> struct MergeDown {
+    // W_K = C, W_k = 2 W_{k+1} + 4, for 0 <= k <= K
+    static constexpr int width(int k) { return (C + 4) * (1 << (K - k)) - 4; }
+    static constexpr int area(int k0, int k1)
+    {
+        int a = 0;
+        for (int k = k0; k < k1; ++k) a += width(k) * width(k);
+        return a;
+    }
+};
+template <int K, int UT> struct MergeUp {
+    // bound on the width of level k's e region; the fine range adds a halo of one
+    static constexpr int width(int k)
+    {
+        int w = UT;
+        for (int i = 0; i < k; ++i) w = w / 2 + 4;
+        return w;
+    }
+    static constexpr int rw(int k) { return width(k) + 2; }
+    static constexpr int rarea(int k0, int k1)
+    {
+        int a = 0;
+        for (int k = k0; k < k1; ++k) a += rw(k) * rw(k);
+        return a;
+    }
+    static constexpr int earea(int k0, int k1)
+    {
+        int a = 0;
+        for (int k = k0; k < k1; ++k) a += width(k) * width(k);
+        return a;
+    }
+    static constexpr int rpos(int k0, int k1)
+    {
+        int a = 0;
+        for (int k = k0; k < k1; ++k) a += 2 * rw(k);
+        return a;
+    }
+};
+
+// origin on level k of the down region whose level-K tile starts at c0:
+// O_K = c0, O_k = 2 O_{k+1} - 2
+template <int K> __device__ __forceinline__ int mdown_origin(int c0, int k)
+{
+    return (c0 << (K - k)) - 2 * ((1 << (K - k)) - 1);
+}
+
+template <typename T, int K, int C, int NT>
+__global__ __launch_bounds__(NT) void k_vdown_m(Ctx cx, LvChain<T, K> lc)
+{
+    using Cx = V2<T>;
+    using MD = MergeDown<K, C>;
+    constexpr int W0 = MD::width(0), N0 = W0 * W0, NL = (N0 + NT - 1) / NT;
+    constexpr int W1 = MD::width(1), NQ = (W1 * W1 + NT - 1) / NT;
+    constexpr int NF = MD::area(1, K + 1);      // f of levels 1 .. K
+    constexpr int NP = MD::area(1, K) + 1;      // phi of levels 1 .. K-1
+    static_assert(K >= 2 && 2 * W0 <= NT, "one coefficient position per thread and level");
+    __shared__ Cx U[N0];
+    __shared__ Cx F0[N0];
+    __shared__ T PH0[N0];
+    __shared__ Cx FK[NF];
+    __shared__ T PK[NP];
+    __shared__ Cx CA[K][2 * W0], CC[K][2 * W0], CD[K][2 * W0];   // [k][axis * W_k + i]
+
+    const Cx zero = cmk<T>(0, 0);
+    const int tid = threadIdx.x;
+    const int run = phase_of(cx, 0);
+    const T omega = (T)(cx.L ? cx.omega : cx.P->omega);
+    const int tx = (lc.L[K].n[0] + C - 1) / C;
+    const int b = tile_of(cx).idx;
+    const int cx0 = (b % tx) * C, cy0 = (b / tx) * C;
+    // all global loads first: f and phi of level lev0 on its region, phi of
+    // levels 1 .. K-1 on theirs, the coefficients of levels 0 .. K-1
+    Cx fr[NL];
+    T pr[NL];
+    {
+        const int nx = lc.L[0].n[0], ny = lc.L[0].n[1];
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int l = tid + q * NT;
+            const int gx = mdown_origin<K>(cx0, 0) + l % W0, gy = mdown_origin<K>(cy0, 0) + l / W0;
+            fr[q] = zero;
+            pr[q] = 0;
+            if (l < N0 && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                const int64_t p = gx + (int64_t)nx * gy;
+                fr[q] = ldg(lc.L[0].f, p);
+                pr[q] = ldg(lc.L[0].phi, p);
+            }
+        }
+    }
+    T pk[K][NQ];
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+        const int Wk = MD::width(k), nx = lc.L[k].n[0], ny = lc.L[k].n[1];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int l = tid + q * NT;
+            const int gx = mdown_origin<K>(cx0, k) + l % Wk, gy = mdown_origin<K>(cy0, k) + l / Wk;
+            pk[k][q] = 0;
+            if (l < Wk * Wk && gx >= 0 && gx < nx && gy >= 0 && gy < ny) pk[k][q] = ldg(lc.L[k].phi, gx + (int64_t)nx * gy);
+        }
+    }
+    Cx qa[K], qc[K], qd[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int Wk = MD::width(k);
+        const int ax = tid >= Wk, i = tid - ax * Wk;
+        const int g = (ax ? mdown_origin<K>(cy0, k) : mdown_origin<K>(cx0, k)) + i, n = ax ? lc.L[k].n[1] : lc.L[k].n[0];
+        qa[k] = qc[k] = qd[k] = zero;
+        if (tid < 2 * Wk && g >= 0 && g < n) {
+            qa[k] = ldg(ax ? lc.L[k].a[1] : lc.L[k].a[0], g);
+            qc[k] = ldg(ax ? lc.L[k].c[1] : lc.L[k].c[0], g);
+            qd[k] = ldg(ax ? lc.L[k].d[1] : lc.L[k].d[0], g);
+        }
+    }
+    {
+        int off = 0;
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+            const int Wk = MD::width(k);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int l = tid + q * NT;
+                if (l < Wk * Wk) PK[off + l] = pk[k][q];
+            }
+            off += Wk * Wk;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (tid < 2 * MD::width(k)) {
+            CA[k][tid] = qa[k];
+            CC[k][tid] = qc[k];
+            CD[k][tid] = qd[k];
+        }
+    if (run != PH_RUN) return;   // uniform over the workgroup
+    __syncthreads();
+    // level lev0: u1 = g f on the region
+    {
+        const int nx = lc.L[0].n[0], ny = lc.L[0].n[1];
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int l = tid + q * NT;
+            if (l >= N0) break;
+            const int lx = l % W0, ly = l / W0;
+            const int gx = mdown_origin<K>(cx0, 0) + lx, gy = mdown_origin<K>(cy0, 0) + ly;
+            Cx u1 = zero;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                Cx d = cadd<T>(CD[0][lx], CD[0][W0 + ly]);
+                Cx D = cmk<T>(d.x - pr[q], d.y);
+                T qq = jscale<T>(omega, D);
+                Cx gw = cmk<T>(D.x * qq, -(D.y * qq));
+                u1 = cmul<T>(gw, fr[q]);
+            }
+            U[l] = u1;
+            F0[l] = fr[q];
+            PH0[l] = pr[q];
+        }
+    }
+    __syncthreads();
+    const T w0 = (T)0.125, w1 = (T)0.375;
+    int foff = 0, poff = 0;   // level k's f and phi in FK / PK (k >= 1)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int Wk = MD::width(k), Wn = MD::width(k + 1);
+        const int nx = lc.L[k].n[0], ny = lc.L[k].n[1];
+        Cx *Fk = k == 0 ? F0 : FK + foff;
+        const T *Pk = k == 0 ? PH0 : PK + poff;
+        Cx *Fn = FK + (k == 0 ? 0 : foff + Wk * Wk);
+        if (k > 0) {
+            // u1 = g f on the region
+            for (int l = tid; l < Wk * Wk; l += NT) {
+                const int lx = l % Wk, ly = l / Wk;
+                const int gx = mdown_origin<K>(cx0, k) + lx, gy = mdown_origin<K>(cy0, k) + ly;
+                Cx u1 = zero;
+                if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                    Cx d = cadd<T>(CD[k][lx], CD[k][Wk + ly]);
+                    Cx D = cmk<T>(d.x - Pk[l], d.y);
+                    T qq = jscale<T>(omega, D);
+                    Cx gw = cmk<T>(D.x * qq, -(D.y * qq));
+                    u1 = cmul<T>(gw, Fk[l]);
+                }
+                U[l] = u1;
+            }
+            __syncthreads();
+        }
+        // r = f - M u1 on the region minus its outer ring, in place
+        for (int r = tid; r < (Wk - 2) * (Wk - 2); r += NT) {
+            const int lx = 1 + r % (Wk - 2), ly = 1 + r / (Wk - 2);
+            const int gx = mdown_origin<K>(cx0, k) + lx, gy = mdown_origin<K>(cy0, k) + ly;
+            const int l = lx + Wk * ly;
+            Cx res = zero;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                Cx d = cadd<T>(CD[k][lx], CD[k][Wk + ly]);
+                Cx D = cmk<T>(d.x - Pk[l], d.y);
+                Cx mu = cmul<T>(D, U[l]);
+                mu = csub<T>(mu, cmul<T>(CA[k][lx], U[l - 1]));
+                mu = csub<T>(mu, cmul<T>(CC[k][lx], U[l + 1]));
+                mu = csub<T>(mu, cmul<T>(CA[k][Wk + ly], U[l - Wk]));
+                mu = csub<T>(mu, cmul<T>(CC[k][Wk + ly], U[l + Wk]));
+                res = csub<T>(Fk[l], mu);
+            }
+            Fk[l] = res;
+        }
+        __syncthreads();
+        // full weighting onto level k + 1's region (zero outside the grid);
+        // the workgroup's own part goes to memory
+        {
+            const int ncx = lc.L[k + 1].n[0], ncy = lc.L[k + 1].n[1];
+            const int own = 2 * ((1 << (K - k - 1)) - 1), ownw = C << (K - k - 1);
+            Cx *__restrict__ fout = lc.L[k + 1].f;
+            for (int cl = tid; cl < Wn * Wn; cl += NT) {
+                const int ix = cl % Wn, iy = cl / Wn;
+                const int I = mdown_origin<K>(cx0, k + 1) + ix, J = mdown_origin<K>(cy0, k + 1) + iy;
+                Cx acc_y = zero;
+                if (I >= 0 && I < ncx && J >= 0 && J < ncy) {
+                    const int bxl = 2 * ix + 1, byl = 2 * iy + 1;
+#pragma unroll
+                    for (int bb = 0; bb < 4; ++bb) {
+                        const T wy = (bb == 0 || bb == 3) ? w0 : w1;
+                        const Cx *row = &Fk[bxl + Wk * (byl + bb)];
+                        Cx sx = crs<T>(w0, row[0]);
+                        sx = cadd<T>(sx, crs<T>(w1, row[1]));
+                        sx = cadd<T>(sx, crs<T>(w1, row[2]));
+                        sx = cadd<T>(sx, crs<T>(w0, row[3]));
+                        acc_y = bb == 0 ? crs<T>(wy, sx) : cadd<T>(acc_y, crs<T>(wy, sx));
+                    }
+                    if (ix >= own && ix < own + ownw && iy >= own && iy < own + ownw)
+                        stg(fout, I + (int64_t)ncx * J, acc_y);
+                }
+                Fn[cl] = acc_y;
+            }
+        }
+        __syncthreads();
+        if (k > 0) {
+            foff += Wk * Wk;
+            poff += Wk * Wk;
+        }
+    }
+}
+
+template <typename T, int K, int UT, int NT>
+__global__ __launch_bounds__(NT) void k_vup_m(Ctx cx, LvChain<T, K> lc)
+{
+    using Cx = V2<T>;
+    using MU = MergeUp<K, UT>;
+    constexpr int RW0 = MU::rw(0), NR = MU::rarea(0, K), NE = MU::earea(1, K + 1), NPOS = MU::rpos(0, K);
+    constexpr int RQ = (RW0 * RW0 + NT - 1) / NT;   // loads per thread and level (level 0 is the largest)
+    constexpr int WK = MU::width(K), EQ = (WK * WK + NT - 1) / NT;
+    static_assert(K >= 2 && 2 * RW0 <= NT, "one coefficient position per thread and level");
+    __shared__ Cx U[RW0 * RW0];
+    __shared__ Cx F[NR];
+    __shared__ T PH[NR];
+    __shared__ Cx E[NE];                  // e of levels 1 .. K
+    __shared__ Cx CA[NPOS], CC[NPOS], CD[NPOS];
+
+    const Cx zero = cmk<T>(0, 0);
+    const int tid = threadIdx.x;
+    const int run = phase_of(cx, 0);
+    const T omega = (T)(cx.L ? cx.omega : cx.P->omega);
+    const int tx = (lc.L[0].n[0] + UT - 1) / UT;
+    const int b = tile_of(cx).idx;
+    // e regions: level 0 is the tile; level k + 1's covers the prolongation
+    // footprint of level k's region plus its halo of one
+    int ox[K + 1], oy[K + 1], wx[K + 1], wy[K + 1];
+    ox[0] = (b % tx) * UT;
+    oy[0] = (b / tx) * UT;
+    wx[0] = wy[0] = UT;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int lx = ox[k] - 1, hx = ox[k] + wx[k], ly = oy[k] - 1, hy = oy[k] + wy[k];
+        ox[k + 1] = (lx >> 1) - ((lx & 1) ? 0 : 1);
+        oy[k + 1] = (ly >> 1) - ((ly & 1) ? 0 : 1);
+        wx[k + 1] = (hx >> 1) + ((hx & 1) ? 1 : 0) - ox[k + 1] + 1;
+        wy[k + 1] = (hy >> 1) + ((hy & 1) ? 1 : 0) - oy[k + 1] + 1;
+    }
+    // all global loads first: f and phi of levels 0 .. K-1 on their regions
+    // with the halo, e of level K, the coefficients
+    Cx fr[K][RQ];
+    T pr[K][RQ];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int R = MU::rw(k), nx = lc.L[k].n[0], ny = lc.L[k].n[1];
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) {
+            const int l = tid + q * NT;
+            const int lx = l % R, ly = l / R;
+            const int gx = ox[k] - 1 + lx, gy = oy[k] - 1 + ly;
+            fr[k][q] = zero;
+            pr[k][q] = 0;
+            if (l < R * R && lx < wx[k] + 2 && ly < wy[k] + 2 && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                const int64_t p = gx + (int64_t)nx * gy;
+                fr[k][q] = ldg(lc.L[k].f, p);
+                pr[k][q] = ldg(lc.L[k].phi, p);
+            }
+        }
+    }
+    Cx er[EQ];
+    {
+        const int nx = lc.L[K].n[0], ny = lc.L[K].n[1];
+#pragma unroll
+        for (int q = 0; q < EQ; ++q) {
+            const int l = tid + q * NT;
+            const int lx = l % WK, ly = l / WK;
+            const int gx = ox[K] + lx, gy = oy[K] + ly;
+            er[q] = zero;
+            if (l < WK * WK && lx < wx[K] && ly < wy[K] && gx >= 0 && gx < nx && gy >= 0 && gy < ny)
+                er[q] = ldg(lc.L[K].e, gx + (int64_t)nx * gy);
+        }
+    }
+    Cx qa[K], qc[K], qd[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int R = MU::rw(k);
+        const int ax = tid >= R, i = tid - ax * R;
+        const int g = (ax ? oy[k] : ox[k]) - 1 + i, n = ax ? lc.L[k].n[1] : lc.L[k].n[0];
+        qa[k] = qc[k] = qd[k] = zero;
+        if (tid < 2 * R && g >= 0 && g < n) {
+            qa[k] = ldg(ax ? lc.L[k].a[1] : lc.L[k].a[0], g);
+            qc[k] = ldg(ax ? lc.L[k].c[1] : lc.L[k].c[0], g);
+            qd[k] = ldg(ax ? lc.L[k].d[1] : lc.L[k].d[0], g);
+        }
+    }
+    {
+        int roff = 0, coff = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int R = MU::rw(k);
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) {
+                const int l = tid + q * NT;
+                if (l < R * R) {
+                    F[roff + l] = fr[k][q];
+                    PH[roff + l] = pr[k][q];
+                }
+            }
+            if (tid < 2 * R) {
+                CA[coff + tid] = qa[k];
+                CC[coff + tid] = qc[k];
+                CD[coff + tid] = qd[k];
+            }
+            roff += R * R;
+            coff += 2 * R;
+        }
+        Cx *EK = E + MU::earea(1, K);
+#pragma unroll
+        for (int q = 0; q < EQ; ++q) {
+            const int l = tid + q * NT;
+            if (l < WK * WK) EK[l] = er[q];
+        }
+    }
+    if (run != PH_RUN) return;   // uniform over the workgroup
+    __syncthreads();
+    const T p3 = (T)0.75, p1 = (T)0.25;
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k) {
+        const int R = MU::rw(k), WE = MU::width(k + 1), WO = MU::width(k);
+        const int roff = MU::rarea(0, k), coff = MU::rpos(0, k);
+        const Cx *Fk = F + roff;
+        const T *Pk = PH + roff;
+        const Cx *Ak = CA + coff, *Ck = CC + coff, *Dk = CD + coff;
+        const Cx *Ec = E + MU::earea(1, k + 1);   // e of level k + 1
+        Cx *Eo = E + (k > 0 ? MU::earea(1, k) : 0);
+        const int nx = lc.L[k].n[0], ny = lc.L[k].n[1];
+        const int x0 = ox[k] - 1, y0 = oy[k] - 1;
+        // u2 = g f + P e on the region with its halo
+        for (int l = tid; l < R * R; l += NT) {
+            const int lx = l % R, ly = l / R;
+            const int gx = x0 + lx, gy = y0 + ly;
+            Cx u2 = zero;
+            if (lx < wx[k] + 2 && ly < wy[k] + 2 && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                Cx d = cadd<T>(Dk[lx], Dk[R + ly]);
+                Cx D = cmk<T>(d.x - Pk[l], d.y);
+                T qq = jscale<T>(omega, D);
+                Cx gw = cmk<T>(D.x * qq, -(D.y * qq));
+                Cx u1 = cmul<T>(gw, Fk[l]);
+                const int Ix = (gx >> 1) - ox[k + 1], Iox = ((gx & 1) ? (gx >> 1) + 1 : (gx >> 1) - 1) - ox[k + 1];
+                const int Iy = (gy >> 1) - oy[k + 1], Ioy = ((gy & 1) ? (gy >> 1) + 1 : (gy >> 1) - 1) - oy[k + 1];
+                Cx a0 = cadd<T>(crs<T>(p3, Ec[Ix + WE * Iy]), crs<T>(p1, Ec[Iox + WE * Iy]));
+                Cx a1 = cadd<T>(crs<T>(p3, Ec[Ix + WE * Ioy]), crs<T>(p1, Ec[Iox + WE * Ioy]));
+                Cx pe = cadd<T>(crs<T>(p3, a0), crs<T>(p1, a1));
+                u2 = cadd<T>(u1, pe);
+            }
+            U[l] = u2;
+        }
+        __syncthreads();
+        // post-smoothing on the region; level lev0's goes to memory
+        for (int r = tid; r < WO * WO; r += NT) {
+            const int ix = r % WO, iy = r / WO;
+            if (ix >= wx[k] || iy >= wy[k]) continue;
+            const int lx = ix + 1, ly = iy + 1;
+            const int gx = x0 + lx, gy = y0 + ly;
+            const int l = lx + R * ly;
+            Cx u = zero;
+            const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            if (in) {
+                Cx d = cadd<T>(Dk[lx], Dk[R + ly]);
+                Cx D = cmk<T>(d.x - Pk[l], d.y);
+                T qq = jscale<T>(omega, D);
+                Cx gw = cmk<T>(D.x * qq, -(D.y * qq));
+                Cx mu = cmul<T>(D, U[l]);
+                mu = csub<T>(mu, cmul<T>(Ak[lx], U[l - 1]));
+                mu = csub<T>(mu, cmul<T>(Ck[lx], U[l + 1]));
+                mu = csub<T>(mu, cmul<T>(Ak[R + ly], U[l - R]));
+                mu = csub<T>(mu, cmul<T>(Ck[R + ly], U[l + R]));
+                u = cadd<T>(U[l], cmul<T>(gw, csub<T>(Fk[l], mu)));
+            }
+            if (k == 0) {
+                if (in) stg(lc.L[0].e, gx + (int64_t)nx * gy, u);
+            } else {
+                Eo[ix + WO * iy] = u;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -2154,10 +2622,10 @@ __global__ __launch_bounds__(HH_WG) void k_coarse(Ctx cx)
 // Bi-CGSTAB passes (right preconditioned; s is kept in r).  Each pass
 // reduces its dot products per chunk and finalises in its last workgroup.
 // ---------------------------------------------------------------------------
-#define CHUNK_P(s_) (base + threadIdx.x + (int64_t)HH_WG * (s_))
+#define CHUNK_P(s_) (base + threadIdx.x + (int64_t)HH_VWG * (s_))
 
 // p = r + beta (p - omega v)
-__global__ __launch_bounds__(HH_WG) void k_bicg_p(Ctx cx)
+__global__ __launch_bounds__(HH_VWG) void k_bicg_p(Ctx cx)
 {
     const Tile tl = tile_of(cx);
     const Ctrl ct = ctrl_of(cx, tl.prob);
@@ -2167,7 +2635,7 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_p(Ctx cx)
     double2 *__restrict__ pv = (double2 *)pd->vec[VS_P];
     const double2 *__restrict__ r = (const double2 *)pd->vec[VS_R];
     const double2 *__restrict__ v = (const double2 *)pd->vec[VS_V];
-    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_CHUNK;
+    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_SPAN;
     double2 pr[HH_PER_SLOT], rr[HH_PER_SLOT], vr[HH_PER_SLOT];
 #pragma unroll
     for (int s = 0; s < HH_PER_SLOT; ++s)
@@ -2184,7 +2652,7 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_p(Ctx cx)
 
 // v = H phat ; partial (rhat, v) ; finalise alpha
 template <int DIM, typename SP>
-__global__ __launch_bounds__(HH_WG) void k_bicg_v(Ctx cx)
+__global__ __launch_bounds__(HH_VWG) void k_bicg_v(Ctx cx)
 {
     const Tile tl = tile_of(cx);
     if (phase_of(cx, tl.prob) != PH_RUN) return;
@@ -2193,7 +2661,7 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_v(Ctx cx)
     const SP *__restrict__ ph = (const SP *)pd->vec[VS_PH];
     double2 *__restrict__ v = (double2 *)pd->vec[VS_V];
     const double2 *__restrict__ rh = (const double2 *)pd->vec[VS_RH];
-    const int64_t base = (int64_t)tl.idx * HH_CHUNK;
+    const int64_t base = (int64_t)tl.idx * HH_SPAN;
     double2 y[HH_PER_SLOT], a[HH_PER_SLOT];
 #pragma unroll
     for (int s = 0; s < HH_PER_SLOT; ++s) {
@@ -2215,12 +2683,12 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_v(Ctx cx)
             acc[1] = acc[1] + (a[s].x * y[s].y - a[s].y * y[s].x);
         }
     }
-    chunk_finish<2>(pd, tl.idx, acc);
+    group_finish<2>(pd, tl.idx, acc);
 }
 
 // s = r - alpha v (in r) ; partial ||s||^2 (value 3, checked by the omega
 // finaliser before it uses t)
-__global__ __launch_bounds__(HH_WG) void k_bicg_s(Ctx cx)
+__global__ __launch_bounds__(HH_VWG) void k_bicg_s(Ctx cx)
 {
     const Tile tl = tile_of(cx);
     const Ctrl ct = ctrl_of(cx, tl.prob);
@@ -2229,7 +2697,7 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_s(Ctx cx)
     const double2 alpha = ct.alpha;
     double2 *__restrict__ r = (double2 *)pd->vec[VS_R];
     const double2 *__restrict__ v = (const double2 *)pd->vec[VS_V];
-    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_CHUNK;
+    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_SPAN;
     double2 rr[HH_PER_SLOT], vr[HH_PER_SLOT];
 #pragma unroll
     for (int s = 0; s < HH_PER_SLOT; ++s)
@@ -2245,12 +2713,12 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_s(Ctx cx)
             stg(r, CHUNK_P(s), sv);
             acc[0] = acc[0] + (sv.x * sv.x + sv.y * sv.y);
         }
-    chunk_finish<1>(pd, tl.idx, acc, 3);   // ||s||^2, finalised with omega
+    group_finish<1>(pd, tl.idx, acc, 3);   // ||s||^2, finalised with omega
 }
 
 // t = H shat ; partials (t, s), (t, t) ; finalise omega
 template <int DIM, typename SP>
-__global__ __launch_bounds__(HH_WG) void k_bicg_t(Ctx cx)
+__global__ __launch_bounds__(HH_VWG) void k_bicg_t(Ctx cx)
 {
     const Tile tl = tile_of(cx);
     if (phase_of(cx, tl.prob) != PH_RUN) return;
@@ -2259,7 +2727,7 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_t(Ctx cx)
     const SP *__restrict__ sh = (const SP *)pd->vec[VS_SH];
     double2 *__restrict__ t = (double2 *)pd->vec[VS_T];
     const double2 *__restrict__ sv = (const double2 *)pd->vec[VS_R];
-    const int64_t base = (int64_t)tl.idx * HH_CHUNK;
+    const int64_t base = (int64_t)tl.idx * HH_SPAN;
     double2 y[HH_PER_SLOT], b[HH_PER_SLOT];
 #pragma unroll
     for (int s = 0; s < HH_PER_SLOT; ++s) {
@@ -2282,13 +2750,13 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_t(Ctx cx)
             acc[2] = acc[2] + (y[s].x * y[s].x + y[s].y * y[s].y);
         }
     }
-    chunk_finish<3>(pd, tl.idx, acc);
+    group_finish<3>(pd, tl.idx, acc);
 }
 
 // x = x + alpha phat + omega shat ; r = s - omega t ; partials (rhat, r),
 // ||r||^2 ; finalise rho/beta (half-step exit: x = x + alpha phat only)
 template <typename SP>
-__global__ __launch_bounds__(HH_WG) void k_bicg_xr(Ctx cx)
+__global__ __launch_bounds__(HH_VWG) void k_bicg_xr(Ctx cx)
 {
     const Tile tl = tile_of(cx);
     const Ctrl ct = ctrl_of(cx, tl.prob);
@@ -2302,7 +2770,7 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_xr(Ctx cx)
     double2 *__restrict__ r = (double2 *)pd->vec[VS_R];
     const double2 *__restrict__ t = (const double2 *)pd->vec[VS_T];
     const double2 *__restrict__ rh = (const double2 *)pd->vec[VS_RH];
-    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_CHUNK;
+    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_SPAN;
     double acc[3] = {0.0, 0.0, 0.0};
     if (phase == PH_HALF) {
         double2 xr[HH_PER_SLOT], pr[HH_PER_SLOT];
@@ -2340,7 +2808,7 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_xr(Ctx cx)
                 acc[2] = acc[2] + (rn.x * rn.x + rn.y * rn.y);
             }
     }
-    chunk_finish<3>(pd, tl.idx, acc);
+    group_finish<3>(pd, tl.idx, acc);
 }
 
 // out = b - H x.  mode 0 (Bi-CGSTAB start): out = r, also rhat = r, p = v = 0,
@@ -2348,7 +2816,7 @@ __global__ __launch_bounds__(HH_WG) void k_bicg_xr(Ctx cx)
 // out = tmp, partial ||.||^2 in slot 2, finalise TRUE.  mode 2 (IDR start):
 // out = r, partial ||r||^2, finalise IDR_INIT.
 template <int DIM>
-__global__ __launch_bounds__(HH_WG) void k_resid(Ctx cx, int mode)
+__global__ __launch_bounds__(HH_VWG) void k_resid(Ctx cx, int mode)
 {
     const Tile tl = tile_of(cx);
     const ProbDev *pd = cx.P + tl.prob;
@@ -2359,7 +2827,7 @@ __global__ __launch_bounds__(HH_WG) void k_resid(Ctx cx, int mode)
     double2 *__restrict__ rh = (double2 *)pd->vec[VS_RH];
     double2 *__restrict__ pv = (double2 *)pd->vec[VS_P];
     double2 *__restrict__ v = (double2 *)pd->vec[VS_V];
-    const int64_t base = (int64_t)tl.idx * HH_CHUNK;
+    const int64_t base = (int64_t)tl.idx * HH_SPAN;
     double2 rr[HH_PER_SLOT];
 #pragma unroll
     for (int s = 0; s < HH_PER_SLOT; ++s) {
@@ -2388,16 +2856,16 @@ __global__ __launch_bounds__(HH_WG) void k_resid(Ctx cx, int mode)
             acc[2] = acc[2] + (rv.x * rv.x + rv.y * rv.y);
         }
     }
-    chunk_finish<3>(pd, tl.idx, acc);
+    group_finish<3>(pd, tl.idx, acc);
 }
 
 // partial ||vec||^2 (slot 2) ; finalise ||b||
-__global__ __launch_bounds__(HH_WG) void k_norm(Ctx cx, int sel)
+__global__ __launch_bounds__(HH_VWG) void k_norm(Ctx cx, int sel)
 {
     const Tile tl = tile_of(cx);
     const ProbDev *pd = cx.P + tl.prob;
     const double2 *__restrict__ x = (const double2 *)pd->vec[sel];
-    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_CHUNK;
+    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_SPAN;
     double2 xr[HH_PER_SLOT];
 #pragma unroll
     for (int s = 0; s < HH_PER_SLOT; ++s)
@@ -2406,16 +2874,16 @@ __global__ __launch_bounds__(HH_WG) void k_norm(Ctx cx, int sel)
 #pragma unroll
     for (int s = 0; s < HH_PER_SLOT; ++s)
         if (CHUNK_P(s) < N) acc[2] = acc[2] + (xr[s].x * xr[s].x + xr[s].y * xr[s].y);
-    chunk_finish<3>(pd, tl.idx, acc);
+    group_finish<3>(pd, tl.idx, acc);
 }
 
 // set a complex double vector to zero
-__global__ __launch_bounds__(HH_WG) void k_zero(Ctx cx, int sel)
+__global__ __launch_bounds__(HH_VWG) void k_zero(Ctx cx, int sel)
 {
     const Tile tl = tile_of(cx);
     const ProbDev *pd = cx.P + tl.prob;
     double2 *__restrict__ x = (double2 *)pd->vec[sel];
-    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_CHUNK;
+    const int64_t N = pd->N, base = (int64_t)tl.idx * HH_SPAN;
 #pragma unroll
     for (int s = 0; s < HH_PER_SLOT; ++s)
         if (CHUNK_P(s) < N) stg(x, CHUNK_P(s), cmk<double>(0.0, 0.0));

@@ -181,7 +181,7 @@ void grid_fill_prob(const hh_grid *g, ProbDev &pd)
     pd.Nc = hs.Nc;
     for (int a = 0; a < 3; ++a) pd.n[a] = hs.lev[0].n[a];
     pd.N = hs.lev[0].N;
-    pd.nchunk = ceil_div(pd.N, HH_CHUNK);
+    pd.ngroup = ceil_div(pd.N, HH_SPAN);
     pd.fx = make_fastdiv((uint32_t)pd.n[0]);
     pd.fxy = make_fastdiv((uint32_t)(pd.n[0] * pd.n[1]));
     for (int a = 0; a < 3; ++a) {
@@ -220,6 +220,34 @@ static void grid_release(hh_grid *g)
 }
 
 // ---------------------------------------------------------------------------
+// Merged coarse legs (one 2D problem): the last K = 2 or 3 levels above the
+// tail, each exactly twice the next, run as one down- and one up-leg launch.
+// Down: C x C tiles of the tail's first level; up: UT x UT tiles of the
+// first merged level; NT threads (four waves per SIMD hide the LDS latency of
+// the per-point chains).  HH_MERGE=0 turns it off.
+template <typename T> struct MergeTile;
+template <> struct MergeTile<float> { static constexpr int C = 4, UT = 32, NT = 1024; };
+template <> struct MergeTile<double> { static constexpr int C = 2, UT = 32, NT = 1024; };
+
+static void plan_merge(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
+{
+    pl.mK = pl.mlev0 = pl.mdn = pl.mup = 0;
+    if (const char *e = getenv("HH_MERGE"))
+        if (atoi(e) == 0) return;
+    if (G.size() != 1 || G[0]->hs.dim != 2 || G[0]->host_only) return;
+    const HostSetup &hs = G[0]->hs;
+    const int t = tail_level(hs, fp32), K = std::min(3, t - 1);
+    if (K < 2) return;
+    for (int l = t - K; l < t; ++l)
+        if (hs.lev[l].n[0] != 2 * hs.lev[l + 1].n[0] || hs.lev[l].n[1] != 2 * hs.lev[l + 1].n[1]) return;
+    const int C = fp32 ? MergeTile<float>::C : MergeTile<double>::C;
+    const int UT = fp32 ? MergeTile<float>::UT : MergeTile<double>::UT;
+    pl.mK = K;
+    pl.mlev0 = t - K;
+    pl.mdn = ceil_div(hs.lev[t].n[0], C) * ceil_div(hs.lev[t].n[1], C);
+    pl.mup = ceil_div(hs.lev[t - K].n[0], UT) * ceil_div(hs.lev[t - K].n[1], UT);
+}
+
 // launch plans: tile lists of every pass for a set of problems
 // ---------------------------------------------------------------------------
 static void tile_shape(int dim, int v, int &x, int &y, int &z)
@@ -377,9 +405,11 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
     std::vector<Tile> chunks, down[HH_MAXLEV], up[HH_MAXLEV], coarse[5];
     std::vector<int> fin;
     pl.tail_down = pl.tail_up = false;
+    plan_merge(pl, G, fp32);
     // tile shape per level and leg, tuned on the largest problem having the level
     for (int l = 0; l < HH_MAXLEV; ++l) {
         pl.vdv[l] = pl.vuv[l] = 0;
+        if (pl.mK && l >= pl.mlev0) continue;   // merged levels
         const hh_grid *rep = nullptr;
         for (const hh_grid *g : G)
             if (l < tail_level(g->hs, fp32) && (!rep || g->hs.lev[l].N > rep->hs.lev[l].N)) rep = g;
@@ -400,8 +430,8 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         }
         if (!split || t < hs.nlev - 1) pl.tail_down = true;
         if (split && t < hs.nlev - 1) pl.tail_up = true;
-        int nch = ceil_div(hs.lev[0].N, HH_CHUNK);
-        for (int i = 0; i < nch; ++i) chunks.push_back(Tile{q, i});
+        const int ngr = ceil_div(hs.lev[0].N, HH_SPAN);
+        for (int i = 0; i < ngr; ++i) chunks.push_back(Tile{q, i});
         for (int l = 0; l < t; ++l) {
             int nd, nu;
             vtile_counts(hs.dim, pl.vdv[l], hs.lev[l], hs.lev[l + 1], nd, nu);
@@ -452,6 +482,12 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
 #define LAUNCH(kernel, n, stream, ...)                                                  \
     do {                                                                                \
         if ((n) > 0) hipLaunchKernelGGL(kernel, dim3(n), dim3(HH_WG), 0, stream, __VA_ARGS__); \
+    } while (0)
+
+// Krylov vector passes: workgroups of HH_GROUP chunks
+#define LAUNCH_K(kernel, n, stream, ...)                                                 \
+    do {                                                                                \
+        if ((n) > 0) hipLaunchKernelGGL(kernel, dim3(n), dim3(HH_VWG), 0, stream, __VA_ARGS__); \
     } while (0)
 
 // level kernels: workgroup size of tile shape v
@@ -658,6 +694,25 @@ static int tune_leg(const hh_grid *g, bool fp32, int leg, int l)
     return best;
 }
 
+// the merged down- (leg 0) or up-leg (leg 1) of a one-problem 2D plan
+template <typename T, int K>
+static void launch_merged_k(int leg, const Plan &pl, hipStream_t s, const LevelDev<T> *L)
+{
+    LvChain<T, K> lc;
+    for (int k = 0; k <= K; ++k) lc.L[k] = L[pl.mlev0 + k];
+    const Ctx c = ctx_of(pl, pl.chunks);
+    constexpr int NT = MergeTile<T>::NT;
+    if (leg == 0) hipLaunchKernelGGL((k_vdown_m<T, K, MergeTile<T>::C, NT>), dim3(pl.mdn), dim3(NT), 0, s, c, lc);
+    else hipLaunchKernelGGL((k_vup_m<T, K, MergeTile<T>::UT, NT>), dim3(pl.mup), dim3(NT), 0, s, c, lc);
+}
+template <typename T>
+static void launch_merged(int leg, const Plan &pl, hipStream_t s, const LvHost &lh)
+{
+    const LevelDev<T> *L = lv_of<T>(lh);
+    if (pl.mK == 2) launch_merged_k<T, 2>(leg, pl, s, L);
+    else launch_merged_k<T, 3>(leg, pl, s, L);
+}
+
 template <int DIM, typename T>
 static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void *optr, hipStream_t s)
 {
@@ -672,8 +727,10 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
         lh.d = pl.lv64h;
         lh.f = pl.lv32h;
     }
-    for (int l = 0; l < pl.Lmax; ++l)
+    const int lsplit = pl.mK ? pl.mlev0 : pl.Lmax;   // first merged level
+    for (int l = 0; l < lsplit; ++l)
         launch_leg<DIM, T>(0, pl.vdv[l], pl.down[l].n, s, ctx_of(pl, pl.down[l]), l, fsel, osel, fptr, optr, lh);
+    if (pl.mK) launch_merged<T>(0, pl, s, lh);
     {
         // coarse part: tail kernel (whole, or down-legs of split problems),
         // multi-workgroup coarsest solves, up-legs of split problems
@@ -689,7 +746,8 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
         if (pl.nfin > 0 && pl.tail_up)
             hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c, probs, 1);
     }
-    for (int l = pl.Lmax - 1; l >= 0; --l)
+    if (pl.mK) launch_merged<T>(1, pl, s, lh);
+    for (int l = lsplit - 1; l >= 0; --l)
         launch_leg<DIM, T>(1, pl.vuv[l], pl.up[l].n, s, ctx_of(pl, pl.up[l]), l, fsel, osel, fptr, optr, lh);
 }
 
@@ -715,16 +773,16 @@ static void bicg_iter_t(const Plan &pl, hipStream_t s)
 {
     const Ctx c = ctx_of(pl, pl.chunks);
     const int n = pl.chunks.n;
-    LAUNCH(k_bicg_p, n, s, c);
+    LAUNCH_K(k_bicg_p, n, s, c);
     launch_vcycle(pl, VS_P, VS_PH, nullptr, nullptr, s);
-    LAUNCH((k_bicg_v<DIM, SP>), n, s, c);
+    LAUNCH_K((k_bicg_v<DIM, SP>), n, s, c);
     launch_fin(pl, pl.fin, pl.nfin, FIN_ALPHA, s);
-    LAUNCH(k_bicg_s, n, s, c);
+    LAUNCH_K(k_bicg_s, n, s, c);
     // the half-step check on ||s|| runs in the omega finaliser
     launch_vcycle(pl, VS_R, VS_SH, nullptr, nullptr, s);
-    LAUNCH((k_bicg_t<DIM, SP>), n, s, c);
+    LAUNCH_K((k_bicg_t<DIM, SP>), n, s, c);
     launch_fin(pl, pl.fin, pl.nfin, FIN_OMEGA, s);
-    LAUNCH((k_bicg_xr<SP>), n, s, c);
+    LAUNCH_K((k_bicg_xr<SP>), n, s, c);
     launch_fin(pl, pl.fin, pl.nfin, FIN_RHO, s);
 }
 
@@ -744,11 +802,11 @@ static void idr_step_t(const Plan &pl, hipStream_t s)
 {
     const Ctx c = ctx_of(pl, pl.chunks);
     const int n = pl.chunks.n;
-    LAUNCH(k_idr_v, n, s, c);
+    LAUNCH_K(k_idr_v, n, s, c);
     launch_vcycle(pl, VS_V, VS_W, nullptr, nullptr, s);
-    LAUNCH((k_idr_t<DIM, SW>), n, s, c);
+    LAUNCH_K((k_idr_t<DIM, SW>), n, s, c);
     launch_fin(pl, pl.fin, pl.nfin, FIN_IDR_OMEGA, s);
-    LAUNCH((k_idr_up<DIM, SW>), n, s, c);
+    LAUNCH_K((k_idr_up<DIM, SW>), n, s, c);
     launch_fin(pl, pl.fin, pl.nfin, FIN_IDR_STEP, s);
 }
 
@@ -766,18 +824,18 @@ void launch_idr_step(const Plan &pl, hipStream_t s)
 void launch_resid(const Plan &pl, const DevList &tiles, int mode, hipStream_t s)
 {
     const Ctx c = ctx_of(pl, tiles);
-    if (pl.dim == 2) LAUNCH(k_resid<2>, tiles.n, s, c, mode);
-    else LAUNCH(k_resid<3>, tiles.n, s, c, mode);
+    if (pl.dim == 2) LAUNCH_K(k_resid<2>, tiles.n, s, c, mode);
+    else LAUNCH_K(k_resid<3>, tiles.n, s, c, mode);
 }
 
 void launch_norm(const Plan &pl, const DevList &tiles, int sel, hipStream_t s)
 {
-    LAUNCH(k_norm, tiles.n, s, ctx_of(pl, tiles), sel);
+    LAUNCH_K(k_norm, tiles.n, s, ctx_of(pl, tiles), sel);
 }
 
 void launch_zero(const Plan &pl, const DevList &tiles, int sel, hipStream_t s)
 {
-    LAUNCH(k_zero, tiles.n, s, ctx_of(pl, tiles), sel);
+    LAUNCH_K(k_zero, tiles.n, s, ctx_of(pl, tiles), sel);
 }
 
 // A grid from a finished host setup: copies the description (not phi) and
@@ -836,13 +894,13 @@ hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_
     g += align256(sizeof(double2) * (size_t)nc * nc) + align256(sizeof(float2) * (size_t)nc * nc);
     g += align256(TailCap<double>::BYTES) + align256(TailCap<float>::BYTES);
     g += 2 * align256(sizeof(LevelDev<double>) * HH_MAXLEV) + align256(sizeof(ProbDev));
-    const int nch = ceil_div(N, HH_CHUNK);
+    const int nch = ceil_div(N, HH_CHUNK), ngr = ceil_div(N, HH_SPAN);
     g += align256(sizeof(Tile) * nch);
     // a mixed-precision solve may continue with the FP64 V-cycle (larger work
     // space), so the FP64 work space is reserved either way
     size_t ws = solve_workspace_bytes(N, o->method, false, s, 0);
     size_t io = 2 * align256(sizeof(double2) * N) + (s > 0 ? align256(sizeof(double2) * (size_t)N * s) : 0);
-    size_t tiles = nch + (nc > HH_SPLIT_NC ? ceil_div(coarse_waves<double>(nc), HH_WG / 64) : 0);
+    size_t tiles = ngr + (nc > HH_SPLIT_NC ? ceil_div(coarse_waves<double>(nc), HH_WG / 64) : 0);
     for (int l = 0; l + 1 < nl; ++l) {
         int md = 0, mu = 0;
         for (int v = 0; v < HH_NTILE; ++v) {
@@ -853,7 +911,7 @@ hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_
         }
         tiles += md + mu;
     }
-    size_t plan = sizeof(Tile) * (tiles + nch) + sizeof(ProbDev) + sizeof(Ctrl) + 2 * sizeof(int) +
+    size_t plan = sizeof(Tile) * (tiles + ngr) + sizeof(ProbDev) + sizeof(Ctrl) + 2 * sizeof(int) +
                   256 * (2 * HH_MAXLEV + 8);
     bytes = g + ws + io + plan;
     return HH_OK;

@@ -32,8 +32,8 @@ static size_t solve_vectors_bytes(int64_t N, int method, bool fp32, int s)
 
 size_t solve_workspace_bytes(int64_t N, int method, bool fp32, int s, int hist_len)
 {
-    const int nch = ceil_div(N, HH_CHUNK);
-    return al256(sizeof(double) * HH_NPART * nch) + al256(sizeof(SolveState)) +
+    const int ngr = ceil_div(N, HH_SPAN);
+    return al256(sizeof(double) * HH_NPART * ngr) + al256(sizeof(SolveState)) +
            al256(sizeof(double) * std::max(hist_len, 1)) + solve_vectors_bytes(N, method, fp32, s);
 }
 
@@ -50,7 +50,7 @@ hh_status workspace_ensure(hh_grid *g, int method, bool fp32, int s, int hist_le
     workspace_release(w);
     const int64_t N = g->hs.lev[0].N;
     const size_t c16 = al256(sizeof(double2) * N), clow = al256((fp32 ? sizeof(float2) : sizeof(double2)) * N);
-    const int nch = ceil_div(N, HH_CHUNK);
+    const int ngr = ceil_div(N, HH_SPAN);
     const size_t bytes = solve_workspace_bytes(N, method, fp32, s, hist_len);
     hipError_t e = hipMalloc(&w.mem, bytes);
     if (e != hipSuccess) {
@@ -64,7 +64,7 @@ hh_status workspace_ensure(hh_grid *g, int method, bool fp32, int s, int hist_le
     w.hist_cap = hist_len;
     char *c = (char *)w.mem;
     auto take = [&](size_t b) { void *p = c; c += b; return p; };
-    w.part = (double *)take(al256(sizeof(double) * HH_NPART * nch));
+    w.part = (double *)take(al256(sizeof(double) * HH_NPART * ngr));
     w.st = (SolveState *)take(al256(sizeof(SolveState)));
     w.hist = (double *)take(al256(sizeof(double) * std::max(hist_len, 1)));
     if (method == HH_METHOD_BICGSTAB) {
@@ -180,11 +180,11 @@ hh_status KBatch::set(const std::vector<KProb *> &probs)
     }
     const int nb = (int)P_.size();
     std::vector<ProbDev> hp(nb);
-    int total_chunks = 0;
+    int total_groups = 0;
     for (int q = 0; q < nb; ++q) {
         fill_solve_prob(P_[q]->g, &P_[q]->o, P_[q]->b, P_[q]->x, hp[q]);
         hp[q].ctrl = pl_->ctrl + q;
-        total_chunks += hp[q].nchunk;
+        total_groups += hp[q].ngroup;
     }
     pl_->host = hp;
     hipStream_t s = pl_->stream;
@@ -193,7 +193,7 @@ hh_status KBatch::set(const std::vector<KProb *> &probs)
         HIPCHK(hipMemcpyAsync(pl_->ctrl, hc.data(), sizeof(Ctrl) * nb, hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));
     }
-    const size_t need = al256(sizeof(Tile) * std::max(total_chunks, 1)) + al256(sizeof(int) * std::max(nb, 1));
+    const size_t need = al256(sizeof(Tile) * std::max(total_groups, 1)) + al256(sizeof(int) * std::max(nb, 1));
     if (need > sub_bytes_) {
         if (sub_mem_) (void)hipFree(sub_mem_);
         sub_mem_ = nullptr;
@@ -206,7 +206,7 @@ hh_status KBatch::set(const std::vector<KProb *> &probs)
         sub_bytes_ = need;
     }
     sub_t_ = (Tile *)sub_mem_;
-    sub_p_ = (int *)((char *)sub_mem_ + al256(sizeof(Tile) * std::max(total_chunks, 1)));
+    sub_p_ = (int *)((char *)sub_mem_ + al256(sizeof(Tile) * std::max(total_groups, 1)));
     return HH_OK;
 }
 
@@ -215,8 +215,8 @@ hh_status KBatch::sub_set(const std::vector<int> &which)
     ht_.clear();
     hp_.clear();
     for (int q : which) {
-        const int nch = pl_->host[q].nchunk;
-        for (int i = 0; i < nch; ++i) ht_.push_back(Tile{q, i});
+        const int ngr = pl_->host[q].ngroup;
+        for (int i = 0; i < ngr; ++i) ht_.push_back(Tile{q, i});
         hp_.push_back(q);
     }
     hipStream_t s = pl_->stream;

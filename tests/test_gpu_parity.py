@@ -378,20 +378,94 @@ def test_graph_replay_equals_eager(torch_dev, hh_mod, monkeypatch):
 
 
 def test_long_partial_arrays_match_oracle(torch_dev, hh_mod, oracle_mod):
-    """2048^2 has 16384 reduction chunks, more than one finaliser block: the
-    first FP64 matvecs give the oracle's residual history and iterate value
-    for value."""
+    """4096 x 2560 unknowns make 40960 reduction chunks (10240 groups of
+    four), more than one finaliser block (8192 partials): the first FP64
+    matvecs give the oracle's residual history and iterate value for value."""
     torch = torch_dev
-    c = W.c2(n=2048, levels=9)
-    g = hh_mod.Grid(c["desc"], c["phi"])
-    o = oracle_mod.Grid(c["desc"], c["phi"])
+    d = W.base_desc(2, (4096, 2560), (-0.25, -0.25), (1.25, 1.25), (0.0, 0.0), (1.0, 1.0), levels=9)
+    h = 1.5 / 4096
+    phi = W.bump_k(d, 2 * np.pi / (10 * h), W.rng(2).uniform(0.15, 0.85, size=(8, 2)))
+    g = hh_mod.Grid(d, phi)
+    o = oracle_mod.Grid(d, phi)
     b = rand_c(np.random.default_rng(17), g.N)
+    print("long partials: N", g.N, flush=True)
     xo, io = o.solve(b, tol=1e-14, max_matvec=4, history=True)
     xg, ig = g.solve(dev(torch, b), tol=1e-14, max_matvec=4, vcycle_prec="c128", history=True)
     assert ig["matvecs"] == io["matvecs"] == 4
     assert np.array_equal(ig["history"], io["history"])
     assert same(host(xg), xo)
     assert ig["rel_res_true"] == io["rel_res_true"]
+
+
+# problems of 1 to 4 reduction chunks (256 unknowns each), ragged and exact:
+# a Krylov workgroup of several chunks stops its group sum at the padded chunk
+# count; 24 x 24 also takes the many-workgroup coarse solve (144 unknowns)
+TINY = [(16, 12), (16, 16), (24, 16), (24, 24), (32, 28)]
+
+
+@pytest.mark.parametrize("n", TINY)
+def test_tiny_problems_match_oracle(torch_dev, hh_mod, oracle_mod, n):
+    torch = torch_dev
+    d = W.base_desc(2, n, (-0.2, -0.3), (1.3, 1.1), (0.0, 0.0), (1.0, 0.9), levels=2)
+    N = n[0] * n[1]
+    phi = 25.0 * (1 + 0.3 * np.random.default_rng(N).uniform(size=N))
+    g = hh_mod.Grid(d, phi)
+    o = oracle_mod.Grid(d, phi)
+    b = rand_c(np.random.default_rng(N + 1), N)
+    print("tiny", n, "chunks", -(-N // 256), flush=True)
+    xo, io = o.solve(b, tol=1e-12, max_matvec=60, history=True)
+    xg, ig = g.solve(dev(torch, b), tol=1e-12, max_matvec=60, vcycle_prec="c128", history=True)
+    assert ig["status"] == io["status"] and ig["matvecs"] == io["matvecs"] > 0
+    assert np.array_equal(ig["history"], io["history"])
+    assert same(host(xg), xo)
+    assert ig["rel_res_true"] == io["rel_res_true"]
+    if n == (24, 24):
+        P = W.shadow_space(N, 2, 5)
+        xo, io = o.solve(b, tol=1e-12, max_matvec=60, method="idr", s=2, P=P, history=True)
+        xg, ig = g.solve(dev(torch, b), tol=1e-12, max_matvec=60, method="idr", s=2, P=hh_mod.shadow_to_device(P),
+                         vcycle_prec="c128", history=True)
+        assert ig["status"] == io["status"] and ig["matvecs"] == io["matvecs"] > 0
+        assert np.array_equal(ig["history"], io["history"])
+        assert same(host(xg), xo)
+
+
+def ragged_merge():
+    d = W.base_desc(2, (352, 224), (-0.2, -0.3), (1.3, 1.1), (0.0, 0.0), (1.0, 0.9), levels=6)
+    rng = np.random.default_rng(23)
+    phi = (100.0 ** 2) * (1 + 0.3 * rng.uniform(size=352 * 224))
+    return {"desc": d, "phi": phi}
+
+
+# 2D problems whose last levels above the tail run as one merged down- and
+# one merged up-leg launch: two levels (256^2), three (512^2), three with
+# ragged tiles on every level (352 x 224)
+MERGE_CASES = {
+    "c2_256": lambda: W.c2(n=256, levels=6),
+    "c2_512": lambda: W.c2(n=512, levels=7),
+    "ragged_merge": ragged_merge,
+}
+
+
+@pytest.mark.parametrize("name", list(MERGE_CASES))
+def test_merged_coarse_legs_match(torch_dev, hh_mod, oracle_mod, monkeypatch, name):
+    """Merged coarse legs give the oracle's FP64 V-cycle value for value, and
+    the same FP32 cycle as the level-by-level kernels (same arithmetic)."""
+    torch = torch_dev
+    c = MERGE_CASES[name]()
+    print("case", name, flush=True)
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    f = rand_c(np.random.default_rng(9), o.N)
+    ref = o.vcycle(f)
+    fd = dev(torch, f)
+    out = {}
+    for merge in ("1", "0"):
+        monkeypatch.setenv("HH_MERGE", merge)
+        g = hh_mod.Grid(c["desc"], c["phi"])
+        assert same(host(g.vcycle(fd, "c128")), ref), (name, merge)
+        out[merge] = host(g.vcycle(fd, "c64"))
+        g.close()
+    assert same(out["1"], out["0"])
+    assert rel(out["1"], ref) < 1e-4
 
 
 @pytest.mark.parametrize("name", ["c2_256", "ragged_2d", "ragged_3d", "c3_32"])
