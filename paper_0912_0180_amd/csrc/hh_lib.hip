@@ -224,10 +224,12 @@ static void grid_release(hh_grid *g)
 // tail, each exactly twice the next, run as one down- and one up-leg launch.
 // Down: C x C tiles of the tail's first level; up: UT x UT tiles of the
 // first merged level; NT threads (four waves per SIMD hide the LDS latency of
-// the per-point chains).  HH_MERGE=0 turns it off.
+// the per-point chains).  At 1024^2 (three merged levels) C = 2, UT = 16 is
+// fastest of C in 1..4, UT in 8..32: more workgroups than that cost more in
+// redundant halo work than they gain.  HH_MERGE=0 turns it off.
 template <typename T> struct MergeTile;
-template <> struct MergeTile<float> { static constexpr int C = 4, UT = 32, NT = 1024; };
-template <> struct MergeTile<double> { static constexpr int C = 2, UT = 32, NT = 1024; };
+template <> struct MergeTile<float> { static constexpr int C = 2, UT = 16, NT = 1024; };
+template <> struct MergeTile<double> { static constexpr int C = 2, UT = 16, NT = 1024; };
 
 static void plan_merge(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
 {
