@@ -438,11 +438,15 @@ def ragged_merge():
 
 # 2D problems whose last levels above the tail run as one merged down- and
 # one merged up-leg launch: two levels (256^2), three (512^2), three with
-# ragged tiles on every level (352 x 224)
+# ragged tiles on every level (352 x 224), three above a 576-unknown coarsest
+# grid solved by k_coarse between the tail's down- and up-legs (384^2), three
+# down and four up (1024^2)
 MERGE_CASES = {
     "c2_256": lambda: W.c2(n=256, levels=6),
     "c2_512": lambda: W.c2(n=512, levels=7),
     "ragged_merge": ragged_merge,
+    "c2_384_split": lambda: W.c2(n=384, levels=5),
+    "c2_1024": lambda: W.c2(),
 }
 
 
