@@ -107,6 +107,16 @@ __device__ __forceinline__ void stg(float2 *p, int64_t i, float2 v)
     ((HH_GLOBAL hh_fvec2 *)p)[i] = w;
 }
 
+// streaming store: output that the next launch does not read past the caches,
+// so they keep the inputs (vector store with the non-temporal hint)
+__device__ __forceinline__ void stg_nt(double2 *p, int64_t i, double2 v)
+{
+    hh_dvec2 w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, (HH_GLOBAL hh_dvec2 *)p + i);
+}
+
 // conversions between the two complex precisions
 template <typename T, typename S> __device__ inline V2<T> ccvt(S v) { return cmk<T>((T)v.x, (T)v.y); }
 

@@ -1004,7 +1004,7 @@ hh_status hh_apply_operator(const hh_grid *g, hh_op op, hh_prec prec, const void
     if (op == HH_OP_H) {
         if (prec != HH_C128) return hh_fail(HH_ERR_ARG, "H is applied in complex double only");
         const int nx = g->hs.lev[0].n[0], ny = g->hs.lev[0].n[1];
-        if (g->hs.dim == 2 && nx % 256 == 0) LAUNCH(k_applyH_band, (nx / 256) * ((ny + 1) / 2), s, c, x, y);
+        if (g->hs.dim == 2 && nx % 256 == 0) LAUNCH(k_applyH_band, (nx / 256) * ((ny + 1) / 2), s, hview(&g->pd_static), x, y);
         else if (g->hs.dim == 2) LAUNCH(k_applyH<2>, n, s, c, x, y);
         else LAUNCH(k_applyH<3>, n, s, c, x, y);
     } else if (op == HH_OP_M) {
