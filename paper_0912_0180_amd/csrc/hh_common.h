@@ -266,8 +266,8 @@ struct Ctx {
 // Levels with at most TailCap<T>::N unknowns (and every coarser level) run
 // inside one workgroup with all data in LDS.
 template <typename T> struct TailCap;
-template <> struct TailCap<double> { static constexpr int N = 1024; static constexpr int BYTES = 96 * 1024; static constexpr int WG = 256; };
-template <> struct TailCap<float> { static constexpr int N = 1024; static constexpr int BYTES = 64 * 1024; static constexpr int WG = 512; };
+template <> struct TailCap<double> { static constexpr int N = 1024; static constexpr int BYTES = 96 * 1024; static constexpr int WG = 512; };
+template <> struct TailCap<float> { static constexpr int N = 1024; static constexpr int BYTES = 64 * 1024; static constexpr int WG = 1024; };
 
 // Tile shapes of the fused V-cycle level kernels (coarse points per axis of
 // the down-leg's tile; the up-leg's fine tile is twice it).  The kernels are
