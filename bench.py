@@ -423,8 +423,8 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true", help="only the launches the counter runs read")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (multi-GPU sharding is a design note, "
-              "not part of the measured path); run with --gpus 1", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU only (multi-GPU sharding is described, not "
+              "implemented, and is not part of the measured path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -78,7 +78,7 @@ typedef struct {
     int32_t csg_mode;       /* hh_csg_mode                                               */
     int32_t levels;         /* multigrid levels; 0 = halve while every side is even and
                                the largest side exceeds 16 (2D) / 8 (3D)                 */
-    int32_t nu1, nu2;       /* smoothing steps; this build supports (1,1)                */
+    int32_t nu1, nu2;       /* smoothing steps; the library supports (1,1)               */
     double omega;           /* Jacobi weight, e.g. 0.8                                   */
     const double *phi;      /* host, prod(n) reals: k(x)^2 at the cell centres; NULL ->
                                phi_const everywhere                                      */
