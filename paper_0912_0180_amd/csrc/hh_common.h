@@ -279,11 +279,11 @@ template <> struct TailCap<float> { static constexpr int N = 1024; static conste
 #define HH_NBOX 7
 template <int DIM> struct TileSet;
 template <> struct TileSet<2> {
-    static constexpr int N = HH_NBOX;   // shapes in use
-    static constexpr int X[HH_NTILE] = {16, 32, 16, 8, 32, 32, 32, 16, 16};
+    static constexpr int N = HH_NBOX + 1;   // shapes in use (the last a 1024-thread box)
+    static constexpr int X[HH_NTILE] = {16, 32, 16, 8, 32, 32, 32, 32, 16};
     static constexpr int Y[HH_NTILE] = {16, 8, 8, 8, 16, 8, 16, 16, 16};
     static constexpr int Z[HH_NTILE] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
-    static constexpr int T[HH_NTILE] = {256, 256, 256, 256, 256, 512, 512, 256, 256};   // threads per workgroup
+    static constexpr int T[HH_NTILE] = {256, 256, 256, 256, 256, 512, 512, 1024, 256};   // threads per workgroup
 };
 template <> struct TileSet<3> {
     static constexpr int N = HH_NTILE;

@@ -527,6 +527,8 @@ static void launch_down_v(int v, int n, hipStream_t s, const Ctx &c, int lev, in
         if constexpr (DIM == 3) {
             if (v == 7) LAUNCH_V((k_vdown_z<T, TF, 7>), 7, n, s, c, lev, fsel, fptr, lp);
             else LAUNCH_V((k_vdown_z<T, TF, 8>), 8, n, s, c, lev, fsel, fptr, lp);
+        } else {
+            LAUNCH_V((k_vdown<DIM, T, TF, 7>), 7, n, s, c, lev, fsel, fptr, lp);
         }
         break;
     }
@@ -548,6 +550,8 @@ static void launch_up_v(int v, int n, hipStream_t s, const Ctx &c, int lev, int 
         if constexpr (DIM == 3) {
             if (v == 7) LAUNCH_V((k_vup_z<T, TF, TO, 7>), 7, n, s, c, lev, fsel, osel, fptr, optr, lp);
             else LAUNCH_V((k_vup_z<T, TF, TO, 8>), 8, n, s, c, lev, fsel, osel, fptr, optr, lp);
+        } else {
+            LAUNCH_V((k_vup<DIM, T, TF, TO, 7>), 7, n, s, c, lev, fsel, osel, fptr, optr, lp);
         }
         break;
     }

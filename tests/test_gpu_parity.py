@@ -484,8 +484,9 @@ def test_every_tile_shape_gives_the_same_cycle(torch_dev, hh_mod, oracle_mod, mo
     ref = o.vcycle(f)
     fd = dev(torch, f)
     u32 = None
-    # tile shapes: 7 box shapes; in 3D two more, the z-streaming kernels
-    for v in range(9 if c["desc"]["dim"] == 3 else 7):
+    # tile shapes: 7 box shapes; in 3D two more, the z-streaming kernels, in
+    # 2D one more box of 1024 threads
+    for v in range(9 if c["desc"]["dim"] == 3 else 8):
         monkeypatch.setenv("HH_TILE", str(v))
         g = hh_mod.Grid(c["desc"], c["phi"])
         assert same(host(g.vcycle(fd, "c128")), ref), (name, v)
