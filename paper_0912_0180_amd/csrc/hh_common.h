@@ -23,10 +23,10 @@
 #define HH_CHUNK (HH_WG * HH_PER_SLOT)
 // Krylov vector passes: a workgroup of HH_GROUP chunks (one unknown per
 // thread, chunk s = waves 4s..4s+3) writes one partial per value, the
-// group's node of the pairwise tree over chunk partials.  One chunk per
-// workgroup measures fastest (four: same 2D solve time, 3D 1-3% slower; the
-// finaliser's cost is its load latency, not the partial count).
-#define HH_GROUP 1
+// group's node of the pairwise tree over chunk partials.  Two chunks per
+// workgroup measure fastest (about 1% over one in 2D and 3D; four: 3D 1-3%
+// slower).
+#define HH_GROUP 2
 #define HH_VWG (HH_WG * HH_GROUP)
 #define HH_SPAN (HH_CHUNK * HH_GROUP)
 #define HH_NPART 40               // reals per chunk partial record (IDR(8) start-up needs 4s+1)
