@@ -25,9 +25,10 @@ struct Plan {
     bool tail_down = false;          // some problem needs the (full or down-only) tail kernel
     bool tail_up = false;            // some problem needs the up-only tail kernel
     int vdv[HH_MAXLEV] = {}, vuv[HH_MAXLEV] = {};   // tile shape of each level's down- and up-leg
-    // one 2D problem: levels mlev0 .. mlev0 + mK - 1 (ending at the tail) run as
-    // one merged down-leg launch of mdn workgroups and one up-leg launch of mup
-    int mK = 0, mlev0 = 0, mdn = 0, mup = 0;
+    // one 2D problem: the down-legs of levels mlev0 .. mlev0 + mK - 1 (ending at
+    // the tail) run as one merged launch of mdn workgroups, the up-legs of
+    // levels mlev0u .. mlev0u + mKup - 1 (ending at the tail too) as one of mup
+    int mK = 0, mlev0 = 0, mdn = 0, mKup = 0, mlev0u = 0, mup = 0;
     int *fin = nullptr;
     int nfin = 0;
     ProbDev *probs = nullptr;

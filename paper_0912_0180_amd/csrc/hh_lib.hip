@@ -220,34 +220,40 @@ static void grid_release(hh_grid *g)
 }
 
 // ---------------------------------------------------------------------------
-// Merged coarse legs (one 2D problem): the last K = 2 or 3 levels above the
-// tail, each exactly twice the next, run as one down- and one up-leg launch.
-// Down: C x C tiles of the tail's first level; up: UT x UT tiles of the
-// first merged level; NT threads (four waves per SIMD hide the LDS latency of
-// the per-point chains).  At 1024^2 (three merged levels) C = 2, UT = 16 is
-// fastest of C in 1..4, UT in 8..32: more workgroups than that cost more in
-// redundant halo work than they gain.  HH_MERGE=0 turns it off.
+// Merged coarse legs (one 2D problem), each level exactly twice the next: the
+// down-legs of the last K = 2 or 3 levels above the tail run as one launch,
+// the up-legs of the last 2 to 4 (their regions stay small) as another.
+// Down: C x C tiles of the tail's first level.  Up: UT x UT tiles of the
+// first merged up level, UT = 16 over up to three levels and 32 over four
+// (about 256 workgroups either way: more would not all be resident at once).
+// NT threads (four waves per SIMD hide the LDS latency of the per-point
+// chains).  At 1024^2 C = 2, UT = 16 is fastest of C in 1..4, UT in 8..32
+// over three levels: more workgroups than that cost more in redundant halo
+// work than they gain.  HH_MERGE=0 turns it off.
 template <typename T> struct MergeTile;
-template <> struct MergeTile<float> { static constexpr int C = 2, UT = 16, NT = 1024; };
-template <> struct MergeTile<double> { static constexpr int C = 2, UT = 16, NT = 1024; };
+template <> struct MergeTile<float> { static constexpr int C = 2, UT = 16, UT4 = 32, NT = 1024; };
+template <> struct MergeTile<double> { static constexpr int C = 2, UT = 16, UT4 = 32, NT = 1024; };
 
 static void plan_merge(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
 {
-    pl.mK = pl.mlev0 = pl.mdn = pl.mup = 0;
+    pl.mK = pl.mlev0 = pl.mdn = pl.mKup = pl.mlev0u = pl.mup = 0;
     if (const char *e = getenv("HH_MERGE"))
         if (atoi(e) == 0) return;
     if (G.size() != 1 || G[0]->hs.dim != 2 || G[0]->host_only) return;
     const HostSetup &hs = G[0]->hs;
-    const int t = tail_level(hs, fp32), K = std::min(3, t - 1);
+    const int t = tail_level(hs, fp32), K = std::min(3, t - 1), Kup = std::min(4, t - 1);
     if (K < 2) return;
-    for (int l = t - K; l < t; ++l)
+    for (int l = t - Kup; l < t; ++l)
         if (hs.lev[l].n[0] != 2 * hs.lev[l + 1].n[0] || hs.lev[l].n[1] != 2 * hs.lev[l + 1].n[1]) return;
     const int C = fp32 ? MergeTile<float>::C : MergeTile<double>::C;
-    const int UT = fp32 ? MergeTile<float>::UT : MergeTile<double>::UT;
+    const int UT = Kup == 4 ? (fp32 ? MergeTile<float>::UT4 : MergeTile<double>::UT4)
+                            : (fp32 ? MergeTile<float>::UT : MergeTile<double>::UT);
     pl.mK = K;
     pl.mlev0 = t - K;
     pl.mdn = ceil_div(hs.lev[t].n[0], C) * ceil_div(hs.lev[t].n[1], C);
-    pl.mup = ceil_div(hs.lev[t - K].n[0], UT) * ceil_div(hs.lev[t - K].n[1], UT);
+    pl.mKup = Kup;
+    pl.mlev0u = t - Kup;
+    pl.mup = ceil_div(hs.lev[t - Kup].n[0], UT) * ceil_div(hs.lev[t - Kup].n[1], UT);
 }
 
 // launch plans: tile lists of every pass for a set of problems
@@ -411,13 +417,13 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
     // tile shape per level and leg, tuned on the largest problem having the level
     for (int l = 0; l < HH_MAXLEV; ++l) {
         pl.vdv[l] = pl.vuv[l] = 0;
-        if (pl.mK && l >= pl.mlev0) continue;   // merged levels
+        if (pl.mK && l >= pl.mlev0) continue;   // merged levels (mlev0u <= mlev0)
         const hh_grid *rep = nullptr;
         for (const hh_grid *g : G)
             if (l < tail_level(g->hs, fp32) && (!rep || g->hs.lev[l].N > rep->hs.lev[l].N)) rep = g;
         if (!rep || rep->host_only) continue;
         pl.vdv[l] = tune_leg(rep, fp32, 0, l);
-        pl.vuv[l] = tune_leg(rep, fp32, 1, l);
+        if (!pl.mK || l < pl.mlev0u) pl.vuv[l] = tune_leg(rep, fp32, 1, l);
     }
     for (int q = 0; q < pl.count; ++q) {
         const HostSetup &hs = G[q]->hs;
@@ -705,18 +711,25 @@ template <typename T, int K>
 static void launch_merged_k(int leg, const Plan &pl, hipStream_t s, const LevelDev<T> *L)
 {
     LvChain<T, K> lc;
-    for (int k = 0; k <= K; ++k) lc.L[k] = L[pl.mlev0 + k];
+    const int l0 = leg == 0 ? pl.mlev0 : pl.mlev0u;
+    for (int k = 0; k <= K; ++k) lc.L[k] = L[l0 + k];
     const Ctx c = ctx_of(pl, pl.chunks);
     constexpr int NT = MergeTile<T>::NT;
-    if (leg == 0) hipLaunchKernelGGL((k_vdown_m<T, K, MergeTile<T>::C, NT>), dim3(pl.mdn), dim3(NT), 0, s, c, lc);
-    else hipLaunchKernelGGL((k_vup_m<T, K, MergeTile<T>::UT, NT>), dim3(pl.mup), dim3(NT), 0, s, c, lc);
+    constexpr int UT = K == 4 ? MergeTile<T>::UT4 : MergeTile<T>::UT;
+    if (leg == 0) {
+        if constexpr (K <= 3) hipLaunchKernelGGL((k_vdown_m<T, K, MergeTile<T>::C, NT>), dim3(pl.mdn), dim3(NT), 0, s, c, lc);
+    } else {
+        hipLaunchKernelGGL((k_vup_m<T, K, UT, NT>), dim3(pl.mup), dim3(NT), 0, s, c, lc);
+    }
 }
 template <typename T>
 static void launch_merged(int leg, const Plan &pl, hipStream_t s, const LvHost &lh)
 {
     const LevelDev<T> *L = lv_of<T>(lh);
-    if (pl.mK == 2) launch_merged_k<T, 2>(leg, pl, s, L);
-    else launch_merged_k<T, 3>(leg, pl, s, L);
+    const int K = leg == 0 ? pl.mK : pl.mKup;
+    if (K == 2) launch_merged_k<T, 2>(leg, pl, s, L);
+    else if (K == 3) launch_merged_k<T, 3>(leg, pl, s, L);
+    else launch_merged_k<T, 4>(leg, pl, s, L);
 }
 
 template <int DIM, typename T>
@@ -753,7 +766,7 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
             hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c, probs, 1);
     }
     if (pl.mK) launch_merged<T>(1, pl, s, lh);
-    for (int l = lsplit - 1; l >= 0; --l)
+    for (int l = (pl.mK ? pl.mlev0u : pl.Lmax) - 1; l >= 0; --l)
         launch_leg<DIM, T>(1, pl.vuv[l], pl.up[l].n, s, ctx_of(pl, pl.up[l]), l, fsel, osel, fptr, optr, lh);
 }
 
