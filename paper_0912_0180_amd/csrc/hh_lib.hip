@@ -735,8 +735,6 @@ static void launch_merged(int leg, const Plan &pl, hipStream_t s, const LvHost &
 template <int DIM, typename T>
 static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void *optr, hipStream_t s)
 {
-    using C = V2<T>;
-    using TO = V2<T>;  // level-0 output in the V-cycle precision
     if (pl.count == 1 && !fptr) {
         fptr = pl.host.at(0).vec[fsel];
         optr = pl.host.at(0).vec[osel];
