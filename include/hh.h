@@ -93,8 +93,9 @@ typedef struct hh_grid hh_grid;   /* opaque */
 /* Builds node maps, Shortley-Weller coefficients of H and M on every level,
  * the coarse phi hierarchy (mean of children) and the explicit inverse of
  * the coarsest M (dense LU with partial pivoting), and uploads them.
- * Errors: HH_ERR_ARG (dim not 2/3; side not divisible by 2^(levels-1);
- * coarsest grid above 1024 unknowns; theta outside (0, pi/2); a, b outside
+ * Errors: HH_ERR_ARG (dim not 2/3; fewer than 2 levels, given or from the
+ * automatic rule; side not divisible by 2^(levels-1); coarsest grid above
+ * 1024 unknowns; theta outside (0, pi/2); a, b outside
  * [lo, hi]; nu1/nu2 other than 1; singular coarse matrix), HH_ERR_OOM,
  * HH_ERR_HIP.  *out is set only on HH_OK. */
 hh_status hh_setup_grid(const hh_grid_desc *d, hh_grid **out);
