@@ -90,7 +90,8 @@ typedef struct {
 
 typedef struct hh_grid hh_grid;   /* opaque */
 
-/* Builds node maps, Shortley-Weller coefficients of H and M on every level,
+/* Builds node maps, Shortley-Weller coefficients of H and M on every level
+ * (Sec. 3, eq. (shortwell); M by Sec. 5.3, eq. (CSL-CSG) / (lapctucsg)),
  * the coarse phi hierarchy (mean of children) and the explicit inverse of
  * the coarsest M (dense LU with partial pivoting), and uploads them.
  * Errors: HH_ERR_ARG (dim not 2/3; fewer than 2 levels, given or from the
@@ -118,15 +119,24 @@ hh_status hh_grid_query(const hh_grid *g, hh_grid_info *info);
 hh_status hh_grid_export(const hh_grid *g, int32_t what, int32_t level, int32_t axis, void *host_dst,
                          size_t bytes);
 
-/* y = A x on the finest grid; A = H (ECS operator, prec must be HH_C128) or
- * M (CSG preconditioner; HH_C128 uses FP64 coefficients, HH_C64 the FP32
- * copies).  x, y: device, N elements of `prec`, must not overlap. */
+/* y = A x on the finest grid; A = H (the ECS operator of Sec. 3, eq.
+ * (shortwell); prec must be HH_C128) or M (the CSG operator of Sec. 5.3;
+ * HH_C128 uses FP64 coefficients, HH_C64 the FP32 copies).  x, y: device, N
+ * elements of `prec`, must not be the same buffer; the caller owns both.
+ * Errors: HH_ERR_ARG (null pointer, host-only grid, x == y, H with HH_C64,
+ * unknown op or prec), HH_ERR_HIP (launch failure or no device). */
 hh_status hh_apply_operator(const hh_grid *g, hh_op op, hh_prec prec, const void *x, void *y, void *stream);
 
-/* u = V(f): one V(1,1) cycle on M from a zero initial guess.
+/* u = V(f): one V(1,1) cycle on M from a zero initial guess (Sec. 6.2: the
+ * preconditioner application; weighted Jacobi, full weighting, linear
+ * interpolation, exact coarsest solve).
  * prec = HH_C128: f and u are complex double, all levels in FP64.
  * prec = HH_C64 : f is complex double, u is complex float, every level
- *                 computes in FP32 (the mixed-precision preconditioner). */
+ *                 computes in FP32 (the mixed-precision preconditioner).
+ * f, u: device, N elements, caller-owned, not the same buffer.  The first call
+ * per precision builds the grid's launch plan (device memory the grid keeps).
+ * Errors: HH_ERR_ARG (null pointer, host-only grid, f == u, unknown prec),
+ * HH_ERR_OOM (plan allocation), HH_ERR_HIP. */
 hh_status hh_vcycle(const hh_grid *g, hh_prec prec, const void *f, void *u, void *stream);
 
 typedef struct {
@@ -156,7 +166,11 @@ typedef struct {
                                    V-cycle; matvecs and iterations count both parts */
 } hh_solve_info;
 
-/* Solves H x = b.  b, x: device complex double, N elements.  Fills *info.
+/* Solves H x = b by right-preconditioned Bi-CGSTAB or IDR(s) with M^{-1}
+ * replaced by one V-cycle (Sec. 6.2).  b, x: device complex double, N
+ * elements, caller-owned.  Fills *info.  Errors: HH_ERR_ARG (invalid options,
+ * host-only grid), HH_ERR_OOM (work space), HH_ERR_HIP, and the solve's own
+ * outcome: HH_ERR_NOCONV, HH_ERR_BREAKDOWN, HH_ERR_NONFINITE.
  * HH_ERR_NOCONV / HH_ERR_BREAKDOWN still leave the last iterate in x and a
  * complete info.  A zero b gives x = 0 with 0 matvecs.  The grid keeps its
  * solve work space allocated until hh_free_grid. */
