@@ -397,6 +397,38 @@ def test_long_partial_arrays_match_oracle(torch_dev, hh_mod, oracle_mod):
     assert ig["rel_res_true"] == io["rel_res_true"]
 
 
+def test_full_size_2d_solve(torch_dev, hh_mod, oracle_mod):
+    """The 1024^2 point-source problem, solved as bench.py times it.  The
+    oracle takes too long for a whole solve here, so its first 24 FP64
+    matvecs are compared: the residual history and the iterate agree value
+    for value.  The whole FP64 and mixed solves must then reach a true
+    residual below 1e-8, evaluated with the oracle's operator, and agree
+    with each other to 1e-6."""
+    torch = torch_dev
+    c = W.c2()
+    print("case c2 1024^2", flush=True)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    b = c["b"]
+    bd = dev(torch, b)
+    xo, io = o.solve(b, tol=1e-8, max_matvec=24, history=True)
+    xg, ig = g.solve(bd, tol=1e-8, max_matvec=24, vcycle_prec="c128", history=True)
+    assert io["status"] == ig["status"] == -4
+    assert ig["matvecs"] == io["matvecs"] == 24
+    assert np.array_equal(ig["history"], io["history"])
+    assert same(host(xg), xo)
+    nb = np.linalg.norm(b)
+    x64, i64 = g.solve(bd, tol=1e-8, vcycle_prec="c128")
+    x32, i32 = g.solve(bd, tol=1e-8, vcycle_prec="c64")
+    x64, x32 = host(x64), host(x32)
+    for x, info in ((x64, i64), (x32, i32)):
+        assert info["status"] == 0
+        assert np.linalg.norm(b - o.apply(x, "H")) / nb < 1e-8
+    assert i32["fp64_fallback"] == 0
+    assert rel(x32, x64) <= 1e-6
+    print("c2 matvecs fp64", i64["matvecs"], "mixed", i32["matvecs"], "diff", rel(x32, x64), flush=True)
+
+
 # problems of 1 to 4 reduction chunks (256 unknowns each), ragged and exact:
 # a Krylov workgroup of several chunks stops its group sum at the padded chunk
 # count; 24 x 24 also takes the many-workgroup coarse solve (144 unknowns)
