@@ -429,6 +429,42 @@ def test_full_size_2d_solve(torch_dev, hh_mod, oracle_mod):
     print("c2 matvecs fp64", i64["matvecs"], "mixed", i32["matvecs"], "diff", rel(x32, x64), flush=True)
 
 
+def test_full_size_3d_solve(torch_dev, hh_mod, oracle_mod):
+    """The 128^3 problem with 16-cell layers (2.1 M unknowns, five levels),
+    solved as bench.py times it.  The first 8 FP64 matvecs of Bi-CGSTAB and
+    of IDR(4) give the oracle's residual history and iterate value for value.
+    The whole mixed Bi-CGSTAB and IDR(4) solves must reach a true residual
+    below 1e-8, evaluated with the oracle's operator, and agree with the
+    whole FP64 Bi-CGSTAB solve to 1e-6."""
+    torch = torch_dev
+    c = W.c3(n=128, layer=16, method="idr", s=4)
+    print("case c3 128^3", flush=True)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    b, P = c["b"], c["P"]
+    bd, Pd = dev(torch, b), hh_mod.shadow_to_device(P)
+    for ko, kg in (({}, {}), ({"method": "idr", "s": 4, "P": P}, {"method": "idr", "s": 4, "P": Pd})):
+        xo, io = o.solve(b, tol=1e-8, max_matvec=8, history=True, **ko)
+        xg, ig = g.solve(bd, tol=1e-8, max_matvec=8, vcycle_prec="c128", history=True, **kg)
+        assert io["status"] == ig["status"] == -4, ko
+        assert ig["matvecs"] == io["matvecs"] == 8 and ig["iterations"] == io["iterations"], ko
+        assert np.array_equal(ig["history"], io["history"]), ko
+        assert same(host(xg), xo), ko
+    nb = np.linalg.norm(b)
+    x64, i64 = g.solve(bd, tol=1e-8, vcycle_prec="c128")
+    x64 = host(x64)
+    runs = {"bicgstab_fp64": (x64, i64)}
+    x, i = g.solve(bd, tol=1e-8, vcycle_prec="c64")
+    runs["bicgstab_mixed"] = (host(x), i)
+    x, i = g.solve(bd, tol=1e-8, vcycle_prec="c64", method="idr", s=4, P=Pd)
+    runs["idr4_mixed"] = (host(x), i)
+    for name, (x, info) in runs.items():
+        assert info["status"] == 0, name
+        assert np.linalg.norm(b - o.apply(x, "H")) / nb < 1e-8, name
+        assert rel(x, x64) <= 1e-6, name
+        print(name, "matvecs", info["matvecs"], "diff to fp64", rel(x, x64), flush=True)
+
+
 # problems of 1 to 4 reduction chunks (256 unknowns each), ragged and exact:
 # a Krylov workgroup of several chunks stops its group sum at the padded chunk
 # count; 24 x 24 also takes the many-workgroup coarse solve (144 unknowns)
