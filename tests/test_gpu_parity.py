@@ -465,6 +465,35 @@ def test_full_size_3d_solve(torch_dev, hh_mod, oracle_mod):
         print(name, "matvecs", info["matvecs"], "diff to fp64", rel(x, x64), flush=True)
 
 
+def test_full_size_batch(torch_dev, hh_mod, oracle_mod):
+    """The 64-problem batch (sides 256 to 1024, 5 to 12 points per
+    wavelength, 1 to 4 Gaussian sources), solved in mixed precision as
+    bench.py times it.  Every problem must reach a true residual below 1e-8,
+    evaluated with the oracle's operator.  Problems whose FP32 V-cycle
+    drifted finish with the FP64 one and report it.  Problems taken from the
+    batch must give alone exactly what they gave in it."""
+    torch = torch_dev
+    probs = W.c4(count=64)
+    print("case c4: 64 problems", flush=True)
+    grids = [hh_mod.Grid(c["desc"], c["phi"]) for c in probs]
+    bs = [dev(torch, c["b"]) for c in probs]
+    xs, infos = hh_mod.solve_batch(grids, bs, tol=1e-8, vcycle_prec="c64")
+    fell = [q for q in range(len(probs)) if infos[q]["fp64_fallback"]]
+    for q, c in enumerate(probs):
+        assert infos[q]["status"] == 0, q
+        o = oracle_mod.Grid(c["desc"], c["phi"])
+        r = np.linalg.norm(c["b"] - o.apply(host(xs[q]), "H")) / np.linalg.norm(c["b"])
+        assert r < 1e-8, (q, r)
+        del o
+    for q in [0, 1, 2] + fell[:1]:
+        xq, iq = grids[q].solve(bs[q], tol=1e-8, vcycle_prec="c64")
+        assert iq["matvecs"] == infos[q]["matvecs"] and iq["fp64_fallback"] == infos[q]["fp64_fallback"], q
+        assert same(host(xq), host(xs[q])), q
+    print("c4: fallbacks", fell, "matvecs max", max(i["matvecs"] for i in infos), flush=True)
+    for g in grids:
+        g.close()
+
+
 # problems of 1 to 4 reduction chunks (256 unknowns each), ragged and exact:
 # a Krylov workgroup of several chunks stops its group sum at the padded chunk
 # count; 24 x 24 also takes the many-workgroup coarse solve (144 unknowns)
