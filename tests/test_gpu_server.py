@@ -204,3 +204,27 @@ def test_server_drift_fallback_matches_alone(hh_mod, monkeypatch):
     assert np.array_equal(x1, xa)
     x2, i2 = res[t2]
     assert i2["fp64_fallback"] == 0 and np.array_equal(x2, xs)
+
+
+def test_full_size_serving_sample(hh_mod, oracle_mod):
+    """The serving sample that bench.py measures: its first 16 requests, 2D
+    up to 2048^2 and 3D up to 160^3 in mixed precision, through one server
+    with 16 slots and the default budget.  Every request must complete with
+    status 0 and a true residual below 1e-8, evaluated with the oracle's
+    operator."""
+    g = W.rng(5)
+    reqs = [W.serving_request(g) for _ in range(16)]
+    print("serving sample: 16 requests", flush=True)
+    sv = hh_mod.Server(budget=0, max_slots=16)
+    try:
+        tickets = [sv.submit(r["desc"], r["b"], phi=r["phi"], method="bicgstab", vcycle_prec="c64") for r in reqs]
+        out = wait_all(sv, tickets, limit=100.0)
+    finally:
+        sv.close()
+    for q, (r, t) in enumerate(zip(reqs, tickets)):
+        x, info = out[t]
+        assert info["status"] == 0, (q, info)
+        o = oracle_mod.Grid(r["desc"], r["phi"])
+        res = np.linalg.norm(r["b"] - o.apply(x, "H")) / np.linalg.norm(r["b"])
+        assert res < 1e-8, (q, res)
+        del o
