@@ -292,6 +292,59 @@ def test_idr_fp64_matches_oracle(torch_dev, hh_mod, oracle_mod, name, s):
     assert np.array_equal(ig["history"], io["history"])
 
 
+def small_problem(n=(16, 16), k=20.0):
+    d = W.base_desc(2, n, (-0.25, -0.25), (1.25, 1.25), (0.0, 0.0), (1.0, 1.0), levels=2)
+    N = int(np.prod(n))
+    rng = np.random.default_rng(7)
+    phi = k * k * (1 + 0.2 * rng.uniform(size=N))
+    b = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    return d, phi, b
+
+
+@pytest.mark.parametrize("s", [1, 4])
+def test_idr_breakdown_and_restarts_match_oracle(torch_dev, hh_mod, oracle_mod, s):
+    """A zero shadow space gives a zero G at the end of each start-up: a
+    breakdown, a restart from the true residual, and after max_restarts the
+    breakdown status.  Status, restarts, counts, history and iterate equal
+    the oracle's."""
+    torch = torch_dev
+    d, phi, b = small_problem()
+    print("case idr P=0 s", s, flush=True)
+    g = hh_mod.Grid(d, phi)
+    o = oracle_mod.Grid(d, phi)
+    P = np.zeros((g.N, s), complex)
+    xo, io = o.solve(b, method="idr", s=s, P=P, max_restarts=2, history=True)
+    xg, ig = g.solve(dev(torch, b), method="idr", s=s, P=hh_mod.shadow_to_device(P), max_restarts=2,
+                     vcycle_prec="c128", history=True)
+    assert io["status"] == -5 == ig["status"]
+    assert ig["restarts"] == io["restarts"] == 2 and ig["matvecs"] == io["matvecs"] == 3 * s
+    assert np.array_equal(ig["history"], io["history"])
+    assert same(host(xg), xo) and ig["rel_res_true"] == io["rel_res_true"]
+
+
+@pytest.mark.parametrize("method,n,tol,restarts", [("bicgstab", (32, 32), 1e-15, 1), ("bicgstab", (16, 16), 2e-15, 2),
+                                                   ("idr", (32, 32), 1e-15, 1), ("idr", (24, 16), 1e-15, 2),
+                                                   ("bicgstab", (16, 16), 1e-15, 3)])
+def test_restart_from_true_residual_matches_oracle(torch_dev, hh_mod, oracle_mod, method, n, tol, restarts):
+    """Tolerances near FP64 rounding force restarts from the true residual
+    (then convergence, or the restarts run out: not converged); the GPU
+    reproduces the oracle's status, restarts, matvecs, history and iterate."""
+    torch = torch_dev
+    d, phi, b = small_problem(n=n)
+    print("case restart", method, n, tol, flush=True)
+    g = hh_mod.Grid(d, phi)
+    o = oracle_mod.Grid(d, phi)
+    P = W.shadow_space(g.N, 4, 11)
+    xo, io = o.solve(b, method=method, tol=tol, s=4, P=P, max_restarts=3, history=True)
+    xg, ig = g.solve(dev(torch, b), method=method, tol=tol, s=4, P=hh_mod.shadow_to_device(P), max_restarts=3,
+                     vcycle_prec="c128", history=True)
+    assert io["restarts"] == restarts == ig["restarts"]
+    assert ig["status"] == io["status"] and ig["matvecs"] == io["matvecs"]
+    assert ig["iterations"] == io["iterations"]
+    assert np.array_equal(ig["history"], io["history"])
+    assert same(host(xg), xo)
+
+
 @pytest.mark.parametrize("name", ["c1", "ragged_3d", "c3_32"])
 def test_idr_mixed_precision(torch_dev, hh_mod, oracle_mod, name):
     torch = torch_dev

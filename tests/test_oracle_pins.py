@@ -114,6 +114,122 @@ def test_paper_ecs_matrix_rows(oracle_mod):
     assert fx["rows"][1]["node"] == n
 
 
+@pytest.mark.parametrize("grid", ["right", "two_sided"])
+def test_interior_csg_matrix_rows(oracle_mod, grid):
+    """Interior-only CSG (Sec. 5.3, eq. (lapctucsg), fig. ctucsg): interior
+    widths beta*h, contour widths gamma*h, connected at the turning points.
+    The rows of -h^2 M_h are the golden fixture's, whose values are those
+    widths put into the Shortley-Weller formula of eq. (shortwell) by a
+    standard-library script.  A map that drops the beta of the turning point
+    (a discontinuous grid) or scales a contour width fails here."""
+    with open(os.path.join(GOLDEN, "csg_interior_1d_scaled_matrix.json")) as fh:
+        fx = json.load(fh)
+    G = fx["grids"][grid]
+    n = G["unknowns"]
+    d = desc1(n, G["lo"], G["hi"], G["a"], G["b"], theta=fx["theta_ecs"], theta_csg=fx["theta_csg"],
+              centering=1, levels=1, mode=1)
+    g = oracle_mod.Grid(d, np.zeros(n))
+    h = 1.0 / fx["n_interior"]
+    A = g.matrix("M") * h * h
+    for r in G["rows"]:
+        j = r["node"] - 1
+        for off, key in ((-1, "lower"), (0, "diag"), (1, "upper")):
+            col = j + off
+            want = complex(*r[key])
+            got = A[j, col] if 0 <= col < n else 0j
+            assert abs(got - want) <= 1e-12 * max(1.0, abs(want)), (grid, r["node"], key, got, want)
+    # the ECS operator of the same grid is untouched by the CSG mode
+    He = oracle_mod.Grid(desc1(n, G["lo"], G["hi"], G["a"], G["b"], theta=fx["theta_ecs"], centering=1, levels=1),
+                         np.zeros(n)).matrix("H")
+    assert np.array_equal(g.matrix("H"), He)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coarse_phi_is_mean_of_children(oracle_mod, dim):
+    """Coarse phi is the mean of the 2^d children.  On a field linear in the
+    cell-centre coordinates the mean of the children equals the field at the
+    coarse cell centre, so level l holds 1 + 2x + 3y (+ 5z) at its own
+    centres on every level; a small integer field checks one value by hand."""
+    n = {2: (16, 8), 3: (8, 8, 4)}[dim]
+    d = W.base_desc(dim, n, (0.0,) * dim, (1.0,) * dim, (0.0,) * dim, (1.0,) * dim, levels=3)
+    coef = [2.0, 3.0, 5.0][:dim]
+
+    def lin(ns):
+        xs = [(np.arange(m) + 0.5) / m for m in ns]
+        X = np.meshgrid(*xs, indexing="ij")
+        return W.flat(1.0 + sum(c * Xa for c, Xa in zip(coef, X)))
+
+    g = oracle_mod.Grid(d, lin(n))
+    for lev in (1, 2):
+        nl = [m >> lev for m in n]
+        assert np.max(np.abs(g.phi(lev) - lin(nl))) < 1e-14
+    # by hand (2D): fine phi = i + 100 j (x fastest); coarse (I, J) averages
+    # fine (2I..2I+1, 2J..2J+1): 2I + 0.5 + 100 (2J + 0.5)
+    if dim == 2:
+        i, j = np.meshgrid(np.arange(16), np.arange(8), indexing="ij")
+        g2 = oracle_mod.Grid(d, W.flat(i + 100.0 * j))
+        c1 = g2.phi(1)
+        assert c1[0] == 50.5            # (0+1+100+101)/4
+        assert c1[1] == 52.5            # (2+3+102+103)/4
+        assert c1[8] == 250.5           # I = 0, J = 1: (200+201+300+301)/4
+        assert c1[3 + 8 * 2] == 456.5   # I = 3, J = 2: (6+7+406+407)/4
+
+
+def fw_1d(n):
+    """Cell-centred full weighting (1,3,3,1)/8 as an (n/2) x n matrix."""
+    R = np.zeros((n // 2, n))
+    for I in range(n // 2):
+        for q, w in enumerate((1, 3, 3, 1)):
+            i = 2 * I - 1 + q
+            if 0 <= i < n:
+                R[I, i] = w / 8.0
+    return R
+
+
+def kron_x_fastest(mats):
+    """Tensor product of per-axis matrices for the x-fastest layout."""
+    out = mats[0]
+    for m in mats[1:]:
+        out = np.kron(m, out)
+    return out
+
+
+def test_vcycle_equals_three_level_matrix(oracle_mod):
+    """Three-level V(1,1) from explicitly assembled pieces:
+    each level's M from a separate one-level grid of that size whose phi is
+    the mean of the finer level's children (computed here), full weighting
+    R = kron of (1,3,3,1)/8, bilinear P = 4 R^T, weighted Jacobi
+    J = omega D^-1, exact solve on the coarsest level:
+      B_2 = M_2^-1,  B_l = (I - J M)(J + P B_{l+1} R (I - M J)) + J."""
+    n0 = (16, 12)
+    lo, hi, a, b = (-0.25, -0.25), (1.25, 1.25), (0.0, 0.0), (1.0, 1.0)
+    rng = np.random.default_rng(16)
+    phi0 = 150.0 + 60.0 * rng.uniform(size=n0[0] * n0[1])
+    g = oracle_mod.Grid(W.base_desc(2, n0, lo, hi, a, b, levels=3), phi0)
+    Ms, phis, ns = [], [phi0], [n0]
+    for lev in range(3):
+        n = ns[lev]
+        if lev > 0:
+            fine = phis[lev - 1].reshape(ns[lev - 1][1], ns[lev - 1][0])   # [y][x]
+            phis.append(fine.reshape(n[1], 2, n[0], 2).mean(axis=(1, 3)).reshape(-1))
+        g1 = oracle_mod.Grid(W.base_desc(2, n, lo, hi, a, b, levels=1), phis[lev])
+        Ms.append(g1.matrix("M"))
+        if lev < 2:
+            ns.append((n[0] // 2, n[1] // 2))
+    B = np.linalg.inv(Ms[2])
+    for lev in (1, 0):
+        M = Ms[lev]
+        N = M.shape[0]
+        R = kron_x_fastest([fw_1d(ns[lev][0]), fw_1d(ns[lev][1])])
+        P = 4.0 * R.T
+        J = 0.8 * np.diag(1.0 / np.diag(M))
+        I = np.eye(N)
+        B = (I - J @ M) @ (J + P @ B @ R @ (I - M @ J)) + J
+    f = rng.standard_normal(g.N) + 1j * rng.standard_normal(g.N)
+    want = B @ f
+    assert np.linalg.norm(g.vcycle(f) - want) < 1e-11 * np.linalg.norm(want)
+
+
 def test_lemma_3_2_eigenvalue_condition(oracle_mod):
     """Lemma 3.2: every eigenvalue lambda of -L_h on the ECS grid solves
     V_{m-1}(t)/V_m(t) + g V_{n-1}(s)/V_n(s) = g s + t, i.e. in Chebyshev-U
@@ -391,6 +507,8 @@ def test_poisson_vcycle_convergence_is_mesh_independent(oracle_mod, dim, ns, bou
 # --------------------------------------------------------------------------
 
 def small_problem(levels=2, n=(16, 16), k=20.0, theta_csg=math.pi / 8):
+    """2D ECS problem on [-0.25, 1.25]^2 with a layer of 0.25 per side, k^2
+    varying by 20% at random, random complex right-hand side (seed 7)."""
     d = W.base_desc(2, n, (-0.25, -0.25), (1.25, 1.25), (0.0, 0.0), (1.0, 1.0), levels=levels,
                     theta_csg=theta_csg)
     N = int(np.prod(n))
@@ -448,6 +566,54 @@ def test_bicgstab_point_source_1d_matches_direct(oracle_mod):
     assert info["status"] == 0 and g.nlev > 2
     xd = np.linalg.solve(g.matrix("H"), b)
     assert np.linalg.norm(x - xd) < 1e-7 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("s", [1, 2, 4])
+def test_idr_zero_shadow_space_breaks_down_and_restarts(oracle_mod, s):
+    """With P = 0 the matrix G = P^H dR of IDR(s) is exactly zero at the end
+    of every start-up, so its LU has a zero pivot: a breakdown.  Each attempt
+    then consists of the s minimal-residual start-up steps, whose residual
+    norms cannot increase (omega minimises ||r - omega t||); after
+    max_restarts restarts from the true residual the solve reports the
+    breakdown with (max_restarts + 1) s matvecs and the iterate's true
+    residual."""
+    d, phi, b = small_problem()
+    g = oracle_mod.Grid(d, phi)
+    x, info = g.solve(b, method="idr", s=s, P=np.zeros((g.N, s), complex), max_restarts=2, history=True)
+    assert info["status"] == -5 and info["restarts"] == 2 and info["matvecs"] == 3 * s
+    h = info["history"]
+    assert np.all(np.diff(h) <= 1e-15) and h[-1] < 1.0
+    tr = np.linalg.norm(b - g.apply(x, "H")) / np.linalg.norm(b)
+    assert abs(info["rel_res_true"] - tr) <= 1e-12 * tr
+
+
+@pytest.mark.parametrize("method,n,tol,restarts", [("bicgstab", (32, 32), 1e-15, 1), ("bicgstab", (16, 16), 2e-15, 2),
+                                                   ("idr", (32, 32), 1e-15, 1), ("idr", (24, 16), 1e-15, 2)])
+def test_restart_from_true_residual_then_converges(oracle_mod, method, n, tol, restarts):
+    """At a tolerance near FP64 rounding the recurrence residual passes tol
+    while the true residual ||b - H x||/||b|| does not; the solve restarts
+    from the true residual (r = b - H x, rhat = r) and that restart, an
+    iterative-refinement step, brings the true residual under tol.  The
+    solution equals the dense direct solve."""
+    d, phi, b = small_problem(n=n)
+    g = oracle_mod.Grid(d, phi)
+    x, info = g.solve(b, method=method, tol=tol, s=4, P=W.shadow_space(g.N, 4, 11), max_restarts=3)
+    assert info["status"] == 0 and info["restarts"] == restarts
+    assert info["rel_res_true"] < tol
+    tr = np.linalg.norm(b - g.apply(x, "H")) / np.linalg.norm(b)
+    assert abs(info["rel_res_true"] - tr) <= 1e-12 * max(tr, 1e-300)
+    xd = np.linalg.solve(g.matrix("H"), b)
+    assert np.linalg.norm(x - xd) < 1e-11 * np.linalg.norm(xd)
+
+
+def test_restarts_exhausted_is_noconv(oracle_mod):
+    """Below what FP64 can reach the restarts run out: not converged, with
+    the last iterate and its true residual."""
+    d, phi, b = small_problem(n=(16, 16))
+    g = oracle_mod.Grid(d, phi)
+    x, info = g.solve(b, tol=1e-15, max_restarts=3)
+    assert info["status"] == -4 and info["restarts"] == 3
+    assert info["rel_res_true"] >= 1e-15
 
 
 def test_zero_rhs_and_limits(oracle_mod):
