@@ -139,6 +139,27 @@ hh_status hh_apply_operator(const hh_grid *g, hh_op op, hh_prec prec, const void
  * HH_ERR_OOM (plan allocation), HH_ERR_HIP. */
 hh_status hh_vcycle(const hh_grid *g, hh_prec prec, const void *f, void *u, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * V-cycle as hh_vcycle, same kernels and results, but the restricted
+ * right-hand sides and level solutions of levels >= 1 live in a static
+ * device array of the library (32 MiB per device, held until the process
+ * ends) instead of memory the grid allocates on first use.  The call
+ * allocates nothing, creates no stream or event and times nothing (tile
+ * shapes come from earlier hh_vcycle/hh_solve plans of the same level class,
+ * else a default; shapes never change results).  Every call on one device
+ * shares that array: calls that overlap in time on one device (other
+ * streams, other threads) race and give wrong results; calls ordered on one
+ * stream are safe.  Nothing in the array needs to start at zero (every value
+ * is written before it is read within one cycle).  f: device complex double,
+ * u: device, complex double (HH_C128) or complex float (HH_C64), N elements,
+ * caller-owned, not the same buffer; the grid must have been set up on the
+ * current device.  Errors: HH_ERR_ARG (as hh_vcycle; the coarse levels need
+ * more than 32 MiB in this precision -- e.g. 2D 2048^2 in complex double;
+ * current device is not the grid's), HH_ERR_HIP (launch failure, or the
+ * array's address was not found at grid setup). */
+hh_status hh_vcycle_noalloc(const hh_grid *g, hh_prec prec, const void *f, void *u, void *stream);
+
 typedef struct {
     int32_t method;          /* hh_method                                              */
     int32_t s;               /* IDR shadow dimension (1..8)                            */

@@ -86,6 +86,15 @@ struct hh_grid {
     Tile *chunks_dev = nullptr;
     int nchunks = 0;
     Plan vplan64, vplan32;   // single-problem V-cycle plans (static descriptor)
+    // allocation-free V-cycle (hh_vcycle_noalloc): level descriptors whose f and
+    // e (levels >= 1) point into the library's static scratch array of this
+    // grid's device; scratch_need* = bytes of that layout per precision
+    LevelDev<double> L64sh[HH_MAXLEV] = {};
+    LevelDev<float> L32sh[HH_MAXLEV] = {};
+    LevelDev<double> *L64s = nullptr;
+    LevelDev<float> *L32s = nullptr;
+    size_t scratch_need64 = 0, scratch_need32 = 0;
+    bool scratch_ok = false;     // scratch address found and descriptors uploaded
     Plan plan;               // single-problem solve plan
     int plan_fp32 = -1;
     Workspace ws;

@@ -60,6 +60,51 @@ struct Carver {
 };
 
 // ---------------------------------------------------------------------------
+// Static scratch of the allocation-free V-cycle (hh_vcycle_noalloc): the
+// restricted right-hand sides f_l and level solutions e_l of levels >= 1 live
+// here instead of in the grid's memory.  Each device holds its own copy for
+// the life of the process.  On the host, `scratch` only names the symbol;
+// kernels get the device address hipGetSymbolAddress returns, looked up once
+// per device while that device is current (at the first grid set up on it).
+// ---------------------------------------------------------------------------
+#define HH_SCRATCH_BYTES ((size_t)32 << 20)
+static __device__ __align__(256) char scratch[HH_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, char *> g_scratch_addr;
+
+static hh_status scratch_address(int dev, char **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return HH_OK;
+    }
+    char *p = nullptr;
+    hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return hh_fail(HH_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+    *out = p;
+    return HH_OK;
+}
+
+// Byte offsets of f_l and e_l (levels >= 1) in the scratch array for one
+// precision; returns the bytes the layout needs.
+static size_t scratch_layout(const HostSetup &hs, bool fp32, size_t (*off)[2])
+{
+    const size_t cb = fp32 ? sizeof(float2) : sizeof(double2);
+    size_t used = 0;
+    for (int l = 1; l < hs.nlev; ++l) {
+        off[l][0] = used;
+        used += align256(cb * hs.lev[l].N);
+        off[l][1] = used;
+        used += align256(cb * hs.lev[l].N);
+    }
+    return used;
+}
+
+// ---------------------------------------------------------------------------
 // grid
 // ---------------------------------------------------------------------------
 hh_status grid_upload(hh_grid *g)
@@ -118,6 +163,8 @@ hh_status grid_upload(hh_grid *g)
         g->timg32 = c.take<char>(g->timg_bytes32);
         g->L64 = c.take<LevelDev<double>>(HH_MAXLEV);
         g->L32 = c.take<LevelDev<float>>(HH_MAXLEV);
+        g->L64s = c.take<LevelDev<double>>(HH_MAXLEV);
+        g->L32s = c.take<LevelDev<float>>(HH_MAXLEV);
         g->pd_static_dev = c.take<ProbDev>(1);
         g->chunks_dev = c.take<Tile>(ceil_div(hs.lev[0].N, HH_CHUNK));
         if (pass == 0) g->dbytes = c.used;
@@ -161,6 +208,31 @@ hh_status grid_upload(hh_grid *g)
     HIPCHK(put32c(g->Minv32, hs.Minv));
     HIPCHK(put64(g->L64, g->L64h, sizeof(LevelDev<double>) * HH_MAXLEV));
     HIPCHK(put64(g->L32, g->L32h, sizeof(LevelDev<float>) * HH_MAXLEV));
+    // the allocation-free V-cycle's descriptors: the same levels with f and e
+    // of levels >= 1 in the device's scratch array
+    {
+        char *sp = nullptr;
+        g->scratch_ok = false;
+        if (scratch_address(g->device, &sp) == HH_OK) {
+            size_t o64[HH_MAXLEV][2] = {}, o32[HH_MAXLEV][2] = {};
+            g->scratch_need64 = scratch_layout(hs, false, o64);
+            g->scratch_need32 = scratch_layout(hs, true, o32);
+            for (int l = 0; l < HH_MAXLEV; ++l) {
+                g->L64sh[l] = g->L64h[l];
+                g->L32sh[l] = g->L32h[l];
+                if (l >= 1 && l < hs.nlev) {
+                    const bool fit64 = g->scratch_need64 <= HH_SCRATCH_BYTES, fit32 = g->scratch_need32 <= HH_SCRATCH_BYTES;
+                    g->L64sh[l].f = fit64 ? (double2 *)(sp + o64[l][0]) : nullptr;
+                    g->L64sh[l].e = fit64 ? (double2 *)(sp + o64[l][1]) : nullptr;
+                    g->L32sh[l].f = fit32 ? (float2 *)(sp + o32[l][0]) : nullptr;
+                    g->L32sh[l].e = fit32 ? (float2 *)(sp + o32[l][1]) : nullptr;
+                }
+            }
+            HIPCHK(put64(g->L64s, g->L64sh, sizeof(LevelDev<double>) * HH_MAXLEV));
+            HIPCHK(put64(g->L32s, g->L32sh, sizeof(LevelDev<float>) * HH_MAXLEV));
+            g->scratch_ok = true;
+        }
+    }
     // static descriptor (no solve state) for hh_apply_operator / hh_vcycle
     ProbDev &pd = g->pd_static;
     grid_fill_prob(g, pd);
@@ -234,12 +306,12 @@ template <typename T> struct MergeTile;
 template <> struct MergeTile<float> { static constexpr int C = 2, UT = 16, UT4 = 32, NT = 1024; };
 template <> struct MergeTile<double> { static constexpr int C = 2, UT = 16, UT4 = 32, NT = 1024; };
 
-static void plan_merge(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
+static void plan_merge(Plan &pl, const hh_grid *const *G, int count, bool fp32)
 {
     pl.mK = pl.mlev0 = pl.mdn = pl.mKup = pl.mlev0u = pl.mup = 0;
     if (const char *e = getenv("HH_MERGE"))
         if (atoi(e) == 0) return;
-    if (G.size() != 1 || G[0]->hs.dim != 2 || G[0]->host_only) return;
+    if (count != 1 || G[0]->hs.dim != 2 || G[0]->host_only) return;
     const HostSetup &hs = G[0]->hs;
     const int t = tail_level(hs, fp32), K = std::min(3, t - 1), Kup = std::min(4, t - 1);
     if (K < 2) return;
@@ -413,7 +485,7 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
     std::vector<Tile> chunks, down[HH_MAXLEV], up[HH_MAXLEV], coarse[5];
     std::vector<int> fin;
     pl.tail_down = pl.tail_up = false;
-    plan_merge(pl, G, fp32);
+    plan_merge(pl, G.data(), (int)G.size(), fp32);
     // tile shape per level and leg, tuned on the largest problem having the level
     for (int l = 0; l < HH_MAXLEV; ++l) {
         pl.vdv[l] = pl.vuv[l] = 0;
@@ -706,6 +778,68 @@ static int tune_leg(const hh_grid *g, bool fp32, int leg, int l)
     return best;
 }
 
+// The shape tune_leg would use, without timing anything: forced, cached by
+// an earlier plan of the same class, or shape 0 (shapes never change results).
+static int tune_cached(const hh_grid *g, bool fp32, int leg, int l)
+{
+    if (const char *e = getenv("HH_TILE")) return std::min(std::max(atoi(e), 0), tile_shapes(g->hs.dim) - 1);
+    const HostSetup &hs = g->hs;
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= hs.lev[l].N) ++lg;
+    const std::array<int, 5> key{hs.dim, (int)fp32, leg, l == 0 ? 0 : 1, lg};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    return it != g_tune.end() ? it->second : 0;
+}
+
+// A one-problem V-cycle plan built on the host only: one-problem launches
+// take the workgroup index as the tile index and read nothing from a plan's
+// device lists, so no device memory, stream or timing is involved.  The level
+// descriptors (device array L1, host copies lv64h/lv32h) are the caller's.
+static void plan_host_one(Plan &pl, const hh_grid *g, bool fp32, const void *L1, const LevelDev<double> *lv64h,
+                          const LevelDev<float> *lv32h)
+{
+    const HostSetup &hs = g->hs;
+    pl.count = 1;
+    pl.dim = hs.dim;
+    pl.fp32 = fp32;
+    const hh_grid *G[1] = {g};
+    plan_merge(pl, G, 1, fp32);
+    const int t = tail_level(hs, fp32);
+    pl.Lmax = t;
+    for (int l = 0; l < HH_MAXLEV; ++l) {
+        pl.vdv[l] = pl.vuv[l] = 0;
+        pl.down[l].n = pl.up[l].n = 0;
+        if (l >= t || (pl.mK && l >= pl.mlev0)) continue;
+        pl.vdv[l] = tune_cached(g, fp32, 0, l);
+        if (!pl.mK || l < pl.mlev0u) pl.vuv[l] = tune_cached(g, fp32, 1, l);
+    }
+    for (int l = 0; l < t; ++l) {
+        int nd, nu;
+        vtile_counts(hs.dim, pl.vdv[l], hs.lev[l], hs.lev[l + 1], nd, nu);
+        pl.down[l].n = nd;
+        vtile_counts(hs.dim, pl.vuv[l], hs.lev[l], hs.lev[l + 1], nd, nu);
+        pl.up[l].n = nu;
+    }
+    for (int q = 0; q < 5; ++q) pl.coarse[q].n = 0;
+    const bool split = hs.Nc > HH_SPLIT_NC;
+    if (split) {
+        int lg = 0;
+        while ((1 << lg) < coarse_seg(hs.Nc)) ++lg;
+        pl.coarse[lg].n = ceil_div(fp32 ? coarse_waves<float>(hs.Nc) : coarse_waves<double>(hs.Nc), HH_WG / 64);
+    }
+    pl.tail_down = !split || t < hs.nlev - 1;
+    pl.tail_up = split && t < hs.nlev - 1;
+    pl.chunks.n = ceil_div(hs.lev[0].N, HH_SPAN);
+    pl.nfin = 1;
+    pl.probs = g->pd_static_dev;
+    pl.ctrl = nullptr;
+    pl.L1 = L1;
+    pl.omega1 = hs.omega;
+    pl.lv64h = lv64h;
+    pl.lv32h = lv32h;
+}
+
 // the merged down- (leg 0) or up-leg (leg 1) of a one-problem 2D plan
 template <typename T, int K>
 static void launch_merged_k(int leg, const Plan &pl, hipStream_t s, const LevelDev<T> *L)
@@ -910,7 +1044,7 @@ hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_
     }
     g += align256(sizeof(double2) * (size_t)nc * nc) + align256(sizeof(float2) * (size_t)nc * nc);
     g += align256(TailCap<double>::BYTES) + align256(TailCap<float>::BYTES);
-    g += 2 * align256(sizeof(LevelDev<double>) * HH_MAXLEV) + align256(sizeof(ProbDev));
+    g += 4 * align256(sizeof(LevelDev<double>) * HH_MAXLEV) + align256(sizeof(ProbDev));
     const int nch = ceil_div(N, HH_CHUNK), ngr = ceil_div(N, HH_SPAN);
     g += align256(sizeof(Tile) * nch);
     // a mixed-precision solve may continue with the FP64 V-cycle (larger work
@@ -1049,6 +1183,33 @@ hh_status hh_vcycle(const hh_grid *g, hh_prec prec, const void *f, void *u, void
     hh_status st = grid_vplan(gm, prec == HH_C64);
     if (st != HH_OK) return st;
     const Plan &pl = prec == HH_C64 ? gm->vplan32 : gm->vplan64;
+    launch_vcycle(pl, VS_IN, VS_OUT, f, u, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
+    return HH_OK;
+}
+
+// The V-cycle of hh_vcycle with the coarse-level f and e in the device's
+// static scratch array: no device allocation, no stream or event creation, no
+// tile timing; the launches go to `stream` only.
+hh_status hh_vcycle_noalloc(const hh_grid *g, hh_prec prec, const void *f, void *u, void *stream)
+{
+    if (!g || !f || !u) return hh_fail(HH_ERR_ARG, "null argument");
+    if (g->host_only) return hh_fail(HH_ERR_ARG, "grid was built host-only");
+    if (f == u) return hh_fail(HH_ERR_ARG, "f and u must not overlap");
+    if (prec != HH_C128 && prec != HH_C64) return hh_fail(HH_ERR_ARG, "unknown precision %d", (int)prec);
+    if (!g->scratch_ok) return hh_fail(HH_ERR_HIP, "the scratch array of device %d was not found at grid setup", g->device);
+    const bool fp32 = prec == HH_C64;
+    const size_t need = fp32 ? g->scratch_need32 : g->scratch_need64;
+    if (need > HH_SCRATCH_BYTES)
+        return hh_fail(HH_ERR_ARG,
+                       "the coarse levels of this grid need %zu bytes of scratch in %s; the allocation-free V-cycle "
+                       "has %zu (use hh_vcycle)", need, fp32 ? "complex float" : "complex double", HH_SCRATCH_BYTES);
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != g->device)
+        return hh_fail(HH_ERR_ARG, "current device %d is not the grid's device %d", dev, g->device);
+    Plan pl;
+    plan_host_one(pl, g, fp32, fp32 ? (const void *)g->L32s : (const void *)g->L64s, g->L64sh, g->L32sh);
     launch_vcycle(pl, VS_IN, VS_OUT, f, u, (hipStream_t)stream);
     HIPCHK(hipGetLastError());
     return HH_OK;

@@ -23,7 +23,7 @@ BICGSTAB, IDR = 0, 1
 
 # every symbol include/hh.h declares
 EXPORTS = ["hh_setup_grid", "hh_free_grid", "hh_grid_query", "hh_grid_export", "hh_apply_operator", "hh_vcycle",
-           "hh_solve", "hh_solve_batch", "hh_server_create", "hh_submit", "hh_poll", "hh_server_destroy",
+           "hh_vcycle_noalloc", "hh_solve", "hh_solve_batch", "hh_server_create", "hh_submit", "hh_poll", "hh_server_destroy",
            "hh_server_query", "hh_request_footprint", "hh_last_error", "hh_version"]
 
 
@@ -105,6 +105,7 @@ def lib():
         L.hh_grid_export.argtypes = [V, I, I, I, V, ctypes.c_size_t]
         L.hh_apply_operator.argtypes = [V, I, I, V, V, V]
         L.hh_vcycle.argtypes = [V, I, V, V, V]
+        L.hh_vcycle_noalloc.argtypes = [V, I, V, V, V]
         L.hh_solve.argtypes = [V, P(SolveOpts), V, V, P(SolveInfo), V]
         L.hh_solve_batch.argtypes = [P(V), I, P(SolveOpts), P(V), P(V), P(SolveInfo), V]
         L.hh_server_create.argtypes = [P(ServerOpts), P(V)]
@@ -116,7 +117,7 @@ def lib():
         L.hh_last_error.restype = ctypes.c_char_p
         L.hh_version.restype = ctypes.c_char_p
         for name in ["hh_setup_grid", "hh_free_grid", "hh_grid_query", "hh_grid_export", "hh_apply_operator",
-                     "hh_vcycle", "hh_solve", "hh_solve_batch", "hh_server_create", "hh_submit", "hh_poll",
+                     "hh_vcycle", "hh_vcycle_noalloc", "hh_solve", "hh_solve_batch", "hh_server_create", "hh_submit", "hh_poll",
                      "hh_server_destroy", "hh_server_query", "hh_request_footprint"]:
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
@@ -250,6 +251,18 @@ class Grid:
         _need(u, dt, self.N, "u")
         check(lib().hh_vcycle(self.h, C128 if prec == "c128" else C64, ctypes.c_void_p(f.data_ptr()),
                               ctypes.c_void_p(u.data_ptr()), _stream(f)))
+        return u
+
+    def vcycle_noalloc(self, f, prec="c128", out=None):
+        """hh_vcycle_noalloc: the same cycle with the coarse levels in the
+        library's static scratch array (nothing allocated by the call)."""
+        torch = _torch()
+        _need(f, torch.complex128, self.N, "f")
+        dt = torch.complex128 if prec == "c128" else torch.complex64
+        u = torch.empty(self.N, dtype=dt, device=f.device) if out is None else out
+        _need(u, dt, self.N, "u")
+        check(lib().hh_vcycle_noalloc(self.h, C128 if prec == "c128" else C64, ctypes.c_void_p(f.data_ptr()),
+                                      ctypes.c_void_p(u.data_ptr()), _stream(f)))
         return u
 
     def solve(self, b, x=None, x0_given=False, **kw):
