@@ -65,6 +65,11 @@ typedef enum { HH_C128 = 0, HH_C64 = 1 } hh_prec;
 typedef enum { HH_OP_H = 0, HH_OP_M = 1 } hh_op;
 typedef enum { HH_CSG_UNIFORM = 0, HH_CSG_INTERIOR = 1 } hh_csg_mode;
 typedef enum { HH_METHOD_BICGSTAB = 0, HH_METHOD_IDR = 1 } hh_method;
+/* Unknowns at cell centres (Sec. 6: the experiments' topology; the Dirichlet
+ * ends lo/hi are half a cell beyond the first/last unknown) or at the
+ * vertices of a uniform grid (Sec. 3, eq. (ecsgrid): n unknowns between the
+ * end nodes lo and hi, width (hi - lo)/(n + 1)). */
+typedef enum { HH_CELL = 0, HH_VERTEX = 1 } hh_centering;
 
 /* Grid description (host memory, read during hh_setup_grid only). */
 typedef struct {
@@ -76,8 +81,12 @@ typedef struct {
     double theta_ecs;       /* ECS angle theta_gamma of H, in (0, pi/2)                  */
     double theta_csg;       /* CSG angle theta_beta of M, in (0, pi/2)                   */
     int32_t csg_mode;       /* hh_csg_mode                                               */
+    int32_t centering;      /* hh_centering.  HH_VERTEX grids have one level and
+                               support hh_apply_operator only (the closed-form
+                               eigenpairs of Sec. 3 are on this grid); every
+                               multigrid or solve call rejects them with HH_ERR_ARG */
     int32_t levels;         /* multigrid levels; 0 = halve while every side is even and
-                               the largest side exceeds 16 (2D) / 8 (3D)                 */
+                               the largest side exceeds 16 (2D) / 8 (3D); HH_VERTEX: 0 or 1 */
     int32_t nu1, nu2;       /* smoothing steps; the library supports (1,1)               */
     double omega;           /* Jacobi weight, e.g. 0.8                                   */
     const double *phi;      /* host, prod(n) reals: k(x)^2 at the cell centres; NULL ->
@@ -94,8 +103,10 @@ typedef struct hh_grid hh_grid;   /* opaque */
  * (Sec. 3, eq. (shortwell); M by Sec. 5.3, eq. (CSL-CSG) / (lapctucsg)),
  * the coarse phi hierarchy (mean of children) and the explicit inverse of
  * the coarsest M (dense LU with partial pivoting), and uploads them.
- * Errors: HH_ERR_ARG (dim not 2/3; fewer than 2 levels, given or from the
- * automatic rule; side not divisible by 2^(levels-1); coarsest grid above
+ * A vertex-centred grid gets the level-0 coefficients and phi only.
+ * Errors: HH_ERR_ARG (dim not 2/3; unknown centering; fewer than 2 levels
+ * on a cell-centred grid, given or from the automatic rule, more than 1 on a
+ * vertex-centred one; side not divisible by 2^(levels-1); coarsest grid above
  * 1024 unknowns; theta outside (0, pi/2); a, b outside
  * [lo, hi]; nu1/nu2 other than 1; singular coarse matrix), HH_ERR_OOM,
  * HH_ERR_HIP.  *out is set only on HH_OK. */

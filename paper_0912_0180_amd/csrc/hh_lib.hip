@@ -172,12 +172,12 @@ hh_status grid_upload(hh_grid *g)
     // host staging of every array, then one copy each
     std::vector<float2> tmp;
     auto put64 = [&](const void *dst, const void *src, size_t bytes) {
-        return hipMemcpy((void *)dst, src, bytes, hipMemcpyHostToDevice);
+        return bytes ? hipMemcpy((void *)dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
     };
     auto put32c = [&](const float2 *dst, const std::vector<double2> &src) {
         tmp.resize(src.size());
         for (size_t i = 0; i < src.size(); ++i) { tmp[i].x = (float)src[i].x; tmp[i].y = (float)src[i].y; }
-        return hipMemcpy((void *)dst, tmp.data(), sizeof(float2) * tmp.size(), hipMemcpyHostToDevice);
+        return tmp.empty() ? hipSuccess : hipMemcpy((void *)dst, tmp.data(), sizeof(float2) * tmp.size(), hipMemcpyHostToDevice);
     };
     for (int a = 0; a < hs.dim; ++a) {
         HIPCHK(put64(g->aH[a], hs.aH[a].data(), sizeof(double2) * hs.aH[a].size()));
@@ -404,6 +404,10 @@ int tail_level(const HostSetup &hs, bool fp32)
 // t + i's phi in 16-byte units) << 16 | (its length in 16-byte units).
 std::vector<char> tail_image(const HostSetup &hs, bool fp32, std::vector<uint32_t> *seg)
 {
+    if (hs.nlev < 2) {   // a one-level (vertex-centred) grid has no V-cycle
+        if (seg) seg->clear();
+        return std::vector<char>();
+    }
     const int t = tail_level(hs, fp32);
     const size_t cb = fp32 ? sizeof(float2) : sizeof(double2), rb = fp32 ? sizeof(float) : sizeof(double);
     auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
@@ -1019,6 +1023,10 @@ hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_
     int nl = 0, nc = 0;
     hh_status st = desc_check(d, nl, nc, err);
     if (st != HH_OK) return st;
+    if (d->centering != HH_CELL) {
+        err = "a vertex-centred grid cannot be solved (operator apply only)";
+        return HH_ERR_ARG;
+    }
     if (!o) {
         err = "null options";
         return HH_ERR_ARG;
@@ -1179,6 +1187,7 @@ hh_status hh_vcycle(const hh_grid *g, hh_prec prec, const void *f, void *u, void
     if (g->host_only) return hh_fail(HH_ERR_ARG, "grid was built host-only");
     if (f == u) return hh_fail(HH_ERR_ARG, "f and u must not overlap");
     if (prec != HH_C128 && prec != HH_C64) return hh_fail(HH_ERR_ARG, "unknown precision %d", (int)prec);
+    if (g->hs.centering != HH_CELL) return hh_fail(HH_ERR_ARG, "a vertex-centred grid has no multigrid hierarchy");
     hh_grid *gm = const_cast<hh_grid *>(g);
     hh_status st = grid_vplan(gm, prec == HH_C64);
     if (st != HH_OK) return st;
@@ -1197,6 +1206,7 @@ hh_status hh_vcycle_noalloc(const hh_grid *g, hh_prec prec, const void *f, void 
     if (g->host_only) return hh_fail(HH_ERR_ARG, "grid was built host-only");
     if (f == u) return hh_fail(HH_ERR_ARG, "f and u must not overlap");
     if (prec != HH_C128 && prec != HH_C64) return hh_fail(HH_ERR_ARG, "unknown precision %d", (int)prec);
+    if (g->hs.centering != HH_CELL) return hh_fail(HH_ERR_ARG, "a vertex-centred grid has no multigrid hierarchy");
     if (!g->scratch_ok) return hh_fail(HH_ERR_HIP, "the scratch array of device %d was not found at grid setup", g->device);
     const bool fp32 = prec == HH_C64;
     const size_t need = fp32 ? g->scratch_need32 : g->scratch_need64;

@@ -179,6 +179,7 @@ hh_status desc_check(const hh_grid_desc *d, int &levels, int &coarse, std::strin
     if (!(d->theta_ecs > 0.0 && d->theta_ecs < half_pi)) { err = "theta_ecs must lie in (0, pi/2)"; return HH_ERR_ARG; }
     if (!(d->theta_csg > 0.0 && d->theta_csg < half_pi)) { err = "theta_csg must lie in (0, pi/2)"; return HH_ERR_ARG; }
     if (d->csg_mode != HH_CSG_UNIFORM && d->csg_mode != HH_CSG_INTERIOR) { err = "csg_mode must be 0 or 1"; return HH_ERR_ARG; }
+    if (d->centering != HH_CELL && d->centering != HH_VERTEX) { err = "centering must be 0 (cell) or 1 (vertex)"; return HH_ERR_ARG; }
     if (d->nu1 != 1 || d->nu2 != 1) { err = "only the V(1,1) cycle is supported (nu1 = nu2 = 1)"; return HH_ERR_ARG; }
     if (!(d->omega > 0.0 && d->omega < 2.0)) { err = "omega must lie in (0, 2)"; return HH_ERR_ARG; }
     int64_t N = 1;
@@ -193,6 +194,13 @@ hh_status desc_check(const hh_grid_desc *d, int &levels, int &coarse, std::strin
     }
     // the finaliser stages at most 64 blocks of HH_FIN_STAGE chunk partials
     if (N > ((int64_t)1 << 28)) { err = "more than 2^28 unknowns"; return HH_ERR_ARG; }
+    if (d->centering == HH_VERTEX) {
+        // the operator of Sec. 3 on its vertex grid: no multigrid hierarchy
+        if (d->levels > 1) { err = "a vertex-centred grid has one level (levels 0 or 1)"; return HH_ERR_ARG; }
+        levels = 1;
+        coarse = 0;
+        return HH_OK;
+    }
     const int nl = d->levels > 0 ? d->levels : auto_levels(dim, d->n);
     if (nl > HH_MAXLEV) { err = "too many levels"; return HH_ERR_ARG; }
     if (nl < 2) { err = "the multigrid preconditioner needs at least 2 levels (set levels, or use a larger grid)"; return HH_ERR_ARG; }
@@ -225,6 +233,8 @@ hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err)
     hs.dim = dim;
     hs.nlev = nl;
     hs.omega = d->omega;
+    hs.centering = d->centering;
+    const bool vertex = d->centering == HH_VERTEX;
     const double cg = std::cos(d->theta_ecs), sg = std::sin(d->theta_ecs);
     const double cb = std::cos(d->theta_csg), sb = std::sin(d->theta_csg);
     for (int l = 0; l < nl; ++l) {
@@ -236,10 +246,18 @@ hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err)
         }
         for (int a = 0; a < dim; ++a) {
             const int n = L.n[a];
-            const double lo = d->lo[a], hi = d->hi[a], h = (hi - lo) / (double)n;
+            // real nodes: the two Dirichlet ends and the n unknowns between
+            // them, at cell centres or at the vertices of n + 1 equal intervals
+            const double lo = d->lo[a], hi = d->hi[a];
             std::vector<double> x(n + 2);
             x[0] = lo;
-            for (int j = 1; j <= n; ++j) x[j] = lo + ((double)j - 0.5) * h;
+            if (vertex) {
+                const double h = (hi - lo) / (double)(n + 1);
+                for (int j = 1; j <= n; ++j) x[j] = lo + (double)j * h;
+            } else {
+                const double h = (hi - lo) / (double)n;
+                for (int j = 1; j <= n; ++j) x[j] = lo + ((double)j - 0.5) * h;
+            }
             x[n + 1] = hi;
             std::vector<double2> zH(n + 2), zM(n + 2);
             for (int j = 0; j <= n + 1; ++j) {
@@ -274,9 +292,10 @@ hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err)
                     }
         }
     }
-    // coarsest inverse
+    // coarsest inverse (a vertex-centred grid has no hierarchy)
     const int n = (int)Nc;
     hs.Nc = n;
+    if (vertex) return HH_OK;
     std::vector<double2> A((size_t)n * n), e(n), col(n);
     for (int q = 0; q < n; ++q) {
         for (int p = 0; p < n; ++p) e[p] = cmk<double>(p == q ? 1.0 : 0.0, 0.0);

@@ -16,6 +16,7 @@ struct HostLevel {
 
 struct HostSetup {
     int dim = 2, nlev = 1;
+    int centering = HH_CELL;                    // HH_VERTEX: one level, no hierarchy
     double omega = 0.8;
     std::vector<double2> aH[3], cH[3], dH[3];   // finest level, ECS operator
     HostLevel lev[HH_MAXLEV];

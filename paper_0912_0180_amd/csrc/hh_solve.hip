@@ -466,6 +466,7 @@ hh_status check_solve_opts(const hh_grid *g, const hh_solve_opts *o)
     if (!(o->tol > 0.0) || o->max_matvec < 1 || o->max_restarts < 0) return hh_fail(HH_ERR_ARG, "need tol > 0, max_matvec >= 1, max_restarts >= 0");
     if (o->vcycle_prec != HH_C128 && o->vcycle_prec != HH_C64) return hh_fail(HH_ERR_ARG, "unknown vcycle precision");
     if (g->host_only) return hh_fail(HH_ERR_ARG, "grid was built host-only");
+    if (g->hs.centering != HH_CELL) return hh_fail(HH_ERR_ARG, "a vertex-centred grid cannot be solved (operator apply only)");
     return HH_OK;
 }
 

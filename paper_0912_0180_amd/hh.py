@@ -37,7 +37,7 @@ class GridDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3),
                 ("hi", ctypes.c_double * 3), ("a", ctypes.c_double * 3), ("b", ctypes.c_double * 3),
                 ("theta_ecs", ctypes.c_double), ("theta_csg", ctypes.c_double), ("csg_mode", ctypes.c_int32),
-                ("levels", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
+                ("centering", ctypes.c_int32), ("levels", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("phi", ctypes.c_void_p), ("phi_const", ctypes.c_double),
                 ("host_only", ctypes.c_int32)]
 
@@ -151,6 +151,7 @@ def make_desc(desc, phi=None, host_only=False):
     d.theta_ecs = float(desc.get("theta_ecs", math.pi / 6))
     d.theta_csg = float(desc.get("theta_csg", math.pi / 8))
     d.csg_mode = int(desc.get("csg_mode", 0))
+    d.centering = int(desc.get("centering", 0))
     d.levels = int(desc.get("levels", 0))
     d.nu1 = int(desc.get("nu1", 1))
     d.nu2 = int(desc.get("nu2", 1))

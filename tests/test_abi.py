@@ -147,3 +147,35 @@ def test_request_footprint_bounds():
     with pytest.raises(hh.HHError) as e:
         hh.request_footprint(bad)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_vertex_grid_host_setup_equals_oracle(oracle_mod, dim):
+    """The vertex-centred grid of Sec. 3 (eq. (ecsgrid)): one level, node
+    widths (hi - lo)/(n + 1); its H and M coefficients equal the oracle's."""
+    n = {2: (12, 10), 3: (6, 5, 7)}[dim]
+    d = W.base_desc(dim, n, (-0.3,) * dim, (1.3,) * dim, (0.0,) * dim, (1.0,) * dim, centering=1, levels=1)
+    phi = np.random.default_rng(dim).uniform(10.0, 20.0, size=int(np.prod(n)))
+    g = host_grid(d, phi)
+    o = oracle_mod.Grid(d, phi)
+    assert g.levels == 1 == o.nlev
+    for ax in range(dim):
+        for w in ("aM", "cM", "dM", "aH", "cH", "dH"):
+            assert np.array_equal(g.export(w, 0, ax).view(np.float64), o.coeffs(0, ax, w).view(np.float64)), (ax, w)
+    assert np.array_equal(g.export("phi", 0), o.phi(0))
+
+
+def test_vertex_grid_validation():
+    d = W.base_desc(2, (12, 10), (0.0, 0.0), (1.0, 1.0), (0.0, 0.0), (1.0, 1.0), centering=1, levels=2)
+    with pytest.raises(hh.HHError):
+        host_grid(d)
+    d["levels"] = 0
+    g = host_grid(d)
+    assert g.levels == 1 and g.Nc == 0
+    d["centering"] = 2
+    with pytest.raises(hh.HHError):
+        host_grid(d)
+    d["centering"] = 1
+    with pytest.raises(hh.HHError) as ei:
+        hh.request_footprint(d)
+    assert "vertex" in str(ei.value)
