@@ -185,6 +185,54 @@ def c4(count=64, seed=4, sides=(256, 384, 512, 768, 1024)):
     return probs
 
 
+def mp_grid(n_int, n_lay, r, theta_csg=PI / 8, levels=0):
+    """The grid of the paper's model problems 2 and 3 (Sec. 4, eq. (BC)): the
+    square (0, r)^2 with n_int cells of width h = r / n_int per axis,
+    homogeneous Dirichlet on the south and west edges (x = 0, y = 0: no layer,
+    a = lo = 0) and an ECS layer of n_lay cells on the north and east edges."""
+    h = r / n_int
+    n = n_int + n_lay
+    hi = r + n_lay * h
+    return base_desc(2, (n, n), (0.0, 0.0), (hi, hi), (0.0, 0.0), (r, r), theta_csg=theta_csg, levels=levels)
+
+
+def mp2(nu=7.0, k=2.0, n_int=384, n_lay=128, r=50.0, theta_csg=PI / 8, levels=0):
+    """Model problem 2 (Sec. 4, eq. (MP2)): phi = nu (e^{-x^2} + e^{-y^2}) + k^2,
+    chi = e^{-(x^2 + y^2)}, on the mp_grid; the paper's sizes are 384 interior
+    + 128 layer cells for r = 50 (nu = 7, k = 2 and nu = 1, k = 4).  phi and
+    chi are sampled at the real cell centres (layer cells included)."""
+    d = mp_grid(n_int, n_lay, r, theta_csg, levels)
+    X, Y = mesh(d)
+    phi = flat(nu * (np.exp(-X * X) + np.exp(-Y * Y)) + k * k)
+    b = flat(np.exp(-(X * X + Y * Y))).astype(np.complex128)
+    return {"name": "mp2", "desc": d, "phi": phi, "b": b, "k0": k, "nu": nu, "r": r,
+            "method": "bicgstab", "tol": 1e-8}
+
+
+def mp3(r=90.0, k=2.0, n_int=1024, n_lay=256, theta_csg=PI / 8, levels=0):
+    """Model problem 3 (Sec. 4, eq. (MP3)): phi = 1/x + 1/y + k^2, chi =
+    e^{-(x^2 + y^2)}, on the mp_grid; the paper's sizes are 1024 interior +
+    256 layer cells for r = 90, k = 2 (2048 + 512 for r = 150, k = 4).  The
+    cell centres never reach the singularity at the origin: the largest phi
+    is at the first centre (h/2, h/2), as in the paper's mesh-width bound."""
+    d = mp_grid(n_int, n_lay, r, theta_csg, levels)
+    X, Y = mesh(d)
+    phi = flat(1.0 / X + 1.0 / Y + k * k)
+    b = flat(np.exp(-(X * X + Y * Y))).astype(np.complex128)
+    return {"name": "mp3", "desc": d, "phi": phi, "b": b, "k0": k, "r": r, "method": "bicgstab", "tol": 1e-8}
+
+
+def mp_max_mesh_width(problem, k, nu=0.0):
+    """Largest mesh width with kh < 0.625 at the largest discrete wave number
+    (Sec. 6.2): MP2 takes phi's supremum at the origin, 2 nu + k^2; MP3 takes
+    phi at the first cell centre (h/2, h/2), 4/h + k^2, which gives the
+    quadratic k^2 h^2 + 4 h - 0.625^2 = 0."""
+    c = 0.625
+    if problem == "mp2":
+        return c / math.sqrt(2.0 * nu + k * k)
+    return (-4.0 + math.sqrt(16.0 + 4.0 * k * k * c * c)) / (2.0 * k * k)
+
+
 def serving_request(g, frac3d=0.25):
     """One request of the serving mix: 75% 2D with side in {256, 320, ...,
     2048}, 25% 3D with side in {64, 96, 128, 160} and layers of side/8;
