@@ -10,11 +10,14 @@ preconditioner application, Bi-CGSTAB.  `value` is solves/s of the
 mixed-precision solve (complex-FP32 V-cycle, FP64 Krylov).
 
 Reported beside it: the FP64 solve, V-cycle and operator bandwidths, the
-roofline of the operator-apply kernel, the 3D 128^3 solves (IDR(4) and
-Bi-CGSTAB), the 64-problem batched solve, a bounded sample of the serving
-stream, and the CPU oracle on a bounded sample of the headline solve.
+roofline of the dominant bandwidth-bound kernel of the solve (the finest
+up-leg of the V-cycle, timed on the same recipe at 4096^2 so its data comes
+from HBM), the 3D 128^3 solves (IDR(4) and Bi-CGSTAB), the 64-problem batched
+solve, the serving stream, and the CPU oracle on a bounded sample of the
+headline solve.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--no-cpu-baseline]
+                    [--roofline-only] [--pmc-probe]
 
 Prints one JSON line.
 """
@@ -33,7 +36,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 # HBM traffic of the roofline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs (see the file); valid only while the kernel sources are unchanged
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_applyH_band_2d_1024_pmc.md")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_vup_finest_2d_4096_pmc.md")
+# side of the HBM-resident grid the roofline kernel is measured on: the
+# headline recipe at 4x the side, so one launch of the finest up-leg touches
+# ~500 MB, twice the 256 MB Infinity Cache
+ROOFLINE_N = 4096
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0912_0180_amd", "csrc", f) for f in ("hh_kernels.hpp", "hh_common.h")]
 
 
@@ -89,6 +96,19 @@ def vcycle_bytes(g, fp32):
 def apply_bytes(g):
     """y = H x in FP64 with variable k: x and y (16 B each) and phi (8 B)."""
     return 40 * g.N
+
+
+def leg_bytes(g, fp32):
+    """Algorithmic bytes of one launch of the finest level's fused legs.
+    Down-leg: read f (the FP64 Krylov vector, 16 B) and phi, write the
+    restricted f of level 1.  Up-leg: read f and phi again and level 1's e,
+    write u (the preconditioned vector, c64 in mixed precision)."""
+    cb = 8 if fp32 else 16
+    pb = 4 if fp32 else 8
+    nc = g.N // (2 ** g.dim)
+    down = g.N * (16 + pb) + nc * cb
+    up = g.N * (16 + pb) + nc * cb + g.N * cb
+    return down, up
 
 
 def time_calls(torch, fn, reps):
@@ -211,13 +231,59 @@ def bench_c2(args, torch, hh, W, out):
     out["vcycle_GBps_mixed"] = vcycle_bytes(g, True) / tv32 / 1e9
     ah = apply_bytes(g) / th / 1e9
     out["applyH_us"] = th * 1e6
-    out["roofline"] = {"bound": "hbm", "kernel": "hh::k_applyH_band (y = H x, 2D rows of 256k, c128, variable k)",
-                       "achieved": ah, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ah / HBM_PEAK_GBPS,
-                       "traffic": measured_traffic(), "bytes_per_unknown": 40, "unknowns_per_launch": g.N,
-                       "algorithmic_bytes_per_launch": apply_bytes(g), "launch_us": th * 1e6,
-                       "timing": "HIP events around three replays of a graph of 200 launches"
-                       if how == "graph" else "HIP events around 200 eager launches"}
+    out["applyH_GBps"] = ah
+    # the finest legs as the timed solve launches them, at this (cache-resident) size
+    prof = g.profile_vcycle(f, "c64", reps=100, out=u32)
+    db, ub = leg_bytes(g, True)
+    out["finest_legs_mixed"] = {"down_us": prof["down_us"], "up_us": prof["up_us"],
+                                "down_GBps": db / prof["down_us"] / 1e3, "up_GBps": ub / prof["up_us"] / 1e3,
+                                "down_shape": prof["down_shape"], "up_shape": prof["up_shape"],
+                                "working_set_MB": (ub + db) / 1e6,
+                                "note": "1024^2: the vectors stay in the 256 MB Infinity Cache between launches"}
     return cfg, g
+
+
+def bench_roofline(args, torch, hh, W, out):
+    """The dominant bandwidth-bound kernel of the timed solve, the finest
+    up-leg k_vup (prolongation + correction + post-smoothing, FP32 V-cycle,
+    FP64 input), measured on the headline recipe at ROOFLINE_N^2 so every
+    launch streams from HBM: HIP events on the launch stream around 100
+    back-to-back launches (hh_profile_vcycle), algorithmic bytes from
+    leg_bytes.  The finest down-leg and the whole V-cycle are reported beside
+    it, in both precisions."""
+    n = args.roofline_n
+    cfg = W.c2(n=n, levels=int(round(np.log2(n))) - 2)
+    g = hh.Grid(cfg["desc"], cfg["phi"])
+    f = torch.randn(g.N, dtype=torch.complex128, device="cuda")
+    res = {}
+    for prec in ("c64", "c128"):
+        u = torch.empty(g.N, dtype=torch.complex64 if prec == "c64" else torch.complex128, device="cuda")
+        prof = g.profile_vcycle(f, prec, reps=100, out=u)
+        db, ub = leg_bytes(g, prec == "c64")
+        vb = vcycle_bytes(g, prec == "c64")
+        res[prec] = {"down_us": prof["down_us"], "up_us": prof["up_us"], "vcycle_us": prof["vcycle_us"],
+                     "down_GBps": db / prof["down_us"] / 1e3, "up_GBps": ub / prof["up_us"] / 1e3,
+                     "vcycle_GBps": vb / prof["vcycle_us"] / 1e3,
+                     "down_shape": prof["down_shape"], "up_shape": prof["up_shape"],
+                     "up_groups": prof["up_groups"], "down_groups": prof["down_groups"]}
+        del u
+    m = res["c64"]
+    _, ub = leg_bytes(g, True)
+    ach = ub / m["up_us"] / 1e3
+    out["roofline"] = {
+        "bound": "hbm",
+        "kernel": "hh::k_vup<2, float, double2, float2, %d> (finest-level fused up-leg of the FP32 V-cycle: "
+                  "bilinear prolongation + correction + weighted-Jacobi post-smoothing; the same template runs "
+                  "twice per Bi-CGSTAB iteration of the timed solve, shape %d at 1024^2)"
+                  % (m["up_shape"], out.get("finest_legs_mixed", {}).get("up_shape", -1)),
+        "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS,
+        "traffic": measured_traffic(), "bytes_per_unknown": 30, "unknowns_per_launch": g.N,
+        "algorithmic_bytes_per_launch": ub, "launch_us": m["up_us"],
+        "working_set": "2D %d^2 (headline recipe at 4x the side): %.0f MB read and written per launch, "
+                       "beyond the 256 MB Infinity Cache" % (n, ub / 1e6),
+        "timing": "HIP events on the launch stream around 100 back-to-back launches (hh_profile_vcycle)"}
+    out["hbm_resident_%d" % n] = res
+    g.close()
 
 
 # --------------------------------------------------------------------------
@@ -250,7 +316,7 @@ def bench_c3(args, torch, hh, W):
     u32 = torch.empty(g.N, dtype=torch.complex64, device="cuda")
     y = torch.empty_like(f)
     tv = time_calls(torch, lambda: g.vcycle(f, "c64", out=u32), 50)
-    th = time_calls(torch, lambda: g.apply(f, "H", out=y), 100)
+    th, _ = time_calls_graph(torch, lambda: g.apply(f, "H", out=y), 100)
     res["vcycle_us_mixed"] = tv * 1e6
     res["vcycle_GBps_mixed"] = vcycle_bytes(g, True) / tv / 1e9
     res["applyH_GBps"] = apply_bytes(g) / th / 1e9
@@ -378,20 +444,29 @@ def cpu_baseline(args, cfg, out):
     ts = time.perf_counter() - t
     full_mv = out.get("matvecs_fp64", out["matvecs_mixed"])
     est = ts / io["matvecs"] * full_mv
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     out["cpu_baseline"] = {"value": 1.0 / est, "unit": "solves/s", "cores": O.num_threads(), "kind": "oracle",
+                           "cpu_model": cpu,
                            "sample": "FP64 oracle Bi-CGSTAB on the headline problem, first %d matvecs in %.1f s, "
                                      "scaled to the %d matvecs of the full FP64 solve" % (io["matvecs"], ts, full_mv)}
 
 
-def pmc_probe(torch, hh, W):
-    """Launches for counter runs: 10 operator applies at the headline size
-    and 10 elementwise copies of 512 MiB (the calibration kernel)."""
-    cfg = W.c2()
+def pmc_probe(torch, hh, W, n):
+    """Launches for counter runs: the mixed V-cycle profile at n^2 (its 10
+    back-to-back launches of the finest up-leg are the roofline kernel's) and
+    10 elementwise copies of 512 MiB (the calibration kernel)."""
+    cfg = W.c2(n=n, levels=int(round(np.log2(n))) - 2)
     g = hh.Grid(cfg["desc"], cfg["phi"])
     f = torch.randn(g.N, dtype=torch.complex128, device="cuda")
-    y = torch.empty_like(f)
-    for _ in range(10):
-        g.apply(f, "H", out=y)
+    u = torch.empty(g.N, dtype=torch.complex64, device="cuda")
+    prof = g.profile_vcycle(f, "c64", reps=10, out=u)
     # calibration: an elementwise kernel reading and writing 512 MiB, over two
     # buffer pairs in turn so every source was last touched 1 GiB of traffic
     # earlier (beyond L2 and the Infinity Cache)
@@ -401,7 +476,8 @@ def pmc_probe(torch, hh, W):
     for i in range(10):
         torch.mul(xs[i % 2], 1, out=ys[i % 2])
     torch.cuda.synchronize()
-    print("pmc probe: 10 x k_applyH_band on %d unknowns, 10 x elementwise copy of %d bytes" % (g.N, 4 * n), flush=True)
+    print("pmc probe: 10 x finest up-leg (shape %d) on %d unknowns, 10 x elementwise copy of %d bytes"
+          % (prof["up_shape"], g.N, 4 * n), flush=True)
 
 
 def main():
@@ -421,6 +497,8 @@ def main():
     ap.add_argument("--cpu-sample-matvecs", type=int, default=300)
     ap.add_argument("--quick", action="store_true", help="headline solve only")
     ap.add_argument("--pmc-probe", action="store_true", help="only the launches the counter runs read")
+    ap.add_argument("--roofline-n", type=int, default=ROOFLINE_N, help="side of the HBM-resident roofline grid")
+    ap.add_argument("--roofline-only", action="store_true", help="only the roofline measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the solver runs on one GPU only (multi-GPU sharding is described, not "
@@ -433,12 +511,19 @@ def main():
 
     torch.cuda.set_device(0)
     if args.pmc_probe:
-        pmc_probe(torch, hh, W)
+        pmc_probe(torch, hh, W, args.roofline_n)
         return
     out = {}
+    if args.roofline_only:
+        bench_roofline(args, torch, hh, W, out)
+        print(json.dumps(out), flush=True)
+        return
     skip = set(s for s in args.skip.split(",") if s)
     cfg, g = bench_c2(args, torch, hh, W, out)
     g.close()
+    if not args.quick:
+        print("bench: roofline", file=sys.stderr, flush=True)
+        bench_roofline(args, torch, hh, W, out)
     if not args.quick:
         if "c3" not in skip:
             print("bench: c3", file=sys.stderr, flush=True)

@@ -150,6 +150,24 @@ hh_status hh_apply_operator(const hh_grid *g, hh_op op, hh_prec prec, const void
  * HH_ERR_OOM (plan allocation), HH_ERR_HIP. */
 hh_status hh_vcycle(const hh_grid *g, hh_prec prec, const void *f, void *u, void *stream);
 
+/* Timing of the preconditioner application (Sec. 6.2: one V-cycle per
+ * matvec) and of the two kernels that carry most of its traffic, the fused
+ * down-leg and up-leg of the finest level, launched exactly as hh_vcycle and
+ * the solves launch them.  Times are averages, from HIP events on `stream`,
+ * over `reps` back-to-back cycles and then `reps` back-to-back launches of
+ * each leg.  f, u as for hh_vcycle; u is overwritten.  Builds the V-cycle
+ * plan like hh_vcycle; creates and destroys six events; synchronises the
+ * stream.  Errors: as hh_vcycle, and HH_ERR_ARG for reps < 1 or a null out. */
+typedef struct {
+    double vcycle_us;               /* one whole V(1,1) cycle                          */
+    double down_us, up_us;          /* one launch of the finest down-leg / up-leg      */
+    int32_t down_shape, up_shape;   /* tile shapes of those launches (index into the
+                                       library's set)                                  */
+    int32_t down_groups, up_groups; /* workgroups per launch                           */
+} hh_vcycle_profile;
+hh_status hh_profile_vcycle(const hh_grid *g, hh_prec prec, const void *f, void *u, int32_t reps,
+                            hh_vcycle_profile *out, void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * V-cycle as hh_vcycle, same kernels and results, but the restricted

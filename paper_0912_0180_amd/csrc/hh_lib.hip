@@ -1225,6 +1225,65 @@ hh_status hh_vcycle_noalloc(const hh_grid *g, hh_prec prec, const void *f, void 
     return HH_OK;
 }
 
+// Times the grid's V-cycle and its finest level's fused legs with HIP events
+// on `stream`: `reps` back-to-back cycles, then `reps` back-to-back launches of
+// the finest down-leg and of the finest up-leg, each leg exactly as the cycle
+// (and a solve's plan) launches it.
+hh_status hh_profile_vcycle(const hh_grid *g, hh_prec prec, const void *f, void *u, int32_t reps,
+                            hh_vcycle_profile *out, void *stream)
+{
+    if (!g || !f || !u || !out) return hh_fail(HH_ERR_ARG, "null argument");
+    if (g->host_only) return hh_fail(HH_ERR_ARG, "grid was built host-only");
+    if (f == u) return hh_fail(HH_ERR_ARG, "f and u must not overlap");
+    if (prec != HH_C128 && prec != HH_C64) return hh_fail(HH_ERR_ARG, "unknown precision %d", (int)prec);
+    if (g->hs.centering != HH_CELL) return hh_fail(HH_ERR_ARG, "a vertex-centred grid has no multigrid hierarchy");
+    if (reps < 1) return hh_fail(HH_ERR_ARG, "reps must be at least 1");
+    const bool fp32 = prec == HH_C64;
+    hh_grid *gm = const_cast<hh_grid *>(g);
+    hh_status st = grid_vplan(gm, fp32);
+    if (st != HH_OK) return st;
+    const Plan &pl = fp32 ? gm->vplan32 : gm->vplan64;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[6] = {};
+    for (int i = 0; i < 6; ++i) {
+        hipError_t e = hipEventCreate(&ev[i]);
+        if (e != hipSuccess) {
+            for (int k = 0; k < i; ++k) (void)hipEventDestroy(ev[k]);
+            return hh_fail(HH_ERR_HIP, "hipEventCreate: %s", hipGetErrorString(e));
+        }
+    }
+    LvHost lh;
+    lh.d = pl.lv64h;
+    lh.f = pl.lv32h;
+    const Ctx cd = ctx_of(pl, pl.down[0]), cu = ctx_of(pl, pl.up[0]);
+    launch_vcycle(pl, VS_IN, VS_OUT, f, u, s);   // warm-up; leaves every level's f and e valid
+    hipError_t e = hipEventRecord(ev[0], s);
+    for (int r = 0; r < reps; ++r) launch_vcycle(pl, VS_IN, VS_OUT, f, u, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) e = hipEventRecord(ev[2], s);
+    for (int r = 0; r < reps; ++r)
+        launch_leg_any(g->hs.dim, fp32, 0, pl.vdv[0], pl.down[0].n, s, cd, 0, VS_IN, VS_OUT, f, u, lh);
+    if (e == hipSuccess) e = hipEventRecord(ev[3], s);
+    if (e == hipSuccess) e = hipEventRecord(ev[4], s);
+    for (int r = 0; r < reps; ++r)
+        launch_leg_any(g->hs.dim, fp32, 1, pl.vuv[0], pl.up[0].n, s, cu, 0, VS_IN, VS_OUT, f, u, lh);
+    if (e == hipSuccess) e = hipEventRecord(ev[5], s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
+    float ms[3] = {0.f, 0.f, 0.f};
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventElapsedTime(&ms[i], ev[2 * i], ev[2 * i + 1]);
+    for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+    if (e != hipSuccess) return hh_fail(HH_ERR_HIP, "V-cycle profile: %s", hipGetErrorString(e));
+    out->vcycle_us = 1e3 * ms[0] / reps;
+    out->down_us = 1e3 * ms[1] / reps;
+    out->up_us = 1e3 * ms[2] / reps;
+    out->down_shape = pl.vdv[0];
+    out->up_shape = pl.vuv[0];
+    out->down_groups = pl.down[0].n;
+    out->up_groups = pl.up[0].n;
+    return HH_OK;
+}
+
 } // extern "C"
 
 hh_status grid_vplan(hh_grid *g, bool fp32)

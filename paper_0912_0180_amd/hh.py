@@ -23,7 +23,7 @@ BICGSTAB, IDR = 0, 1
 
 # every symbol include/hh.h declares
 EXPORTS = ["hh_setup_grid", "hh_free_grid", "hh_grid_query", "hh_grid_export", "hh_apply_operator", "hh_vcycle",
-           "hh_vcycle_noalloc", "hh_solve", "hh_solve_batch", "hh_server_create", "hh_submit", "hh_poll", "hh_server_destroy",
+           "hh_vcycle_noalloc", "hh_profile_vcycle", "hh_solve", "hh_solve_batch", "hh_server_create", "hh_submit", "hh_poll", "hh_server_destroy",
            "hh_server_query", "hh_request_footprint", "hh_last_error", "hh_version"]
 
 
@@ -58,6 +58,15 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("matvecs", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("restarts", ctypes.c_int32), ("rel_res_recurrence", ctypes.c_double),
                 ("rel_res_true", ctypes.c_double), ("seconds", ctypes.c_double), ("fp64_fallback", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class VcycleProfile(ctypes.Structure):
+    _fields_ = [("vcycle_us", ctypes.c_double), ("down_us", ctypes.c_double), ("up_us", ctypes.c_double),
+                ("down_shape", ctypes.c_int32), ("up_shape", ctypes.c_int32), ("down_groups", ctypes.c_int32),
+                ("up_groups", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -106,6 +115,7 @@ def lib():
         L.hh_apply_operator.argtypes = [V, I, I, V, V, V]
         L.hh_vcycle.argtypes = [V, I, V, V, V]
         L.hh_vcycle_noalloc.argtypes = [V, I, V, V, V]
+        L.hh_profile_vcycle.argtypes = [V, I, V, V, I, P(VcycleProfile), V]
         L.hh_solve.argtypes = [V, P(SolveOpts), V, V, P(SolveInfo), V]
         L.hh_solve_batch.argtypes = [P(V), I, P(SolveOpts), P(V), P(V), P(SolveInfo), V]
         L.hh_server_create.argtypes = [P(ServerOpts), P(V)]
@@ -117,7 +127,7 @@ def lib():
         L.hh_last_error.restype = ctypes.c_char_p
         L.hh_version.restype = ctypes.c_char_p
         for name in ["hh_setup_grid", "hh_free_grid", "hh_grid_query", "hh_grid_export", "hh_apply_operator",
-                     "hh_vcycle", "hh_vcycle_noalloc", "hh_solve", "hh_solve_batch", "hh_server_create", "hh_submit", "hh_poll",
+                     "hh_vcycle", "hh_vcycle_noalloc", "hh_profile_vcycle", "hh_solve", "hh_solve_batch", "hh_server_create", "hh_submit", "hh_poll",
                      "hh_server_destroy", "hh_server_query", "hh_request_footprint"]:
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
@@ -265,6 +275,19 @@ class Grid:
         check(lib().hh_vcycle_noalloc(self.h, C128 if prec == "c128" else C64, ctypes.c_void_p(f.data_ptr()),
                                       ctypes.c_void_p(u.data_ptr()), _stream(f)))
         return u
+
+    def profile_vcycle(self, f, prec="c64", reps=50, out=None):
+        """hh_profile_vcycle: average microseconds of one V-cycle and of one
+        launch of the finest level's down- and up-leg kernels."""
+        torch = _torch()
+        _need(f, torch.complex128, self.N, "f")
+        dt = torch.complex128 if prec == "c128" else torch.complex64
+        u = torch.empty(self.N, dtype=dt, device=f.device) if out is None else out
+        _need(u, dt, self.N, "u")
+        r = VcycleProfile()
+        check(lib().hh_profile_vcycle(self.h, C128 if prec == "c128" else C64, ctypes.c_void_p(f.data_ptr()),
+                                      ctypes.c_void_p(u.data_ptr()), int(reps), ctypes.byref(r), _stream(f)))
+        return r.as_dict()
 
     def solve(self, b, x=None, x0_given=False, **kw):
         torch = _torch()
