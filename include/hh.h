@@ -63,7 +63,23 @@ typedef enum {
 
 typedef enum { HH_C128 = 0, HH_C64 = 1 } hh_prec;
 typedef enum { HH_OP_H = 0, HH_OP_M = 1 } hh_op;
-typedef enum { HH_CSG_UNIFORM = 0, HH_CSG_INTERIOR = 1 } hh_csg_mode;
+/* The preconditioner M: the complex stretched grid with every width times
+ * beta = e^{i theta_csg} (uniform, Sec. 5.3, eq. (CSL-CSG)), with only the
+ * interior widths stretched (interior, eq. (lapctucsg)), or the complex
+ * shifted Laplacian -(Lap + beta^2 phi) of Sec. 5.2, eq. (helmctucsl), with
+ * beta^2 = csl_shift.  The library applies the CSL through eq. (CSL-CSG):
+ * M = M_CSL / beta^2, the uniform stretched grid with beta the principal
+ * square root of the shift (any modulus); the constant factor does not change
+ * the Krylov iterates, and hh_apply_operator(HH_OP_M) returns M_CSL x / beta^2. */
+typedef enum { HH_CSG_UNIFORM = 0, HH_CSG_INTERIOR = 1, HH_CSL = 2 } hh_csg_mode;
+/* Boundary condition of one side of one axis: homogeneous Dirichlet (at the
+ * contour end of a layer, or at the edge), or the first-order Sommerfeld
+ * condition du/dn = -i k_bc u (Sec. 2, eq. (sommerfeld1); Sec. 4, eq. (BC)),
+ * discretised by a ghost node one cell beyond the last unknown and the
+ * centred difference of the condition at the boundary face.  A Sommerfeld
+ * side has no layer (a == lo, resp. b == hi) and needs a cell-centred grid;
+ * the preconditioner takes the condition in its own stretched coordinate. */
+typedef enum { HH_BC_DIRICHLET = 0, HH_BC_SOMMERFELD = 1 } hh_bc;
 typedef enum { HH_METHOD_BICGSTAB = 0, HH_METHOD_IDR = 1 } hh_method;
 /* Unknowns at cell centres (Sec. 6: the experiments' topology; the Dirichlet
  * ends lo/hi are half a cell beyond the first/last unknown) or at the
@@ -79,7 +95,9 @@ typedef struct {
     double a[3], b[3];      /* interior [a,b] per axis (ECS turning points), lo<=a<b<=hi;
                                a == lo (b == hi) means no layer on that side             */
     double theta_ecs;       /* ECS angle theta_gamma of H, in (0, pi/2)                  */
-    double theta_csg;       /* CSG angle theta_beta of M, in (0, pi/2)                   */
+    double theta_csg;       /* CSG angle theta_beta of M, |theta| < pi/2 (negative for
+                               Sommerfeld problems, as in the paper's tables); unused
+                               for HH_CSL                                                */
     int32_t csg_mode;       /* hh_csg_mode                                               */
     int32_t centering;      /* hh_centering.  HH_VERTEX grids have one level and
                                support hh_apply_operator only (the closed-form
@@ -95,6 +113,16 @@ typedef struct {
     int32_t host_only;      /* 1: build the host-side setup only (no device memory);
                                only hh_grid_query / hh_grid_export / hh_free_grid may
                                then be called                                            */
+    /* A zero-filled tail keeps the linear contour, Dirichlet sides and no shift. */
+    double csl_shift[2];    /* HH_CSL: the complex shift beta^2 = (re, im), nonzero; the
+                               paper's tables print -beta^2 (shift -1 - 0.2i is beta^2 =
+                               1 + 0.2i)                                                 */
+    int32_t contour_steps;  /* 0 or 1: linear ECS contour (eq. (lapctuecs)); m > 1: the
+                               contour of each layer turns to theta_ecs in m equal angle
+                               steps over m equal parts of the layer (Sec. 6.2, remark on
+                               a smooth ECS transition)                                  */
+    int32_t bc[3][2];       /* hh_bc per axis, (low side, high side)                     */
+    double k_bc;            /* k of the Sommerfeld condition, > 0 when a side uses it    */
 } hh_grid_desc;
 
 typedef struct hh_grid hh_grid;   /* opaque */

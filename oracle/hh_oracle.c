@@ -15,9 +15,21 @@
  * What is computed, with the passage it follows:
  *   geometry        Sec. 2, eq. (ecstrans) and the linear ECS map of Simon
  *                   (exterior complex scaling): z(x) = r + (x - r) e^{i th}
- *                   on the layer; Sec. 5.3, eq. (CSL-CSG) and eq.
- *                   (lapctucsg): the complex stretched grid (CSG) map of the
- *                   preconditioner, uniform (z -> beta z) or interior-only.
+ *                   on the layer, or (Sec. 6.2, remark on a smooth ECS
+ *                   transition) a contour that turns to th in m equal angle
+ *                   steps over m equal parts of the layer; Sec. 5.3, eq.
+ *                   (CSL-CSG) and eq. (lapctucsg): the complex stretched grid
+ *                   (CSG) map of the preconditioner, uniform (z -> beta z) or
+ *                   interior-only; Sec. 5.2, eq. (helmctucsl): the complex
+ *                   shifted Laplacian -(L + beta^2 phi), taken through eq.
+ *                   (CSL-CSG) as the uniform CSG with beta the principal
+ *                   square root of the shift (M_CSL = beta^2 M_CSG).
+ *   boundaries      Dirichlet at the contour ends (eq. (lapctuecs)), or on
+ *                   an edge without a layer the first-order Sommerfeld
+ *                   condition du/dn = -i k u (Sec. 2, eq. (sommerfeld1);
+ *                   Sec. 4, eq. (BC)), by a ghost node one cell beyond the
+ *                   boundary and the centred difference of the condition at
+ *                   the boundary face.
  *   operator        Sec. 3, eq. (shortwell): Shortley-Weller 3-point second
  *                   derivative on complex, non-uniform widths, per axis;
  *                   Sec. 4, eq. (Helgen): -(Lap + phi) u with phi = k(x)^2;
@@ -48,6 +60,15 @@
  * code -- with the device path):
  *   complex multiply   (ar*br - ai*bi, ar*bi + ai*br)
  *   complex divide     d = br*br + bi*bi; ((ar*br + ai*bi)/d, (ai*br - ar*bi)/d)
+ *   principal sqrt     of (x, y): r = sqrt(x*x + y*y); x >= 0: re = sqrt(0.5*(r + x)),
+ *                      im = y/(2 re); x < 0: im = +-sqrt(0.5*(r - x)) (sign of y),
+ *                      re = y/(2 im)
+ *   Sommerfeld factor  hk = 0.5*k; rho = (1 + hk*w.im, -(hk*w.re)) / (1 - hk*w.im, hk*w.re)
+ *                      (contract divide), d_last = d_last - c_last*rho (a_first*rho on the
+ *                      low side), w = complex width from the last unknown to the ghost
+ *   smooth contour     w = L/m; q = floor(t/w) (at most m); s = 0; for p = 1..q:
+ *                      s = s + (w cos(p th/m), w sin(p th/m)); if q < m and t - q w > 0:
+ *                      s = s + ((t - q w) cos((q+1) th/m), (t - q w) sin((q+1) th/m))
  *   stencil            y = Dg*u - a_x*u_w - c_x*u_e - a_y*u_s - c_y*u_n
  *                          - a_z*u_d - c_z*u_u,  Dg = (d_x + d_y + d_z) - phi
  *   Jacobi weight      g = omega*conj(Dg)/|Dg|^2 : q = omega/(Dr*Dr + Di*Di),
@@ -111,6 +132,10 @@ typedef struct og_grid {
     int dim, nlev, centering, csg_mode, nu1, nu2;
     double lo[3], hi[3], a[3], b[3];
     double th_ecs, th_csg, omega;
+    double beta_re, beta_im;   /* CSG scale factor beta (CSL: principal sqrt of the shift) */
+    int steps;                 /* ECS contour: <= 1 linear, m > 1 m equal angle steps   */
+    int bc[3][2];              /* per axis and side: 0 Dirichlet, 1 Sommerfeld           */
+    double k_bc;               /* wave number of the Sommerfeld condition                 */
     og_level lev[OG_MAXLEV];
     long Nc;
     cx *Minv;              /* Nc x Nc, row major: explicit inverse of the coarsest M */
@@ -125,29 +150,92 @@ static cx ecs_map(double x, double a, double b, double c, double s)
     return cx_make(x, 0.0);
 }
 
-/* CSG map of the preconditioner (Sec. 5.3).  Uniform: every width of the ECS
- * grid is multiplied by beta = e^{i th_b}.  Interior: the interior widths are
- * multiplied by beta, the layer widths keep the ECS rotation. */
-static cx csg_map(double x, double a, double b, double cg, double sg, double cb, double sb, int mode)
+/* Displacement of a smooth ECS contour from its turning point after a real
+ * distance t >= 0 into a layer of real width L (Sec. 6.2, remark on a smooth
+ * ECS transition): the layer is cut into m equal parts and part p is rotated
+ * by p th / m, so the contour turns gradually to the angle th. */
+static cx contour_disp(double t, double L, double th, int m)
 {
-    if (mode == 0) {
-        cx z = ecs_map(x, a, b, cg, sg);
-        return cx_mul(cx_make(cb, sb), z);
+    double w = L / (double)m;
+    int q = (int)floor(t / w);
+    if (q > m) q = m;
+    if (q < 0) q = 0;
+    cx s = cx_make(0.0, 0.0);
+    for (int p = 1; p <= q; ++p) {
+        double ang = th * (double)p / (double)m;
+        s = cx_add(s, cx_make(w * cos(ang), w * sin(ang)));
     }
-    if (x < a) { double t = x - a; return cx_make(a * cb + t * cg, a * sb + t * sg); }
-    if (x > b) { double t = x - b; return cx_make(b * cb + t * cg, b * sb + t * sg); }
+    double rem = t - (double)q * w;
+    if (q < m && rem > 0.0) {
+        double ang = th * (double)(q + 1) / (double)m;
+        s = cx_add(s, cx_make(rem * cos(ang), rem * sin(ang)));
+    }
+    return s;
+}
+
+/* ECS map of one axis (linear, or smooth with g->steps > 1 parts). */
+static cx ecs_map_axis(const og_grid *g, int ax, double x, double cg, double sg)
+{
+    double a = g->a[ax], b = g->b[ax];
+    if (g->steps <= 1) return ecs_map(x, a, b, cg, sg);
+    if (x < a) return cx_sub(cx_make(a, 0.0), contour_disp(a - x, a - g->lo[ax], g->th_ecs, g->steps));
+    if (x > b) return cx_add(cx_make(b, 0.0), contour_disp(x - b, g->hi[ax] - b, g->th_ecs, g->steps));
+    return cx_make(x, 0.0);
+}
+
+/* CSG map of the preconditioner (Sec. 5.3).  Uniform: every width of the ECS
+ * grid is multiplied by beta (e^{i th_b}, or for the CSL the square root of
+ * the shift, eq. (CSL-CSG)).  Interior: the interior widths are multiplied by
+ * beta, the layer keeps the ECS contour. */
+static cx csg_map_axis(const og_grid *g, int ax, double x, double cg, double sg)
+{
+    double a = g->a[ax], b = g->b[ax], cb = g->beta_re, sb = g->beta_im;
+    if (g->csg_mode != 1) return cx_mul(cx_make(cb, sb), ecs_map_axis(g, ax, x, cg, sg));
+    if (g->steps <= 1) {
+        if (x < a) { double t = x - a; return cx_make(a * cb + t * cg, a * sb + t * sg); }
+        if (x > b) { double t = x - b; return cx_make(b * cb + t * cg, b * sb + t * sg); }
+        return cx_make(x * cb, x * sb);
+    }
+    if (x < a) return cx_sub(cx_make(a * cb, a * sb), contour_disp(a - x, a - g->lo[ax], g->th_ecs, g->steps));
+    if (x > b) return cx_add(cx_make(b * cb, b * sb), contour_disp(x - b, g->hi[ax] - b, g->th_ecs, g->steps));
     return cx_make(x * cb, x * sb);
+}
+
+/* Principal square root of x + i y. */
+static cx sqrt_principal(double x, double y)
+{
+    double r = sqrt(x * x + y * y);
+    if (x >= 0.0) {
+        double re = sqrt(0.5 * (r + x));
+        return cx_make(re, y / (2.0 * re));
+    }
+    double im = sqrt(0.5 * (r - x));
+    if (y < 0.0) im = -im;
+    return cx_make(y / (2.0 * im), im);
+}
+
+/* Factor rho of the Sommerfeld ghost value u_ghost = rho u_last: the centred
+ * difference of du/dn = -i k u at the boundary face between the last unknown
+ * and a ghost at complex distance w, (u_g - u_l)/w = -i k (u_g + u_l)/2. */
+static cx sommerfeld_rho(double k, cx w)
+{
+    double hk = 0.5 * k;
+    cx num = cx_make(1.0 + hk * w.im, -(hk * w.re));
+    cx den = cx_make(1.0 - hk * w.im, hk * w.re);
+    return cx_div(num, den);
 }
 
 /* Real node coordinates of one axis with n unknowns: x[0] and x[n+1] are the
  * Dirichlet ends lo and hi. */
-static void axis_nodes(int n, double lo, double hi, int centering, double *x)
+static void axis_nodes(int n, double lo, double hi, int centering, const int *bc, double *x)
 {
     if (centering == 0) {
         double h = (hi - lo) / (double)n;
-        x[0] = lo;
+        /* a Sommerfeld side's end node is the ghost one cell beyond the last
+         * unknown (the boundary is the face half a cell beyond it) */
+        x[0] = bc[0] ? lo - 0.5 * h : lo;
         for (int j = 1; j <= n; ++j) x[j] = lo + ((double)j - 0.5) * h;
-        x[n + 1] = hi;
+        x[n + 1] = bc[1] ? hi + 0.5 * h : hi;
     } else {
         double h = (hi - lo) / (double)(n + 1);
         x[0] = lo;
@@ -182,18 +270,38 @@ static void build_axis(og_grid *g, int lev, int ax)
     double *x = (double *)malloc(sizeof(double) * (size_t)(n + 2));
     cx *zH = (cx *)malloc(sizeof(cx) * (size_t)(n + 2));
     cx *zM = (cx *)malloc(sizeof(cx) * (size_t)(n + 2));
-    axis_nodes(n, g->lo[ax], g->hi[ax], g->centering, x);
+    axis_nodes(n, g->lo[ax], g->hi[ax], g->centering, g->bc[ax], x);
     double cg = cos(g->th_ecs), sg = sin(g->th_ecs);
-    double cb = cos(g->th_csg), sb = sin(g->th_csg);
     for (int j = 0; j <= n + 1; ++j) {
-        zH[j] = ecs_map(x[j], g->a[ax], g->b[ax], cg, sg);
-        zM[j] = csg_map(x[j], g->a[ax], g->b[ax], cg, sg, cb, sb, g->csg_mode);
+        zH[j] = ecs_map_axis(g, ax, x[j], cg, sg);
+        zM[j] = csg_map_axis(g, ax, x[j], cg, sg);
+    }
+    /* a Sommerfeld side has no layer: its ghost continues the interior map
+     * (real for H, scaled by beta for M) */
+    for (int side = 0; side < 2; ++side) {
+        if (!g->bc[ax][side]) continue;
+        int j = side == 0 ? 0 : n + 1;
+        zH[j] = cx_make(x[j], 0.0);
+        zM[j] = cx_make(g->beta_re * x[j], g->beta_im * x[j]);
     }
     size_t bytes = sizeof(cx) * (size_t)n;
     A->aH = (cx *)malloc(bytes); A->cH = (cx *)malloc(bytes); A->dH = (cx *)malloc(bytes);
     A->aM = (cx *)malloc(bytes); A->cM = (cx *)malloc(bytes); A->dM = (cx *)malloc(bytes);
     sw_coeffs(n, zH, A->aH, A->cH, A->dH);
     sw_coeffs(n, zM, A->aM, A->cM, A->dM);
+    /* Sommerfeld sides: eliminate the ghost (its coefficient moves onto the
+     * diagonal of the unknown next to the boundary); the preconditioner takes
+     * the condition in its own stretched coordinate (its complex widths) */
+    if (g->bc[ax][0]) {
+        cx rH = sommerfeld_rho(g->k_bc, cx_sub(zH[1], zH[0])), rM = sommerfeld_rho(g->k_bc, cx_sub(zM[1], zM[0]));
+        A->dH[0] = cx_sub(A->dH[0], cx_mul(A->aH[0], rH));
+        A->dM[0] = cx_sub(A->dM[0], cx_mul(A->aM[0], rM));
+    }
+    if (g->bc[ax][1]) {
+        cx rH = sommerfeld_rho(g->k_bc, cx_sub(zH[n + 1], zH[n])), rM = sommerfeld_rho(g->k_bc, cx_sub(zM[n + 1], zM[n]));
+        A->dH[n - 1] = cx_sub(A->dH[n - 1], cx_mul(A->cH[n - 1], rH));
+        A->dM[n - 1] = cx_sub(A->dM[n - 1], cx_mul(A->cM[n - 1], rM));
+    }
     free(x); free(zH); free(zM);
 }
 
@@ -428,16 +536,32 @@ static int build_coarse_inverse(og_grid *g)
 
 void og_free(og_grid *g);
 
+/* csg_mode: 0 uniform CSG, 1 interior CSG, 2 CSL with shift (shift_re,
+ * shift_im); contour_steps: ECS contour parts (<= 1 linear); bc: 6 ints, per
+ * axis (low side, high side), 1 = Sommerfeld with wave number k_bc. */
 og_grid *og_create(int dim, const int *n, const double *lo, const double *hi,
                    const double *a, const double *b, double theta_ecs, double theta_csg,
                    int csg_mode, int centering, int levels, int nu1, int nu2, double omega,
-                   const double *phi)
+                   const double *phi, double shift_re, double shift_im, int contour_steps,
+                   const int *bc, double k_bc)
 {
     if (dim < 1 || dim > 3) return NULL;
     og_grid *g = (og_grid *)calloc(1, sizeof(og_grid));
     g->dim = dim; g->centering = centering; g->csg_mode = csg_mode;
     g->nu1 = nu1; g->nu2 = nu2; g->omega = omega;
     g->th_ecs = theta_ecs; g->th_csg = theta_csg;
+    g->steps = contour_steps;
+    g->k_bc = k_bc;
+    for (int d = 0; d < 3; ++d) {
+        g->bc[d][0] = bc && d < dim ? bc[2 * d] : 0;
+        g->bc[d][1] = bc && d < dim ? bc[2 * d + 1] : 0;
+    }
+    if (csg_mode == 2) {
+        cx be = sqrt_principal(shift_re, shift_im);
+        g->beta_re = be.re; g->beta_im = be.im;
+    } else {
+        g->beta_re = cos(theta_csg); g->beta_im = sin(theta_csg);
+    }
     int n0[3] = {1, 1, 1};
     for (int d = 0; d < 3; ++d) {
         if (d < dim) {

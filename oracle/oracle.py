@@ -54,7 +54,7 @@ def lib():
         L = ctypes.CDLL(LIB)
         P, D, I = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
         L.og_create.restype = P
-        L.og_create.argtypes = [I, P, P, P, P, P, D, D, I, I, I, I, I, D, P]
+        L.og_create.argtypes = [I, P, P, P, P, P, D, D, I, I, I, I, I, D, P, D, D, I, P, D]
         L.og_free.argtypes = [P]
         L.og_levels.argtypes = [P]
         L.og_level_dims.argtypes = [P, I, P]
@@ -96,9 +96,12 @@ class Grid:
     on every level, coarse phi, the explicit coarsest inverse.
 
     desc keys (same meaning as the library's grid descriptor): dim, n, lo, hi,
-    a, b, theta_ecs, theta_csg, csg_mode (0 uniform, 1 interior), centering
-    (0 cell, 1 vertex), levels (0 auto), nu1, nu2, omega; phi is the real array
-    k(x)^2 on the finest grid (shape prod(n)), or phi_const."""
+    a, b, theta_ecs, theta_csg, csg_mode (0 uniform CSG, 1 interior CSG, 2
+    CSL), centering (0 cell, 1 vertex), levels (0 auto), nu1, nu2, omega,
+    csl_shift ([re, im] of beta^2 for the CSL), contour_steps (ECS contour
+    parts, 0/1 linear), bc ([[lo, hi]] per axis, 1 = Sommerfeld), k_bc (its
+    wave number); phi is the real array k(x)^2 on the finest grid (shape
+    prod(n)), or phi_const."""
 
     def __init__(self, desc, phi=None):
         L = lib()
@@ -112,14 +115,20 @@ class Grid:
             phi = np.full(N, float(d.get("phi_const", 0.0)))
         phi = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).reshape(-1))
         assert phi.size == N, (phi.size, N)
+        bc = np.zeros(6, dtype=np.int32)
+        for ax, sides in enumerate(d.get("bc", [])[:dim]):
+            bc[2 * ax], bc[2 * ax + 1] = int(sides[0]), int(sides[1])
         self._keep = [np.array(_three(n, 1), dtype=np.int32),
                       np.array(_three(d["lo"], 0.0)), np.array(_three(d["hi"], 1.0)),
-                      np.array(_three(d["a"], 0.0)), np.array(_three(d["b"], 1.0)), phi]
-        ni, lo, hi, a, b, _ = self._keep
+                      np.array(_three(d["a"], 0.0)), np.array(_three(d["b"], 1.0)), phi, bc]
+        ni, lo, hi, a, b, _, _ = self._keep
+        shift = d.get("csl_shift", [0.0, 0.0])
         self.h = L.og_create(dim, _ptr(ni), _ptr(lo), _ptr(hi), _ptr(a), _ptr(b),
                              float(d.get("theta_ecs", np.pi / 6)), float(d.get("theta_csg", np.pi / 8)),
                              int(d.get("csg_mode", 0)), int(d.get("centering", 0)), int(d.get("levels", 0)),
-                             int(d.get("nu1", 1)), int(d.get("nu2", 1)), float(d.get("omega", 0.8)), _ptr(phi))
+                             int(d.get("nu1", 1)), int(d.get("nu2", 1)), float(d.get("omega", 0.8)), _ptr(phi),
+                             float(shift[0]), float(shift[1]), int(d.get("contour_steps", 0)), _ptr(bc),
+                             float(d.get("k_bc", 0.0)))
         if not self.h:
             raise ValueError("oracle rejected the grid description")
         self.dim = dim

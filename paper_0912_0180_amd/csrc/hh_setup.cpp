@@ -21,37 +21,88 @@
 // (complex multiply/divide formulas of hh_common.h, no FMA contraction).
 #include "hh_setup.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 
 namespace {
 
-double2 ecs_map(double x, double a, double b, double c, double s)
+// Complex node positions of one axis: the ECS contour of H and the stretched
+// grid of the preconditioner M, with the Dirichlet or Sommerfeld treatment of
+// the two ends.
+struct AxisGeometry {
+    double lo, hi, a, b;
+    double theta, cg, sg;      // ECS angle and its cosine / sine
+    double2 beta;              // stretching factor of M
+    int mode, steps;
+    int bc[2];                 // low / high side: HH_BC_*
+
+    // How far a smooth contour has moved from its turning point after a real
+    // distance t into a layer of width L: the layer is cut into `steps`
+    // equal parts, part p turned by p theta / steps.
+    double2 turn(double t, double L) const
+    {
+        const double w = L / (double)steps;
+        int whole = (int)std::floor(t / w);
+        whole = std::min(std::max(whole, 0), steps);
+        double2 acc = cmk<double>(0.0, 0.0);
+        for (int p = 1; p <= whole; ++p) {
+            const double ang = theta * (double)p / (double)steps;
+            acc = cadd<double>(acc, cmk<double>(w * std::cos(ang), w * std::sin(ang)));
+        }
+        const double part = t - (double)whole * w;
+        if (whole < steps && part > 0.0) {
+            const double ang = theta * (double)(whole + 1) / (double)steps;
+            acc = cadd<double>(acc, cmk<double>(part * std::cos(ang), part * std::sin(ang)));
+        }
+        return acc;
+    }
+    double2 zH(double x) const
+    {
+        const bool left = x < a, right = x > b;
+        if (!left && !right) return cmk<double>(x, 0.0);
+        if (steps <= 1) {
+            const double r = left ? a : b, t = x - r;
+            return cmk<double>(r + t * cg, t * sg);
+        }
+        return left ? csub<double>(cmk<double>(a, 0.0), turn(a - x, a - lo))
+                    : cadd<double>(cmk<double>(b, 0.0), turn(x - b, hi - b));
+    }
+    double2 zM(double x) const
+    {
+        if (mode != HH_CSG_INTERIOR) return cmul<double>(beta, zH(x));
+        const bool left = x < a, right = x > b;
+        if (!left && !right) return cmk<double>(x * beta.x, x * beta.y);
+        const double r = left ? a : b;
+        if (steps <= 1) {
+            const double t = x - r;
+            return cmk<double>(r * beta.x + t * cg, r * beta.y + t * sg);
+        }
+        const double2 rb = cmk<double>(r * beta.x, r * beta.y);
+        return left ? csub<double>(rb, turn(a - x, a - lo)) : cadd<double>(rb, turn(x - b, hi - b));
+    }
+};
+
+// Principal square root of a nonzero complex number.
+double2 principal_sqrt(double2 v)
 {
-    if (x < a) {
-        double t = x - a;
-        return cmk<double>(a + t * c, t * s);
+    const double r = std::sqrt(v.x * v.x + v.y * v.y);
+    if (v.x >= 0.0) {
+        const double re = std::sqrt(0.5 * (r + v.x));
+        return cmk<double>(re, v.y / (2.0 * re));
     }
-    if (x > b) {
-        double t = x - b;
-        return cmk<double>(b + t * c, t * s);
-    }
-    return cmk<double>(x, 0.0);
+    double im = std::sqrt(0.5 * (r - v.x));
+    if (v.y < 0.0) im = -im;
+    return cmk<double>(v.y / (2.0 * im), im);
 }
 
-double2 csg_map(double x, double a, double b, double cg, double sg, double cb, double sb, int mode)
+// u_ghost = rho u_last from the centred difference of du/dn = -i k u at the
+// face between the last unknown and the ghost at complex distance w.
+double2 ghost_factor(double k, double2 w)
 {
-    if (mode == HH_CSG_UNIFORM) return cmul<double>(cmk<double>(cb, sb), ecs_map(x, a, b, cg, sg));
-    if (x < a) {
-        double t = x - a;
-        return cmk<double>(a * cb + t * cg, a * sb + t * sg);
-    }
-    if (x > b) {
-        double t = x - b;
-        return cmk<double>(b * cb + t * cg, b * sb + t * sg);
-    }
-    return cmk<double>(x * cb, x * sb);
+    const double hk = 0.5 * k;
+    return cdiv<double>(cmk<double>(1.0 + hk * w.y, -(hk * w.x)), cmk<double>(1.0 - hk * w.y, hk * w.x));
 }
 
 void sw(int n, const std::vector<double2> &z, std::vector<double2> &A, std::vector<double2> &C,
@@ -177,8 +228,17 @@ hh_status desc_check(const hh_grid_desc *d, int &levels, int &coarse, std::strin
     const int dim = d->dim;
     const double half_pi = 1.5707963267948966;
     if (!(d->theta_ecs > 0.0 && d->theta_ecs < half_pi)) { err = "theta_ecs must lie in (0, pi/2)"; return HH_ERR_ARG; }
-    if (!(d->theta_csg > 0.0 && d->theta_csg < half_pi)) { err = "theta_csg must lie in (0, pi/2)"; return HH_ERR_ARG; }
-    if (d->csg_mode != HH_CSG_UNIFORM && d->csg_mode != HH_CSG_INTERIOR) { err = "csg_mode must be 0 or 1"; return HH_ERR_ARG; }
+    if (d->csg_mode != HH_CSG_UNIFORM && d->csg_mode != HH_CSG_INTERIOR && d->csg_mode != HH_CSL) {
+        err = "csg_mode must be 0 (uniform CSG), 1 (interior CSG) or 2 (CSL)";
+        return HH_ERR_ARG;
+    }
+    if (d->csg_mode != HH_CSL && !(std::fabs(d->theta_csg) < half_pi)) { err = "theta_csg must lie in (-pi/2, pi/2)"; return HH_ERR_ARG; }
+    if (d->csg_mode == HH_CSL && !(std::isfinite(d->csl_shift[0]) && std::isfinite(d->csl_shift[1]) &&
+                                   (d->csl_shift[0] != 0.0 || d->csl_shift[1] != 0.0))) {
+        err = "the CSL shift must be finite and nonzero";
+        return HH_ERR_ARG;
+    }
+    if (d->contour_steps < 0 || d->contour_steps > 65536) { err = "contour_steps must lie in [0, 65536]"; return HH_ERR_ARG; }
     if (d->centering != HH_CELL && d->centering != HH_VERTEX) { err = "centering must be 0 (cell) or 1 (vertex)"; return HH_ERR_ARG; }
     if (d->nu1 != 1 || d->nu2 != 1) { err = "only the V(1,1) cycle is supported (nu1 = nu2 = 1)"; return HH_ERR_ARG; }
     if (!(d->omega > 0.0 && d->omega < 2.0)) { err = "omega must lie in (0, 2)"; return HH_ERR_ARG; }
@@ -189,6 +249,18 @@ hh_status desc_check(const hh_grid_desc *d, int &levels, int &coarse, std::strin
             snprintf(buf, sizeof buf, "axis %d: need lo <= a < b <= hi", a);
             err = buf;
             return HH_ERR_ARG;
+        }
+        for (int side = 0; side < 2; ++side) {
+            const int bc = d->bc[a][side];
+            if (bc != HH_BC_DIRICHLET && bc != HH_BC_SOMMERFELD) { err = "bc must be 0 (Dirichlet) or 1 (Sommerfeld)"; return HH_ERR_ARG; }
+            if (bc != HH_BC_SOMMERFELD) continue;
+            if (side == 0 ? d->a[a] != d->lo[a] : d->b[a] != d->hi[a]) {
+                snprintf(buf, sizeof buf, "axis %d: a Sommerfeld side has no layer (need %s)", a, side == 0 ? "a == lo" : "b == hi");
+                err = buf;
+                return HH_ERR_ARG;
+            }
+            if (d->centering != HH_CELL) { err = "Sommerfeld sides need a cell-centred grid"; return HH_ERR_ARG; }
+            if (!(d->k_bc > 0.0 && std::isfinite(d->k_bc))) { err = "a Sommerfeld side needs k_bc > 0"; return HH_ERR_ARG; }
         }
         N *= d->n[a];
     }
@@ -236,7 +308,8 @@ hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err)
     hs.centering = d->centering;
     const bool vertex = d->centering == HH_VERTEX;
     const double cg = std::cos(d->theta_ecs), sg = std::sin(d->theta_ecs);
-    const double cb = std::cos(d->theta_csg), sb = std::sin(d->theta_csg);
+    const double2 beta = d->csg_mode == HH_CSL ? principal_sqrt(cmk<double>(d->csl_shift[0], d->csl_shift[1]))
+                                               : cmk<double>(std::cos(d->theta_csg), std::sin(d->theta_csg));
     for (int l = 0; l < nl; ++l) {
         HostLevel &L = hs.lev[l];
         L.N = 1;
@@ -246,26 +319,39 @@ hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err)
         }
         for (int a = 0; a < dim; ++a) {
             const int n = L.n[a];
-            // real nodes: the two Dirichlet ends and the n unknowns between
-            // them, at cell centres or at the vertices of n + 1 equal intervals
+            const AxisGeometry geo{d->lo[a], d->hi[a], d->a[a], d->b[a], d->theta_ecs, cg, sg, beta,
+                                   d->csg_mode, d->contour_steps, {d->bc[a][0], d->bc[a][1]}};
+            // real nodes: the two ends and the n unknowns between them, at
+            // cell centres or at the vertices of n + 1 equal intervals; the
+            // end of a Sommerfeld side is a ghost one cell beyond the last
+            // unknown, on the continuation of the interior (no layer there)
             const double lo = d->lo[a], hi = d->hi[a];
+            const double h = vertex ? (hi - lo) / (double)(n + 1) : (hi - lo) / (double)n;
             std::vector<double> x(n + 2);
-            x[0] = lo;
-            if (vertex) {
-                const double h = (hi - lo) / (double)(n + 1);
-                for (int j = 1; j <= n; ++j) x[j] = lo + (double)j * h;
-            } else {
-                const double h = (hi - lo) / (double)n;
-                for (int j = 1; j <= n; ++j) x[j] = lo + ((double)j - 0.5) * h;
-            }
-            x[n + 1] = hi;
+            for (int j = 1; j <= n; ++j) x[j] = vertex ? lo + (double)j * h : lo + ((double)j - 0.5) * h;
+            x[0] = geo.bc[0] == HH_BC_SOMMERFELD ? lo - 0.5 * h : lo;
+            x[n + 1] = geo.bc[1] == HH_BC_SOMMERFELD ? hi + 0.5 * h : hi;
             std::vector<double2> zH(n + 2), zM(n + 2);
             for (int j = 0; j <= n + 1; ++j) {
-                zH[j] = ecs_map(x[j], d->a[a], d->b[a], cg, sg);
-                zM[j] = csg_map(x[j], d->a[a], d->b[a], cg, sg, cb, sb, d->csg_mode);
+                const bool ghost = (j == 0 && geo.bc[0] == HH_BC_SOMMERFELD) || (j == n + 1 && geo.bc[1] == HH_BC_SOMMERFELD);
+                zH[j] = ghost ? cmk<double>(x[j], 0.0) : geo.zH(x[j]);
+                zM[j] = ghost ? cmk<double>(beta.x * x[j], beta.y * x[j]) : geo.zM(x[j]);
             }
             sw(n, zM, L.aM[a], L.cM[a], L.dM[a]);
             if (l == 0) sw(n, zH, hs.aH[a], hs.cH[a], hs.dH[a]);
+            // Sommerfeld sides: the ghost's coefficient folds onto the diagonal
+            // of the unknown next to the boundary
+            for (int side = 0; side < 2; ++side) {
+                if (geo.bc[side] != HH_BC_SOMMERFELD) continue;
+                const int j = side == 0 ? 0 : n - 1;                  // unknown next to the boundary
+                const int inner = side == 0 ? 1 : n, outer = side == 0 ? 0 : n + 1;
+                const double2 rM = ghost_factor(d->k_bc, csub<double>(zM[side == 0 ? inner : outer], zM[side == 0 ? outer : inner]));
+                L.dM[a][j] = csub<double>(L.dM[a][j], cmul<double>(side == 0 ? L.aM[a][j] : L.cM[a][j], rM));
+                if (l == 0) {
+                    const double2 rH = ghost_factor(d->k_bc, csub<double>(zH[side == 0 ? inner : outer], zH[side == 0 ? outer : inner]));
+                    hs.dH[a][j] = csub<double>(hs.dH[a][j], cmul<double>(side == 0 ? hs.aH[a][j] : hs.cH[a][j], rH));
+                }
+            }
         }
         L.phi.resize(L.N);
         if (l == 0) {

@@ -39,7 +39,8 @@ class GridDesc(ctypes.Structure):
                 ("theta_ecs", ctypes.c_double), ("theta_csg", ctypes.c_double), ("csg_mode", ctypes.c_int32),
                 ("centering", ctypes.c_int32), ("levels", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("phi", ctypes.c_void_p), ("phi_const", ctypes.c_double),
-                ("host_only", ctypes.c_int32)]
+                ("host_only", ctypes.c_int32), ("csl_shift", ctypes.c_double * 2), ("contour_steps", ctypes.c_int32),
+                ("bc", (ctypes.c_int32 * 2) * 3), ("k_bc", ctypes.c_double)]
 
 
 class GridInfo(ctypes.Structure):
@@ -174,6 +175,12 @@ def make_desc(desc, phi=None, host_only=False):
         d.phi = None
         d.phi_const = float(desc.get("phi_const", 0.0))
     d.host_only = 1 if host_only else 0
+    shift = desc.get("csl_shift", (0.0, 0.0))
+    d.csl_shift[0], d.csl_shift[1] = float(shift[0]), float(shift[1])
+    d.contour_steps = int(desc.get("contour_steps", 0))
+    for a, sides in enumerate(desc.get("bc", [])[:dim]):
+        d.bc[a][0], d.bc[a][1] = int(sides[0]), int(sides[1])
+    d.k_bc = float(desc.get("k_bc", 0.0))
     return d, keep
 
 

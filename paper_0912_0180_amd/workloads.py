@@ -27,11 +27,16 @@ def rng(seed):
 
 
 def base_desc(dim, n, lo, hi, a, b, theta_ecs=PI / 6, theta_csg=PI / 8, csg_mode=0, levels=0,
-              nu1=1, nu2=1, omega=0.8, centering=0):
+              nu1=1, nu2=1, omega=0.8, centering=0, csl_shift=(0.0, 0.0), contour_steps=0, bc=None, k_bc=0.0):
+    """Grid description (the keys of the library's hh_grid_desc).  bc: per axis
+    [low side, high side], 0 Dirichlet / contour end, 1 Sommerfeld (wave number
+    k_bc); csg_mode 2 is the CSL preconditioner with the shift csl_shift."""
     return {"dim": dim, "n": list(n), "lo": list(lo), "hi": list(hi), "a": list(a), "b": list(b),
             "theta_ecs": float(theta_ecs), "theta_csg": float(theta_csg), "csg_mode": int(csg_mode),
             "centering": int(centering), "levels": int(levels), "nu1": int(nu1), "nu2": int(nu2),
-            "omega": float(omega)}
+            "omega": float(omega), "csl_shift": [float(csl_shift[0]), float(csl_shift[1])],
+            "contour_steps": int(contour_steps), "bc": [list(v) for v in (bc or [[0, 0]] * dim)],
+            "k_bc": float(k_bc)}
 
 
 def cell_centres(n, lo, hi):
@@ -185,23 +190,28 @@ def c4(count=64, seed=4, sides=(256, 384, 512, 768, 1024)):
     return probs
 
 
-def mp_grid(n_int, n_lay, r, theta_csg=PI / 8, levels=0):
+def mp_grid(n_int, n_lay, r, theta_csg=PI / 8, levels=0, bc="ecs", k=0.0):
     """The grid of the paper's model problems 2 and 3 (Sec. 4, eq. (BC)): the
     square (0, r)^2 with n_int cells of width h = r / n_int per axis,
     homogeneous Dirichlet on the south and west edges (x = 0, y = 0: no layer,
-    a = lo = 0) and an ECS layer of n_lay cells on the north and east edges."""
+    a = lo = 0), and on the north and east edges either an ECS layer of n_lay
+    cells (bc "ecs") or the Sommerfeld condition du/dn = -i k u (bc
+    "sommerfeld", no layer)."""
     h = r / n_int
+    if bc == "sommerfeld":
+        return base_desc(2, (n_int, n_int), (0.0, 0.0), (r, r), (0.0, 0.0), (r, r), theta_csg=theta_csg,
+                         levels=levels, bc=[[0, 1], [0, 1]], k_bc=k)
     n = n_int + n_lay
     hi = r + n_lay * h
     return base_desc(2, (n, n), (0.0, 0.0), (hi, hi), (0.0, 0.0), (r, r), theta_csg=theta_csg, levels=levels)
 
 
-def mp2(nu=7.0, k=2.0, n_int=384, n_lay=128, r=50.0, theta_csg=PI / 8, levels=0):
+def mp2(nu=7.0, k=2.0, n_int=384, n_lay=128, r=50.0, theta_csg=PI / 8, levels=0, bc="ecs"):
     """Model problem 2 (Sec. 4, eq. (MP2)): phi = nu (e^{-x^2} + e^{-y^2}) + k^2,
     chi = e^{-(x^2 + y^2)}, on the mp_grid; the paper's sizes are 384 interior
     + 128 layer cells for r = 50 (nu = 7, k = 2 and nu = 1, k = 4).  phi and
     chi are sampled at the real cell centres (layer cells included)."""
-    d = mp_grid(n_int, n_lay, r, theta_csg, levels)
+    d = mp_grid(n_int, n_lay, r, theta_csg, levels, bc, k)
     X, Y = mesh(d)
     phi = flat(nu * (np.exp(-X * X) + np.exp(-Y * Y)) + k * k)
     b = flat(np.exp(-(X * X + Y * Y))).astype(np.complex128)
@@ -209,13 +219,13 @@ def mp2(nu=7.0, k=2.0, n_int=384, n_lay=128, r=50.0, theta_csg=PI / 8, levels=0)
             "method": "bicgstab", "tol": 1e-8}
 
 
-def mp3(r=90.0, k=2.0, n_int=1024, n_lay=256, theta_csg=PI / 8, levels=0):
+def mp3(r=90.0, k=2.0, n_int=1024, n_lay=256, theta_csg=PI / 8, levels=0, bc="ecs"):
     """Model problem 3 (Sec. 4, eq. (MP3)): phi = 1/x + 1/y + k^2, chi =
     e^{-(x^2 + y^2)}, on the mp_grid; the paper's sizes are 1024 interior +
     256 layer cells for r = 90, k = 2 (2048 + 512 for r = 150, k = 4).  The
     cell centres never reach the singularity at the origin: the largest phi
     is at the first centre (h/2, h/2), as in the paper's mesh-width bound."""
-    d = mp_grid(n_int, n_lay, r, theta_csg, levels)
+    d = mp_grid(n_int, n_lay, r, theta_csg, levels, bc, k)
     X, Y = mesh(d)
     phi = flat(1.0 / X + 1.0 / Y + k * k)
     b = flat(np.exp(-(X * X + Y * Y))).astype(np.complex128)

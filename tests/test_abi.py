@@ -179,3 +179,76 @@ def test_vertex_grid_validation():
     with pytest.raises(hh.HHError) as ei:
         hh.request_footprint(d)
     assert "vertex" in str(ei.value)
+
+
+def _variant(name):
+    if name == "csl":
+        c = W.c1()
+        c["desc"].update(csg_mode=2, csl_shift=[1.0, 0.2])
+        return c
+    if name == "csl_interior_angle":
+        c = W.c1(mode=1)
+        c["desc"].update(contour_steps=8)
+        return c
+    if name == "smooth":
+        c = W.c2(n=128, levels=4)
+        c["desc"].update(contour_steps=32)
+        return c
+    if name == "mp2":
+        return W.mp2(n_int=96, n_lay=32, r=12.5)
+    if name == "mp3":
+        return W.mp3(n_int=96, n_lay=32, r=90.0 * 96 / 1024)
+    if name == "mp2_sommerfeld":
+        return W.mp2(n_int=128, n_lay=0, r=50.0 / 3, bc="sommerfeld", theta_csg=-math.pi / 20)
+    if name == "sommerfeld_3d":
+        c = W.c3(n=32, layer=4, method="bicgstab")
+        d = c["desc"]
+        d["a"][2] = d["lo"][2]                      # no layer on the low z side: Sommerfeld there
+        d["bc"][2] = [1, 0]
+        d["k_bc"] = 12.0
+        return c
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["csl", "csl_interior_angle", "smooth", "mp2", "mp3", "mp2_sommerfeld", "sommerfeld_3d"])
+def test_host_setup_variants_equal_oracle_bitwise(oracle_mod, name):
+    """CSL shift, smooth contours, one-sided layers and Sommerfeld sides: the
+    library's node maps, coefficients, coarse phi and coarsest inverse equal
+    the oracle's value for value."""
+    c = _variant(name)
+    g = host_grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    assert g.levels == o.nlev and g.Nc == o.Nc
+    for lev in range(g.levels):
+        for ax in range(g.dim):
+            names = ["aM", "cM", "dM"] + (["aH", "cH", "dH"] if lev == 0 else [])
+            for w in names:
+                a, b = g.export(w, lev, ax), o.coeffs(lev, ax, w)
+                assert np.array_equal(a.view(np.float64), b.view(np.float64)), (name, lev, ax, w)
+        assert np.array_equal(g.export("phi", lev), o.phi(lev))
+    assert np.array_equal(g.export("Minv").view(np.float64), o.coarse_inverse().view(np.float64))
+
+
+def test_variant_validation():
+    base = W.c1()["desc"]
+
+    def bad(**kw):
+        d = dict(base)
+        d.update(kw)
+        with pytest.raises(hh.HHError):
+            host_grid(d)
+
+    bad(csg_mode=3)
+    bad(csg_mode=2, csl_shift=[0.0, 0.0])
+    bad(theta_csg=1.6)
+    bad(contour_steps=-1)
+    bad(bc=[[1, 0], [0, 0]], k_bc=3.0)             # Sommerfeld on a side with a layer
+    d = dict(base)
+    d.update(a=[-0.25, 0.0], bc=[[1, 0], [0, 0]], k_bc=0.0)
+    with pytest.raises(hh.HHError):
+        host_grid(d)                                # no k_bc
+    d.update(k_bc=5.0)
+    assert host_grid(d).levels == 4
+    d2 = dict(base)
+    d2.update(theta_csg=-math.pi / 20)              # negative angles are the Sommerfeld tables' choice
+    assert host_grid(d2).levels == 4

@@ -17,9 +17,9 @@ from paper_0912_0180_amd import workloads as W
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def desc1(n, lo, hi, a, b, theta=math.pi / 6, theta_csg=math.pi / 8, centering=0, levels=1, mode=0):
+def desc1(n, lo, hi, a, b, theta=math.pi / 6, theta_csg=math.pi / 8, centering=0, levels=1, mode=0, **kw):
     return W.base_desc(1, (n,), (lo,), (hi,), (a,), (b,), theta_ecs=theta, theta_csg=theta_csg,
-                       csg_mode=mode, levels=levels, centering=centering)
+                       csg_mode=mode, levels=levels, centering=centering, **kw)
 
 
 def cheb_u(m, x):
@@ -350,6 +350,134 @@ def test_csl_csg_identity_and_spectral_map(oracle_mod):
     pred = (mu - 60.0) / (mu - beta2 * 60.0)
     for e in ev:
         assert np.min(np.abs(pred - e)) < 1e-8 * max(1.0, abs(e))
+
+
+@pytest.mark.parametrize("shift", [(1.0, 0.2), (1.0, -0.35), (0.93, 0.36), (-0.5, 0.8)])
+def test_csl_is_the_shifted_laplacian(oracle_mod, shift):
+    """Sec. 5.2, eq. (helmctucsl): the CSL preconditioner is -(L_h + beta^2 phi)
+    on the ECS grid, for any complex shift beta^2 (the tables print -beta^2).
+    The oracle's CSL mode is the uniform CSG with beta the square root of the
+    shift, so by eq. (CSL-CSG) beta^2 M = -(L_h + beta^2 phi) = H + (1 - beta^2) phi,
+    with a variable phi and |beta| != 1 too."""
+    d = W.base_desc(2, (12, 10), (-0.25, -0.3), (1.25, 1.2), (0.0, 0.0), (1.0, 0.9), levels=1, csg_mode=2,
+                    csl_shift=shift)
+    rng = np.random.default_rng(31)
+    phi = 300.0 + 80.0 * rng.uniform(size=120)
+    g = oracle_mod.Grid(d, phi)
+    s2 = complex(*shift)
+    x = rng.standard_normal(120) + 1j * rng.standard_normal(120)
+    lhs = s2 * g.apply(x, "M")
+    rhs = g.apply(x, "H") + (1 - s2) * phi * x
+    assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(rhs)
+
+
+def test_csl_with_unit_shift_equals_uniform_csg(oracle_mod):
+    """Tables MP1-MP3 pair CSG with angle theta and CSL with shift
+    -e^{2 i theta} (beta^2 = e^{2 i theta}): the same operator (eq. (CSL-CSG));
+    its preconditioned spectrum is the linear-fractional image
+    (mu - k^2)/(mu - beta^2 k^2) of the ECS Laplacian's (Sec. 5.2)."""
+    th = math.pi / 28
+    base = dict(dim=1, n=(24,), lo=(-0.25,), hi=(1.25,), a=(0.0,), b=(1.0,))
+    dc = desc1(24, -0.25, 1.25, 0.0, 1.0, theta_csg=th)
+    dl = desc1(24, -0.25, 1.25, 0.0, 1.0, mode=2, csl_shift=(math.cos(2 * th), math.sin(2 * th)))
+    k2 = 60.0
+    gc, gl = oracle_mod.Grid(dc, np.full(24, k2)), oracle_mod.Grid(dl, np.full(24, k2))
+    Mc, Ml = gc.matrix("M"), gl.matrix("M")
+    assert np.linalg.norm(Mc - Ml) <= 1e-13 * np.linalg.norm(Mc)
+    s2 = complex(0.95, -0.31)       # a printed Sommerfeld-table shift, as beta^2
+    g = oracle_mod.Grid(desc1(24, -0.25, 1.25, 0.0, 1.0, mode=2, csl_shift=(s2.real, s2.imag)), np.full(24, k2))
+    H = g.matrix("H")
+    mu = np.linalg.eigvals(H + k2 * np.eye(24))
+    ev = np.linalg.eigvals(np.linalg.solve(s2 * g.matrix("M"), H))
+    pred = (mu - k2) / (mu - s2 * k2)
+    for e in ev:
+        assert np.min(np.abs(pred - e)) < 1e-8 * max(1.0, abs(e))
+
+
+def test_sommerfeld_point_source_1d(oracle_mod):
+    """Sec. 2, eq. (sommerfeld1): with du/dn = -i k u at both ends of [0, 1]
+    (cell-centred, a ghost node one cell beyond each end), a unit-mass interior
+    point source gives the wave (-i/2k) e^{-ik|x - x0|} that the condition
+    lets out (the first-order condition is exact for a 1D plane wave), at
+    second order in h.  Dirichlet ends reflect it (control), and the opposite
+    ECS convention (layers at angle -pi/6) gives the same wave as the condition."""
+    k = 40.0
+    errs = []
+    for n in (400, 800):
+        h = 1.0 / n
+        x = (np.arange(n) + 0.5) * h
+        j0 = n // 2
+        b = np.zeros(n, dtype=complex)
+        b[j0] = 1.0 / h
+        g = oracle_mod.Grid(desc1(n, 0.0, 1.0, 0.0, 1.0, bc=[[1, 1]], k_bc=k), np.full(n, k * k))
+        u = np.linalg.solve(g.matrix("H"), b)
+        gc = -1j / (2 * k) * np.exp(-1j * k * np.abs(x - x[j0]))
+        errs.append(np.max(np.abs(u - gc)) / np.max(np.abs(gc)))
+        if n == 400:
+            gd = oracle_mod.Grid(desc1(n, 0.0, 1.0, 0.0, 1.0), np.full(n, k * k))
+            ud = np.linalg.solve(gd.matrix("H"), b)
+            assert np.max(np.abs(ud - gc)) / np.max(np.abs(gc)) > 0.5
+    assert errs[1] < 5e-3 and errs[0] / errs[1] > 3.0
+    # the layers of the other rotation sense absorb the same wave
+    n = 800
+    h = 1.5 / n
+    x = -0.25 + (np.arange(n) + 0.5) * h
+    j0 = n // 2
+    b = np.zeros(n, dtype=complex)
+    b[j0] = 1.0 / h
+    ge = oracle_mod.Grid(desc1(n, -0.25, 1.25, 0.0, 1.0, theta=-math.pi / 6), np.full(n, k * k))
+    ue = np.linalg.solve(ge.matrix("H"), b)
+    gc = -1j / (2 * k) * np.exp(-1j * k * np.abs(x - x[j0]))
+    inside = (x > 0.02) & (x < 0.98)
+    assert np.max(np.abs(ue - gc)[inside]) / np.max(np.abs(gc[inside])) < 5e-3
+
+
+def test_sommerfeld_ghost_row(oracle_mod):
+    """The boundary row of a Sommerfeld side: standard widths h to both
+    neighbours, the ghost eliminated as u_g = rho u_last with
+    rho = (1 - i k h/2)/(1 + i k h/2), so the diagonal of -u'' is (2 - rho)/h^2;
+    the preconditioner (uniform CSG, widths beta h) uses beta h in rho."""
+    n, k, th = 16, 7.0, math.pi / 8
+    h = 1.0 / n
+    g = oracle_mod.Grid(desc1(n, 0.0, 1.0, 0.0, 1.0, bc=[[1, 1]], k_bc=k, theta_csg=th), np.zeros(n))
+    H, M = g.matrix("H"), g.matrix("M")
+    be = complex(math.cos(th), math.sin(th))
+    for A, w in ((H, h), (M, be * h)):
+        rho = (1 - 1j * k * w / 2) / (1 + 1j * k * w / 2)
+        for j in (0, n - 1):
+            assert abs(A[j, j] - (2 - rho) / (w * w)) <= 1e-12 * abs(2 / (w * w))
+        assert abs(A[0, 1] + 1 / (w * w)) <= 1e-12 / abs(w * w)
+        assert abs(A[5, 5] - 2 / (w * w)) <= 1e-12 / abs(w * w)
+
+
+def test_smooth_contour_with_one_step_is_linear(oracle_mod):
+    d0 = desc1(40, -0.25, 1.3, 0.0, 1.0)
+    d1 = desc1(40, -0.25, 1.3, 0.0, 1.0, contour_steps=1)
+    a, b = oracle_mod.Grid(d0, np.full(40, 50.0)), oracle_mod.Grid(d1, np.full(40, 50.0))
+    assert np.array_equal(a.matrix("H"), b.matrix("H")) and np.array_equal(a.matrix("M"), b.matrix("M"))
+
+
+def test_smooth_contour_eigenvalues_depend_on_its_end_point_only(oracle_mod):
+    """Sec. 2: the eigenvalues (j pi / R_z)^2 of -d^2/dz^2 depend only on the
+    contour's end points.  A contour that turns to pi/6 in 8 equal steps (Sec.
+    6.2, smooth ECS remark) ends at R_z = 1 + (L/8) e^{i th/8} (1 - e^{i th})/
+    (1 - e^{i th/8}) (a geometric sum); the smallest discrete eigenvalues
+    approach (j pi/R_z)^2 at second order, and not the linear contour's."""
+    th, m = math.pi / 6, 8
+    L = 0.5
+    q = complex(math.cos(th / m), math.sin(th / m))
+    Rz = 1 + (L / m) * q * (1 - q ** m) / (1 - q)
+    Rlin = 1 + L * complex(math.cos(th), math.sin(th))
+    errs = []
+    for n in (32, 64, 128):
+        lay = n // 2
+        d = desc1(n + lay - 1, 0.0, 1.0 + L, 0.0, 1.0, theta=th, centering=1, levels=1, contour_steps=m)
+        lam = np.linalg.eigvals(oracle_mod.Grid(d, np.zeros(n + lay - 1)).matrix("H"))
+        e = [np.min(np.abs(lam - (j * math.pi / Rz) ** 2)) / abs((j * math.pi / Rz) ** 2) for j in (1, 2, 3)]
+        errs.append(max(e))
+        if n == 128:
+            assert np.min(np.abs(lam - (math.pi / Rlin) ** 2)) / abs((math.pi / Rlin) ** 2) > 1e-2
+    assert errs[-1] < 1e-3 and errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0
 
 
 def test_point_source_outgoing_wave_1d(oracle_mod):
