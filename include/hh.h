@@ -262,6 +262,47 @@ hh_status hh_solve(hh_grid *g, const hh_solve_opts *o, const void *b, void *x, h
 hh_status hh_solve_batch(hh_grid *const *g, int32_t count, const hh_solve_opts *o, const void *const *b,
                          void *const *x, hh_solve_info *info, void *stream);
 
+/* ---- choosing the preconditioner's stretch or shift --------------------- */
+/* Sec. 6.2, remark on choosing the CSL and CSG parameters: starting from a
+ * given CSG angle (or CSL imaginary shift), multigrid alone is run on the
+ * preconditioner problem M u = f, u_k = u_{k-1} + V(f - M u_{k-1}), u_0 = 0,
+ * with the FP64 V-cycle of hh_vcycle, and the parameter is multiplied by
+ * `factor` while multigrid still reduces ||f - M u_k|| / ||f|| below
+ * `reduction` within `max_cycles` cycles (the paper: "just converges, say in
+ * 10-20 cycles"; its tables count cycles to 7 orders).  The result is the
+ * last value that converged: the CSG angle theta_csg, or for the CSL the
+ * imaginary part eps of the shift beta^2 = 1 + i eps (the paper's tables
+ * print -beta^2 = -1 - i eps; a negative start searches negative values).
+ * d describes the problem (its own theta_csg / csl_shift / csg_mode are
+ * replaced: CSG_ANGLE keeps csg_mode unless it is HH_CSL, which becomes
+ * uniform; CSL_SHIFT sets HH_CSL).  f: device, N complex double, nonzero.
+ * trace: optional host array of 3 * max_steps doubles, (value, cycles to
+ * converge or 0, last relative residual) per candidate.  Norms follow the
+ * fixed reduction order of the solves, so the choice is reproducible.
+ * Builds and frees one grid per candidate; allocates three work vectors.
+ * Errors: HH_ERR_ARG (description or options), HH_ERR_NOCONV (no
+ * convergence at the start value), HH_ERR_OOM, HH_ERR_HIP. */
+typedef enum { HH_SELECT_CSG_ANGLE = 0, HH_SELECT_CSL_SHIFT = 1 } hh_select_which;
+typedef struct {
+    int32_t which;          /* hh_select_which                                       */
+    double start;           /* first candidate (angle in radians, or eps)            */
+    double factor;          /* each next candidate is the previous one times this,
+                               0 < factor < 1                                         */
+    double min_value;       /* stop before |candidate| falls below this               */
+    int32_t max_cycles;     /* e.g. 20                                                */
+    double reduction;       /* e.g. 1e-7                                              */
+    int32_t max_steps;      /* candidates at most                                     */
+} hh_select_opts;
+typedef struct {
+    double value;           /* chosen angle or eps                                    */
+    int32_t cycles;         /* cycles it needed                                       */
+    double factor;          /* its average residual reduction per cycle               */
+    int32_t tried;          /* candidates run                                         */
+    int32_t status;         /* HH_OK or HH_ERR_NOCONV                                 */
+} hh_select_result;
+hh_status hh_select_preconditioner(const hh_grid_desc *d, const hh_select_opts *o, const void *f,
+                                   hh_select_result *res, double *trace, void *stream);
+
 /* ---- serving ---------------------------------------------------------- */
 typedef struct {
     uint64_t hbm_budget_bytes;   /* 0: 80% of the free device memory at creation   */

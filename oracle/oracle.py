@@ -261,3 +261,55 @@ def nrm2(x):
 
 def num_threads():
     return int(lib().og_num_threads())
+
+
+def select_preconditioner(desc, phi, f, which="csg", start=np.pi / 4, factor=0.8, min_value=1e-3, max_cycles=20,
+                          reduction=1e-7, max_steps=30):
+    """Sec. 6.2, remark on choosing the CSL and CSG parameters: multigrid alone
+    on M u = f (u_k = u_{k-1} + V(f - M u_{k-1}), u_0 = 0) for the candidates
+    start, start*factor, ...; a candidate converges when ||f - M u_k||/||f||
+    drops below `reduction` within `max_cycles` cycles; the search stops at the
+    first that does not and returns the last that did.  which "csg" sets the
+    CSG angle (a CSL description becomes uniform CSG), "csl" the shift
+    1 + i*value.  Returns (result dict, trace rows (value, cycles or 0, last
+    relative residual)).  Stops a candidate early once its residual exceeds
+    1e3 or is not finite."""
+    d = dict(desc)
+    d["csl_shift"] = list(d.get("csl_shift", [0.0, 0.0]))
+    if which == "csg":
+        d["csg_mode"] = 0 if int(d.get("csg_mode", 0)) == 2 else int(d.get("csg_mode", 0))
+    else:
+        d["csg_mode"] = 2
+    f = _c128(f).reshape(-1)
+    fn = nrm2(f)
+    value, res, trace = float(start), None, []
+    for _ in range(max_steps):
+        if abs(value) < min_value:
+            break
+        if which == "csg":
+            d["theta_csg"] = value
+        else:
+            d["csl_shift"] = [1.0, value]
+        g = Grid(d, phi)
+        u = np.zeros_like(f)
+        r = f.copy()
+        cycles, rel = 0, 1.0
+        for k in range(1, max_cycles + 1):
+            v = g.vcycle(r)
+            u = u + v
+            r = f - g.apply(u, "M")
+            rel = nrm2(r) / fn
+            if rel < reduction:
+                cycles = k
+                break
+            if not np.isfinite(rel) or rel > 1e3:
+                break
+        trace.append((value, cycles, rel))
+        if cycles == 0:
+            break
+        res = {"value": value, "cycles": cycles, "factor": rel ** (1.0 / cycles)}
+        value = value * factor
+    out = {"status": 0 if res else -4, "tried": len(trace)}
+    if res:
+        out.update(res)
+    return out, np.array(trace, dtype=float).reshape(-1, 3)

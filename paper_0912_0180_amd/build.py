@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhh.so")
-SOURCES = ["hh_setup.cpp", "hh_lib.hip", "hh_solve.hip", "hh_server.cpp"]
+SOURCES = ["hh_setup.cpp", "hh_lib.hip", "hh_solve.hip", "hh_select.hip", "hh_server.cpp"]
 HEADERS = ["hh_common.h", "hh_kernels.hpp", "hh_lib.h", "hh_setup.h", "hh_idr_kernels.hpp"]
 ARCH = os.environ.get("HH_OFFLOAD_ARCH", "gfx950")
 

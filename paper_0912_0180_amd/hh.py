@@ -24,7 +24,7 @@ BICGSTAB, IDR = 0, 1
 # every symbol include/hh.h declares
 EXPORTS = ["hh_setup_grid", "hh_free_grid", "hh_grid_query", "hh_grid_export", "hh_apply_operator", "hh_vcycle",
            "hh_vcycle_noalloc", "hh_profile_vcycle", "hh_solve", "hh_solve_batch", "hh_server_create", "hh_submit", "hh_poll", "hh_server_destroy",
-           "hh_server_query", "hh_request_footprint", "hh_last_error", "hh_version"]
+           "hh_server_query", "hh_request_footprint", "hh_select_preconditioner", "hh_last_error", "hh_version"]
 
 
 class HHError(RuntimeError):
@@ -71,6 +71,17 @@ class VcycleProfile(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SelectOpts(ctypes.Structure):
+    _fields_ = [("which", ctypes.c_int32), ("start", ctypes.c_double), ("factor", ctypes.c_double),
+                ("min_value", ctypes.c_double), ("max_cycles", ctypes.c_int32), ("reduction", ctypes.c_double),
+                ("max_steps", ctypes.c_int32)]
+
+
+class SelectResult(ctypes.Structure):
+    _fields_ = [("value", ctypes.c_double), ("cycles", ctypes.c_int32), ("factor", ctypes.c_double),
+                ("tried", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -125,11 +136,12 @@ def lib():
         L.hh_server_destroy.argtypes = [V]
         L.hh_server_query.argtypes = [V, P(ServerStats)]
         L.hh_request_footprint.argtypes = [P(GridDesc), P(SolveOpts), P(ctypes.c_uint64)]
+        L.hh_select_preconditioner.argtypes = [P(GridDesc), P(SelectOpts), V, P(SelectResult), V, V]
         L.hh_last_error.restype = ctypes.c_char_p
         L.hh_version.restype = ctypes.c_char_p
         for name in ["hh_setup_grid", "hh_free_grid", "hh_grid_query", "hh_grid_export", "hh_apply_operator",
                      "hh_vcycle", "hh_vcycle_noalloc", "hh_profile_vcycle", "hh_solve", "hh_solve_batch", "hh_server_create", "hh_submit", "hh_poll",
-                     "hh_server_destroy", "hh_server_query", "hh_request_footprint"]:
+                     "hh_server_destroy", "hh_server_query", "hh_request_footprint", "hh_select_preconditioner"]:
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -357,6 +369,25 @@ def solve_batch(grids, bs, xs=None, **kw):
     st = lib().hh_solve_batch(G, n, opts, B, X, infos, _stream(bs[0]))
     check(st, allow=(OK, -4, -5, -6))
     return xs, [infos[q].as_dict() for q in range(n)]
+
+
+def select_preconditioner(desc, f, phi=None, which="csg", start=math.pi / 4, factor=0.8, min_value=1e-3,
+                          max_cycles=20, reduction=1e-7, max_steps=30):
+    """hh_select_preconditioner: the smallest CSG angle (which "csg") or CSL
+    imaginary shift (which "csl") of the sequence start * factor^j at which
+    multigrid alone still converges; returns (result dict, trace rows)."""
+    d, keep = make_desc(desc, phi if phi is not None else desc.get("phi"))
+    o = SelectOpts()
+    o.which = 0 if which == "csg" else 1
+    o.start, o.factor, o.min_value = float(start), float(factor), float(min_value)
+    o.max_cycles, o.reduction, o.max_steps = int(max_cycles), float(reduction), int(max_steps)
+    r = SelectResult()
+    tr = np.zeros(3 * max_steps)
+    st = lib().hh_select_preconditioner(ctypes.byref(d), ctypes.byref(o), ctypes.c_void_p(f.data_ptr()),
+                                        ctypes.byref(r), tr.ctypes.data_as(ctypes.c_void_p), _stream(f))
+    check(st, allow=(OK, -4))
+    res = {k: getattr(r, k) for k, _ in r._fields_}
+    return res, tr.reshape(-1, 3)[: r.tried].copy()
 
 
 def shadow_to_device(P, device="cuda"):

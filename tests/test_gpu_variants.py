@@ -187,3 +187,24 @@ def test_mp3_full_size(torch_dev, hh_mod, oracle_mod):
         assert np.linalg.norm(c["b"] - o.apply(xh, "H")) / bn < 1e-8
     assert rel(host(xm), host(x64)) <= 1e-6
     print("mp3 1280^2 matvecs fp64", i64["matvecs"], "mixed", im["matvecs"], "fallback", im["fp64_fallback"], flush=True)
+
+
+@pytest.mark.parametrize("name,which,start,cycles", [("c1", "csg", math.pi / 4, 20), ("mp2_nu7k2", "csg", math.pi / 4, 30),
+                                                     ("c1", "csl", 2.0, 20),
+                                                     ("mp2_sommerfeld", "csg", -math.pi / 4, 20)])
+def test_preconditioner_selection_matches_oracle(torch_dev, hh_mod, oracle_mod, name, which, start, cycles):
+    """Sec. 6.2, remark on choosing the CSL and CSG parameters: the library's
+    search (FP64 V-cycles and operator applies, norms in the contract's order)
+    picks the oracle's value, with the same cycle counts and the same
+    residuals for every candidate."""
+    torch = torch_dev
+    c = VARIANTS[name]() if name in VARIANTS else W.c1()
+    print("case selection", name, which, flush=True)
+    ro, to = oracle_mod.select_preconditioner(c["desc"], c["phi"], c["b"], which=which, start=start,
+                                              max_cycles=cycles)
+    rg, tg = hh_mod.select_preconditioner(c["desc"], dev(torch, c["b"]), phi=c["phi"], which=which, start=start,
+                                          max_cycles=cycles)
+    assert rg["status"] == ro["status"] == 0 and rg["tried"] == ro["tried"]
+    assert rg["value"] == ro["value"] and rg["cycles"] == ro["cycles"]
+    assert np.array_equal(tg, to)
+    print(name, which, "chose %.4f after %d candidates, %d cycles" % (rg["value"], rg["tried"], rg["cycles"]), flush=True)

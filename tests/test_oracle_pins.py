@@ -696,6 +696,25 @@ def test_bicgstab_point_source_1d_matches_direct(oracle_mod):
     assert np.linalg.norm(x - xd) < 1e-7 * np.linalg.norm(xd)
 
 
+@pytest.mark.parametrize("which,start", [("csg", math.pi / 4), ("csl", 2.0)])
+def test_parameter_search_follows_its_definition(oracle_mod, which, start):
+    """Sec. 6.2, remark on choosing the CSL and CSG parameters: candidates
+    start * 0.8^j; each converged candidate reached 1e-7 within 20 cycles
+    (its last residual is below 1e-7 and the count within the budget), the
+    search stops at the first that did not, and the answer is the last that
+    did.  Multigrid needs more cycles as the stretch or shift shrinks (it moves
+    M towards the indefinite H)."""
+    d, phi, b = small_problem(n=(32, 32), k=25.0, levels=3)
+    res, tr = oracle_mod.select_preconditioner(d, phi, b, which=which, start=start, factor=0.8, max_cycles=20)
+    assert res["status"] == 0 and res["tried"] == len(tr) >= 2
+    vals = tr[:, 0]
+    assert np.allclose(vals, start * 0.8 ** np.arange(len(tr)), rtol=1e-15)
+    assert np.all((tr[:-1, 1] >= 1) & (tr[:-1, 1] <= 20) & (tr[:-1, 2] < 1e-7))
+    assert tr[-1, 1] == 0 and tr[-1, 2] >= 1e-7
+    assert res["value"] == tr[-2, 0] and res["cycles"] == tr[-2, 1]
+    assert np.all(np.diff(tr[:-1, 1]) >= 0)
+
+
 @pytest.mark.parametrize("s", [1, 2, 4])
 def test_idr_zero_shadow_space_breaks_down_and_restarts(oracle_mod, s):
     """With P = 0 the matrix G = P^H dR of IDR(s) is exactly zero at the end
