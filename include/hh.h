@@ -105,7 +105,8 @@ typedef struct {
                                multigrid or solve call rejects them with HH_ERR_ARG */
     int32_t levels;         /* multigrid levels; 0 = halve while every side is even and
                                the largest side exceeds 16 (2D) / 8 (3D); HH_VERTEX: 0 or 1 */
-    int32_t nu1, nu2;       /* smoothing steps; the library supports (1,1)               */
+    int32_t nu1, nu2;       /* smoothing steps: (1,1), or (0,1), the paper's V(0,1) cycle
+                               (Sec. 6.1: no pre-smoothing, one post-smoothing step)     */
     double omega;           /* Jacobi weight, e.g. 0.8                                   */
     const double *phi;      /* host, prod(n) reals: k(x)^2 at the cell centres; NULL ->
                                phi_const everywhere                                      */
@@ -136,7 +137,7 @@ typedef struct hh_grid hh_grid;   /* opaque */
  * on a cell-centred grid, given or from the automatic rule, more than 1 on a
  * vertex-centred one; side not divisible by 2^(levels-1); coarsest grid above
  * 1024 unknowns; theta outside (0, pi/2); a, b outside
- * [lo, hi]; nu1/nu2 other than 1; singular coarse matrix), HH_ERR_OOM,
+ * [lo, hi]; (nu1, nu2) not (1, 1) or (0, 1); singular coarse matrix), HH_ERR_OOM,
  * HH_ERR_HIP.  *out is set only on HH_OK. */
 hh_status hh_setup_grid(const hh_grid_desc *d, hh_grid **out);
 hh_status hh_free_grid(hh_grid *g);

@@ -240,6 +240,7 @@ struct ProbDev {
     uint32_t tseg64[HH_MAXLEV], tseg32[HH_MAXLEV];
     int tnseg64, tnseg32;
     double omega;
+    int nu1;                         // pre-smoothing steps of the V-cycle (0 or 1)
     void *vec[VS_NVEC];
     double2 *dR, *dX;                // IDR: s columns of N each
     int nidr;                        // IDR: s
@@ -261,6 +262,7 @@ struct Ctx {
     const Ctrl *ctrl;                // control blocks; null: every problem runs
     const void *L;                   // one problem: its LevelDev array in the V-cycle precision
     double omega;                    // one problem: Jacobi weight
+    int nu1;                         // one problem: pre-smoothing steps (1: V(1,1), 0: V(0,1))
 };
 
 // Levels with at most TailCap<T>::N unknowns (and every coarser level) run

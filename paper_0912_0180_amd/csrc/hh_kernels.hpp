@@ -866,6 +866,7 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vdown(Ctx cx, int lev, 
     C *__restrict__ fout = Lc.f;
     const TF *__restrict__ f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lf.f;
     const T omega = (T)(cx.L ? cx.omega : pd->omega);
+    const bool pre = (cx.L ? cx.nu1 : pd->nu1) != 0;   // V(1,1), or V(0,1) without pre-smoothing
     const int tx = (ncx + CX - 1) / CX, ty = (ncy + CY - 1) / CY;
     int t = tl.idx;
     const int bx = t % tx;
@@ -923,7 +924,7 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vdown(Ctx cx, int lev, 
             C D = cmk<T>(d.x - ph, d.y);
             T qq = jscale<T>(omega, D);
             C gw = cmk<T>(D.x * qq, -(D.y * qq));
-            u1 = cmul<T>(gw, fv);
+            if (pre) u1 = cmul<T>(gw, fv);
         }
         U[l] = u1;
         F[l] = fv;
@@ -1040,6 +1041,7 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, in
     const TF *__restrict__ f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lf.f;
     TO *__restrict__ outv = lev == 0 ? (TO *)(optr ? optr : pd->vec[osel]) : nullptr;
     const T omega = (T)(cx.L ? cx.omega : pd->omega);
+    const bool pre = (cx.L ? cx.nu1 : pd->nu1) != 0;   // V(1,1), or V(0,1) without pre-smoothing
     const int tx = (nfx + FX - 1) / FX, ty = (nfy + FY - 1) / FY;
     int t = tl.idx;
     const int bx = t % tx;
@@ -1114,7 +1116,7 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, in
             C D = cmk<T>(d.x - ph, d.y);
             T qq = jscale<T>(omega, D);
             C gw = cmk<T>(D.x * qq, -(D.y * qq));
-            C u1 = cmul<T>(gw, fv);
+            C u1 = pre ? cmul<T>(gw, fv) : zero;
             const int Ix = (gx >> 1) - ex0, Iox = ((gx & 1) ? (gx >> 1) + 1 : (gx >> 1) - 1) - ex0;
             const int Iy = (gy >> 1) - ey0, Ioy = ((gy & 1) ? (gy >> 1) + 1 : (gy >> 1) - 1) - ey0;
             C pe;
@@ -1264,6 +1266,7 @@ __global__ __launch_bounds__(NT) void k_vdown_m(Ctx cx, LvChain<T, K> lc)
     const int tid = threadIdx.x;
     const int run = phase_of(cx, 0);
     const T omega = (T)(cx.L ? cx.omega : cx.P->omega);
+    const bool pre = (cx.L ? cx.nu1 : cx.P->nu1) != 0;
     const int tx = (lc.L[K].n[0] + C - 1) / C;
     const int b = tile_of(cx).idx;
     const int cx0 = (b % tx) * C, cy0 = (b / tx) * C;
@@ -1348,7 +1351,7 @@ __global__ __launch_bounds__(NT) void k_vdown_m(Ctx cx, LvChain<T, K> lc)
                 Cx D = cmk<T>(d.x - pr[q], d.y);
                 T qq = jscale<T>(omega, D);
                 Cx gw = cmk<T>(D.x * qq, -(D.y * qq));
-                u1 = cmul<T>(gw, fr[q]);
+                if (pre) u1 = cmul<T>(gw, fr[q]);
             }
             U[l] = u1;
             F0[l] = fr[q];
@@ -1376,7 +1379,7 @@ __global__ __launch_bounds__(NT) void k_vdown_m(Ctx cx, LvChain<T, K> lc)
                     Cx D = cmk<T>(d.x - Pk[l], d.y);
                     T qq = jscale<T>(omega, D);
                     Cx gw = cmk<T>(D.x * qq, -(D.y * qq));
-                    u1 = cmul<T>(gw, Fk[l]);
+                    if (pre) u1 = cmul<T>(gw, Fk[l]);
                 }
                 U[l] = u1;
             }
@@ -1456,6 +1459,7 @@ __global__ __launch_bounds__(NT) void k_vup_m(Ctx cx, LvChain<T, K> lc)
     const int tid = threadIdx.x;
     const int run = phase_of(cx, 0);
     const T omega = (T)(cx.L ? cx.omega : cx.P->omega);
+    const bool pre = (cx.L ? cx.nu1 : cx.P->nu1) != 0;
     const int tx = (lc.L[0].n[0] + UT - 1) / UT;
     const int b = tile_of(cx).idx;
     // e regions: level 0 is the tile; level k + 1's covers the prolongation
@@ -1571,7 +1575,7 @@ __global__ __launch_bounds__(NT) void k_vup_m(Ctx cx, LvChain<T, K> lc)
                 Cx D = cmk<T>(d.x - Pk[l], d.y);
                 T qq = jscale<T>(omega, D);
                 Cx gw = cmk<T>(D.x * qq, -(D.y * qq));
-                Cx u1 = cmul<T>(gw, Fk[l]);
+                Cx u1 = pre ? cmul<T>(gw, Fk[l]) : zero;
                 const int Ix = (gx >> 1) - ox[k + 1], Iox = ((gx & 1) ? (gx >> 1) + 1 : (gx >> 1) - 1) - ox[k + 1];
                 const int Iy = (gy >> 1) - oy[k + 1], Ioy = ((gy & 1) ? (gy >> 1) + 1 : (gy >> 1) - 1) - oy[k + 1];
                 Cx a0 = cadd<T>(crs<T>(p3, Ec[Ix + WE * Iy]), crs<T>(p1, Ec[Iox + WE * Iy]));
@@ -1666,6 +1670,7 @@ __global__ __launch_bounds__(TileSet<3>::T[VT]) void k_vdown_z(Ctx cx, int lev, 
     C *__restrict__ fout = Lc.f;
     const TF *__restrict__ f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lf.f;
     const T omega = (T)(cx.L ? cx.omega : pd->omega);
+    const bool pre = (cx.L ? cx.nu1 : pd->nu1) != 0;   // V(1,1), or V(0,1) without pre-smoothing
     const int tx = (ncx + CX - 1) / CX, ty = (ncy + CY - 1) / CY;
     int t = tl.idx;
     const int bx = t % tx;
@@ -1772,7 +1777,7 @@ __global__ __launch_bounds__(TileSet<3>::T[VT]) void k_vdown_z(Ctx cx, int lev, 
                         C D = cmk<T>(d.x - pj[q], d.y);
                         T qq = jscale<T>(omega, D);
                         C gw = cmk<T>(D.x * qq, -(D.y * qq));
-                        u1 = cmul<T>(gw, fv);
+                        if (pre) u1 = cmul<T>(gw, fv);
                     }
                     Uj[l] = u1;
                 }
@@ -1899,6 +1904,7 @@ __global__ __launch_bounds__(TileSet<3>::T[VT]) void k_vup_z(Ctx cx, int lev, in
     const TF *__restrict__ f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lf.f;
     TO *__restrict__ outv = lev == 0 ? (TO *)(optr ? optr : pd->vec[osel]) : nullptr;
     const T omega = (T)(cx.L ? cx.omega : pd->omega);
+    const bool pre = (cx.L ? cx.nu1 : pd->nu1) != 0;   // V(1,1), or V(0,1) without pre-smoothing
     const int tx = (nfx + FX - 1) / FX, ty = (nfy + FY - 1) / FY;
     int t = tl.idx;
     const int bx = t % tx;
@@ -2020,7 +2026,7 @@ __global__ __launch_bounds__(TileSet<3>::T[VT]) void k_vup_z(Ctx cx, int lev, in
                         C D = cmk<T>(d.x - pj[q], d.y);
                         T qq = jscale<T>(omega, D);
                         C gw = cmk<T>(D.x * qq, -(D.y * qq));
-                        C u1 = cmul<T>(gw, fv);
+                        C u1 = pre ? cmul<T>(gw, fv) : zero;
                         const int Ix = ixq[q], Iox = ioxq[q], Iy = iyq[q], Ioy = ioyq[q];
                         C pz[2];
 #pragma unroll
@@ -2362,6 +2368,7 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
     const LevelDev<T> *Lv = levels_of<T>(cx, pd);
     const int t0 = tail_level<T>(pd), L = pd->nlev;
     const T omega = (T)pd->omega;
+    const bool pre = pd->nu1 != 0;
     const C zero = cmk<T>(0, 0);
     const int tid = threadIdx.x, nth = TailCap<T>::WG;
     __shared__ TailTab tab;
@@ -2464,7 +2471,7 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
         for (int p = tid; p < Q.N; p += nth) {
             int i, j, k;
             tail_ijk(Q, p, i, j, k);
-            U[p] = cmul<T>(jweight<T>(tail_diag<DIM, T>(Q, i, j, k, p), omega), Q.F[p]);
+            U[p] = pre ? cmul<T>(jweight<T>(tail_diag<DIM, T>(Q, i, j, k, p), omega), Q.F[p]) : zero;
         }
         __syncthreads();
         for (int p = tid; p < Q.N; p += nth) {
@@ -2541,7 +2548,7 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
         for (int p = tid; p < Q.N; p += nth) {
             int i, j, k;
             tail_ijk(Q, p, i, j, k);
-            C u1 = cmul<T>(jweight<T>(tail_diag<DIM, T>(Q, i, j, k, p), omega), Q.F[p]);
+            C u1 = pre ? cmul<T>(jweight<T>(tail_diag<DIM, T>(Q, i, j, k, p), omega), Q.F[p]) : zero;
             const int Ix = i >> 1, Iox = (i & 1) ? Ix + 1 : Ix - 1;
             const int Iy = j >> 1, Ioy = (j & 1) ? Iy + 1 : Iy - 1;
             // coarse values outside the level are zero (read clamped, then masked)

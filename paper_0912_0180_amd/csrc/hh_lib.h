@@ -37,6 +37,7 @@ struct Plan {
     const LevelDev<double> *lv64h = nullptr;   // one-problem plans: host copies of its level descriptors
     const LevelDev<float> *lv32h = nullptr;
     double omega1 = 0.8;
+    int nu1_1 = 1;                   // one-problem plans: pre-smoothing steps
     std::vector<ProbDev> host;       // host copies of the descriptors of the current solve
     void *mem = nullptr;
     size_t bytes = 0;

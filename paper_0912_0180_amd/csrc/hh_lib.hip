@@ -267,6 +267,7 @@ void grid_fill_prob(const hh_grid *g, ProbDev &pd)
     pd.Minv64 = g->Minv64;
     pd.Minv32 = g->Minv32;
     pd.omega = hs.omega;
+    pd.nu1 = hs.nu1;
     pd.tail64 = tail_level(hs, false);
     pd.tail32 = tail_level(hs, true);
     pd.csplit = hs.Nc > HH_SPLIT_NC ? 1 : 0;
@@ -554,6 +555,7 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
     if (pl.count == 1) {
         pl.L1 = fp32 ? (const void *)G[0]->L32 : (const void *)G[0]->L64;
         pl.omega1 = G[0]->hs.omega;
+        pl.nu1_1 = G[0]->hs.nu1;
         pl.lv64h = G[0]->L64h;
         pl.lv32h = G[0]->L32h;
     }
@@ -590,6 +592,7 @@ static Ctx ctx_of(const Plan &pl, const DevList &tiles)
     c.ctrl = pl.ctrl;
     c.L = pl.count == 1 ? pl.L1 : nullptr;
     c.omega = pl.omega1;
+    c.nu1 = pl.nu1_1;
     return c;
 }
 
@@ -730,6 +733,7 @@ static int tune_leg(const hh_grid *g, bool fp32, int leg, int l)
         c.ctrl = nullptr;
         c.L = fp32 ? (const void *)g->L32 : (const void *)g->L64;
         c.omega = hs.omega;
+        c.nu1 = hs.nu1;
         LvHost lh;
         lh.d = g->L64h;
         lh.f = g->L32h;
@@ -840,6 +844,7 @@ static void plan_host_one(Plan &pl, const hh_grid *g, bool fp32, const void *L1,
     pl.ctrl = nullptr;
     pl.L1 = L1;
     pl.omega1 = hs.omega;
+    pl.nu1_1 = hs.nu1;
     pl.lv64h = lv64h;
     pl.lv32h = lv32h;
 }
@@ -1158,6 +1163,7 @@ hh_status hh_apply_operator(const hh_grid *g, hh_op op, hh_prec prec, const void
     c.ctrl = nullptr;
     c.L = prec == HH_C64 ? (const void *)g->L32 : (const void *)g->L64;
     c.omega = g->hs.omega;
+    c.nu1 = g->hs.nu1;
     if (op == HH_OP_H) {
         if (prec != HH_C128) return hh_fail(HH_ERR_ARG, "H is applied in complex double only");
         const int nx = g->hs.lev[0].n[0], ny = g->hs.lev[0].n[1];

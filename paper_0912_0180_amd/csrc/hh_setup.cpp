@@ -240,7 +240,10 @@ hh_status desc_check(const hh_grid_desc *d, int &levels, int &coarse, std::strin
     }
     if (d->contour_steps < 0 || d->contour_steps > 65536) { err = "contour_steps must lie in [0, 65536]"; return HH_ERR_ARG; }
     if (d->centering != HH_CELL && d->centering != HH_VERTEX) { err = "centering must be 0 (cell) or 1 (vertex)"; return HH_ERR_ARG; }
-    if (d->nu1 != 1 || d->nu2 != 1) { err = "only the V(1,1) cycle is supported (nu1 = nu2 = 1)"; return HH_ERR_ARG; }
+    if ((d->nu1 != 0 && d->nu1 != 1) || d->nu2 != 1) {
+        err = "the cycle is V(1,1) or the paper's V(0,1): nu1 = 0 or 1, nu2 = 1";
+        return HH_ERR_ARG;
+    }
     if (!(d->omega > 0.0 && d->omega < 2.0)) { err = "omega must lie in (0, 2)"; return HH_ERR_ARG; }
     int64_t N = 1;
     for (int a = 0; a < dim; ++a) {
@@ -306,6 +309,7 @@ hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err)
     hs.nlev = nl;
     hs.omega = d->omega;
     hs.centering = d->centering;
+    hs.nu1 = d->nu1;
     const bool vertex = d->centering == HH_VERTEX;
     const double cg = std::cos(d->theta_ecs), sg = std::sin(d->theta_ecs);
     const double2 beta = d->csg_mode == HH_CSL ? principal_sqrt(cmk<double>(d->csl_shift[0], d->csl_shift[1]))

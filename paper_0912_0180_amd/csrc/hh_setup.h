@@ -17,6 +17,7 @@ struct HostLevel {
 struct HostSetup {
     int dim = 2, nlev = 1;
     int centering = HH_CELL;                    // HH_VERTEX: one level, no hierarchy
+    int nu1 = 1;                                // pre-smoothing steps: 1 (V(1,1)) or 0 (V(0,1))
     double omega = 0.8;
     std::vector<double2> aH[3], cH[3], dH[3];   // finest level, ECS operator
     HostLevel lev[HH_MAXLEV];

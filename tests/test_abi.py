@@ -252,3 +252,13 @@ def test_variant_validation():
     d2 = dict(base)
     d2.update(theta_csg=-math.pi / 20)              # negative angles are the Sommerfeld tables' choice
     assert host_grid(d2).levels == 4
+
+
+def test_paper_cycle_v01_accepted():
+    d = dict(W.c1()["desc"])
+    d["nu1"] = 0
+    assert host_grid(d).levels == 4
+    for nu1, nu2 in ((0, 0), (1, 2), (2, 1)):
+        d.update(nu1=nu1, nu2=nu2)
+        with pytest.raises(hh.HHError):
+            host_grid(d)

@@ -208,3 +208,57 @@ def test_preconditioner_selection_matches_oracle(torch_dev, hh_mod, oracle_mod, 
     assert rg["value"] == ro["value"] and rg["cycles"] == ro["cycles"]
     assert np.array_equal(tg, to)
     print(name, which, "chose %.4f after %d candidates, %d cycles" % (rg["value"], rg["tried"], rg["cycles"]), flush=True)
+
+
+def _v01(c):
+    c["desc"]["nu1"] = 0
+    return c
+
+
+# every kernel path of the cycle: box-tile legs, merged 2D legs (256^2, the
+# full 1024^2), the one-workgroup tail, the split coarsest solve, 3D box and
+# z-streaming legs, a ragged 3D grid
+V01_CASES = {
+    "c1": lambda: _v01(W.c1()),
+    "c2_256": lambda: _v01(W.c2(n=256, levels=6)),
+    "c2_1024": lambda: _v01(W.c2()),
+    "c2_384_split": lambda: _v01(W.c2(n=384, levels=5)),
+    "c3_32": lambda: _v01(W.c3(n=32, layer=4, method="bicgstab")),
+    "c3_64": lambda: _v01(W.c3(n=64, layer=8, method="bicgstab")),
+    "mp2_nu7k2": lambda: _v01(W.mp2(n_int=96, n_lay=32, r=12.5)),
+}
+
+
+@pytest.mark.parametrize("name", list(V01_CASES))
+def test_v01_cycle_matches_oracle(torch_dev, hh_mod, oracle_mod, name):
+    """The paper's V(0,1) cycle (Sec. 6.1: no pre-smoothing, one post-smoothing
+    step) equals the oracle's value for value in FP64, in every kernel path."""
+    torch = torch_dev
+    c = V01_CASES[name]()
+    print("case v01", name, flush=True)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    rng = np.random.default_rng(51)
+    f = rng.standard_normal(g.N) + 1j * rng.standard_normal(g.N)
+    fd = dev(torch, f)
+    ref = o.vcycle(f)
+    assert same(host(g.vcycle(fd, "c128")), ref)
+    assert rel(host(g.vcycle(fd, "c64")).astype(np.complex128), ref) < 1e-4
+    assert same(host(g.vcycle_noalloc(fd, "c128")), ref)
+
+
+@pytest.mark.parametrize("name,method", [("c1", "bicgstab"), ("mp2_nu7k2", "bicgstab"), ("mp2_nu7k2", "idr"),
+                                         ("c3_32", "bicgstab")])
+def test_v01_solves_match_oracle(torch_dev, hh_mod, oracle_mod, name, method):
+    torch = torch_dev
+    c = V01_CASES[name]()
+    print("case v01 solve", name, method, flush=True)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    P = W.shadow_space(g.N, 4, 4004)
+    xo, io = o.solve(c["b"], method=method, s=4, P=P, tol=1e-8, history=True)
+    xg, ig = g.solve(dev(torch, c["b"]), method=method, s=4, P=hh_mod.shadow_to_device(P), tol=1e-8,
+                     vcycle_prec="c128", history=True)
+    assert io["status"] == 0 == ig["status"] and ig["matvecs"] == io["matvecs"]
+    assert np.array_equal(ig["history"], io["history"]) and same(host(xg), xo)
+    print(name, method, "V(0,1) matvecs", io["matvecs"], flush=True)

@@ -194,18 +194,20 @@ def kron_x_fastest(mats):
     return out
 
 
-def test_vcycle_equals_three_level_matrix(oracle_mod):
+@pytest.mark.parametrize("nu1", [1, 0])
+def test_vcycle_equals_three_level_matrix(oracle_mod, nu1):
     """Three-level V(1,1) from explicitly assembled pieces:
     each level's M from a separate one-level grid of that size whose phi is
     the mean of the finer level's children (computed here), full weighting
     R = kron of (1,3,3,1)/8, bilinear P = 4 R^T, weighted Jacobi
     J = omega D^-1, exact solve on the coarsest level:
-      B_2 = M_2^-1,  B_l = (I - J M)(J + P B_{l+1} R (I - M J)) + J."""
+      V(1,1): B_2 = M_2^-1,  B_l = (I - J M)(J + P B_{l+1} R (I - M J)) + J;
+      V(0,1) (the paper's cycle, Sec. 6.1): B_l = (I - J M) P B_{l+1} R + J."""
     n0 = (16, 12)
     lo, hi, a, b = (-0.25, -0.25), (1.25, 1.25), (0.0, 0.0), (1.0, 1.0)
     rng = np.random.default_rng(16)
     phi0 = 150.0 + 60.0 * rng.uniform(size=n0[0] * n0[1])
-    g = oracle_mod.Grid(W.base_desc(2, n0, lo, hi, a, b, levels=3), phi0)
+    g = oracle_mod.Grid(W.base_desc(2, n0, lo, hi, a, b, levels=3, nu1=nu1), phi0)
     Ms, phis, ns = [], [phi0], [n0]
     for lev in range(3):
         n = ns[lev]
@@ -224,7 +226,7 @@ def test_vcycle_equals_three_level_matrix(oracle_mod):
         P = 4.0 * R.T
         J = 0.8 * np.diag(1.0 / np.diag(M))
         I = np.eye(N)
-        B = (I - J @ M) @ (J + P @ B @ R @ (I - M @ J)) + J
+        B = (I - J @ M) @ (J + P @ B @ R @ (I - M @ J)) + J if nu1 else (I - J @ M) @ P @ B @ R + J
     f = rng.standard_normal(g.N) + 1j * rng.standard_normal(g.N)
     want = B @ f
     assert np.linalg.norm(g.vcycle(f) - want) < 1e-11 * np.linalg.norm(want)
