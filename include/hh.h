@@ -243,6 +243,9 @@ typedef struct {
                                    stalled or rose far above its best) and was
                                    finished from its current iterate with the FP64
                                    V-cycle; matvecs and iterations count both parts */
+    int32_t stages;             /* mixed precision: stages run (each restarts from
+                                   the FP64 true residual after a fixed reduction;
+                                   not counted in `restarts`); 0 in FP64           */
 } hh_solve_info;
 
 /* Solves H x = b by right-preconditioned Bi-CGSTAB or IDR(s) with M^{-1}

@@ -20,6 +20,11 @@ struct KProb {
     bool closed = false;
     bool drift = false;     // stopped by the mixed-precision guard
     int mv0 = 0, it0 = 0;   // counts carried over from an earlier phase of the solve
+    // staged mixed-precision solve: the true residual at the start of the
+    // current stage, the stages begun so far, the current stage tolerance
+    double stage_rel = 1.0;
+    int stages = 0;
+    double stage_tol = 0.0;
     SolveState S{};         // last state read back
     void *tag = nullptr;    // owner's handle
     uint64_t serial = 0;    // set when the problem first joins a batch
@@ -70,6 +75,7 @@ class KBatch {
     int *sub_p_ = nullptr;
     int K_;
     bool graph_;
+    double stage_;          // mixed precision: each stage reduces the true residual by this factor
     double drift_grow_;
     int drift_stall_;
 };

@@ -182,6 +182,14 @@ enum Phase { PH_RUN = 0, PH_HALF = 1, PH_STOP = 2, PH_IDLE = 3 };
 // the best one since the last (re)start, or no new best for a long stretch,
 // stops the solve so the host continues it from the current iterate with
 // the FP64 V-cycle.
+// Stage factors of mixed-precision solves (see KBatch): each stage restarts
+// from the FP64 true residual once the recurrence residual has dropped by
+// this factor.  Measured on 1024^2, a 5.4-points-per-wavelength 512^2 problem,
+// MP2/MP3 and 1536^2/2048^2 grids: 1e-1 for Bi-CGSTAB (no FP64 fallback
+// left, 1024^2 147 ms against 167 ms unstaged); IDR(4) loses with frequent
+// stages (128^3: 497 matvecs at 1e-1 against 396) and takes 1e-4.
+#define HH_MIXED_STAGE_BICG 1e-1
+#define HH_MIXED_STAGE_IDR 1e-4
 #define HH_DRIFT_GROW 1000.0
 #define HH_DRIFT_STALL 300           // 0: no stall test
 

@@ -7,7 +7,9 @@
 // and a false stop or a breakdown restarts from the true residual).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -127,6 +129,22 @@ KBatch::KBatch(int method, bool fp32, Plan *external) : method_(method), fp32_(f
     const char *eg = getenv("HH_DRIFT_GROW"), *es = getenv("HH_DRIFT_STALL");
     drift_grow_ = eg ? atof(eg) : HH_DRIFT_GROW;
     drift_stall_ = es ? atoi(es) : HH_DRIFT_STALL;
+    // Mixed precision runs in stages: each stops once the recurrence residual
+    // has dropped by a fixed factor from the stage's starting true residual,
+    // and the next restarts from the FP64 true residual with a fresh shadow
+    // vector.  An FP32 V-cycle differs by rounding from one application to
+    // the next; the short recurrences of Bi-CGSTAB and IDR(s) assume one fixed
+    // preconditioner, and on indefinite problems that mismatch accumulates
+    // (relative perturbations of 1e-7 double the matvecs of a 5.4-points-per-
+    // wavelength problem, and the FP32 cycle stalls it).  A restart discards
+    // the accumulated mismatch.  Bi-CGSTAB restarts cheaply and gains from
+    // frequent stages; an IDR(s) restart repeats s start-up steps and rebuilds
+    // its shadow-space matrix, so it takes rare ones.  HH_MIXED_STAGE sets the
+    // factor for both, 0 turns stages off.
+    const char *st = getenv("HH_MIXED_STAGE");
+    const double def = method == HH_METHOD_BICGSTAB ? HH_MIXED_STAGE_BICG : HH_MIXED_STAGE_IDR;
+    stage_ = fp32_ ? (st ? atof(st) : def) : 0.0;
+    if (!(stage_ > 0.0 && stage_ < 1.0)) stage_ = 0.0;
 }
 
 KBatch::~KBatch()
@@ -254,7 +272,10 @@ hh_status KBatch::start(const std::vector<KProb *> &probs)
         SolveState st;
         memset(&st, 0, sizeof st);
         st.phase = PH_IDLE;
-        st.tol = p->o.tol;
+        p->stage_rel = 1.0;
+        p->stages = stage_ > 0.0 ? 1 : 0;
+        p->stage_tol = stage_ > 0.0 ? std::max(p->o.tol, stage_) : p->o.tol;
+        st.tol = p->stage_tol;
         st.max_mv = p->o.max_matvec;
         st.hist_len = p->o.history ? p->o.history_len : 0;
         st.s = method_ == HH_METHOD_IDR ? p->o.s : 0;
@@ -374,6 +395,7 @@ hh_status KBatch::close(const std::vector<int> &which, std::vector<KProb *> &clo
         in.matvecs = S.mv;
         in.iterations = S.it;
         in.restarts = p->restarts;
+        in.stages = p->stages;
         in.rel_res_recurrence = S.bnorm > 0.0 ? S.rel : 0.0;
         in.rel_res_true = S.bnorm > 0.0 ? S.true_rel : 0.0;
         if (p->status == HH_ERR_NONFINITE) in.rel_res_true = NAN;
@@ -434,6 +456,15 @@ hh_status KBatch::collect(std::vector<KProb *> &closed)
                 if (p->S.reason == RS_CONV && p->S.true_rel < p->o.tol) {
                     p->done = true;
                     p->status = HH_OK;
+                } else if (stage_ > 0.0 && p->S.reason == RS_CONV && p->S.true_rel < p->stage_rel) {
+                    // a stage ended with progress: the next one starts from
+                    // the true residual and aims `stage_` lower
+                    p->stage_rel = p->S.true_rel;
+                    p->stages++;
+                    p->stage_tol = std::max(p->o.tol, stage_ * p->S.true_rel);
+                    HIPCHK(hipMemcpyAsync((char *)p->g->ws.st + offsetof(SolveState, tol), &p->stage_tol,
+                                          sizeof(double), hipMemcpyHostToDevice, s));
+                    restart.push_back(q);
                 } else if (p->restarts >= p->o.max_restarts) {
                     p->done = true;
                     p->status = p->S.reason == RS_BREAK ? HH_ERR_BREAKDOWN : HH_ERR_NOCONV;
@@ -567,8 +598,10 @@ extern "C" hh_status hh_solve_batch(hh_grid *const *g, int32_t count, const hh_s
         rc = run_phase(eg.data(), ep, o[0].method, false, s);
         if (rc != HH_OK) return rc;
         for (size_t i = 0; i < eq.size(); ++i) {
+            const int st0 = K[eq[i]].info.stages;
             K[eq[i]].info = E[i].info;
             K[eq[i]].info.fp64_fallback = 1;
+            K[eq[i]].info.stages = st0;
         }
     }
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

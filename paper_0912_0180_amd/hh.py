@@ -58,7 +58,8 @@ class SolveOpts(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("matvecs", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("restarts", ctypes.c_int32), ("rel_res_recurrence", ctypes.c_double),
-                ("rel_res_true", ctypes.c_double), ("seconds", ctypes.c_double), ("fp64_fallback", ctypes.c_int32)]
+                ("rel_res_true", ctypes.c_double), ("seconds", ctypes.c_double), ("fp64_fallback", ctypes.c_int32),
+                ("stages", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

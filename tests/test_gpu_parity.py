@@ -178,6 +178,7 @@ def test_mixed_drift_falls_back_to_fp64(torch_dev, hh_mod, monkeypatch):
         bs.append(b)
         x64s.append(host(x64))
     monkeypatch.setenv("HH_DRIFT_STALL", "3")
+    monkeypatch.setenv("HH_MIXED_STAGE", "0")   # the guard alone, without stage restarts
     alone = []
     for g, b, x64 in zip(grids, bs, x64s):
         xm, im = g.solve(b, tol=1e-8, vcycle_prec="c64", history=True)
@@ -207,6 +208,40 @@ def test_underresolved_mixed_solve_is_correct(torch_dev, hh_mod):
     print("5.4 ppw 512^2: fp64 matvecs", i64["matvecs"], "mixed", im["matvecs"], "fallback", im["fp64_fallback"])
     assert i64["status"] == 0 and im["status"] == 0 and im["rel_res_true"] < 1e-8
     assert rel(host(xm), host(x64)) <= 1e-6
+
+
+def big_2d(n, ppw, seed):
+    g = W.rng(seed)
+    d = W.base_desc(2, (n, n), (-0.25, -0.25), (1.25, 1.25), (0.0, 0.0), (1.0, 1.0))
+    h = 1.5 / n
+    k0 = 2 * math.pi / (ppw * h)
+    phi = W.bump_k(d, k0, g.uniform(0.15, 0.85, size=(8, 2)))
+    b = W.gaussian_sources(d, g.uniform(0.1, 0.9, size=(3, 2)))
+    return {"desc": d, "phi": phi, "b": b}
+
+
+@pytest.mark.parametrize("n,ppw,seed", [(1280, 10.0, 7), (1536, 10.0, 7)])
+def test_staged_mixed_solve_needs_no_fp64_fallback(torch_dev, hh_mod, monkeypatch, n, ppw, seed):
+    """2D grids of 1216^2 and more at 10 points per wavelength used to drift
+    in mixed precision and fall back to the FP64 V-cycle.  Run in stages, each
+    restarting from the FP64 true residual after a tenfold reduction, the mixed
+    Bi-CGSTAB solve reaches 1e-8 without the fallback and agrees with the FP64
+    solve; with stages off it is the old unstaged iteration."""
+    torch = torch_dev
+    c = big_2d(n, ppw, seed)
+    print("case staged mixed", n, ppw, flush=True)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    b = dev(torch, c["b"])
+    x64, i64 = g.solve(b, tol=1e-8, vcycle_prec="c128")
+    xm, im = g.solve(b, tol=1e-8, vcycle_prec="c64")
+    assert i64["status"] == 0 and i64["stages"] == 0
+    assert im["status"] == 0 and im["fp64_fallback"] == 0 and im["stages"] > 1 and im["rel_res_true"] < 1e-8
+    assert rel(host(xm), host(x64)) <= 1e-6
+    monkeypatch.setenv("HH_MIXED_STAGE", "0")
+    xu, iu = g.solve(b, tol=1e-8, vcycle_prec="c64")
+    assert iu["stages"] == 0 and iu["status"] == 0 and iu["rel_res_true"] < 1e-8
+    print(n, "matvecs fp64", i64["matvecs"], "staged mixed", im["matvecs"], "stages", im["stages"],
+          "unstaged mixed", iu["matvecs"], "fallback", iu["fp64_fallback"], flush=True)
 
 
 def test_batch_equals_single(torch_dev, hh_mod):

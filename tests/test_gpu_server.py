@@ -187,6 +187,7 @@ def test_server_drift_fallback_matches_alone(hh_mod, monkeypatch):
     alone; a request in FP64 from the start is unaffected."""
     hh = hh_mod
     monkeypatch.setenv("HH_DRIFT_STALL", "3")
+    monkeypatch.setenv("HH_MIXED_STAGE", "0")   # the guard alone, without stage restarts
     req = small_request(seed=32, dim=2, n=128)
     xa, ia = solve_alone(hh, req)
     assert ia["fp64_fallback"] == 1
