@@ -825,7 +825,7 @@ __global__ __launch_bounds__(HH_WG) void k_applyM(Ctx cx, const void *xp, void *
 // with a halo of 2 (restriction footprint + stencil).
 // ---------------------------------------------------------------------------
 template <int DIM, typename T, typename TF, int VT>
-__global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vdown(Ctx cx, int lev, int fsel, const void *fptr, LvPair<T> lp)
+__device__ __forceinline__ void vdown_box(Ctx cx, int lev, int fsel, const void *fptr, LvPair<T> lp)
 {
     using C = V2<T>;
     constexpr int CX = TileSet<DIM>::X[VT], CY = TileSet<DIM>::Y[VT], CZ = DIM == 3 ? TileSet<DIM>::Z[VT] : 1;
@@ -834,9 +834,11 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vdown(Ctx cx, int lev, 
     constexpr int RN = RX * RY * RZ;
     constexpr int RM = RX > RY ? (RX > RZ ? RX : RZ) : (RY > RZ ? RY : RZ);
     constexpr int NL = (RN + NT - 1) / NT;
+    // u1 and the residual go through LDS (the stencil and the restriction
+    // read neighbours); each thread keeps f and the diagonal of the box points
+    // it loaded in registers for the residual at the same points
     __shared__ C U[RN];
-    __shared__ C F[RN];
-    __shared__ T PH[RN];
+    __shared__ C R[RN];
     __shared__ C A[3][RM];
     __shared__ C Cc[3][RM];
     __shared__ C Dd[3][RM];
@@ -907,6 +909,7 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vdown(Ctx cx, int lev, 
     }
     if (run != PH_RUN) return;   // uniform over the workgroup
     __syncthreads();
+    C fk[NL], Dk[NL];
     // step 1: u1 = g f on the whole box
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
@@ -914,48 +917,45 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vdown(Ctx cx, int lev, 
         if (l >= RN) break;
         const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
         const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
-        C fv = zero, u1 = zero;
-        T ph = 0;
+        C u1 = zero;
+        fk[q] = Dk[q] = zero;
         if (gx >= 0 && gx < nfx && gy >= 0 && gy < nfy && (DIM == 2 || (gz >= 0 && gz < nfz))) {
-            fv = ccvt<T>(fr[q]);
-            ph = pr[q];
+            const C fv = ccvt<T>(fr[q]);
             C d = cadd<T>(Dd[0][lx], Dd[1][ly]);
             if (DIM == 3) d = cadd<T>(d, Dd[2][lz]);
-            C D = cmk<T>(d.x - ph, d.y);
+            C D = cmk<T>(d.x - pr[q], d.y);
             T qq = jscale<T>(omega, D);
             C gw = cmk<T>(D.x * qq, -(D.y * qq));
+            fk[q] = fv;
+            Dk[q] = D;
             if (pre) u1 = cmul<T>(gw, fv);
         }
         U[l] = u1;
-        F[l] = fv;
-        PH[l] = ph;
     }
     __syncthreads();
-    // step 2: r = f - M u1 on the box minus its outer ring, in place in F
-    {
-        constexpr int QX = RX - 2, QY = RY - 2, QZ = DIM == 3 ? RZ - 2 : 1;
-        for (int r = threadIdx.x; r < QX * QY * QZ; r += NT) {
-            const int lx = 1 + r % QX, ly = 1 + (r / QX) % QY, lz = (DIM == 3 ? 1 : 0) + r / (QX * QY);
-            const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
-            const int l = lx + RX * (ly + RY * lz);
-            C res = zero;
-            if (gx >= 0 && gx < nfx && gy >= 0 && gy < nfy && (DIM == 2 || (gz >= 0 && gz < nfz))) {
-                C d = cadd<T>(Dd[0][lx], Dd[1][ly]);
-                if (DIM == 3) d = cadd<T>(d, Dd[2][lz]);
-                C D = cmk<T>(d.x - PH[l], d.y);
-                C mu = cmul<T>(D, U[l]);
-                mu = csub<T>(mu, cmul<T>(A[0][lx], U[l - 1]));
-                mu = csub<T>(mu, cmul<T>(Cc[0][lx], U[l + 1]));
-                mu = csub<T>(mu, cmul<T>(A[1][ly], U[l - RX]));
-                mu = csub<T>(mu, cmul<T>(Cc[1][ly], U[l + RX]));
-                if (DIM == 3) {
-                    mu = csub<T>(mu, cmul<T>(A[2][lz], U[l - RX * RY]));
-                    mu = csub<T>(mu, cmul<T>(Cc[2][lz], U[l + RX * RY]));
-                }
-                res = csub<T>(F[l], mu);
+    // step 2: r = f - M u1 on the box minus its outer ring (the restriction's
+    // footprint), zero outside the grid, for the points each thread loaded
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int l = threadIdx.x + q * NT;
+        if (l >= RN) break;
+        const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
+        if (lx == 0 || lx == RX - 1 || ly == 0 || ly == RY - 1 || (DIM == 3 && (lz == 0 || lz == RZ - 1))) continue;
+        const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+        C res = zero;
+        if (gx >= 0 && gx < nfx && gy >= 0 && gy < nfy && (DIM == 2 || (gz >= 0 && gz < nfz))) {
+            C mu = cmul<T>(Dk[q], U[l]);
+            mu = csub<T>(mu, cmul<T>(A[0][lx], U[l - 1]));
+            mu = csub<T>(mu, cmul<T>(Cc[0][lx], U[l + 1]));
+            mu = csub<T>(mu, cmul<T>(A[1][ly], U[l - RX]));
+            mu = csub<T>(mu, cmul<T>(Cc[1][ly], U[l + RX]));
+            if (DIM == 3) {
+                mu = csub<T>(mu, cmul<T>(A[2][lz], U[l - RX * RY]));
+                mu = csub<T>(mu, cmul<T>(Cc[2][lz], U[l + RX * RY]));
             }
-            F[l] = res;
+            res = csub<T>(fk[q], mu);
         }
+        R[l] = res;
     }
     __syncthreads();
     // step 3: full weighting, x then y then z
@@ -972,7 +972,7 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vdown(Ctx cx, int lev, 
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const T wy = (b == 0 || b == 3) ? w0 : w1;
-                const C *row = &F[bxl + RX * ((byl + b) + RY * (bzl + c))];
+                const C *row = &R[bxl + RX * ((byl + b) + RY * (bzl + c))];
                 C sx = crs<T>(w0, row[0]);
                 sx = cadd<T>(sx, crs<T>(w1, row[1]));
                 sx = cadd<T>(sx, crs<T>(w1, row[2]));
@@ -992,8 +992,7 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vdown(Ctx cx, int lev, 
 // Output: e_lev (lev >= 1) or the output vector (lev == 0, storage TO).
 // ---------------------------------------------------------------------------
 template <int DIM, typename T, typename TF, typename TO, int VT>
-__global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, int fsel, int osel, const void *fptr, void *optr,
-                                                LvPair<T> lp)
+__device__ __forceinline__ void vup_box(Ctx cx, int lev, int fsel, int osel, const void *fptr, void *optr, LvPair<T> lp)
 {
     using C = V2<T>;
     constexpr int CX = TileSet<DIM>::X[VT], CY = TileSet<DIM>::Y[VT], CZ = DIM == 3 ? TileSet<DIM>::Z[VT] : 1;
@@ -1006,9 +1005,10 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, in
     constexpr int RM = RX > RY ? (RX > RZ ? RX : RZ) : (RY > RZ ? RY : RZ);
     constexpr int NL = (RN + NT - 1) / NT;
     constexpr int NE = (EN + NT - 1) / NT;
+    // only u2 goes through LDS (the stencil reads its neighbours); each
+    // thread keeps f, the diagonal and the Jacobi weight of the box points it
+    // loaded in registers for the post-smoothing of the same points
     __shared__ C U[RN];
-    __shared__ C F[RN];
-    __shared__ T PH[RN];
     __shared__ C E[EN];
     __shared__ C A[3][RM];
     __shared__ C Cc[3][RM];
@@ -1099,6 +1099,7 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, in
     if (run != PH_RUN) return;   // uniform over the workgroup
     __syncthreads();
     const T p3 = (T)0.75, p1 = (T)0.25;
+    C fk[NL], Dk[NL], gk[NL];
     // step 1: u2 = g f + P e on the tile plus a halo of one
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
@@ -1107,15 +1108,18 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, in
         const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
         const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
         C fv = zero, u2 = zero;
-        T ph = 0;
+        fk[q] = Dk[q] = gk[q] = zero;
         if (gx >= 0 && gx < nfx && gy >= 0 && gy < nfy && (DIM == 2 || (gz >= 0 && gz < nfz))) {
             fv = ccvt<T>(fr[q]);
-            ph = pr[q];
+            const T ph = pr[q];
             C d = cadd<T>(Dd[0][lx], Dd[1][ly]);
             if (DIM == 3) d = cadd<T>(d, Dd[2][lz]);
             C D = cmk<T>(d.x - ph, d.y);
             T qq = jscale<T>(omega, D);
             C gw = cmk<T>(D.x * qq, -(D.y * qq));
+            fk[q] = fv;
+            Dk[q] = D;
+            gk[q] = gw;
             C u1 = pre ? cmul<T>(gw, fv) : zero;
             const int Ix = (gx >> 1) - ex0, Iox = ((gx & 1) ? (gx >> 1) + 1 : (gx >> 1) - 1) - ex0;
             const int Iy = (gy >> 1) - ey0, Ioy = ((gy & 1) ? (gy >> 1) + 1 : (gy >> 1) - 1) - ey0;
@@ -1139,21 +1143,19 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, in
             u2 = cadd<T>(u1, pe);
         }
         U[l] = u2;
-        F[l] = fv;
-        PH[l] = ph;
     }
     __syncthreads();
-    // step 2: post-smoothing on the tile
-    for (int r = threadIdx.x; r < FX * FY * FZ; r += NT) {
-        const int lx = 1 + r % FX, ly = 1 + (r / FX) % FY, lz = (DIM == 3 ? 1 : 0) + r / (FX * FY);
+    // step 2: post-smoothing on the tile (the box points this thread owns,
+    // the halo left out)
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int l = threadIdx.x + q * NT;
+        if (l >= RN) break;
+        const int lx = l % RX, ly = (l / RX) % RY, lz = l / (RX * RY);
+        const bool halo = lx == 0 || lx == RX - 1 || ly == 0 || ly == RY - 1 || (DIM == 3 && (lz == 0 || lz == RZ - 1));
         const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
-        if (gx >= nfx || gy >= nfy || (DIM == 3 && gz >= nfz)) continue;
-        const int l = lx + RX * (ly + RY * lz);
-        C d = cadd<T>(Dd[0][lx], Dd[1][ly]);
-        if (DIM == 3) d = cadd<T>(d, Dd[2][lz]);
-        C D = cmk<T>(d.x - PH[l], d.y);
-        T qq = jscale<T>(omega, D);
-        C gw = cmk<T>(D.x * qq, -(D.y * qq));
+        if (halo || gx >= nfx || gy >= nfy || (DIM == 3 && gz >= nfz)) continue;
+        const C D = Dk[q], gw = gk[q];
         C mu = cmul<T>(D, U[l]);
         mu = csub<T>(mu, cmul<T>(A[0][lx], U[l - 1]));
         mu = csub<T>(mu, cmul<T>(Cc[0][lx], U[l + 1]));
@@ -1163,7 +1165,7 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, in
             mu = csub<T>(mu, cmul<T>(A[2][lz], U[l - RX * RY]));
             mu = csub<T>(mu, cmul<T>(Cc[2][lz], U[l + RX * RY]));
         }
-        C u = cadd<T>(U[l], cmul<T>(gw, csub<T>(F[l], mu)));
+        C u = cadd<T>(U[l], cmul<T>(gw, csub<T>(fk[q], mu)));
         const int64_t p = gx + sy * gy + sz * gz;
         if (lev == 0) {
             TO o;
@@ -1174,6 +1176,461 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, in
             stg(eout, p, u);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// 2D forms of the fused legs.  A workgroup owns the same coarse tile as the
+// box form, and every point's arithmetic is the box form's, operation for
+// operation; only the assignment of points to threads differs.  Thread
+// (tx, ty) = (t mod FX, t / FX) owns fine column tx of rows ty, ty + PR, ...,
+// ty + (NP - 1) PR (FX = 2 CX a power of two, PR = NT / FX), so the row
+// offsets of its loads, LDS slots and coarse reads are compile-time
+// constants, and its Jacobi data stay in registers between the steps.  The
+// halo rings around the owned points go one point per thread.  A tile whose
+// fine box lies inside the grid takes a path without bounds checks (the
+// choice is uniform over the workgroup).
+// ---------------------------------------------------------------------------
+
+// Point h of the ring at distance dist around an FX x FY tile, relative to
+// the tile's first point: the two rows (length FX + 2 dist), then the two
+// columns without the corners.  The ring has 2 FX + 2 FY + 8 dist - 4 points.
+template <int FX, int FY> __device__ __forceinline__ void ring_point(int h, int dist, int &hx, int &hy)
+{
+    const int W = FX + 2 * dist;
+    if (h < 2 * W) {
+        hx = (h < W ? h : h - W) - dist;
+        hy = h < W ? -dist : FY - 1 + dist;
+    } else {
+        const int k = h - 2 * W, Hc = FY + 2 * dist - 2;
+        hx = k < Hc ? -dist : FX - 1 + dist;
+        hy = (k < Hc ? k : k - Hc) - dist + 1;
+    }
+}
+
+template <typename T, int RM> struct PlaneTables {
+    V2<T> A[2][RM], Cc[2][RM], Dd[2][RM];
+};
+// LDS of the 2D legs: u on the fine box, the residual (down) or the coarse
+// box of e (up), and the coefficient tables
+template <typename T, int RN, int RM> struct DownLds {
+    V2<T> U[RN], R[RN];
+    PlaneTables<T, RM> tb;
+};
+template <typename T, int RN, int EN, int RM> struct UpLds {
+    V2<T> U[RN], E[EN];
+    PlaneTables<T, RM> tb;
+};
+template <int VT> struct PlaneDown {
+    static constexpr int CX = TileSet<2>::X[VT], CY = TileSet<2>::Y[VT];
+    static constexpr int RX = 2 * CX + 4, RY = 2 * CY + 4, RN = RX * RY, RM = RX > RY ? RX : RY;
+};
+template <int VT> struct PlaneUp {
+    static constexpr int CX = TileSet<2>::X[VT], CY = TileSet<2>::Y[VT];
+    static constexpr int RX = 2 * CX + 2, RY = 2 * CY + 2, RN = RX * RY, RM = RX > RY ? RX : RY;
+    static constexpr int EN = (CX + 4) * (CY + 4);
+};
+
+// x and y coefficient tables of the fine box [ox, ox + RX) x [oy, oy + RY)
+// (zero outside the grid).  The axis is chosen by selects, not by indexing
+// the descriptor's arrays, which would move the descriptor to scratch memory.
+template <typename T, int RX, int RY, int RM, int NT>
+__device__ __forceinline__ void plane_tables(PlaneTables<T, RM> &tb, const LevelDev<T> &Lf, int ox, int oy)
+{
+    for (int l = threadIdx.x; l < RX + RY; l += NT) {
+        const bool ya = l >= RX;
+        const int q = ya ? l - RX : l;
+        const int g = (ya ? oy : ox) + q;
+        const bool in = g >= 0 && g < (ya ? Lf.n[1] : Lf.n[0]);
+        const V2<T> z = cmk<T>(0, 0);
+        const V2<T> *pa = ya ? Lf.a[1] : Lf.a[0], *pc = ya ? Lf.c[1] : Lf.c[0], *pd = ya ? Lf.d[1] : Lf.d[0];
+        const int ax = ya ? 1 : 0;
+        tb.A[ax][q] = in ? ldg(pa, g) : z;
+        tb.Cc[ax][q] = in ? ldg(pc, g) : z;
+        tb.Dd[ax][q] = in ? ldg(pd, g) : z;
+    }
+}
+
+// the diagonal D = d_x + d_y - phi and the Jacobi weight g = omega / D
+template <typename T>
+__device__ __forceinline__ void plane_jacobi(V2<T> dx, V2<T> dy, T ph, T omega, V2<T> &D, V2<T> &gw)
+{
+    const V2<T> d = cadd<T>(dx, dy);
+    D = cmk<T>(d.x - ph, d.y);
+    const T qq = jscale<T>(omega, D);
+    gw = cmk<T>(D.x * qq, -(D.y * qq));
+}
+
+// r = f - M u at box slot l (stencil in LDS)
+template <typename T, int RX>
+__device__ __forceinline__ V2<T> plane_resid(const V2<T> *U, int l, V2<T> D, V2<T> f, V2<T> ax, V2<T> cxx, V2<T> ay,
+                                             V2<T> cy)
+{
+    V2<T> mu = cmul<T>(D, U[l]);
+    mu = csub<T>(mu, cmul<T>(ax, U[l - 1]));
+    mu = csub<T>(mu, cmul<T>(cxx, U[l + 1]));
+    mu = csub<T>(mu, cmul<T>(ay, U[l - RX]));
+    mu = csub<T>(mu, cmul<T>(cy, U[l + RX]));
+    return csub<T>(f, mu);
+}
+
+// bilinear prolongation of the coarse box E at fine point (gx, gy)
+template <typename T, int EX>
+__device__ __forceinline__ V2<T> plane_prolong(const V2<T> *E, int Ix, int Iox, int Iy, int Ioy)
+{
+    const T p3 = (T)0.75, p1 = (T)0.25;
+    const V2<T> a0 = cadd<T>(crs<T>(p3, E[Ix + EX * Iy]), crs<T>(p1, E[Iox + EX * Iy]));
+    const V2<T> a1 = cadd<T>(crs<T>(p3, E[Ix + EX * Ioy]), crs<T>(p1, E[Iox + EX * Ioy]));
+    return cadd<T>(crs<T>(p3, a0), crs<T>(p1, a1));
+}
+
+// 2D down-leg of the tile at coarse (c0x, c0y): u1 = g f on the fine box
+// (owned points plus two rings), r = f - M u1 on the owned points and the
+// first ring, full weighting onto the coarse tile.
+template <typename T, typename TF, int VT, bool EDGE>
+__device__ __forceinline__ void vdown_plane_tile(DownLds<T, PlaneDown<VT>::RN, PlaneDown<VT>::RM> &sm,
+                                                 const LevelDev<T> &Lf, const LevelDev<T> &Lc, const TF *__restrict__ f,
+                                                 T omega, bool pre, int c0x, int c0y, bool run)
+{
+    using C = V2<T>;
+    constexpr int CX = TileSet<2>::X[VT], CY = TileSet<2>::Y[VT], NT = TileSet<2>::T[VT];
+    constexpr int FX = 2 * CX, FY = 2 * CY;
+    constexpr int RX = FX + 4, RY = FY + 4, RN = RX * RY, RM = RX > RY ? RX : RY;
+    constexpr int PR = NT / FX, NP = FY / PR;
+    constexpr int N1 = 2 * FX + 2 * FY + 4, N2 = 2 * FX + 2 * FY + 12;
+    static_assert((FX & (FX - 1)) == 0 && NT % FX == 0 && FY % PR == 0 && N1 <= NT && N2 <= NT, "2D down-leg tile");
+    static_assert(RN == PlaneDown<VT>::RN && RM == PlaneDown<VT>::RM, "2D down-leg LDS");
+    C *U = sm.U, *R = sm.R;
+    PlaneTables<T, RM> &tb = sm.tb;
+
+    const int nfx = Lf.n[0], nfy = Lf.n[1], ncx = Lc.n[0], ncy = Lc.n[1];
+    const T *__restrict__ phi = Lf.phi;
+    const int64_t sy = nfx;
+    const int f0x = 2 * c0x, f0y = 2 * c0y, ox = f0x - 2, oy = f0y - 2;
+    const int tx = threadIdx.x & (FX - 1), ty = threadIdx.x / FX;
+    const int gx = f0x + tx;
+    const int64_t p0 = (int64_t)(f0y + ty) * sy + gx, dq = (int64_t)PR * sy;
+    const C zero = cmk<T>(0, 0);
+
+    // loads: owned points, one point of each ring, the coefficient tables
+    TF fr[NP];
+    T pr[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        if (!EDGE || (gx < nfx && f0y + ty + q * PR < nfy)) {
+            fr[q] = ldg(f, p0 + q * dq);
+            pr[q] = ldg(phi, p0 + q * dq);
+        }
+    }
+    const int t1 = threadIdx.x, t2 = NT - 1 - (int)threadIdx.x;   // ring slots (ring 2 from the last thread)
+    int h1x = 0, h1y = 0, h2x = 0, h2y = 0;
+    if (t1 < N1) ring_point<FX, FY>(t1, 1, h1x, h1y);
+    if (t2 < N2) ring_point<FX, FY>(t2, 2, h2x, h2y);
+    const int g1x = f0x + h1x, g1y = f0y + h1y, g2x = f0x + h2x, g2y = f0y + h2y;
+    const bool in1 = t1 < N1 && (!EDGE || (g1x >= 0 && g1x < nfx && g1y >= 0 && g1y < nfy));
+    const bool in2 = t2 < N2 && (!EDGE || (g2x >= 0 && g2x < nfx && g2y >= 0 && g2y < nfy));
+    TF f1, f2;
+    T ph1 = 0, ph2 = 0;
+    if (in1) {
+        f1 = ldg(f, g1x + sy * g1y);
+        ph1 = ldg(phi, g1x + sy * g1y);
+    }
+    if (in2) {
+        f2 = ldg(f, g2x + sy * g2y);
+        ph2 = ldg(phi, g2x + sy * g2y);
+    }
+    plane_tables<T, RX, RY, RM, NT>(tb, Lf, ox, oy);
+    if (!run) return;   // uniform over the workgroup
+    __syncthreads();
+
+    // step 1: u1 = g f on the box
+    const int lx = tx + 2;
+    const C dxo = tb.Dd[0][lx];
+    C fk[NP], Dk[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int ly = ty + q * PR + 2;
+        C u1 = zero;
+        fk[q] = Dk[q] = zero;
+        if (!EDGE || (gx < nfx && f0y + ly - 2 < nfy)) {
+            C gw;
+            fk[q] = ccvt<T>(fr[q]);
+            plane_jacobi<T>(dxo, tb.Dd[1][ly], pr[q], omega, Dk[q], gw);
+            if (pre) u1 = cmul<T>(gw, fk[q]);
+        }
+        U[lx + RX * ly] = u1;
+    }
+    C fr1 = zero, D1 = zero;
+    if (t1 < N1) {
+        C u1 = zero;
+        if (in1) {
+            C gw;
+            fr1 = ccvt<T>(f1);
+            plane_jacobi<T>(tb.Dd[0][h1x + 2], tb.Dd[1][h1y + 2], ph1, omega, D1, gw);
+            if (pre) u1 = cmul<T>(gw, fr1);
+        }
+        U[(h1x + 2) + RX * (h1y + 2)] = u1;
+    }
+    if (t2 < N2) {
+        C u1 = zero;
+        if (in2) {
+            C D, gw;
+            const C fv = ccvt<T>(f2);
+            plane_jacobi<T>(tb.Dd[0][h2x + 2], tb.Dd[1][h2y + 2], ph2, omega, D, gw);
+            if (pre) u1 = cmul<T>(gw, fv);
+        }
+        U[(h2x + 2) + RX * (h2y + 2)] = u1;
+    }
+    __syncthreads();
+
+    // step 2: r = f - M u1 on the owned points and the first ring (zero
+    // outside the grid)
+    const C axo = tb.A[0][lx], cxo = tb.Cc[0][lx];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int ly = ty + q * PR + 2;
+        const int l = lx + RX * ly;
+        C res = zero;
+        if (!EDGE || (gx < nfx && f0y + ly - 2 < nfy))
+            res = plane_resid<T, RX>(U, l, Dk[q], fk[q], axo, cxo, tb.A[1][ly], tb.Cc[1][ly]);
+        R[l] = res;
+    }
+    if (t1 < N1) {
+        const int x = h1x + 2, y = h1y + 2, l = x + RX * y;
+        C res = zero;
+        if (in1) res = plane_resid<T, RX>(U, l, D1, fr1, tb.A[0][x], tb.Cc[0][x], tb.A[1][y], tb.Cc[1][y]);
+        R[l] = res;
+    }
+    __syncthreads();
+
+    // step 3: full weighting, x then y
+    C *__restrict__ fout = Lc.f;
+    const T w0 = (T)0.125, w1 = (T)0.375;
+    for (int cl = threadIdx.x; cl < CX * CY; cl += NT) {
+        const int ix = cl % CX, iy = cl / CX;
+        const int I = c0x + ix, J = c0y + iy;
+        if (I >= ncx || J >= ncy) continue;
+        const int bxl = 2 * ix + 1, byl = 2 * iy + 1;
+        C acc = zero;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const T wy = (b == 0 || b == 3) ? w0 : w1;
+            const C *row = &R[bxl + RX * (byl + b)];
+            C sx = crs<T>(w0, row[0]);
+            sx = cadd<T>(sx, crs<T>(w1, row[1]));
+            sx = cadd<T>(sx, crs<T>(w1, row[2]));
+            sx = cadd<T>(sx, crs<T>(w0, row[3]));
+            acc = b == 0 ? crs<T>(wy, sx) : cadd<T>(acc, crs<T>(wy, sx));
+        }
+        stg(fout, I + (int64_t)ncx * J, acc);
+    }
+}
+
+template <typename T, typename TF, int VT>
+__device__ __forceinline__ void vdown_plane(Ctx cx, int lev, int fsel, const void *fptr, LvPair<T> lp)
+{
+    constexpr int CX = TileSet<2>::X[VT], CY = TileSet<2>::Y[VT];
+    const Tile tl = tile_of(cx);
+    const ProbDev *pd = cx.P + tl.prob;
+    LevelDev<T> Lf, Lc;
+    int run = PH_RUN;
+    if (lp.valid) {
+        run = phase_of(cx, tl.prob);
+        Lf = lp.f;
+        Lc = lp.c;
+    } else {
+        if (phase_of(cx, tl.prob) != PH_RUN) return;
+        const LevelDev<T> *Lv = levels_of<T>(cx, pd);
+        Lf = Lv[lev];
+        Lc = Lv[lev + 1];
+    }
+    const TF *f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lf.f;
+    const T omega = (T)(cx.L ? cx.omega : pd->omega);
+    const bool pre = (cx.L ? cx.nu1 : pd->nu1) != 0;   // V(1,1), or V(0,1) without pre-smoothing
+    const int ntx = (Lc.n[0] + CX - 1) / CX;
+    const int c0x = (tl.idx % ntx) * CX, c0y = (tl.idx / ntx) * CY;
+    // the fine box [2 c0x - 2, 2 c0x + 2 CX + 2) (and in y) inside the grid
+    const bool edge = c0x == 0 || c0y == 0 || 2 * c0x + 2 * CX + 2 > Lf.n[0] || 2 * c0y + 2 * CY + 2 > Lf.n[1];
+    __shared__ DownLds<T, PlaneDown<VT>::RN, PlaneDown<VT>::RM> sm;
+    if (edge) vdown_plane_tile<T, TF, VT, true>(sm, Lf, Lc, f, omega, pre, c0x, c0y, run == PH_RUN);
+    else vdown_plane_tile<T, TF, VT, false>(sm, Lf, Lc, f, omega, pre, c0x, c0y, run == PH_RUN);
+}
+
+// 2D up-leg of the fine tile at (f0x, f0y): u2 = g f + P e on the owned
+// points and the ring of one around them, then u = u2 + g (f - M u2) on the
+// owned points.
+template <typename T, typename TF, typename TO, int VT, bool EDGE>
+__device__ __forceinline__ void vup_plane_tile(UpLds<T, PlaneUp<VT>::RN, PlaneUp<VT>::EN, PlaneUp<VT>::RM> &sm,
+                                               const LevelDev<T> &Lf, const LevelDev<T> &Lc, const TF *__restrict__ f,
+                                               TO *__restrict__ outv, int lev, T omega, bool pre, int f0x, int f0y,
+                                               bool run)
+{
+    using C = V2<T>;
+    constexpr int CX = TileSet<2>::X[VT], CY = TileSet<2>::Y[VT], NT = TileSet<2>::T[VT];
+    constexpr int FX = 2 * CX, FY = 2 * CY;
+    constexpr int RX = FX + 2, RY = FY + 2, RN = RX * RY, RM = RX > RY ? RX : RY;
+    constexpr int EX = CX + 4, EY = CY + 4, EN = EX * EY;
+    constexpr int PR = NT / FX, NP = FY / PR;
+    constexpr int NH = 2 * FX + 2 * FY + 4;
+    static_assert((FX & (FX - 1)) == 0 && NT % FX == 0 && FY % PR == 0 && PR % 2 == 0 && NH <= NT, "2D up-leg tile");
+    // the coarse box is loaded as rows of EXP lanes (EXP a power of two >= EX)
+    constexpr int EXP = EX <= 16 ? 16 : (EX <= 32 ? 32 : 64);
+    static_assert(EX <= EXP && NT % EXP == 0, "2D up-leg coarse box");
+    constexpr int ER = NT / EXP, NE = (EY + ER - 1) / ER;
+    static_assert(RN == PlaneUp<VT>::RN && EN == PlaneUp<VT>::EN && RM == PlaneUp<VT>::RM, "2D up-leg LDS");
+    C *U = sm.U, *E = sm.E;
+    PlaneTables<T, RM> &tb = sm.tb;
+
+    const int nfx = Lf.n[0], nfy = Lf.n[1], ncx = Lc.n[0], ncy = Lc.n[1];
+    const T *__restrict__ phi = Lf.phi;
+    const C *__restrict__ ec = Lc.e;
+    const int64_t sy = nfx;
+    const int ox = f0x - 1, oy = f0y - 1;
+    const int ex0 = (f0x >> 1) - 2, ey0 = (f0y >> 1) - 2;
+    const int tx = threadIdx.x & (FX - 1), ty = threadIdx.x / FX;
+    const int gx = f0x + tx;
+    const int64_t p0 = (int64_t)(f0y + ty) * sy + gx, dq = (int64_t)PR * sy;
+    const C zero = cmk<T>(0, 0);
+
+    // loads: owned points, the ring point, the coarse box, the tables
+    TF fr[NP];
+    T pr[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        if (!EDGE || (gx < nfx && f0y + ty + q * PR < nfy)) {
+            fr[q] = ldg(f, p0 + q * dq);
+            pr[q] = ldg(phi, p0 + q * dq);
+        }
+    }
+    const bool hr = (int)threadIdx.x < NH;
+    int hx = 0, hy = 0;
+    if (hr) ring_point<FX, FY>(threadIdx.x, 1, hx, hy);
+    const int hgx = f0x + hx, hgy = f0y + hy;
+    const bool hin = hr && (!EDGE || (hgx >= 0 && hgx < nfx && hgy >= 0 && hgy < nfy));
+    TF hf;
+    T hph = 0;
+    if (hin) {
+        hf = ldg(f, hgx + sy * hgy);
+        hph = ldg(phi, hgx + sy * hgy);
+    }
+    const int ex = threadIdx.x & (EXP - 1), ey = threadIdx.x / EXP;
+    C er[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int yy = ey + q * ER, gxe = ex0 + ex, gye = ey0 + yy;
+        er[q] = zero;
+        if (ex < EX && yy < EY && gxe >= 0 && gxe < ncx && gye >= 0 && gye < ncy) er[q] = ldg(ec, gxe + (int64_t)ncx * gye);
+    }
+    plane_tables<T, RX, RY, RM, NT>(tb, Lf, ox, oy);
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int yy = ey + q * ER;
+        if (ex < EX && yy < EY) E[ex + EX * yy] = er[q];
+    }
+    if (!run) return;   // uniform over the workgroup
+    __syncthreads();
+
+    // step 1: u2 = g f + P e.  Owned fine column gx = f0x + tx has coarse
+    // neighbours (tx >> 1) + 2 and one to the side of its parity in the
+    // coarse box (f0x is even); likewise in y, and PR is even, so the rows
+    // of this thread keep their parity.
+    const int lx = tx + 1;
+    const int Ix = (tx >> 1) + 2, Iox = Ix + ((tx & 1) ? 1 : -1);
+    const int Iy0 = (ty >> 1) + 2, Ioy0 = Iy0 + ((ty & 1) ? 1 : -1);
+    const C dxo = tb.Dd[0][lx];
+    C fk[NP], Dk[NP], gk[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int ly = ty + q * PR + 1;
+        C u2 = zero;
+        fk[q] = Dk[q] = gk[q] = zero;
+        if (!EDGE || (gx < nfx && f0y + ly - 1 < nfy)) {
+            fk[q] = ccvt<T>(fr[q]);
+            plane_jacobi<T>(dxo, tb.Dd[1][ly], pr[q], omega, Dk[q], gk[q]);
+            const C u1 = pre ? cmul<T>(gk[q], fk[q]) : zero;
+            const C pe = plane_prolong<T, EX>(E, Ix, Iox, Iy0 + q * (PR / 2), Ioy0 + q * (PR / 2));
+            u2 = cadd<T>(u1, pe);
+        }
+        U[lx + RX * ly] = u2;
+    }
+    if (hr) {
+        C u2 = zero;
+        if (hin) {
+            C D, gw;
+            const C fv = ccvt<T>(hf);
+            plane_jacobi<T>(tb.Dd[0][hx + 1], tb.Dd[1][hy + 1], hph, omega, D, gw);
+            const C u1 = pre ? cmul<T>(gw, fv) : zero;
+            const int Jx = (hgx >> 1) - ex0, Jox = ((hgx & 1) ? (hgx >> 1) + 1 : (hgx >> 1) - 1) - ex0;
+            const int Jy = (hgy >> 1) - ey0, Joy = ((hgy & 1) ? (hgy >> 1) + 1 : (hgy >> 1) - 1) - ey0;
+            u2 = cadd<T>(u1, plane_prolong<T, EX>(E, Jx, Jox, Jy, Joy));
+        }
+        U[(hx + 1) + RX * (hy + 1)] = u2;
+    }
+    __syncthreads();
+
+    // step 2: post-smoothing of the owned points
+    const C axo = tb.A[0][lx], cxo = tb.Cc[0][lx];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int ly = ty + q * PR + 1;
+        if (EDGE && (gx >= nfx || f0y + ly - 1 >= nfy)) continue;
+        const int l = lx + RX * ly;
+        const C r = plane_resid<T, RX>(U, l, Dk[q], fk[q], axo, cxo, tb.A[1][ly], tb.Cc[1][ly]);
+        const C u = cadd<T>(U[l], cmul<T>(gk[q], r));
+        if (lev == 0) {
+            TO o;
+            o.x = u.x;
+            o.y = u.y;
+            stg(outv, p0 + q * dq, o);
+        } else {
+            stg(Lf.e, p0 + q * dq, u);
+        }
+    }
+}
+
+template <typename T, typename TF, typename TO, int VT>
+__device__ __forceinline__ void vup_plane(Ctx cx, int lev, int fsel, int osel, const void *fptr, void *optr, LvPair<T> lp)
+{
+    constexpr int FX = 2 * TileSet<2>::X[VT], FY = 2 * TileSet<2>::Y[VT];
+    const Tile tl = tile_of(cx);
+    const ProbDev *pd = cx.P + tl.prob;
+    LevelDev<T> Lf, Lc;
+    int run = PH_RUN;
+    if (lp.valid) {
+        run = phase_of(cx, tl.prob);
+        Lf = lp.f;
+        Lc = lp.c;
+    } else {
+        if (phase_of(cx, tl.prob) != PH_RUN) return;
+        const LevelDev<T> *Lv = levels_of<T>(cx, pd);
+        Lf = Lv[lev];
+        Lc = Lv[lev + 1];
+    }
+    const TF *f = lev == 0 ? (const TF *)(fptr ? fptr : pd->vec[fsel]) : (const TF *)Lf.f;
+    TO *outv = lev == 0 ? (TO *)(optr ? optr : pd->vec[osel]) : nullptr;
+    const T omega = (T)(cx.L ? cx.omega : pd->omega);
+    const bool pre = (cx.L ? cx.nu1 : pd->nu1) != 0;   // V(1,1), or V(0,1) without pre-smoothing
+    const int ntx = (Lf.n[0] + FX - 1) / FX;
+    const int f0x = (tl.idx % ntx) * FX, f0y = (tl.idx / ntx) * FY;
+    // the fine box [f0x - 1, f0x + FX + 1) (and in y) inside the grid
+    const bool edge = f0x == 0 || f0y == 0 || f0x + FX + 1 > Lf.n[0] || f0y + FY + 1 > Lf.n[1];
+    __shared__ UpLds<T, PlaneUp<VT>::RN, PlaneUp<VT>::EN, PlaneUp<VT>::RM> sm;
+    if (edge) vup_plane_tile<T, TF, TO, VT, true>(sm, Lf, Lc, f, outv, lev, omega, pre, f0x, f0y, run == PH_RUN);
+    else vup_plane_tile<T, TF, TO, VT, false>(sm, Lf, Lc, f, outv, lev, omega, pre, f0x, f0y, run == PH_RUN);
+}
+
+// The fused legs: the plane form in 2D, the box form in 3D.
+template <int DIM, typename T, typename TF, int VT>
+__global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vdown(Ctx cx, int lev, int fsel, const void *fptr, LvPair<T> lp)
+{
+    if constexpr (DIM == 2) vdown_plane<T, TF, VT>(cx, lev, fsel, fptr, lp);
+    else vdown_box<DIM, T, TF, VT>(cx, lev, fsel, fptr, lp);
+}
+template <int DIM, typename T, typename TF, typename TO, int VT>
+__global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, int fsel, int osel, const void *fptr, void *optr,
+                                                LvPair<T> lp)
+{
+    if constexpr (DIM == 2) vup_plane<T, TF, TO, VT>(cx, lev, fsel, osel, fptr, optr, lp);
+    else vup_box<DIM, T, TF, TO, VT>(cx, lev, fsel, osel, fptr, optr, lp);
 }
 
 // ---------------------------------------------------------------------------
