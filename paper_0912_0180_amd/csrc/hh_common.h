@@ -160,6 +160,21 @@ template <typename T> struct LevelDev {
     V2<T> *e;                        // level solution / correction (levels >= 1)
 };
 
+// LDS layout of the tail kernel (levels t0 .. L-1 of one problem in one
+// workgroup): for each level the byte offsets of f, e, phi and the per-axis
+// coefficient arrays, 16-byte rounded and carved level after level; the
+// scratch U follows the last level (uoff).  Built on the host (tail_table).
+struct TailOff {
+    int n[3], N;
+    int F, E, PH, A[3], Cc[3], Dd[3];
+    int end;
+};
+struct TailTab {
+    TailOff o[HH_MAXLEV];
+    FastDiv fx[HH_MAXLEV], fxy[HH_MAXLEV];
+    int uoff;
+};
+
 // the two levels a V-cycle level kernel works on, passed by value for
 // one-problem launches (valid = 0: read them from the problem's descriptor)
 template <typename T> struct LvPair {
@@ -243,6 +258,7 @@ struct ProbDev {
     const double2 *Minv64;
     const float2 *Minv32;
     const void *timg64, *timg32;     // LDS image of the tail levels (phi, coefficients), per precision
+    const TailTab *ttab64, *ttab32;  // LDS layout of the tail levels, per precision
     int timg_bytes64, timg_bytes32;
     // image segments, one per tail level: LDS offset << 16 | length, in 16-byte units
     uint32_t tseg64[HH_MAXLEV], tseg32[HH_MAXLEV];

@@ -2682,39 +2682,19 @@ template <typename T> __device__ inline V2<T> jweight(V2<T> D, T omega)
     return cmk<T>(D.x * q, -(D.y * q));
 }
 
-// LDS layout of one tail level: byte offsets of f, e, phi and the per-axis
-// coefficient arrays (16-byte rounded, carved level after level from the
-// tail's first level; the shared scratch U follows the last level).
-struct TailOff {
-    int n[3], N;
-    int F, E, PH, A[3], Cc[3], Dd[3];
-    int end;
+// What the tail kernel of a one-problem plan takes by value (see k_vtail).
+template <typename T> struct TailArgs {
+    const LevelDev<T> *Lv;           // level descriptors (device array)
+    const V2<T> *f_top;              // f of the tail's first level
+    V2<T> *e_top;                    // e of the tail's first level
+    const V2<T> *Minv;               // coarsest inverse
+    const void *img;                 // tail image (see tail_image)
+    int n16, nseg;                   // image length in 16-byte units, segments
+    const TailTab *tab;              // level table (see tail_table)
+    int t0, L, Nc, split, nu1;
+    T omega;
+    uint32_t seg[HH_MAXLEV];         // image segments
 };
-
-template <int DIM, typename T>
-__device__ inline TailOff tail_off(const LevelDev<T> *Lv, int t0, int l)
-{
-    const int cb = sizeof(V2<T>), rb = sizeof(T);
-    auto r16 = [](int b) { return (b + 15) & ~15; };
-    int off = 0;
-    TailOff o;
-    for (int q = t0; q <= l; ++q) {
-        const int N = (int)Lv[q].N;
-        o.N = N;
-        for (int a = 0; a < 3; ++a) o.n[a] = Lv[q].n[a];
-        o.F = off; off += r16(cb * N);
-        o.E = off; off += r16(cb * N);
-        o.PH = off; off += r16(rb * N);
-        for (int a = 0; a < 3; ++a) {
-            const int na = a < DIM ? o.n[a] : 1;
-            o.A[a] = off; off += r16(cb * na);
-            o.Cc[a] = off; off += r16(cb * na);
-            o.Dd[a] = off; off += r16(cb * na);
-        }
-    }
-    o.end = off;
-    return o;
-}
 
 // pointers of one tail level into the LDS block
 template <typename T> struct TailPtr {
@@ -2723,26 +2703,6 @@ template <typename T> struct TailPtr {
     V2<T> *F, *E, *A0, *A1, *A2, *C0, *C1, *C2, *D0, *D1, *D2;
     T *PH;
 };
-
-// Level table of the tail, computed once per workgroup into LDS: byte
-// offsets of every array of level l and its index decomposition.
-struct TailTab {
-    TailOff o[HH_MAXLEV];
-    FastDiv fx[HH_MAXLEV], fxy[HH_MAXLEV];
-    int uoff;
-};
-
-// one thread per level (callers synchronise before use)
-template <int DIM, typename T>
-__device__ inline void tail_tab_fill(TailTab &tab, const LevelDev<T> *Lv, int t0, int L)
-{
-    for (int l = t0 + (int)threadIdx.x; l < L; l += (int)blockDim.x) {
-        tab.o[l] = tail_off<DIM, T>(Lv, t0, l);
-        tab.fx[l] = Lv[l].fx;
-        tab.fxy[l] = Lv[l].fxy;
-        if (l == L - 1) tab.uoff = tab.o[l].end;
-    }
-}
 
 template <int DIM, typename T>
 __device__ inline TailPtr<T> tail_ptr(char *lds, const TailTab &tab, int l)
@@ -2812,20 +2772,27 @@ __device__ inline void tail_ijk(const TailPtr<T> &Q, int p, int &i, int &j, int 
 // restricted right-hand sides of the tail levels go to global memory).
 // up = 1: the up-legs of such a problem, from those right-hand sides and the
 // coarsest solution k_coarse left in global memory.
-template <int DIM, typename T>
-__global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__restrict__ probs, int up)
+// BV (one problem): every value read before the first barrier comes by
+// value in ta, so the loads of f, the image and the inverse issue at once,
+// next to the phase load, instead of after a chain of dependent descriptor
+// loads; the phase decides only at that barrier.  Batches (BV false) read
+// the problem descriptor.
+template <int DIM, typename T, bool BV>
+__global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__restrict__ probs, int up, TailArgs<T> ta)
 {
     using C = V2<T>;
     __shared__ __attribute__((aligned(16))) char lds[TailCap<T>::BYTES];
-    const int prob = probs ? probs[blockIdx.x] : 0;
-    if (phase_of(cx, prob) != PH_RUN) return;
+    const int prob = !BV && probs ? probs[blockIdx.x] : 0;
+    int run = PH_RUN;
+    if constexpr (BV) run = phase_of(cx, prob);
+    else if (phase_of(cx, prob) != PH_RUN) return;
     const ProbDev *pd = cx.P + prob;
-    const int split = pd->csplit;
+    const int split = BV ? ta.split : pd->csplit;
     if (up && !split) return;
-    const LevelDev<T> *Lv = levels_of<T>(cx, pd);
-    const int t0 = tail_level<T>(pd), L = pd->nlev;
-    const T omega = (T)pd->omega;
-    const bool pre = pd->nu1 != 0;
+    const LevelDev<T> *Lv = BV ? ta.Lv : levels_of<T>(cx, pd);
+    const int t0 = BV ? ta.t0 : tail_level<T>(pd), L = BV ? ta.L : pd->nlev;
+    const T omega = BV ? ta.omega : (T)pd->omega;
+    const bool pre = (BV ? ta.nu1 : pd->nu1) != 0;
     const C zero = cmk<T>(0, 0);
     const int tid = threadIdx.x, nth = TailCap<T>::WG;
     __shared__ TailTab tab;
@@ -2835,20 +2802,26 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
     // until the coarse solve, so its latency overlaps the image, f and the
     // down-legs
     constexpr int MR = sizeof(T) == 4 ? 64 / (TailCap<T>::WG / 64) : 1;   // rows per lane
-    const bool mreg = sizeof(T) == 4 && !up && !split && pd->Nc <= 64;
-    const int nc = pd->Nc;
+    const int nc = BV ? ta.Nc : pd->Nc;
+    const bool mreg = sizeof(T) == 4 && !up && !split && nc <= 64;
     C mt[MR];
-    const C *fg_top = Lv[t0].f;
-    C *eg_top = Lv[t0].e;
-    const C *__restrict__ Minv = (const C *)(sizeof(T) == 8 ? (const void *)pd->Minv64 : (const void *)pd->Minv32);
+    const C *fg_top = BV ? ta.f_top : Lv[t0].f;
+    C *eg_top = BV ? ta.e_top : Lv[t0].e;
+    const C *__restrict__ Minv =
+        BV ? ta.Minv : (const C *)(sizeof(T) == 8 ? (const void *)pd->Minv64 : (const void *)pd->Minv32);
     // the tail image (phi and coefficients of every tail level, see
     // tail_image), the coarsest inverse when it goes to LDS, and f of the top
     // level, all loads in flight together while the level table is built
     {
-        const void *img = sizeof(T) == 8 ? pd->timg64 : pd->timg32;
-        const int n16 = (sizeof(T) == 8 ? pd->timg_bytes64 : pd->timg_bytes32) / 16;
-        const uint32_t *seg = sizeof(T) == 8 ? pd->tseg64 : pd->tseg32;
-        const int nseg = sizeof(T) == 8 ? pd->tnseg64 : pd->tnseg32;
+        const void *img = BV ? ta.img : (sizeof(T) == 8 ? pd->timg64 : pd->timg32);
+        const int n16 = BV ? ta.n16 : (sizeof(T) == 8 ? pd->timg_bytes64 : pd->timg_bytes32) / 16;
+        const uint32_t *seg = BV ? ta.seg : (sizeof(T) == 8 ? pd->tseg64 : pd->tseg32);
+        const int nseg = BV ? ta.nseg : (sizeof(T) == 8 ? pd->tnseg64 : pd->tnseg32);
+        // the level table, one 32-bit word per thread
+        constexpr int TW = sizeof(TailTab) / 4;
+        static_assert(sizeof(TailTab) % 4 == 0 && TW <= TailCap<T>::WG, "tail table words");
+        const uint32_t *tabg = (const uint32_t *)(BV ? ta.tab : (sizeof(T) == 8 ? pd->ttab64 : pd->ttab32));
+        const uint32_t tw = tid < TW ? ((const HH_GLOBAL uint32_t *)tabg)[tid] : 0u;
         hh_uvec4 *l16 = (hh_uvec4 *)lds;
         if (mreg) {
             const int w = tid >> 6, lane = tid & 63;
@@ -2874,7 +2847,6 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
                 const int i = b + tid + q * nth;
                 if (i < n16) tmp[q] = ldg16(img, i);
             }
-            if (b == 0) tail_tab_fill<DIM, T>(tab, Lv, t0, L);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int i = b + tid + q * nth;
@@ -2890,12 +2862,13 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
                 }
             }
         }
-        if (n16 <= 0) tail_tab_fill<DIM, T>(tab, Lv, t0, L);
+        if (tid < TW) ((uint32_t *)&tab)[tid] = tw;
 #pragma unroll
         for (int q = 0; q < FT; ++q) {
             const int i = tid + q * nth;
             if (i < ntop) ((C *)lds)[i] = ft[q];
         }
+        if (run != PH_RUN) return;   // uniform over the workgroup
         __syncthreads();
         // for the up-legs of a split tail: f of every tail level and e of the
         // coarsest

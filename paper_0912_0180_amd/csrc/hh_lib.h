@@ -33,6 +33,7 @@ struct Plan {
     int nfin = 0;
     ProbDev *probs = nullptr;
     Ctrl *ctrl = nullptr;            // per-problem control blocks (device)
+    ProbDev pd1{};                   // one-problem plans: copy of the problem's static descriptor
     const void *L1 = nullptr;        // one-problem plans: LevelDev array of the V-cycle precision
     const LevelDev<double> *lv64h = nullptr;   // one-problem plans: host copies of its level descriptors
     const LevelDev<float> *lv32h = nullptr;
@@ -80,6 +81,7 @@ struct hh_grid {
     double2 *Minv64 = nullptr;
     float2 *Minv32 = nullptr;
     void *timg64 = nullptr, *timg32 = nullptr;
+    TailTab *ttab64 = nullptr, *ttab32 = nullptr;   // tail level tables (see tail_table)
     size_t timg_bytes64 = 0, timg_bytes32 = 0;
     std::vector<uint32_t> tseg64, tseg32;   // segments of the tail images (see tail_image)
     ProbDev pd_static{};

@@ -107,6 +107,8 @@ static size_t scratch_layout(const HostSetup &hs, bool fp32, size_t (*off)[2])
 // ---------------------------------------------------------------------------
 // grid
 // ---------------------------------------------------------------------------
+template <typename T> static TailTab tail_table(const LevelDev<T> *Lh, const HostSetup &hs, bool fp32);
+
 hh_status grid_upload(hh_grid *g)
 {
     const HostSetup &hs = g->hs;
@@ -161,6 +163,8 @@ hh_status grid_upload(hh_grid *g)
         }
         g->timg64 = c.take<char>(g->timg_bytes64);
         g->timg32 = c.take<char>(g->timg_bytes32);
+        g->ttab64 = c.take<TailTab>(1);
+        g->ttab32 = c.take<TailTab>(1);
         g->L64 = c.take<LevelDev<double>>(HH_MAXLEV);
         g->L32 = c.take<LevelDev<float>>(HH_MAXLEV);
         g->L64s = c.take<LevelDev<double>>(HH_MAXLEV);
@@ -204,6 +208,9 @@ hh_status grid_upload(hh_grid *g)
         std::vector<char> i64 = tail_image(hs, false, &g->tseg64), i32 = tail_image(hs, true, &g->tseg32);
         HIPCHK(put64(g->timg64, i64.data(), i64.size()));
         HIPCHK(put64(g->timg32, i32.data(), i32.size()));
+        const TailTab t64 = tail_table(g->L64h, hs, false), t32 = tail_table(g->L32h, hs, true);
+        HIPCHK(put64(g->ttab64, &t64, sizeof t64));
+        HIPCHK(put64(g->ttab32, &t32, sizeof t32));
     }
     HIPCHK(put32c(g->Minv32, hs.Minv));
     HIPCHK(put64(g->L64, g->L64h, sizeof(LevelDev<double>) * HH_MAXLEV));
@@ -273,6 +280,8 @@ void grid_fill_prob(const hh_grid *g, ProbDev &pd)
     pd.csplit = hs.Nc > HH_SPLIT_NC ? 1 : 0;
     pd.timg64 = g->timg64;
     pd.timg32 = g->timg32;
+    pd.ttab64 = g->ttab64;
+    pd.ttab32 = g->ttab32;
     pd.timg_bytes64 = (int)g->timg_bytes64;
     pd.timg_bytes32 = (int)g->timg_bytes32;
     pd.tnseg64 = (int)g->tseg64.size();
@@ -395,6 +404,39 @@ int tail_level(const HostSetup &hs, bool fp32)
     for (int t = 1; t < hs.nlev; ++t)
         if (hs.lev[t].N <= cap && tail_bytes(hs, t, fp32) <= bytes) return t;
     return hs.nlev - 1;
+}
+
+// Level table of the tail kernel: the layout of tail_bytes, level by level
+// from the tail's first level, with each level's sizes and index dividers
+// from its uploaded descriptor (Lh: host copies, either precision).
+template <typename T> static TailTab tail_table(const LevelDev<T> *Lh, const HostSetup &hs, bool fp32)
+{
+    TailTab tab;
+    memset(&tab, 0, sizeof tab);
+    if (hs.nlev < 2) return tab;   // a one-level grid has no V-cycle
+    const int t0 = tail_level(hs, fp32);
+    const int cb = sizeof(V2<T>), rb = sizeof(T);
+    auto r16 = [](int b) { return (b + 15) & ~15; };
+    int off = 0;
+    for (int l = t0; l < hs.nlev; ++l) {
+        TailOff &o = tab.o[l];
+        o.N = (int)Lh[l].N;
+        for (int a = 0; a < 3; ++a) o.n[a] = Lh[l].n[a];
+        o.F = off; off += r16(cb * o.N);
+        o.E = off; off += r16(cb * o.N);
+        o.PH = off; off += r16(rb * o.N);
+        for (int a = 0; a < 3; ++a) {
+            const int na = a < hs.dim ? o.n[a] : 1;
+            o.A[a] = off; off += r16(cb * na);
+            o.Cc[a] = off; off += r16(cb * na);
+            o.Dd[a] = off; off += r16(cb * na);
+        }
+        o.end = off;
+        tab.fx[l] = Lh[l].fx;
+        tab.fxy[l] = Lh[l].fxy;
+    }
+    tab.uoff = off;
+    return tab;
 }
 
 // Compact image of the tail's LDS block (layout of tail_bytes / k_vtail):
@@ -553,6 +595,7 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
     pl.probs = c.take<ProbDev>(pl.count);
     pl.ctrl = c.take<Ctrl>(pl.count);
     if (pl.count == 1) {
+        pl.pd1 = G[0]->pd_static;
         pl.L1 = fp32 ? (const void *)G[0]->L32 : (const void *)G[0]->L64;
         pl.omega1 = G[0]->hs.omega;
         pl.nu1_1 = G[0]->hs.nu1;
@@ -842,6 +885,7 @@ static void plan_host_one(Plan &pl, const hh_grid *g, bool fp32, const void *L1,
     pl.nfin = 1;
     pl.probs = g->pd_static_dev;
     pl.ctrl = nullptr;
+    pl.pd1 = g->pd_static;
     pl.L1 = L1;
     pl.omega1 = hs.omega;
     pl.nu1_1 = hs.nu1;
@@ -875,6 +919,32 @@ static void launch_merged(int leg, const Plan &pl, hipStream_t s, const LvHost &
     else launch_merged_k<T, 4>(leg, pl, s, L);
 }
 
+// tail arguments of a one-problem plan, from its copy of the problem's static
+// descriptor and host copies of its level descriptors
+template <typename T> static TailArgs<T> tail_args(const Plan &pl)
+{
+    const ProbDev &h = pl.pd1;
+    constexpr bool f32 = sizeof(T) == 4;
+    const LevelDev<T> *lvh = (const LevelDev<T> *)(f32 ? (const void *)pl.lv32h : (const void *)pl.lv64h);
+    TailArgs<T> a{};
+    a.t0 = f32 ? h.tail32 : h.tail64;
+    a.L = h.nlev;
+    a.Nc = h.Nc;
+    a.split = h.csplit;
+    a.nu1 = h.nu1;
+    a.omega = (T)h.omega;
+    a.Lv = (const LevelDev<T> *)pl.L1;
+    a.f_top = lvh[a.t0].f;
+    a.e_top = lvh[a.t0].e;
+    a.Minv = (const V2<T> *)(f32 ? (const void *)h.Minv32 : (const void *)h.Minv64);
+    a.img = f32 ? h.timg32 : h.timg64;
+    a.tab = f32 ? h.ttab32 : h.ttab64;
+    a.n16 = (f32 ? h.timg_bytes32 : h.timg_bytes64) / 16;
+    a.nseg = f32 ? h.tnseg32 : h.tnseg64;
+    memcpy(a.seg, f32 ? h.tseg32 : h.tseg64, sizeof a.seg);
+    return a;
+}
+
 template <int DIM, typename T>
 static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void *optr, hipStream_t s)
 {
@@ -896,15 +966,23 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
         // multi-workgroup coarsest solves, up-legs of split problems
         Ctx c = ctx_of(pl, pl.chunks);
         const int *probs = pl.count == 1 ? nullptr : pl.fin;
-        if (pl.nfin > 0 && pl.tail_down)
-            hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c, probs, 0);
+        if (pl.nfin > 0 && pl.tail_down) {
+            if (pl.count == 1)
+                hipLaunchKernelGGL((k_vtail<DIM, T, true>), dim3(1), dim3(TailCap<T>::WG), 0, s, c, nullptr, 0, tail_args<T>(pl));
+            else
+                hipLaunchKernelGGL((k_vtail<DIM, T, false>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c, probs, 0, TailArgs<T>{});
+        }
         LAUNCH((k_coarse<T, 1>), pl.coarse[0].n, s, ctx_of(pl, pl.coarse[0]));
         LAUNCH((k_coarse<T, 2>), pl.coarse[1].n, s, ctx_of(pl, pl.coarse[1]));
         LAUNCH((k_coarse<T, 4>), pl.coarse[2].n, s, ctx_of(pl, pl.coarse[2]));
         LAUNCH((k_coarse<T, 8>), pl.coarse[3].n, s, ctx_of(pl, pl.coarse[3]));
         LAUNCH((k_coarse<T, 16>), pl.coarse[4].n, s, ctx_of(pl, pl.coarse[4]));
-        if (pl.nfin > 0 && pl.tail_up)
-            hipLaunchKernelGGL((k_vtail<DIM, T>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c, probs, 1);
+        if (pl.nfin > 0 && pl.tail_up) {
+            if (pl.count == 1)
+                hipLaunchKernelGGL((k_vtail<DIM, T, true>), dim3(1), dim3(TailCap<T>::WG), 0, s, c, nullptr, 1, tail_args<T>(pl));
+            else
+                hipLaunchKernelGGL((k_vtail<DIM, T, false>), dim3(pl.nfin), dim3(TailCap<T>::WG), 0, s, c, probs, 1, TailArgs<T>{});
+        }
     }
     if (pl.mK) launch_merged<T>(1, pl, s, lh);
     for (int l = (pl.mK ? pl.mlev0u : pl.Lmax) - 1; l >= 0; --l)
