@@ -12,9 +12,10 @@ mixed-precision solve (complex-FP32 V-cycle, FP64 Krylov).
 Reported beside it: the FP64 solve, V-cycle and operator bandwidths, the
 roofline of the dominant bandwidth-bound kernel of the solve (the finest
 up-leg of the V-cycle, timed on the same recipe at 4096^2 so its data comes
-from HBM), the 3D 128^3 solves (IDR(4) and Bi-CGSTAB), the 64-problem batched
-solve, the serving stream, and the CPU oracle on a bounded sample of the
-headline solve.
+from HBM), the C1 128^2 and 192^2 solves (microseconds per V-cycle and per
+iteration), the 3D 128^3 solves (IDR(4) and Bi-CGSTAB), the 64-problem batched
+solve, the serving stream, the paper's model problems, and the CPU oracle on a
+bounded sample of the headline solve.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--no-cpu-baseline]
                     [--roofline-only] [--pmc-probe]
@@ -510,6 +511,40 @@ PAPER_MP = {
 }
 
 
+def bench_c1(args, torch, hh, W):
+    """C1: the 128^2 grid (layers included) of Sec. 6.1 with kh = 0.625, CSG
+    pi/8 uniform and interior, and the paper-aligned 192^2, k = 80 row;
+    4 levels, Bi-CGSTAB to 1e-8.  The working set (a few MiB) stays in L2, so
+    the row reports microseconds per V-cycle and per iteration (two matvecs)
+    rather than a bandwidth fraction."""
+    cases = [("c1_uniform", lambda: W.c1(mode=0)), ("c1_interior", lambda: W.c1(mode=1)),
+             ("c1_paper", lambda: W.c1_paper())]
+    res = {}
+    for name, mk in cases:
+        c = mk()
+        g = hh.Grid(c["desc"], c["phi"])
+        b = torch.from_numpy(c["b"]).to("cuda")
+        x = torch.zeros_like(b)
+        f = torch.randn(g.N, dtype=torch.complex128, device="cuda")
+        row = {"grid": "%dx%d" % (c["desc"]["n"][0], c["desc"]["n"][1]), "levels": g.levels,
+               "csg_mode": ("uniform", "interior")[c["desc"]["csg_mode"]]}
+        for prec in ("c128", "c64"):
+            row["vcycle_us_" + prec] = g.profile_vcycle(f, prec, reps=200)["vcycle_us"]
+        for rname, vp in (("bicgstab_fp64", "c128"), ("bicgstab_mixed", "c64")):
+            g.solve(b, x=x, tol=1e-8, vcycle_prec=vp)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, info = g.solve(b, x=x, tol=1e-8, vcycle_prec=vp)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3
+            row[rname] = {"time_to_tol_ms": ms, "matvecs": info["matvecs"],
+                          "us_per_iteration": ms * 1e3 / max(1, info["matvecs"] / 2),
+                          "rel_res_true": info["rel_res_true"], "status": info["status"]}
+        res[name] = row
+        g.close()
+    return res
+
+
 def bench_mp(args, torch, hh, W):
     """The paper's model problems at its sizes: MP2 (nu = 7, k = 2 and nu = 1,
     k = 4; 384 + 128 cells per axis, r = 50), MP3 (r = 90, k = 2; 1024 + 256
@@ -620,7 +655,7 @@ def main():
     ap.add_argument("--serve-low-requests", type=int, default=80)
     ap.add_argument("--serve-oracle-budget-s", type=float, default=90.0)
     ap.add_argument("--serve-slots", type=int, default=16)
-    ap.add_argument("--skip", default="", help="comma list of c3,c4,c5,mp to skip")
+    ap.add_argument("--skip", default="", help="comma list of c1,c3,c4,c5,mp to skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-matvecs", type=int, default=300)
     ap.add_argument("--quick", action="store_true", help="headline solve only")
@@ -653,6 +688,9 @@ def main():
         print("bench: roofline", file=sys.stderr, flush=True)
         bench_roofline(args, torch, hh, W, out)
     if not args.quick:
+        if "c1" not in skip:
+            print("bench: c1", file=sys.stderr, flush=True)
+            out["c1"] = bench_c1(args, torch, hh, W)
         if "c3" not in skip:
             print("bench: c3", file=sys.stderr, flush=True)
             out["c3"] = bench_c3(args, torch, hh, W)

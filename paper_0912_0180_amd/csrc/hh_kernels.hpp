@@ -365,15 +365,14 @@ __device__ inline void record(const ProbDev *pd, SolveState *st, double rel)
 // staged in LDS in blocks of HH_FIN_STAGE entries (an aligned power-of-two
 // block of a pairwise tree is itself a subtree, so block sums combine
 // exactly).
-// np = PER * 256 partials of each of G values.  Loads are coalesced
-// (thread t takes partials t + 256 i), then transposed through LDS (one
-// padding word per 16 against bank conflicts) so that thread t sums the
-// aligned block [t PER, (t+1) PER) pairwise in registers; the 256 block sums
-// are combined by the wave butterfly and the four-wave sum (block_reduce),
-// which is the same tree.  Zero past n.  lds holds PER * 256 * 17 / 16
-// doubles.
+// np = PER * 256 partials of each of G values.  Thread t loads the aligned
+// block [t PER, (t+1) PER) of each value (consecutive addresses, zero past
+// n) and sums it pairwise in registers; the 256 block sums are combined by
+// the wave butterfly and the four-wave sum (block_reduce), which is the same
+// tree.  Loading the block directly, rather than coalesced and transposed
+// through LDS, saves two barriers per value.
 template <int PER, int G>
-__device__ inline void reduce_values_blocked(const double *part, int n, int64_t off, int ng, double *out, double *lds)
+__device__ inline void reduce_values_blocked(const double *part, int n, int64_t off, int ng, double *out)
 {
     const int t = (int)threadIdx.x;
     double r[G][PER];
@@ -381,30 +380,17 @@ __device__ inline void reduce_values_blocked(const double *part, int n, int64_t 
     for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-            const int e = t + HH_WG * i;
+            const int e = t * PER + i;
             r[g][i] = (g < ng && e < n) ? ldg(part, off + (int64_t)g * n + e) : 0.0;
         }
     double sums[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int e = t + HH_WG * i;
-            lds[e + (e >> 4)] = r[g][i];
-        }
-        __syncthreads();
-        double v[PER];
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int e = t * PER + i;
-            v[i] = lds[e + (e >> 4)];
-        }
-        __syncthreads();
-#pragma unroll
         for (int w = 1; w < PER; w <<= 1)
 #pragma unroll
-            for (int i = 0; i + w < PER; i += 2 * w) v[i] = v[i] + v[i + w];
-        sums[g] = v[0];
+            for (int i = 0; i + w < PER; i += 2 * w) r[g][i] = r[g][i] + r[g][i + w];
+        sums[g] = r[g][0];
     }
     __shared__ double tmp[G];
     block_reduce<G>(sums, tmp);
@@ -426,12 +412,12 @@ __device__ void reduce_partials(const double *part, int n, int first, int nv, do
             const int64_t off = (int64_t)(first + q) * n;
             const int ng = nv - q < G ? nv - q : G;
             switch (per) {
-            case 1: reduce_values_blocked<1, 4>(part, n, off, ng, out + q, stage); break;
-            case 2: reduce_values_blocked<2, 4>(part, n, off, ng, out + q, stage); break;
-            case 4: reduce_values_blocked<4, 4>(part, n, off, ng, out + q, stage); break;
-            case 8: reduce_values_blocked<8, 4>(part, n, off, ng, out + q, stage); break;
-            case 16: reduce_values_blocked<16, 4>(part, n, off, ng, out + q, stage); break;
-            default: reduce_values_blocked<32, 1>(part, n, off, ng, out + q, stage); break;
+            case 1: reduce_values_blocked<1, 4>(part, n, off, ng, out + q); break;
+            case 2: reduce_values_blocked<2, 4>(part, n, off, ng, out + q); break;
+            case 4: reduce_values_blocked<4, 4>(part, n, off, ng, out + q); break;
+            case 8: reduce_values_blocked<8, 4>(part, n, off, ng, out + q); break;
+            case 16: reduce_values_blocked<16, 4>(part, n, off, ng, out + q); break;
+            default: reduce_values_blocked<32, 1>(part, n, off, ng, out + q); break;
             }
             __syncthreads();   // block_reduce's LDS is reused by the next group
         }
@@ -445,7 +431,7 @@ __device__ void reduce_partials(const double *part, int n, int first, int nv, do
         for (int q = 0; q < nv; ++q) {
             for (int b = 0; b < nblk; ++b) {
                 const int valid = n - b * B < B ? (n - b * B > 0 ? n - b * B : 0) : B;
-                reduce_values_blocked<32, 1>(part, valid, (int64_t)(first + q) * n + (int64_t)b * B, 1, &bsum[q][b], stage);
+                reduce_values_blocked<32, 1>(part, valid, (int64_t)(first + q) * n + (int64_t)b * B, 1, &bsum[q][b]);
                 __syncthreads();
             }
         }
