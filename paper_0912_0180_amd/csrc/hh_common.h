@@ -66,6 +66,30 @@ template <typename T> __host__ __device__ inline V2<T> cdiv(V2<T> a, V2<T> b)
 }
 template <typename T> __host__ __device__ inline V2<T> crs(T s, V2<T> a) { return cmk<T>(s * a.x, s * a.y); }
 
+// Multiply-accumulates of the V-cycle kernels: a - b c, a + b c, a + s x and
+// s x + t y.  In FP64 they are exactly the separate operations above, in that
+// order (the arithmetic contract); FP32 takes fused multiply-adds.
+template <typename T> __host__ __device__ inline V2<T> cmsub(V2<T> a, V2<T> b, V2<T> c) { return csub<T>(a, cmul<T>(b, c)); }
+template <typename T> __host__ __device__ inline V2<T> cmadd(V2<T> a, V2<T> b, V2<T> c) { return cadd<T>(a, cmul<T>(b, c)); }
+template <typename T> __host__ __device__ inline V2<T> crsadd(V2<T> a, T s, V2<T> x) { return cadd<T>(a, crs<T>(s, x)); }
+template <typename T> __host__ __device__ inline V2<T> crs2(T s, V2<T> x, T t, V2<T> y) { return cadd<T>(crs<T>(s, x), crs<T>(t, y)); }
+template <> __host__ __device__ inline V2<float> cmsub<float>(V2<float> a, V2<float> b, V2<float> c)
+{
+    return cmk<float>(fmaf(-b.x, c.x, fmaf(b.y, c.y, a.x)), fmaf(-b.x, c.y, fmaf(-b.y, c.x, a.y)));
+}
+template <> __host__ __device__ inline V2<float> cmadd<float>(V2<float> a, V2<float> b, V2<float> c)
+{
+    return cmk<float>(fmaf(b.x, c.x, fmaf(-b.y, c.y, a.x)), fmaf(b.x, c.y, fmaf(b.y, c.x, a.y)));
+}
+template <> __host__ __device__ inline V2<float> crsadd<float>(V2<float> a, float s, V2<float> x)
+{
+    return cmk<float>(fmaf(s, x.x, a.x), fmaf(s, x.y, a.y));
+}
+template <> __host__ __device__ inline V2<float> crs2<float>(float s, V2<float> x, float t, V2<float> y)
+{
+    return cmk<float>(fmaf(s, x.x, t * y.x), fmaf(s, x.y, t * y.y));
+}
+
 // Explicit global-address-space accesses: pointers taken from descriptors in
 // memory are generic to the compiler, which would otherwise emit flat
 // loads/stores; these emit global_load / global_store.

@@ -269,13 +269,13 @@ __device__ inline V2<T> stencil(const VW &h, const S *__restrict__ x, int i, int
     if (DIM == 3) d = cadd<T>(d, ldg(h.d2, k));
     C D = cmk<T>(d.x - ldg(h.phi, p), d.y);
     C t = cmul<T>(D, xc);
-    t = csub<T>(t, cmul<T>(ldg(h.a0, i), xw));
-    t = csub<T>(t, cmul<T>(ldg(h.c0, i), xe));
-    t = csub<T>(t, cmul<T>(ldg(h.a1, j), xs));
-    t = csub<T>(t, cmul<T>(ldg(h.c1, j), xn));
+    t = cmsub<T>(t, ldg(h.a0, i), xw);
+    t = cmsub<T>(t, ldg(h.c0, i), xe);
+    t = cmsub<T>(t, ldg(h.a1, j), xs);
+    t = cmsub<T>(t, ldg(h.c1, j), xn);
     if (DIM == 3) {
-        t = csub<T>(t, cmul<T>(ldg(h.a2, k), xd));
-        t = csub<T>(t, cmul<T>(ldg(h.c2, k), xu));
+        t = cmsub<T>(t, ldg(h.a2, k), xd);
+        t = cmsub<T>(t, ldg(h.c2, k), xu);
     }
     return t;
 }
@@ -931,13 +931,13 @@ __device__ __forceinline__ void vdown_box(Ctx cx, int lev, int fsel, const void 
         C res = zero;
         if (gx >= 0 && gx < nfx && gy >= 0 && gy < nfy && (DIM == 2 || (gz >= 0 && gz < nfz))) {
             C mu = cmul<T>(Dk[q], U[l]);
-            mu = csub<T>(mu, cmul<T>(A[0][lx], U[l - 1]));
-            mu = csub<T>(mu, cmul<T>(Cc[0][lx], U[l + 1]));
-            mu = csub<T>(mu, cmul<T>(A[1][ly], U[l - RX]));
-            mu = csub<T>(mu, cmul<T>(Cc[1][ly], U[l + RX]));
+            mu = cmsub<T>(mu, A[0][lx], U[l - 1]);
+            mu = cmsub<T>(mu, Cc[0][lx], U[l + 1]);
+            mu = cmsub<T>(mu, A[1][ly], U[l - RX]);
+            mu = cmsub<T>(mu, Cc[1][ly], U[l + RX]);
             if (DIM == 3) {
-                mu = csub<T>(mu, cmul<T>(A[2][lz], U[l - RX * RY]));
-                mu = csub<T>(mu, cmul<T>(Cc[2][lz], U[l + RX * RY]));
+                mu = cmsub<T>(mu, A[2][lz], U[l - RX * RY]);
+                mu = cmsub<T>(mu, Cc[2][lz], U[l + RX * RY]);
             }
             res = csub<T>(fk[q], mu);
         }
@@ -960,12 +960,12 @@ __device__ __forceinline__ void vdown_box(Ctx cx, int lev, int fsel, const void 
                 const T wy = (b == 0 || b == 3) ? w0 : w1;
                 const C *row = &R[bxl + RX * ((byl + b) + RY * (bzl + c))];
                 C sx = crs<T>(w0, row[0]);
-                sx = cadd<T>(sx, crs<T>(w1, row[1]));
-                sx = cadd<T>(sx, crs<T>(w1, row[2]));
-                sx = cadd<T>(sx, crs<T>(w0, row[3]));
-                acc_y = b == 0 ? crs<T>(wy, sx) : cadd<T>(acc_y, crs<T>(wy, sx));
+                sx = crsadd<T>(sx, w1, row[1]);
+                sx = crsadd<T>(sx, w1, row[2]);
+                sx = crsadd<T>(sx, w0, row[3]);
+                acc_y = b == 0 ? crs<T>(wy, sx) : crsadd<T>(acc_y, wy, sx);
             }
-            if (DIM == 3) acc_z = c == 0 ? crs<T>(wz, acc_y) : cadd<T>(acc_z, crs<T>(wz, acc_y));
+            if (DIM == 3) acc_z = c == 0 ? crs<T>(wz, acc_y) : crsadd<T>(acc_z, wz, acc_y);
             else acc_z = acc_y;
         }
         stg(fout, I + (int64_t)ncx * (J + (int64_t)ncy * K), acc_z);
@@ -1111,20 +1111,20 @@ __device__ __forceinline__ void vup_box(Ctx cx, int lev, int fsel, int osel, con
             const int Iy = (gy >> 1) - ey0, Ioy = ((gy & 1) ? (gy >> 1) + 1 : (gy >> 1) - 1) - ey0;
             C pe;
             if (DIM == 2) {
-                C a0 = cadd<T>(crs<T>(p3, E[Ix + EX * Iy]), crs<T>(p1, E[Iox + EX * Iy]));
-                C a1 = cadd<T>(crs<T>(p3, E[Ix + EX * Ioy]), crs<T>(p1, E[Iox + EX * Ioy]));
-                pe = cadd<T>(crs<T>(p3, a0), crs<T>(p1, a1));
+                C a0 = crs2<T>(p3, E[Ix + EX * Iy], p1, E[Iox + EX * Iy]);
+                C a1 = crs2<T>(p3, E[Ix + EX * Ioy], p1, E[Iox + EX * Ioy]);
+                pe = crs2<T>(p3, a0, p1, a1);
             } else {
                 const int Iz = (gz >> 1) - ez0, Ioz = ((gz & 1) ? (gz >> 1) + 1 : (gz >> 1) - 1) - ez0;
                 C pz[2];
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     const int zz = c == 0 ? Iz : Ioz;
-                    C a0 = cadd<T>(crs<T>(p3, E[Ix + EX * (Iy + EY * zz)]), crs<T>(p1, E[Iox + EX * (Iy + EY * zz)]));
-                    C a1 = cadd<T>(crs<T>(p3, E[Ix + EX * (Ioy + EY * zz)]), crs<T>(p1, E[Iox + EX * (Ioy + EY * zz)]));
-                    pz[c] = cadd<T>(crs<T>(p3, a0), crs<T>(p1, a1));
+                    C a0 = crs2<T>(p3, E[Ix + EX * (Iy + EY * zz)], p1, E[Iox + EX * (Iy + EY * zz)]);
+                    C a1 = crs2<T>(p3, E[Ix + EX * (Ioy + EY * zz)], p1, E[Iox + EX * (Ioy + EY * zz)]);
+                    pz[c] = crs2<T>(p3, a0, p1, a1);
                 }
-                pe = cadd<T>(crs<T>(p3, pz[0]), crs<T>(p1, pz[1]));
+                pe = crs2<T>(p3, pz[0], p1, pz[1]);
             }
             u2 = cadd<T>(u1, pe);
         }
@@ -1143,15 +1143,15 @@ __device__ __forceinline__ void vup_box(Ctx cx, int lev, int fsel, int osel, con
         if (halo || gx >= nfx || gy >= nfy || (DIM == 3 && gz >= nfz)) continue;
         const C D = Dk[q], gw = gk[q];
         C mu = cmul<T>(D, U[l]);
-        mu = csub<T>(mu, cmul<T>(A[0][lx], U[l - 1]));
-        mu = csub<T>(mu, cmul<T>(Cc[0][lx], U[l + 1]));
-        mu = csub<T>(mu, cmul<T>(A[1][ly], U[l - RX]));
-        mu = csub<T>(mu, cmul<T>(Cc[1][ly], U[l + RX]));
+        mu = cmsub<T>(mu, A[0][lx], U[l - 1]);
+        mu = cmsub<T>(mu, Cc[0][lx], U[l + 1]);
+        mu = cmsub<T>(mu, A[1][ly], U[l - RX]);
+        mu = cmsub<T>(mu, Cc[1][ly], U[l + RX]);
         if (DIM == 3) {
-            mu = csub<T>(mu, cmul<T>(A[2][lz], U[l - RX * RY]));
-            mu = csub<T>(mu, cmul<T>(Cc[2][lz], U[l + RX * RY]));
+            mu = cmsub<T>(mu, A[2][lz], U[l - RX * RY]);
+            mu = cmsub<T>(mu, Cc[2][lz], U[l + RX * RY]);
         }
-        C u = cadd<T>(U[l], cmul<T>(gw, csub<T>(fk[q], mu)));
+        C u = cmadd<T>(U[l], gw, csub<T>(fk[q], mu));
         const int64_t p = gx + sy * gy + sz * gz;
         if (lev == 0) {
             TO o;
@@ -1252,10 +1252,10 @@ __device__ __forceinline__ V2<T> plane_resid(const V2<T> *U, int l, V2<T> D, V2<
                                              V2<T> cy)
 {
     V2<T> mu = cmul<T>(D, U[l]);
-    mu = csub<T>(mu, cmul<T>(ax, U[l - 1]));
-    mu = csub<T>(mu, cmul<T>(cxx, U[l + 1]));
-    mu = csub<T>(mu, cmul<T>(ay, U[l - RX]));
-    mu = csub<T>(mu, cmul<T>(cy, U[l + RX]));
+    mu = cmsub<T>(mu, ax, U[l - 1]);
+    mu = cmsub<T>(mu, cxx, U[l + 1]);
+    mu = cmsub<T>(mu, ay, U[l - RX]);
+    mu = cmsub<T>(mu, cy, U[l + RX]);
     return csub<T>(f, mu);
 }
 
@@ -1264,9 +1264,9 @@ template <typename T, int EX>
 __device__ __forceinline__ V2<T> plane_prolong(const V2<T> *E, int Ix, int Iox, int Iy, int Ioy)
 {
     const T p3 = (T)0.75, p1 = (T)0.25;
-    const V2<T> a0 = cadd<T>(crs<T>(p3, E[Ix + EX * Iy]), crs<T>(p1, E[Iox + EX * Iy]));
-    const V2<T> a1 = cadd<T>(crs<T>(p3, E[Ix + EX * Ioy]), crs<T>(p1, E[Iox + EX * Ioy]));
-    return cadd<T>(crs<T>(p3, a0), crs<T>(p1, a1));
+    const V2<T> a0 = crs2<T>(p3, E[Ix + EX * Iy], p1, E[Iox + EX * Iy]);
+    const V2<T> a1 = crs2<T>(p3, E[Ix + EX * Ioy], p1, E[Iox + EX * Ioy]);
+    return crs2<T>(p3, a0, p1, a1);
 }
 
 // 2D down-leg of the tile at coarse (c0x, c0y): u1 = g f on the fine box
@@ -1402,10 +1402,10 @@ __device__ __forceinline__ void vdown_plane_tile(DownLds<T, PlaneDown<VT>::RN, P
             const T wy = (b == 0 || b == 3) ? w0 : w1;
             const C *row = &R[bxl + RX * (byl + b)];
             C sx = crs<T>(w0, row[0]);
-            sx = cadd<T>(sx, crs<T>(w1, row[1]));
-            sx = cadd<T>(sx, crs<T>(w1, row[2]));
-            sx = cadd<T>(sx, crs<T>(w0, row[3]));
-            acc = b == 0 ? crs<T>(wy, sx) : cadd<T>(acc, crs<T>(wy, sx));
+            sx = crsadd<T>(sx, w1, row[1]);
+            sx = crsadd<T>(sx, w1, row[2]);
+            sx = crsadd<T>(sx, w0, row[3]);
+            acc = b == 0 ? crs<T>(wy, sx) : crsadd<T>(acc, wy, sx);
         }
         stg(fout, I + (int64_t)ncx * J, acc);
     }
@@ -1561,7 +1561,7 @@ __device__ __forceinline__ void vup_plane_tile(UpLds<T, PlaneUp<VT>::RN, PlaneUp
         if (EDGE && (gx >= nfx || f0y + ly - 1 >= nfy)) continue;
         const int l = lx + RX * ly;
         const C r = plane_resid<T, RX>(U, l, Dk[q], fk[q], axo, cxo, tb.A[1][ly], tb.Cc[1][ly]);
-        const C u = cadd<T>(U[l], cmul<T>(gk[q], r));
+        const C u = cmadd<T>(U[l], gk[q], r);
         if (lev == 0) {
             TO o;
             o.x = u.x;
@@ -1838,10 +1838,10 @@ __global__ __launch_bounds__(NT) void k_vdown_m(Ctx cx, LvChain<T, K> lc)
                 Cx d = cadd<T>(CD[k][lx], CD[k][Wk + ly]);
                 Cx D = cmk<T>(d.x - Pk[l], d.y);
                 Cx mu = cmul<T>(D, U[l]);
-                mu = csub<T>(mu, cmul<T>(CA[k][lx], U[l - 1]));
-                mu = csub<T>(mu, cmul<T>(CC[k][lx], U[l + 1]));
-                mu = csub<T>(mu, cmul<T>(CA[k][Wk + ly], U[l - Wk]));
-                mu = csub<T>(mu, cmul<T>(CC[k][Wk + ly], U[l + Wk]));
+                mu = cmsub<T>(mu, CA[k][lx], U[l - 1]);
+                mu = cmsub<T>(mu, CC[k][lx], U[l + 1]);
+                mu = cmsub<T>(mu, CA[k][Wk + ly], U[l - Wk]);
+                mu = cmsub<T>(mu, CC[k][Wk + ly], U[l + Wk]);
                 res = csub<T>(Fk[l], mu);
             }
             Fk[l] = res;
@@ -1864,10 +1864,10 @@ __global__ __launch_bounds__(NT) void k_vdown_m(Ctx cx, LvChain<T, K> lc)
                         const T wy = (bb == 0 || bb == 3) ? w0 : w1;
                         const Cx *row = &Fk[bxl + Wk * (byl + bb)];
                         Cx sx = crs<T>(w0, row[0]);
-                        sx = cadd<T>(sx, crs<T>(w1, row[1]));
-                        sx = cadd<T>(sx, crs<T>(w1, row[2]));
-                        sx = cadd<T>(sx, crs<T>(w0, row[3]));
-                        acc_y = bb == 0 ? crs<T>(wy, sx) : cadd<T>(acc_y, crs<T>(wy, sx));
+                        sx = crsadd<T>(sx, w1, row[1]);
+                        sx = crsadd<T>(sx, w1, row[2]);
+                        sx = crsadd<T>(sx, w0, row[3]);
+                        acc_y = bb == 0 ? crs<T>(wy, sx) : crsadd<T>(acc_y, wy, sx);
                     }
                     if (ix >= own && ix < own + ownw && iy >= own && iy < own + ownw)
                         stg(fout, I + (int64_t)ncx * J, acc_y);
@@ -2021,9 +2021,9 @@ __global__ __launch_bounds__(NT) void k_vup_m(Ctx cx, LvChain<T, K> lc)
                 Cx u1 = pre ? cmul<T>(gw, Fk[l]) : zero;
                 const int Ix = (gx >> 1) - ox[k + 1], Iox = ((gx & 1) ? (gx >> 1) + 1 : (gx >> 1) - 1) - ox[k + 1];
                 const int Iy = (gy >> 1) - oy[k + 1], Ioy = ((gy & 1) ? (gy >> 1) + 1 : (gy >> 1) - 1) - oy[k + 1];
-                Cx a0 = cadd<T>(crs<T>(p3, Ec[Ix + WE * Iy]), crs<T>(p1, Ec[Iox + WE * Iy]));
-                Cx a1 = cadd<T>(crs<T>(p3, Ec[Ix + WE * Ioy]), crs<T>(p1, Ec[Iox + WE * Ioy]));
-                Cx pe = cadd<T>(crs<T>(p3, a0), crs<T>(p1, a1));
+                Cx a0 = crs2<T>(p3, Ec[Ix + WE * Iy], p1, Ec[Iox + WE * Iy]);
+                Cx a1 = crs2<T>(p3, Ec[Ix + WE * Ioy], p1, Ec[Iox + WE * Ioy]);
+                Cx pe = crs2<T>(p3, a0, p1, a1);
                 u2 = cadd<T>(u1, pe);
             }
             U[l] = u2;
@@ -2044,11 +2044,11 @@ __global__ __launch_bounds__(NT) void k_vup_m(Ctx cx, LvChain<T, K> lc)
                 T qq = jscale<T>(omega, D);
                 Cx gw = cmk<T>(D.x * qq, -(D.y * qq));
                 Cx mu = cmul<T>(D, U[l]);
-                mu = csub<T>(mu, cmul<T>(Ak[lx], U[l - 1]));
-                mu = csub<T>(mu, cmul<T>(Ck[lx], U[l + 1]));
-                mu = csub<T>(mu, cmul<T>(Ak[R + ly], U[l - R]));
-                mu = csub<T>(mu, cmul<T>(Ck[R + ly], U[l + R]));
-                u = cadd<T>(U[l], cmul<T>(gw, csub<T>(Fk[l], mu)));
+                mu = cmsub<T>(mu, Ak[lx], U[l - 1]);
+                mu = cmsub<T>(mu, Ck[lx], U[l + 1]);
+                mu = cmsub<T>(mu, Ak[R + ly], U[l - R]);
+                mu = cmsub<T>(mu, Ck[R + ly], U[l + R]);
+                u = cmadd<T>(U[l], gw, csub<T>(Fk[l], mu));
             }
             if (k == 0) {
                 if (in) stg(lc.L[0].e, gx + (int64_t)nx * gy, u);
@@ -2237,22 +2237,22 @@ __global__ __launch_bounds__(TileSet<3>::T[VT]) void k_vdown_z(Ctx cx, int lev, 
                 const T wy = (b == 0 || b == 3) ? w0 : w1;
                 const C *row = &Rm[bxl + RX * (byl + b)];
                 C sx = crs<T>(w0, row[0]);
-                sx = cadd<T>(sx, crs<T>(w1, row[1]));
-                sx = cadd<T>(sx, crs<T>(w1, row[2]));
-                sx = cadd<T>(sx, crs<T>(w0, row[3]));
-                acc_y = b == 0 ? crs<T>(wy, sx) : cadd<T>(acc_y, crs<T>(wy, sx));
+                sx = crsadd<T>(sx, w1, row[1]);
+                sx = crsadd<T>(sx, w1, row[2]);
+                sx = crsadd<T>(sx, w0, row[3]);
+                acc_y = b == 0 ? crs<T>(wy, sx) : crsadd<T>(acc_y, wy, sx);
             }
             // plane m is term c = 0 of coarse plane (m - 1) / 2 and term
             // c = 2 of the one below (m odd), or terms c = 1 and c = 3 (m even)
             if (m & 1) {
                 const int i = (m - 1) >> 1;
-                if (i >= 1) accOld = cadd<T>(accOld, crs<T>(w1, acc_y));
+                if (i >= 1) accOld = crsadd<T>(accOld, w1, acc_y);
                 accNew = crs<T>(w0, acc_y);
             } else {
                 const int i = (m - 2) >> 1;
-                accNew = cadd<T>(accNew, crs<T>(w1, acc_y));
+                accNew = crsadd<T>(accNew, w1, acc_y);
                 if (i >= 1) {
-                    accOld = cadd<T>(accOld, crs<T>(w0, acc_y));
+                    accOld = crsadd<T>(accOld, w0, acc_y);
                     const int K = c0z + i - 1;
                     if (K < ncz) stg(fout, (c0x + ix) + (int64_t)ncx * ((c0y + iy) + (int64_t)ncy * K), accOld);
                 }
@@ -2277,12 +2277,12 @@ __global__ __launch_bounds__(TileSet<3>::T[VT]) void k_vdown_z(Ctx cx, int lev, 
                         const C d = cadd<T>(dxy[q], Dz[r]);
                         C D = cmk<T>(d.x - pm[q], d.y);
                         C mu = cmul<T>(D, Uc[l]);
-                        mu = csub<T>(mu, cmul<T>(a0q[q], Uc[l - 1]));
-                        mu = csub<T>(mu, cmul<T>(c0q[q], Uc[l + 1]));
-                        mu = csub<T>(mu, cmul<T>(a1q[q], Uc[l - RX]));
-                        mu = csub<T>(mu, cmul<T>(c1q[q], Uc[l + RX]));
-                        mu = csub<T>(mu, cmul<T>(Az[r], Ub[l]));
-                        mu = csub<T>(mu, cmul<T>(Cz[r], Ut[l]));
+                        mu = cmsub<T>(mu, a0q[q], Uc[l - 1]);
+                        mu = cmsub<T>(mu, c0q[q], Uc[l + 1]);
+                        mu = cmsub<T>(mu, a1q[q], Uc[l - RX]);
+                        mu = cmsub<T>(mu, c1q[q], Uc[l + RX]);
+                        mu = cmsub<T>(mu, Az[r], Ub[l]);
+                        mu = cmsub<T>(mu, Cz[r], Ut[l]);
                         res = csub<T>(ccvt<T>(fm[q]), mu);
                     }
                     Rr[l] = res;
@@ -2475,11 +2475,11 @@ __global__ __launch_bounds__(TileSet<3>::T[VT]) void k_vup_z(Ctx cx, int lev, in
 #pragma unroll
                         for (int c = 0; c < 2; ++c) {
                             const int zz = c == 0 ? Iz : Ioz;
-                            C a0 = cadd<T>(crs<T>(p3, E[Ix + EX * (Iy + EY * zz)]), crs<T>(p1, E[Iox + EX * (Iy + EY * zz)]));
-                            C a1 = cadd<T>(crs<T>(p3, E[Ix + EX * (Ioy + EY * zz)]), crs<T>(p1, E[Iox + EX * (Ioy + EY * zz)]));
-                            pz[c] = cadd<T>(crs<T>(p3, a0), crs<T>(p1, a1));
+                            C a0 = crs2<T>(p3, E[Ix + EX * (Iy + EY * zz)], p1, E[Iox + EX * (Iy + EY * zz)]);
+                            C a1 = crs2<T>(p3, E[Ix + EX * (Ioy + EY * zz)], p1, E[Iox + EX * (Ioy + EY * zz)]);
+                            pz[c] = crs2<T>(p3, a0, p1, a1);
                         }
-                        const C pe = cadd<T>(crs<T>(p3, pz[0]), crs<T>(p1, pz[1]));
+                        const C pe = crs2<T>(p3, pz[0], p1, pz[1]);
                         u2 = cadd<T>(u1, pe);
                     }
                     Uj[l] = u2;
@@ -2503,13 +2503,13 @@ __global__ __launch_bounds__(TileSet<3>::T[VT]) void k_vup_z(Ctx cx, int lev, in
                         T qq = jscale<T>(omega, D);
                         C gw = cmk<T>(D.x * qq, -(D.y * qq));
                         C mu = cmul<T>(D, Uc[l]);
-                        mu = csub<T>(mu, cmul<T>(a0q[q], Uc[l - 1]));
-                        mu = csub<T>(mu, cmul<T>(c0q[q], Uc[l + 1]));
-                        mu = csub<T>(mu, cmul<T>(a1q[q], Uc[l - RX]));
-                        mu = csub<T>(mu, cmul<T>(c1q[q], Uc[l + RX]));
-                        mu = csub<T>(mu, cmul<T>(Az[r], Ub[l]));
-                        mu = csub<T>(mu, cmul<T>(Cz[r], Ut[l]));
-                        C u = cadd<T>(Uc[l], cmul<T>(gw, csub<T>(ccvt<T>(fm[q]), mu)));
+                        mu = cmsub<T>(mu, a0q[q], Uc[l - 1]);
+                        mu = cmsub<T>(mu, c0q[q], Uc[l + 1]);
+                        mu = cmsub<T>(mu, a1q[q], Uc[l - RX]);
+                        mu = cmsub<T>(mu, c1q[q], Uc[l + RX]);
+                        mu = cmsub<T>(mu, Az[r], Ub[l]);
+                        mu = cmsub<T>(mu, Cz[r], Ut[l]);
+                        C u = cmadd<T>(Uc[l], gw, csub<T>(ccvt<T>(fm[q]), mu));
                         const int64_t p = pxy[q] + sz * gz;
                         if (lev == 0) {
                             TO o;
@@ -2729,14 +2729,14 @@ __device__ inline V2<T> tail_Mu(const TailPtr<T> &Q, const V2<T> *U, V2<T> D, in
     const C uw = U[i > 0 ? p - 1 : p], ue = U[i < Q.nx - 1 ? p + 1 : p];
     const C us = U[j > 0 ? p - sy : p], un = U[j < Q.ny - 1 ? p + sy : p];
     C mu = cmul<T>(D, U[p]);
-    mu = csub<T>(mu, cmul<T>(Q.A0[i], i > 0 ? uw : zero));
-    mu = csub<T>(mu, cmul<T>(Q.C0[i], i < Q.nx - 1 ? ue : zero));
-    mu = csub<T>(mu, cmul<T>(Q.A1[j], j > 0 ? us : zero));
-    mu = csub<T>(mu, cmul<T>(Q.C1[j], j < Q.ny - 1 ? un : zero));
+    mu = cmsub<T>(mu, Q.A0[i], i > 0 ? uw : zero);
+    mu = cmsub<T>(mu, Q.C0[i], i < Q.nx - 1 ? ue : zero);
+    mu = cmsub<T>(mu, Q.A1[j], j > 0 ? us : zero);
+    mu = cmsub<T>(mu, Q.C1[j], j < Q.ny - 1 ? un : zero);
     if (DIM == 3) {
         const C ub = U[k > 0 ? p - sz : p], ut = U[k < Q.nz - 1 ? p + sz : p];
-        mu = csub<T>(mu, cmul<T>(Q.A2[k], k > 0 ? ub : zero));
-        mu = csub<T>(mu, cmul<T>(Q.C2[k], k < Q.nz - 1 ? ut : zero));
+        mu = cmsub<T>(mu, Q.A2[k], k > 0 ? ub : zero);
+        mu = cmsub<T>(mu, Q.C2[k], k < Q.nz - 1 ? ut : zero);
     }
     return mu;
 }
@@ -2923,12 +2923,12 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
                         v[a] = (jin && ii >= 0 && ii < Q.nx) ? e : zero;
                     }
                     C sx = crs<T>(w0, v[0]);
-                    sx = cadd<T>(sx, crs<T>(w1, v[1]));
-                    sx = cadd<T>(sx, crs<T>(w1, v[2]));
-                    sx = cadd<T>(sx, crs<T>(w0, v[3]));
-                    acc_y = b == 0 ? crs<T>(wy, sx) : cadd<T>(acc_y, crs<T>(wy, sx));
+                    sx = crsadd<T>(sx, w1, v[1]);
+                    sx = crsadd<T>(sx, w1, v[2]);
+                    sx = crsadd<T>(sx, w0, v[3]);
+                    acc_y = b == 0 ? crs<T>(wy, sx) : crsadd<T>(acc_y, wy, sx);
                 }
-                if (DIM == 3) acc_z = c == 0 ? crs<T>(wz, acc_y) : cadd<T>(acc_z, crs<T>(wz, acc_y));
+                if (DIM == 3) acc_z = c == 0 ? crs<T>(wz, acc_y) : crsadd<T>(acc_z, wz, acc_y);
                 else acc_z = acc_y;
             }
             R.F[p] = acc_z;
@@ -2977,20 +2977,20 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
             };
             C pe;
             if (DIM == 2) {
-                C a0 = cadd<T>(crs<T>(p3, ev(Ix, Iy, 0)), crs<T>(p1, ev(Iox, Iy, 0)));
-                C a1 = cadd<T>(crs<T>(p3, ev(Ix, Ioy, 0)), crs<T>(p1, ev(Iox, Ioy, 0)));
-                pe = cadd<T>(crs<T>(p3, a0), crs<T>(p1, a1));
+                C a0 = crs2<T>(p3, ev(Ix, Iy, 0), p1, ev(Iox, Iy, 0));
+                C a1 = crs2<T>(p3, ev(Ix, Ioy, 0), p1, ev(Iox, Ioy, 0));
+                pe = crs2<T>(p3, a0, p1, a1);
             } else {
                 const int Iz = k >> 1, Ioz = (k & 1) ? Iz + 1 : Iz - 1;
                 C pz[2];
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     const int zz = c == 0 ? Iz : Ioz;
-                    C a0 = cadd<T>(crs<T>(p3, ev(Ix, Iy, zz)), crs<T>(p1, ev(Iox, Iy, zz)));
-                    C a1 = cadd<T>(crs<T>(p3, ev(Ix, Ioy, zz)), crs<T>(p1, ev(Iox, Ioy, zz)));
-                    pz[c] = cadd<T>(crs<T>(p3, a0), crs<T>(p1, a1));
+                    C a0 = crs2<T>(p3, ev(Ix, Iy, zz), p1, ev(Iox, Iy, zz));
+                    C a1 = crs2<T>(p3, ev(Ix, Ioy, zz), p1, ev(Iox, Ioy, zz));
+                    pz[c] = crs2<T>(p3, a0, p1, a1);
                 }
-                pe = cadd<T>(crs<T>(p3, pz[0]), crs<T>(p1, pz[1]));
+                pe = crs2<T>(p3, pz[0], p1, pz[1]);
             }
             U[p] = cadd<T>(u1, pe);
         }
@@ -3000,7 +3000,7 @@ __global__ __launch_bounds__(TailCap<T>::WG) void k_vtail(Ctx cx, const int *__r
             tail_ijk(Q, p, i, j, k);
             C D = tail_diag<DIM, T>(Q, i, j, k, p);
             C mu = tail_Mu<DIM, T>(Q, U, D, i, j, k, p);
-            Q.E[p] = cadd<T>(U[p], cmul<T>(jweight<T>(D, omega), csub<T>(Q.F[p], mu)));
+            Q.E[p] = cmadd<T>(U[p], jweight<T>(D, omega), csub<T>(Q.F[p], mu));
         }
         __syncthreads();
     }
