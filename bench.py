@@ -401,6 +401,7 @@ def serve_stream(hh, reqs, arrivals, slots):
     th = threading.Thread(target=producer)
     th.start()
     done = {}
+    reported = 0
     while len(done) < n and not submit_err:
         for q in range(n):
             if q in done or tickets[q] is None:
@@ -408,6 +409,9 @@ def serve_stream(hh, reqs, arrivals, slots):
             r = sv.poll(tickets[q])
             if r is not None:
                 done[q] = r
+        if len(done) >= reported + 100:
+            reported = len(done) - len(done) % 100
+            print("serving: %d of %d requests done" % (len(done), n), file=sys.stderr, flush=True)
         time.sleep(0.001)
     th.join()
     stats = sv.stats()
@@ -445,9 +449,11 @@ def bench_c5(args, torch, hh, W):
         `serve_requests` measured ones (arrivals far above capacity: latency
         is mostly queueing);
     (b) below capacity, `serve_low_requests` at `serve_low_rate` req/s.
-    Untimed: every measured request of (a) gets its true residual with the
-    CPU oracle's operator; those up to 512^2 unknowns are solved by the oracle
-    (FP64) and compared, smallest first, within `serve_oracle_budget_s`."""
+    Untimed: the measured requests of (a) get their true residual with the
+    CPU oracle's operator, in arrival order within `serve_residual_budget_s`
+    (all of them at the default size); those up to 512^2 unknowns are solved
+    by the oracle (FP64) and compared, smallest first, within
+    `serve_oracle_budget_s`."""
     from oracle import oracle as O
     g = W.rng(5)
     nw, nm = args.serve_warmup, args.serve_requests
@@ -474,12 +480,17 @@ def bench_c5(args, torch, hh, W):
     eligible = [q for q in order if int(np.prod(reqs[q]["desc"]["n"][:reqs[q]["desc"]["dim"]])) <= 512 * 512]
     t_or = time.perf_counter()
     for q in range(nw, nw + nm):
+        if time.perf_counter() - t_or > args.serve_residual_budget_s:
+            break
         r = reqs[q]
         o = O.Grid(r["desc"], r["phi"])
         x = results[q][0]
         bb = r["b"].reshape(-1)
         trues.append(float(np.linalg.norm(bb - o.apply(x, "H")) / np.linalg.norm(bb)))
         del o
+        if len(trues) % 250 == 0:
+            print("serving: %d true residuals checked by the oracle" % len(trues), file=sys.stderr, flush=True)
+    t_or = time.perf_counter()
     for q in eligible:
         if time.perf_counter() - t_or > args.serve_oracle_budget_s:
             break
@@ -488,6 +499,7 @@ def bench_c5(args, torch, hh, W):
         xo, io = o.solve(r["b"], tol=1e-8)
         errs.append(float(np.linalg.norm(results[q][0] - xo) / np.linalg.norm(xo)))
         del o
+        print("serving: %d requests solved by the oracle" % len(errs), file=sys.stderr, flush=True)
     res["oracle_true_residual_max"] = max(trues)
     res["oracle_true_residual_checked"] = len(trues)
     res["oracle_solve_eligible"] = len(eligible)
@@ -542,6 +554,119 @@ def bench_c1(args, torch, hh, W):
                           "rel_res_true": info["rel_res_true"], "status": info["status"]}
         res[name] = row
         g.close()
+    return res
+
+
+def bench_c5_long(args, torch, hh, W):
+    """The serving stream at length: `serve_long_warmup` + `serve_long_requests`
+    requests of the serving mix offered at `serve_long_rate` req/s (below
+    capacity, so latency is service, not an ever-growing queue).  Request q is
+    generated from its own seed just before it is submitted, and only the
+    solutions the oracle checks are kept: every measured request of up to
+    512^2 unknowns and a seeded 5% of the rest.  Untimed afterwards, each
+    checked request is regenerated from its seed; its true residual is taken
+    with the CPU oracle's operator, and those of up to 512^2 unknowns are
+    solved by the oracle within `serve_oracle_budget_s` (smallest first)."""
+    import concurrent.futures as cf
+    from oracle import oracle as O
+    nw, nm, rate = args.serve_long_warmup, args.serve_long_requests, args.serve_long_rate
+    n = nw + nm
+    arrivals = W.poisson_arrivals(rate, n, 57)
+    sample5 = W.rng(58).uniform(size=n) < 0.05
+
+    def make(q):
+        return W.serving_request(W.rng(7_000_000 + q))
+
+    sv = hh.Server(budget=0, max_slots=args.serve_slots)
+    tickets = {}
+    sizes = [0] * n
+    err = []
+
+    def producer():
+        t0 = time.perf_counter()
+        try:
+            with cf.ThreadPoolExecutor(4) as ex:
+                ahead = {q: ex.submit(make, q) for q in range(min(n, 16))}
+                for q in range(n):
+                    r = ahead.pop(q).result()
+                    if q + 16 < n:
+                        ahead[q + 16] = ex.submit(make, q + 16)
+                    sizes[q] = int(np.prod(r["desc"]["n"][:r["desc"]["dim"]]))
+                    wait = arrivals[q] - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(wait)
+                    tickets[q] = sv.submit(r["desc"], r["b"], phi=r["phi"], method="bicgstab", vcycle_prec="c64")
+                    del r
+        except Exception as e:       # reported below
+            err.append(repr(e))
+
+    th = threading.Thread(target=producer)
+    t_start = time.perf_counter()
+    th.start()
+    done, keep_x = {}, {}
+    reported = 0
+    while len(done) < n and not err:
+        for q, tk in dict(tickets).items():
+            if q in done:
+                continue
+            r = sv.poll(tk)
+            if r is None:
+                continue
+            done[q] = r[1]
+            if q >= nw and (sizes[q] <= 512 * 512 or sample5[q]):
+                keep_x[q] = r[0]
+        if len(done) >= reported + 100:
+            reported = len(done) - len(done) % 100
+            print("serving (long): %d of %d requests done" % (len(done), n), file=sys.stderr, flush=True)
+        time.sleep(0.002)
+    th.join()
+    wall = time.perf_counter() - t_start
+    stats = sv.stats()
+    sv.close()
+    if err:
+        raise RuntimeError("serving submit failed: %s" % err[0])
+    meas = [done[q] for q in range(nw, n)]
+    lat = [r["t_done"] - r["t_submit"] for r in meas]
+    qwait = [r["t_admit"] - r["t_submit"] for r in meas]
+    t_sub = [r["t_submit"] for r in meas]
+    span_in = max(t_sub) - min(t_sub)
+    span_out = max(r["t_done"] for r in meas) - min(t_sub)
+    res = {"workload": "Poisson stream of the serving mix (as the default serving row), %d warm-up + %d measured "
+                       "requests offered at %.1f req/s" % (nw, nm, rate),
+           "wall_s": wall, "peak_admitted_bytes": int(stats["peak_bytes"]),
+           "requests_measured": nm, "ok": int(sum(r["status"] == 0 for r in meas)),
+           "offered_req_per_s": rate, "arrival_req_per_s": (nm - 1) / span_in if span_in > 0 else None,
+           "achieved_solves_per_s": nm / span_out,
+           "latency_p50_s": pct(lat, 50), "latency_p90_s": pct(lat, 90), "latency_p99_s": pct(lat, 99),
+           "latency_max_s": max(lat), "queue_wait_p50_s": pct(qwait, 50), "queue_wait_p99_s": pct(qwait, 99),
+           "unknowns_measured": int(sum(sizes[nw:])), "max_rel_res_true": float(max(r["rel_res_true"] for r in meas)),
+           "fp64_fallbacks": int(sum(r["fp64_fallback"] for r in meas))}
+    # untimed oracle checks of the kept solutions
+    trues, errs = [], []
+    t_or = time.perf_counter()
+    for q in sorted(keep_x):
+        if time.perf_counter() - t_or > args.serve_residual_budget_s:
+            break
+        r = make(q)
+        o = O.Grid(r["desc"], r["phi"])
+        bb = r["b"].reshape(-1)
+        trues.append(float(np.linalg.norm(bb - o.apply(keep_x[q], "H")) / np.linalg.norm(bb)))
+        del o
+        if len(trues) % 10 == 0:
+            print("serving (long): %d true residuals checked by the oracle" % len(trues), file=sys.stderr, flush=True)
+    small = sorted((q for q in keep_x if sizes[q] <= 512 * 512), key=lambda q: sizes[q])
+    t_or = time.perf_counter()
+    for q in small:
+        if time.perf_counter() - t_or > args.serve_oracle_budget_s:
+            break
+        r = make(q)
+        xo, _ = O.Grid(r["desc"], r["phi"]).solve(r["b"], tol=1e-8)
+        errs.append(float(np.linalg.norm(keep_x[q] - xo) / np.linalg.norm(xo)))
+        print("serving (long): %d requests solved by the oracle" % len(errs), file=sys.stderr, flush=True)
+    res.update({"oracle_checked": len(trues), "oracle_checked_small": sum(1 for q in keep_x if sizes[q] <= 512 * 512),
+                "oracle_true_residual_max": max(trues) if trues else None,
+                "oracle_solve_eligible": len(small), "oracle_solve_checked": len(errs),
+                "rel_err_vs_oracle_max": max(errs) if errs else None})
     return res
 
 
@@ -654,7 +779,14 @@ def main():
     ap.add_argument("--serve-low-rate", type=float, default=3.0)
     ap.add_argument("--serve-low-requests", type=int, default=80)
     ap.add_argument("--serve-oracle-budget-s", type=float, default=90.0)
+    ap.add_argument("--serve-residual-budget-s", type=float, default=300.0,
+                    help="seconds for the oracle's true-residual checks of the measured requests (in arrival order)")
     ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-long", action="store_true",
+                    help="also serve the long stream (serve-long-warmup + serve-long-requests at serve-long-rate)")
+    ap.add_argument("--serve-long-requests", type=int, default=2000)
+    ap.add_argument("--serve-long-warmup", type=int, default=200)
+    ap.add_argument("--serve-long-rate", type=float, default=10.0)
     ap.add_argument("--skip", default="", help="comma list of c1,c3,c4,c5,mp to skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-matvecs", type=int, default=300)
@@ -703,6 +835,9 @@ def main():
         if "mp" not in skip:
             print("bench: mp2/mp3", file=sys.stderr, flush=True)
             out["model_problems"] = bench_mp(args, torch, hh, W)
+    if args.serve_long:
+        print("bench: c5 long", file=sys.stderr, flush=True)
+        out["serving_long"] = bench_c5_long(args, torch, hh, W)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         cpu_baseline(args, cfg, out)
