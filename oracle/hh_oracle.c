@@ -39,8 +39,10 @@
  *   multigrid       Sec. 5.1 / 6.1: geometric multigrid with weighted Jacobi
  *                   smoothing, full-weighting restriction, bilinear
  *                   (trilinear) prolongation, rediscretised coarse
- *                   operators, exact coarsest solve; one V(nu1,nu2) cycle
- *                   per preconditioner application (Sec. 6.2).
+ *                   operators or (2D, Sec. 6.1) Galerkin coarse operators
+ *                   M_{l+1} = R M_l P (25-point: the cell-centred transfers
+ *                   reach two coarse cells), exact coarsest solve; one V(nu1,nu2)
+ *                   cycle per preconditioner application (Sec. 6.2).
  *   Krylov          Sec. 6.2: right-preconditioned Bi-CGSTAB (van der Vorst
  *                   1992) and IDR(s) (Sonneveld & van Gijzen 2008, the
  *                   prototype with minimal-residual omega), stopping on the
@@ -71,6 +73,12 @@
  *                      s = s + ((t - q w) cos((q+1) th/m), (t - q w) sin((q+1) th/m))
  *   stencil            y = Dg*u - a_x*u_w - c_x*u_e - a_y*u_s - c_y*u_n
  *                          - a_z*u_d - c_z*u_u,  Dg = (d_x + d_y + d_z) - phi
+ *   Galerkin stencil   (2D levels >= 1) entries G_s = M_l[p, p + dx + nx*dy],
+ *                      |dx|, |dy| <= 2, s = (dx+2) + 5(dy+2); y = G_12*u_p, then
+ *                      y = y + G_s*u_q for s = 0..24 ascending, s != 12 (u_q = 0
+ *                      outside); Dg = G_12.
+ *                      Column J of M_{l+1} is R (M_l (P e_J)), computed with the
+ *                      transfer and apply functions below.
  *   Jacobi weight      g = omega*conj(Dg)/|Dg|^2 : q = omega/(Dr*Dr + Di*Di),
  *                      g = (Dr*q, -(Di*q))
  *   reductions         chunks of 256 elements; slot t (0..255) of a chunk
@@ -126,10 +134,12 @@ typedef struct {
     long N;
     og_axis ax[3];
     double *phi;           /* N reals, x fastest                            */
+    cx *gal;               /* Galerkin levels: 25 x N stencil (see the contract), else NULL */
 } og_level;
 
 typedef struct og_grid {
     int dim, nlev, centering, csg_mode, nu1, nu2;
+    int coarse_op;             /* 0 rediscretised coarse operators, 1 Galerkin (2D)       */
     double lo[3], hi[3], a[3], b[3];
     double th_ecs, th_csg, omega;
     double beta_re, beta_im;   /* CSG scale factor beta (CSL: principal sqrt of the shift) */
@@ -331,6 +341,7 @@ static void coarsen_phi(const og_level *F, og_level *C, int dim)
 
 static inline cx diag_at(const og_level *L, int dim, int op, int i, int j, int k, long p)
 {
+    if (op == 1 && L->gal) return L->gal[12 * L->N + p];
     cx d = op == 0 ? L->ax[0].dH[i] : L->ax[0].dM[i];
     if (dim >= 2) d = cx_add(d, op == 0 ? L->ax[1].dH[j] : L->ax[1].dM[j]);
     if (dim >= 3) d = cx_add(d, op == 0 ? L->ax[2].dH[k] : L->ax[2].dM[k]);
@@ -345,6 +356,25 @@ static void apply_level(const og_grid *g, int op, int lev, const cx *x, cx *y)
     int dim = g->dim, nx = L->n[0], ny = L->n[1], nz = L->n[2];
     long sy = nx, sz = (long)nx * ny;
     const cx zero = cx_make(0.0, 0.0);
+    if (op == 1 && L->gal) {
+        /* Galerkin level (2D): the stored 25-point stencil */
+        const cx *G = L->gal;
+        long N = L->N;
+#pragma omp parallel for schedule(static) if (L->N > OG_PAR_MIN)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                long p = (long)i + sy * j;
+                cx t = cx_mul(G[12 * N + p], x[p]);
+                for (int s = 0; s < 25; ++s) {
+                    if (s == 12) continue;
+                    int ii = i + s % 5 - 2, jj = j + s / 5 - 2;
+                    cx xq = (ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? x[(long)ii + sy * jj] : zero;
+                    t = cx_add(t, cx_mul(G[s * N + p], xq));
+                }
+                y[p] = t;
+            }
+        return;
+    }
 #pragma omp parallel for schedule(static) if (L->N > OG_PAR_MIN)
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
@@ -535,6 +565,54 @@ static int build_coarse_inverse(og_grid *g)
 /* ------------------------------------------------------------------------ */
 
 void og_free(og_grid *g);
+static void restrict_level(const og_grid *g, int lev, const cx *r, cx *rc);
+static void prolong_level(const og_grid *g, int lev, const cx *ec, cx *ef);
+
+/* Galerkin coarse operators (Sec. 6.1): M_{l+1} = R M_l P for levels 1 ..
+ * nlev-1 in turn, M_0 the rediscretised preconditioner of the finest level.
+ * Column J of M_{l+1} is R (M_l (P e_J)), from the same transfer and apply
+ * functions the V-cycle uses.  P e_J covers fine cells 2J-1 .. 2J+2 per
+ * axis, M_l widens that by its bandwidth (1 on level 0, 2 below), and a
+ * restriction row covers four fine cells, so the nonzeros lie on the 5 x 5
+ * coarse points around J; a nonzero anywhere else is reported as an error. */
+static int build_galerkin(og_grid *g)
+{
+    int bad = 0;
+    for (int l = 1; l < g->nlev; ++l) {
+        og_level *C = &g->lev[l];
+        const og_level *F = &g->lev[l - 1];
+        const long Nc = C->N, Nf = F->N;
+        const int cxn = C->n[0];
+        C->gal = (cx *)calloc((size_t)(25 * Nc), sizeof(cx));
+#pragma omp parallel
+        {
+            cx *e = (cx *)calloc((size_t)Nc, sizeof(cx));
+            cx *w = (cx *)malloc(sizeof(cx) * (size_t)Nf);
+            cx *y = (cx *)malloc(sizeof(cx) * (size_t)Nf);
+            cx *z = (cx *)malloc(sizeof(cx) * (size_t)Nc);
+#pragma omp for schedule(dynamic, 16)
+            for (long J = 0; J < Nc; ++J) {
+                e[J] = cx_make(1.0, 0.0);
+                prolong_level(g, l - 1, e, w);
+                apply_level(g, 1, l - 1, w, y);
+                restrict_level(g, l - 1, y, z);
+                e[J] = cx_make(0.0, 0.0);
+                const int Jx = (int)(J % cxn), Jy = (int)(J / cxn);
+                for (long I = 0; I < Nc; ++I) {
+                    const int dx = Jx - (int)(I % cxn), dy = Jy - (int)(I / cxn);
+                    if (dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2) {
+                        C->gal[((dx + 2) + 5 * (dy + 2)) * Nc + I] = z[I];
+                    } else if (z[I].re != 0.0 || z[I].im != 0.0) {
+#pragma omp atomic write
+                        bad = 1;
+                    }
+                }
+            }
+            free(e); free(w); free(y); free(z);
+        }
+    }
+    return bad ? OG_ERR_ARG : OG_OK;
+}
 
 /* csg_mode: 0 uniform CSG, 1 interior CSG, 2 CSL with shift (shift_re,
  * shift_im); contour_steps: ECS contour parts (<= 1 linear); bc: 6 ints, per
@@ -543,11 +621,12 @@ og_grid *og_create(int dim, const int *n, const double *lo, const double *hi,
                    const double *a, const double *b, double theta_ecs, double theta_csg,
                    int csg_mode, int centering, int levels, int nu1, int nu2, double omega,
                    const double *phi, double shift_re, double shift_im, int contour_steps,
-                   const int *bc, double k_bc)
+                   const int *bc, double k_bc, int coarse_op)
 {
     if (dim < 1 || dim > 3) return NULL;
+    if (coarse_op != 0 && (coarse_op != 1 || dim != 2 || centering != 0)) return NULL;
     og_grid *g = (og_grid *)calloc(1, sizeof(og_grid));
-    g->dim = dim; g->centering = centering; g->csg_mode = csg_mode;
+    g->dim = dim; g->centering = centering; g->csg_mode = csg_mode; g->coarse_op = coarse_op;
     g->nu1 = nu1; g->nu2 = nu2; g->omega = omega;
     g->th_ecs = theta_ecs; g->th_csg = theta_csg;
     g->steps = contour_steps;
@@ -597,6 +676,7 @@ og_grid *og_create(int dim, const int *n, const double *lo, const double *hi,
         if (l == 0) memcpy(L->phi, phi, sizeof(double) * (size_t)L->N);
         else coarsen_phi(&g->lev[l - 1], L, dim);
     }
+    if (coarse_op == 1 && (nl < 2 || build_galerkin(g) != 0)) { og_free(g); return NULL; }
     if (build_coarse_inverse(g) != 0) { og_free(g); return NULL; }
     return g;
 }
@@ -611,6 +691,7 @@ void og_free(og_grid *g)
             free(A->aH); free(A->cH); free(A->dH); free(A->aM); free(A->cM); free(A->dM);
         }
         free(L->phi);
+        free(L->gal);
     }
     free(g->Minv);
     free(g);
@@ -640,6 +721,15 @@ int og_phi(const og_grid *g, int lev, double *out)
 {
     if (lev < 0 || lev >= g->nlev) return OG_ERR_ARG;
     memcpy(out, g->lev[lev].phi, sizeof(double) * (size_t)g->lev[lev].N);
+    return OG_OK;
+}
+
+/* The Galerkin stencil of level lev (25 x N complex values, entry s of point
+ * p at s*N + p); OG_ERR_ARG if the level has none. */
+int og_galerkin(const og_grid *g, int lev, double *out)
+{
+    if (lev < 1 || lev >= g->nlev || !g->lev[lev].gal) return OG_ERR_ARG;
+    memcpy(out, g->lev[lev].gal, sizeof(cx) * (size_t)(25 * g->lev[lev].N));
     return OG_OK;
 }
 

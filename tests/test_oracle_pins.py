@@ -795,3 +795,97 @@ def test_blocked_reductions(oracle_mod):
         bound = 4 * np.finfo(float).eps * (math.log2(n) + 10) * np.sum(np.abs(x) * np.abs(y))
         assert abs(oracle_mod.dotc(x, y) - ref) <= bound
         assert abs(oracle_mod.nrm2(x) - np.linalg.norm(x)) <= 1e-14 * np.linalg.norm(x) * (math.log2(n) + 10)
+
+
+def stencil_to_dense(G, n):
+    """Dense matrix of a 25-point stencil G (25 x N, row s = (dx+2) + 5(dy+2)
+    holding entry [p, p + dx + nx*dy]); entries reaching outside the grid must
+    be zero."""
+    nx, ny = n
+    N = nx * ny
+    D = np.zeros((N, N), dtype=complex)
+    for s in range(25):
+        dx, dy = s % 5 - 2, s // 5 - 2
+        for j in range(ny):
+            for i in range(nx):
+                p = i + nx * j
+                if 0 <= i + dx < nx and 0 <= j + dy < ny:
+                    D[p, p + dx + nx * dy] = G[s, p]
+                else:
+                    assert G[s, p] == 0, (s, i, j)
+    return D
+
+
+@pytest.mark.parametrize("nu1", [1, 0])
+def test_galerkin_coarse_operators_and_vcycle(oracle_mod, nu1):
+    """Galerkin coarse operators (Sec. 6.1), M_{l+1} = R M_l P with the
+    V-cycle's own transfers, assembled here from dense matrices: R = kron of
+    (1,3,3,1)/8, P = 4 R^T, M_0 the finest preconditioner of a one-level grid.
+    Each coarse level's 25-point stencil is checked entry by entry against the
+    dense triple product (and is zero wherever it would reach outside the
+    grid), the coarsest inverse against it, and the three-level V-cycle
+    against B_l = (I - J M)(J + P B_{l+1} R (I - M J)) + J (V(1,1)) or
+    (I - J M) P B_{l+1} R + J (V(0,1)) with Jacobi on the Galerkin diagonals."""
+    n0 = (16, 12)
+    lo, hi, a, b = (-0.25, -0.25), (1.25, 1.25), (0.0, 0.0), (1.0, 1.0)
+    rng = np.random.default_rng(61)
+    phi0 = 150.0 + 60.0 * rng.uniform(size=n0[0] * n0[1])
+    g = oracle_mod.Grid(W.base_desc(2, n0, lo, hi, a, b, levels=3, nu1=nu1, coarse_op=1), phi0)
+    Ms = [oracle_mod.Grid(W.base_desc(2, n0, lo, hi, a, b, levels=1), phi0).matrix("M")]
+    ns = [n0, (8, 6), (4, 3)]
+    Rs = [kron_x_fastest([fw_1d(ns[lev][0]), fw_1d(ns[lev][1])]) for lev in range(2)]
+    for lev in range(2):
+        Ms.append(Rs[lev] @ Ms[lev] @ (4.0 * Rs[lev].T))
+    for lev in (1, 2):
+        D = stencil_to_dense(g.galerkin(lev), ns[lev])
+        scale = np.abs(Ms[lev]).max()
+        assert np.abs(D - Ms[lev]).max() <= 1e-13 * scale, lev
+    Minv = g.coarse_inverse()
+    assert np.abs(Minv @ Ms[2] - np.eye(12)).max() < 1e-12
+    B = np.linalg.inv(Ms[2])
+    for lev in (1, 0):
+        M = Ms[lev]
+        N = M.shape[0]
+        R, P = Rs[lev], 4.0 * Rs[lev].T
+        J = 0.8 * np.diag(1.0 / np.diag(M))
+        I = np.eye(N)
+        B = (I - J @ M) @ (J + P @ B @ R @ (I - M @ J)) + J if nu1 else (I - J @ M) @ P @ B @ R + J
+    f = rng.standard_normal(g.N) + 1j * rng.standard_normal(g.N)
+    want = B @ f
+    assert np.linalg.norm(g.vcycle(f) - want) < 1e-11 * np.linalg.norm(want)
+
+
+def test_galerkin_of_poisson_is_known_stencil(oracle_mod):
+    """Closed form at an interior point: for the Laplacian's 5-point stencil
+    (a real grid without layers, phi = 0, width h) the Galerkin product of the
+    cell-centred transfers factors by axis.  Worked out by hand in 1D, with
+    T = (-1, 2, -1)/h^2, P e_J = (1, 3, 3, 1)/4 on fine cells 2J-1 .. 2J+2 and
+    the restriction row (1, 3, 3, 1)/8 on cells 2I-1 .. 2I+2:
+      T P e_J = (-1, -1, 2, 2, -1, -1)/(4 h^2) on cells 2J-2 .. 2J+3, so
+      R T P has the row (-1, -4, 10, -4, -1)/(32 h^2) (it sums to zero), and
+      R P has the row (0, 3, 10, 3, 0)/16 (it sums to one).
+    In 2D, -Lap = T_x (x) I + I (x) T_y gives the 5 x 5 stencil
+    S[dy][dx] = m[dy] t[dx] + t[dy] m[dx]."""
+    n, h = 16, 1.0 / 16
+    d = W.base_desc(2, (n, n), (0.0, 0.0), (1.0, 1.0), (0.0, 0.0), (1.0, 1.0), theta_csg=0.0, levels=2,
+                    coarse_op=1)
+    g = oracle_mod.Grid(d, np.zeros(n * n))
+    G = g.galerkin(1)
+    I = 4 + 8 * 4        # an interior coarse point of the 8 x 8 level
+    t = np.array([-1.0, -4.0, 10.0, -4.0, -1.0]) / (32.0 * h * h)
+    m = np.array([0.0, 3.0, 10.0, 3.0, 0.0]) / 16.0
+    want = np.outer(m, t) + np.outer(t, m)                   # [dy][dx]
+    got = G[:, I].reshape(5, 5)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), (got, want)
+
+
+@pytest.mark.parametrize("kw", [dict(dim=3), dict(centering=1), dict(levels=1)])
+def test_galerkin_rejected_outside_its_scope(oracle_mod, kw):
+    """Galerkin coarse operators are defined for 2D cell-centred hierarchies."""
+    dim = kw.get("dim", 2)
+    n = (16,) * dim
+    d = W.base_desc(dim, n, (0.0,) * dim, (1.0,) * dim, (0.0,) * dim, (1.0,) * dim,
+                    levels=kw.get("levels", 2 if kw.get("centering", 0) == 0 else 1),
+                    centering=kw.get("centering", 0), coarse_op=1)
+    with pytest.raises(ValueError):
+        oracle_mod.Grid(d, np.zeros(16 ** dim))
