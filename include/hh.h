@@ -86,6 +86,11 @@ typedef enum { HH_METHOD_BICGSTAB = 0, HH_METHOD_IDR = 1 } hh_method;
  * vertices of a uniform grid (Sec. 3, eq. (ecsgrid): n unknowns between the
  * end nodes lo and hi, width (hi - lo)/(n + 1)). */
 typedef enum { HH_CELL = 0, HH_VERTEX = 1 } hh_centering;
+/* Coarse-level operators of the V-cycle: rediscretised on the halved grid, or
+ * Galerkin M_{l+1} = R M_l P with the cycle's own transfers (Sec. 6.1; 2D,
+ * cell-centred; a 25-point stencil per coarse point, since the cell-centred
+ * transfers reach two coarse cells). */
+typedef enum { HH_COARSE_REDISCRETISED = 0, HH_COARSE_GALERKIN = 1 } hh_coarse_op;
 
 /* Grid description (host memory, read during hh_setup_grid only). */
 typedef struct {
@@ -124,6 +129,9 @@ typedef struct {
                                a smooth ECS transition)                                  */
     int32_t bc[3][2];       /* hh_bc per axis, (low side, high side)                     */
     double k_bc;            /* k of the Sommerfeld condition, > 0 when a side uses it    */
+    int32_t coarse_op;      /* hh_coarse_op.  HH_COARSE_GALERKIN: 2D cell-centred grids;
+                               single solves and every V-cycle call (batched solves with
+                               more than one problem, and hh_submit, reject it)          */
 } hh_grid_desc;
 
 typedef struct hh_grid hh_grid;   /* opaque */
@@ -155,7 +163,9 @@ hh_status hh_grid_query(const hh_grid *g, hh_grid_info *info);
  * what = 0 aH, 1 cH, 2 dH (ECS coefficients, level 0 only), 3 aM, 4 cM, 5 dM
  * (CSG coefficients), complex double per unknown of `axis` on `level`;
  * 6 phi of `level` (N_level doubles); 7 the coarsest inverse (Nc*Nc complex
- * double, row major).  `bytes` must equal the array size. */
+ * double, row major); 8 the Galerkin stencil of `level` >= 1 (25 * N_level
+ * complex double, entry s = (dx+2) + 5(dy+2) of point p at s*N + p, the
+ * matrix entry M[p, p + dx + nx*dy]).  `bytes` must equal the array size. */
 hh_status hh_grid_export(const hh_grid *g, int32_t what, int32_t level, int32_t axis, void *host_dst,
                          size_t bytes);
 

@@ -182,6 +182,7 @@ template <typename T> struct LevelDev {
     const T *phi;
     V2<T> *f;                        // restricted right-hand side (levels >= 1)
     V2<T> *e;                        // level solution / correction (levels >= 1)
+    const V2<T> *g;                  // Galerkin levels >= 1: the 25 x N stencil, else null
 };
 
 // LDS layout of the tail kernel (levels t0 .. L-1 of one problem in one

@@ -39,6 +39,12 @@ template <> __device__ inline float jscale<float>(float omega, V2<float> D)
 {
     return omega * __builtin_amdgcn_rcpf(fmaf(D.x, D.x, D.y * D.y));
 }
+// the Jacobi weight g = omega / D = (D.x q, -(D.y q)), q = jscale(omega, D)
+template <typename T> __device__ inline V2<T> jweight(V2<T> D, T omega)
+{
+    T q = jscale<T>(omega, D);
+    return cmk<T>(D.x * q, -(D.y * q));
+}
 
 // ---------------------------------------------------------------------------
 // reductions
@@ -1620,6 +1626,144 @@ __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, in
 }
 
 // ---------------------------------------------------------------------------
+// Fused legs of a Galerkin level l >= 1 (2D): the level's operator is its
+// stored 25-point stencil G (entry s = (dx+2) + 5(dy+2) of point p at s*N + p,
+// the matrix entry M[p, p + dx + nx*dy]), applied as G_12 u_p and then + G_s u_q
+// for s ascending, s != 12, with u = 0 outside the grid; the Jacobi weight is
+// taken from G_12.  Transfers and the order of every other operation are those
+// of the rediscretised legs.  One problem; descriptors by value.
+// ---------------------------------------------------------------------------
+template <typename T> struct GalArgs {
+    const V2<T> *G;      // stencil of the leg's fine level
+    const V2<T> *f;      // f of the fine level
+    V2<T> *e;            // up-leg output: e of the fine level
+    V2<T> *fc;           // down-leg output: f of the coarse level
+    const V2<T> *ec;     // up-leg input: e of the coarse level
+    int nfx, nfy, ncx, ncy;
+    T omega;
+    int pre;             // pre-smoothing (V(1,1)) or none (V(0,1))
+};
+constexpr int GAL_C = 16;    // down-leg: coarse tile side; up-leg: fine tile side 2 GAL_C
+constexpr int GAL_NT = 256;
+
+// Down-leg: u1 = g f on the fine box (the owned 2C x 2C cells and a ring of
+// three: the residual's stencil reaches two cells beyond the restriction's
+// footprint), r = f - G u1 on the footprint (owned cells and a ring of one),
+// full weighting onto the C x C coarse tile.
+template <typename T>
+__global__ __launch_bounds__(GAL_NT) void k_gdown(Ctx cx, GalArgs<T> ga)
+{
+    using C = V2<T>;
+    constexpr int FX = 2 * GAL_C, BX = FX + 6, RX = FX + 2;   // u1 box, residual box
+    __shared__ C U[BX * BX];
+    __shared__ C R[RX * RX];
+    if (phase_of(cx, 0) != PH_RUN) return;
+    const int nfx = ga.nfx, nfy = ga.nfy;
+    const int tiles_x = (ga.ncx + GAL_C - 1) / GAL_C;
+    const int c0x = (blockIdx.x % tiles_x) * GAL_C, c0y = (blockIdx.x / tiles_x) * GAL_C;
+    const int f0x = 2 * c0x, f0y = 2 * c0y;
+    const int64_t N = (int64_t)nfx * nfy;
+    const C zero = cmk<T>(0, 0);
+    for (int l = threadIdx.x; l < BX * BX; l += GAL_NT) {
+        const int gx = f0x - 3 + l % BX, gy = f0y - 3 + l / BX;
+        C u1 = zero;
+        if (ga.pre && gx >= 0 && gx < nfx && gy >= 0 && gy < nfy) {
+            const int64_t p = gx + (int64_t)nfx * gy;
+            u1 = cmul<T>(jweight<T>(ldg(ga.G, 12 * N + p), ga.omega), ldg(ga.f, p));
+        }
+        U[l] = u1;
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < RX * RX; l += GAL_NT) {
+        const int rx = l % RX, ry = l / RX;
+        const int gx = f0x - 1 + rx, gy = f0y - 1 + ry;
+        C res = zero;
+        if (gx >= 0 && gx < nfx && gy >= 0 && gy < nfy) {
+            const int64_t p = gx + (int64_t)nfx * gy;
+            const int c = (rx + 2) + BX * (ry + 2);
+            C mu = cmul<T>(ldg(ga.G, 12 * N + p), U[c]);
+#pragma unroll
+            for (int s = 0; s < 25; ++s) {
+                if (s == 12) continue;
+                mu = cmadd<T>(mu, ldg(ga.G, s * N + p), U[c + (s % 5 - 2) + BX * (s / 5 - 2)]);
+            }
+            res = csub<T>(ldg(ga.f, p), mu);
+        }
+        R[l] = res;
+    }
+    __syncthreads();
+    const T w0 = (T)0.125, w1 = (T)0.375;
+    for (int cl = threadIdx.x; cl < GAL_C * GAL_C; cl += GAL_NT) {
+        const int ix = cl % GAL_C, iy = cl / GAL_C;
+        const int I = c0x + ix, J = c0y + iy;
+        if (I >= ga.ncx || J >= ga.ncy) continue;
+        C acc = zero;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const T wy = (b == 0 || b == 3) ? w0 : w1;
+            const C *row = &R[2 * ix + RX * (2 * iy + b)];
+            C sx = crs<T>(w0, row[0]);
+            sx = crsadd<T>(sx, w1, row[1]);
+            sx = crsadd<T>(sx, w1, row[2]);
+            sx = crsadd<T>(sx, w0, row[3]);
+            acc = b == 0 ? crs<T>(wy, sx) : crsadd<T>(acc, wy, sx);
+        }
+        stg(ga.fc, I + (int64_t)ga.ncx * J, acc);
+    }
+}
+
+// Up-leg: u2 = g f + P e on the owned 2C x 2C fine cells and a ring of two
+// (the stencil's reach), then u = u2 + g (f - G u2) on the owned cells.
+template <typename T>
+__global__ __launch_bounds__(GAL_NT) void k_gup(Ctx cx, GalArgs<T> ga)
+{
+    using C = V2<T>;
+    constexpr int FX = 2 * GAL_C, BX = FX + 4, EX = GAL_C + 4;   // u2 box, coarse box
+    __shared__ C U[BX * BX];
+    __shared__ C E[EX * EX];
+    if (phase_of(cx, 0) != PH_RUN) return;
+    const int nfx = ga.nfx, nfy = ga.nfy;
+    const int tiles_x = (nfx + FX - 1) / FX;
+    const int f0x = (blockIdx.x % tiles_x) * FX, f0y = (blockIdx.x / tiles_x) * FX;
+    const int ex0 = (f0x >> 1) - 2, ey0 = (f0y >> 1) - 2;
+    const int64_t N = (int64_t)nfx * nfy;
+    const C zero = cmk<T>(0, 0);
+    for (int l = threadIdx.x; l < EX * EX; l += GAL_NT) {
+        const int gx = ex0 + l % EX, gy = ey0 + l / EX;
+        E[l] = (gx >= 0 && gx < ga.ncx && gy >= 0 && gy < ga.ncy) ? ldg(ga.ec, gx + (int64_t)ga.ncx * gy) : zero;
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < BX * BX; l += GAL_NT) {
+        const int gx = f0x - 2 + l % BX, gy = f0y - 2 + l / BX;
+        C u2 = zero;
+        if (gx >= 0 && gx < nfx && gy >= 0 && gy < nfy) {
+            const int64_t p = gx + (int64_t)nfx * gy;
+            const C fv = ldg(ga.f, p);
+            const C u1 = ga.pre ? cmul<T>(jweight<T>(ldg(ga.G, 12 * N + p), ga.omega), fv) : zero;
+            const int Ix = (gx >> 1) - ex0, Iox = ((gx & 1) ? (gx >> 1) + 1 : (gx >> 1) - 1) - ex0;
+            const int Iy = (gy >> 1) - ey0, Ioy = ((gy & 1) ? (gy >> 1) + 1 : (gy >> 1) - 1) - ey0;
+            u2 = cadd<T>(u1, plane_prolong<T, EX>(E, Ix, Iox, Iy, Ioy));
+        }
+        U[l] = u2;
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < FX * FX; l += GAL_NT) {
+        const int gx = f0x + l % FX, gy = f0y + l / FX;
+        if (gx >= nfx || gy >= nfy) continue;
+        const int64_t p = gx + (int64_t)nfx * gy;
+        const int c = (l % FX + 2) + BX * (l / FX + 2);
+        const C D = ldg(ga.G, 12 * N + p);
+        C mu = cmul<T>(D, U[c]);
+#pragma unroll
+        for (int s = 0; s < 25; ++s) {
+            if (s == 12) continue;
+            mu = cmadd<T>(mu, ldg(ga.G, s * N + p), U[c + (s % 5 - 2) + BX * (s / 5 - 2)]);
+        }
+        stg(ga.e, p, cmadd<T>(U[c], jweight<T>(D, ga.omega), csub<T>(ldg(ga.f, p), mu)));
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Merged 2D legs of K consecutive coarse levels lev0 .. lev0 + K - 1 (ending
 // at the tail's first level lev0 + K), one launch per leg instead of K.  On
 // these small levels a launch costs its latency, not its work.
@@ -2662,11 +2806,6 @@ __device__ __forceinline__ void coarse_rows_tail(const V2<T> *__restrict__ Minv,
     else coarse_rows_seg<T, 2>(Minv, f, e, n, row0, rstep);
 }
 
-template <typename T> __device__ inline V2<T> jweight(V2<T> D, T omega)
-{
-    T q = jscale<T>(omega, D);
-    return cmk<T>(D.x * q, -(D.y * q));
-}
 
 // What the tail kernel of a one-problem plan takes by value (see k_vtail).
 template <typename T> struct TailArgs {

@@ -39,6 +39,7 @@ struct Plan {
     const LevelDev<float> *lv32h = nullptr;
     double omega1 = 0.8;
     int nu1_1 = 1;                   // one-problem plans: pre-smoothing steps
+    bool galerkin = false;           // one-problem plans: Galerkin coarse operators (levels >= 1)
     std::vector<ProbDev> host;       // host copies of the descriptors of the current solve
     void *mem = nullptr;
     size_t bytes = 0;
@@ -105,6 +106,8 @@ struct hh_grid {
 };
 
 hh_status hh_fail(hh_status st, const char *fmt, ...);
+// the coarsest solve runs in k_coarse (many workgroups) rather than in the tail
+bool coarse_split(const HostSetup &hs);
 hh_status grid_create(HostSetup &&hs, const hh_grid_desc *d, hh_grid **out);
 hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_t &bytes, std::string &err);
 size_t solve_workspace_bytes(int64_t N, int method, bool fp32, int s, int hist_len);

@@ -154,6 +154,13 @@ hh_status grid_upload(hh_grid *g)
                 D.f = D.e = nullptr;
                 F.f = F.e = nullptr;
             }
+            if (!L.gal.empty()) {
+                D.g = c.take<double2>(L.gal.size());
+                F.g = c.take<float2>(L.gal.size());
+            } else {
+                D.g = nullptr;
+                F.g = nullptr;
+            }
         }
         g->Minv64 = c.take<double2>((size_t)hs.Nc * hs.Nc);
         g->Minv32 = c.take<float2>((size_t)hs.Nc * hs.Nc);
@@ -199,6 +206,10 @@ hh_status grid_upload(hh_grid *g)
             HIPCHK(put32c(g->L32h[l].d[a], L.dM[a]));
         }
         HIPCHK(put64(g->L64h[l].phi, L.phi.data(), sizeof(double) * L.N));
+        if (!L.gal.empty()) {
+            HIPCHK(put64(g->L64h[l].g, L.gal.data(), sizeof(double2) * L.gal.size()));
+            HIPCHK(put32c(g->L32h[l].g, L.gal));
+        }
         std::vector<float> p32(L.N);
         for (int64_t i = 0; i < L.N; ++i) p32[i] = (float)L.phi[i];
         HIPCHK(put64(g->L32h[l].phi, p32.data(), sizeof(float) * L.N));
@@ -277,7 +288,7 @@ void grid_fill_prob(const hh_grid *g, ProbDev &pd)
     pd.nu1 = hs.nu1;
     pd.tail64 = tail_level(hs, false);
     pd.tail32 = tail_level(hs, true);
-    pd.csplit = hs.Nc > HH_SPLIT_NC ? 1 : 0;
+    pd.csplit = coarse_split(hs) ? 1 : 0;
     pd.timg64 = g->timg64;
     pd.timg32 = g->timg32;
     pd.ttab64 = g->ttab64;
@@ -321,7 +332,7 @@ static void plan_merge(Plan &pl, const hh_grid *const *G, int count, bool fp32)
     pl.mK = pl.mlev0 = pl.mdn = pl.mKup = pl.mlev0u = pl.mup = 0;
     if (const char *e = getenv("HH_MERGE"))
         if (atoi(e) == 0) return;
-    if (count != 1 || G[0]->hs.dim != 2 || G[0]->host_only) return;
+    if (count != 1 || G[0]->hs.dim != 2 || G[0]->host_only || G[0]->hs.coarse_op == HH_COARSE_GALERKIN) return;
     const HostSetup &hs = G[0]->hs;
     const int t = tail_level(hs, fp32), K = std::min(3, t - 1), Kup = std::min(4, t - 1);
     if (K < 2) return;
@@ -395,10 +406,15 @@ static size_t tail_bytes(const HostSetup &hs, int t, bool fp32)
     return off;
 }
 
+bool coarse_split(const HostSetup &hs) { return hs.Nc > HH_SPLIT_NC || hs.coarse_op == HH_COARSE_GALERKIN; }
+
 // First level of the one-workgroup tail: the finest level >= 1 whose level
-// and every coarser one fit the tail's LDS budget.
+// and every coarser one fit the tail's LDS budget.  A Galerkin hierarchy has
+// no tail levels (the tail kernel knows only the rediscretised stencil): only
+// its coarsest level, which k_coarse solves.
 int tail_level(const HostSetup &hs, bool fp32)
 {
+    if (hs.coarse_op == HH_COARSE_GALERKIN) return hs.nlev - 1;
     const int cap = fp32 ? TailCap<float>::N : TailCap<double>::N;
     const size_t bytes = fp32 ? TailCap<float>::BYTES : TailCap<double>::BYTES;
     for (int t = 1; t < hs.nlev; ++t)
@@ -525,6 +541,10 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         HIPCHK(hipHostMalloc((void **)&pl.hctrl, sizeof(Ctrl) * G.size(), 0));
         pl.hcap = (int)G.size();
     }
+    if (G.size() > 1)
+        for (const hh_grid *g : G)
+            if (g->hs.coarse_op == HH_COARSE_GALERKIN)
+                return hh_fail(HH_ERR_ARG, "Galerkin coarse operators are supported for single solves, not batches");
     pl.count = (int)G.size();
     pl.dim = G.empty() ? 2 : G[0]->hs.dim;
     pl.fp32 = fp32;
@@ -548,7 +568,7 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         const HostSetup &hs = G[q]->hs;
         const int t = tail_level(hs, fp32);
         pl.Lmax = std::max(pl.Lmax, t);
-        const bool split = hs.Nc > HH_SPLIT_NC;
+        const bool split = coarse_split(hs);
         if (split) {
             const int nwg = ceil_div(fp32 ? coarse_waves<float>(hs.Nc) : coarse_waves<double>(hs.Nc), HH_WG / 64);
             int lg = 0;
@@ -595,6 +615,7 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
     pl.probs = c.take<ProbDev>(pl.count);
     pl.ctrl = c.take<Ctrl>(pl.count);
     if (pl.count == 1) {
+        pl.galerkin = G[0]->hs.coarse_op == HH_COARSE_GALERKIN;
         pl.pd1 = G[0]->pd_static;
         pl.L1 = fp32 ? (const void *)G[0]->L32 : (const void *)G[0]->L64;
         pl.omega1 = G[0]->hs.omega;
@@ -873,7 +894,7 @@ static void plan_host_one(Plan &pl, const hh_grid *g, bool fp32, const void *L1,
         pl.up[l].n = nu;
     }
     for (int q = 0; q < 5; ++q) pl.coarse[q].n = 0;
-    const bool split = hs.Nc > HH_SPLIT_NC;
+    const bool split = coarse_split(hs);
     if (split) {
         int lg = 0;
         while ((1 << lg) < coarse_seg(hs.Nc)) ++lg;
@@ -886,6 +907,7 @@ static void plan_host_one(Plan &pl, const hh_grid *g, bool fp32, const void *L1,
     pl.probs = g->pd_static_dev;
     pl.ctrl = nullptr;
     pl.pd1 = g->pd_static;
+    pl.galerkin = hs.coarse_op == HH_COARSE_GALERKIN;
     pl.L1 = L1;
     pl.omega1 = hs.omega;
     pl.nu1_1 = hs.nu1;
@@ -917,6 +939,34 @@ static void launch_merged(int leg, const Plan &pl, hipStream_t s, const LvHost &
     if (K == 2) launch_merged_k<T, 2>(leg, pl, s, L);
     else if (K == 3) launch_merged_k<T, 3>(leg, pl, s, L);
     else launch_merged_k<T, 4>(leg, pl, s, L);
+}
+
+// the fused legs of Galerkin level l >= 1 of a one-problem 2D plan (leg 0
+// down, 1 up), with the level descriptors' host copies
+template <typename T> static void launch_gal_leg(int leg, const Plan &pl, int l, hipStream_t s, const LvHost &lh)
+{
+    const LevelDev<T> *L = lv_of<T>(lh);
+    const LevelDev<T> &F = L[l], &Cs = L[l + 1];
+    GalArgs<T> a;
+    a.G = F.g;
+    a.f = F.f;
+    a.e = F.e;
+    a.fc = Cs.f;
+    a.ec = Cs.e;
+    a.nfx = F.n[0];
+    a.nfy = F.n[1];
+    a.ncx = Cs.n[0];
+    a.ncy = Cs.n[1];
+    a.omega = (T)pl.omega1;
+    a.pre = pl.nu1_1;
+    const Ctx c = ctx_of(pl, pl.chunks);
+    if (leg == 0) {
+        const int n = ceil_div(a.ncx, GAL_C) * ceil_div(a.ncy, GAL_C);
+        hipLaunchKernelGGL((k_gdown<T>), dim3(n), dim3(GAL_NT), 0, s, c, a);
+    } else {
+        const int n = ceil_div(a.nfx, 2 * GAL_C) * ceil_div(a.nfy, 2 * GAL_C);
+        hipLaunchKernelGGL((k_gup<T>), dim3(n), dim3(GAL_NT), 0, s, c, a);
+    }
 }
 
 // tail arguments of a one-problem plan, from its copy of the problem's static
@@ -958,8 +1008,10 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
         lh.f = pl.lv32h;
     }
     const int lsplit = pl.mK ? pl.mlev0 : pl.Lmax;   // first merged level
-    for (int l = 0; l < lsplit; ++l)
-        launch_leg<DIM, T>(0, pl.vdv[l], pl.down[l].n, s, ctx_of(pl, pl.down[l]), l, fsel, osel, fptr, optr, lh);
+    for (int l = 0; l < lsplit; ++l) {
+        if (pl.galerkin && l >= 1) launch_gal_leg<T>(0, pl, l, s, lh);
+        else launch_leg<DIM, T>(0, pl.vdv[l], pl.down[l].n, s, ctx_of(pl, pl.down[l]), l, fsel, osel, fptr, optr, lh);
+    }
     if (pl.mK) launch_merged<T>(0, pl, s, lh);
     {
         // coarse part: tail kernel (whole, or down-legs of split problems),
@@ -985,8 +1037,10 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
         }
     }
     if (pl.mK) launch_merged<T>(1, pl, s, lh);
-    for (int l = (pl.mK ? pl.mlev0u : pl.Lmax) - 1; l >= 0; --l)
-        launch_leg<DIM, T>(1, pl.vuv[l], pl.up[l].n, s, ctx_of(pl, pl.up[l]), l, fsel, osel, fptr, optr, lh);
+    for (int l = (pl.mK ? pl.mlev0u : pl.Lmax) - 1; l >= 0; --l) {
+        if (pl.galerkin && l >= 1) launch_gal_leg<T>(1, pl, l, s, lh);
+        else launch_leg<DIM, T>(1, pl.vuv[l], pl.up[l].n, s, ctx_of(pl, pl.up[l]), l, fsel, osel, fptr, optr, lh);
+    }
 }
 
 void launch_vcycle(const Plan &pl, int fsel, int osel, const void *fptr, void *optr, hipStream_t s)
@@ -1132,6 +1186,8 @@ hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_
         for (int a = 0; a < dim; ++a) g += 3 * align256(sizeof(double2) * L[l].n[a]) + 3 * align256(sizeof(float2) * L[l].n[a]);
         g += align256(sizeof(double) * L[l].N) + align256(sizeof(float) * L[l].N);
         if (l >= 1) g += 2 * align256(sizeof(double2) * L[l].N) + 2 * align256(sizeof(float2) * L[l].N);
+        if (l >= 1 && d->coarse_op == HH_COARSE_GALERKIN)
+            g += align256(sizeof(double2) * 25 * L[l].N) + align256(sizeof(float2) * 25 * L[l].N);
     }
     g += align256(sizeof(double2) * (size_t)nc * nc) + align256(sizeof(float2) * (size_t)nc * nc);
     g += align256(TailCap<double>::BYTES) + align256(TailCap<float>::BYTES);
@@ -1142,7 +1198,8 @@ hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_
     // space), so the FP64 work space is reserved either way
     size_t ws = solve_workspace_bytes(N, o->method, false, s, 0);
     size_t io = 2 * align256(sizeof(double2) * N) + (s > 0 ? align256(sizeof(double2) * (size_t)N * s) : 0);
-    size_t tiles = ngr + (nc > HH_SPLIT_NC ? ceil_div(coarse_waves<double>(nc), HH_WG / 64) : 0);
+    const bool split = nc > HH_SPLIT_NC || d->coarse_op == HH_COARSE_GALERKIN;
+    size_t tiles = ngr + (split ? ceil_div(coarse_waves<double>(nc), HH_WG / 64) : 0);
     for (int l = 0; l + 1 < nl; ++l) {
         int md = 0, mu = 0;
         for (int v = 0; v < HH_NTILE; ++v) {
@@ -1220,6 +1277,10 @@ hh_status hh_grid_export(const hh_grid *g, int32_t what, int32_t level, int32_t 
     } else if (what == 7) {
         src = hs.Minv.data();
         need = sizeof(double2) * hs.Minv.size();
+    } else if (what == 8) {
+        if (hs.lev[level].gal.empty()) return hh_fail(HH_ERR_ARG, "level %d has no Galerkin stencil", level);
+        src = hs.lev[level].gal.data();
+        need = sizeof(double2) * hs.lev[level].gal.size();
     } else {
         return hh_fail(HH_ERR_ARG, "unknown export %d", what);
     }

@@ -25,6 +25,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <thread>
 
 namespace {
 
@@ -199,6 +201,23 @@ void host_apply_M(const HostSetup &hs, int lev, const double2 *x, double2 *y)
     const int nx = L.n[0], ny = L.n[1], nz = L.n[2];
     const int64_t sy = nx, sz = (int64_t)nx * ny;
     const double2 zero = cmk<double>(0.0, 0.0);
+    if (!L.gal.empty()) {
+        // Galerkin level (2D): centre entry first, then the others in entry order
+        const int64_t N = L.N;
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int64_t p = i + sy * j;
+                double2 t = cmul<double>(L.gal[12 * N + p], x[p]);
+                for (int s = 0; s < 25; ++s) {
+                    if (s == 12) continue;
+                    const int ii = i + s % 5 - 2, jj = j + s / 5 - 2;
+                    const double2 xq = (ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? x[ii + sy * jj] : zero;
+                    t = cadd<double>(t, cmul<double>(L.gal[s * N + p], xq));
+                }
+                y[p] = t;
+            }
+        return;
+    }
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -218,6 +237,113 @@ void host_apply_M(const HostSetup &hs, int lev, const double2 *x, double2 *y)
                 }
                 y[p] = t;
             }
+}
+
+// Galerkin operator of level lc (Sec. 6.1), M_lc = R M_{lc-1} P, for the
+// coarse rows [j0, j1): column J is R (M_{lc-1} (P e_J)), evaluated only on
+// the cells it reaches.  Per axis, P e_J is 3/4 or 1/4 on fine cells 2J-1 ..
+// 2J+2 (exact products of the two); M widens that by its bandwidth b (1 for
+// the rediscretised stencil, 2 for a Galerkin one); a restriction row covers
+// fine cells 2I-1 .. 2I+2, so only rows |I - J| <= 2 per axis are nonzero.
+// Values follow the V-cycle's arithmetic: the level's stencil as in
+// host_apply_M, full weighting along x and then y with zero outside the grid,
+// so each entry is what R (M (P e_J)) over whole vectors gives.  Columns are
+// independent; entry (s, I) belongs to column I + offset(s) alone.
+static void galerkin_rows(HostSetup &hs, int lc, int j0, int j1)
+{
+    const HostLevel &F = hs.lev[lc - 1];
+    HostLevel &C = hs.lev[lc];
+    const int nfx = F.n[0], nfy = F.n[1], ncx = C.n[0], ncy = C.n[1];
+    const int64_t Nc = C.N, Nf = F.N;
+    const int b = F.gal.empty() ? 1 : 2;
+    const int W = 4 + 2 * b;   // side of the window of M P e_J
+    const double2 zero = cmk<double>(0.0, 0.0);
+    const double RW[4] = {0.125, 0.375, 0.375, 0.125};
+    // weight of coarse J at fine i along one axis (the prolongation of a unit vector)
+    auto pw = [](int i, int J, int ncoarse) -> double {
+        const int I = i / 2, Io = (i % 2) ? I + 1 : I - 1;
+        if (I == J) return 0.75;
+        return (Io == J && Io >= 0 && Io < ncoarse) ? 0.25 : 0.0;
+    };
+    double2 w[4][4], y[8][8];
+    for (int Jy = j0; Jy < j1; ++Jy)
+        for (int Jx = 0; Jx < ncx; ++Jx) {
+            const int wx0 = 2 * Jx - 1, wy0 = 2 * Jy - 1;
+            for (int v = 0; v < 4; ++v)
+                for (int u = 0; u < 4; ++u) {
+                    const int i = wx0 + u, j = wy0 + v;
+                    const bool in = i >= 0 && i < nfx && j >= 0 && j < nfy;
+                    w[v][u] = in ? cmk<double>(pw(j, Jy, ncy) * pw(i, Jx, ncx), 0.0) : zero;
+                }
+            auto wv = [&](int i, int j) -> double2 {
+                const int u = i - wx0, v = j - wy0;
+                return (u >= 0 && u < 4 && v >= 0 && v < 4) ? w[v][u] : zero;
+            };
+            const int yx0 = wx0 - b, yy0 = wy0 - b;
+            for (int v = 0; v < W; ++v)
+                for (int u = 0; u < W; ++u) {
+                    const int i = yx0 + u, j = yy0 + v;
+                    double2 t = zero;
+                    if (i >= 0 && i < nfx && j >= 0 && j < nfy) {
+                        const int64_t p = i + (int64_t)nfx * j;
+                        if (F.gal.empty()) {
+                            double2 d = cadd<double>(F.dM[0][i], F.dM[1][j]);
+                            const double2 D = cmk<double>(d.x - F.phi[p], d.y);
+                            t = cmul<double>(D, wv(i, j));
+                            t = csub<double>(t, cmul<double>(F.aM[0][i], i > 0 ? wv(i - 1, j) : zero));
+                            t = csub<double>(t, cmul<double>(F.cM[0][i], i < nfx - 1 ? wv(i + 1, j) : zero));
+                            t = csub<double>(t, cmul<double>(F.aM[1][j], j > 0 ? wv(i, j - 1) : zero));
+                            t = csub<double>(t, cmul<double>(F.cM[1][j], j < nfy - 1 ? wv(i, j + 1) : zero));
+                        } else {
+                            t = cmul<double>(F.gal[12 * Nf + p], wv(i, j));
+                            for (int s = 0; s < 25; ++s) {
+                                if (s == 12) continue;
+                                const int ii = i + s % 5 - 2, jj = j + s / 5 - 2;
+                                const double2 xq = (ii >= 0 && ii < nfx && jj >= 0 && jj < nfy) ? wv(ii, jj) : zero;
+                                t = cadd<double>(t, cmul<double>(F.gal[s * Nf + p], xq));
+                            }
+                        }
+                    }
+                    y[v][u] = t;
+                }
+            auto yv = [&](int i, int j) -> double2 {
+                const int u = i - yx0, v = j - yy0;
+                return (u >= 0 && u < W && v >= 0 && v < W) ? y[v][u] : zero;
+            };
+            for (int Iy = Jy - 2; Iy <= Jy + 2; ++Iy)
+                for (int Ix = Jx - 2; Ix <= Jx + 2; ++Ix) {
+                    if (Ix < 0 || Ix >= ncx || Iy < 0 || Iy >= ncy) continue;
+                    double2 rows[4];
+                    for (int q = 0; q < 4; ++q) {
+                        const int j = 2 * Iy - 1 + q;
+                        double2 sx = zero;
+                        for (int r = 0; r < 4; ++r) {
+                            const int i = 2 * Ix - 1 + r;
+                            const double2 val = (i >= 0 && i < nfx) ? yv(i, j) : zero;
+                            sx = r == 0 ? crs<double>(RW[r], val) : cadd<double>(sx, crs<double>(RW[r], val));
+                        }
+                        rows[q] = (j >= 0 && j < nfy) ? sx : zero;
+                    }
+                    double2 z = zero;
+                    for (int q = 0; q < 4; ++q) z = q == 0 ? crs<double>(RW[q], rows[q]) : cadd<double>(z, crs<double>(RW[q], rows[q]));
+                    const int s = (Jx - Ix + 2) + 5 * (Jy - Iy + 2);
+                    C.gal[s * Nc + (Ix + (int64_t)ncx * Iy)] = z;
+                }
+        }
+}
+
+static void galerkin_level(HostSetup &hs, int lc)
+{
+    HostLevel &C = hs.lev[lc];
+    C.gal.assign((size_t)25 * C.N, cmk<double>(0.0, 0.0));
+    const int ny = C.n[1];
+    const int nt = std::max(1, std::min(16, std::min(ny, (int)std::thread::hardware_concurrency())));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) {
+        const int j0 = (int)((int64_t)ny * t / nt), j1 = (int)((int64_t)ny * (t + 1) / nt);
+        th.emplace_back(galerkin_rows, std::ref(hs), lc, j0, j1);
+    }
+    for (auto &x : th) x.join();
 }
 
 hh_status desc_check(const hh_grid_desc *d, int &levels, int &coarse, std::string &err)
@@ -245,6 +371,14 @@ hh_status desc_check(const hh_grid_desc *d, int &levels, int &coarse, std::strin
         return HH_ERR_ARG;
     }
     if (!(d->omega > 0.0 && d->omega < 2.0)) { err = "omega must lie in (0, 2)"; return HH_ERR_ARG; }
+    if (d->coarse_op != HH_COARSE_REDISCRETISED && d->coarse_op != HH_COARSE_GALERKIN) {
+        err = "coarse_op must be 0 (rediscretised) or 1 (Galerkin)";
+        return HH_ERR_ARG;
+    }
+    if (d->coarse_op == HH_COARSE_GALERKIN && (dim != 2 || d->centering != HH_CELL)) {
+        err = "Galerkin coarse operators need a 2D cell-centred grid";
+        return HH_ERR_ARG;
+    }
     int64_t N = 1;
     for (int a = 0; a < dim; ++a) {
         if (d->n[a] < 2) { err = "every side needs at least 2 cells"; return HH_ERR_ARG; }
@@ -382,6 +516,10 @@ hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err)
                     }
         }
     }
+    // Galerkin coarse operators, level after level from the finest preconditioner
+    hs.coarse_op = d->coarse_op;
+    if (hs.coarse_op == HH_COARSE_GALERKIN)
+        for (int l = 1; l < nl; ++l) galerkin_level(hs, l);
     // coarsest inverse (a vertex-centred grid has no hierarchy)
     const int n = (int)Nc;
     hs.Nc = n;

@@ -12,12 +12,15 @@ struct HostLevel {
     int64_t N = 1;
     std::vector<double2> aM[3], cM[3], dM[3];
     std::vector<double> phi;
+    std::vector<double2> gal;     // Galerkin levels >= 1: 25 x N stencil, entry s = (dx+2) + 5(dy+2)
+                                  // of point p at s*N + p (the matrix entry M[p, p + dx + nx*dy])
 };
 
 struct HostSetup {
     int dim = 2, nlev = 1;
     int centering = HH_CELL;                    // HH_VERTEX: one level, no hierarchy
     int nu1 = 1;                                // pre-smoothing steps: 1 (V(1,1)) or 0 (V(0,1))
+    int coarse_op = HH_COARSE_REDISCRETISED;    // HH_COARSE_GALERKIN: levels >= 1 carry gal
     double omega = 0.8;
     std::vector<double2> aH[3], cH[3], dH[3];   // finest level, ECS operator
     HostLevel lev[HH_MAXLEV];
@@ -36,5 +39,7 @@ hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err);
 // Number of levels the automatic rule picks for sides n[0..dim).
 int auto_levels(int dim, const int *n);
 
-// Host evaluation of y = M x on one level (used to build the coarse matrix).
+// Host evaluation of y = M x on one level (used to build the coarse matrix and
+// the Galerkin operators): the rediscretised stencil, or the level's Galerkin
+// stencil when it has one.
 void host_apply_M(const HostSetup &hs, int lev, const double2 *x, double2 *y);

@@ -40,7 +40,7 @@ class GridDesc(ctypes.Structure):
                 ("centering", ctypes.c_int32), ("levels", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("phi", ctypes.c_void_p), ("phi_const", ctypes.c_double),
                 ("host_only", ctypes.c_int32), ("csl_shift", ctypes.c_double * 2), ("contour_steps", ctypes.c_int32),
-                ("bc", (ctypes.c_int32 * 2) * 3), ("k_bc", ctypes.c_double)]
+                ("bc", (ctypes.c_int32 * 2) * 3), ("k_bc", ctypes.c_double), ("coarse_op", ctypes.c_int32)]
 
 
 class GridInfo(ctypes.Structure):
@@ -194,6 +194,7 @@ def make_desc(desc, phi=None, host_only=False):
     for a, sides in enumerate(desc.get("bc", [])[:dim]):
         d.bc[a][0], d.bc[a][1] = int(sides[0]), int(sides[1])
     d.k_bc = float(desc.get("k_bc", 0.0))
+    d.coarse_op = int(desc.get("coarse_op", 0))
     return d, keep
 
 
@@ -251,15 +252,18 @@ class Grid:
 
     def export(self, what, level=0, axis=0):
         """Host copy of a setup array: 'aH','cH','dH','aM','cM','dM' (per axis),
-        'phi' (per level), 'Minv' (coarsest inverse)."""
-        names = ["aH", "cH", "dH", "aM", "cM", "dM", "phi", "Minv"]
+        'phi' (per level), 'Minv' (coarsest inverse), 'galerkin' (the 25 x N
+        stencil of a Galerkin level >= 1)."""
+        names = ["aH", "cH", "dH", "aM", "cM", "dM", "phi", "Minv", "galerkin"]
         w = names.index(what)
         if w <= 5:
             out = np.zeros(self.level_dims[level][axis], dtype=np.complex128)
         elif w == 6:
             out = np.zeros(int(np.prod(self.level_dims[level])), dtype=np.float64)
-        else:
+        elif w == 7:
             out = np.zeros((self.Nc, self.Nc), dtype=np.complex128)
+        else:
+            out = np.zeros((25, int(np.prod(self.level_dims[level]))), dtype=np.complex128)
         check(lib().hh_grid_export(self.h, w, level, axis, out.ctypes.data, out.nbytes))
         return out
 

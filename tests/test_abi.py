@@ -262,3 +262,38 @@ def test_paper_cycle_v01_accepted():
         d.update(nu1=nu1, nu2=nu2)
         with pytest.raises(hh.HHError):
             host_grid(d)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c1_interior", "ragged", "paper"])
+def test_galerkin_host_setup_equals_oracle_bitwise(oracle_mod, cfg):
+    """The library's Galerkin stencils (built on the cells each column reaches)
+    and the coarsest inverse equal the oracle's column-by-column R (M (P e_J))
+    value for value."""
+    if cfg == "ragged":
+        d = W.base_desc(2, (96, 80), (-0.2, -0.3), (1.3, 1.1), (0.0, 0.0), (1.0, 0.9), levels=4, coarse_op=1)
+        phi = 900.0 * (1 + 0.3 * np.random.default_rng(72).uniform(size=96 * 80))
+    else:
+        c = W.c1_paper() if cfg == "paper" else W.c1(mode=1 if cfg == "c1_interior" else 0)
+        d, phi = dict(c["desc"]), c["phi"]
+        d["coarse_op"] = 1
+    g = host_grid(d, phi)
+    o = oracle_mod.Grid(d, phi)
+    assert g.levels == o.nlev
+    for lev in range(1, g.levels):
+        assert np.array_equal(g.export("galerkin", lev), o.galerkin(lev)), lev
+    assert np.array_equal(g.export("Minv"), o.coarse_inverse())
+    with pytest.raises(hh.HHError):
+        g.export("galerkin", 0)
+
+
+def test_galerkin_validation():
+    base = dict(n=(32, 32), lo=(0.0, 0.0), hi=(1.0, 1.0), a=(0.0, 0.0), b=(1.0, 1.0))
+    for kw, msg in ((dict(coarse_op=2), "coarse_op"), (dict(coarse_op=1, centering=1, levels=1), "2D cell-centred")):
+        d = W.base_desc(2, base["n"], base["lo"], base["hi"], base["a"], base["b"], **kw)
+        with pytest.raises(hh.HHError) as ei:
+            host_grid(d, np.zeros(32 * 32))
+        assert msg in str(ei.value)
+    d3 = W.base_desc(3, (16,) * 3, (0.0,) * 3, (1.0,) * 3, (0.0,) * 3, (1.0,) * 3, coarse_op=1)
+    with pytest.raises(hh.HHError) as ei:
+        host_grid(d3, np.zeros(16 ** 3))
+    assert "2D cell-centred" in str(ei.value)
