@@ -525,12 +525,22 @@ PAPER_MP = {
 
 def bench_c1(args, torch, hh, W):
     """C1: the 128^2 grid (layers included) of Sec. 6.1 with kh = 0.625, CSG
-    pi/8 uniform and interior, and the paper-aligned 192^2, k = 80 row;
-    4 levels, Bi-CGSTAB to 1e-8.  The working set (a few MiB) stays in L2, so
+    pi/8 uniform and interior, and the paper-aligned 192^2, k = 80 row, each
+    with rediscretised coarse operators, plus the Galerkin rows (C1 with
+    V(1,1), the 192^2 row with the paper's V(0,1)); 4 levels, Bi-CGSTAB to 1e-8.  The working set (a few MiB) stays in L2, so
     the row reports microseconds per V-cycle and per iteration (two matvecs)
     rather than a bandwidth fraction."""
+    def galerkin(c, nu1):
+        d = dict(c["desc"])
+        d["coarse_op"], d["nu1"] = 1, nu1
+        return dict(c, desc=d)
+
     cases = [("c1_uniform", lambda: W.c1(mode=0)), ("c1_interior", lambda: W.c1(mode=1)),
-             ("c1_paper", lambda: W.c1_paper())]
+             ("c1_paper", lambda: W.c1_paper()),
+             # the paper's multigrid configuration (Sec. 6.1): Galerkin coarse
+             # operators, and the V(0,1) cycle (weighted Jacobi, not ILU(0))
+             ("c1_galerkin", lambda: galerkin(W.c1(mode=0), 1)),
+             ("c1_paper_galerkin_v01", lambda: galerkin(W.c1_paper(), 0))]
     res = {}
     for name, mk in cases:
         c = mk()
@@ -539,7 +549,9 @@ def bench_c1(args, torch, hh, W):
         x = torch.zeros_like(b)
         f = torch.randn(g.N, dtype=torch.complex128, device="cuda")
         row = {"grid": "%dx%d" % (c["desc"]["n"][0], c["desc"]["n"][1]), "levels": g.levels,
-               "csg_mode": ("uniform", "interior")[c["desc"]["csg_mode"]]}
+               "csg_mode": ("uniform", "interior")[c["desc"]["csg_mode"]],
+               "coarse_op": ("rediscretised", "galerkin")[c["desc"].get("coarse_op", 0)],
+               "cycle": "V(%d,1)" % c["desc"].get("nu1", 1)}
         for prec in ("c128", "c64"):
             row["vcycle_us_" + prec] = g.profile_vcycle(f, prec, reps=200)["vcycle_us"]
         for rname, vp in (("bicgstab_fp64", "c128"), ("bicgstab_mixed", "c64")):
