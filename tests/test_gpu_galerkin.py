@@ -5,8 +5,9 @@ The library builds M_{l+1} = R M_l P on the host (the same values as the
 oracle's column-by-column definition, tested bitwise on the CPU); the device
 V-cycle applies the 25-point stencils in the oracle's operation order, so
 FP64 V-cycles and whole FP64 Bi-CGSTAB solves equal the oracle's value for
-value.  The FP32 cycle is held to the tolerance of the rediscretised FP32
-cycle (1e-4 in norm).
+value.  The FP32 cycle is held to 1e-5 in norm: its measured error is up to
+1.0e-6 (the 25-point stencils cancel more than the 5-point ones, whose FP32
+cycle stays near 1.4e-7), and the bound keeps a 10x margin.
 """
 import math
 
@@ -94,7 +95,8 @@ def test_galerkin_vcycle_matches_oracle(torch_dev, hh_mod, oracle_mod, name):
     torch.cuda.synchronize()
     ref = o.vcycle(f)
     assert np.array_equal(u64, ref)
-    assert rel(u32.astype(np.complex128), ref) < 1e-4
+    err = rel(u32.astype(np.complex128), ref)
+    assert err < 1e-5, err
 
 
 @pytest.mark.parametrize("name", ["c1_v11", "ragged_v01", "paper_v01"])

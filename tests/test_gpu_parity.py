@@ -16,6 +16,12 @@ from paper_0912_0180_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
+# FP32 V-cycle against the oracle's FP64 cycle, relative error in norm.  FP32
+# unit roundoff u = 2^-24 = 6.0e-8; the measured error of the rediscretised
+# cycle is 1.1e-7 .. 1.4e-7 (about 2u) on every parity case, so the bound is
+# 1e-6 (about 17u, 7x the largest measured).
+FP32_VCYCLE_TOL = 1e-6
+
 
 @pytest.fixture(scope="module")
 def torch_dev():
@@ -114,7 +120,8 @@ def test_vcycle_matches_oracle(torch_dev, hh_mod, oracle_mod, name):
     torch.cuda.synchronize()
     ref = o.vcycle(f)
     assert same(u64, ref)
-    assert rel(u32.astype(np.complex128), ref) < 1e-4
+    err = rel(u32.astype(np.complex128), ref)
+    assert err < FP32_VCYCLE_TOL, err
 
 
 @pytest.mark.parametrize("name", ["c1", "c1_interior", "ragged_2d", "ragged_3d", "c3_32", "c2_80"])
@@ -654,7 +661,7 @@ def test_merged_coarse_legs_match(torch_dev, hh_mod, oracle_mod, monkeypatch, na
         out[merge] = host(g.vcycle(fd, "c64"))
         g.close()
     assert same(out["1"], out["0"])
-    assert rel(out["1"], ref) < 1e-4
+    assert rel(out["1"], ref) < FP32_VCYCLE_TOL, rel(out["1"], ref)
 
 
 @pytest.mark.parametrize("name", ["c2_256", "ragged_2d", "ragged_3d", "c3_32"])
@@ -680,3 +687,34 @@ def test_every_tile_shape_gives_the_same_cycle(torch_dev, hh_mod, oracle_mod, mo
             u32 = u
         assert same(u, u32), (name, v)
         g.close()
+
+
+def test_c2_full_solve_against_oracle_fixture(torch_dev, hh_mod):
+    """The whole headline solve at 1024^2 against the oracle's own
+    (tests/golden/c2_1024_oracle_solve.json, written from the oracle alone by
+    tests/golden/make_c2_oracle_fixture.py): the FP64 GPU solve reproduces its
+    matvec and iteration counts, its whole residual history and its sampled
+    solution entries value for value; the mixed solve reaches 1e-8 with the
+    sampled entries within 1e-6 of the oracle's (relative)."""
+    import json
+    import os
+    torch = torch_dev
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_1024_oracle_solve.json")
+    fx = json.load(open(path))
+    c = W.c2()
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    b = dev(torch, c["b"])
+    idx = np.array(fx["sample_index"])
+    xo = np.array(fx["sample_re"]) + 1j * np.array(fx["sample_im"])
+    print("case c2 fp64", flush=True)
+    x64, i64 = g.solve(b, tol=1e-8, vcycle_prec="c128", history=True)
+    assert i64["status"] == 0 and fx["status"] == 0
+    assert i64["matvecs"] == fx["matvecs"] and i64["iterations"] == fx["iterations"]
+    assert np.array_equal(i64["history"], np.array(fx["history"]))
+    x64 = host(x64)
+    assert same(x64[idx], xo)
+    assert abs(np.linalg.norm(x64) - fx["x_norm"]) <= 1e-14 * fx["x_norm"]
+    print("case c2 mixed", flush=True)
+    xm, im = g.solve(b, tol=1e-8, vcycle_prec="c64")
+    assert im["status"] == 0 and im["rel_res_true"] < 1e-8
+    assert rel(host(xm)[idx], xo) <= 1e-6

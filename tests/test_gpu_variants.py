@@ -26,6 +26,12 @@ from paper_0912_0180_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
+# FP32 V-cycle against the oracle's FP64 cycle, relative error in norm.  FP32
+# unit roundoff u = 2^-24 = 6.0e-8; the measured error of the rediscretised
+# cycle is 1.1e-7 .. 1.4e-7 (about 2u) on every parity case, so the bound is
+# 1e-6 (about 17u, 7x the largest measured).
+FP32_VCYCLE_TOL = 1e-6
+
 
 @pytest.fixture(scope="module")
 def torch_dev():
@@ -105,7 +111,8 @@ def test_variant_operators_and_vcycle_match_oracle(torch_dev, hh_mod, oracle_mod
     assert same(host(g.apply(xd, "M")), o.apply(x, "M"))
     ref = o.vcycle(x)
     assert same(host(g.vcycle(xd, "c128")), ref)
-    assert rel(host(g.vcycle(xd, "c64")).astype(np.complex128), ref) < 1e-4
+    err = rel(host(g.vcycle(xd, "c64")).astype(np.complex128), ref)
+    assert err < FP32_VCYCLE_TOL, err
 
 
 @pytest.mark.parametrize("name", list(VARIANTS))
@@ -243,7 +250,8 @@ def test_v01_cycle_matches_oracle(torch_dev, hh_mod, oracle_mod, name):
     fd = dev(torch, f)
     ref = o.vcycle(f)
     assert same(host(g.vcycle(fd, "c128")), ref)
-    assert rel(host(g.vcycle(fd, "c64")).astype(np.complex128), ref) < 1e-4
+    err = rel(host(g.vcycle(fd, "c64")).astype(np.complex128), ref)
+    assert err < FP32_VCYCLE_TOL, err
     assert same(host(g.vcycle_noalloc(fd, "c128")), ref)
 
 
