@@ -42,6 +42,8 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_vup_finest_2d_4096_pmc.md")
 # headline recipe at 4x the side, so one launch of the finest up-leg touches
 # ~500 MB, twice the 256 MB Infinity Cache
 ROOFLINE_N = 4096
+# finest levels of at least this many unknowns run the streaming legs
+STREAM_MIN = 8 << 20
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0912_0180_amd", "csrc", f) for f in ("hh_kernels.hpp", "hh_common.h")]
 
 
@@ -273,10 +275,12 @@ def bench_roofline(args, torch, hh, W, out):
     ach = ub / m["up_us"] / 1e3
     out["roofline"] = {
         "bound": "hbm",
-        "kernel": "hh::k_vup<2, float, double2, float2, %d> (finest-level fused up-leg of the FP32 V-cycle: "
-                  "bilinear prolongation + correction + weighted-Jacobi post-smoothing; the same template runs "
-                  "twice per Bi-CGSTAB iteration of the timed solve, shape %d at 1024^2)"
-                  % (m["up_shape"], out.get("finest_legs_mixed", {}).get("up_shape", -1)),
+        "kernel": "hh::k_vup<2, float, double2, float2, %d, %s> (finest-level fused up-leg of the FP32 V-cycle: "
+                  "bilinear prolongation + correction + weighted-Jacobi post-smoothing; hh_solve launches it twice "
+                  "per Bi-CGSTAB iteration, in the streaming form (non-temporal per-point accesses) on finest "
+                  "levels of at least 8M unknowns and in the plain form below, shape %d at 1024^2)"
+                  % (m["up_shape"], "true" if g.N >= STREAM_MIN else "false",
+                     out.get("finest_legs_mixed", {}).get("up_shape", -1)),
         "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS,
         "traffic": measured_traffic(), "bytes_per_unknown": 30, "unknowns_per_launch": g.N,
         "algorithmic_bytes_per_launch": ub, "launch_us": m["up_us"],

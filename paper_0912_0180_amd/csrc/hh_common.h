@@ -141,6 +141,36 @@ __device__ __forceinline__ void stg_nt(double2 *p, int64_t i, double2 v)
     __builtin_nontemporal_store(w, (HH_GLOBAL hh_dvec2 *)p + i);
 }
 
+__device__ __forceinline__ void stg_nt(float2 *p, int64_t i, float2 v)
+{
+    hh_fvec2 w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, (HH_GLOBAL hh_fvec2 *)p + i);
+}
+// streaming loads: input that a launch reads once, from HBM when it exceeds
+// the caches (vector load with the non-temporal hint, which streams at a
+// higher rate than plain loads and leaves the caches to the data that the
+// launch's neighbouring tiles share)
+__device__ __forceinline__ double2 ldg_nt(const double2 *p, int64_t i)
+{
+    const hh_dvec2 v = __builtin_nontemporal_load((const HH_GLOBAL hh_dvec2 *)p + i);
+    double2 r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+__device__ __forceinline__ float2 ldg_nt(const float2 *p, int64_t i)
+{
+    const hh_fvec2 v = __builtin_nontemporal_load((const HH_GLOBAL hh_fvec2 *)p + i);
+    float2 r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+__device__ __forceinline__ float ldg_nt(const float *p, int64_t i) { return __builtin_nontemporal_load((const HH_GLOBAL float *)p + i); }
+__device__ __forceinline__ double ldg_nt(const double *p, int64_t i) { return __builtin_nontemporal_load((const HH_GLOBAL double *)p + i); }
+
 // conversions between the two complex precisions
 template <typename T, typename S> __device__ inline V2<T> ccvt(S v) { return cmk<T>((T)v.x, (T)v.y); }
 
@@ -329,6 +359,15 @@ template <> struct TailCap<float> { static constexpr int N = 1024; static conste
 #define HH_NTILE 9
 #define HH_NBOX 7
 template <int DIM> struct TileSet;
+// Fine levels of at least HH_STREAM_MIN unknowns (one problem, 2D, FP32
+// cycle) run the legs that stream their per-point inputs and the finest
+// output with non-temporal accesses: their fields exceed the 256 MB Infinity
+// Cache, so no reuse is lost, and streaming moves this mix of reads and writes
+// at a higher rate (4096^2 up-leg 99 -> 88 us).  Smaller levels keep plain
+// accesses, which leave f in the cache for the up-leg's second read (2048^2
+// legs measured 15% slower streamed).
+#define HH_STREAM_MIN (int64_t(8) << 20)
+
 template <> struct TileSet<2> {
     static constexpr int N = HH_NBOX + 1;   // shapes in use (the last a 1024-thread box)
     static constexpr int X[HH_NTILE] = {16, 32, 16, 8, 32, 32, 32, 32, 16};

@@ -1278,7 +1278,7 @@ __device__ __forceinline__ V2<T> plane_prolong(const V2<T> *E, int Ix, int Iox, 
 // 2D down-leg of the tile at coarse (c0x, c0y): u1 = g f on the fine box
 // (owned points plus two rings), r = f - M u1 on the owned points and the
 // first ring, full weighting onto the coarse tile.
-template <typename T, typename TF, int VT, bool EDGE>
+template <typename T, typename TF, int VT, bool EDGE, bool STREAM>
 __device__ __forceinline__ void vdown_plane_tile(DownLds<T, PlaneDown<VT>::RN, PlaneDown<VT>::RM> &sm,
                                                  const LevelDev<T> &Lf, const LevelDev<T> &Lc, const TF *__restrict__ f,
                                                  T omega, bool pre, int c0x, int c0y, bool run)
@@ -1309,8 +1309,8 @@ __device__ __forceinline__ void vdown_plane_tile(DownLds<T, PlaneDown<VT>::RN, P
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
         if (!EDGE || (gx < nfx && f0y + ty + q * PR < nfy)) {
-            fr[q] = ldg(f, p0 + q * dq);
-            pr[q] = ldg(phi, p0 + q * dq);
+            fr[q] = STREAM ? ldg_nt(f, p0 + q * dq) : ldg(f, p0 + q * dq);
+            pr[q] = STREAM ? ldg_nt(phi, p0 + q * dq) : ldg(phi, p0 + q * dq);
         }
     }
     const int t1 = threadIdx.x, t2 = NT - 1 - (int)threadIdx.x;   // ring slots (ring 2 from the last thread)
@@ -1417,7 +1417,7 @@ __device__ __forceinline__ void vdown_plane_tile(DownLds<T, PlaneDown<VT>::RN, P
     }
 }
 
-template <typename T, typename TF, int VT>
+template <typename T, typename TF, int VT, bool ST>
 __device__ __forceinline__ void vdown_plane(Ctx cx, int lev, int fsel, const void *fptr, LvPair<T> lp)
 {
     constexpr int CX = TileSet<2>::X[VT], CY = TileSet<2>::Y[VT];
@@ -1443,14 +1443,14 @@ __device__ __forceinline__ void vdown_plane(Ctx cx, int lev, int fsel, const voi
     // the fine box [2 c0x - 2, 2 c0x + 2 CX + 2) (and in y) inside the grid
     const bool edge = c0x == 0 || c0y == 0 || 2 * c0x + 2 * CX + 2 > Lf.n[0] || 2 * c0y + 2 * CY + 2 > Lf.n[1];
     __shared__ DownLds<T, PlaneDown<VT>::RN, PlaneDown<VT>::RM> sm;
-    if (edge) vdown_plane_tile<T, TF, VT, true>(sm, Lf, Lc, f, omega, pre, c0x, c0y, run == PH_RUN);
-    else vdown_plane_tile<T, TF, VT, false>(sm, Lf, Lc, f, omega, pre, c0x, c0y, run == PH_RUN);
+    if (edge) vdown_plane_tile<T, TF, VT, true, false>(sm, Lf, Lc, f, omega, pre, c0x, c0y, run == PH_RUN);
+    else vdown_plane_tile<T, TF, VT, false, ST>(sm, Lf, Lc, f, omega, pre, c0x, c0y, run == PH_RUN);
 }
 
 // 2D up-leg of the fine tile at (f0x, f0y): u2 = g f + P e on the owned
 // points and the ring of one around them, then u = u2 + g (f - M u2) on the
 // owned points.
-template <typename T, typename TF, typename TO, int VT, bool EDGE>
+template <typename T, typename TF, typename TO, int VT, bool EDGE, bool STREAM>
 __device__ __forceinline__ void vup_plane_tile(UpLds<T, PlaneUp<VT>::RN, PlaneUp<VT>::EN, PlaneUp<VT>::RM> &sm,
                                                const LevelDev<T> &Lf, const LevelDev<T> &Lc, const TF *__restrict__ f,
                                                TO *__restrict__ outv, int lev, T omega, bool pre, int f0x, int f0y,
@@ -1489,8 +1489,8 @@ __device__ __forceinline__ void vup_plane_tile(UpLds<T, PlaneUp<VT>::RN, PlaneUp
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
         if (!EDGE || (gx < nfx && f0y + ty + q * PR < nfy)) {
-            fr[q] = ldg(f, p0 + q * dq);
-            pr[q] = ldg(phi, p0 + q * dq);
+            fr[q] = STREAM ? ldg_nt(f, p0 + q * dq) : ldg(f, p0 + q * dq);
+            pr[q] = STREAM ? ldg_nt(phi, p0 + q * dq) : ldg(phi, p0 + q * dq);
         }
     }
     const bool hr = (int)threadIdx.x < NH;
@@ -1572,14 +1572,15 @@ __device__ __forceinline__ void vup_plane_tile(UpLds<T, PlaneUp<VT>::RN, PlaneUp
             TO o;
             o.x = u.x;
             o.y = u.y;
-            stg(outv, p0 + q * dq, o);
+            if (STREAM) stg_nt(outv, p0 + q * dq, o);
+            else stg(outv, p0 + q * dq, o);
         } else {
             stg(Lf.e, p0 + q * dq, u);
         }
     }
 }
 
-template <typename T, typename TF, typename TO, int VT>
+template <typename T, typename TF, typename TO, int VT, bool ST>
 __device__ __forceinline__ void vup_plane(Ctx cx, int lev, int fsel, int osel, const void *fptr, void *optr, LvPair<T> lp)
 {
     constexpr int FX = 2 * TileSet<2>::X[VT], FY = 2 * TileSet<2>::Y[VT];
@@ -1606,22 +1607,25 @@ __device__ __forceinline__ void vup_plane(Ctx cx, int lev, int fsel, int osel, c
     // the fine box [f0x - 1, f0x + FX + 1) (and in y) inside the grid
     const bool edge = f0x == 0 || f0y == 0 || f0x + FX + 1 > Lf.n[0] || f0y + FY + 1 > Lf.n[1];
     __shared__ UpLds<T, PlaneUp<VT>::RN, PlaneUp<VT>::EN, PlaneUp<VT>::RM> sm;
-    if (edge) vup_plane_tile<T, TF, TO, VT, true>(sm, Lf, Lc, f, outv, lev, omega, pre, f0x, f0y, run == PH_RUN);
-    else vup_plane_tile<T, TF, TO, VT, false>(sm, Lf, Lc, f, outv, lev, omega, pre, f0x, f0y, run == PH_RUN);
+    if (edge) vup_plane_tile<T, TF, TO, VT, true, false>(sm, Lf, Lc, f, outv, lev, omega, pre, f0x, f0y, run == PH_RUN);
+    else vup_plane_tile<T, TF, TO, VT, false, ST>(sm, Lf, Lc, f, outv, lev, omega, pre, f0x, f0y, run == PH_RUN);
 }
 
-// The fused legs: the plane form in 2D, the box form in 3D.
-template <int DIM, typename T, typename TF, int VT>
+// The fused legs: the plane form in 2D, the box form in 3D.  ST: the 2D
+// interior tiles stream their per-point inputs and the finest output with
+// non-temporal accesses (the host takes it for levels of at least
+// HH_STREAM_MIN points).
+template <int DIM, typename T, typename TF, int VT, bool ST = false>
 __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vdown(Ctx cx, int lev, int fsel, const void *fptr, LvPair<T> lp)
 {
-    if constexpr (DIM == 2) vdown_plane<T, TF, VT>(cx, lev, fsel, fptr, lp);
+    if constexpr (DIM == 2) vdown_plane<T, TF, VT, ST>(cx, lev, fsel, fptr, lp);
     else vdown_box<DIM, T, TF, VT>(cx, lev, fsel, fptr, lp);
 }
-template <int DIM, typename T, typename TF, typename TO, int VT>
+template <int DIM, typename T, typename TF, typename TO, int VT, bool ST = false>
 __global__ __launch_bounds__(TileSet<DIM>::T[VT]) void k_vup(Ctx cx, int lev, int fsel, int osel, const void *fptr, void *optr,
                                                 LvPair<T> lp)
 {
-    if constexpr (DIM == 2) vup_plane<T, TF, TO, VT>(cx, lev, fsel, osel, fptr, optr, lp);
+    if constexpr (DIM == 2) vup_plane<T, TF, TO, VT, ST>(cx, lev, fsel, osel, fptr, optr, lp);
     else vup_box<DIM, T, TF, TO, VT>(cx, lev, fsel, osel, fptr, optr, lp);
 }
 

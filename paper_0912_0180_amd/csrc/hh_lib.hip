@@ -10,6 +10,7 @@
 #include <array>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -706,6 +707,45 @@ static void launch_up_v(int v, int n, hipStream_t s, const Ctx &c, int lev, int 
     }
 }
 
+// the streaming forms of the 2D FP32 finest-level legs (k_vdown / k_vup with
+// ST = true), for levels of at least HH_STREAM_MIN unknowns; HH_STREAM=0
+// keeps the plain forms (same values, bit for bit)
+static bool stream_legs()
+{
+    const char *e = getenv("HH_STREAM");
+    return !e || atoi(e) != 0;
+}
+static void launch_down_stream(int v, int n, hipStream_t s, const Ctx &c, int fsel, const void *fptr,
+                               const LvPair<float> &lp)
+{
+    constexpr int DIM = 2;
+    switch (v) {
+    case 0: LAUNCH_V((k_vdown<2, float, double2, 0, true>), 0, n, s, c, 0, fsel, fptr, lp); break;
+    case 1: LAUNCH_V((k_vdown<2, float, double2, 1, true>), 1, n, s, c, 0, fsel, fptr, lp); break;
+    case 2: LAUNCH_V((k_vdown<2, float, double2, 2, true>), 2, n, s, c, 0, fsel, fptr, lp); break;
+    case 3: LAUNCH_V((k_vdown<2, float, double2, 3, true>), 3, n, s, c, 0, fsel, fptr, lp); break;
+    case 4: LAUNCH_V((k_vdown<2, float, double2, 4, true>), 4, n, s, c, 0, fsel, fptr, lp); break;
+    case 5: LAUNCH_V((k_vdown<2, float, double2, 5, true>), 5, n, s, c, 0, fsel, fptr, lp); break;
+    case 6: LAUNCH_V((k_vdown<2, float, double2, 6, true>), 6, n, s, c, 0, fsel, fptr, lp); break;
+    default: LAUNCH_V((k_vdown<2, float, double2, 7, true>), 7, n, s, c, 0, fsel, fptr, lp); break;
+    }
+}
+static void launch_up_stream(int v, int n, hipStream_t s, const Ctx &c, int fsel, int osel, const void *fptr, void *optr,
+                             const LvPair<float> &lp)
+{
+    constexpr int DIM = 2;
+    switch (v) {
+    case 0: LAUNCH_V((k_vup<2, float, double2, float2, 0, true>), 0, n, s, c, 0, fsel, osel, fptr, optr, lp); break;
+    case 1: LAUNCH_V((k_vup<2, float, double2, float2, 1, true>), 1, n, s, c, 0, fsel, osel, fptr, optr, lp); break;
+    case 2: LAUNCH_V((k_vup<2, float, double2, float2, 2, true>), 2, n, s, c, 0, fsel, osel, fptr, optr, lp); break;
+    case 3: LAUNCH_V((k_vup<2, float, double2, float2, 3, true>), 3, n, s, c, 0, fsel, osel, fptr, optr, lp); break;
+    case 4: LAUNCH_V((k_vup<2, float, double2, float2, 4, true>), 4, n, s, c, 0, fsel, osel, fptr, optr, lp); break;
+    case 5: LAUNCH_V((k_vup<2, float, double2, float2, 5, true>), 5, n, s, c, 0, fsel, osel, fptr, optr, lp); break;
+    case 6: LAUNCH_V((k_vup<2, float, double2, float2, 6, true>), 6, n, s, c, 0, fsel, osel, fptr, optr, lp); break;
+    default: LAUNCH_V((k_vup<2, float, double2, float2, 7, true>), 7, n, s, c, 0, fsel, osel, fptr, optr, lp); break;
+    }
+}
+
 // host copies of one problem's level descriptors (null for a batch)
 struct LvHost {
     const LevelDev<double> *d = nullptr;
@@ -727,6 +767,13 @@ static void launch_leg(int leg, int v, int n, hipStream_t s, const Ctx &c, int l
         lp.f = L[lev];
         lp.c = L[lev + 1];
         lp.valid = 1;
+    }
+    if constexpr (DIM == 2 && std::is_same<T, float>::value) {
+        if (lev == 0 && lp.valid && lp.f.N >= HH_STREAM_MIN && stream_legs()) {
+            if (leg == 0) launch_down_stream(v, n, s, c, fsel, fptr, lp);
+            else launch_up_stream(v, n, s, c, fsel, osel, fptr, optr, lp);
+            return;
+        }
     }
     if (leg == 0) {
         if (lev == 0) launch_down_v<DIM, T, double2>(v, n, s, c, lev, fsel, fptr, lp);

@@ -689,6 +689,33 @@ def test_every_tile_shape_gives_the_same_cycle(torch_dev, hh_mod, oracle_mod, mo
         g.close()
 
 
+def test_streaming_legs_equal_plain_legs(torch_dev, hh_mod, oracle_mod, monkeypatch):
+    """Finest 2D levels of at least 8M unknowns run the FP32 legs with
+    non-temporal per-point accesses (interior tiles).  The arithmetic is the
+    plain legs', so the cycle equals theirs bit for bit (HH_STREAM=0), and it
+    stays within the FP32 bound of the oracle's FP64 cycle."""
+    torch = torch_dev
+    n = 2944
+    c = W.c2(n=n, levels=8)
+    assert n * n >= 8 << 20
+    print("case c2_%d" % n, flush=True)
+    f = rand_c(np.random.default_rng(10), n * n)
+    fd = dev(torch, f)
+    out = {}
+    for st in ("1", "0"):
+        monkeypatch.setenv("HH_STREAM", st)
+        g = hh_mod.Grid(c["desc"], c["phi"])
+        out[st] = host(g.vcycle(fd, "c64"))
+        g.close()
+    assert same(out["1"], out["0"])
+    del fd
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    ref = o.vcycle(f)
+    err = rel(out["1"], ref)
+    print("FP32 cycle vs oracle", err, flush=True)
+    assert err < FP32_VCYCLE_TOL, err
+
+
 def test_c2_full_solve_against_oracle_fixture(torch_dev, hh_mod):
     """The whole headline solve at 1024^2 against the oracle's own
     (tests/golden/c2_1024_oracle_solve.json, written from the oracle alone by
