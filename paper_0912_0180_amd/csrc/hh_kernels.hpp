@@ -550,7 +550,19 @@ __device__ inline void bi_record(const ProbDev *pd, BiLoc &b, double rel)
     if (pd->hist && b.mv - 1 < b.hist_len && b.mv >= 1) pd->hist[b.mv - 1] = rel;
 }
 
-__device__ void finalize(const ProbDev *pd, int kind)
+// the phases in which a pass's finalisation advances the state (otherwise the
+// problem has stopped, or half-stopped, and the pass is a no-op)
+__device__ inline bool fin_runs(int kind, int phase)
+{
+    if (kind == FIN_RHO) return phase == PH_RUN || phase == PH_HALF;
+    if (kind == FIN_ALPHA || kind == FIN_OMEGA) return phase == PH_RUN;
+    if (kind >= FIN_IDR_OMEGA && kind != FIN_IDR_INIT) return phase == PH_RUN;
+    return true;
+}
+
+// gate: skip the update unless fin_runs(kind, phase of the state block),
+// decided after the state and the partials are loaded
+__device__ __forceinline__ void finalize(const ProbDev *pd, int kind, bool gate)
 {
     SolveState *st = pd->st;
     BiLoc b;
@@ -581,6 +593,7 @@ __device__ void finalize(const ProbDev *pd, int kind)
     reduce_partials(pd->part, pd->ngroup, first, nv, res);
     const double *s = res;
     if (threadIdx.x != 0) return;
+    if (gate && !fin_runs(kind, phase)) return;
     if (kind >= FIN_IDR_OMEGA) {
         idr_finalize(pd, st, kind, s, phase);
         mirror(pd, st);
@@ -731,15 +744,19 @@ __global__ __launch_bounds__(HH_WG) void k_fin(Ctx cx, const int *__restrict__ p
     const int prob = probs ? probs[blockIdx.x] : 0;
     const ProbDev *pd = cx.P + prob;
     // the control block mirrors the phase of the state block; one load
-    const int phase = phase_of(cx, prob);
-    if (kind == FIN_RHO) {
-        if (phase != PH_RUN && phase != PH_HALF) return;
-    } else if (kind == FIN_ALPHA || kind == FIN_OMEGA) {
-        if (phase != PH_RUN) return;
-    } else if (kind >= FIN_IDR_OMEGA && kind != FIN_IDR_INIT) {
-        if (phase != PH_RUN) return;
-    }
-    finalize(pd, kind);
+    if (!fin_runs(kind, phase_of(cx, prob))) return;
+    finalize(pd, kind, false);
+}
+
+// k_fin of a one-problem plan: the problem descriptor comes by value, so the
+// loads of the state block and of the partials issue together instead of
+// behind the control block's phase and the descriptor's pointers (three
+// dependent round trips to memory the other XCDs wrote); the phase gate is
+// applied after them, on the state block's phase (which the control block
+// mirrors).
+__global__ __launch_bounds__(HH_WG) void k_fin1(int kind, ProbDev pv)
+{
+    finalize(&pv, kind, true);
 }
 
 // ---------------------------------------------------------------------------

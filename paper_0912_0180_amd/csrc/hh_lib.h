@@ -48,7 +48,7 @@ struct Plan {
     hipStream_t stream = nullptr;
     hipGraphExec_t gexec = nullptr;
     int gmethod = -1, gK = 0;
-    void *gvec[VS_NVEC] = {};        // one-problem plans: the vectors the graph's V-cycles name
+    ProbDev gpd{};                   // one-problem plans: the descriptor the graph was captured with
     Ctrl *hctrl = nullptr;
     int hcap = 0;                    // capacity of hctrl (problems)
 };

@@ -1103,6 +1103,10 @@ void launch_vcycle(const Plan &pl, int fsel, int osel, const void *fptr, void *o
 
 void launch_fin(const Plan &pl, const int *probs, int n, int kind, hipStream_t s)
 {
+    if (pl.count == 1 && !pl.host.empty()) {
+        if (n > 0) hipLaunchKernelGGL(k_fin1, dim3(1), dim3(HH_WG), 0, s, kind, pl.host[0]);
+        return;
+    }
     const Ctx c = ctx_of(pl, pl.chunks);
     LAUNCH(k_fin, n, s, c, pl.count == 1 ? nullptr : probs, kind);
 }

@@ -343,11 +343,13 @@ hh_status KBatch::launch()
         return HH_OK;
     }
     // the graph bakes in the plan's lists and, for one-problem plans, the
-    // work-space vectors the V-cycle reads and writes (a work space
-    // reallocated at the same address may be carved differently)
-    void *vec[VS_NVEC] = {};
-    if (pl_->count == 1) memcpy(vec, pl_->host[0].vec, sizeof vec);
-    if (!pl_->gexec || pl_->gmethod != method_ || pl_->gK != K_ || memcmp(vec, pl_->gvec, sizeof vec) != 0) {
+    // problem descriptor the finalisation takes by value, with the work-space
+    // vectors the V-cycle reads and writes (a work space reallocated at the
+    // same address may be carved differently)
+    ProbDev key;
+    memset(&key, 0, sizeof key);
+    if (pl_->count == 1) memcpy(&key, &pl_->host[0], sizeof key);   // padding zero (grid_fill_prob)
+    if (!pl_->gexec || pl_->gmethod != method_ || pl_->gK != K_ || memcmp(&key, &pl_->gpd, sizeof key) != 0) {
         if (pl_->gexec) {
             HIPCHK(hipGraphExecDestroy(pl_->gexec));
             pl_->gexec = nullptr;
@@ -364,7 +366,7 @@ hh_status KBatch::launch()
         }
         pl_->gmethod = method_;
         pl_->gK = K_;
-        memcpy(pl_->gvec, vec, sizeof vec);
+        memcpy(&pl_->gpd, &key, sizeof key);
     }
     HIPCHK(hipGraphLaunch(pl_->gexec, s));
     return HH_OK;
