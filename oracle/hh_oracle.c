@@ -37,6 +37,7 @@
  *                   (lapctuecs).  Cell-centred topology (Sec. 6) by default,
  *                   vertex-centred (Sec. 3, eq. (ecsgrid)) for closed forms.
  *   multigrid       Sec. 5.1 / 6.1: geometric multigrid with weighted Jacobi
+ *                   smoothing or (2D, Sec. 6.1, the paper's choice) ILU(0)
  *                   smoothing, full-weighting restriction, bilinear
  *                   (trilinear) prolongation, rediscretised coarse
  *                   operators or (2D, Sec. 6.1) Galerkin coarse operators
@@ -53,7 +54,8 @@
  * Parity pins live in tests/test_oracle_pins.py (closed-form eigenpairs,
  * Lemma 3.1 box, Lemma 3.2 eigenvalue condition, CSL/CSG identity of eq.
  * (CSL-CSG), the 1D outgoing Green's function, dense direct solves, grid
- * transfer identities).  The multigrid convergence factor and the Krylov
+ * transfer identities, Galerkin products, the ILU(0) factors' L U = M on the
+ * pattern of M).  The multigrid convergence factor and the Krylov
  * iteration counts are "parity unpinned" by the paper (its numbers are for a
  * different smoother and coarse operator); they are checked only for
  * self-consistency and against the device path.
@@ -79,6 +81,22 @@
  *                      outside); Dg = G_12.
  *                      Column J of M_{l+1} is R (M_l (P e_J)), computed with the
  *                      transfer and apply functions below.
+ *   ILU(0) smoother    (2D, Sec. 6.1) on levels 0 .. nlev-2.  Stencil of M_l in the
+ *                      Galerkin layout s = (dx+2) + 5(dy+2): the Galerkin stencil, or
+ *                      on a rediscretised level the 5-point set s = 12: Dg, 11: -a_x,
+ *                      13: -c_x, 7: -a_y, 17: -c_y (in-grid neighbours only).  Pattern:
+ *                      the diagonal and the in-grid entries that are nonzero.  Rows p
+ *                      ascending; in row p the pattern's columns q < p ascending:
+ *                      l = a[p,q] / a[q,q] (contract divide), then for each pattern
+ *                      column c > q of row p whose entry (q, c) is in row q's pattern:
+ *                      a[p,c] = a[p,c] - l*a[q,c].  Stored: l below the diagonal,
+ *                      u on and above it (zero off the pattern).  A sweep: r = f - M u
+ *                      (stencil above); forward, p ascending: y = r_p, then
+ *                      y = y - l_s*y_q over the level's offsets (the 5-point set, or all
+ *                      25) below the diagonal, in-grid, columns ascending; backward, p
+ *                      descending: z = y_p, z = z - u_s*z_c over those above the
+ *                      diagonal, columns ascending, z = z / u_12 (contract divide);
+ *                      u = u + omega*z (omega real, separate products).
  *   Jacobi weight      g = omega*conj(Dg)/|Dg|^2 : q = omega/(Dr*Dr + Di*Di),
  *                      g = (Dr*q, -(Di*q))
  *   reductions         chunks of 256 elements; slot t (0..255) of a chunk
@@ -135,11 +153,13 @@ typedef struct {
     og_axis ax[3];
     double *phi;           /* N reals, x fastest                            */
     cx *gal;               /* Galerkin levels: 25 x N stencil (see the contract), else NULL */
+    cx *ilu;               /* ILU(0) smoother: 25 x N factors (see the contract), else NULL */
 } og_level;
 
 typedef struct og_grid {
     int dim, nlev, centering, csg_mode, nu1, nu2;
     int coarse_op;             /* 0 rediscretised coarse operators, 1 Galerkin (2D)       */
+    int smoother;              /* 0 weighted Jacobi, 1 ILU(0) (2D, V(0,1))                */
     double lo[3], hi[3], a[3], b[3];
     double th_ecs, th_csg, omega;
     double beta_re, beta_im;   /* CSG scale factor beta (CSL: principal sqrt of the shift) */
@@ -614,6 +634,134 @@ static int build_galerkin(og_grid *g)
     return bad ? OG_ERR_ARG : OG_OK;
 }
 
+/* Entry s (Galerkin layout, s = (dx+2) + 5(dy+2)) of row p of M_l, 2D; zero
+ * for a neighbour outside the grid and, on a rediscretised level, off the
+ * 5-point set. */
+static cx level_entry(const og_grid *g, int lev, int s, int i, int j)
+{
+    const og_level *L = &g->lev[lev];
+    int nx = L->n[0], ny = L->n[1], dx = s % 5 - 2, dy = s / 5 - 2;
+    long p = (long)i + (long)nx * j;
+    if (i + dx < 0 || i + dx >= nx || j + dy < 0 || j + dy >= ny) return cx_make(0.0, 0.0);
+    if (L->gal) return L->gal[s * L->N + p];
+    const og_axis *X = &L->ax[0], *Y = &L->ax[1];
+    if (s == 12) return diag_at(L, 2, 1, i, j, 0, p);
+    if (s == 11) return cx_make(-X->aM[i].re, -X->aM[i].im);
+    if (s == 13) return cx_make(-X->cM[i].re, -X->cM[i].im);
+    if (s == 7) return cx_make(-Y->aM[j].re, -Y->aM[j].im);
+    if (s == 17) return cx_make(-Y->cM[j].re, -Y->cM[j].im);
+    return cx_make(0.0, 0.0);
+}
+
+/* The level's stencil offsets (the 5-point set or all 25) in ascending
+ * column order (column offset dx + nx*dy); returns their count. */
+static int level_offsets(const og_level *L, int *ord)
+{
+    int m = 0, nx = L->n[0];
+    for (int s = 0; s < 25; ++s)
+        if (L->gal || s == 7 || s == 11 || s == 12 || s == 13 || s == 17) ord[m++] = s;
+    for (int a = 1; a < m; ++a)   /* insertion sort by column offset */
+        for (int b = a; b > 0; --b) {
+            int s0 = ord[b - 1], s1 = ord[b];
+            long c0 = (s0 % 5 - 2) + (long)nx * (s0 / 5 - 2), c1 = (s1 % 5 - 2) + (long)nx * (s1 / 5 - 2);
+            if (c0 <= c1) break;
+            ord[b - 1] = s1; ord[b] = s0;
+        }
+    return m;
+}
+
+/* ILU(0) of M_l on its nonzero pattern (Saad's row-wise incomplete
+ * elimination), for the smoothing levels 0 .. nlev-2.  Fails on a zero
+ * pivot. */
+static int build_ilu(og_grid *g)
+{
+    for (int l = 0; l + 1 < g->nlev; ++l) {
+        og_level *L = &g->lev[l];
+        const long N = L->N;
+        const int nx = L->n[0], ny = L->n[1];
+        int ord[25];
+        const int m = level_offsets(L, ord);
+        cx *a = (cx *)calloc((size_t)(25 * N), sizeof(cx));
+        unsigned char *pat = (unsigned char *)calloc((size_t)(25 * N), 1);
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                long p = (long)i + (long)nx * j;
+                for (int k = 0; k < m; ++k) {
+                    int s = ord[k];
+                    cx v = level_entry(g, l, s, i, j);
+                    int dx = s % 5 - 2, dy = s / 5 - 2;
+                    int in = i + dx >= 0 && i + dx < nx && j + dy >= 0 && j + dy < ny;
+                    if (in && (s == 12 || v.re != 0.0 || v.im != 0.0)) { a[s * N + p] = v; pat[s * N + p] = 1; }
+                }
+            }
+        int bad = 0;
+        for (long p = 0; p < N && !bad; ++p) {
+            for (int k = 0; k < m; ++k) {
+                int s = ord[k];
+                long cs = (s % 5 - 2) + (long)nx * (s / 5 - 2);
+                if (cs >= 0) break;                       /* diagonal reached */
+                if (!pat[s * N + p]) continue;
+                long q = p + cs;
+                cx piv = a[12 * N + q];
+                if (piv.re == 0.0 && piv.im == 0.0) { bad = 1; break; }
+                cx lv = cx_div(a[s * N + p], piv);
+                a[s * N + p] = lv;
+                for (int kk = k + 1; kk < m; ++kk) {
+                    int t = ord[kk];
+                    if (!pat[t * N + p]) continue;
+                    int ux = (t % 5) - (s % 5), uy = (t / 5) - (s / 5);   /* offset of (q, c) from q */
+                    if (ux < -2 || ux > 2 || uy < -2 || uy > 2) continue;
+                    long cu = (long)ux + (long)nx * uy;
+                    if (cu <= 0) continue;                    /* only row q's upper part */
+                    int u = (ux + 2) + 5 * (uy + 2);
+                    if (!pat[u * N + q]) continue;
+                    a[t * N + p] = cx_sub(a[t * N + p], cx_mul(lv, a[u * N + q]));
+                }
+            }
+        }
+        free(pat);
+        if (bad) { free(a); return OG_ERR_ARG; }
+        L->ilu = a;
+    }
+    return OG_OK;
+}
+
+/* One ILU(0) sweep u <- u + omega (L U)^{-1} (f - M u) on level lev. */
+static void ilu_sweep(const og_grid *g, int lev, const cx *f, cx *u, cx *tmp)
+{
+    const og_level *L = &g->lev[lev];
+    const long N = L->N;
+    const int nx = L->n[0], ny = L->n[1];
+    const cx *F = L->ilu;
+    int ord[25];
+    const int m = level_offsets(L, ord);
+    apply_level(g, 1, lev, u, tmp);
+    for (long p = 0; p < N; ++p) tmp[p] = cx_sub(f[p], tmp[p]);
+    for (long p = 0; p < N; ++p) {
+        int i = (int)(p % nx), j = (int)(p / nx);
+        cx y = tmp[p];
+        for (int k = 0; k < m; ++k) {
+            int s = ord[k], dx = s % 5 - 2, dy = s / 5 - 2;
+            if (dx + (long)nx * dy >= 0) break;
+            if (i + dx < 0 || i + dx >= nx || j + dy < 0 || j + dy >= ny) continue;
+            y = cx_sub(y, cx_mul(F[s * N + p], tmp[p + dx + (long)nx * dy]));
+        }
+        tmp[p] = y;
+    }
+    for (long p = N - 1; p >= 0; --p) {
+        int i = (int)(p % nx), j = (int)(p / nx);
+        cx z = tmp[p];
+        for (int k = 0; k < m; ++k) {
+            int s = ord[k], dx = s % 5 - 2, dy = s / 5 - 2;
+            if (dx + (long)nx * dy <= 0) continue;
+            if (i + dx < 0 || i + dx >= nx || j + dy < 0 || j + dy >= ny) continue;
+            z = cx_sub(z, cx_mul(F[s * N + p], tmp[p + dx + (long)nx * dy]));
+        }
+        tmp[p] = cx_div(z, F[12 * N + p]);
+    }
+    for (long p = 0; p < N; ++p) u[p] = cx_add(u[p], cx_rscale(g->omega, tmp[p]));
+}
+
 /* csg_mode: 0 uniform CSG, 1 interior CSG, 2 CSL with shift (shift_re,
  * shift_im); contour_steps: ECS contour parts (<= 1 linear); bc: 6 ints, per
  * axis (low side, high side), 1 = Sommerfeld with wave number k_bc. */
@@ -621,12 +769,14 @@ og_grid *og_create(int dim, const int *n, const double *lo, const double *hi,
                    const double *a, const double *b, double theta_ecs, double theta_csg,
                    int csg_mode, int centering, int levels, int nu1, int nu2, double omega,
                    const double *phi, double shift_re, double shift_im, int contour_steps,
-                   const int *bc, double k_bc, int coarse_op)
+                   const int *bc, double k_bc, int coarse_op, int smoother)
 {
     if (dim < 1 || dim > 3) return NULL;
     if (coarse_op != 0 && (coarse_op != 1 || dim != 2 || centering != 0)) return NULL;
+    if (smoother != 0 && (smoother != 1 || dim != 2 || centering != 0 || nu1 != 0)) return NULL;
     og_grid *g = (og_grid *)calloc(1, sizeof(og_grid));
     g->dim = dim; g->centering = centering; g->csg_mode = csg_mode; g->coarse_op = coarse_op;
+    g->smoother = smoother;
     g->nu1 = nu1; g->nu2 = nu2; g->omega = omega;
     g->th_ecs = theta_ecs; g->th_csg = theta_csg;
     g->steps = contour_steps;
@@ -677,6 +827,7 @@ og_grid *og_create(int dim, const int *n, const double *lo, const double *hi,
         else coarsen_phi(&g->lev[l - 1], L, dim);
     }
     if (coarse_op == 1 && (nl < 2 || build_galerkin(g) != 0)) { og_free(g); return NULL; }
+    if (smoother == 1 && build_ilu(g) != 0) { og_free(g); return NULL; }
     if (build_coarse_inverse(g) != 0) { og_free(g); return NULL; }
     return g;
 }
@@ -692,6 +843,7 @@ void og_free(og_grid *g)
         }
         free(L->phi);
         free(L->gal);
+        free(L->ilu);
     }
     free(g->Minv);
     free(g);
@@ -730,6 +882,13 @@ int og_galerkin(const og_grid *g, int lev, double *out)
 {
     if (lev < 1 || lev >= g->nlev || !g->lev[lev].gal) return OG_ERR_ARG;
     memcpy(out, g->lev[lev].gal, sizeof(cx) * (size_t)(25 * g->lev[lev].N));
+    return OG_OK;
+}
+
+int og_ilu(const og_grid *g, int lev, double *out)
+{
+    if (lev < 0 || lev >= g->nlev || !g->lev[lev].ilu) return OG_ERR_ARG;
+    memcpy(out, g->lev[lev].ilu, sizeof(cx) * (size_t)(25 * g->lev[lev].N));
     return OG_OK;
 }
 
@@ -904,7 +1063,10 @@ static void vcycle_level(const og_grid *g, int lev, const cx *f, cx *u)
     vcycle_level(g, lev + 1, fc, ec);
     prolong_level(g, lev, ec, tmp);
     for (long p = 0; p < N; ++p) u[p] = cx_add(u[p], tmp[p]);
-    for (int s = 0; s < g->nu2; ++s) jacobi(g, lev, f, u, tmp);
+    for (int s = 0; s < g->nu2; ++s) {
+        if (g->smoother == 1) ilu_sweep(g, lev, f, u, tmp);
+        else jacobi(g, lev, f, u, tmp);
+    }
     free(tmp); free(fc); free(ec);
 }
 
@@ -922,6 +1084,15 @@ void og_jacobi(const og_grid *g, int lev, const double *f, double *u)
 }
 
 void og_coarse_solve(const og_grid *g, const double *f, double *e) { coarse_solve(g, (const cx *)f, (cx *)e); }
+
+int og_ilu_sweep(const og_grid *g, int lev, const double *f, double *u)
+{
+    if (lev < 0 || lev >= g->nlev || !g->lev[lev].ilu) return OG_ERR_ARG;
+    cx *tmp = (cx *)malloc(sizeof(cx) * (size_t)g->lev[lev].N);
+    ilu_sweep(g, lev, (const cx *)f, (cx *)u, tmp);
+    free(tmp);
+    return OG_OK;
+}
 
 void og_dotc(const double *x, const double *y, long n, double *out)
 {

@@ -54,7 +54,7 @@ def lib():
         L = ctypes.CDLL(LIB)
         P, D, I = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
         L.og_create.restype = P
-        L.og_create.argtypes = [I, P, P, P, P, P, D, D, I, I, I, I, I, D, P, D, D, I, P, D, I]
+        L.og_create.argtypes = [I, P, P, P, P, P, D, D, I, I, I, I, I, D, P, D, D, I, P, D, I, I]
         L.og_free.argtypes = [P]
         L.og_levels.argtypes = [P]
         L.og_level_dims.argtypes = [P, I, P]
@@ -64,6 +64,8 @@ def lib():
         L.og_phi.argtypes = [P, I, P]
         L.og_coarse_inverse.argtypes = [P, P]
         L.og_galerkin.argtypes = [P, I, P]
+        L.og_ilu.argtypes = [P, I, P]
+        L.og_ilu_sweep.argtypes = [P, I, P, P]
         L.og_apply.argtypes = [P, I, I, P, P]
         L.og_vcycle.argtypes = [P, P, P]
         L.og_restrict.argtypes = [P, I, P, P]
@@ -102,7 +104,8 @@ class Grid:
     csl_shift ([re, im] of beta^2 for the CSL), contour_steps (ECS contour
     parts, 0/1 linear), bc ([[lo, hi]] per axis, 1 = Sommerfeld), k_bc (its
     wave number), coarse_op (0 rediscretised coarse operators, 1 Galerkin,
-    2D only); phi is the real array k(x)^2 on the finest grid (shape
+    2D only), smoother (0 weighted Jacobi, 1 ILU(0): 2D, cell-centred,
+    nu1 = 0, omega its relaxation factor); phi is the real array k(x)^2 on the finest grid (shape
     prod(n)), or phi_const."""
 
     def __init__(self, desc, phi=None):
@@ -130,7 +133,7 @@ class Grid:
                              int(d.get("csg_mode", 0)), int(d.get("centering", 0)), int(d.get("levels", 0)),
                              int(d.get("nu1", 1)), int(d.get("nu2", 1)), float(d.get("omega", 0.8)), _ptr(phi),
                              float(shift[0]), float(shift[1]), int(d.get("contour_steps", 0)), _ptr(bc),
-                             float(d.get("k_bc", 0.0)), int(d.get("coarse_op", 0)))
+                             float(d.get("k_bc", 0.0)), int(d.get("coarse_op", 0)), int(d.get("smoother", 0)))
         if not self.h:
             raise ValueError("oracle rejected the grid description")
         self.dim = dim
@@ -165,6 +168,26 @@ class Grid:
         out = np.zeros(self.level_size(lev))
         lib().og_phi(self.h, lev, _ptr(out))
         return out
+
+    def ilu(self, lev):
+        """ILU(0) factors of level lev (a smoothing level) as (25, N), in the
+        Galerkin stencil layout: rows s < 12 (columns below the diagonal) hold
+        L (unit diagonal not stored), s >= 12 hold U; zero off the pattern."""
+        N = self.level_size(lev)
+        out = np.zeros(25 * N, dtype=np.complex128)
+        rc = lib().og_ilu(self.h, lev, _ptr(out))
+        if rc != 0:
+            raise ValueError("level %d has no ILU(0) factors" % lev)
+        return out.reshape(25, N)
+
+    def ilu_sweep(self, lev, f, u):
+        """One ILU(0) smoothing sweep on level lev: returns u + omega (LU)^-1 (f - M u)."""
+        f = _c128(f)
+        u = _c128(u).copy()
+        rc = lib().og_ilu_sweep(self.h, lev, _ptr(f), _ptr(u))
+        if rc != 0:
+            raise ValueError("level %d has no ILU(0) factors" % lev)
+        return u
 
     def galerkin(self, lev):
         """Galerkin stencil of level lev >= 1 as (25, N): row s = (dx+2) + 5(dy+2)

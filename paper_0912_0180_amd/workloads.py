@@ -28,17 +28,18 @@ def rng(seed):
 
 def base_desc(dim, n, lo, hi, a, b, theta_ecs=PI / 6, theta_csg=PI / 8, csg_mode=0, levels=0,
               nu1=1, nu2=1, omega=0.8, centering=0, csl_shift=(0.0, 0.0), contour_steps=0, bc=None, k_bc=0.0,
-              coarse_op=0):
+              coarse_op=0, smoother=0):
     """Grid description (the keys of the library's hh_grid_desc).  bc: per axis
     [low side, high side], 0 Dirichlet / contour end, 1 Sommerfeld (wave number
     k_bc); csg_mode 2 is the CSL preconditioner with the shift csl_shift;
-    coarse_op 1 takes Galerkin coarse operators (2D)."""
+    coarse_op 1 takes Galerkin coarse operators (2D); smoother 1 takes ILU(0)
+    smoothing (2D, V(0,1), omega its relaxation factor)."""
     return {"dim": dim, "n": list(n), "lo": list(lo), "hi": list(hi), "a": list(a), "b": list(b),
             "theta_ecs": float(theta_ecs), "theta_csg": float(theta_csg), "csg_mode": int(csg_mode),
             "centering": int(centering), "levels": int(levels), "nu1": int(nu1), "nu2": int(nu2),
             "omega": float(omega), "csl_shift": [float(csl_shift[0]), float(csl_shift[1])],
             "contour_steps": int(contour_steps), "bc": [list(v) for v in (bc or [[0, 0]] * dim)],
-            "k_bc": float(k_bc), "coarse_op": int(coarse_op)}
+            "k_bc": float(k_bc), "coarse_op": int(coarse_op), "smoother": int(smoother)}
 
 
 def cell_centres(n, lo, hi):

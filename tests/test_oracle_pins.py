@@ -889,3 +889,105 @@ def test_galerkin_rejected_outside_its_scope(oracle_mod, kw):
                     centering=kw.get("centering", 0), coarse_op=1)
     with pytest.raises(ValueError):
         oracle_mod.Grid(d, np.zeros(16 ** dim))
+
+
+def ilu_dense(F, n):
+    """Dense unit-lower L and upper U from ILU(0) factors in the (25, N)
+    stencil layout (entries reaching outside the grid must be zero)."""
+    nx, ny = n
+    N = nx * ny
+    L = np.eye(N, dtype=complex)
+    U = np.zeros((N, N), dtype=complex)
+    for s in range(25):
+        dx, dy = s % 5 - 2, s // 5 - 2
+        for j in range(ny):
+            for i in range(nx):
+                p = i + nx * j
+                if 0 <= i + dx < nx and 0 <= j + dy < ny:
+                    c = p + dx + nx * dy
+                    if c < p:
+                        L[p, c] = F[s, p]
+                    else:
+                        U[p, c] = F[s, p]
+                else:
+                    assert F[s, p] == 0, (s, i, j)
+    return L, U
+
+
+def ilu_grid(oracle_mod, coarse_op, levels=3, omega=1.0, seed=67):
+    n0 = (16, 12)
+    rng = np.random.default_rng(seed)
+    phi0 = 150.0 + 60.0 * rng.uniform(size=n0[0] * n0[1])
+    d = W.base_desc(2, n0, (-0.25, -0.25), (1.25, 1.25), (0.0, 0.0), (1.0, 1.0), levels=levels, nu1=0,
+                    omega=omega, coarse_op=coarse_op, smoother=1)
+    return oracle_mod.Grid(d, phi0), rng
+
+
+@pytest.mark.parametrize("coarse_op", [0, 1])
+def test_ilu0_factors_match_the_operator_on_its_pattern(oracle_mod, coarse_op):
+    """ILU(0), the paper's smoother (Sec. 6.1), is defined by L U = M on the
+    nonzero pattern of M, with L unit lower and U upper triangular, both zero
+    off that pattern (Saad, Iterative Methods for Sparse Linear Systems, Sec.
+    10.3.2): as many equations as unknowns, solved row by row, so the property
+    fixes the factors.  Checked with dense products on both smoothing levels of
+    a 3-level hierarchy, rediscretised (5-point) and Galerkin (25-point), the
+    pattern and M taken from the oracle's operator apply column by column.
+    The dropped fill is not zero (else ILU(0) would be the exact LU and the
+    check would not tell them apart)."""
+    g, _ = ilu_grid(oracle_mod, coarse_op)
+    for lev in (0, 1):
+        n = g.level_dims(lev)[:2]
+        M = g.matrix("M", lev)
+        L, U = ilu_dense(g.ilu(lev), n)
+        pat = (M != 0) | np.eye(M.shape[0], dtype=bool)
+        scale = np.abs(M).max()
+        LU = L @ U
+        assert np.abs((LU - M)[pat]).max() <= 1e-12 * scale, lev
+        off = ~pat
+        assert np.all(L[off] == 0) and np.all(U[off] == 0), lev
+        assert np.abs((LU - M)[off]).max() > 1e-6 * scale, lev        # the dropped fill
+        assert np.all(np.abs(np.diag(U)) > 0), lev
+
+
+@pytest.mark.parametrize("coarse_op", [0, 1])
+def test_ilu0_sweep_and_vcycle_match_dense_formulas(oracle_mod, coarse_op):
+    """One ILU(0) sweep is u + omega K^{-1} (f - M u) with K = L U (dense solve
+    here), and the V(0,1) cycle with ILU(0) post-smoothing is the recursion
+    B_l = (I - omega K_l^{-1} M_l) P B_{l+1} R + omega K_l^{-1}, B_coarsest =
+    M^{-1}, with M_l the level operators of the oracle (Galerkin or
+    rediscretised) and the transfers R = kron of (1,3,3,1)/8, P = 4 R^T."""
+    omega = 0.9
+    g, rng = ilu_grid(oracle_mod, coarse_op, omega=omega)
+    ns = [tuple(g.level_dims(l)[:2]) for l in range(3)]
+    Ms = [g.matrix("M", l) for l in range(3)]
+    Ks = [np.matmul(*ilu_dense(g.ilu(l), ns[l])) for l in range(2)]
+    for lev in (0, 1):
+        N = Ms[lev].shape[0]
+        f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        u = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        want = u + omega * np.linalg.solve(Ks[lev], f - Ms[lev] @ u)
+        got = g.ilu_sweep(lev, f, u)
+        assert np.linalg.norm(got - want) < 1e-11 * np.linalg.norm(want), lev
+    B = np.linalg.inv(Ms[2])
+    for lev in (1, 0):
+        R = kron_x_fastest([fw_1d(ns[lev][0]), fw_1d(ns[lev][1])])
+        P = 4.0 * R.T
+        Ki = np.linalg.inv(Ks[lev])
+        I = np.eye(Ms[lev].shape[0])
+        B = (I - omega * Ki @ Ms[lev]) @ P @ B @ R + omega * Ki
+    f = rng.standard_normal(g.N) + 1j * rng.standard_normal(g.N)
+    want = B @ f
+    assert np.linalg.norm(g.vcycle(f) - want) < 1e-10 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("kw", [dict(dim=3), dict(centering=1), dict(nu1=1)])
+def test_ilu0_rejected_outside_its_scope(oracle_mod, kw):
+    """The ILU(0) smoother is defined here for 2D cell-centred hierarchies
+    with the paper's V(0,1) cycle."""
+    dim = kw.get("dim", 2)
+    n = (16,) * dim
+    d = W.base_desc(dim, n, (0.0,) * dim, (1.0,) * dim, (0.0,) * dim, (1.0,) * dim,
+                    levels=2 if kw.get("centering", 0) == 0 else 1, nu1=kw.get("nu1", 0),
+                    centering=kw.get("centering", 0), smoother=1)
+    with pytest.raises(ValueError):
+        oracle_mod.Grid(d, np.zeros(16 ** dim))
