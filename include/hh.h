@@ -91,6 +91,18 @@ typedef enum { HH_CELL = 0, HH_VERTEX = 1 } hh_centering;
  * cell-centred; a 25-point stencil per coarse point, since the cell-centred
  * transfers reach two coarse cells). */
 typedef enum { HH_COARSE_REDISCRETISED = 0, HH_COARSE_GALERKIN = 1 } hh_coarse_op;
+/* Smoother of the V-cycle: weighted Jacobi (omega its weight), or ILU(0), the
+ * paper's choice (Sec. 6.1): one sweep u = u + omega (L U)^-1 (f - M u) per
+ * level with the incomplete LU factors of the level operator on its nonzero
+ * pattern, lexicographic order (omega its relaxation, 1 for the plain
+ * sweep).  HH_SMOOTH_ILU0 needs a 2D cell-centred grid, the V(0,1) cycle
+ * (nu1 = 0), at least 5 cells per side on every level but the coarsest, and
+ * the FP64 V-cycle (HH_C128); it runs single solves and V-cycle calls
+ * (batches of more than one problem, hh_submit and hh_profile_vcycle reject
+ * it).  Its triangular solves are sequential along anti-diagonals, so a
+ * cycle costs about (n_x + n_y) dependent steps per level (rediscretised)
+ * or (n_x + 3 n_y) (Galerkin). */
+typedef enum { HH_SMOOTH_JACOBI = 0, HH_SMOOTH_ILU0 = 1 } hh_smoother;
 
 /* Grid description (host memory, read during hh_setup_grid only). */
 typedef struct {
@@ -132,6 +144,7 @@ typedef struct {
     int32_t coarse_op;      /* hh_coarse_op.  HH_COARSE_GALERKIN: 2D cell-centred grids;
                                single solves and every V-cycle call (batched solves with
                                more than one problem, and hh_submit, reject it)          */
+    int32_t smoother;       /* hh_smoother (zero: weighted Jacobi)                       */
 } hh_grid_desc;
 
 typedef struct hh_grid hh_grid;   /* opaque */
@@ -165,7 +178,11 @@ hh_status hh_grid_query(const hh_grid *g, hh_grid_info *info);
  * 6 phi of `level` (N_level doubles); 7 the coarsest inverse (Nc*Nc complex
  * double, row major); 8 the Galerkin stencil of `level` >= 1 (25 * N_level
  * complex double, entry s = (dx+2) + 5(dy+2) of point p at s*N + p, the
- * matrix entry M[p, p + dx + nx*dy]).  `bytes` must equal the array size. */
+ * matrix entry M[p, p + dx + nx*dy]); 9 the ILU(0) factors of a smoothing
+ * `level` of an HH_SMOOTH_ILU0 grid (25 * N_level complex double in the same
+ * layout: entries below the diagonal hold L, whose unit diagonal is not
+ * stored, the diagonal and above hold U, zero off the pattern).  `bytes` must
+ * equal the array size. */
 hh_status hh_grid_export(const hh_grid *g, int32_t what, int32_t level, int32_t axis, void *host_dst,
                          size_t bytes);
 

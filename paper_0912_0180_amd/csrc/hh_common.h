@@ -213,6 +213,8 @@ template <typename T> struct LevelDev {
     V2<T> *f;                        // restricted right-hand side (levels >= 1)
     V2<T> *e;                        // level solution / correction (levels >= 1)
     const V2<T> *g;                  // Galerkin levels >= 1: the 25 x N stencil, else null
+    const V2<T> *ilu;                // ILU(0) smoothing levels (FP64): the 25 x N factors, else null
+    V2<T> *w;                        // ILU(0) smoothing levels (FP64): N values of work space
 };
 
 // LDS layout of the tail kernel (levels t0 .. L-1 of one problem in one

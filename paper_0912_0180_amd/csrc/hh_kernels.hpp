@@ -1785,6 +1785,136 @@ __global__ __launch_bounds__(GAL_NT) void k_gup(Ctx cx, GalArgs<T> ga)
 }
 
 // ---------------------------------------------------------------------------
+// ILU(0) up-leg (2D, FP64): the paper's smoother (Sec. 6.1) in its V(0,1)
+// cycle.  Level l's up-leg is u = P e_{l+1} (no pre-smoothing: the down-legs
+// only restrict), then one sweep u = u + omega (L U)^-1 (f - M u) with the
+// level's ILU(0) factors (lexicographic order, set up on the host).  The
+// triangular solves are the exact lexicographic ones: point (i, j) depends
+// on its stencil neighbours below (resp. above) the diagonal only, so the
+// anti-diagonals d = i + m j (m = 1 for the 5-point set, whose lower
+// neighbours are (i-1, j) and (i, j-1); m = 3 for the 25-point set, whose
+// lower neighbours reach (i+2, j-1) and (i-2, j)) are sets of independent
+// points, taken in order with a barrier between them.  That is n_x + m n_y
+// dependent steps per solve, so one workgroup runs the level and the leg is
+// latency-bound by construction; every per-point operation is the oracle's,
+// in its order.  Every side of a smoothing level has at least 5 cells (the
+// 25-point offsets are then in column order).
+// ---------------------------------------------------------------------------
+#define HH_ILU_WG 1024
+struct IluArgs {
+    LevelDev<double> fl, cl;          // level l and the coarser level l + 1
+    const double2 *f;                 // right-hand side of level l (the cycle's input on level 0)
+    double2 *u;                       // result of level l (e_l, or the cycle's output on level 0)
+    double omega;                     // relaxation of the ILU(0) update
+};
+
+// entry s (offset (s % 5 - 2, s / 5 - 2)) of row p of M_l applied to u, with
+// the neighbour outside the grid taken as zero: the Galerkin stencil, or the
+// 5-point set of the rediscretised stencil; y = M u in the contract's order
+__device__ __forceinline__ double2 ilu_Mu(const LevelDev<double> &L, const double2 *u, int i, int j, int64_t p)
+{
+    const int nx = L.n[0], ny = L.n[1];
+    const double2 zero = cmk<double>(0.0, 0.0);
+    if (L.g) {
+        const int64_t N = L.N;
+        double2 t = cmul<double>(ldg(L.g, 12 * N + p), ldg(u, p));
+        for (int s = 0; s < 25; ++s) {
+            if (s == 12) continue;
+            const int ii = i + s % 5 - 2, jj = j + s / 5 - 2;
+            const double2 uq = (ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? ldg(u, ii + (int64_t)nx * jj) : zero;
+            t = cadd<double>(t, cmul<double>(ldg(L.g, s * N + p), uq));
+        }
+        return t;
+    }
+    double2 d = cadd<double>(ldg(L.d[0], i), ldg(L.d[1], j));
+    const double2 D = cmk<double>(d.x - ldg(L.phi, p), d.y);
+    double2 t = cmul<double>(D, ldg(u, p));
+    t = csub<double>(t, cmul<double>(ldg(L.a[0], i), i > 0 ? ldg(u, p - 1) : zero));
+    t = csub<double>(t, cmul<double>(ldg(L.c[0], i), i < nx - 1 ? ldg(u, p + 1) : zero));
+    t = csub<double>(t, cmul<double>(ldg(L.a[1], j), j > 0 ? ldg(u, p - nx) : zero));
+    t = csub<double>(t, cmul<double>(ldg(L.c[1], j), j < ny - 1 ? ldg(u, p + nx) : zero));
+    return t;
+}
+
+__global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
+{
+    if (phase_of(cx, 0) != PH_RUN) return;
+    const LevelDev<double> L = a.fl;
+    const int nx = L.n[0], ny = L.n[1], ncx = a.cl.n[0], ncy = a.cl.n[1];
+    const int64_t N = L.N;
+    const double2 *__restrict__ F = L.ilu;
+    const double2 *__restrict__ ec = a.cl.e;
+    double2 *w = L.w;
+    double2 *u = a.u;
+    const double2 zero = cmk<double>(0.0, 0.0);
+    const bool gal = L.g != nullptr;
+    const int tid = threadIdx.x;
+    // u = 0 + P e_{l+1} (bilinear, x then y; coarse values outside are zero)
+    for (int64_t p = tid; p < N; p += HH_ILU_WG) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        const int Ix = i >> 1, Iox = (i & 1) ? Ix + 1 : Ix - 1;
+        const int Iy = j >> 1, Ioy = (j & 1) ? Iy + 1 : Iy - 1;
+        auto ev = [&](int x, int y) -> double2 {
+            return (x >= 0 && x < ncx && y >= 0 && y < ncy) ? ldg(ec, x + (int64_t)ncx * y) : zero;
+        };
+        const double2 a0 = crs2<double>(0.75, ev(Ix, Iy), 0.25, ev(Iox, Iy));
+        const double2 a1 = crs2<double>(0.75, ev(Ix, Ioy), 0.25, ev(Iox, Ioy));
+        stg(u, p, cadd<double>(zero, crs2<double>(0.75, a0, 0.25, a1)));
+    }
+    __syncthreads();
+    // r = f - M u
+    for (int64_t p = tid; p < N; p += HH_ILU_WG) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        stg(w, p, csub<double>(ldg(a.f, p), ilu_Mu(L, u, i, j, p)));
+    }
+    __syncthreads();
+    const int m = gal ? 3 : 1;
+    const int nd = (nx - 1) + m * (ny - 1) + 1;
+    // forward: y = r - sum of l_s y_q over the neighbours below, columns ascending
+    for (int d = 0; d < nd; ++d) {
+        const int jlo = d - (nx - 1) > 0 ? (d - (nx - 1) + m - 1) / m : 0, jhi = min(ny - 1, d / m);
+        for (int j = jlo + tid; j <= jhi; j += HH_ILU_WG) {
+            const int i = d - m * j;
+            const int64_t p = i + (int64_t)nx * j;
+            double2 y = ldg(w, p);
+            if (gal) {
+                for (int s = 0; s < 12; ++s) {
+                    const int ii = i + s % 5 - 2, jj = j + s / 5 - 2;
+                    if (ii >= 0 && ii < nx && jj >= 0) y = csub<double>(y, cmul<double>(ldg(F, s * N + p), ldg(w, ii + (int64_t)nx * jj)));
+                }
+            } else {
+                if (j > 0) y = csub<double>(y, cmul<double>(ldg(F, 7 * N + p), ldg(w, p - nx)));
+                if (i > 0) y = csub<double>(y, cmul<double>(ldg(F, 11 * N + p), ldg(w, p - 1)));
+            }
+            stg(w, p, y);
+        }
+        __syncthreads();
+    }
+    // backward: z = (y - sum of u_s z_c over the neighbours above, columns ascending) / u_12
+    for (int d = nd - 1; d >= 0; --d) {
+        const int jlo = d - (nx - 1) > 0 ? (d - (nx - 1) + m - 1) / m : 0, jhi = min(ny - 1, d / m);
+        for (int j = jlo + tid; j <= jhi; j += HH_ILU_WG) {
+            const int i = d - m * j;
+            const int64_t p = i + (int64_t)nx * j;
+            double2 z = ldg(w, p);
+            if (gal) {
+                for (int s = 13; s < 25; ++s) {
+                    const int ii = i + s % 5 - 2, jj = j + s / 5 - 2;
+                    if (ii >= 0 && ii < nx && jj < ny) z = csub<double>(z, cmul<double>(ldg(F, s * N + p), ldg(w, ii + (int64_t)nx * jj)));
+                }
+            } else {
+                if (i < nx - 1) z = csub<double>(z, cmul<double>(ldg(F, 13 * N + p), ldg(w, p + 1)));
+                if (j < ny - 1) z = csub<double>(z, cmul<double>(ldg(F, 17 * N + p), ldg(w, p + nx)));
+            }
+            stg(w, p, cdiv<double>(z, ldg(F, 12 * N + p)));
+        }
+        __syncthreads();
+    }
+    // u = u + omega z
+    for (int64_t p = tid; p < N; p += HH_ILU_WG) stg(u, p, crsadd<double>(ldg(u, p), a.omega, ldg(w, p)));
+}
+
+// ---------------------------------------------------------------------------
 // Merged 2D legs of K consecutive coarse levels lev0 .. lev0 + K - 1 (ending
 // at the tail's first level lev0 + K), one launch per leg instead of K.  On
 // these small levels a launch costs its latency, not its work.

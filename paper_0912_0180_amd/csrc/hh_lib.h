@@ -40,6 +40,7 @@ struct Plan {
     double omega1 = 0.8;
     int nu1_1 = 1;                   // one-problem plans: pre-smoothing steps
     bool galerkin = false;           // one-problem plans: Galerkin coarse operators (levels >= 1)
+    bool ilu = false;                // one-problem plans: ILU(0) up-legs (FP64, V(0,1))
     std::vector<ProbDev> host;       // host copies of the descriptors of the current solve
     void *mem = nullptr;
     size_t bytes = 0;

@@ -162,6 +162,15 @@ hh_status grid_upload(hh_grid *g)
                 D.g = nullptr;
                 F.g = nullptr;
             }
+            F.ilu = nullptr;
+            F.w = nullptr;
+            if (!L.ilu.empty()) {
+                D.ilu = c.take<double2>(L.ilu.size());
+                D.w = c.take<double2>(L.N);
+            } else {
+                D.ilu = nullptr;
+                D.w = nullptr;
+            }
         }
         g->Minv64 = c.take<double2>((size_t)hs.Nc * hs.Nc);
         g->Minv32 = c.take<float2>((size_t)hs.Nc * hs.Nc);
@@ -211,6 +220,7 @@ hh_status grid_upload(hh_grid *g)
             HIPCHK(put64(g->L64h[l].g, L.gal.data(), sizeof(double2) * L.gal.size()));
             HIPCHK(put32c(g->L32h[l].g, L.gal));
         }
+        if (!L.ilu.empty()) HIPCHK(put64(g->L64h[l].ilu, L.ilu.data(), sizeof(double2) * L.ilu.size()));
         std::vector<float> p32(L.N);
         for (int64_t i = 0; i < L.N; ++i) p32[i] = (float)L.phi[i];
         HIPCHK(put64(g->L32h[l].phi, p32.data(), sizeof(float) * L.N));
@@ -333,7 +343,9 @@ static void plan_merge(Plan &pl, const hh_grid *const *G, int count, bool fp32)
     pl.mK = pl.mlev0 = pl.mdn = pl.mKup = pl.mlev0u = pl.mup = 0;
     if (const char *e = getenv("HH_MERGE"))
         if (atoi(e) == 0) return;
-    if (count != 1 || G[0]->hs.dim != 2 || G[0]->host_only || G[0]->hs.coarse_op == HH_COARSE_GALERKIN) return;
+    if (count != 1 || G[0]->hs.dim != 2 || G[0]->host_only || G[0]->hs.coarse_op == HH_COARSE_GALERKIN ||
+        G[0]->hs.smoother == HH_SMOOTH_ILU0)
+        return;
     const HostSetup &hs = G[0]->hs;
     const int t = tail_level(hs, fp32), K = std::min(3, t - 1), Kup = std::min(4, t - 1);
     if (K < 2) return;
@@ -407,15 +419,19 @@ static size_t tail_bytes(const HostSetup &hs, int t, bool fp32)
     return off;
 }
 
-bool coarse_split(const HostSetup &hs) { return hs.Nc > HH_SPLIT_NC || hs.coarse_op == HH_COARSE_GALERKIN; }
+bool coarse_split(const HostSetup &hs)
+{
+    return hs.Nc > HH_SPLIT_NC || hs.coarse_op == HH_COARSE_GALERKIN || hs.smoother == HH_SMOOTH_ILU0;
+}
 
 // First level of the one-workgroup tail: the finest level >= 1 whose level
-// and every coarser one fit the tail's LDS budget.  A Galerkin hierarchy has
-// no tail levels (the tail kernel knows only the rediscretised stencil): only
-// its coarsest level, which k_coarse solves.
+// and every coarser one fit the tail's LDS budget.  A Galerkin or ILU(0)
+// hierarchy has no tail levels (the tail kernel knows only the rediscretised
+// stencil and weighted Jacobi): only its coarsest level, which k_coarse
+// solves.
 int tail_level(const HostSetup &hs, bool fp32)
 {
-    if (hs.coarse_op == HH_COARSE_GALERKIN) return hs.nlev - 1;
+    if (hs.coarse_op == HH_COARSE_GALERKIN || hs.smoother == HH_SMOOTH_ILU0) return hs.nlev - 1;
     const int cap = fp32 ? TailCap<float>::N : TailCap<double>::N;
     const size_t bytes = fp32 ? TailCap<float>::BYTES : TailCap<double>::BYTES;
     for (int t = 1; t < hs.nlev; ++t)
@@ -543,9 +559,16 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
         pl.hcap = (int)G.size();
     }
     if (G.size() > 1)
-        for (const hh_grid *g : G)
+        for (const hh_grid *g : G) {
             if (g->hs.coarse_op == HH_COARSE_GALERKIN)
                 return hh_fail(HH_ERR_ARG, "Galerkin coarse operators are supported for single solves, not batches");
+            if (g->hs.smoother == HH_SMOOTH_ILU0)
+                return hh_fail(HH_ERR_ARG, "ILU(0) smoothing is supported for single solves, not batches");
+        }
+    if (fp32)
+        for (const hh_grid *g : G)
+            if (g->hs.smoother == HH_SMOOTH_ILU0)
+                return hh_fail(HH_ERR_ARG, "ILU(0) smoothing runs in the FP64 V-cycle only (vcycle_prec HH_C128)");
     pl.count = (int)G.size();
     pl.dim = G.empty() ? 2 : G[0]->hs.dim;
     pl.fp32 = fp32;
@@ -617,6 +640,7 @@ hh_status plan_build(Plan &pl, const std::vector<const hh_grid *> &G, bool fp32)
     pl.ctrl = c.take<Ctrl>(pl.count);
     if (pl.count == 1) {
         pl.galerkin = G[0]->hs.coarse_op == HH_COARSE_GALERKIN;
+        pl.ilu = G[0]->hs.smoother == HH_SMOOTH_ILU0;
         pl.pd1 = G[0]->pd_static;
         pl.L1 = fp32 ? (const void *)G[0]->L32 : (const void *)G[0]->L64;
         pl.omega1 = G[0]->hs.omega;
@@ -955,6 +979,7 @@ static void plan_host_one(Plan &pl, const hh_grid *g, bool fp32, const void *L1,
     pl.ctrl = nullptr;
     pl.pd1 = g->pd_static;
     pl.galerkin = hs.coarse_op == HH_COARSE_GALERKIN;
+    pl.ilu = hs.smoother == HH_SMOOTH_ILU0;
     pl.L1 = L1;
     pl.omega1 = hs.omega;
     pl.nu1_1 = hs.nu1;
@@ -1084,6 +1109,22 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
         }
     }
     if (pl.mK) launch_merged<T>(1, pl, s, lh);
+    if constexpr (DIM == 2 && std::is_same<T, double>::value) {
+        if (pl.ilu) {
+            // ILU(0) up-legs (one problem): one workgroup per level
+            const Ctx c = ctx_of(pl, pl.chunks);
+            for (int l = pl.Lmax - 1; l >= 0; --l) {
+                IluArgs a;
+                a.fl = lh.d[l];
+                a.cl = lh.d[l + 1];
+                a.f = l == 0 ? (const double2 *)fptr : lh.d[l].f;
+                a.u = l == 0 ? (double2 *)optr : lh.d[l].e;
+                a.omega = pl.omega1;
+                hipLaunchKernelGGL(k_ilu_up, dim3(1), dim3(HH_ILU_WG), 0, s, c, a);
+            }
+            return;
+        }
+    }
     for (int l = (pl.mK ? pl.mlev0u : pl.Lmax) - 1; l >= 0; --l) {
         if (pl.galerkin && l >= 1) launch_gal_leg<T>(1, pl, l, s, lh);
         else launch_leg<DIM, T>(1, pl.vuv[l], pl.up[l].n, s, ctx_of(pl, pl.up[l]), l, fsel, osel, fptr, optr, lh);
@@ -1239,6 +1280,8 @@ hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_
         if (l >= 1) g += 2 * align256(sizeof(double2) * L[l].N) + 2 * align256(sizeof(float2) * L[l].N);
         if (l >= 1 && d->coarse_op == HH_COARSE_GALERKIN)
             g += align256(sizeof(double2) * 25 * L[l].N) + align256(sizeof(float2) * 25 * L[l].N);
+        if (l + 1 < nl && d->smoother == HH_SMOOTH_ILU0)
+            g += align256(sizeof(double2) * 25 * L[l].N) + align256(sizeof(double2) * L[l].N);
     }
     g += align256(sizeof(double2) * (size_t)nc * nc) + align256(sizeof(float2) * (size_t)nc * nc);
     g += align256(TailCap<double>::BYTES) + align256(TailCap<float>::BYTES);
@@ -1249,7 +1292,7 @@ hh_status footprint_bytes(const hh_grid_desc *d, const hh_solve_opts *o, uint64_
     // space), so the FP64 work space is reserved either way
     size_t ws = solve_workspace_bytes(N, o->method, false, s, 0);
     size_t io = 2 * align256(sizeof(double2) * N) + (s > 0 ? align256(sizeof(double2) * (size_t)N * s) : 0);
-    const bool split = nc > HH_SPLIT_NC || d->coarse_op == HH_COARSE_GALERKIN;
+    const bool split = nc > HH_SPLIT_NC || d->coarse_op == HH_COARSE_GALERKIN || d->smoother == HH_SMOOTH_ILU0;
     size_t tiles = ngr + (split ? ceil_div(coarse_waves<double>(nc), HH_WG / 64) : 0);
     for (int l = 0; l + 1 < nl; ++l) {
         int md = 0, mu = 0;
@@ -1332,6 +1375,10 @@ hh_status hh_grid_export(const hh_grid *g, int32_t what, int32_t level, int32_t 
         if (hs.lev[level].gal.empty()) return hh_fail(HH_ERR_ARG, "level %d has no Galerkin stencil", level);
         src = hs.lev[level].gal.data();
         need = sizeof(double2) * hs.lev[level].gal.size();
+    } else if (what == 9) {
+        if (hs.lev[level].ilu.empty()) return hh_fail(HH_ERR_ARG, "level %d has no ILU(0) factors", level);
+        src = hs.lev[level].ilu.data();
+        need = sizeof(double2) * hs.lev[level].ilu.size();
     } else {
         return hh_fail(HH_ERR_ARG, "unknown export %d", what);
     }
@@ -1384,6 +1431,8 @@ hh_status hh_vcycle(const hh_grid *g, hh_prec prec, const void *f, void *u, void
     if (f == u) return hh_fail(HH_ERR_ARG, "f and u must not overlap");
     if (prec != HH_C128 && prec != HH_C64) return hh_fail(HH_ERR_ARG, "unknown precision %d", (int)prec);
     if (g->hs.centering != HH_CELL) return hh_fail(HH_ERR_ARG, "a vertex-centred grid has no multigrid hierarchy");
+    if (g->hs.smoother == HH_SMOOTH_ILU0 && prec == HH_C64)
+        return hh_fail(HH_ERR_ARG, "ILU(0) smoothing runs in the FP64 V-cycle only (HH_C128)");
     hh_grid *gm = const_cast<hh_grid *>(g);
     hh_status st = grid_vplan(gm, prec == HH_C64);
     if (st != HH_OK) return st;
@@ -1404,6 +1453,8 @@ hh_status hh_vcycle_noalloc(const hh_grid *g, hh_prec prec, const void *f, void 
     if (prec != HH_C128 && prec != HH_C64) return hh_fail(HH_ERR_ARG, "unknown precision %d", (int)prec);
     if (g->hs.centering != HH_CELL) return hh_fail(HH_ERR_ARG, "a vertex-centred grid has no multigrid hierarchy");
     if (!g->scratch_ok) return hh_fail(HH_ERR_HIP, "the scratch array of device %d was not found at grid setup", g->device);
+    if (g->hs.smoother == HH_SMOOTH_ILU0 && prec == HH_C64)
+        return hh_fail(HH_ERR_ARG, "ILU(0) smoothing runs in the FP64 V-cycle only (HH_C128)");
     const bool fp32 = prec == HH_C64;
     const size_t need = fp32 ? g->scratch_need32 : g->scratch_need64;
     if (need > HH_SCRATCH_BYTES)
@@ -1434,6 +1485,8 @@ hh_status hh_profile_vcycle(const hh_grid *g, hh_prec prec, const void *f, void 
     if (prec != HH_C128 && prec != HH_C64) return hh_fail(HH_ERR_ARG, "unknown precision %d", (int)prec);
     if (g->hs.centering != HH_CELL) return hh_fail(HH_ERR_ARG, "a vertex-centred grid has no multigrid hierarchy");
     if (reps < 1) return hh_fail(HH_ERR_ARG, "reps must be at least 1");
+    if (g->hs.smoother == HH_SMOOTH_ILU0)
+        return hh_fail(HH_ERR_ARG, "the profile times the weighted-Jacobi legs; an ILU(0) grid has none");
     const bool fp32 = prec == HH_C64;
     hh_grid *gm = const_cast<hh_grid *>(g);
     hh_status st = grid_vplan(gm, fp32);

@@ -487,6 +487,8 @@ hh_status hh_submit(hh_server *sv, const hh_request *r, uint64_t *ticket)
     if (!sv || !r || !ticket) return hh_fail(HH_ERR_ARG, "null argument");
     if (r->grid.coarse_op == HH_COARSE_GALERKIN)
         return hh_fail(HH_ERR_ARG, "the server batches requests: Galerkin coarse operators are for single solves");
+    if (r->grid.smoother == HH_SMOOTH_ILU0)
+        return hh_fail(HH_ERR_ARG, "the server batches requests: ILU(0) smoothing is for single solves");
     uint64_t foot = 0;
     std::string err;
     hh_status st = footprint_bytes(&r->grid, &r->opts, foot, err);

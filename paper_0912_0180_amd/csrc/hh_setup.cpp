@@ -346,6 +346,67 @@ static void galerkin_level(HostSetup &hs, int lc)
     for (auto &x : th) x.join();
 }
 
+// ILU(0) of the 2D level operator M_l on its nonzero pattern (Sec. 6.1, the
+// paper's smoother; the incomplete row-wise elimination, rows in
+// lexicographic order).  Entries use the Galerkin layout s = (dx+2) +
+// 5(dy+2); a rediscretised level has the 5-point set {7, 11, 12, 13, 17}.
+// The pattern is the diagonal and the nonzero in-grid entries.  With at
+// least 5 cells per side (checked by desc_check) ascending s is ascending
+// column, so row p eliminates its entries below the diagonal in s order:
+// l = a[p][s] / a[q][12] with q the column of s, then every pattern entry t
+// of row p beyond s loses l times entry (q, column of t) when that entry is
+// in row q's pattern.  Returns false on a zero pivot.
+static bool ilu_level(HostSetup &hs, int l)
+{
+    HostLevel &L = hs.lev[l];
+    const int nx = L.n[0], ny = L.n[1];
+    const int64_t N = L.N;
+    const bool gal = !L.gal.empty();
+    std::vector<double2> &A = L.ilu;
+    A.assign((size_t)25 * N, cmk<double>(0.0, 0.0));
+    std::vector<uint8_t> in((size_t)25 * N, 0);
+    auto member = [gal](int s) { return gal || s == 7 || s == 11 || s == 12 || s == 13 || s == 17; };
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int64_t p = i + (int64_t)nx * j;
+            for (int s = 0; s < 25; ++s) {
+                const int dx = s % 5 - 2, dy = s / 5 - 2;
+                if (!member(s) || i + dx < 0 || i + dx >= nx || j + dy < 0 || j + dy >= ny) continue;
+                double2 v;
+                if (gal) {
+                    v = L.gal[s * N + p];
+                } else if (s == 12) {
+                    const double2 d = cadd<double>(L.dM[0][i], L.dM[1][j]);
+                    v = cmk<double>(d.x - L.phi[p], d.y);
+                } else {
+                    const double2 c = s == 11 ? L.aM[0][i] : s == 13 ? L.cM[0][i] : s == 7 ? L.aM[1][j] : L.cM[1][j];
+                    v = cmk<double>(-c.x, -c.y);
+                }
+                if (s != 12 && v.x == 0.0 && v.y == 0.0) continue;
+                A[s * N + p] = v;
+                in[s * N + p] = 1;
+            }
+        }
+    for (int64_t p = 0; p < N; ++p)
+        for (int s = 0; s < 12; ++s) {
+            if (!in[s * N + p]) continue;
+            const int64_t q = p + (s % 5 - 2) + (int64_t)nx * (s / 5 - 2);
+            const double2 piv = A[12 * N + q];
+            if (piv.x == 0.0 && piv.y == 0.0) return false;
+            const double2 lv = cdiv<double>(A[s * N + p], piv);
+            A[s * N + p] = lv;
+            for (int t = s + 1; t < 25; ++t) {
+                if (!in[t * N + p]) continue;
+                const int ux = t % 5 - s % 5, uy = t / 5 - s / 5;
+                if (ux < -2 || ux > 2 || uy < -2 || uy > 2) continue;
+                const int r = (ux + 2) + 5 * (uy + 2);
+                if (!in[r * N + q]) continue;
+                A[t * N + p] = csub<double>(A[t * N + p], cmul<double>(lv, A[r * N + q]));
+            }
+        }
+    return true;
+}
+
 hh_status desc_check(const hh_grid_desc *d, int &levels, int &coarse, std::string &err)
 {
     char buf[256];
@@ -377,6 +438,14 @@ hh_status desc_check(const hh_grid_desc *d, int &levels, int &coarse, std::strin
     }
     if (d->coarse_op == HH_COARSE_GALERKIN && (dim != 2 || d->centering != HH_CELL)) {
         err = "Galerkin coarse operators need a 2D cell-centred grid";
+        return HH_ERR_ARG;
+    }
+    if (d->smoother != HH_SMOOTH_JACOBI && d->smoother != HH_SMOOTH_ILU0) {
+        err = "smoother must be 0 (weighted Jacobi) or 1 (ILU(0))";
+        return HH_ERR_ARG;
+    }
+    if (d->smoother == HH_SMOOTH_ILU0 && (dim != 2 || d->centering != HH_CELL || d->nu1 != 0)) {
+        err = "ILU(0) smoothing needs a 2D cell-centred grid and the V(0,1) cycle (nu1 = 0)";
         return HH_ERR_ARG;
     }
     int64_t N = 1;
@@ -427,6 +496,14 @@ hh_status desc_check(const hh_grid_desc *d, int &levels, int &coarse, std::strin
         err = buf;
         return HH_ERR_ARG;
     }
+    if (d->smoother == HH_SMOOTH_ILU0)
+        for (int a = 0; a < dim; ++a)
+            if ((d->n[a] >> (nl - 2)) < 5) {
+                snprintf(buf, sizeof buf, "ILU(0) smoothing needs at least 5 cells per side on level %d (side %d has %d)",
+                         nl - 2, a, d->n[a] >> (nl - 2));
+                err = buf;
+                return HH_ERR_ARG;
+            }
     levels = nl;
     coarse = (int)Nc;
     return HH_OK;
@@ -520,6 +597,14 @@ hh_status host_setup(const hh_grid_desc *d, HostSetup &hs, std::string &err)
     hs.coarse_op = d->coarse_op;
     if (hs.coarse_op == HH_COARSE_GALERKIN)
         for (int l = 1; l < nl; ++l) galerkin_level(hs, l);
+    // ILU(0) factors of every smoothing level
+    hs.smoother = d->smoother;
+    if (hs.smoother == HH_SMOOTH_ILU0)
+        for (int l = 0; l + 1 < nl; ++l)
+            if (!ilu_level(hs, l)) {
+                err = "ILU(0) of level " + std::to_string(l) + " met a zero pivot";
+                return HH_ERR_ARG;
+            }
     // coarsest inverse (a vertex-centred grid has no hierarchy)
     const int n = (int)Nc;
     hs.Nc = n;

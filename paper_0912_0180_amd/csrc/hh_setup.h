@@ -14,6 +14,8 @@ struct HostLevel {
     std::vector<double> phi;
     std::vector<double2> gal;     // Galerkin levels >= 1: 25 x N stencil, entry s = (dx+2) + 5(dy+2)
                                   // of point p at s*N + p (the matrix entry M[p, p + dx + nx*dy])
+    std::vector<double2> ilu;     // ILU(0) smoothing levels: 25 x N factors in the same layout
+                                  // (L below the diagonal, unit diagonal not stored; U on and above)
 };
 
 struct HostSetup {
@@ -21,6 +23,7 @@ struct HostSetup {
     int centering = HH_CELL;                    // HH_VERTEX: one level, no hierarchy
     int nu1 = 1;                                // pre-smoothing steps: 1 (V(1,1)) or 0 (V(0,1))
     int coarse_op = HH_COARSE_REDISCRETISED;    // HH_COARSE_GALERKIN: levels >= 1 carry gal
+    int smoother = HH_SMOOTH_JACOBI;            // HH_SMOOTH_ILU0: levels 0 .. nlev-2 carry ilu
     double omega = 0.8;
     std::vector<double2> aH[3], cH[3], dH[3];   // finest level, ECS operator
     HostLevel lev[HH_MAXLEV];

@@ -500,6 +500,8 @@ hh_status check_solve_opts(const hh_grid *g, const hh_solve_opts *o)
     if (o->vcycle_prec != HH_C128 && o->vcycle_prec != HH_C64) return hh_fail(HH_ERR_ARG, "unknown vcycle precision");
     if (g->host_only) return hh_fail(HH_ERR_ARG, "grid was built host-only");
     if (g->hs.centering != HH_CELL) return hh_fail(HH_ERR_ARG, "a vertex-centred grid cannot be solved (operator apply only)");
+    if (g->hs.smoother == HH_SMOOTH_ILU0 && o->vcycle_prec != HH_C128)
+        return hh_fail(HH_ERR_ARG, "ILU(0) smoothing runs in the FP64 V-cycle only (vcycle_prec HH_C128)");
     return HH_OK;
 }
 

@@ -40,7 +40,8 @@ class GridDesc(ctypes.Structure):
                 ("centering", ctypes.c_int32), ("levels", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("phi", ctypes.c_void_p), ("phi_const", ctypes.c_double),
                 ("host_only", ctypes.c_int32), ("csl_shift", ctypes.c_double * 2), ("contour_steps", ctypes.c_int32),
-                ("bc", (ctypes.c_int32 * 2) * 3), ("k_bc", ctypes.c_double), ("coarse_op", ctypes.c_int32)]
+                ("bc", (ctypes.c_int32 * 2) * 3), ("k_bc", ctypes.c_double), ("coarse_op", ctypes.c_int32),
+                ("smoother", ctypes.c_int32)]
 
 
 class GridInfo(ctypes.Structure):
@@ -195,6 +196,7 @@ def make_desc(desc, phi=None, host_only=False):
         d.bc[a][0], d.bc[a][1] = int(sides[0]), int(sides[1])
     d.k_bc = float(desc.get("k_bc", 0.0))
     d.coarse_op = int(desc.get("coarse_op", 0))
+    d.smoother = int(desc.get("smoother", 0))
     return d, keep
 
 
@@ -253,8 +255,9 @@ class Grid:
     def export(self, what, level=0, axis=0):
         """Host copy of a setup array: 'aH','cH','dH','aM','cM','dM' (per axis),
         'phi' (per level), 'Minv' (coarsest inverse), 'galerkin' (the 25 x N
-        stencil of a Galerkin level >= 1)."""
-        names = ["aH", "cH", "dH", "aM", "cM", "dM", "phi", "Minv", "galerkin"]
+        stencil of a Galerkin level >= 1), 'ilu' (the 25 x N ILU(0) factors of
+        a smoothing level)."""
+        names = ["aH", "cH", "dH", "aM", "cM", "dM", "phi", "Minv", "galerkin", "ilu"]
         w = names.index(what)
         if w <= 5:
             out = np.zeros(self.level_dims[level][axis], dtype=np.complex128)

@@ -133,6 +133,32 @@ def c1_paper():
             "method": "bicgstab", "tol": 1e-8}
 
 
+def mp1(k=160.0, n_int=256, layers=True, theta_csg=None, levels=6, smoother=1, coarse_op=1):
+    """Model problem 1 (Sec. 4, eq. (MP1)) as in Table MP1: the unit square
+    with n_int interior cells per axis (h = 1/n_int), constant k, unit point
+    source at the cell just past the centre (a cell-centred grid has no centre
+    node).  layers: ECS layers of n_int/4 cells (width 0.25, angle pi/6) on
+    every side; else first-order Sommerfeld sides (wave number k) on the bare
+    square.  CSG angle pi/28 (layers) or -pi/28 (Sommerfeld), the table's; the
+    paper's multigrid by default: ILU(0) V(0,1) on Galerkin coarse
+    operators, relaxation 1."""
+    if layers:
+        nl = n_int // 4
+        n = n_int + 2 * nl
+        lo, hi = -nl / n_int, 1.0 + nl / n_int
+        th = PI / 28 if theta_csg is None else theta_csg
+        d = base_desc(2, (n, n), (lo, lo), (hi, hi), (0.0, 0.0), (1.0, 1.0), theta_csg=th, levels=levels,
+                      nu1=0, omega=1.0, coarse_op=coarse_op, smoother=smoother)
+    else:
+        n = n_int
+        th = -PI / 28 if theta_csg is None else theta_csg
+        d = base_desc(2, (n, n), (0.0, 0.0), (1.0, 1.0), (0.0, 0.0), (1.0, 1.0), theta_csg=th, levels=levels,
+                      nu1=0, omega=1.0, coarse_op=coarse_op, smoother=smoother, bc=[[1, 1], [1, 1]], k_bc=k)
+    phi = np.full(n * n, k * k)
+    return {"name": "mp1", "desc": d, "phi": phi, "b": point_source(d, (n // 2, n // 2)), "k0": k,
+            "method": "bicgstab", "tol": 1e-6}
+
+
 def c2(n=1024, levels=8, seed=2):
     """2D n x n (default 1024^2) over the C1 geometry, k0 at 10 points per
     wavelength, k(x) = k0 (1 + 0.3 sum of 8 Gaussian bumps of width 0.05 with
