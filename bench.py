@@ -527,6 +527,61 @@ PAPER_MP = {
 }
 
 
+# Table MP1 (Sec. 6.2): MP1, k = 160, 256 interior points, the paper's
+# multigrid (ILU(0) V(0,1), Galerkin), tolerance 1e-6; matvecs and the
+# paper's CPU times (Matlab with mex-C, 2009), and the multigrid on the
+# preconditioner alone (average factor per cycle, cycles for seven orders)
+PAPER_MP1 = {
+    "ecs": {"csg_angle": "pi/28", "mg": [0.24, 10], "bicgstab": [58, "9 s"], "idr4": [62, "9.23 s"],
+            "idr8": [56, "9.62 s"]},
+    "sommerfeld": {"csg_angle": "-pi/28", "mg": [0.24, 10], "bicgstab": [74, "4 s"], "idr4": [70, "3.98 s"],
+                   "idr8": [72, "4.40 s"]},
+}
+
+
+def bench_mp1_table(args, torch, hh, W):
+    """Table MP1 in the paper's own configuration: MP1 with k = 160 (ECS
+    layers on 256 + 2 x 64 cells per axis, CSG pi/28; and the Sommerfeld
+    condition on 256^2, CSG -pi/28), one ILU(0) V(0,1) cycle on Galerkin
+    coarse operators per preconditioner application (FP64), Bi-CGSTAB, IDR(4)
+    and IDR(8) to the paper's 1e-6; the multigrid alone as a solver of the
+    preconditioner problem; the ILU(0) V-cycle's time."""
+    res = {}
+    for bc in ("ecs", "sommerfeld"):
+        c = W.mp1(layers=bc == "ecs")
+        g = hh.Grid(c["desc"], c["phi"])
+        b = torch.from_numpy(c["b"]).to("cuda")
+        x = torch.zeros_like(b)
+        row = {"grid": "%dx%d" % (c["desc"]["n"][0], c["desc"]["n"][1]), "levels": g.levels,
+               "smoother": "ILU(0) V(0,1), Galerkin", "paper": PAPER_MP1[bc]}
+        u = torch.empty_like(b)
+        row["vcycle_ms"] = time_calls(torch, lambda: g.vcycle(b, "c128", out=u), 10) * 1e3
+        # the multigrid alone: u <- u + V(f - M u) until the residual drops by 1e-7
+        uu = torch.zeros_like(b)
+        r = b.clone()
+        r0 = float(torch.linalg.vector_norm(b))
+        it = 0
+        while float(torch.linalg.vector_norm(r)) > 1e-7 * r0 and it < 40:
+            uu += g.vcycle(r, "c128")
+            r = b - g.apply(uu, "M")
+            it += 1
+        row["mg_alone"] = {"cycles": it, "factor": (float(torch.linalg.vector_norm(r)) / r0) ** (1.0 / it)}
+        runs = [("bicgstab", dict(method="bicgstab"))]
+        for sd in (4, 8):
+            runs.append(("idr%d" % sd, dict(method="idr", s=sd, P=hh.shadow_to_device(W.shadow_space(g.N, sd, 500 + sd)))))
+        for rname, kw in runs:
+            g.solve(b, x=x, tol=1e-6, vcycle_prec="c128", **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, info = g.solve(b, x=x, tol=1e-6, vcycle_prec="c128", **kw)
+            torch.cuda.synchronize()
+            row[rname] = {"time_to_tol_ms": (time.perf_counter() - t) * 1e3, "matvecs": info["matvecs"],
+                          "rel_res_true": info["rel_res_true"], "status": info["status"]}
+        res["mp1_k160_" + bc] = row
+        g.close()
+    return res
+
+
 def bench_c1(args, torch, hh, W):
     """C1: the 128^2 grid (layers included) of Sec. 6.1 with kh = 0.625, CSG
     pi/8 uniform and interior, and the paper-aligned 192^2, k = 80 row, each
@@ -851,6 +906,8 @@ def main():
         if "mp" not in skip:
             print("bench: mp2/mp3", file=sys.stderr, flush=True)
             out["model_problems"] = bench_mp(args, torch, hh, W)
+            print("bench: mp1 table (ILU(0))", file=sys.stderr, flush=True)
+            out["mp1_table"] = bench_mp1_table(args, torch, hh, W)
     if args.serve_long:
         print("bench: c5 long", file=sys.stderr, flush=True)
         out["serving_long"] = bench_c5_long(args, torch, hh, W)

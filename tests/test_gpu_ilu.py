@@ -151,3 +151,24 @@ def test_ilu_rejections(torch_dev, hh_mod):
         assert "ILU(0)" in str(ei.value)
     finally:
         sv.close()
+
+
+@pytest.mark.parametrize("layers", [True, False])
+def test_ilu_mp1_table_problem_matches_oracle(torch_dev, hh_mod, oracle_mod, layers):
+    """Table MP1's problem at the paper's size (256 interior points per axis:
+    384^2 with ECS layers, 256^2 with the Sommerfeld condition) and tolerance
+    (1e-6), in the paper's multigrid configuration: the GPU's Bi-CGSTAB solve
+    equals the oracle's value for value (whose matvec counts are held against
+    the table on the CPU)."""
+    torch = torch_dev
+    c = W.mp1(layers=layers)
+    print("case mp1", "ecs" if layers else "sommerfeld", flush=True)
+    g = hh_mod.Grid(c["desc"], c["phi"])
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    xo, io = o.solve(c["b"], tol=1e-6, history=True)
+    xg, ig = g.solve(dev(torch, c["b"]), tol=1e-6, vcycle_prec="c128", history=True)
+    print("matvecs", io["matvecs"], ig["matvecs"], flush=True)
+    assert io["status"] == 0 and ig["status"] == 0
+    assert ig["matvecs"] == io["matvecs"]
+    assert np.array_equal(host(xg), xo)
+    assert np.array_equal(ig["history"], io["history"])
