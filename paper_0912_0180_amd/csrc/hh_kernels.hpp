@@ -1914,6 +1914,151 @@ __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
     for (int64_t p = tid; p < N; p += HH_ILU_WG) stg(u, p, crsadd<double>(ldg(u, p), a.omega, ldg(w, p)));
 }
 
+// The same up-leg for levels of at most NT rows (NT = 1024 for the 5-point
+// set; 512 for the 25-point one, whose 2 x 12 factors in flight need the
+// registers of a 512-thread workgroup), with the triangular
+// solves in the pipelined row form: thread j owns row j, and on anti-diagonal
+// d it solves point (d - m j, j), so its points come left to right (right to
+// left in the backward solve) one step after another.  The values of the
+// last ILU_RING diagonals sit in LDS (slot d mod ILU_RING, entry j): the
+// neighbours below a point lie on the 8 diagonals before it (m = 3) or the
+// one before (m = 1), and those above on as many after it, so no neighbour
+// value is read from global memory, and a slot is rewritten only after every
+// read of its previous diagonal.  The factors and the right-hand side of a
+// thread's next points are loaded two (25-point) or three (5-point) steps
+// ahead, behind the arithmetic and barriers of the steps before them.
+// Values and operation order are k_ilu_up's.
+#define ILU_RING 9
+template <bool GAL> struct IluSet;
+template <> struct IluSet<true> {
+    static constexpr int M = 3, NLO = 12;
+    __device__ static constexpr int lo(int k) { return k; }          // s = 0 .. 11
+    __device__ static constexpr int up(int k) { return 13 + k; }     // s = 13 .. 24
+};
+template <> struct IluSet<false> {
+    static constexpr int M = 1, NLO = 2;
+    __device__ static constexpr int lo(int k) { return k == 0 ? 7 : 11; }
+    __device__ static constexpr int up(int k) { return k == 0 ? 13 : 17; }
+};
+
+template <bool GAL, int NT>
+__global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
+{
+    using S = IluSet<GAL>;
+    constexpr int M = S::M, NK = S::NLO;
+    __shared__ double2 ring[ILU_RING * NT];
+    if (phase_of(cx, 0) != PH_RUN) return;
+    const LevelDev<double> L = a.fl;
+    const int nx = L.n[0], ny = L.n[1], ncx = a.cl.n[0], ncy = a.cl.n[1];
+    const int64_t N = L.N;
+    const double2 *__restrict__ F = L.ilu;
+    const double2 *__restrict__ ec = a.cl.e;
+    double2 *w = L.w;
+    double2 *u = a.u;
+    const double2 zero = cmk<double>(0.0, 0.0);
+    const int tid = threadIdx.x;
+    // u = 0 + P e_{l+1}, then r = f - M u (as k_ilu_up)
+    for (int64_t p = tid; p < N; p += NT) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        const int Ix = i >> 1, Iox = (i & 1) ? Ix + 1 : Ix - 1;
+        const int Iy = j >> 1, Ioy = (j & 1) ? Iy + 1 : Iy - 1;
+        auto ev = [&](int x, int y) -> double2 {
+            return (x >= 0 && x < ncx && y >= 0 && y < ncy) ? ldg(ec, x + (int64_t)ncx * y) : zero;
+        };
+        const double2 a0 = crs2<double>(0.75, ev(Ix, Iy), 0.25, ev(Iox, Iy));
+        const double2 a1 = crs2<double>(0.75, ev(Ix, Ioy), 0.25, ev(Iox, Ioy));
+        stg(u, p, cadd<double>(zero, crs2<double>(0.75, a0, 0.25, a1)));
+    }
+    __syncthreads();
+    for (int64_t p = tid; p < N; p += NT) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        stg(w, p, csub<double>(ldg(a.f, p), ilu_Mu(L, u, i, j, p)));
+    }
+    __syncthreads();
+    const int j = tid;
+    const bool row = j < ny;
+    const int nd = (nx - 1) + M * (ny - 1) + 1;
+    auto slot = [&](int d, int jj) -> double2 & { return ring[(d % ILU_RING) * NT + jj]; };
+    // the factors and the right-hand side (and, backward, the diagonal) of
+    // point (i, j), neighbours outside the grid zero; the next PF points of
+    // the row are in flight in a shift register (compile-time slots)
+    constexpr int PF = GAL ? 2 : 3;
+    double2 fq[PF][NK], rq[PF], dq[PF];
+    auto fetch = [&](int i, bool lower, double2(&fv)[NK], double2 &rv, double2 &dv) {
+        if (i < 0 || i >= nx) return;
+        const int64_t p = i + (int64_t)nx * j;
+        rv = ldg(w, p);
+        if (!lower) dv = ldg(F, 12 * N + p);
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            const int sk = lower ? S::lo(k) : S::up(k);
+            const int ii = i + sk % 5 - 2, jj = j + sk / 5 - 2;
+            fv[k] = (ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? ldg(F, sk * N + p) : zero;
+        }
+    };
+    auto shift = [&]() {
+#pragma unroll
+        for (int b = 0; b + 1 < PF; ++b) {
+#pragma unroll
+            for (int k = 0; k < NK; ++k) fq[b][k] = fq[b + 1][k];
+            rq[b] = rq[b + 1];
+            dq[b] = dq[b + 1];
+        }
+    };
+    // forward: y = r - sum over the neighbours below, columns ascending
+    if (row)
+#pragma unroll
+        for (int b = 0; b < PF; ++b) fetch(b, true, fq[b], rq[b], dq[b]);
+    for (int d = 0; d < nd; ++d) {
+        const int i = d - M * j;
+        if (row && i >= 0 && i < nx) {
+            double2 fc[NK];
+#pragma unroll
+            for (int k = 0; k < NK; ++k) fc[k] = fq[0][k];
+            double2 y = rq[0];
+            shift();
+            fetch(i + PF, true, fq[PF - 1], rq[PF - 1], dq[PF - 1]);
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                const int sk = S::lo(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
+                if (i + dx >= 0 && i + dx < nx && j + dy >= 0)
+                    y = csub<double>(y, cmul<double>(fc[k], slot(d + dx + M * dy, j + dy)));
+            }
+            slot(d, j) = y;
+            stg(w, i + (int64_t)nx * j, y);
+        }
+        __syncthreads();
+    }
+    // backward: z = (y - sum over the neighbours above, columns ascending) / u_12
+    if (row)
+#pragma unroll
+        for (int b = 0; b < PF; ++b) fetch(nx - 1 - b, false, fq[b], rq[b], dq[b]);
+    for (int d = nd - 1; d >= 0; --d) {
+        const int i = d - M * j;
+        if (row && i >= 0 && i < nx) {
+            double2 fc[NK];
+#pragma unroll
+            for (int k = 0; k < NK; ++k) fc[k] = fq[0][k];
+            double2 z = rq[0];
+            const double2 dc = dq[0];
+            shift();
+            fetch(i - PF, false, fq[PF - 1], rq[PF - 1], dq[PF - 1]);
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                const int sk = S::up(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
+                if (i + dx >= 0 && i + dx < nx && j + dy < ny)
+                    z = csub<double>(z, cmul<double>(fc[k], slot(d + dx + M * dy, j + dy)));
+            }
+            z = cdiv<double>(z, dc);
+            slot(d, j) = z;
+            stg(w, i + (int64_t)nx * j, z);
+        }
+        __syncthreads();
+    }
+    // u = u + omega z
+    for (int64_t p = tid; p < N; p += NT) stg(u, p, crsadd<double>(ldg(u, p), a.omega, ldg(w, p)));
+}
+
 // ---------------------------------------------------------------------------
 // Merged 2D legs of K consecutive coarse levels lev0 .. lev0 + K - 1 (ending
 // at the tail's first level lev0 + K), one launch per leg instead of K.  On

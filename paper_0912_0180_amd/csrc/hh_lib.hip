@@ -1120,7 +1120,16 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
                 a.f = l == 0 ? (const double2 *)fptr : lh.d[l].f;
                 a.u = l == 0 ? (double2 *)optr : lh.d[l].e;
                 a.omega = pl.omega1;
-                hipLaunchKernelGGL(k_ilu_up, dim3(1), dim3(HH_ILU_WG), 0, s, c, a);
+                // levels of at most HH_ILU_WG rows: the pipelined row form
+                // with the recent diagonals in LDS
+                const bool rows = !getenv("HH_ILU_GLOBAL");
+                if (rows && a.fl.g && a.fl.n[1] <= 512) {
+                    hipLaunchKernelGGL((k_ilu_up_rows<true, 512>), dim3(1), dim3(512), 0, s, c, a);
+                } else if (rows && !a.fl.g && a.fl.n[1] <= HH_ILU_WG) {
+                    hipLaunchKernelGGL((k_ilu_up_rows<false, HH_ILU_WG>), dim3(1), dim3(HH_ILU_WG), 0, s, c, a);
+                } else {
+                    hipLaunchKernelGGL(k_ilu_up, dim3(1), dim3(HH_ILU_WG), 0, s, c, a);
+                }
             }
             return;
         }
