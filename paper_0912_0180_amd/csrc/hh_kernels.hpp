@@ -1925,9 +1925,9 @@ __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
 // one before (m = 1), and those above on as many after it, so no neighbour
 // value is read from global memory, and a slot is rewritten only after every
 // read of its previous diagonal.  The factors and the right-hand side of a
-// thread's next points are loaded two (25-point) or three (5-point) steps
-// ahead, behind the arithmetic and barriers of the steps before them.
-// Values and operation order are k_ilu_up's.
+// thread's next point are loaded as soon as the current one is done, behind
+// the barriers of the steps before it is needed.  Values and operation order
+// are k_ilu_up's.
 #define ILU_RING 9
 template <bool GAL> struct IluSet;
 template <> struct IluSet<true> {
@@ -1980,9 +1980,13 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
     const int nd = (nx - 1) + M * (ny - 1) + 1;
     auto slot = [&](int d, int jj) -> double2 & { return ring[(d % ILU_RING) * NT + jj]; };
     // the factors and the right-hand side (and, backward, the diagonal) of
-    // point (i, j), neighbours outside the grid zero; the next PF points of
-    // the row are in flight in a shift register (compile-time slots)
-    constexpr int PF = GAL ? 2 : 3;
+    // point (i, j), neighbours outside the grid zero.  The points of a row
+    // are prefetched into PF buffers with fixed roles: the point of step d
+    // uses buffer d mod PF, which is i mod PF for every thread since M j is
+    // a multiple of PF (PF = 3 with m = 3, PF = 1 with m = 1); a buffer is
+    // refilled only after its values are used, so no register holding a
+    // load in flight is copied.
+    constexpr int PF = GAL ? 3 : 1;
     double2 fq[PF][NK], rq[PF], dq[PF];
     auto fetch = [&](int i, bool lower, double2(&fv)[NK], double2 &rv, double2 &dv) {
         if (i < 0 || i >= nx) return;
@@ -1996,64 +2000,56 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
             fv[k] = (ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? ldg(F, sk * N + p) : zero;
         }
     };
-    auto shift = [&]() {
-#pragma unroll
-        for (int b = 0; b + 1 < PF; ++b) {
-#pragma unroll
-            for (int k = 0; k < NK; ++k) fq[b][k] = fq[b + 1][k];
-            rq[b] = rq[b + 1];
-            dq[b] = dq[b + 1];
-        }
-    };
     // forward: y = r - sum over the neighbours below, columns ascending
-    if (row)
-#pragma unroll
-        for (int b = 0; b < PF; ++b) fetch(b, true, fq[b], rq[b], dq[b]);
-    for (int d = 0; d < nd; ++d) {
+    auto fwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
+        if (d >= nd) return;   // uniform
         const int i = d - M * j;
         if (row && i >= 0 && i < nx) {
-            double2 fc[NK];
-#pragma unroll
-            for (int k = 0; k < NK; ++k) fc[k] = fq[0][k];
-            double2 y = rq[0];
-            shift();
-            fetch(i + PF, true, fq[PF - 1], rq[PF - 1], dq[PF - 1]);
+            double2 y = rv;
 #pragma unroll
             for (int k = 0; k < NK; ++k) {
                 const int sk = S::lo(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
                 if (i + dx >= 0 && i + dx < nx && j + dy >= 0)
-                    y = csub<double>(y, cmul<double>(fc[k], slot(d + dx + M * dy, j + dy)));
+                    y = csub<double>(y, cmul<double>(fv[k], slot(d + dx + M * dy, j + dy)));
             }
             slot(d, j) = y;
             stg(w, i + (int64_t)nx * j, y);
+            fetch(i + PF, true, fv, rv, dv);
         }
         __syncthreads();
-    }
-    // backward: z = (y - sum over the neighbours above, columns ascending) / u_12
+    };
     if (row)
 #pragma unroll
-        for (int b = 0; b < PF; ++b) fetch(nx - 1 - b, false, fq[b], rq[b], dq[b]);
-    for (int d = nd - 1; d >= 0; --d) {
+        for (int b = 0; b < PF; ++b) fetch(b, true, fq[b], rq[b], dq[b]);
+    for (int d0 = 0; d0 < nd; d0 += PF) {
+#pragma unroll
+        for (int b = 0; b < PF; ++b) fwd(d0 + b, fq[b], rq[b], dq[b]);
+    }
+    // backward: z = (y - sum over the neighbours above, columns ascending) / u_12
+    auto bwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
+        if (d >= nd) return;   // uniform
         const int i = d - M * j;
         if (row && i >= 0 && i < nx) {
-            double2 fc[NK];
-#pragma unroll
-            for (int k = 0; k < NK; ++k) fc[k] = fq[0][k];
-            double2 z = rq[0];
-            const double2 dc = dq[0];
-            shift();
-            fetch(i - PF, false, fq[PF - 1], rq[PF - 1], dq[PF - 1]);
+            double2 z = rv;
 #pragma unroll
             for (int k = 0; k < NK; ++k) {
                 const int sk = S::up(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
                 if (i + dx >= 0 && i + dx < nx && j + dy < ny)
-                    z = csub<double>(z, cmul<double>(fc[k], slot(d + dx + M * dy, j + dy)));
+                    z = csub<double>(z, cmul<double>(fv[k], slot(d + dx + M * dy, j + dy)));
             }
-            z = cdiv<double>(z, dc);
+            z = cdiv<double>(z, dv);
             slot(d, j) = z;
             stg(w, i + (int64_t)nx * j, z);
+            fetch(i - PF, false, fv, rv, dv);
         }
         __syncthreads();
+    };
+    if (row)
+#pragma unroll
+        for (int b = 0; b < PF; ++b) fetch(nx - 1 - ((nx - 1 - b) % PF), false, fq[b], rq[b], dq[b]);
+    for (int d0 = (nd - 1) / PF * PF; d0 >= 0; d0 -= PF) {
+#pragma unroll
+        for (int b = PF - 1; b >= 0; --b) bwd(d0 + b, fq[b], rq[b], dq[b]);
     }
     // u = u + omega z
     for (int64_t p = tid; p < N; p += NT) stg(u, p, crsadd<double>(ldg(u, p), a.omega, ldg(w, p)));

@@ -172,3 +172,22 @@ def test_ilu_mp1_table_problem_matches_oracle(torch_dev, hh_mod, oracle_mod, lay
     assert ig["matvecs"] == io["matvecs"]
     assert np.array_equal(host(xg), xo)
     assert np.array_equal(ig["history"], io["history"])
+
+
+@pytest.mark.parametrize("name", ["c1_gal", "ragged_redisc"])
+def test_ilu_global_form_equals_row_form(torch_dev, hh_mod, oracle_mod, monkeypatch, name):
+    """Levels of more rows than a workgroup's threads take the up-leg that
+    solves along anti-diagonals in global memory; HH_ILU_GLOBAL=1 forces it
+    everywhere.  Both forms give the oracle's cycle value for value."""
+    torch = torch_dev
+    c = CASES[name]()
+    print("case", name, flush=True)
+    o = oracle_mod.Grid(c["desc"], c["phi"])
+    f = rand_c(np.random.default_rng(18), o.N)
+    ref = o.vcycle(f)
+    fd = dev(torch, f)
+    for form in ("0", "1"):
+        monkeypatch.setenv("HH_ILU_GLOBAL", form) if form == "1" else monkeypatch.delenv("HH_ILU_GLOBAL", raising=False)
+        g = hh_mod.Grid(c["desc"], c["phi"])
+        assert np.array_equal(host(g.vcycle(fd, "c128")), ref), form
+        g.close()
