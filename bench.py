@@ -835,6 +835,21 @@ def pmc_probe(torch, hh, W, n):
           % (prof["up_shape"], g.N, 4 * n), flush=True)
 
 
+def legs_probe(torch, hh, W):
+    """Launches for SQ counter runs on the V-cycle legs: hh_profile_vcycle in
+    complex float (20 cycles, 20 launches of each finest leg) on the 3D 128^3
+    grid (16-cell layers) and on the 2D 1024^2 headline grid."""
+    for name, mk in (("3d128", lambda: W.c3(n=128, layer=16, method="bicgstab")), ("2d1024", lambda: W.c2())):
+        c = mk()
+        g = hh.Grid(c["desc"], c["phi"])
+        f = torch.randn(g.N, dtype=torch.complex128, device="cuda")
+        u = torch.empty(g.N, dtype=torch.complex64, device="cuda")
+        r = g.profile_vcycle(f, "c64", reps=20, out=u)
+        print("legs probe %s: down shape %d %.2f us, up shape %d %.2f us, V-cycle %.1f us"
+              % (name, r["down_shape"], r["down_us"], r["up_shape"], r["up_us"], r["vcycle_us"]), flush=True)
+        g.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -863,6 +878,7 @@ def main():
     ap.add_argument("--cpu-sample-matvecs", type=int, default=300)
     ap.add_argument("--quick", action="store_true", help="headline solve only")
     ap.add_argument("--pmc-probe", action="store_true", help="only the launches the counter runs read")
+    ap.add_argument("--legs-probe", action="store_true", help="only the V-cycle leg launches of the SQ counter runs")
     ap.add_argument("--roofline-n", type=int, default=ROOFLINE_N, help="side of the HBM-resident roofline grid")
     ap.add_argument("--roofline-only", action="store_true", help="only the roofline measurement")
     args = ap.parse_args()
@@ -878,6 +894,9 @@ def main():
     torch.cuda.set_device(0)
     if args.pmc_probe:
         pmc_probe(torch, hh, W, args.roofline_n)
+        return
+    if args.legs_probe:
+        legs_probe(torch, hh, W)
         return
     out = {}
     if args.roofline_only:
