@@ -536,19 +536,30 @@ PAPER_MP1 = {
             "idr8": [56, "9.62 s"]},
     "sommerfeld": {"csg_angle": "-pi/28", "mg": [0.24, 10], "bicgstab": [74, "4 s"], "idr4": [70, "3.98 s"],
                    "idr8": [72, "4.40 s"]},
+    "ecs_csl": {"csl_shift_printed": "-1-0.2i", "mg": [0.29, 12], "bicgstab": [59, "9.15 s"], "idr4": [62, "9.11 s"],
+                "idr8": [60, "9.61 s"]},
+    "sommerfeld_csl": {"csl_shift_printed": "-1+0.2i", "mg": [0.31, 12], "bicgstab": [79, "4.75 s"],
+                       "idr4": [72, "4 s"], "idr8": [76, "5.35 s"]},
 }
 
 
 def bench_mp1_table(args, torch, hh, W):
     """Table MP1 in the paper's own configuration: MP1 with k = 160 (ECS
-    layers on 256 + 2 x 64 cells per axis, CSG pi/28; and the Sommerfeld
-    condition on 256^2, CSG -pi/28), one ILU(0) V(0,1) cycle on Galerkin
+    layers on 256 + 2 x 64 cells per axis, CSG pi/28 or the CSL with the
+    printed shift -1 - 0.2i; the Sommerfeld condition on 256^2, CSG -pi/28 or
+    CSL -1 + 0.2i), one ILU(0) V(0,1) cycle on Galerkin
     coarse operators per preconditioner application (FP64), Bi-CGSTAB, IDR(4)
     and IDR(8) to the paper's 1e-6; the multigrid alone as a solver of the
     preconditioner problem; the ILU(0) V-cycle's time."""
     res = {}
-    for bc in ("ecs", "sommerfeld"):
-        c = W.mp1(layers=bc == "ecs")
+    for bc in ("ecs", "sommerfeld", "ecs_csl", "sommerfeld_csl"):
+        c = W.mp1(layers=bc.startswith("ecs"))
+        if bc.endswith("_csl"):
+            # the CSL preconditioner with beta^2 = 1 -+ 0.2i (printed shift -1 -+ 0.2i)
+            d = dict(c["desc"])
+            d["csg_mode"] = 2
+            d["csl_shift"] = [1.0, 0.2 if bc == "ecs_csl" else -0.2]
+            c = dict(c, desc=d)
         g = hh.Grid(c["desc"], c["phi"])
         b = torch.from_numpy(c["b"]).to("cuda")
         x = torch.zeros_like(b)

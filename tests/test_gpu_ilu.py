@@ -153,8 +153,8 @@ def test_ilu_rejections(torch_dev, hh_mod):
         sv.close()
 
 
-@pytest.mark.parametrize("layers", [True, False])
-def test_ilu_mp1_table_problem_matches_oracle(torch_dev, hh_mod, oracle_mod, layers):
+@pytest.mark.parametrize("layers,csl", [(True, False), (False, False), (False, True)])
+def test_ilu_mp1_table_problem_matches_oracle(torch_dev, hh_mod, oracle_mod, layers, csl):
     """Table MP1's problem at the paper's size (256 interior points per axis:
     384^2 with ECS layers, 256^2 with the Sommerfeld condition) and tolerance
     (1e-6), in the paper's multigrid configuration: the GPU's Bi-CGSTAB solve
@@ -162,7 +162,12 @@ def test_ilu_mp1_table_problem_matches_oracle(torch_dev, hh_mod, oracle_mod, lay
     the table on the CPU)."""
     torch = torch_dev
     c = W.mp1(layers=layers)
-    print("case mp1", "ecs" if layers else "sommerfeld", flush=True)
+    if csl:   # the table's CSL row, beta^2 = 1 + 0.2i (printed shift -1 + 0.2i with the Sommerfeld condition)
+        d = dict(c["desc"])
+        d["csg_mode"] = 2
+        d["csl_shift"] = [1.0, -0.2]
+        c = dict(c, desc=d)
+    print("case mp1", "ecs" if layers else "sommerfeld", "csl" if csl else "csg", flush=True)
     g = hh_mod.Grid(c["desc"], c["phi"])
     o = oracle_mod.Grid(c["desc"], c["phi"])
     xo, io = o.solve(c["b"], tol=1e-6, history=True)
