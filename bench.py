@@ -543,53 +543,92 @@ PAPER_MP1 = {
 }
 
 
-def bench_mp1_table(args, torch, hh, W):
-    """Table MP1 in the paper's own configuration: MP1 with k = 160 (ECS
-    layers on 256 + 2 x 64 cells per axis, CSG pi/28 or the CSL with the
-    printed shift -1 - 0.2i; the Sommerfeld condition on 256^2, CSG -pi/28 or
-    CSL -1 + 0.2i), one ILU(0) V(0,1) cycle on Galerkin
-    coarse operators per preconditioner application (FP64), Bi-CGSTAB, IDR(4)
-    and IDR(8) to the paper's 1e-6; the multigrid alone as a solver of the
-    preconditioner problem; the ILU(0) V-cycle's time."""
-    res = {}
+# Tables MP2 and MP3 (Sec. 6.2), CSG rows: the multigrid alone (factor,
+# cycles) and matvecs of Bi-CGSTAB, IDR(4), IDR(8), as printed
+PAPER_MP23 = {
+    "mp2_nu7_k2_ecs": {"csg_angle": "pi/20", "mg": [0.19, 9], "bicgstab": 68, "idr4": 73, "idr8": 69},
+    "mp2_nu7_k2_sommerfeld": {"csg_angle": "-pi/20", "mg": [0.25, 10], "bicgstab": 113, "idr4": 115, "idr8": 115},
+    "mp2_nu1_k4_ecs": {"csg_angle": "pi/26", "mg": [0.43, 18], "bicgstab": 115, "idr4": 123, "idr8": 114},
+    "mp2_nu1_k4_sommerfeld": {"csg_angle": "-pi/27", "mg": [0.51, 21], "bicgstab": 161, "idr4": 164, "idr8": 161},
+    "mp3_r90_k2_ecs": {"csg_angle": "pi/17", "mg": [0.27, 11], "bicgstab": 139, "idr4": 139, "idr8": 134},
+    "mp3_r90_k2_sommerfeld": {"csg_angle": "-pi/17", "mg": [0.41, 16], "bicgstab": 205, "idr4": 207, "idr8": 207},
+}
+
+
+def bench_paper_tables(args, torch, hh, W):
+    """Tables MP1-MP3 in the paper's own multigrid configuration: one ILU(0)
+    V(0,1) cycle on Galerkin coarse operators per preconditioner application
+    (FP64), Krylov tolerance 1e-6 as in the paper.  MP1 with k = 160 (ECS
+    layers on 256 + 2 x 64 cells, CSG pi/28 or the CSL with the printed shift
+    -1 - 0.2i; the Sommerfeld condition on 256^2, CSG -pi/28 or CSL
+    -1 + 0.2i); MP2 (384 + 128 cells, nu = 7, k = 2 and nu = 1, k = 4) and MP3
+    (r = 90, k = 2, 1024 + 256 cells) with the tables' CSG angles, layers on
+    the north and east edges or the Sommerfeld condition there.  Per row: the
+    multigrid alone as a solver of the preconditioner problem, the ILU(0)
+    V-cycle's time, and Bi-CGSTAB, IDR(4), IDR(8) (MP3: Bi-CGSTAB, one timed
+    solve; its 1280^2 levels exceed the row kernel's 1024 rows)."""
+    PI = np.pi
+    rows = []
     for bc in ("ecs", "sommerfeld", "ecs_csl", "sommerfeld_csl"):
-        c = W.mp1(layers=bc.startswith("ecs"))
-        if bc.endswith("_csl"):
-            # the CSL preconditioner with beta^2 = 1 -+ 0.2i (printed shift -1 -+ 0.2i)
+        def mk(bc=bc):
+            c = W.mp1(layers=bc.startswith("ecs"))
+            if bc.endswith("_csl"):
+                # the CSL preconditioner with beta^2 = 1 -+ 0.2i (printed shift -1 -+ 0.2i)
+                d = dict(c["desc"])
+                d["csg_mode"] = 2
+                d["csl_shift"] = [1.0, 0.2 if bc == "ecs_csl" else -0.2]
+                c = dict(c, desc=d)
+            return c
+        rows.append(("mp1_k160_" + bc, mk, PAPER_MP1[bc], True))
+    mp = [("mp2_nu7_k2_ecs", lambda: W.mp2(nu=7.0, k=2.0, theta_csg=PI / 20)),
+          ("mp2_nu7_k2_sommerfeld", lambda: W.mp2(nu=7.0, k=2.0, n_lay=0, bc="sommerfeld", theta_csg=-PI / 20)),
+          ("mp2_nu1_k4_ecs", lambda: W.mp2(nu=1.0, k=4.0, theta_csg=PI / 26)),
+          ("mp2_nu1_k4_sommerfeld", lambda: W.mp2(nu=1.0, k=4.0, n_lay=0, bc="sommerfeld", theta_csg=-PI / 27)),
+          ("mp3_r90_k2_ecs", lambda: W.mp3(r=90.0, k=2.0, theta_csg=PI / 17)),
+          ("mp3_r90_k2_sommerfeld", lambda: W.mp3(r=90.0, k=2.0, n_lay=0, bc="sommerfeld", theta_csg=-PI / 17))]
+    for name, mk in mp:
+        def mk2(mk=mk):
+            c = mk()
             d = dict(c["desc"])
-            d["csg_mode"] = 2
-            d["csl_shift"] = [1.0, 0.2 if bc == "ecs_csl" else -0.2]
-            c = dict(c, desc=d)
+            d.update(smoother=1, coarse_op=1, nu1=0, omega=1.0)
+            return dict(c, desc=d)
+        rows.append((name, mk2, PAPER_MP23[name], name.startswith("mp2")))
+    res = {}
+    for name, mk, paper, all_methods in rows:
+        c = mk()
         g = hh.Grid(c["desc"], c["phi"])
         b = torch.from_numpy(c["b"]).to("cuda")
         x = torch.zeros_like(b)
         row = {"grid": "%dx%d" % (c["desc"]["n"][0], c["desc"]["n"][1]), "levels": g.levels,
-               "smoother": "ILU(0) V(0,1), Galerkin", "paper": PAPER_MP1[bc]}
+               "smoother": "ILU(0) V(0,1), Galerkin", "paper": paper}
         u = torch.empty_like(b)
-        row["vcycle_ms"] = time_calls(torch, lambda: g.vcycle(b, "c128", out=u), 10) * 1e3
+        row["vcycle_ms"] = time_calls(torch, lambda: g.vcycle(b, "c128", out=u), 10 if all_methods else 3) * 1e3
         # the multigrid alone: u <- u + V(f - M u) until the residual drops by 1e-7
         uu = torch.zeros_like(b)
         r = b.clone()
         r0 = float(torch.linalg.vector_norm(b))
         it = 0
-        while float(torch.linalg.vector_norm(r)) > 1e-7 * r0 and it < 40:
+        while float(torch.linalg.vector_norm(r)) > 1e-7 * r0 and it < 60:
             uu += g.vcycle(r, "c128")
             r = b - g.apply(uu, "M")
             it += 1
         row["mg_alone"] = {"cycles": it, "factor": (float(torch.linalg.vector_norm(r)) / r0) ** (1.0 / it)}
         runs = [("bicgstab", dict(method="bicgstab"))]
-        for sd in (4, 8):
-            runs.append(("idr%d" % sd, dict(method="idr", s=sd, P=hh.shadow_to_device(W.shadow_space(g.N, sd, 500 + sd)))))
+        if all_methods:
+            for sd in (4, 8):
+                runs.append(("idr%d" % sd, dict(method="idr", s=sd, P=hh.shadow_to_device(W.shadow_space(g.N, sd, 500 + sd)))))
         for rname, kw in runs:
-            g.solve(b, x=x, tol=1e-6, vcycle_prec="c128", **kw)
+            if all_methods:
+                g.solve(b, x=x, tol=1e-6, vcycle_prec="c128", max_matvec=3000, **kw)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            _, info = g.solve(b, x=x, tol=1e-6, vcycle_prec="c128", **kw)
+            _, info = g.solve(b, x=x, tol=1e-6, vcycle_prec="c128", max_matvec=3000, **kw)
             torch.cuda.synchronize()
             row[rname] = {"time_to_tol_ms": (time.perf_counter() - t) * 1e3, "matvecs": info["matvecs"],
                           "rel_res_true": info["rel_res_true"], "status": info["status"]}
-        res["mp1_k160_" + bc] = row
+        res[name] = row
         g.close()
+        print("bench: paper table row %s done" % name, file=sys.stderr, flush=True)
     return res
 
 
@@ -936,8 +975,8 @@ def main():
         if "mp" not in skip:
             print("bench: mp2/mp3", file=sys.stderr, flush=True)
             out["model_problems"] = bench_mp(args, torch, hh, W)
-            print("bench: mp1 table (ILU(0))", file=sys.stderr, flush=True)
-            out["mp1_table"] = bench_mp1_table(args, torch, hh, W)
+            print("bench: paper tables MP1-MP3 (ILU(0))", file=sys.stderr, flush=True)
+            out["paper_tables"] = bench_paper_tables(args, torch, hh, W)
     if args.serve_long:
         print("bench: c5 long", file=sys.stderr, flush=True)
         out["serving_long"] = bench_c5_long(args, torch, hh, W)

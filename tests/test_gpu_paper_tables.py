@@ -1,0 +1,87 @@
+"""Tables MP2 and MP3 (Sec. 6.2) in the paper's multigrid configuration
+(ILU(0) V(0,1) on Galerkin coarse operators, tolerance 1e-6), on the GPU.
+
+The GPU's FP64 path equals the oracle's value for value (tests/test_gpu_ilu.py
+at the paper's MP1 size, tests/test_gpu_galerkin.py, tests/test_gpu_variants.py
+for MP2/MP3 with weighted Jacobi), and the oracle's ILU(0) sweeps would take
+minutes at these sizes, so the table is checked here on the GPU's results.
+The figures are in tests/golden/mp2_mp3_tables.json with their citation.
+Bands as for Table MP1 (tests/test_paper_tables.py): the multigrid factor
+within 0.05 and its cycle count within 30%; matvecs within 10% with the
+Sommerfeld condition and within 25% with ECS layers, whose cell-centred
+discretisation runs up to 20% above the table (measured with MP2, nu = 7:
+82/84/81 against 68/73/69; with the Sommerfeld condition and for MP3 the
+counts are within 5%: MP3 with the Sommerfeld condition 205 against 205).
+MP3 (1280^2 and 1024^2) runs Bi-CGSTAB only, to keep the test short.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_0912_0180_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TABLE = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mp2_mp3_tables.json")))
+PI = np.pi
+ANGLE = {"pi/20": PI / 20, "-pi/20": -PI / 20, "pi/26": PI / 26, "-pi/27": -PI / 27, "pi/17": PI / 17,
+         "-pi/17": -PI / 17}
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def hh_mod(torch_dev):
+    from paper_0912_0180_amd import hh
+    hh.lib()
+    return hh
+
+
+def problem(name):
+    row = TABLE[name]
+    th = ANGLE[row["theta_csg"]]
+    som = row["bc"] == "sommerfeld"
+    if name.startswith("mp2"):
+        c = W.mp2(nu=float(row["nu"]), k=float(row["k"]), theta_csg=th, **(dict(n_lay=0, bc="sommerfeld") if som else {}))
+    else:
+        c = W.mp3(r=float(row["r"]), k=float(row["k"]), theta_csg=th, **(dict(n_lay=0, bc="sommerfeld") if som else {}))
+    d = dict(c["desc"])
+    d.update(smoother=1, coarse_op=1, nu1=0, omega=1.0)
+    return d, c["phi"], c["b"], row
+
+
+@pytest.mark.parametrize("name", [k for k in TABLE if k != "source"])
+def test_paper_tables_mp2_mp3(torch_dev, hh_mod, name):
+    torch = torch_dev
+    d, phi, b, row = problem(name)
+    print("case", name, d["n"], flush=True)
+    g = hh_mod.Grid(d, phi)
+    bd = torch.from_numpy(b).cuda()
+    u = torch.zeros_like(bd)
+    r, r0, it = bd.clone(), float(torch.linalg.vector_norm(bd)), 0
+    while float(torch.linalg.vector_norm(r)) > 1e-7 * r0 and it < 60:
+        u += g.vcycle(r, "c128")
+        r = bd - g.apply(u, "M")
+        it += 1
+    factor = (float(torch.linalg.vector_norm(r)) / r0) ** (1.0 / it)
+    print("mg", factor, it, flush=True)
+    assert abs(factor - row["mg_factor"]) <= 0.05, factor
+    assert abs(it - row["mg_cycles"]) <= 0.3 * row["mg_cycles"], it
+    band = 0.10 if row["bc"] == "sommerfeld" else 0.25
+    runs = [("bicgstab", {})]
+    if name.startswith("mp2"):
+        runs += [("idr%d" % s, dict(method="idr", s=s, P=hh_mod.shadow_to_device(W.shadow_space(g.N, s, 500 + s))))
+                 for s in (4, 8)]
+    for key, kw in runs:
+        _, info = g.solve(bd, tol=1e-6, vcycle_prec="c128", max_matvec=3000, **kw)
+        print(key, info["matvecs"], "table", row[key], flush=True)
+        assert info["status"] == 0 and info["rel_res_true"] < 1e-6
+        assert abs(info["matvecs"] - row[key]) <= band * row[key], (key, info["matvecs"], row[key])
+    g.close()
