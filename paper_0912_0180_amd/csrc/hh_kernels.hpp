@@ -1801,11 +1801,19 @@ __global__ __launch_bounds__(GAL_NT) void k_gup(Ctx cx, GalArgs<T> ga)
 // 25-point offsets are then in column order).
 // ---------------------------------------------------------------------------
 #define HH_ILU_WG 1024
+// the pointwise phases (prolongation, residual, update) of a level with more
+// points than this run as grid-wide launches of HH_ILU_PW threads per
+// workgroup: in one workgroup they would take N / 1024 dependent load
+// round trips per thread
+#define HH_ILU_PW 256
+#define HH_ILU_INNER_MAX (int64_t(16) << 10)
 struct IluArgs {
     LevelDev<double> fl, cl;          // level l and the coarser level l + 1
     const double2 *f;                 // right-hand side of level l (the cycle's input on level 0)
     double2 *u;                       // result of level l (e_l, or the cycle's output on level 0)
     double omega;                     // relaxation of the ILU(0) update
+    int inner;                        // 1: the sweep kernel runs the pointwise phases too;
+                                      // 0: k_ilu_prolong, k_ilu_resid, k_ilu_update run them
 };
 
 // entry s (offset (s % 5 - 2, s / 5 - 2)) of row p of M_l applied to u, with
@@ -1836,38 +1844,72 @@ __device__ __forceinline__ double2 ilu_Mu(const LevelDev<double> &L, const doubl
     return t;
 }
 
+// the pointwise phases of the up-leg at point p: u = 0 + P e_{l+1} (bilinear,
+// x then y; coarse values outside are zero), r = f - M u (into w, once every
+// u is written), and after the solves u = u + omega z
+__device__ __forceinline__ void ilu_prolong_at(const IluArgs &a, int64_t p)
+{
+    const int nx = a.fl.n[0], ncx = a.cl.n[0], ncy = a.cl.n[1];
+    const double2 *__restrict__ ec = a.cl.e;
+    const double2 zero = cmk<double>(0.0, 0.0);
+    const int i = (int)(p % nx), j = (int)(p / nx);
+    const int Ix = i >> 1, Iox = (i & 1) ? Ix + 1 : Ix - 1;
+    const int Iy = j >> 1, Ioy = (j & 1) ? Iy + 1 : Iy - 1;
+    auto ev = [&](int x, int y) -> double2 {
+        return (x >= 0 && x < ncx && y >= 0 && y < ncy) ? ldg(ec, x + (int64_t)ncx * y) : zero;
+    };
+    const double2 a0 = crs2<double>(0.75, ev(Ix, Iy), 0.25, ev(Iox, Iy));
+    const double2 a1 = crs2<double>(0.75, ev(Ix, Ioy), 0.25, ev(Iox, Ioy));
+    stg(a.u, p, cadd<double>(zero, crs2<double>(0.75, a0, 0.25, a1)));
+}
+__device__ __forceinline__ void ilu_resid_at(const IluArgs &a, int64_t p)
+{
+    const int nx = a.fl.n[0];
+    const int i = (int)(p % nx), j = (int)(p / nx);
+    stg(a.fl.w, p, csub<double>(ldg(a.f, p), ilu_Mu(a.fl, a.u, i, j, p)));
+}
+__device__ __forceinline__ void ilu_update_at(const IluArgs &a, int64_t p)
+{
+    stg(a.u, p, crsadd<double>(ldg(a.u, p), a.omega, ldg(a.fl.w, p)));
+}
+
+// the pointwise phases as grid-wide launches, for levels whose points are
+// too many for one workgroup's loops (same values: one point per thread)
+__global__ __launch_bounds__(HH_ILU_PW) void k_ilu_prolong(Ctx cx, IluArgs a)
+{
+    if (phase_of(cx, 0) != PH_RUN) return;
+    const int64_t p = blockIdx.x * (int64_t)HH_ILU_PW + threadIdx.x;
+    if (p < a.fl.N) ilu_prolong_at(a, p);
+}
+__global__ __launch_bounds__(HH_ILU_PW) void k_ilu_resid(Ctx cx, IluArgs a)
+{
+    if (phase_of(cx, 0) != PH_RUN) return;
+    const int64_t p = blockIdx.x * (int64_t)HH_ILU_PW + threadIdx.x;
+    if (p < a.fl.N) ilu_resid_at(a, p);
+}
+__global__ __launch_bounds__(HH_ILU_PW) void k_ilu_update(Ctx cx, IluArgs a)
+{
+    if (phase_of(cx, 0) != PH_RUN) return;
+    const int64_t p = blockIdx.x * (int64_t)HH_ILU_PW + threadIdx.x;
+    if (p < a.fl.N) ilu_update_at(a, p);
+}
+
 __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
 {
     if (phase_of(cx, 0) != PH_RUN) return;
     const LevelDev<double> L = a.fl;
-    const int nx = L.n[0], ny = L.n[1], ncx = a.cl.n[0], ncy = a.cl.n[1];
+    const int nx = L.n[0], ny = L.n[1];
     const int64_t N = L.N;
     const double2 *__restrict__ F = L.ilu;
-    const double2 *__restrict__ ec = a.cl.e;
     double2 *w = L.w;
-    double2 *u = a.u;
-    const double2 zero = cmk<double>(0.0, 0.0);
     const bool gal = L.g != nullptr;
     const int tid = threadIdx.x;
-    // u = 0 + P e_{l+1} (bilinear, x then y; coarse values outside are zero)
-    for (int64_t p = tid; p < N; p += HH_ILU_WG) {
-        const int i = (int)(p % nx), j = (int)(p / nx);
-        const int Ix = i >> 1, Iox = (i & 1) ? Ix + 1 : Ix - 1;
-        const int Iy = j >> 1, Ioy = (j & 1) ? Iy + 1 : Iy - 1;
-        auto ev = [&](int x, int y) -> double2 {
-            return (x >= 0 && x < ncx && y >= 0 && y < ncy) ? ldg(ec, x + (int64_t)ncx * y) : zero;
-        };
-        const double2 a0 = crs2<double>(0.75, ev(Ix, Iy), 0.25, ev(Iox, Iy));
-        const double2 a1 = crs2<double>(0.75, ev(Ix, Ioy), 0.25, ev(Iox, Ioy));
-        stg(u, p, cadd<double>(zero, crs2<double>(0.75, a0, 0.25, a1)));
+    if (a.inner) {
+        for (int64_t p = tid; p < N; p += HH_ILU_WG) ilu_prolong_at(a, p);
+        __syncthreads();
+        for (int64_t p = tid; p < N; p += HH_ILU_WG) ilu_resid_at(a, p);
+        __syncthreads();
     }
-    __syncthreads();
-    // r = f - M u
-    for (int64_t p = tid; p < N; p += HH_ILU_WG) {
-        const int i = (int)(p % nx), j = (int)(p / nx);
-        stg(w, p, csub<double>(ldg(a.f, p), ilu_Mu(L, u, i, j, p)));
-    }
-    __syncthreads();
     const int m = gal ? 3 : 1;
     const int nd = (nx - 1) + m * (ny - 1) + 1;
     // forward: y = r - sum of l_s y_q over the neighbours below, columns ascending
@@ -1910,33 +1952,36 @@ __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
         }
         __syncthreads();
     }
-    // u = u + omega z
-    for (int64_t p = tid; p < N; p += HH_ILU_WG) stg(u, p, crsadd<double>(ldg(u, p), a.omega, ldg(w, p)));
+    if (a.inner)
+        for (int64_t p = tid; p < N; p += HH_ILU_WG) ilu_update_at(a, p);
 }
 
-// The same up-leg for levels of at most NT rows (NT = 1024 for the 5-point
-// set; 512 for the 25-point one, whose 2 x 12 factors in flight need the
-// registers of a 512-thread workgroup), with the triangular
-// solves in the pipelined row form: thread j owns row j, and on anti-diagonal
-// d it solves point (d - m j, j), so its points come left to right (right to
-// left in the backward solve) one step after another.  The values of the
-// last ILU_RING diagonals sit in LDS (slot d mod ILU_RING, entry j): the
-// neighbours below a point lie on the 8 diagonals before it (m = 3) or the
-// one before (m = 1), and those above on as many after it, so no neighbour
-// value is read from global memory, and a slot is rewritten only after every
-// read of its previous diagonal.  The factors and the right-hand side of a
-// thread's next point are loaded as soon as the current one is done, behind
-// the barriers of the steps before it is needed.  Values and operation order
-// are k_ilu_up's.
-#define ILU_RING 9
+// The same up-leg with the triangular solves in the pipelined row form, in
+// bands of at most NT rows (NT = 1024 for the 5-point set; 512 for the
+// 25-point one, whose 2 x 12 factors in flight need the registers of a
+// 512-thread workgroup).  Within a band, thread t owns row j0 + t, and on the
+// band's anti-diagonal d it solves point (d - m t, j0 + t), so its points
+// come left to right (right to left in the backward solve) one step after
+// another.  The values of the last RING diagonals sit in LDS (slot d mod
+// RING, entry t): the neighbours below a point lie on the 8 diagonals before
+// it (m = 3) or the one before (m = 1), and those above on as many after it,
+// so no neighbour value is read from global memory, and a slot is rewritten
+// only after every read of its previous diagonal.  Bands run one after
+// another (bottom up forward, top down backward); the rows a band reads from
+// the band before it (two with m = 3, one with m = 1) are kept in an LDS halo
+// by column, each entry rewritten by the band's own boundary rows only after
+// its last read (bands have at least 3 rows).  The factors and the
+// right-hand side of a thread's next point are loaded as soon as the current
+// one is done, behind the barriers of the steps before it is needed.  Values
+// and operation order are k_ilu_up's.
 template <bool GAL> struct IluSet;
 template <> struct IluSet<true> {
-    static constexpr int M = 3, NLO = 12;
+    static constexpr int M = 3, NLO = 12, RING = 9, HR = 2, HMAX = 2048, PF = 3;
     __device__ static constexpr int lo(int k) { return k; }          // s = 0 .. 11
     __device__ static constexpr int up(int k) { return 13 + k; }     // s = 13 .. 24
 };
 template <> struct IluSet<false> {
-    static constexpr int M = 1, NLO = 2;
+    static constexpr int M = 1, NLO = 2, RING = 2, HR = 1, HMAX = 4096, PF = 1;
     __device__ static constexpr int lo(int k) { return k == 0 ? 7 : 11; }
     __device__ static constexpr int up(int k) { return k == 0 ? 13 : 17; }
 };
@@ -1945,50 +1990,39 @@ template <bool GAL, int NT>
 __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
 {
     using S = IluSet<GAL>;
-    constexpr int M = S::M, NK = S::NLO;
-    __shared__ double2 ring[ILU_RING * NT];
+    constexpr int M = S::M, NK = S::NLO, RG = S::RING, HR = S::HR, HM = S::HMAX;
+    __shared__ double2 ring[RG * NT];
+    __shared__ double2 halo[HR * HM];
     if (phase_of(cx, 0) != PH_RUN) return;
     const LevelDev<double> L = a.fl;
-    const int nx = L.n[0], ny = L.n[1], ncx = a.cl.n[0], ncy = a.cl.n[1];
+    const int nx = L.n[0], ny = L.n[1];
     const int64_t N = L.N;
     const double2 *__restrict__ F = L.ilu;
-    const double2 *__restrict__ ec = a.cl.e;
     double2 *w = L.w;
-    double2 *u = a.u;
     const double2 zero = cmk<double>(0.0, 0.0);
-    const int tid = threadIdx.x;
-    // u = 0 + P e_{l+1}, then r = f - M u (as k_ilu_up)
-    for (int64_t p = tid; p < N; p += NT) {
-        const int i = (int)(p % nx), j = (int)(p / nx);
-        const int Ix = i >> 1, Iox = (i & 1) ? Ix + 1 : Ix - 1;
-        const int Iy = j >> 1, Ioy = (j & 1) ? Iy + 1 : Iy - 1;
-        auto ev = [&](int x, int y) -> double2 {
-            return (x >= 0 && x < ncx && y >= 0 && y < ncy) ? ldg(ec, x + (int64_t)ncx * y) : zero;
-        };
-        const double2 a0 = crs2<double>(0.75, ev(Ix, Iy), 0.25, ev(Iox, Iy));
-        const double2 a1 = crs2<double>(0.75, ev(Ix, Ioy), 0.25, ev(Iox, Ioy));
-        stg(u, p, cadd<double>(zero, crs2<double>(0.75, a0, 0.25, a1)));
+    const int t = threadIdx.x;
+    if (a.inner) {
+        for (int64_t p = t; p < N; p += NT) ilu_prolong_at(a, p);
+        __syncthreads();
+        for (int64_t p = t; p < N; p += NT) ilu_resid_at(a, p);
+        __syncthreads();
     }
-    __syncthreads();
-    for (int64_t p = tid; p < N; p += NT) {
-        const int i = (int)(p % nx), j = (int)(p / nx);
-        stg(w, p, csub<double>(ldg(a.f, p), ilu_Mu(L, u, i, j, p)));
-    }
-    __syncthreads();
-    const int j = tid;
-    const bool row = j < ny;
-    const int nd = (nx - 1) + M * (ny - 1) + 1;
-    auto slot = [&](int d, int jj) -> double2 & { return ring[(d % ILU_RING) * NT + jj]; };
+    // nb bands of ny / nb or ny / nb + 1 rows; the halo is used (and nx <= HM
+    // holds) only when nb > 1
+    const int nb = (ny + NT - 1) / NT, base = ny / nb, extra = ny % nb;
+    const bool banded = nb > 1;
+    auto band0 = [&](int bi) { return bi * base + min(bi, extra); };
+    auto slot = [&](int d, int tt) -> double2 & { return ring[(d % RG) * NT + tt]; };
     // the factors and the right-hand side (and, backward, the diagonal) of
     // point (i, j), neighbours outside the grid zero.  The points of a row
     // are prefetched into PF buffers with fixed roles: the point of step d
-    // uses buffer d mod PF, which is i mod PF for every thread since M j is
+    // uses buffer d mod PF, which is i mod PF for every thread since M t is
     // a multiple of PF (PF = 3 with m = 3, PF = 1 with m = 1); a buffer is
     // refilled only after its values are used, so no register holding a
     // load in flight is copied.
-    constexpr int PF = GAL ? 3 : 1;
+    constexpr int PF = S::PF;
     double2 fq[PF][NK], rq[PF], dq[PF];
-    auto fetch = [&](int i, bool lower, double2(&fv)[NK], double2 &rv, double2 &dv) {
+    auto fetch = [&](int i, int j, bool lower, double2(&fv)[NK], double2 &rv, double2 &dv) {
         if (i < 0 || i >= nx) return;
         const int64_t p = i + (int64_t)nx * j;
         rv = ldg(w, p);
@@ -2001,58 +2035,74 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
         }
     };
     // forward: y = r - sum over the neighbours below, columns ascending
-    auto fwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
-        if (d >= nd) return;   // uniform
-        const int i = d - M * j;
-        if (row && i >= 0 && i < nx) {
-            double2 y = rv;
+    for (int bi = 0; bi < nb; ++bi) {
+        const int j0 = band0(bi), R = band0(bi + 1) - j0, j = j0 + t;
+        const bool row = t < R;
+        const int nd = (nx - 1) + M * (R - 1) + 1;
+        auto fwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
+            if (d >= nd) return;   // uniform
+            const int i = d - M * t;
+            if (row && i >= 0 && i < nx) {
+                double2 y = rv;
 #pragma unroll
-            for (int k = 0; k < NK; ++k) {
-                const int sk = S::lo(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
-                if (i + dx >= 0 && i + dx < nx && j + dy >= 0)
-                    y = csub<double>(y, cmul<double>(fv[k], slot(d + dx + M * dy, j + dy)));
+                for (int k = 0; k < NK; ++k) {
+                    const int sk = S::lo(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
+                    if (i + dx >= 0 && i + dx < nx && j + dy >= 0) {
+                        const double2 q = t + dy >= 0 ? slot(d + dx + M * dy, t + dy) : halo[(HR + t + dy) * HM + i + dx];
+                        y = csub<double>(y, cmul<double>(fv[k], q));
+                    }
+                }
+                slot(d, t) = y;
+                if (banded && t >= R - HR) halo[(t - (R - HR)) * HM + i] = y;
+                stg(w, i + (int64_t)nx * j, y);
+                fetch(i + PF, j, true, fv, rv, dv);
             }
-            slot(d, j) = y;
-            stg(w, i + (int64_t)nx * j, y);
-            fetch(i + PF, true, fv, rv, dv);
+            __syncthreads();
+        };
+        if (row)
+#pragma unroll
+            for (int b = 0; b < PF; ++b) fetch(b, j, true, fq[b], rq[b], dq[b]);
+        for (int d0 = 0; d0 < nd; d0 += PF) {
+#pragma unroll
+            for (int b = 0; b < PF; ++b) fwd(d0 + b, fq[b], rq[b], dq[b]);
         }
-        __syncthreads();
-    };
-    if (row)
-#pragma unroll
-        for (int b = 0; b < PF; ++b) fetch(b, true, fq[b], rq[b], dq[b]);
-    for (int d0 = 0; d0 < nd; d0 += PF) {
-#pragma unroll
-        for (int b = 0; b < PF; ++b) fwd(d0 + b, fq[b], rq[b], dq[b]);
     }
     // backward: z = (y - sum over the neighbours above, columns ascending) / u_12
-    auto bwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
-        if (d >= nd) return;   // uniform
-        const int i = d - M * j;
-        if (row && i >= 0 && i < nx) {
-            double2 z = rv;
+    for (int bi = nb - 1; bi >= 0; --bi) {
+        const int j0 = band0(bi), R = band0(bi + 1) - j0, j = j0 + t;
+        const bool row = t < R;
+        const int nd = (nx - 1) + M * (R - 1) + 1;
+        auto bwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
+            if (d >= nd) return;   // uniform
+            const int i = d - M * t;
+            if (row && i >= 0 && i < nx) {
+                double2 z = rv;
 #pragma unroll
-            for (int k = 0; k < NK; ++k) {
-                const int sk = S::up(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
-                if (i + dx >= 0 && i + dx < nx && j + dy < ny)
-                    z = csub<double>(z, cmul<double>(fv[k], slot(d + dx + M * dy, j + dy)));
+                for (int k = 0; k < NK; ++k) {
+                    const int sk = S::up(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
+                    if (i + dx >= 0 && i + dx < nx && j + dy < ny) {
+                        const double2 q = t + dy < R ? slot(d + dx + M * dy, t + dy) : halo[(t + dy - R) * HM + i + dx];
+                        z = csub<double>(z, cmul<double>(fv[k], q));
+                    }
+                }
+                z = cdiv<double>(z, dv);
+                slot(d, t) = z;
+                if (banded && t < HR) halo[t * HM + i] = z;
+                stg(w, i + (int64_t)nx * j, z);
+                fetch(i - PF, j, false, fv, rv, dv);
             }
-            z = cdiv<double>(z, dv);
-            slot(d, j) = z;
-            stg(w, i + (int64_t)nx * j, z);
-            fetch(i - PF, false, fv, rv, dv);
+            __syncthreads();
+        };
+        if (row)
+#pragma unroll
+            for (int b = 0; b < PF; ++b) fetch(nx - 1 - ((nx - 1 - b) % PF), j, false, fq[b], rq[b], dq[b]);
+        for (int d0 = (nd - 1) / PF * PF; d0 >= 0; d0 -= PF) {
+#pragma unroll
+            for (int b = PF - 1; b >= 0; --b) bwd(d0 + b, fq[b], rq[b], dq[b]);
         }
-        __syncthreads();
-    };
-    if (row)
-#pragma unroll
-        for (int b = 0; b < PF; ++b) fetch(nx - 1 - ((nx - 1 - b) % PF), false, fq[b], rq[b], dq[b]);
-    for (int d0 = (nd - 1) / PF * PF; d0 >= 0; d0 -= PF) {
-#pragma unroll
-        for (int b = PF - 1; b >= 0; --b) bwd(d0 + b, fq[b], rq[b], dq[b]);
     }
-    // u = u + omega z
-    for (int64_t p = tid; p < N; p += NT) stg(u, p, crsadd<double>(ldg(u, p), a.omega, ldg(w, p)));
+    if (a.inner)
+        for (int64_t p = t; p < N; p += NT) ilu_update_at(a, p);
 }
 
 // ---------------------------------------------------------------------------

@@ -1120,16 +1120,28 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
                 a.f = l == 0 ? (const double2 *)fptr : lh.d[l].f;
                 a.u = l == 0 ? (double2 *)optr : lh.d[l].e;
                 a.omega = pl.omega1;
-                // levels of at most HH_ILU_WG rows: the pipelined row form
-                // with the recent diagonals in LDS
+                // the pointwise phases of levels above HH_ILU_INNER_MAX points
+                // run grid-wide (HH_ILU_FUSED: inside the sweep kernel always)
+                a.inner = (a.fl.N <= HH_ILU_INNER_MAX || getenv("HH_ILU_FUSED")) ? 1 : 0;
+                const dim3 pg((unsigned)((a.fl.N + HH_ILU_PW - 1) / HH_ILU_PW));
+                if (!a.inner) {
+                    hipLaunchKernelGGL(k_ilu_prolong, pg, dim3(HH_ILU_PW), 0, s, c, a);
+                    hipLaunchKernelGGL(k_ilu_resid, pg, dim3(HH_ILU_PW), 0, s, c, a);
+                }
+                // the pipelined row form with the recent diagonals in LDS,
+                // in bands where a level has more rows than the workgroup
+                // threads (then its rows must fit the LDS halo);
+                // HH_ILU_GLOBAL: the global-memory form on every level
                 const bool rows = !getenv("HH_ILU_GLOBAL");
-                if (rows && a.fl.g && a.fl.n[1] <= 512) {
+                const int nx = a.fl.n[0], ny = a.fl.n[1];
+                if (rows && a.fl.g && (ny <= 512 || nx <= IluSet<true>::HMAX)) {
                     hipLaunchKernelGGL((k_ilu_up_rows<true, 512>), dim3(1), dim3(512), 0, s, c, a);
-                } else if (rows && !a.fl.g && a.fl.n[1] <= HH_ILU_WG) {
+                } else if (rows && !a.fl.g && (ny <= HH_ILU_WG || nx <= IluSet<false>::HMAX)) {
                     hipLaunchKernelGGL((k_ilu_up_rows<false, HH_ILU_WG>), dim3(1), dim3(HH_ILU_WG), 0, s, c, a);
                 } else {
                     hipLaunchKernelGGL(k_ilu_up, dim3(1), dim3(HH_ILU_WG), 0, s, c, a);
                 }
+                if (!a.inner) hipLaunchKernelGGL(k_ilu_update, pg, dim3(HH_ILU_PW), 0, s, c, a);
             }
             return;
         }

@@ -61,9 +61,25 @@ def ragged(coarse_op):
     return ilu_case({"desc": d, "phi": phi}, coarse_op, omega=0.9)
 
 
+def tall(coarse_op):
+    """48 x 2096 cells, 5 levels: more rows than the row form's workgroup on
+    the levels 0 (3 bands of 699, 699, 698 rows), 1 (3 Galerkin bands of 350,
+    349, 349, or 2 rediscretised ones of 524) and 2 (2 Galerkin bands of 262);
+    the pointwise phases of levels 0 and 1 run grid-wide, those of level 2 in
+    the sweep kernel."""
+    h = 1.0 / 64
+    n = (48, 2096)
+    hi = (-0.2 + n[0] * h, -0.3 + n[1] * h)
+    d = W.base_desc(2, n, (-0.2, -0.3), hi, (0.0, 0.0), (hi[0] - 0.2, hi[1] - 0.35), levels=5)
+    rng = np.random.default_rng(75)
+    phi = (8.0 ** 2) * (1 + 0.3 * rng.uniform(size=n[0] * n[1]))
+    return ilu_case({"desc": d, "phi": phi}, coarse_op, omega=0.9)
+
+
 CASES = {"c1_gal": lambda: ilu_case(W.c1(), 1), "c1_redisc": lambda: ilu_case(W.c1(), 0),
          "c1_interior_gal": lambda: ilu_case(W.c1(mode=1), 1), "ragged_gal": lambda: ragged(1),
-         "ragged_redisc": lambda: ragged(0), "paper_gal": lambda: ilu_case(W.c1_paper(), 1)}
+         "ragged_redisc": lambda: ragged(0), "paper_gal": lambda: ilu_case(W.c1_paper(), 1),
+         "tall_gal": lambda: tall(1), "tall_redisc": lambda: tall(0)}
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -84,7 +100,7 @@ def test_ilu_vcycle_matches_oracle(torch_dev, hh_mod, oracle_mod, name):
     assert np.array_equal(host(g.vcycle(fd, "c128")), u)
 
 
-@pytest.mark.parametrize("name", ["c1_gal", "c1_redisc", "ragged_gal", "paper_gal"])
+@pytest.mark.parametrize("name", ["c1_gal", "c1_redisc", "ragged_gal", "paper_gal", "tall_gal", "tall_redisc"])
 def test_ilu_bicgstab_fp64_matches_oracle(torch_dev, hh_mod, oracle_mod, name):
     torch = torch_dev
     c = CASES[name]()
@@ -179,11 +195,13 @@ def test_ilu_mp1_table_problem_matches_oracle(torch_dev, hh_mod, oracle_mod, lay
     assert np.array_equal(ig["history"], io["history"])
 
 
-@pytest.mark.parametrize("name", ["c1_gal", "ragged_redisc"])
-def test_ilu_global_form_equals_row_form(torch_dev, hh_mod, oracle_mod, monkeypatch, name):
-    """Levels of more rows than a workgroup's threads take the up-leg that
-    solves along anti-diagonals in global memory; HH_ILU_GLOBAL=1 forces it
-    everywhere.  Both forms give the oracle's cycle value for value."""
+@pytest.mark.parametrize("name", ["c1_gal", "ragged_redisc", "tall_gal"])
+def test_ilu_up_leg_forms_are_equal(torch_dev, hh_mod, oracle_mod, monkeypatch, name):
+    """The up-leg's forms: the pipelined row form (in bands where a level has
+    more rows than its workgroup), the global-memory form (HH_ILU_GLOBAL=1 on
+    every level), and the pointwise phases inside the sweep kernel
+    (HH_ILU_FUSED=1) instead of grid-wide on large levels.  Every combination
+    gives the oracle's cycle value for value."""
     torch = torch_dev
     c = CASES[name]()
     print("case", name, flush=True)
@@ -191,8 +209,10 @@ def test_ilu_global_form_equals_row_form(torch_dev, hh_mod, oracle_mod, monkeypa
     f = rand_c(np.random.default_rng(18), o.N)
     ref = o.vcycle(f)
     fd = dev(torch, f)
-    for form in ("0", "1"):
-        monkeypatch.setenv("HH_ILU_GLOBAL", form) if form == "1" else monkeypatch.delenv("HH_ILU_GLOBAL", raising=False)
-        g = hh_mod.Grid(c["desc"], c["phi"])
-        assert np.array_equal(host(g.vcycle(fd, "c128")), ref), form
-        g.close()
+    for glob in (False, True):
+        for fused in (False, True):
+            for var, on in (("HH_ILU_GLOBAL", glob), ("HH_ILU_FUSED", fused)):
+                monkeypatch.setenv(var, "1") if on else monkeypatch.delenv(var, raising=False)
+            g = hh_mod.Grid(c["desc"], c["phi"])
+            assert np.array_equal(host(g.vcycle(fd, "c128")), ref), (glob, fused)
+            g.close()
