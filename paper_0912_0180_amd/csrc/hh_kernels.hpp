@@ -1894,6 +1894,24 @@ __global__ __launch_bounds__(HH_ILU_PW) void k_ilu_update(Ctx cx, IluArgs a)
     if (p < a.fl.N) ilu_update_at(a, p);
 }
 
+// The entry sets of the triangular solves, and the device layout of a
+// level's factors (point-major, so that the entries one thread needs for a
+// point are adjacent): the lower entries of point p at p NLO + k, k in the
+// set's order, then from NLO N the diagonal of p at NLO N + p UPW and its
+// upper entries at NLO N + p UPW + 1 + k (UPW leaves the rest of 16 or 4
+// entries unused, so a point's upper block fills whole cache lines).
+template <bool GAL> struct IluSet;
+template <> struct IluSet<true> {
+    static constexpr int M = 3, NLO = 12, UPW = 16, RING = 9, HR = 2, HMAX = 2048, PF = 3;
+    __host__ __device__ static constexpr int lo(int k) { return k; }          // s = 0 .. 11
+    __host__ __device__ static constexpr int up(int k) { return 13 + k; }     // s = 13 .. 24
+};
+template <> struct IluSet<false> {
+    static constexpr int M = 1, NLO = 2, UPW = 4, RING = 2, HR = 1, HMAX = 4096, PF = 4;
+    __host__ __device__ static constexpr int lo(int k) { return k == 0 ? 7 : 11; }
+    __host__ __device__ static constexpr int up(int k) { return k == 0 ? 13 : 17; }
+};
+
 __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
 {
     if (phase_of(cx, 0) != PH_RUN) return;
@@ -1912,6 +1930,7 @@ __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
     }
     const int m = gal ? 3 : 1;
     const int nd = (nx - 1) + m * (ny - 1) + 1;
+    const int64_t ub = (gal ? IluSet<true>::NLO : IluSet<false>::NLO) * N;
     // forward: y = r - sum of l_s y_q over the neighbours below, columns ascending
     for (int d = 0; d < nd; ++d) {
         const int jlo = d - (nx - 1) > 0 ? (d - (nx - 1) + m - 1) / m : 0, jhi = min(ny - 1, d / m);
@@ -1922,11 +1941,11 @@ __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
             if (gal) {
                 for (int s = 0; s < 12; ++s) {
                     const int ii = i + s % 5 - 2, jj = j + s / 5 - 2;
-                    if (ii >= 0 && ii < nx && jj >= 0) y = csub<double>(y, cmul<double>(ldg(F, s * N + p), ldg(w, ii + (int64_t)nx * jj)));
+                    if (ii >= 0 && ii < nx && jj >= 0) y = csub<double>(y, cmul<double>(ldg(F, p * 12 + s), ldg(w, ii + (int64_t)nx * jj)));
                 }
             } else {
-                if (j > 0) y = csub<double>(y, cmul<double>(ldg(F, 7 * N + p), ldg(w, p - nx)));
-                if (i > 0) y = csub<double>(y, cmul<double>(ldg(F, 11 * N + p), ldg(w, p - 1)));
+                if (j > 0) y = csub<double>(y, cmul<double>(ldg(F, p * 2), ldg(w, p - nx)));
+                if (i > 0) y = csub<double>(y, cmul<double>(ldg(F, p * 2 + 1), ldg(w, p - 1)));
             }
             stg(w, p, y);
         }
@@ -1940,15 +1959,18 @@ __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
             const int64_t p = i + (int64_t)nx * j;
             double2 z = ldg(w, p);
             if (gal) {
+                const int64_t q = ub + p * IluSet<true>::UPW;
                 for (int s = 13; s < 25; ++s) {
                     const int ii = i + s % 5 - 2, jj = j + s / 5 - 2;
-                    if (ii >= 0 && ii < nx && jj < ny) z = csub<double>(z, cmul<double>(ldg(F, s * N + p), ldg(w, ii + (int64_t)nx * jj)));
+                    if (ii >= 0 && ii < nx && jj < ny) z = csub<double>(z, cmul<double>(ldg(F, q + 1 + (s - 13)), ldg(w, ii + (int64_t)nx * jj)));
                 }
+                stg(w, p, cdiv<double>(z, ldg(F, q)));
             } else {
-                if (i < nx - 1) z = csub<double>(z, cmul<double>(ldg(F, 13 * N + p), ldg(w, p + 1)));
-                if (j < ny - 1) z = csub<double>(z, cmul<double>(ldg(F, 17 * N + p), ldg(w, p + nx)));
+                const int64_t q = ub + p * IluSet<false>::UPW;
+                if (i < nx - 1) z = csub<double>(z, cmul<double>(ldg(F, q + 1), ldg(w, p + 1)));
+                if (j < ny - 1) z = csub<double>(z, cmul<double>(ldg(F, q + 2), ldg(w, p + nx)));
+                stg(w, p, cdiv<double>(z, ldg(F, q)));
             }
-            stg(w, p, cdiv<double>(z, ldg(F, 12 * N + p)));
         }
         __syncthreads();
     }
@@ -1971,21 +1993,9 @@ __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
 // the band before it (two with m = 3, one with m = 1) are kept in an LDS halo
 // by column, each entry rewritten by the band's own boundary rows only after
 // its last read (bands have at least 3 rows).  The factors and the
-// right-hand side of a thread's next point are loaded as soon as the current
-// one is done, behind the barriers of the steps before it is needed.  Values
-// and operation order are k_ilu_up's.
-template <bool GAL> struct IluSet;
-template <> struct IluSet<true> {
-    static constexpr int M = 3, NLO = 12, RING = 9, HR = 2, HMAX = 2048, PF = 3;
-    __device__ static constexpr int lo(int k) { return k; }          // s = 0 .. 11
-    __device__ static constexpr int up(int k) { return 13 + k; }     // s = 13 .. 24
-};
-template <> struct IluSet<false> {
-    static constexpr int M = 1, NLO = 2, RING = 2, HR = 1, HMAX = 4096, PF = 1;
-    __device__ static constexpr int lo(int k) { return k == 0 ? 7 : 11; }
-    __device__ static constexpr int up(int k) { return k == 0 ? 13 : 17; }
-};
-
+// right-hand side of a thread's points are loaded PF steps before they are
+// needed (3 with m = 3, 4 with m = 1), behind the barriers of the steps in
+// between.  Values and operation order are k_ilu_up's.
 template <bool GAL, int NT>
 __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
 {
@@ -2014,24 +2024,29 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
     auto band0 = [&](int bi) { return bi * base + min(bi, extra); };
     auto slot = [&](int d, int tt) -> double2 & { return ring[(d % RG) * NT + tt]; };
     // the factors and the right-hand side (and, backward, the diagonal) of
-    // point (i, j), neighbours outside the grid zero.  The points of a row
-    // are prefetched into PF buffers with fixed roles: the point of step d
-    // uses buffer d mod PF, which is i mod PF for every thread since M t is
-    // a multiple of PF (PF = 3 with m = 3, PF = 1 with m = 1); a buffer is
-    // refilled only after its values are used, so no register holding a
-    // load in flight is copied.
-    constexpr int PF = S::PF;
+    // a thread's points are prefetched PF steps ahead into PF buffers with
+    // fixed roles: step d uses buffer d mod PF, and refills it with the point
+    // the thread solves at step d + PF.  Every thread loads on every step, a
+    // thread without a point there (before its row's first point, after its
+    // last, or beyond the band) from point 0, so the same number of loads
+    // follows each refill on every path and the wait before a use is for
+    // that buffer's loads only, while idle lanes add one cache line per
+    // load; a factor of a neighbour outside the grid is loaded but never
+    // used.  The loops start PF steps early (loads only), so no buffer needs
+    // filling before them.
+    constexpr int PF = S::PF, NLO = S::NLO, UPW = S::UPW;
     double2 fq[PF][NK], rq[PF], dq[PF];
-    auto fetch = [&](int i, int j, bool lower, double2(&fv)[NK], double2 &rv, double2 &dv) {
-        if (i < 0 || i >= nx) return;
-        const int64_t p = i + (int64_t)nx * j;
+    auto fetch = [&](bool ok, int i, int j, bool lower, double2(&fv)[NK], double2 &rv, double2 &dv) {
+        const int64_t p = ok && i >= 0 && i < nx ? i + (int64_t)nx * j : 0;
         rv = ldg(w, p);
-        if (!lower) dv = ldg(F, 12 * N + p);
+        if (lower) {
 #pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            const int sk = lower ? S::lo(k) : S::up(k);
-            const int ii = i + sk % 5 - 2, jj = j + sk / 5 - 2;
-            fv[k] = (ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? ldg(F, sk * N + p) : zero;
+            for (int k = 0; k < NK; ++k) fv[k] = ldg(F, p * NLO + k);
+        } else {
+            const int64_t q = NLO * N + p * UPW;
+            dv = ldg(F, q);
+#pragma unroll
+            for (int k = 0; k < NK; ++k) fv[k] = ldg(F, q + 1 + k);
         }
     };
     // forward: y = r - sum over the neighbours below, columns ascending
@@ -2040,7 +2055,6 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
         const bool row = t < R;
         const int nd = (nx - 1) + M * (R - 1) + 1;
         auto fwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
-            if (d >= nd) return;   // uniform
             const int i = d - M * t;
             if (row && i >= 0 && i < nx) {
                 double2 y = rv;
@@ -2055,14 +2069,11 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
                 slot(d, t) = y;
                 if (banded && t >= R - HR) halo[(t - (R - HR)) * HM + i] = y;
                 stg(w, i + (int64_t)nx * j, y);
-                fetch(i + PF, j, true, fv, rv, dv);
             }
+            fetch(row, i + PF, j, true, fv, rv, dv);
             __syncthreads();
         };
-        if (row)
-#pragma unroll
-            for (int b = 0; b < PF; ++b) fetch(b, j, true, fq[b], rq[b], dq[b]);
-        for (int d0 = 0; d0 < nd; d0 += PF) {
+        for (int d0 = -PF; d0 < nd; d0 += PF) {
 #pragma unroll
             for (int b = 0; b < PF; ++b) fwd(d0 + b, fq[b], rq[b], dq[b]);
         }
@@ -2073,7 +2084,6 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
         const bool row = t < R;
         const int nd = (nx - 1) + M * (R - 1) + 1;
         auto bwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
-            if (d >= nd) return;   // uniform
             const int i = d - M * t;
             if (row && i >= 0 && i < nx) {
                 double2 z = rv;
@@ -2089,14 +2099,12 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
                 slot(d, t) = z;
                 if (banded && t < HR) halo[t * HM + i] = z;
                 stg(w, i + (int64_t)nx * j, z);
-                fetch(i - PF, j, false, fv, rv, dv);
             }
+            fetch(row, i - PF, j, false, fv, rv, dv);
             __syncthreads();
         };
-        if (row)
-#pragma unroll
-            for (int b = 0; b < PF; ++b) fetch(nx - 1 - ((nx - 1 - b) % PF), j, false, fq[b], rq[b], dq[b]);
-        for (int d0 = (nd - 1) / PF * PF; d0 >= 0; d0 -= PF) {
+        // the first block (from nd rounded up to a multiple of PF) only loads
+        for (int d0 = (nd + PF - 1) / PF * PF; d0 >= 0; d0 -= PF) {
 #pragma unroll
             for (int b = PF - 1; b >= 0; --b) bwd(d0 + b, fq[b], rq[b], dq[b]);
         }

@@ -110,6 +110,34 @@ static size_t scratch_layout(const HostSetup &hs, bool fp32, size_t (*off)[2])
 // ---------------------------------------------------------------------------
 template <typename T> static TailTab tail_table(const LevelDev<T> *Lh, const HostSetup &hs, bool fp32);
 
+// a level's ILU(0) factors in the device layout of the up-leg kernels
+// (IluSet: point-major lower block, then the diagonal and upper entries of
+// each point), from the host's 25 planes of N points; the level's stencil is
+// the Galerkin one (the 25-point sets) when it has Galerkin entries
+static size_t ilu_device_count(const HostLevel &L)
+{
+    return L.gal.empty() ? (size_t)(IluSet<false>::NLO + IluSet<false>::UPW) * L.N
+                         : (size_t)(IluSet<true>::NLO + IluSet<true>::UPW) * L.N;
+}
+template <bool GAL> static void ilu_pack_set(const HostLevel &L, std::vector<double2> &out)
+{
+    using S = IluSet<GAL>;
+    const int64_t N = L.N;
+    for (int64_t p = 0; p < N; ++p) {
+        for (int k = 0; k < S::NLO; ++k) out[p * S::NLO + k] = L.ilu[S::lo(k) * N + p];
+        double2 *u = &out[S::NLO * N + p * S::UPW];
+        u[0] = L.ilu[12 * N + p];
+        for (int k = 0; k < S::NLO; ++k) u[1 + k] = L.ilu[S::up(k) * N + p];
+    }
+}
+static std::vector<double2> ilu_device_pack(const HostLevel &L)
+{
+    std::vector<double2> out(ilu_device_count(L), double2{0.0, 0.0});
+    if (L.gal.empty()) ilu_pack_set<false>(L, out);
+    else ilu_pack_set<true>(L, out);
+    return out;
+}
+
 hh_status grid_upload(hh_grid *g)
 {
     const HostSetup &hs = g->hs;
@@ -165,7 +193,7 @@ hh_status grid_upload(hh_grid *g)
             F.ilu = nullptr;
             F.w = nullptr;
             if (!L.ilu.empty()) {
-                D.ilu = c.take<double2>(L.ilu.size());
+                D.ilu = c.take<double2>(ilu_device_count(L));
                 D.w = c.take<double2>(L.N);
             } else {
                 D.ilu = nullptr;
@@ -220,7 +248,10 @@ hh_status grid_upload(hh_grid *g)
             HIPCHK(put64(g->L64h[l].g, L.gal.data(), sizeof(double2) * L.gal.size()));
             HIPCHK(put32c(g->L32h[l].g, L.gal));
         }
-        if (!L.ilu.empty()) HIPCHK(put64(g->L64h[l].ilu, L.ilu.data(), sizeof(double2) * L.ilu.size()));
+        if (!L.ilu.empty()) {
+            const std::vector<double2> pk = ilu_device_pack(L);
+            HIPCHK(put64(g->L64h[l].ilu, pk.data(), sizeof(double2) * pk.size()));
+        }
         std::vector<float> p32(L.N);
         for (int64_t i = 0; i < L.N; ++i) p32[i] = (float)L.phi[i];
         HIPCHK(put64(g->L32h[l].phi, p32.data(), sizeof(float) * L.N));
