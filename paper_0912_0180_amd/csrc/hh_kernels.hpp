@@ -1894,22 +1894,55 @@ __global__ __launch_bounds__(HH_ILU_PW) void k_ilu_update(Ctx cx, IluArgs a)
     if (p < a.fl.N) ilu_update_at(a, p);
 }
 
-// The entry sets of the triangular solves, and the device layout of a
-// level's factors (point-major, so that the entries one thread needs for a
-// point are adjacent): the lower entries of point p at p NLO + k, k in the
-// set's order, then from NLO N the diagonal of p at NLO N + p UPW and its
-// upper entries at NLO N + p UPW + 1 + k (UPW leaves the rest of 16 or 4
-// entries unused, so a point's upper block fills whole cache lines).
+// The entry sets of the triangular solves (NLO entries on each side of the
+// diagonal), the anti-diagonal step m, and the workgroup size NT of the row
+// form (k_ilu_up_rows) for the 25-point (Galerkin) and the 5-point stencils.
 template <bool GAL> struct IluSet;
 template <> struct IluSet<true> {
-    static constexpr int M = 3, NLO = 12, UPW = 16, RING = 9, HR = 2, HMAX = 2048, PF = 3;
+    static constexpr int M = 3, NLO = 12, NT = 512, RING = 9, HR = 2, HMAX = 2048, PF = 3;
     __host__ __device__ static constexpr int lo(int k) { return k; }          // s = 0 .. 11
     __host__ __device__ static constexpr int up(int k) { return 13 + k; }     // s = 13 .. 24
 };
 template <> struct IluSet<false> {
-    static constexpr int M = 1, NLO = 2, UPW = 4, RING = 2, HR = 1, HMAX = 4096, PF = 4;
+    static constexpr int M = 1, NLO = 2, NT = 1024, RING = 2, HR = 1, HMAX = 4096, PF = 4;
     __host__ __device__ static constexpr int lo(int k) { return k == 0 ? 7 : 11; }
     __host__ __device__ static constexpr int up(int k) { return k == 0 ? 13 : 17; }
+};
+
+// Device layout of a level's ILU(0) factors, in the order the row form reads
+// them.  The rows are split into nb bands of at most NT rows (sizes base or
+// base + 1, the first `extra` bands the larger); row t of band b is solved by
+// thread t, point (i, j0(b) + t) at the band's step d = i + m t, and the
+// bands' steps are numbered on from one band to the next (global step dd =
+// d0(b) + d).  The entries of one step are stored lane-contiguous: entry k
+// of thread t at (dd NLO + k) TS + t for the lower set, and the diagonal
+// (k = 0) and upper entries (k = 1 .. NLO) at (DT NLO + dd (NLO + 1) + k) TS
+// + t, where TS is the largest band rounded up to 64 lanes and DT the total
+// step count; positions without a point are zero.  A wave's loads of one
+// entry are then one contiguous 1 KB block.
+template <bool GAL> struct IluLayout {
+    using S = IluSet<GAL>;
+    int nx, ny, nb, base, extra, TS;
+    int64_t DT;
+    __host__ __device__ IluLayout(int nx_, int ny_) : nx(nx_), ny(ny_)
+    {
+        nb = (ny + S::NT - 1) / S::NT;
+        base = ny / nb;
+        extra = ny % nb;
+        TS = (base + (extra > 0 ? 1 : 0) + 63) / 64 * 64;
+        DT = (int64_t)nb * (nx - S::M) + (int64_t)S::M * ny;
+    }
+    __host__ __device__ int j0(int b) const { return b * base + (b < extra ? b : extra); }
+    __host__ __device__ int band_of(int j) const
+    {
+        const int c = extra * (base + 1);
+        return j < c ? j / (base + 1) : extra + (j - c) / base;
+    }
+    // steps of the bands before b: sum of (nx - 1) + m (R - 1) + 1
+    __host__ __device__ int64_t d0(int b) const { return (int64_t)b * (nx - S::M) + (int64_t)S::M * j0(b); }
+    __host__ __device__ int64_t lo(int64_t dd, int k, int t) const { return (dd * S::NLO + k) * TS + t; }
+    __host__ __device__ int64_t up(int64_t dd, int k, int t) const { return (DT * S::NLO + dd * (S::NLO + 1) + k) * TS + t; }
+    __host__ __device__ int64_t size() const { return DT * (2 * S::NLO + 1) * TS; }
 };
 
 __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
@@ -1930,22 +1963,38 @@ __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
     }
     const int m = gal ? 3 : 1;
     const int nd = (nx - 1) + m * (ny - 1) + 1;
-    const int64_t ub = (gal ? IluSet<true>::NLO : IluSet<false>::NLO) * N;
+    const IluLayout<true> lg(nx, ny);
+    const IluLayout<false> l5(nx, ny);
+    // the layout position (global step, thread) of point (i, j)
+    auto pos = [&](int i, int j, int64_t &dd, int &t) {
+        if (gal) {
+            const int b = lg.band_of(j);
+            t = j - lg.j0(b);
+            dd = lg.d0(b) + i + 3 * t;
+        } else {
+            const int b = l5.band_of(j);
+            t = j - l5.j0(b);
+            dd = l5.d0(b) + i + t;
+        }
+    };
     // forward: y = r - sum of l_s y_q over the neighbours below, columns ascending
     for (int d = 0; d < nd; ++d) {
         const int jlo = d - (nx - 1) > 0 ? (d - (nx - 1) + m - 1) / m : 0, jhi = min(ny - 1, d / m);
         for (int j = jlo + tid; j <= jhi; j += HH_ILU_WG) {
             const int i = d - m * j;
             const int64_t p = i + (int64_t)nx * j;
+            int64_t dd;
+            int t;
+            pos(i, j, dd, t);
             double2 y = ldg(w, p);
             if (gal) {
                 for (int s = 0; s < 12; ++s) {
                     const int ii = i + s % 5 - 2, jj = j + s / 5 - 2;
-                    if (ii >= 0 && ii < nx && jj >= 0) y = csub<double>(y, cmul<double>(ldg(F, p * 12 + s), ldg(w, ii + (int64_t)nx * jj)));
+                    if (ii >= 0 && ii < nx && jj >= 0) y = csub<double>(y, cmul<double>(ldg(F, lg.lo(dd, s, t)), ldg(w, ii + (int64_t)nx * jj)));
                 }
             } else {
-                if (j > 0) y = csub<double>(y, cmul<double>(ldg(F, p * 2), ldg(w, p - nx)));
-                if (i > 0) y = csub<double>(y, cmul<double>(ldg(F, p * 2 + 1), ldg(w, p - 1)));
+                if (j > 0) y = csub<double>(y, cmul<double>(ldg(F, l5.lo(dd, 0, t)), ldg(w, p - nx)));
+                if (i > 0) y = csub<double>(y, cmul<double>(ldg(F, l5.lo(dd, 1, t)), ldg(w, p - 1)));
             }
             stg(w, p, y);
         }
@@ -1957,19 +2006,20 @@ __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
         for (int j = jlo + tid; j <= jhi; j += HH_ILU_WG) {
             const int i = d - m * j;
             const int64_t p = i + (int64_t)nx * j;
+            int64_t dd;
+            int t;
+            pos(i, j, dd, t);
             double2 z = ldg(w, p);
             if (gal) {
-                const int64_t q = ub + p * IluSet<true>::UPW;
                 for (int s = 13; s < 25; ++s) {
                     const int ii = i + s % 5 - 2, jj = j + s / 5 - 2;
-                    if (ii >= 0 && ii < nx && jj < ny) z = csub<double>(z, cmul<double>(ldg(F, q + 1 + (s - 13)), ldg(w, ii + (int64_t)nx * jj)));
+                    if (ii >= 0 && ii < nx && jj < ny) z = csub<double>(z, cmul<double>(ldg(F, lg.up(dd, 1 + (s - 13), t)), ldg(w, ii + (int64_t)nx * jj)));
                 }
-                stg(w, p, cdiv<double>(z, ldg(F, q)));
+                stg(w, p, cdiv<double>(z, ldg(F, lg.up(dd, 0, t))));
             } else {
-                const int64_t q = ub + p * IluSet<false>::UPW;
-                if (i < nx - 1) z = csub<double>(z, cmul<double>(ldg(F, q + 1), ldg(w, p + 1)));
-                if (j < ny - 1) z = csub<double>(z, cmul<double>(ldg(F, q + 2), ldg(w, p + nx)));
-                stg(w, p, cdiv<double>(z, ldg(F, q)));
+                if (i < nx - 1) z = csub<double>(z, cmul<double>(ldg(F, l5.up(dd, 1, t)), ldg(w, p + 1)));
+                if (j < ny - 1) z = csub<double>(z, cmul<double>(ldg(F, l5.up(dd, 2, t)), ldg(w, p + nx)));
+                stg(w, p, cdiv<double>(z, ldg(F, l5.up(dd, 0, t))));
             }
         }
         __syncthreads();
@@ -2000,6 +2050,7 @@ template <bool GAL, int NT>
 __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
 {
     using S = IluSet<GAL>;
+    static_assert(NT == S::NT, "the factor layout's workgroup size");
     constexpr int M = S::M, NK = S::NLO, RG = S::RING, HR = S::HR, HM = S::HMAX;
     __shared__ double2 ring[RG * NT];
     __shared__ double2 halo[HR * HM];
@@ -2017,36 +2068,39 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
         for (int64_t p = t; p < N; p += NT) ilu_resid_at(a, p);
         __syncthreads();
     }
-    // nb bands of ny / nb or ny / nb + 1 rows; the halo is used (and nx <= HM
-    // holds) only when nb > 1
-    const int nb = (ny + NT - 1) / NT, base = ny / nb, extra = ny % nb;
+    // nb bands of ny / nb or ny / nb + 1 rows (the layout's); the halo is used
+    // (and nx <= HM holds) only when nb > 1
+    const IluLayout<GAL> lay(nx, ny);
+    const int nb = lay.nb;
     const bool banded = nb > 1;
-    auto band0 = [&](int bi) { return bi * base + min(bi, extra); };
+    auto band0 = [&](int bi) { return lay.j0(bi); };
     auto slot = [&](int d, int tt) -> double2 & { return ring[(d % RG) * NT + tt]; };
     // the factors and the right-hand side (and, backward, the diagonal) of
     // a thread's points are prefetched PF steps ahead into PF buffers with
     // fixed roles: step d uses buffer d mod PF, and refills it with the point
     // the thread solves at step d + PF.  Every thread loads on every step, a
     // thread without a point there (before its row's first point, after its
-    // last, or beyond the band) from point 0, so the same number of loads
-    // follows each refill on every path and the wait before a use is for
-    // that buffer's loads only, while idle lanes add one cache line per
-    // load; a factor of a neighbour outside the grid is loaded but never
-    // used.  The loops start PF steps early (loads only), so no buffer needs
-    // filling before them.
-    constexpr int PF = S::PF, NLO = S::NLO, UPW = S::UPW;
+    // last, or beyond the band) from point 0 and layout position 0, so the
+    // same number of loads follows each refill on every path and the wait
+    // before a use is for that buffer's loads only, while idle lanes add one
+    // cache line per load; the active lanes of a wave read lane-contiguous
+    // factors (IluLayout); a factor of a neighbour outside the grid is loaded
+    // but never used.  The loops start PF steps early (loads only), so no
+    // buffer needs filling before them.
+    constexpr int PF = S::PF;
     double2 fq[PF][NK], rq[PF], dq[PF];
-    auto fetch = [&](bool ok, int i, int j, bool lower, double2(&fv)[NK], double2 &rv, double2 &dv) {
-        const int64_t p = ok && i >= 0 && i < nx ? i + (int64_t)nx * j : 0;
+    auto fetch = [&](bool ok, int i, int j, int64_t dd, bool lower, double2(&fv)[NK], double2 &rv, double2 &dv) {
+        const bool in = ok && i >= 0 && i < nx;
+        const int64_t p = in ? i + (int64_t)nx * j : 0, dc = in ? dd : 0;
+        const int tc = in ? t : 0;
         rv = ldg(w, p);
         if (lower) {
 #pragma unroll
-            for (int k = 0; k < NK; ++k) fv[k] = ldg(F, p * NLO + k);
+            for (int k = 0; k < NK; ++k) fv[k] = ldg(F, lay.lo(dc, k, tc));
         } else {
-            const int64_t q = NLO * N + p * UPW;
-            dv = ldg(F, q);
+            dv = ldg(F, lay.up(dc, 0, tc));
 #pragma unroll
-            for (int k = 0; k < NK; ++k) fv[k] = ldg(F, q + 1 + k);
+            for (int k = 0; k < NK; ++k) fv[k] = ldg(F, lay.up(dc, 1 + k, tc));
         }
     };
     // forward: y = r - sum over the neighbours below, columns ascending
@@ -2054,6 +2108,7 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
         const int j0 = band0(bi), R = band0(bi + 1) - j0, j = j0 + t;
         const bool row = t < R;
         const int nd = (nx - 1) + M * (R - 1) + 1;
+        const int64_t D0 = lay.d0(bi);
         auto fwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
             const int i = d - M * t;
             if (row && i >= 0 && i < nx) {
@@ -2070,7 +2125,7 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
                 if (banded && t >= R - HR) halo[(t - (R - HR)) * HM + i] = y;
                 stg(w, i + (int64_t)nx * j, y);
             }
-            fetch(row, i + PF, j, true, fv, rv, dv);
+            fetch(row, i + PF, j, D0 + d + PF, true, fv, rv, dv);
             __syncthreads();
         };
         for (int d0 = -PF; d0 < nd; d0 += PF) {
@@ -2083,6 +2138,7 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
         const int j0 = band0(bi), R = band0(bi + 1) - j0, j = j0 + t;
         const bool row = t < R;
         const int nd = (nx - 1) + M * (R - 1) + 1;
+        const int64_t D0 = lay.d0(bi);
         auto bwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
             const int i = d - M * t;
             if (row && i >= 0 && i < nx) {
@@ -2100,7 +2156,7 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
                 if (banded && t < HR) halo[t * HM + i] = z;
                 stg(w, i + (int64_t)nx * j, z);
             }
-            fetch(row, i - PF, j, false, fv, rv, dv);
+            fetch(row, i - PF, j, D0 + d - PF, false, fv, rv, dv);
             __syncthreads();
         };
         // the first block (from nd rounded up to a multiple of PF) only loads

@@ -111,23 +111,29 @@ static size_t scratch_layout(const HostSetup &hs, bool fp32, size_t (*off)[2])
 template <typename T> static TailTab tail_table(const LevelDev<T> *Lh, const HostSetup &hs, bool fp32);
 
 // a level's ILU(0) factors in the device layout of the up-leg kernels
-// (IluSet: point-major lower block, then the diagonal and upper entries of
-// each point), from the host's 25 planes of N points; the level's stencil is
-// the Galerkin one (the 25-point sets) when it has Galerkin entries
+// (IluLayout: by band, step and entry, lane-contiguous), from the host's 25
+// planes of N points; the level's stencil is the Galerkin one (the 25-point
+// sets) when it has Galerkin entries
 static size_t ilu_device_count(const HostLevel &L)
 {
-    return L.gal.empty() ? (size_t)(IluSet<false>::NLO + IluSet<false>::UPW) * L.N
-                         : (size_t)(IluSet<true>::NLO + IluSet<true>::UPW) * L.N;
+    return L.gal.empty() ? (size_t)IluLayout<false>(L.n[0], L.n[1]).size()
+                         : (size_t)IluLayout<true>(L.n[0], L.n[1]).size();
 }
 template <bool GAL> static void ilu_pack_set(const HostLevel &L, std::vector<double2> &out)
 {
     using S = IluSet<GAL>;
+    const IluLayout<GAL> lay(L.n[0], L.n[1]);
+    const int nx = L.n[0];
     const int64_t N = L.N;
-    for (int64_t p = 0; p < N; ++p) {
-        for (int k = 0; k < S::NLO; ++k) out[p * S::NLO + k] = L.ilu[S::lo(k) * N + p];
-        double2 *u = &out[S::NLO * N + p * S::UPW];
-        u[0] = L.ilu[12 * N + p];
-        for (int k = 0; k < S::NLO; ++k) u[1 + k] = L.ilu[S::up(k) * N + p];
+    for (int b = 0; b < lay.nb; ++b) {
+        const int j0 = lay.j0(b), R = lay.j0(b + 1) - j0;
+        for (int t = 0; t < R; ++t)
+            for (int i = 0; i < nx; ++i) {
+                const int64_t p = i + (int64_t)nx * (j0 + t), dd = lay.d0(b) + i + S::M * t;
+                for (int k = 0; k < S::NLO; ++k) out[lay.lo(dd, k, t)] = L.ilu[S::lo(k) * N + p];
+                out[lay.up(dd, 0, t)] = L.ilu[12 * N + p];
+                for (int k = 0; k < S::NLO; ++k) out[lay.up(dd, 1 + k, t)] = L.ilu[S::up(k) * N + p];
+            }
     }
 }
 static std::vector<double2> ilu_device_pack(const HostLevel &L)
@@ -1165,10 +1171,10 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
                 // HH_ILU_GLOBAL: the global-memory form on every level
                 const bool rows = !getenv("HH_ILU_GLOBAL");
                 const int nx = a.fl.n[0], ny = a.fl.n[1];
-                if (rows && a.fl.g && (ny <= 512 || nx <= IluSet<true>::HMAX)) {
-                    hipLaunchKernelGGL((k_ilu_up_rows<true, 512>), dim3(1), dim3(512), 0, s, c, a);
-                } else if (rows && !a.fl.g && (ny <= HH_ILU_WG || nx <= IluSet<false>::HMAX)) {
-                    hipLaunchKernelGGL((k_ilu_up_rows<false, HH_ILU_WG>), dim3(1), dim3(HH_ILU_WG), 0, s, c, a);
+                if (rows && a.fl.g && (ny <= IluSet<true>::NT || nx <= IluSet<true>::HMAX)) {
+                    hipLaunchKernelGGL((k_ilu_up_rows<true, IluSet<true>::NT>), dim3(1), dim3(IluSet<true>::NT), 0, s, c, a);
+                } else if (rows && !a.fl.g && (ny <= IluSet<false>::NT || nx <= IluSet<false>::HMAX)) {
+                    hipLaunchKernelGGL((k_ilu_up_rows<false, IluSet<false>::NT>), dim3(1), dim3(IluSet<false>::NT), 0, s, c, a);
                 } else {
                     hipLaunchKernelGGL(k_ilu_up, dim3(1), dim3(HH_ILU_WG), 0, s, c, a);
                 }
