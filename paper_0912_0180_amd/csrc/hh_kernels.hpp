@@ -1814,6 +1814,8 @@ struct IluArgs {
     double omega;                     // relaxation of the ILU(0) update
     int inner;                        // 1: the sweep kernel runs the pointwise phases too;
                                       // 0: k_ilu_prolong, k_ilu_resid, k_ilu_update run them
+    int diag;                         // 1: w in the row form's step order (IluLayout position
+                                      // dd TS + t of each point); 0: w by point
 };
 
 // entry s (offset (s % 5 - 2, s / 5 - 2)) of row p of M_l applied to u, with
@@ -1842,56 +1844,6 @@ __device__ __forceinline__ double2 ilu_Mu(const LevelDev<double> &L, const doubl
     t = csub<double>(t, cmul<double>(ldg(L.a[1], j), j > 0 ? ldg(u, p - nx) : zero));
     t = csub<double>(t, cmul<double>(ldg(L.c[1], j), j < ny - 1 ? ldg(u, p + nx) : zero));
     return t;
-}
-
-// the pointwise phases of the up-leg at point p: u = 0 + P e_{l+1} (bilinear,
-// x then y; coarse values outside are zero), r = f - M u (into w, once every
-// u is written), and after the solves u = u + omega z
-__device__ __forceinline__ void ilu_prolong_at(const IluArgs &a, int64_t p)
-{
-    const int nx = a.fl.n[0], ncx = a.cl.n[0], ncy = a.cl.n[1];
-    const double2 *__restrict__ ec = a.cl.e;
-    const double2 zero = cmk<double>(0.0, 0.0);
-    const int i = (int)(p % nx), j = (int)(p / nx);
-    const int Ix = i >> 1, Iox = (i & 1) ? Ix + 1 : Ix - 1;
-    const int Iy = j >> 1, Ioy = (j & 1) ? Iy + 1 : Iy - 1;
-    auto ev = [&](int x, int y) -> double2 {
-        return (x >= 0 && x < ncx && y >= 0 && y < ncy) ? ldg(ec, x + (int64_t)ncx * y) : zero;
-    };
-    const double2 a0 = crs2<double>(0.75, ev(Ix, Iy), 0.25, ev(Iox, Iy));
-    const double2 a1 = crs2<double>(0.75, ev(Ix, Ioy), 0.25, ev(Iox, Ioy));
-    stg(a.u, p, cadd<double>(zero, crs2<double>(0.75, a0, 0.25, a1)));
-}
-__device__ __forceinline__ void ilu_resid_at(const IluArgs &a, int64_t p)
-{
-    const int nx = a.fl.n[0];
-    const int i = (int)(p % nx), j = (int)(p / nx);
-    stg(a.fl.w, p, csub<double>(ldg(a.f, p), ilu_Mu(a.fl, a.u, i, j, p)));
-}
-__device__ __forceinline__ void ilu_update_at(const IluArgs &a, int64_t p)
-{
-    stg(a.u, p, crsadd<double>(ldg(a.u, p), a.omega, ldg(a.fl.w, p)));
-}
-
-// the pointwise phases as grid-wide launches, for levels whose points are
-// too many for one workgroup's loops (same values: one point per thread)
-__global__ __launch_bounds__(HH_ILU_PW) void k_ilu_prolong(Ctx cx, IluArgs a)
-{
-    if (phase_of(cx, 0) != PH_RUN) return;
-    const int64_t p = blockIdx.x * (int64_t)HH_ILU_PW + threadIdx.x;
-    if (p < a.fl.N) ilu_prolong_at(a, p);
-}
-__global__ __launch_bounds__(HH_ILU_PW) void k_ilu_resid(Ctx cx, IluArgs a)
-{
-    if (phase_of(cx, 0) != PH_RUN) return;
-    const int64_t p = blockIdx.x * (int64_t)HH_ILU_PW + threadIdx.x;
-    if (p < a.fl.N) ilu_resid_at(a, p);
-}
-__global__ __launch_bounds__(HH_ILU_PW) void k_ilu_update(Ctx cx, IluArgs a)
-{
-    if (phase_of(cx, 0) != PH_RUN) return;
-    const int64_t p = blockIdx.x * (int64_t)HH_ILU_PW + threadIdx.x;
-    if (p < a.fl.N) ilu_update_at(a, p);
 }
 
 // The entry sets of the triangular solves (NLO entries on each side of the
@@ -1944,6 +1896,73 @@ template <bool GAL> struct IluLayout {
     __host__ __device__ int64_t up(int64_t dd, int k, int t) const { return (DT * S::NLO + dd * (S::NLO + 1) + k) * TS + t; }
     __host__ __device__ int64_t size() const { return DT * (2 * S::NLO + 1) * TS; }
 };
+
+// position of point p in w: p, or with the row form the point's layout
+// position (the level's set: the 25-point one on Galerkin levels)
+__device__ __forceinline__ int64_t ilu_wpos(const IluArgs &a, int64_t p)
+{
+    if (!a.diag) return p;
+    const int nx = a.fl.n[0], ny = a.fl.n[1];
+    const int i = (int)(p % nx), j = (int)(p / nx);
+    if (a.fl.g) {
+        const IluLayout<true> lay(nx, ny);
+        const int b = lay.band_of(j), t = j - lay.j0(b);
+        return (lay.d0(b) + i + 3 * t) * lay.TS + t;
+    }
+    const IluLayout<false> lay(nx, ny);
+    const int b = lay.band_of(j), t = j - lay.j0(b);
+    return (lay.d0(b) + i + t) * lay.TS + t;
+}
+
+// the pointwise phases of the up-leg at point p: u = 0 + P e_{l+1} (bilinear,
+// x then y; coarse values outside are zero), r = f - M u (into w, once every
+// u is written), and after the solves u = u + omega z
+__device__ __forceinline__ void ilu_prolong_at(const IluArgs &a, int64_t p)
+{
+    const int nx = a.fl.n[0], ncx = a.cl.n[0], ncy = a.cl.n[1];
+    const double2 *__restrict__ ec = a.cl.e;
+    const double2 zero = cmk<double>(0.0, 0.0);
+    const int i = (int)(p % nx), j = (int)(p / nx);
+    const int Ix = i >> 1, Iox = (i & 1) ? Ix + 1 : Ix - 1;
+    const int Iy = j >> 1, Ioy = (j & 1) ? Iy + 1 : Iy - 1;
+    auto ev = [&](int x, int y) -> double2 {
+        return (x >= 0 && x < ncx && y >= 0 && y < ncy) ? ldg(ec, x + (int64_t)ncx * y) : zero;
+    };
+    const double2 a0 = crs2<double>(0.75, ev(Ix, Iy), 0.25, ev(Iox, Iy));
+    const double2 a1 = crs2<double>(0.75, ev(Ix, Ioy), 0.25, ev(Iox, Ioy));
+    stg(a.u, p, cadd<double>(zero, crs2<double>(0.75, a0, 0.25, a1)));
+}
+__device__ __forceinline__ void ilu_resid_at(const IluArgs &a, int64_t p)
+{
+    const int nx = a.fl.n[0];
+    const int i = (int)(p % nx), j = (int)(p / nx);
+    stg(a.fl.w, ilu_wpos(a, p), csub<double>(ldg(a.f, p), ilu_Mu(a.fl, a.u, i, j, p)));
+}
+__device__ __forceinline__ void ilu_update_at(const IluArgs &a, int64_t p)
+{
+    stg(a.u, p, crsadd<double>(ldg(a.u, p), a.omega, ldg(a.fl.w, ilu_wpos(a, p))));
+}
+
+// the pointwise phases as grid-wide launches, for levels whose points are
+// too many for one workgroup's loops (same values: one point per thread)
+__global__ __launch_bounds__(HH_ILU_PW) void k_ilu_prolong(Ctx cx, IluArgs a)
+{
+    if (phase_of(cx, 0) != PH_RUN) return;
+    const int64_t p = blockIdx.x * (int64_t)HH_ILU_PW + threadIdx.x;
+    if (p < a.fl.N) ilu_prolong_at(a, p);
+}
+__global__ __launch_bounds__(HH_ILU_PW) void k_ilu_resid(Ctx cx, IluArgs a)
+{
+    if (phase_of(cx, 0) != PH_RUN) return;
+    const int64_t p = blockIdx.x * (int64_t)HH_ILU_PW + threadIdx.x;
+    if (p < a.fl.N) ilu_resid_at(a, p);
+}
+__global__ __launch_bounds__(HH_ILU_PW) void k_ilu_update(Ctx cx, IluArgs a)
+{
+    if (phase_of(cx, 0) != PH_RUN) return;
+    const int64_t p = blockIdx.x * (int64_t)HH_ILU_PW + threadIdx.x;
+    if (p < a.fl.N) ilu_update_at(a, p);
+}
 
 __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
 {
@@ -2052,8 +2071,9 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
     using S = IluSet<GAL>;
     static_assert(NT == S::NT, "the factor layout's workgroup size");
     constexpr int M = S::M, NK = S::NLO, RG = S::RING, HR = S::HR, HM = S::HMAX;
-    __shared__ double2 ring[RG * NT];
-    __shared__ double2 halo[HR * HM];
+    // the ring of the last RG diagonals (slot d mod RG, entry t), then the halo
+    __shared__ double2 lds[RG * NT + HR * HM];
+    constexpr int HB = RG * NT;
     if (phase_of(cx, 0) != PH_RUN) return;
     const LevelDev<double> L = a.fl;
     const int nx = L.n[0], ny = L.n[1];
@@ -2074,7 +2094,7 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
     const int nb = lay.nb;
     const bool banded = nb > 1;
     auto band0 = [&](int bi) { return lay.j0(bi); };
-    auto slot = [&](int d, int tt) -> double2 & { return ring[(d % RG) * NT + tt]; };
+    auto slot = [&](int d, int tt) -> int { return (d % RG) * NT + tt; };
     // the factors and the right-hand side (and, backward, the diagonal) of
     // a thread's points are prefetched PF steps ahead into PF buffers with
     // fixed roles: step d uses buffer d mod PF, and refills it with the point
@@ -2087,13 +2107,13 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
     // factors (IluLayout); a factor of a neighbour outside the grid is loaded
     // but never used.  The loops start PF steps early (loads only), so no
     // buffer needs filling before them.
-    constexpr int PF = S::PF;
+    constexpr int PF = S::PF, G = GAL ? 4 : 2;   // G divides NK
     double2 fq[PF][NK], rq[PF], dq[PF];
     auto fetch = [&](bool ok, int i, int j, int64_t dd, bool lower, double2(&fv)[NK], double2 &rv, double2 &dv) {
         const bool in = ok && i >= 0 && i < nx;
-        const int64_t p = in ? i + (int64_t)nx * j : 0, dc = in ? dd : 0;
+        const int64_t dc = in ? dd : 0;
         const int tc = in ? t : 0;
-        rv = ldg(w, p);
+        rv = ldg(w, dc * lay.TS + tc);
         if (lower) {
 #pragma unroll
             for (int k = 0; k < NK; ++k) fv[k] = ldg(F, lay.lo(dc, k, tc));
@@ -2112,18 +2132,33 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
         auto fwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
             const int i = d - M * t;
             if (row && i >= 0 && i < nx) {
+                // the neighbour values are read G at a time (a neighbour
+                // outside the grid reads entry 0), then their terms are taken
+                // in order; for a missing neighbour both factors are +0, and
+                // subtracting their product (+0, +0) leaves y as it is
                 double2 y = rv;
 #pragma unroll
-                for (int k = 0; k < NK; ++k) {
-                    const int sk = S::lo(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
-                    if (i + dx >= 0 && i + dx < nx && j + dy >= 0) {
-                        const double2 q = t + dy >= 0 ? slot(d + dx + M * dy, t + dy) : halo[(HR + t + dy) * HM + i + dx];
-                        y = csub<double>(y, cmul<double>(fv[k], q));
+                for (int g = 0; g < NK; g += G) {
+                    double2 q[G];
+                    bool in[G];
+                    int ix[G];
+#pragma unroll
+                    for (int k = g; k < g + G; ++k) {
+                        const int sk = S::lo(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
+                        in[k - g] = i + dx >= 0 && i + dx < nx && j + dy >= 0;
+                        const int ir = ((d + dx + M * dy + RG) % RG) * NT + t + dy;
+                        const int ih = HB + (HR + t + dy) * HM + i + dx;
+                        ix[k - g] = in[k - g] ? (dy >= 0 || t + dy >= 0 ? ir : ih) : 0;
                     }
+#pragma unroll
+                    for (int k = 0; k < G; ++k) q[k] = lds[ix[k]];
+#pragma unroll
+                    for (int k = g; k < g + G; ++k)
+                        y = csub<double>(y, cmul<double>(in[k - g] ? fv[k] : zero, in[k - g] ? q[k - g] : zero));
                 }
-                slot(d, t) = y;
-                if (banded && t >= R - HR) halo[(t - (R - HR)) * HM + i] = y;
-                stg(w, i + (int64_t)nx * j, y);
+                lds[slot(d, t)] = y;
+                if (banded && t >= R - HR) lds[HB + (t - (R - HR)) * HM + i] = y;
+                stg(w, (D0 + d) * lay.TS + t, y);
             }
             fetch(row, i + PF, j, D0 + d + PF, true, fv, rv, dv);
             __syncthreads();
@@ -2144,17 +2179,28 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
             if (row && i >= 0 && i < nx) {
                 double2 z = rv;
 #pragma unroll
-                for (int k = 0; k < NK; ++k) {
-                    const int sk = S::up(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
-                    if (i + dx >= 0 && i + dx < nx && j + dy < ny) {
-                        const double2 q = t + dy < R ? slot(d + dx + M * dy, t + dy) : halo[(t + dy - R) * HM + i + dx];
-                        z = csub<double>(z, cmul<double>(fv[k], q));
+                for (int g = 0; g < NK; g += G) {
+                    double2 q[G];
+                    bool in[G];
+                    int ix[G];
+#pragma unroll
+                    for (int k = g; k < g + G; ++k) {
+                        const int sk = S::up(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
+                        in[k - g] = i + dx >= 0 && i + dx < nx && j + dy < ny;
+                        const int ir = ((d + dx + M * dy) % RG) * NT + t + dy;
+                        const int ih = HB + (t + dy - R) * HM + i + dx;
+                        ix[k - g] = in[k - g] ? (dy <= 0 || t + dy < R ? ir : ih) : 0;
                     }
+#pragma unroll
+                    for (int k = 0; k < G; ++k) q[k] = lds[ix[k]];
+#pragma unroll
+                    for (int k = g; k < g + G; ++k)
+                        z = csub<double>(z, cmul<double>(in[k - g] ? fv[k] : zero, in[k - g] ? q[k - g] : zero));
                 }
                 z = cdiv<double>(z, dv);
-                slot(d, t) = z;
-                if (banded && t < HR) halo[t * HM + i] = z;
-                stg(w, i + (int64_t)nx * j, z);
+                lds[slot(d, t)] = z;
+                if (banded && t < HR) lds[HB + t * HM + i] = z;
+                stg(w, (D0 + d) * lay.TS + t, z);
             }
             fetch(row, i - PF, j, D0 + d - PF, false, fv, rv, dv);
             __syncthreads();

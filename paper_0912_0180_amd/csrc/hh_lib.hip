@@ -136,6 +136,13 @@ template <bool GAL> static void ilu_pack_set(const HostLevel &L, std::vector<dou
             }
     }
 }
+// the up-leg's work array: by point, or in the row form's step order
+static size_t ilu_w_count(const HostLevel &L)
+{
+    const size_t d = L.gal.empty() ? (size_t)(IluLayout<false>(L.n[0], L.n[1]).DT * IluLayout<false>(L.n[0], L.n[1]).TS)
+                                   : (size_t)(IluLayout<true>(L.n[0], L.n[1]).DT * IluLayout<true>(L.n[0], L.n[1]).TS);
+    return std::max((size_t)L.N, d);
+}
 static std::vector<double2> ilu_device_pack(const HostLevel &L)
 {
     std::vector<double2> out(ilu_device_count(L), double2{0.0, 0.0});
@@ -200,7 +207,7 @@ hh_status grid_upload(hh_grid *g)
             F.w = nullptr;
             if (!L.ilu.empty()) {
                 D.ilu = c.take<double2>(ilu_device_count(L));
-                D.w = c.take<double2>(L.N);
+                D.w = c.take<double2>(ilu_w_count(L));
             } else {
                 D.ilu = nullptr;
                 D.w = nullptr;
@@ -1157,6 +1164,17 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
                 a.f = l == 0 ? (const double2 *)fptr : lh.d[l].f;
                 a.u = l == 0 ? (double2 *)optr : lh.d[l].e;
                 a.omega = pl.omega1;
+                // the pipelined row form with the recent diagonals in LDS,
+                // in bands where a level has more rows than the workgroup
+                // threads (then its rows must fit the LDS halo), and w in its
+                // step order; HH_ILU_GLOBAL: the global-memory form on every
+                // level
+                const bool rows = !getenv("HH_ILU_GLOBAL");
+                const int nx = a.fl.n[0], ny = a.fl.n[1];
+                const int form = !rows ? 0
+                                 : a.fl.g ? (ny <= IluSet<true>::NT || nx <= IluSet<true>::HMAX ? 1 : 0)
+                                          : (ny <= IluSet<false>::NT || nx <= IluSet<false>::HMAX ? 2 : 0);
+                a.diag = form != 0;
                 // the pointwise phases of levels above HH_ILU_INNER_MAX points
                 // run grid-wide (HH_ILU_FUSED: inside the sweep kernel always)
                 a.inner = (a.fl.N <= HH_ILU_INNER_MAX || getenv("HH_ILU_FUSED")) ? 1 : 0;
@@ -1165,19 +1183,12 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
                     hipLaunchKernelGGL(k_ilu_prolong, pg, dim3(HH_ILU_PW), 0, s, c, a);
                     hipLaunchKernelGGL(k_ilu_resid, pg, dim3(HH_ILU_PW), 0, s, c, a);
                 }
-                // the pipelined row form with the recent diagonals in LDS,
-                // in bands where a level has more rows than the workgroup
-                // threads (then its rows must fit the LDS halo);
-                // HH_ILU_GLOBAL: the global-memory form on every level
-                const bool rows = !getenv("HH_ILU_GLOBAL");
-                const int nx = a.fl.n[0], ny = a.fl.n[1];
-                if (rows && a.fl.g && (ny <= IluSet<true>::NT || nx <= IluSet<true>::HMAX)) {
+                if (form == 1)
                     hipLaunchKernelGGL((k_ilu_up_rows<true, IluSet<true>::NT>), dim3(1), dim3(IluSet<true>::NT), 0, s, c, a);
-                } else if (rows && !a.fl.g && (ny <= IluSet<false>::NT || nx <= IluSet<false>::HMAX)) {
+                else if (form == 2)
                     hipLaunchKernelGGL((k_ilu_up_rows<false, IluSet<false>::NT>), dim3(1), dim3(IluSet<false>::NT), 0, s, c, a);
-                } else {
+                else
                     hipLaunchKernelGGL(k_ilu_up, dim3(1), dim3(HH_ILU_WG), 0, s, c, a);
-                }
                 if (!a.inner) hipLaunchKernelGGL(k_ilu_update, pg, dim3(HH_ILU_PW), 0, s, c, a);
             }
             return;
