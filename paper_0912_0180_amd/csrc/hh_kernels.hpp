@@ -1870,7 +1870,8 @@ template <> struct IluSet<false> {
 // of thread t at (dd NLO + k) TS + t for the lower set, and the diagonal
 // (k = 0) and upper entries (k = 1 .. NLO) at (DT NLO + dd (NLO + 1) + k) TS
 // + t, where TS is the largest band rounded up to 64 lanes and DT the total
-// step count; positions without a point are zero.  A wave's loads of one
+// step count; positions without a point, and the entries of a point's
+// neighbours outside the grid, are +0.  A wave's loads of one
 // entry are then one contiguous 1 KB block.
 template <bool GAL> struct IluLayout {
     using S = IluSet<GAL>;
@@ -2071,9 +2072,11 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
     using S = IluSet<GAL>;
     static_assert(NT == S::NT, "the factor layout's workgroup size");
     constexpr int M = S::M, NK = S::NLO, RG = S::RING, HR = S::HR, HM = S::HMAX;
-    // the ring of the last RG diagonals (slot d mod RG, entry t), then the halo
-    __shared__ double2 lds[RG * NT + HR * HM];
-    constexpr int HB = RG * NT;
+    // the ring of the last RG diagonals (slot d mod RG, entry t), then the
+    // halo, then one entry holding +0 (the value of a neighbour outside the
+    // grid)
+    __shared__ double2 lds[RG * NT + HR * HM + 1];
+    constexpr int HB = RG * NT, Z0 = RG * NT + HR * HM;
     if (phase_of(cx, 0) != PH_RUN) return;
     const LevelDev<double> L = a.fl;
     const int nx = L.n[0], ny = L.n[1];
@@ -2082,12 +2085,13 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
     double2 *w = L.w;
     const double2 zero = cmk<double>(0.0, 0.0);
     const int t = threadIdx.x;
+    if (t == 0) lds[Z0] = zero;
     if (a.inner) {
         for (int64_t p = t; p < N; p += NT) ilu_prolong_at(a, p);
         __syncthreads();
         for (int64_t p = t; p < N; p += NT) ilu_resid_at(a, p);
-        __syncthreads();
     }
+    __syncthreads();
     // nb bands of ny / nb or ny / nb + 1 rows (the layout's); the halo is used
     // (and nx <= HM holds) only when nb > 1
     const IluLayout<GAL> lay(nx, ny);
@@ -2132,10 +2136,11 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
         auto fwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
             const int i = d - M * t;
             if (row && i >= 0 && i < nx) {
-                // the neighbour values are read G at a time (a neighbour
-                // outside the grid reads entry 0), then their terms are taken
-                // in order; for a missing neighbour both factors are +0, and
-                // subtracting their product (+0, +0) leaves y as it is
+                // the neighbour values are read G at a time, then their terms
+                // are taken in order; for a neighbour outside the grid both
+                // factors are +0 (the layout stores its entry as +0, and it
+                // reads the +0 entry of LDS), and subtracting their product
+                // (+0, +0) leaves y as it is
                 double2 y = rv;
 #pragma unroll
                 for (int g = 0; g < NK; g += G) {
@@ -2148,13 +2153,12 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
                         in[k - g] = i + dx >= 0 && i + dx < nx && j + dy >= 0;
                         const int ir = ((d + dx + M * dy + RG) % RG) * NT + t + dy;
                         const int ih = HB + (HR + t + dy) * HM + i + dx;
-                        ix[k - g] = in[k - g] ? (dy >= 0 || t + dy >= 0 ? ir : ih) : 0;
+                        ix[k - g] = in[k - g] ? (dy >= 0 || t + dy >= 0 ? ir : ih) : Z0;
                     }
 #pragma unroll
                     for (int k = 0; k < G; ++k) q[k] = lds[ix[k]];
 #pragma unroll
-                    for (int k = g; k < g + G; ++k)
-                        y = csub<double>(y, cmul<double>(in[k - g] ? fv[k] : zero, in[k - g] ? q[k - g] : zero));
+                    for (int k = g; k < g + G; ++k) y = csub<double>(y, cmul<double>(fv[k], q[k - g]));
                 }
                 lds[slot(d, t)] = y;
                 if (banded && t >= R - HR) lds[HB + (t - (R - HR)) * HM + i] = y;
@@ -2189,13 +2193,12 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
                         in[k - g] = i + dx >= 0 && i + dx < nx && j + dy < ny;
                         const int ir = ((d + dx + M * dy) % RG) * NT + t + dy;
                         const int ih = HB + (t + dy - R) * HM + i + dx;
-                        ix[k - g] = in[k - g] ? (dy <= 0 || t + dy < R ? ir : ih) : 0;
+                        ix[k - g] = in[k - g] ? (dy <= 0 || t + dy < R ? ir : ih) : Z0;
                     }
 #pragma unroll
                     for (int k = 0; k < G; ++k) q[k] = lds[ix[k]];
 #pragma unroll
-                    for (int k = g; k < g + G; ++k)
-                        z = csub<double>(z, cmul<double>(in[k - g] ? fv[k] : zero, in[k - g] ? q[k - g] : zero));
+                    for (int k = g; k < g + G; ++k) z = csub<double>(z, cmul<double>(fv[k], q[k - g]));
                 }
                 z = cdiv<double>(z, dv);
                 lds[slot(d, t)] = z;

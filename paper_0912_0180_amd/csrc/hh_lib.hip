@@ -129,10 +129,17 @@ template <bool GAL> static void ilu_pack_set(const HostLevel &L, std::vector<dou
         const int j0 = lay.j0(b), R = lay.j0(b + 1) - j0;
         for (int t = 0; t < R; ++t)
             for (int i = 0; i < nx; ++i) {
-                const int64_t p = i + (int64_t)nx * (j0 + t), dd = lay.d0(b) + i + S::M * t;
-                for (int k = 0; k < S::NLO; ++k) out[lay.lo(dd, k, t)] = L.ilu[S::lo(k) * N + p];
+                const int j = j0 + t;
+                const int64_t p = i + (int64_t)nx * j, dd = lay.d0(b) + i + S::M * t;
+                // the entry of a neighbour outside the grid is +0 exactly: the
+                // kernels multiply it by a +0 neighbour value
+                auto entry = [&](int sk) {
+                    const int ii = i + sk % 5 - 2, jj = j + sk / 5 - 2;
+                    return ii >= 0 && ii < nx && jj >= 0 && jj < L.n[1] ? L.ilu[sk * N + p] : double2{0.0, 0.0};
+                };
+                for (int k = 0; k < S::NLO; ++k) out[lay.lo(dd, k, t)] = entry(S::lo(k));
                 out[lay.up(dd, 0, t)] = L.ilu[12 * N + p];
-                for (int k = 0; k < S::NLO; ++k) out[lay.up(dd, 1 + k, t)] = L.ilu[S::up(k) * N + p];
+                for (int k = 0; k < S::NLO; ++k) out[lay.up(dd, 1 + k, t)] = entry(S::up(k));
             }
     }
 }
