@@ -900,6 +900,27 @@ def legs_probe(torch, hh, W):
         g.close()
 
 
+def ilu_probe(torch, hh, W):
+    """Launches for a kernel trace of the paper's multigrid: 5 FP64 ILU(0)
+    V(0,1) cycles on Galerkin operators for Table MP1's problem with ECS layers
+    (384^2) and Table MP3's (r = 90, k = 2) with ECS layers (1280^2) and with
+    the Sommerfeld condition (1024^2), each printing its mean cycle time."""
+    PI = np.pi
+    cases = (("mp1_k160_ecs", lambda: W.mp1(layers=True)),
+             ("mp3_r90_k2_ecs", lambda: W.mp3(r=90.0, k=2.0, theta_csg=PI / 17)),
+             ("mp3_r90_k2_sommerfeld", lambda: W.mp3(r=90.0, k=2.0, n_lay=0, bc="sommerfeld", theta_csg=-PI / 17)))
+    for name, mk in cases:
+        c = mk()
+        d = dict(c["desc"])
+        d.update(smoother=1, coarse_op=1, nu1=0, omega=1.0)
+        g = hh.Grid(d, c["phi"])
+        b = torch.from_numpy(c["b"]).to("cuda")
+        u = torch.empty_like(b)
+        ms = time_calls(torch, lambda: g.vcycle(b, "c128", out=u), 5) * 1e3
+        print("ilu probe %s: %dx%d, %d levels, V-cycle %.2f ms" % (name, d["n"][0], d["n"][1], g.levels, ms), flush=True)
+        g.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -929,6 +950,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline solve only")
     ap.add_argument("--pmc-probe", action="store_true", help="only the launches the counter runs read")
     ap.add_argument("--legs-probe", action="store_true", help="only the V-cycle leg launches of the SQ counter runs")
+    ap.add_argument("--ilu-probe", action="store_true", help="only ILU(0) V-cycles of Tables MP1 and MP3 (kernel trace)")
     ap.add_argument("--roofline-n", type=int, default=ROOFLINE_N, help="side of the HBM-resident roofline grid")
     ap.add_argument("--roofline-only", action="store_true", help="only the roofline measurement")
     args = ap.parse_args()
@@ -947,6 +969,9 @@ def main():
         return
     if args.legs_probe:
         legs_probe(torch, hh, W)
+        return
+    if args.ilu_probe:
+        ilu_probe(torch, hh, W)
         return
     out = {}
     if args.roofline_only:

@@ -1806,7 +1806,7 @@ __global__ __launch_bounds__(GAL_NT) void k_gup(Ctx cx, GalArgs<T> ga)
 // workgroup: in one workgroup they would take N / 1024 dependent load
 // round trips per thread
 #define HH_ILU_PW 256
-#define HH_ILU_INNER_MAX (int64_t(16) << 10)
+#define HH_ILU_INNER_MAX (int64_t(1) << 10)
 struct IluArgs {
     LevelDev<double> fl, cl;          // level l and the coarser level l + 1
     const double2 *f;                 // right-hand side of level l (the cycle's input on level 0)
@@ -2070,7 +2070,9 @@ template <bool GAL, int NT>
 __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
 {
     using S = IluSet<GAL>;
-    static_assert(NT == S::NT, "the factor layout's workgroup size");
+    // NT below the layout's S::NT serves levels of at most NT rows (one band,
+    // whose layout does not depend on the workgroup size)
+    static_assert(NT <= S::NT && NT % 64 == 0, "the factor layout's workgroup size");
     constexpr int M = S::M, NK = S::NLO, RG = S::RING, HR = S::HR, HM = S::HMAX;
     // the ring of the last RG diagonals (slot d mod RG, entry t), then the
     // halo, then one entry holding +0 (the value of a neighbour outside the

@@ -1182,15 +1182,24 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
                                  : a.fl.g ? (ny <= IluSet<true>::NT || nx <= IluSet<true>::HMAX ? 1 : 0)
                                           : (ny <= IluSet<false>::NT || nx <= IluSet<false>::HMAX ? 2 : 0);
                 a.diag = form != 0;
-                // the pointwise phases of levels above HH_ILU_INNER_MAX points
-                // run grid-wide (HH_ILU_FUSED: inside the sweep kernel always)
-                a.inner = (a.fl.N <= HH_ILU_INNER_MAX || getenv("HH_ILU_FUSED")) ? 1 : 0;
+                // levels of few rows take a workgroup of as few waves (the same
+                // layout: one band either way)
+                const int wg = form == 1 ? (ny <= 64 ? 64 : ny <= 128 ? 128 : IluSet<true>::NT)
+                                         : form == 2 ? IluSet<false>::NT : HH_ILU_WG;
+                // the pointwise phases run grid-wide except on levels of at
+                // most HH_ILU_INNER_MAX points in a full-size workgroup
+                // (HH_ILU_FUSED: inside the solve kernel always)
+                a.inner = ((a.fl.N <= HH_ILU_INNER_MAX && wg >= 512) || getenv("HH_ILU_FUSED")) ? 1 : 0;
                 const dim3 pg((unsigned)((a.fl.N + HH_ILU_PW - 1) / HH_ILU_PW));
                 if (!a.inner) {
                     hipLaunchKernelGGL(k_ilu_prolong, pg, dim3(HH_ILU_PW), 0, s, c, a);
                     hipLaunchKernelGGL(k_ilu_resid, pg, dim3(HH_ILU_PW), 0, s, c, a);
                 }
-                if (form == 1)
+                if (form == 1 && wg == 64)
+                    hipLaunchKernelGGL((k_ilu_up_rows<true, 64>), dim3(1), dim3(64), 0, s, c, a);
+                else if (form == 1 && wg == 128)
+                    hipLaunchKernelGGL((k_ilu_up_rows<true, 128>), dim3(1), dim3(128), 0, s, c, a);
+                else if (form == 1)
                     hipLaunchKernelGGL((k_ilu_up_rows<true, IluSet<true>::NT>), dim3(1), dim3(IluSet<true>::NT), 0, s, c, a);
                 else if (form == 2)
                     hipLaunchKernelGGL((k_ilu_up_rows<false, IluSet<false>::NT>), dim3(1), dim3(IluSet<false>::NT), 0, s, c, a);

@@ -65,8 +65,8 @@ def tall(coarse_op):
     """48 x 2096 cells, 5 levels: more rows than the row form's workgroup on
     the levels 0 (3 bands of 699, 699, 698 rows), 1 (3 Galerkin bands of 350,
     349, 349, or 2 rediscretised ones of 524) and 2 (2 Galerkin bands of 262);
-    the pointwise phases of levels 0 and 1 run grid-wide, those of level 2 in
-    the sweep kernel."""
+    the pointwise phases of every smoothing level run grid-wide (the c1 cases
+    and HH_ILU_FUSED cover them inside the solve kernel)."""
     h = 1.0 / 64
     n = (48, 2096)
     hi = (-0.2 + n[0] * h, -0.3 + n[1] * h)
