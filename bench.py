@@ -552,6 +552,8 @@ PAPER_MP23 = {
     "mp2_nu1_k4_sommerfeld": {"csg_angle": "-pi/27", "mg": [0.51, 21], "bicgstab": 161, "idr4": 164, "idr8": 161},
     "mp3_r90_k2_ecs": {"csg_angle": "pi/17", "mg": [0.27, 11], "bicgstab": 139, "idr4": 139, "idr8": 134},
     "mp3_r90_k2_sommerfeld": {"csg_angle": "-pi/17", "mg": [0.41, 16], "bicgstab": 205, "idr4": 207, "idr8": 207},
+    "mp3_r150_k4_ecs": {"csg_angle": "pi/17", "mg": [0.31, 13], "bicgstab": 390, "idr4": 387, "idr8": 392},
+    "mp3_r150_k4_sommerfeld": {"csg_angle": "-pi/17", "mg": [0.37, 15], "bicgstab": 620, "idr4": 650, "idr8": 652},
 }
 
 
@@ -562,11 +564,11 @@ def bench_paper_tables(args, torch, hh, W):
     layers on 256 + 2 x 64 cells, CSG pi/28 or the CSL with the printed shift
     -1 - 0.2i; the Sommerfeld condition on 256^2, CSG -pi/28 or CSL
     -1 + 0.2i); MP2 (384 + 128 cells, nu = 7, k = 2 and nu = 1, k = 4) and MP3
-    (r = 90, k = 2, 1024 + 256 cells) with the tables' CSG angles, layers on
-    the north and east edges or the Sommerfeld condition there.  Per row: the
-    multigrid alone as a solver of the preconditioner problem, the ILU(0)
-    V-cycle's time, and Bi-CGSTAB, IDR(4), IDR(8) (MP3: Bi-CGSTAB, one timed
-    solve; its 1280^2 levels exceed the row kernel's 1024 rows)."""
+    (r = 90, k = 2, 1024 + 256 cells; r = 150, k = 4, 2048 + 512 cells) with
+    the tables' CSG angles, layers on the north and east edges or the
+    Sommerfeld condition there.  Per row: the multigrid alone as a solver of
+    the preconditioner problem, the ILU(0) V-cycle's time, and Bi-CGSTAB,
+    IDR(4), IDR(8) (MP3: Bi-CGSTAB, one timed solve)."""
     PI = np.pi
     rows = []
     for bc in ("ecs", "sommerfeld", "ecs_csl", "sommerfeld_csl"):
@@ -585,7 +587,9 @@ def bench_paper_tables(args, torch, hh, W):
           ("mp2_nu1_k4_ecs", lambda: W.mp2(nu=1.0, k=4.0, theta_csg=PI / 26)),
           ("mp2_nu1_k4_sommerfeld", lambda: W.mp2(nu=1.0, k=4.0, n_lay=0, bc="sommerfeld", theta_csg=-PI / 27)),
           ("mp3_r90_k2_ecs", lambda: W.mp3(r=90.0, k=2.0, theta_csg=PI / 17)),
-          ("mp3_r90_k2_sommerfeld", lambda: W.mp3(r=90.0, k=2.0, n_lay=0, bc="sommerfeld", theta_csg=-PI / 17))]
+          ("mp3_r90_k2_sommerfeld", lambda: W.mp3(r=90.0, k=2.0, n_lay=0, bc="sommerfeld", theta_csg=-PI / 17)),
+          ("mp3_r150_k4_ecs", lambda: W.mp3(r=150.0, k=4.0, n_int=2048, n_lay=512, theta_csg=PI / 17)),
+          ("mp3_r150_k4_sommerfeld", lambda: W.mp3(r=150.0, k=4.0, n_int=2048, n_lay=0, bc="sommerfeld", theta_csg=-PI / 17))]
     for name, mk in mp:
         def mk2(mk=mk):
             c = mk()
