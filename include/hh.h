@@ -101,7 +101,10 @@ typedef enum { HH_COARSE_REDISCRETISED = 0, HH_COARSE_GALERKIN = 1 } hh_coarse_o
  * (batches of more than one problem, hh_submit and hh_profile_vcycle reject
  * it).  Its triangular solves are sequential along anti-diagonals, so a
  * cycle costs about (n_x + n_y) dependent steps per level (rediscretised)
- * or (n_x + 3 n_y) (Galerkin). */
+ * or (n_x + 3 n_y) (Galerkin), plus n_x for each further band of rows
+ * where a level has more than 1024 (5-point) or 512 (Galerkin) rows.  The
+ * device copy of the factors is stored in the solves' step order, padded
+ * to whole waves (up to about 2.5 times the 25 N_level entries). */
 typedef enum { HH_SMOOTH_JACOBI = 0, HH_SMOOTH_ILU0 = 1 } hh_smoother;
 
 /* Grid description (host memory, read during hh_setup_grid only). */
