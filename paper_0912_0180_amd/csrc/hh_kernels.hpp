@@ -1862,16 +1862,18 @@ template <> struct IluSet<false> {
 };
 
 // Device layout of a level's ILU(0) factors, in the order the row form reads
-// them.  The rows are split into nb bands of at most NT rows (sizes base or
-// base + 1, the first `extra` bands the larger); row t of band b is solved by
-// thread t, point (i, j0(b) + t) at the band's step d = i + m t, and the
-// bands' steps are numbered on from one band to the next (global step dd =
-// d0(b) + d).  The entries of one step are stored lane-contiguous: entry k
-// of thread t at (dd NLO + k) TS + t for the lower set, and the diagonal
-// (k = 0) and upper entries (k = 1 .. NLO) at (DT NLO + dd (NLO + 1) + k) TS
-// + t, where TS is the largest band rounded up to 64 lanes and DT the total
-// step count; positions without a point, and the entries of a point's
-// neighbours outside the grid, are +0.  A wave's loads of one
+// them.  Where nx <= m NT all rows form one band, thread t solving rows t,
+// t + NT, ... (a row ends before the one NT below it starts); otherwise the
+// rows are split into nb bands of at most NT rows (sizes base or base + 1,
+// the first `extra` bands the larger).  Row offset r of band b is solved by
+// thread lane(r) = r mod NT, point (i, j0(b) + r) at the band's step d = i +
+// m r, and the bands' steps are numbered on from one band to the next
+// (global step dd = d0(b) + d).  The entries of one step are stored
+// lane-contiguous: entry k of lane t at (dd NLO + k) TS + t for the lower
+// set, and the diagonal (k = 0) and upper entries (k = 1 .. NLO) at (DT NLO
+// + dd (NLO + 1) + k) TS + t, where TS is the largest band rounded up to 64
+// lanes (at most NT) and DT the total step count; positions without a point,
+// and the entries of a point's neighbours outside the grid, are +0.  A wave's loads of one
 // entry are then one contiguous 1 KB block.
 template <bool GAL> struct IluLayout {
     using S = IluSet<GAL>;
@@ -1879,12 +1881,17 @@ template <bool GAL> struct IluLayout {
     int64_t DT;
     __host__ __device__ IluLayout(int nx_, int ny_) : nx(nx_), ny(ny_)
     {
-        nb = (ny + S::NT - 1) / S::NT;
+        // one band when a thread finishes a row before the row NT below it
+        // starts (nx <= m NT): thread t then owns rows t, t + NT, ...
+        nb = nx <= S::M * S::NT ? 1 : (ny + S::NT - 1) / S::NT;
         base = ny / nb;
         extra = ny % nb;
-        TS = (base + (extra > 0 ? 1 : 0) + 63) / 64 * 64;
+        const int rmax = base + (extra > 0 ? 1 : 0);
+        TS = rmax > S::NT ? S::NT : (rmax + 63) / 64 * 64;
         DT = (int64_t)nb * (nx - S::M) + (int64_t)S::M * ny;
     }
+    // lane of row offset r within its band
+    __host__ __device__ static int lane(int r) { return r % S::NT; }
     __host__ __device__ int j0(int b) const { return b * base + (b < extra ? b : extra); }
     __host__ __device__ int band_of(int j) const
     {
@@ -1907,12 +1914,12 @@ __device__ __forceinline__ int64_t ilu_wpos(const IluArgs &a, int64_t p)
     const int i = (int)(p % nx), j = (int)(p / nx);
     if (a.fl.g) {
         const IluLayout<true> lay(nx, ny);
-        const int b = lay.band_of(j), t = j - lay.j0(b);
-        return (lay.d0(b) + i + 3 * t) * lay.TS + t;
+        const int b = lay.band_of(j), r = j - lay.j0(b);
+        return (lay.d0(b) + i + 3 * r) * lay.TS + lay.lane(r);
     }
     const IluLayout<false> lay(nx, ny);
-    const int b = lay.band_of(j), t = j - lay.j0(b);
-    return (lay.d0(b) + i + t) * lay.TS + t;
+    const int b = lay.band_of(j), r = j - lay.j0(b);
+    return (lay.d0(b) + i + r) * lay.TS + lay.lane(r);
 }
 
 // the pointwise phases of the up-leg at point p: u = 0 + P e_{l+1} (bilinear,
@@ -1988,13 +1995,13 @@ __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
     // the layout position (global step, thread) of point (i, j)
     auto pos = [&](int i, int j, int64_t &dd, int &t) {
         if (gal) {
-            const int b = lg.band_of(j);
-            t = j - lg.j0(b);
-            dd = lg.d0(b) + i + 3 * t;
+            const int b = lg.band_of(j), r = j - lg.j0(b);
+            t = lg.lane(r);
+            dd = lg.d0(b) + i + 3 * r;
         } else {
-            const int b = l5.band_of(j);
-            t = j - l5.j0(b);
-            dd = l5.d0(b) + i + t;
+            const int b = l5.band_of(j), r = j - l5.j0(b);
+            t = l5.lane(r);
+            dd = l5.d0(b) + i + r;
         }
     };
     // forward: y = r - sum of l_s y_q over the neighbours below, columns ascending
@@ -2048,17 +2055,21 @@ __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
         for (int64_t p = tid; p < N; p += HH_ILU_WG) ilu_update_at(a, p);
 }
 
-// The same up-leg with the triangular solves in the pipelined row form, in
-// bands of at most NT rows (NT = 1024 for the 5-point set; 512 for the
-// 25-point one, whose 2 x 12 factors in flight need the registers of a
-// 512-thread workgroup).  Within a band, thread t owns row j0 + t, and on the
-// band's anti-diagonal d it solves point (d - m t, j0 + t), so its points
-// come left to right (right to left in the backward solve) one step after
-// another.  The values of the last RING diagonals sit in LDS (slot d mod
-// RING, entry t): the neighbours below a point lie on the 8 diagonals before
-// it (m = 3) or the one before (m = 1), and those above on as many after it,
-// so no neighbour value is read from global memory, and a slot is rewritten
-// only after every read of its previous diagonal.  Bands run one after
+// The same up-leg with the triangular solves in the pipelined row form
+// (NT = 1024 threads for the 5-point set; 512 for the 25-point one, whose
+// 2 x 12 factors in flight need the registers of a 512-thread workgroup).
+// Thread t owns row t, and on anti-diagonal d it solves point (d - m t, t),
+// so its points come left to right (right to left in the backward solve) one
+// step after another.  A level of more rows than threads runs as one pass
+// with thread t owning rows t, t + NT, ... where a row ends before the row NT
+// below it starts (nx <= m NT), and otherwise in bands of at most NT rows.
+// The values of the last RING diagonals sit in LDS (slot d mod RING, entry
+// lane t of the thread that solved the point): the neighbours below a point
+// lie on the 8 diagonals before it (m = 3) or the one before (m = 1), in the
+// same or the two lanes before (wrapping from lane 0 to NT - 1 in the one
+// pass), and those above on as many after it, so no neighbour value is read
+// from global memory, and a slot is rewritten only after every read of its
+// previous diagonal.  Bands run one after
 // another (bottom up forward, top down backward); the rows a band reads from
 // the band before it (two with m = 3, one with m = 1) are kept in an LDS halo
 // by column, each entry rewritten by the band's own boundary rows only after
@@ -2066,13 +2077,14 @@ __global__ __launch_bounds__(HH_ILU_WG) void k_ilu_up(Ctx cx, IluArgs a)
 // right-hand side of a thread's points are loaded PF steps before they are
 // needed (3 with m = 3, 4 with m = 1), behind the barriers of the steps in
 // between.  Values and operation order are k_ilu_up's.
-template <bool GAL, int NT>
+template <bool GAL, int NT, bool MULTI>
 __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
 {
     using S = IluSet<GAL>;
     // NT below the layout's S::NT serves levels of at most NT rows (one band,
-    // whose layout does not depend on the workgroup size)
-    static_assert(NT <= S::NT && NT % 64 == 0, "the factor layout's workgroup size");
+    // whose layout does not depend on the workgroup size); MULTI (one band of
+    // more rows than threads) needs the layout's NT
+    static_assert(NT <= S::NT && NT % 64 == 0 && (!MULTI || NT == S::NT), "the factor layout's workgroup size");
     constexpr int M = S::M, NK = S::NLO, RG = S::RING, HR = S::HR, HM = S::HMAX;
     // the ring of the last RG diagonals (slot d mod RG, entry t), then the
     // halo, then one entry holding +0 (the value of a neighbour outside the
@@ -2115,10 +2127,9 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
     // buffer needs filling before them.
     constexpr int PF = S::PF, G = GAL ? 4 : 2;   // G divides NK
     double2 fq[PF][NK], rq[PF], dq[PF];
-    auto fetch = [&](bool ok, int i, int j, int64_t dd, bool lower, double2(&fv)[NK], double2 &rv, double2 &dv) {
-        const bool in = ok && i >= 0 && i < nx;
-        const int64_t dc = in ? dd : 0;
-        const int tc = in ? t : 0;
+    auto fetch = [&](bool act, int64_t dd, bool lower, double2(&fv)[NK], double2 &rv, double2 &dv) {
+        const int64_t dc = act ? dd : 0;
+        const int tc = act ? t : 0;
         rv = ldg(w, dc * lay.TS + tc);
         if (lower) {
 #pragma unroll
@@ -2131,13 +2142,23 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
     };
     // forward: y = r - sum over the neighbours below, columns ascending
     for (int bi = 0; bi < nb; ++bi) {
-        const int j0 = band0(bi), R = band0(bi + 1) - j0, j = j0 + t;
-        const bool row = t < R;
+        const int j0 = band0(bi), R = band0(bi + 1) - j0;
         const int nd = (nx - 1) + M * (R - 1) + 1;
         const int64_t D0 = lay.d0(bi);
+        // the row offset r and column i the thread solves at step d: row t,
+        // or with more rows than threads (MULTI: one band, nx <= M NT) the
+        // row t + k NT whose steps contain d
+        auto locate = [&](int d, int &r, int &i) -> bool {
+            const int q = d - M * t;
+            const int k = MULTI && q >= 0 ? q / (M * NT) : 0;
+            r = t + k * NT;
+            i = q - k * (M * NT);
+            return r < R && i >= 0 && i < nx;
+        };
         auto fwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
-            const int i = d - M * t;
-            if (row && i >= 0 && i < nx) {
+            int r, i;
+            if (locate(d, r, i)) {
+                const int j = j0 + r;
                 // the neighbour values are read G at a time, then their terms
                 // are taken in order; for a neighbour outside the grid both
                 // factors are +0 (the layout stores its entry as +0, and it
@@ -2153,9 +2174,9 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
                     for (int k = g; k < g + G; ++k) {
                         const int sk = S::lo(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
                         in[k - g] = i + dx >= 0 && i + dx < nx && j + dy >= 0;
-                        const int ir = ((d + dx + M * dy + RG) % RG) * NT + t + dy;
-                        const int ih = HB + (HR + t + dy) * HM + i + dx;
-                        ix[k - g] = in[k - g] ? (dy >= 0 || t + dy >= 0 ? ir : ih) : Z0;
+                        const int ir = ((d + dx + M * dy + RG) % RG) * NT + (MULTI ? (t + dy + NT) % NT : t + dy);
+                        const int ih = HB + (HR + r + dy) * HM + i + dx;
+                        ix[k - g] = in[k - g] ? (dy >= 0 || r + dy >= 0 ? ir : ih) : Z0;
                     }
 #pragma unroll
                     for (int k = 0; k < G; ++k) q[k] = lds[ix[k]];
@@ -2163,10 +2184,12 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
                     for (int k = g; k < g + G; ++k) y = csub<double>(y, cmul<double>(fv[k], q[k - g]));
                 }
                 lds[slot(d, t)] = y;
-                if (banded && t >= R - HR) lds[HB + (t - (R - HR)) * HM + i] = y;
+                if (banded && r >= R - HR) lds[HB + (r - (R - HR)) * HM + i] = y;
                 stg(w, (D0 + d) * lay.TS + t, y);
             }
-            fetch(row, i + PF, j, D0 + d + PF, true, fv, rv, dv);
+            int rn, in_;
+            const bool an = locate(d + PF, rn, in_);
+            fetch(an, D0 + d + PF, true, fv, rv, dv);
             __syncthreads();
         };
         for (int d0 = -PF; d0 < nd; d0 += PF) {
@@ -2176,13 +2199,20 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
     }
     // backward: z = (y - sum over the neighbours above, columns ascending) / u_12
     for (int bi = nb - 1; bi >= 0; --bi) {
-        const int j0 = band0(bi), R = band0(bi + 1) - j0, j = j0 + t;
-        const bool row = t < R;
+        const int j0 = band0(bi), R = band0(bi + 1) - j0;
         const int nd = (nx - 1) + M * (R - 1) + 1;
         const int64_t D0 = lay.d0(bi);
+        auto locate = [&](int d, int &r, int &i) -> bool {
+            const int q = d - M * t;
+            const int k = MULTI && q >= 0 ? q / (M * NT) : 0;
+            r = t + k * NT;
+            i = q - k * (M * NT);
+            return r < R && i >= 0 && i < nx;
+        };
         auto bwd = [&](int d, double2(&fv)[NK], double2 &rv, double2 &dv) {
-            const int i = d - M * t;
-            if (row && i >= 0 && i < nx) {
+            int r, i;
+            if (locate(d, r, i)) {
+                const int j = j0 + r;
                 double2 z = rv;
 #pragma unroll
                 for (int g = 0; g < NK; g += G) {
@@ -2193,9 +2223,9 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
                     for (int k = g; k < g + G; ++k) {
                         const int sk = S::up(k), dx = sk % 5 - 2, dy = sk / 5 - 2;
                         in[k - g] = i + dx >= 0 && i + dx < nx && j + dy < ny;
-                        const int ir = ((d + dx + M * dy) % RG) * NT + t + dy;
-                        const int ih = HB + (t + dy - R) * HM + i + dx;
-                        ix[k - g] = in[k - g] ? (dy <= 0 || t + dy < R ? ir : ih) : Z0;
+                        const int ir = ((d + dx + M * dy) % RG) * NT + (MULTI ? (t + dy) % NT : t + dy);
+                        const int ih = HB + (r + dy - R) * HM + i + dx;
+                        ix[k - g] = in[k - g] ? (dy <= 0 || r + dy < R ? ir : ih) : Z0;
                     }
 #pragma unroll
                     for (int k = 0; k < G; ++k) q[k] = lds[ix[k]];
@@ -2204,10 +2234,12 @@ __global__ __launch_bounds__(NT) void k_ilu_up_rows(Ctx cx, IluArgs a)
                 }
                 z = cdiv<double>(z, dv);
                 lds[slot(d, t)] = z;
-                if (banded && t < HR) lds[HB + t * HM + i] = z;
+                if (banded && r < HR) lds[HB + r * HM + i] = z;
                 stg(w, (D0 + d) * lay.TS + t, z);
             }
-            fetch(row, i - PF, j, D0 + d - PF, false, fv, rv, dv);
+            int rn, in_;
+            const bool an = locate(d - PF, rn, in_);
+            fetch(an, D0 + d - PF, false, fv, rv, dv);
             __syncthreads();
         };
         // the first block (from nd rounded up to a multiple of PF) only loads

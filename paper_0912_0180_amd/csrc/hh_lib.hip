@@ -127,10 +127,10 @@ template <bool GAL> static void ilu_pack_set(const HostLevel &L, std::vector<dou
     const int64_t N = L.N;
     for (int b = 0; b < lay.nb; ++b) {
         const int j0 = lay.j0(b), R = lay.j0(b + 1) - j0;
-        for (int t = 0; t < R; ++t)
+        for (int r = 0; r < R; ++r)
             for (int i = 0; i < nx; ++i) {
-                const int j = j0 + t;
-                const int64_t p = i + (int64_t)nx * j, dd = lay.d0(b) + i + S::M * t;
+                const int j = j0 + r, t = lay.lane(r);
+                const int64_t p = i + (int64_t)nx * j, dd = lay.d0(b) + i + S::M * r;
                 // the entry of a neighbour outside the grid is +0 exactly: the
                 // kernels multiply it by a +0 neighbour value
                 auto entry = [&](int sk) {
@@ -1195,14 +1195,21 @@ static void vcycle_t(const Plan &pl, int fsel, int osel, const void *fptr, void 
                     hipLaunchKernelGGL(k_ilu_prolong, pg, dim3(HH_ILU_PW), 0, s, c, a);
                     hipLaunchKernelGGL(k_ilu_resid, pg, dim3(HH_ILU_PW), 0, s, c, a);
                 }
+                // one band of more rows than threads: the multi-row instance
+                const bool multi = form == 1 ? IluLayout<true>(nx, ny).nb == 1 && ny > IluSet<true>::NT
+                                             : form == 2 && IluLayout<false>(nx, ny).nb == 1 && ny > IluSet<false>::NT;
                 if (form == 1 && wg == 64)
-                    hipLaunchKernelGGL((k_ilu_up_rows<true, 64>), dim3(1), dim3(64), 0, s, c, a);
+                    hipLaunchKernelGGL((k_ilu_up_rows<true, 64, false>), dim3(1), dim3(64), 0, s, c, a);
                 else if (form == 1 && wg == 128)
-                    hipLaunchKernelGGL((k_ilu_up_rows<true, 128>), dim3(1), dim3(128), 0, s, c, a);
+                    hipLaunchKernelGGL((k_ilu_up_rows<true, 128, false>), dim3(1), dim3(128), 0, s, c, a);
+                else if (form == 1 && multi)
+                    hipLaunchKernelGGL((k_ilu_up_rows<true, IluSet<true>::NT, true>), dim3(1), dim3(IluSet<true>::NT), 0, s, c, a);
                 else if (form == 1)
-                    hipLaunchKernelGGL((k_ilu_up_rows<true, IluSet<true>::NT>), dim3(1), dim3(IluSet<true>::NT), 0, s, c, a);
+                    hipLaunchKernelGGL((k_ilu_up_rows<true, IluSet<true>::NT, false>), dim3(1), dim3(IluSet<true>::NT), 0, s, c, a);
+                else if (form == 2 && multi)
+                    hipLaunchKernelGGL((k_ilu_up_rows<false, IluSet<false>::NT, true>), dim3(1), dim3(IluSet<false>::NT), 0, s, c, a);
                 else if (form == 2)
-                    hipLaunchKernelGGL((k_ilu_up_rows<false, IluSet<false>::NT>), dim3(1), dim3(IluSet<false>::NT), 0, s, c, a);
+                    hipLaunchKernelGGL((k_ilu_up_rows<false, IluSet<false>::NT, false>), dim3(1), dim3(IluSet<false>::NT), 0, s, c, a);
                 else
                     hipLaunchKernelGGL(k_ilu_up, dim3(1), dim3(HH_ILU_WG), 0, s, c, a);
                 if (!a.inner) hipLaunchKernelGGL(k_ilu_update, pg, dim3(HH_ILU_PW), 0, s, c, a);

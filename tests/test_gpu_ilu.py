@@ -63,10 +63,10 @@ def ragged(coarse_op):
 
 def tall(coarse_op):
     """48 x 2096 cells, 5 levels: more rows than the row form's workgroup on
-    the levels 0 (3 bands of 699, 699, 698 rows), 1 (3 Galerkin bands of 350,
-    349, 349, or 2 rediscretised ones of 524) and 2 (2 Galerkin bands of 262);
-    the pointwise phases of every smoothing level run grid-wide (the c1 cases
-    and HH_ILU_FUSED cover them inside the solve kernel)."""
+    the levels 0 (2096 rows), 1 (1048) and 2 (524, Galerkin), each solved in
+    one pass with a thread owning rows t, t + NT, ...; the pointwise phases of
+    every smoothing level run grid-wide (the c1 cases and HH_ILU_FUSED cover
+    them inside the solve kernel)."""
     h = 1.0 / 64
     n = (48, 2096)
     hi = (-0.2 + n[0] * h, -0.3 + n[1] * h)
@@ -76,10 +76,23 @@ def tall(coarse_op):
     return ilu_case({"desc": d, "phi": phi}, coarse_op, omega=0.9)
 
 
+def wide_redisc():
+    """1088^2 cells, 7 levels, rediscretised 5-point operators: the finest
+    level is wider than the one-pass form allows (1088 > 1024 columns) and
+    taller than its workgroup, so it runs in 2 bands of 544 rows."""
+    n = (1088, 1088)
+    h = 1.0 / 1024
+    hi = (-0.01 + n[0] * h, -0.01 + n[1] * h)
+    d = W.base_desc(2, n, (-0.01, -0.01), hi, (0.0, 0.0), (hi[0] - 0.02, hi[1] - 0.02), levels=7)
+    rng = np.random.default_rng(76)
+    phi = (40.0 ** 2) * (1 + 0.3 * rng.uniform(size=n[0] * n[1]))
+    return ilu_case({"desc": d, "phi": phi}, 0, omega=0.9)
+
+
 CASES = {"c1_gal": lambda: ilu_case(W.c1(), 1), "c1_redisc": lambda: ilu_case(W.c1(), 0),
          "c1_interior_gal": lambda: ilu_case(W.c1(mode=1), 1), "ragged_gal": lambda: ragged(1),
          "ragged_redisc": lambda: ragged(0), "paper_gal": lambda: ilu_case(W.c1_paper(), 1),
-         "tall_gal": lambda: tall(1), "tall_redisc": lambda: tall(0)}
+         "tall_gal": lambda: tall(1), "tall_redisc": lambda: tall(0), "wide_redisc": wide_redisc}
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -195,7 +208,7 @@ def test_ilu_mp1_table_problem_matches_oracle(torch_dev, hh_mod, oracle_mod, lay
     assert np.array_equal(ig["history"], io["history"])
 
 
-@pytest.mark.parametrize("name", ["c1_gal", "ragged_redisc", "tall_gal"])
+@pytest.mark.parametrize("name", ["c1_gal", "ragged_redisc", "tall_gal", "wide_redisc"])
 def test_ilu_up_leg_forms_are_equal(torch_dev, hh_mod, oracle_mod, monkeypatch, name):
     """The up-leg's forms: the pipelined row form (in bands where a level has
     more rows than its workgroup), the global-memory form (HH_ILU_GLOBAL=1 on

@@ -1,8 +1,9 @@
 """CPU model checks of the ILU(0) row form's schedule (k_ilu_up_rows) and
 factor layout (IluLayout), written from their definitions in the kernel
-source: the anti-diagonal steps d = i + m t within bands of rows, the LDS ring
-of the last RING diagonals, the halo of the band before (rewritten in place),
-the prefetch buffers with fixed roles d mod PF, and the layout positions.
+source: the anti-diagonal steps d = i + m t within bands of rows or in one
+pass with several rows per thread, the LDS ring of the last RING diagonals,
+the halo of the band before (rewritten in place), the prefetch buffers with
+fixed roles d mod PF, and the layout positions.
 
 These are pure-Python models of the kernel's index arithmetic, not of the
 method: they check that the schedule reads every neighbour's final value,
@@ -149,10 +150,15 @@ def test_prefetch_buffers_hold_each_steps_point():
 @pytest.mark.parametrize("NT,M,NLO", [(64, 3, 12), (128, 1, 2)])
 def test_factor_layout_positions_are_distinct_and_in_range(NT, M, NLO):
     for ny in [5, 17, 63, 64, 65, NT, NT + 1, 2 * NT + 3, 3 * NT - 1]:
-        for nx in (5, 9):
-            nb, j0 = bands(ny, NT)
+        for nx in (5, 9, M * NT, M * NT + 1, M * NT + 7):
+            # one band (rows t, t + NT, ... per lane) when nx <= M NT
+            if nx <= M * NT:
+                nb, j0 = 1, (lambda b: 0 if b == 0 else ny)
+            else:
+                nb, j0 = bands(ny, NT)
             base, extra = ny // nb, ny % nb
-            TS = (base + (1 if extra else 0) + 63) // 64 * 64
+            rmax = base + (1 if extra else 0)
+            TS = NT if rmax > NT else (rmax + 63) // 64 * 64
             DT = nb * (nx - M) + M * ny
             size = DT * (2 * NLO + 1) * TS
             assert TS <= NT
@@ -163,14 +169,100 @@ def test_factor_layout_positions_are_distinct_and_in_range(NT, M, NLO):
                 R = j0(b + 1) - j0(b)
                 acc += (nx - 1) + M * (R - 1) + 1
                 c = extra * (base + 1)
-                for t in range(R):
-                    j = j0(b) + t
+                for r in range(R):
+                    j, t = j0(b) + r, r % NT
                     assert (j // (base + 1) if j < c else extra + (j - c) // base) == b
                     for i in range(nx):
-                        dd = d0 + i + M * t
+                        dd = d0 + i + M * r
                         pos = [(dd * NLO + k) * TS + t for k in range(NLO)]
                         pos += [(DT * NLO + dd * (NLO + 1) + k) * TS + t for k in range(NLO + 1)]
                         for a in pos:
                             assert 0 <= a < size and a not in seen
                             seen.add(a)
             assert acc == DT and j0(nb) == ny
+
+
+def emulate_one_pass(nx, ny, NT, S, seed):
+    """The one-pass form (nx <= m NT): thread t owns rows t, t + NT, ...; at
+    step d it solves the row whose steps contain d, and prefetches for the
+    row of step d +- PF, whichever row that is."""
+    M, RG, PF = S["M"], S["RING"], S["PF"]
+    assert nx <= M * NT < M * ny or ny <= NT
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal((25, ny, nx)) * 0.1
+    F[12] = 1.0 + rng.random((ny, nx))
+    r0 = rng.standard_normal((ny, nx))
+    y = r0.copy()
+    for j in range(ny):
+        for i in range(nx):
+            for s in S["lo"]:
+                dx, dy = s % 5 - 2, s // 5 - 2
+                if 0 <= i + dx < nx and 0 <= j + dy < ny:
+                    y[j, i] -= F[s, j, i] * y[j + dy, i + dx]
+    z = y.copy()
+    for j in reversed(range(ny)):
+        for i in reversed(range(nx)):
+            for s in S["up"]:
+                dx, dy = s % 5 - 2, s // 5 - 2
+                if 0 <= i + dx < nx and 0 <= j + dy < ny:
+                    z[j, i] -= F[s, j, i] * z[j + dy, i + dx]
+            z[j, i] /= F[12, j, i]
+    multi = ny > NT
+
+    def locate(d, t):
+        q = d - M * t
+        k = (q // (M * NT) if q >= 0 else 0) if multi else 0
+        r, i = t + k * NT, q - k * M * NT
+        return r, i, r < ny and 0 <= i < nx
+
+    nd = (nx - 1) + M * (ny - 1) + 1
+    ring, tag = np.full(RG * NT, np.nan), [None] * (RG * NT)
+    w = r0.copy()
+    for fwd in (True, False):
+        bufs = [[None] * PF for _ in range(NT)]
+        top = (nd + PF - 1) // PF * PF
+        steps = range(-PF, top) if fwd else range(top + PF - 1, -1, -1)
+        for d in steps:
+            reads, writes, new = [], [], []
+            for t in range(NT):
+                r, i, act = locate(d, t)
+                if act:
+                    assert bufs[t][d % PF] == (r, i)
+                    v = w[r, i]
+                    for s in (S["lo"] if fwd else S["up"]):
+                        dx, dy = s % 5 - 2, s // 5 - 2
+                        if not (0 <= i + dx < nx and 0 <= r + dy < ny):
+                            continue
+                        loc = ((d + dx + M * dy) % RG) * NT + (t + dy) % NT
+                        assert tag[loc] == (r + dy, i + dx)
+                        reads.append((loc, t))
+                        v -= F[s, r, i] * ring[loc]
+                    if not fwd:
+                        v /= F[12, r, i]
+                    new.append((t, r, i, v))
+                    writes.append(((d % RG) * NT + t, t))
+                dn = d + PF if fwd else d - PF
+                rn, iN, an = locate(dn, t)
+                bufs[t][dn % PF] = (rn, iN) if an else None
+            owner = dict((loc, t) for loc, t in writes)
+            for loc, t in reads:
+                assert owner.get(loc, t) == t, ("read and written in one step", loc)
+            for t, r, i, v in new:
+                k = (d % RG) * NT + t
+                ring[k], tag[k] = v, (r, i)
+                w[r, i] = v
+        np.testing.assert_allclose(w, y if fwd else z, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["gal", "five"])
+def test_one_pass_schedule_with_several_rows_per_thread(name):
+    S = GAL if name == "gal" else FIVE
+    n = 0
+    for NT in (4, 6, 8, 10):
+        for nx in range(5, S["M"] * NT + 1, 2):
+            for ny in (NT + 1, 2 * NT + 3, 3 * NT):
+                if ny < 5:
+                    continue
+                emulate_one_pass(nx, ny, NT, S, seed=n)
+                n += 1
+    assert n > 5
