@@ -19,10 +19,10 @@ with Bi-CGSTAB (its IDR counts are not measured here).  MP3 with r = 150,
 k = 4 (2560^2 with layers, 2048^2 with the Sommerfeld condition) runs
 Bi-CGSTAB only, to keep the test short: 395 and 623 matvecs against the
 table's 390 and 620, about 20 s each.  (Its IDR(4) counts, 400 and 649, match
-the table's 387 and 650; IDR(8) reaches 1e-6 in its recurrence after about
-680 matvecs, near the table's 392 / 652, but the true residual is then
-~1e-1, so the solve restarts from it and ends near twice the table's
-count.)
+the table's 387 and 650; IDR(8) with the Sommerfeld condition reaches 1e-6
+in its recurrence after 677 matvecs, near the table's 652, but the true
+residual is then ~1e-1, so the solve restarts from it and ends near twice
+the table's count, as it does with layers.)
 """
 import json
 import os
