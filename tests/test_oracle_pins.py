@@ -196,7 +196,7 @@ def kron_x_fastest(mats):
 
 @pytest.mark.parametrize("nu1", [1, 0])
 def test_vcycle_equals_three_level_matrix(oracle_mod, nu1):
-    """Three-level V(1,1) from explicitly assembled pieces:
+    """Three-level V(1,1) from explicitly assembled pieces (Sec. 5.1, 6.1):
     each level's M from a separate one-level grid of that size whose phi is
     the mean of the finer level's children (computed here), full weighting
     R = kron of (1,3,3,1)/8, bilinear P = 4 R^T, weighted Jacobi
